@@ -1,0 +1,19 @@
+"""Seeded synthetic inputs for the butterfly-compressed multifrontal solver.
+
+This package only builds problem data: sparse operators in CSR form, velocity
+and permittivity fields, right-hand sides and request streams.  It contains no
+step of the solver itself, so both the CPU oracle and the GPU path can draw
+their inputs from it without sharing any solver arithmetic.
+"""
+from .seeds import rng_for, CONFIG_IDS, PURPOSE_IDS
+from .helmholtz import helmholtz_7pt, omega_for_ppw, grf_velocity
+from .maxwell import yee_curlcurl
+from .rhs import point_sources, center_source_with_noise, random_edge_dipoles
+from .configs import CONFIGS, make_problem
+
+__all__ = [
+    "rng_for", "CONFIG_IDS", "PURPOSE_IDS",
+    "helmholtz_7pt", "omega_for_ppw", "grf_velocity", "yee_curlcurl",
+    "point_sources", "center_source_with_noise", "random_edge_dipoles",
+    "CONFIGS", "make_problem",
+]
