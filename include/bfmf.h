@@ -1,0 +1,225 @@
+/*
+ * bfmf.h -- C ABI of libbfmf, a butterfly-compressed multifrontal solver for
+ * complex sparse systems on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Liu, Ghysels, Claus, Li, "Sparse Approximate Multifrontal
+ * Factorization with Butterfly Compression for High Frequency Wave
+ * Equations".  The problem statement is: given A in C^{N x N} and b, compute
+ * x ~= A^{-1} b (Sec. 2, Alg. 1 and Alg. 5).  The three phases map to:
+ *
+ *   bfmf_analyze : fill-reducing nested dissection P, separator bisection
+ *                  P-hat, assembly tree, index sets I^s / I^u, extend-add maps
+ *                  (Alg. 1 steps 1-3, Alg. 5 steps 1-3, Sec. 5.1, Sec. 5.2)
+ *   bfmf_factor  : numerical factorization with ID tolerance `tol` and the
+ *                  compression threshold n_min (Alg. 5 loop); fronts below
+ *                  the threshold use the dense partial LU of Alg. 1
+ *   bfmf_solve   : preconditioned restarted GMRES (Alg. 5 last step, Sec. 6)
+ *                  with the factorization as preconditioner
+ *
+ * Conventions
+ *   - Every call returns a bfmf_status; no exception crosses the ABI.
+ *   - Complex numbers are interleaved (re, im) pairs of doubles at the ABI.
+ *     Dense blocks are column-major with an explicit leading dimension.
+ *   - Input arrays are borrowed for the duration of the call only and are
+ *     copied.  The handle owns all device memory it allocates until
+ *     bfmf_destroy.  Pointers returned through views are owned by the handle
+ *     and stay valid until the next bfmf_analyze or bfmf_destroy.
+ *   - State machine: created -> analyzed -> factored.  A call out of order
+ *     returns BFMF_E_STATE.  bfmf_factor may be called again (new tol, new
+ *     values through bfmf_set_values) on an analyzed handle.
+ *   - A handle is not thread-safe; use one handle per host thread or lock.
+ *   - On BFMF_E_DEVICE the handle is unusable; destroy it.
+ */
+#ifndef BFMF_H
+#define BFMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bfmf_ctx* bfmf_handle;
+
+typedef enum {
+    BFMF_OK = 0,
+    BFMF_E_INVAL = -1,    /* bad argument, malformed CSR, NaN/Inf input */
+    BFMF_E_NOMEM = -2,    /* device memory (or the handle's HBM budget) exhausted */
+    BFMF_E_STATE = -3,    /* call out of order (e.g. solve before factor) */
+    BFMF_E_SINGULAR = -4, /* exact zero pivot; see bfmf_stats.singular_front */
+    BFMF_E_NOCONV = -5,   /* GMRES hit max_iter; X holds the best iterate */
+    BFMF_E_DEVICE = -6    /* HIP runtime error */
+} bfmf_status;
+
+enum { BFMF_ORD_GRID = 0, BFMF_ORD_YEE = 1 };
+enum { BFMF_C128 = 0, BFMF_C64_MIXED = 1 };
+enum { BFMF_HOST = 0, BFMF_DEVICE = 1 };
+
+/* Geometric nested dissection (Sec. 2; planar separators as in Sec. 6).
+ * GRID: unknown i sits on node (i % nx, (i / nx) % ny, i / (nx ny)) of an
+ *       nx x ny x nz grid; boxes of at most leaf_max nodes are leaves.
+ * YEE : unknowns are interior edges of an nx^3 cell grid; coords[3 i + d]
+ *       holds the doubled coordinate of edge i along axis d (one odd entry).
+ * sep_leaf: leaf size of the recursive separator bisection that defines the
+ *       HOD-BF tree of F11 and the permutation P-hat (Sec. 5.1); also the leaf
+ *       size of the balanced tree on I^u. */
+typedef struct {
+    int32_t kind;
+    int32_t nx, ny, nz;
+    const int32_t* coords;
+    int32_t leaf_max; /* default 512 */
+    int32_t sep_leaf; /* default 64 */
+} bfmf_ordering;
+
+/* Numerical factorization options (Alg. 5; Sec. 3.1 for alpha and k_nn). */
+typedef struct {
+    double tol;          /* ID tolerance epsilon (Sec. 6: "ID tolerance") */
+    int64_t n_min;       /* compress separator fronts with #I^s >= n_min; <= 0: none */
+    int32_t precision;   /* BFMF_C128 or BFMF_C64_MIXED (c64 bulk, FP64 pivots) */
+    int32_t batched;     /* 0: one launch per front and op; 1: level-batched launches */
+    int32_t samples;     /* random probe columns per block in randomized construction */
+    int32_t knn;         /* graph nearest neighbours per row for proxy sampling */
+    double alpha;        /* uniform over-sampling factor for proxy sampling */
+    uint64_t seed;       /* seed of the device Philox probe generator */
+    uint64_t hbm_budget; /* bytes the factorization may use; 0 = all free memory */
+    int32_t keep_fronts; /* debug: keep a copy of every assembled dense front */
+    int32_t timing;      /* 1: time every kernel class with HIP events (bfmf_get_kernel_stats) */
+    int32_t reserved[6];
+} bfmf_factor_opts;
+
+/* GMRES options (Sec. 6): restarted GMRES(restart), modified Gram-Schmidt,
+ * zero initial guess, left preconditioning, stop when ||u_i|| <= atol or
+ * ||u_i|| / ||u_0|| <= rtol with u_i = M^-1 (A x_i - b).  If true_rtol > 0,
+ * iterations continue until the true residual ||b - A x|| / ||b|| of every
+ * column is also at most true_rtol. */
+typedef struct {
+    int32_t restart;     /* default 30 */
+    int32_t max_iter;    /* default 300 */
+    double rtol, atol;   /* defaults 1e-6, 1e-10 */
+    double true_rtol;    /* e.g. 1e-3; 0 disables */
+    /* outputs */
+    int32_t iters_max;   /* largest iteration count over the columns */
+    int32_t reserved0;
+    double relres_max;   /* largest true relative residual over the columns */
+    double seconds;      /* wall time of the call */
+} bfmf_solve_opts;
+
+/* Read-only view of the symbolic analysis (all arrays owned by the handle). */
+typedef struct {
+    int64_t n;
+    int32_t nfronts;
+    int32_t nlevels;
+    const int64_t* perm;       /* [n] new index -> original index */
+    const int64_t* sbeg;       /* [nfronts] I^s = [sbeg, send) in the new numbering */
+    const int64_t* send;
+    const int32_t* parent;     /* [nfronts] -1 at the root; fronts are in postorder */
+    const int32_t* level;      /* [nfronts] depth, root = 0 */
+    const int32_t* child_ptr;  /* [nfronts+1] */
+    const int32_t* child_list; /* children, left first */
+    const int64_t* iu_ptr;     /* [nfronts+1] */
+    const int64_t* iu;         /* sorted I^u of each front (new numbering) */
+    const int32_t* map;        /* at iu_ptr[f]: position of I^u_f in concat(I^s_p, I^u_p) */
+    const int32_t* sep_ptr;    /* [nfronts+1] node ranges of the bisection trees */
+    const int32_t* sep_nodes;  /* 4 ints per node in preorder: beg, end, left, right */
+} bfmf_symbolic_view;
+
+/* Counters mirroring the paper's Table "HH" rows plus timings. */
+typedef struct {
+    int32_t nfronts, compressed_fronts, dense_fronts, nlevels;
+    double analyze_seconds, factor_seconds;
+    double factor_flops;          /* algorithmic flops of the factorization */
+    double factor_bytes;          /* bytes held by the factors */
+    double dense_factor_bytes;    /* bytes the same factors take uncompressed */
+    int32_t max_rank;
+    int32_t singular_front;       /* front of an exact zero pivot, or -1 */
+    int32_t singular_index;       /* local pivot index within that front */
+    int32_t reserved0;
+    double solve_flops_per_rhs;   /* one preconditioner application */
+    uint64_t device_bytes_peak;   /* device memory held by the handle */
+    double reserved[8];
+} bfmf_stats;
+
+/* Create a handle on HIP device `device`.  `hip_stream` (hipStream_t) is the
+ * stream all work is queued on; NULL uses a stream owned by the handle.
+ * device = -1 creates a host-only handle that supports bfmf_analyze,
+ * bfmf_get_symbolic and bfmf_get_stats (no device is touched); factor and
+ * solve on it return BFMF_E_STATE.  E_DEVICE if the device does not exist. */
+bfmf_status bfmf_create(bfmf_handle* h, int32_t device, void* hip_stream);
+
+/* Analyze A (CSR: rowptr[n+1] int64, colind[nnz] int32 sorted per row,
+ * values[2 nnz] interleaved complex128 or NULL for pattern only) with the
+ * given ordering.  Computes P, P-hat, the assembly tree, I^s, I^u and all
+ * extend-add maps on the host and uploads them with the CSR to the device.
+ * Errors: E_INVAL for malformed CSR or ordering, E_NOMEM, E_DEVICE. */
+bfmf_status bfmf_analyze(bfmf_handle h, int64_t n, const int64_t* rowptr,
+                         const int32_t* colind, const double* values,
+                         const bfmf_ordering* ord);
+
+/* Replace the numerical values of A (same pattern).  Host array of 2 nnz
+ * doubles.  Returns the handle to the analyzed state. */
+bfmf_status bfmf_set_values(bfmf_handle h, const double* values);
+
+/* Fill `opts` with the defaults: tol 1e-3, n_min 1024, c128, plain, 64
+ * samples, knn 8, alpha 2, seed 0, no budget. */
+void bfmf_default_factor_opts(bfmf_factor_opts* opts);
+void bfmf_default_solve_opts(bfmf_solve_opts* opts);
+
+/* Numerical factorization (Alg. 5).  Fronts whose separator has at least
+ * n_min nodes are compressed (HOD-BF F11 and its inverse, butterfly F12, F21
+ * and Schur update); all others use the dense partial LU with pivoting
+ * restricted to F11 (Alg. 1).  On E_NOMEM or E_SINGULAR the handle returns
+ * to the analyzed state. */
+bfmf_status bfmf_factor(bfmf_handle h, const bfmf_factor_opts* opts);
+
+/* Solve A X = B for nrhs columns with GMRES preconditioned by the
+ * factorization.  B (ldb >= n) and X (ldx >= n) are interleaved complex128,
+ * column-major, in host memory (mem = BFMF_HOST) or device memory
+ * (BFMF_DEVICE).  `io` may be NULL (defaults); its output fields are written.
+ * Returns E_NOCONV (with the best X) when max_iter is reached. */
+bfmf_status bfmf_solve(bfmf_handle h, int64_t nrhs, const double* B, int64_t ldb,
+                       double* X, int64_t ldx, int32_t mem, bfmf_solve_opts* io);
+
+/* Apply the preconditioner once, X = M^-1 B (forward then backward sweep
+ * through all fronts), without GMRES.  Same layout rules as bfmf_solve. */
+bfmf_status bfmf_apply_preconditioner(bfmf_handle h, int64_t nrhs, const double* B,
+                                      int64_t ldb, double* X, int64_t ldx, int32_t mem);
+
+bfmf_status bfmf_get_symbolic(bfmf_handle h, bfmf_symbolic_view* out);
+bfmf_status bfmf_get_stats(bfmf_handle h, bfmf_stats* out);
+
+/* Debug access to a dense front after bfmf_factor, copied to host memory:
+ *   what = 0: the assembled front F (needs keep_fronts), n x n
+ *   what = 1: the factored front [LU F12'; F21' C], n x n
+ *   what = 2: the pivot sequence of F11 (ns int32 values, 0-based, LAPACK
+ *             interchange convention), written to out as int32
+ * n = #I^s + #I^u of the front; out has leading dimension ld >= n.
+ * E_INVAL for compressed fronts or out-of-range arguments. */
+bfmf_status bfmf_get_front(bfmf_handle h, int32_t front, int32_t what, void* out, int64_t ld);
+
+/* Per kernel-class timing, collected with HIP events on the handle's stream
+ * while bfmf_factor_opts.timing is set (factor and solve calls accumulate).
+ * Classes: 0 assemble (extend-add), 1 panel LU loop (panel, interchanges,
+ * triangular solves, rank-32 updates), 2 Schur GEMM C = F22 - F21 F12,
+ * 3 forward sweep level, 4 backward sweep level, 5 SpMV, 6 GMRES vector ops.
+ * flops / bytes are the algorithmic counts of the timed launches.
+ * E_INVAL for an unknown class; bfmf_reset_kernel_stats clears all. */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double seconds;
+    double flops;
+    double bytes;
+} bfmf_kernel_stat;
+enum { BFMF_KERNEL_CLASSES = 7 };
+bfmf_status bfmf_get_kernel_stats(bfmf_handle h, int32_t kind, bfmf_kernel_stat* out);
+bfmf_status bfmf_reset_kernel_stats(bfmf_handle h);
+
+const char* bfmf_status_str(bfmf_status s);
+const char* bfmf_last_error(bfmf_handle h);
+void bfmf_destroy(bfmf_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BFMF_H */

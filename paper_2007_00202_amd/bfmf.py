@@ -1,0 +1,321 @@
+"""ctypes binding of libbfmf (include/bfmf.h), argument marshalling only.
+
+The module-level functions carry the names of the C entry points; the
+``Solver`` class strings them together.  Every numerical step runs inside
+the library; when the library is not built this module raises on import.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libbfmf.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libbfmf.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+_lib = C.CDLL(LIB_PATH)
+
+# --------------------------------------------------------------- constants
+BFMF_OK, BFMF_E_INVAL, BFMF_E_NOMEM, BFMF_E_STATE = 0, -1, -2, -3
+BFMF_E_SINGULAR, BFMF_E_NOCONV, BFMF_E_DEVICE = -4, -5, -6
+BFMF_ORD_GRID, BFMF_ORD_YEE = 0, 1
+BFMF_C128, BFMF_C64_MIXED = 0, 1
+BFMF_HOST, BFMF_DEVICE = 0, 1
+
+
+class bfmf_ordering(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("coords", C.POINTER(C.c_int32)), ("leaf_max", C.c_int32), ("sep_leaf", C.c_int32)]
+
+
+class bfmf_factor_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("n_min", C.c_int64), ("precision", C.c_int32),
+                ("batched", C.c_int32), ("samples", C.c_int32), ("knn", C.c_int32),
+                ("alpha", C.c_double), ("seed", C.c_uint64), ("hbm_budget", C.c_uint64),
+                ("keep_fronts", C.c_int32), ("timing", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+
+class bfmf_kernel_stat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("seconds", C.c_double),
+                ("flops", C.c_double), ("bytes", C.c_double)]
+
+
+BFMF_KERNEL_CLASSES = 7
+
+
+class bfmf_solve_opts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("rtol", C.c_double),
+                ("atol", C.c_double), ("true_rtol", C.c_double), ("iters_max", C.c_int32),
+                ("reserved0", C.c_int32), ("relres_max", C.c_double), ("seconds", C.c_double)]
+
+
+class bfmf_symbolic_view(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nfronts", C.c_int32), ("nlevels", C.c_int32),
+                ("perm", C.POINTER(C.c_int64)), ("sbeg", C.POINTER(C.c_int64)),
+                ("send", C.POINTER(C.c_int64)), ("parent", C.POINTER(C.c_int32)),
+                ("level", C.POINTER(C.c_int32)), ("child_ptr", C.POINTER(C.c_int32)),
+                ("child_list", C.POINTER(C.c_int32)), ("iu_ptr", C.POINTER(C.c_int64)),
+                ("iu", C.POINTER(C.c_int64)), ("map", C.POINTER(C.c_int32)),
+                ("sep_ptr", C.POINTER(C.c_int32)), ("sep_nodes", C.POINTER(C.c_int32))]
+
+
+class bfmf_stats(C.Structure):
+    _fields_ = [("nfronts", C.c_int32), ("compressed_fronts", C.c_int32), ("dense_fronts", C.c_int32),
+                ("nlevels", C.c_int32), ("analyze_seconds", C.c_double), ("factor_seconds", C.c_double),
+                ("factor_flops", C.c_double), ("factor_bytes", C.c_double),
+                ("dense_factor_bytes", C.c_double), ("max_rank", C.c_int32),
+                ("singular_front", C.c_int32), ("singular_index", C.c_int32), ("reserved0", C.c_int32),
+                ("solve_flops_per_rhs", C.c_double), ("device_bytes_peak", C.c_uint64),
+                ("reserved", C.c_double * 8)]
+
+
+_h = C.c_void_p
+_P = C.c_void_p
+_SIGS = {
+    "bfmf_create": (C.c_int, [C.POINTER(_h), C.c_int32, _P]),
+    "bfmf_analyze": (C.c_int, [_h, C.c_int64, _P, _P, _P, C.POINTER(bfmf_ordering)]),
+    "bfmf_set_values": (C.c_int, [_h, _P]),
+    "bfmf_default_factor_opts": (None, [C.POINTER(bfmf_factor_opts)]),
+    "bfmf_default_solve_opts": (None, [C.POINTER(bfmf_solve_opts)]),
+    "bfmf_factor": (C.c_int, [_h, C.POINTER(bfmf_factor_opts)]),
+    "bfmf_solve": (C.c_int, [_h, C.c_int64, _P, C.c_int64, _P, C.c_int64, C.c_int32,
+                             C.POINTER(bfmf_solve_opts)]),
+    "bfmf_apply_preconditioner": (C.c_int, [_h, C.c_int64, _P, C.c_int64, _P, C.c_int64, C.c_int32]),
+    "bfmf_get_symbolic": (C.c_int, [_h, C.POINTER(bfmf_symbolic_view)]),
+    "bfmf_get_stats": (C.c_int, [_h, C.POINTER(bfmf_stats)]),
+    "bfmf_get_front": (C.c_int, [_h, C.c_int32, C.c_int32, _P, C.c_int64]),
+    "bfmf_get_kernel_stats": (C.c_int, [_h, C.c_int32, C.POINTER(bfmf_kernel_stat)]),
+    "bfmf_reset_kernel_stats": (C.c_int, [_h]),
+    "bfmf_status_str": (C.c_char_p, [C.c_int]),
+    "bfmf_last_error": (C.c_char_p, [_h]),
+    "bfmf_destroy": (None, [_h]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+class BfmfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_lib.bfmf_status_str(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def _check(h, st):
+    if st != BFMF_OK:
+        msg = _lib.bfmf_last_error(h).decode() if h else ""
+        raise BfmfError(st, msg)
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+# ------------------------------------------------------- entry-point wrappers
+def bfmf_create(device=0, stream=None):
+    h = _h()
+    st = _lib.bfmf_create(C.byref(h), int(device), C.c_void_p(stream) if stream else None)
+    if st != BFMF_OK:
+        raise BfmfError(st, "create")
+    return h
+
+
+def bfmf_analyze(h, rowptr, colind, values, kind=BFMF_ORD_GRID, dims=(0, 0, 0), coords=None,
+                 leaf_max=512, sep_leaf=64):
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    colind = np.ascontiguousarray(colind, dtype=np.int32)
+    vals = None if values is None else np.ascontiguousarray(values, dtype=np.complex128)
+    cc = None if coords is None else np.ascontiguousarray(coords, dtype=np.int32)
+    o = bfmf_ordering(kind, dims[0], dims[1], dims[2],
+                      cc.ctypes.data_as(C.POINTER(C.c_int32)) if cc is not None else None,
+                      leaf_max, sep_leaf)
+    _check(h, _lib.bfmf_analyze(h, rowptr.shape[0] - 1, _ptr(rowptr), _ptr(colind), _ptr(vals), C.byref(o)))
+
+
+def bfmf_set_values(h, values):
+    vals = np.ascontiguousarray(values, dtype=np.complex128)
+    _check(h, _lib.bfmf_set_values(h, _ptr(vals)))
+
+
+def bfmf_default_factor_opts():
+    o = bfmf_factor_opts()
+    _lib.bfmf_default_factor_opts(C.byref(o))
+    return o
+
+
+def bfmf_default_solve_opts():
+    o = bfmf_solve_opts()
+    _lib.bfmf_default_solve_opts(C.byref(o))
+    return o
+
+
+def bfmf_factor(h, opts=None):
+    opts = opts or bfmf_default_factor_opts()
+    _check(h, _lib.bfmf_factor(h, C.byref(opts)))
+
+
+def bfmf_solve(h, B, opts=None, X=None):
+    """Host arrays: B (n, nrhs) complex128.  Returns (X, opts) with the outputs filled."""
+    B = np.asfortranarray(B, dtype=np.complex128)
+    if B.ndim == 1:
+        B = B[:, None]
+    n, nrhs = B.shape
+    if X is None:
+        X = np.zeros((n, nrhs), dtype=np.complex128, order="F")
+    opts = opts or bfmf_default_solve_opts()
+    st = _lib.bfmf_solve(h, nrhs, _ptr(B), n, _ptr(X), n, BFMF_HOST, C.byref(opts))
+    if st not in (BFMF_OK, BFMF_E_NOCONV):
+        _check(h, st)
+    return X, opts, st
+
+
+def bfmf_solve_device(h, dB, ldb, dX, ldx, nrhs, opts=None):
+    """Device pointers (e.g. torch tensors' data_ptr()) of interleaved complex128."""
+    opts = opts or bfmf_default_solve_opts()
+    st = _lib.bfmf_solve(h, nrhs, C.c_void_p(dB), ldb, C.c_void_p(dX), ldx, BFMF_DEVICE, C.byref(opts))
+    if st not in (BFMF_OK, BFMF_E_NOCONV):
+        _check(h, st)
+    return opts, st
+
+
+def bfmf_apply_preconditioner(h, B):
+    B = np.asfortranarray(B, dtype=np.complex128)
+    if B.ndim == 1:
+        B = B[:, None]
+    n, nrhs = B.shape
+    X = np.zeros((n, nrhs), dtype=np.complex128, order="F")
+    _check(h, _lib.bfmf_apply_preconditioner(h, nrhs, _ptr(B), n, _ptr(X), n, BFMF_HOST))
+    return X
+
+
+def bfmf_get_symbolic(h):
+    v = bfmf_symbolic_view()
+    _check(h, _lib.bfmf_get_symbolic(h, C.byref(v)))
+    nf = v.nfronts
+
+    def arr(p, cnt, dt):
+        return np.ctypeslib.as_array(p, shape=(cnt,)).astype(dt, copy=True) if cnt else np.zeros(0, dt)
+
+    out = {"n": v.n, "nfronts": nf, "nlevels": v.nlevels}
+    out["perm"] = arr(v.perm, v.n, np.int64)
+    out["sbeg"] = arr(v.sbeg, nf, np.int64)
+    out["send"] = arr(v.send, nf, np.int64)
+    out["parent"] = arr(v.parent, nf, np.int32)
+    out["level"] = arr(v.level, nf, np.int32)
+    out["child_ptr"] = arr(v.child_ptr, nf + 1, np.int32)
+    out["child_list"] = arr(v.child_list, int(out["child_ptr"][-1]), np.int32)
+    out["iu_ptr"] = arr(v.iu_ptr, nf + 1, np.int64)
+    out["iu"] = arr(v.iu, int(out["iu_ptr"][-1]), np.int64)
+    out["map"] = arr(v.map, int(out["iu_ptr"][-1]), np.int32)
+    out["sep_ptr"] = arr(v.sep_ptr, nf + 1, np.int32)
+    out["sep_nodes"] = arr(v.sep_nodes, 4 * int(out["sep_ptr"][-1]), np.int32).reshape(-1, 4)
+    return out
+
+
+def bfmf_get_stats(h):
+    s = bfmf_stats()
+    _check(h, _lib.bfmf_get_stats(h, C.byref(s)))
+    return {name: getattr(s, name) for name, _ in bfmf_stats._fields_ if not name.startswith("reserved")}
+
+
+def bfmf_get_front(h, front, what, n):
+    if what == 2:
+        out = np.zeros(max(n, 1), dtype=np.int32)
+        _check(h, _lib.bfmf_get_front(h, front, what, _ptr(out), 1))
+        return out[:n]
+    out = np.zeros((n, n), dtype=np.complex128, order="F")
+    _check(h, _lib.bfmf_get_front(h, front, what, _ptr(out), n))
+    return out
+
+
+def bfmf_get_kernel_stats(h):
+    out = {}
+    for k in range(BFMF_KERNEL_CLASSES):
+        st = bfmf_kernel_stat()
+        _check(h, _lib.bfmf_get_kernel_stats(h, k, C.byref(st)))
+        out[st.name.decode()] = {"launches": st.launches, "seconds": st.seconds, "flops": st.flops,
+                                 "bytes": st.bytes}
+    return out
+
+
+def bfmf_reset_kernel_stats(h):
+    _check(h, _lib.bfmf_reset_kernel_stats(h))
+
+
+def bfmf_status_str(st):
+    return _lib.bfmf_status_str(st).decode()
+
+
+def bfmf_last_error(h):
+    return _lib.bfmf_last_error(h).decode()
+
+
+def bfmf_destroy(h):
+    _lib.bfmf_destroy(h)
+
+
+# ------------------------------------------------------------ convenience
+class Solver:
+    """analyze(A, ordering) -> factor(tol) -> solve(B) on one device."""
+
+    def __init__(self, device=0, stream=None):
+        self.h = bfmf_create(device, stream)
+        self.n = None
+
+    def analyze(self, rowptr, colind, values, dims=None, coords=None, cells=None, leaf_max=512, sep_leaf=64):
+        if coords is not None:
+            bfmf_analyze(self.h, rowptr, colind, values, BFMF_ORD_YEE, (cells, 0, 0), coords, leaf_max, sep_leaf)
+        else:
+            bfmf_analyze(self.h, rowptr, colind, values, BFMF_ORD_GRID, dims, None, leaf_max, sep_leaf)
+        self.n = rowptr.shape[0] - 1
+        return self
+
+    def factor(self, tol=1e-3, n_min=1024, precision=BFMF_C128, batched=False, samples=64, knn=8,
+               alpha=2.0, seed=0, hbm_budget=0, keep_fronts=False, timing=False):
+        o = bfmf_default_factor_opts()
+        o.timing = int(bool(timing))
+        o.tol, o.n_min, o.precision, o.batched = tol, n_min, precision, int(bool(batched))
+        o.samples, o.knn, o.alpha, o.seed = samples, knn, alpha, seed
+        o.hbm_budget, o.keep_fronts = hbm_budget, int(bool(keep_fronts))
+        bfmf_factor(self.h, o)
+        return self
+
+    def solve(self, B, restart=30, max_iter=300, rtol=1e-6, atol=1e-10, true_rtol=0.0):
+        o = bfmf_default_solve_opts()
+        o.restart, o.max_iter, o.rtol, o.atol, o.true_rtol = restart, max_iter, rtol, atol, true_rtol
+        X, o, st = bfmf_solve(self.h, B, o)
+        return X, {"iters": o.iters_max, "relres": o.relres_max, "seconds": o.seconds, "status": st}
+
+    def precondition(self, B):
+        return bfmf_apply_preconditioner(self.h, B)
+
+    def symbolic(self):
+        return bfmf_get_symbolic(self.h)
+
+    def stats(self):
+        return bfmf_get_stats(self.h)
+
+    def kernel_stats(self):
+        return bfmf_get_kernel_stats(self.h)
+
+    def front(self, f, what):
+        sym = self.symbolic()
+        n = int(sym["send"][f] - sym["sbeg"][f] + sym["iu_ptr"][f + 1] - sym["iu_ptr"][f])
+        if what == 2:
+            n = int(sym["send"][f] - sym["sbeg"][f])
+        return bfmf_get_front(self.h, f, what, n)
+
+    def close(self):
+        if self.h:
+            bfmf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

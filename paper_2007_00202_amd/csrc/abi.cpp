@@ -1,0 +1,355 @@
+// extern "C" entry points of libbfmf (declared in include/bfmf.h).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "context.hpp"
+
+using namespace bfmf;
+
+struct bfmf_ctx : public Context {};
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <class F>
+bfmf_status guarded(bfmf_handle h, F&& fn) {
+  if (!h) return BFMF_E_INVAL;
+  try {
+    if (h->device >= 0) HIPCHK(hipSetDevice(h->device));
+    fn();
+    return BFMF_OK;
+  } catch (const Error& e) {
+    h->last_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    h->last_error = "host allocation failed";
+    return BFMF_E_NOMEM;
+  } catch (const std::exception& e) {
+    h->last_error = e.what();
+    return BFMF_E_INVAL;
+  }
+}
+
+bool finite_values(const double* v, int64_t cnt) {
+  for (int64_t i = 0; i < cnt; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+bfmf_status bfmf_create(bfmf_handle* h, int32_t device, void* hip_stream) {
+  if (!h) return BFMF_E_INVAL;
+  *h = nullptr;
+  if (device == -1) {  // host-only handle: analysis without a device
+    bfmf_ctx* c = new (std::nothrow) bfmf_ctx();
+    if (!c) return BFMF_E_NOMEM;
+    c->device = -1;
+    bfmf_default_factor_opts(&c->fopts);
+    *h = c;
+    return BFMF_OK;
+  }
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return BFMF_E_DEVICE;
+  bfmf_ctx* c = new (std::nothrow) bfmf_ctx();
+  if (!c) return BFMF_E_NOMEM;
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return BFMF_E_DEVICE;
+  }
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return BFMF_E_DEVICE;
+    }
+    c->own_stream = true;
+  }
+  bfmf_default_factor_opts(&c->fopts);
+  c->stats.singular_front = -1;
+  c->stats.singular_index = -1;
+  *h = c;
+  return BFMF_OK;
+}
+
+void bfmf_default_factor_opts(bfmf_factor_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-3;
+  o->n_min = 1024;
+  o->precision = BFMF_C128;
+  o->batched = 0;
+  o->samples = 64;
+  o->knn = 8;
+  o->alpha = 2.0;
+  o->seed = 0;
+  o->hbm_budget = 0;
+}
+
+void bfmf_default_solve_opts(bfmf_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->restart = 30;
+  o->max_iter = 300;
+  o->rtol = 1e-6;
+  o->atol = 1e-10;
+  o->true_rtol = 0;
+}
+
+bfmf_status bfmf_analyze(bfmf_handle h, int64_t n, const int64_t* rowptr, const int32_t* colind,
+                         const double* values, const bfmf_ordering* ord) {
+  return guarded(h, [&] {
+    if (n <= 0 || !rowptr || !colind || !ord) throw Error(BFMF_E_INVAL, "analyze: null argument or n <= 0");
+    if (rowptr[0] != 0) throw Error(BFMF_E_INVAL, "analyze: rowptr[0] must be 0");
+    for (int64_t i = 0; i < n; ++i)
+      if (rowptr[i + 1] < rowptr[i]) throw Error(BFMF_E_INVAL, "analyze: rowptr not non-decreasing");
+    const int64_t nnz = rowptr[n];
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t t = rowptr[i]; t < rowptr[i + 1]; ++t) {
+        if (colind[t] < 0 || colind[t] >= n) throw Error(BFMF_E_INVAL, "analyze: column index out of range");
+        if (t > rowptr[i] && colind[t] <= colind[t - 1])
+          throw Error(BFMF_E_INVAL, "analyze: column indices not strictly increasing within a row");
+      }
+    if (values && !finite_values(values, 2 * nnz)) throw Error(BFMF_E_INVAL, "analyze: non-finite matrix value");
+    const double t0 = now_s();
+    h->state = State::Created;
+    h->n = n;
+    h->nnz = nnz;
+    h->rowptr.assign(rowptr, rowptr + n + 1);
+    h->colind.assign(colind, colind + nnz);
+    if (values)
+      h->values.assign(values, values + 2 * nnz);
+    else
+      h->values.assign(2 * nnz, 0.0);
+    std::string err;
+    const int32_t leaf = ord->leaf_max > 0 ? ord->leaf_max : 512;
+    const int32_t sl = ord->sep_leaf > 0 ? ord->sep_leaf : 64;
+    bool ok;
+    if (ord->kind == BFMF_ORD_GRID) {
+      if ((int64_t)ord->nx * ord->ny * ord->nz != n) throw Error(BFMF_E_INVAL, "analyze: nx*ny*nz != n");
+      ok = nd_grid(ord->nx, ord->ny, ord->nz, leaf, sl, h->sym, err);
+    } else if (ord->kind == BFMF_ORD_YEE) {
+      ok = nd_yee(ord->nx, n, ord->coords, leaf, sl, h->sym, err);
+    } else {
+      throw Error(BFMF_E_INVAL, "analyze: unknown ordering kind");
+    }
+    if (!ok) throw Error(BFMF_E_INVAL, err);
+    if (!symbolic_phase(n, rowptr, colind, h->sym, err)) throw Error(BFMF_E_INVAL, err);
+    build_plan(*h);
+    if (h->device >= 0) upload_plan(*h);
+    h->d_arena.release();
+    h->d_kept.release();
+    h->analyze_seconds = now_s() - t0;
+    h->stats.analyze_seconds = h->analyze_seconds;
+    h->state = State::Analyzed;
+  });
+}
+
+bfmf_status bfmf_set_values(bfmf_handle h, const double* values) {
+  return guarded(h, [&] {
+    if (h->state == State::Created) throw Error(BFMF_E_STATE, "set_values before analyze");
+    if (!values) throw Error(BFMF_E_INVAL, "set_values: null values");
+    if (!finite_values(values, 2 * h->nnz)) throw Error(BFMF_E_INVAL, "set_values: non-finite matrix value");
+    h->values.assign(values, values + 2 * h->nnz);
+    if (h->device >= 0) upload_values(*h);
+    h->state = State::Analyzed;
+  });
+}
+
+bfmf_status bfmf_factor(bfmf_handle h, const bfmf_factor_opts* opts) {
+  return guarded(h, [&] {
+    if (h->state == State::Created) throw Error(BFMF_E_STATE, "factor before analyze");
+    if (h->device < 0) throw Error(BFMF_E_STATE, "factor on a host-only handle");
+    bfmf_factor_opts o;
+    if (opts)
+      o = *opts;
+    else
+      bfmf_default_factor_opts(&o);
+    if (!(o.tol > 0) || o.samples < 0 || o.knn < 0 || o.alpha < 0)
+      throw Error(BFMF_E_INVAL, "factor: bad options");
+    if (o.precision != BFMF_C128 && o.precision != BFMF_C64_MIXED)
+      throw Error(BFMF_E_INVAL, "factor: unknown precision");
+    h->fopts = o;
+    h->timer.enabled = o.timing != 0;
+    h->state = State::Analyzed;
+    factor_dense(*h);
+    h->stats.device_bytes_peak = h->device_bytes();
+    h->state = State::Factored;
+  });
+}
+
+static bfmf_status solve_common(bfmf_handle h, int64_t nrhs, const double* B, int64_t ldb, double* X, int64_t ldx,
+                                int32_t mem, bfmf_solve_opts* io, bool precond_only) {
+  return guarded(h, [&] {
+    if (h->state != State::Factored) throw Error(BFMF_E_STATE, "solve before factor");
+    if (nrhs <= 0 || !B || !X || ldb < h->n || ldx < h->n) throw Error(BFMF_E_INVAL, "solve: bad arguments");
+    if (mem != BFMF_HOST && mem != BFMF_DEVICE) throw Error(BFMF_E_INVAL, "solve: bad memory kind");
+    bfmf_solve_opts o;
+    if (io)
+      o = *io;
+    else
+      bfmf_default_solve_opts(&o);
+    if (o.restart <= 0) o.restart = 30;
+    if (o.max_iter <= 0) o.max_iter = 300;
+    const double t0 = now_s();
+    const size_t elem = 2 * sizeof(double);
+    const void* dB = B;
+    void* dX = X;
+    int64_t lb = ldb, lx = ldx;
+    if (mem == BFMF_HOST) {
+      DevBuf& bb = h->g_B;
+      DevBuf& xb = h->g_X;
+      const size_t need = (size_t)h->n * nrhs * elem;
+      if (bb.bytes < need) {
+        bb.release();
+        HIPCHK(hipMalloc(&bb.p, need));
+        bb.bytes = need;
+      }
+      if (xb.bytes < need) {
+        xb.release();
+        HIPCHK(hipMalloc(&xb.p, need));
+        xb.bytes = need;
+      }
+      HIPCHK(hipMemcpy2DAsync(bb.p, h->n * elem, B, ldb * elem, h->n * elem, nrhs, hipMemcpyHostToDevice,
+                              h->stream));
+      dB = bb.p;
+      dX = xb.p;
+      lb = lx = h->n;
+    }
+    int rc = 0;
+    if (precond_only) {
+      apply_preconditioner_dev(*h, dB, lb, dX, lx, nrhs);
+      HIPCHK(hipStreamSynchronize(h->stream));
+      h->timer.collect();
+    } else {
+      rc = gmres_dev(*h, dB, lb, dX, lx, nrhs, o);
+    }
+    if (mem == BFMF_HOST)
+      HIPCHK(hipMemcpy2DAsync(X, ldx * elem, dX, lx * elem, h->n * elem, nrhs, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    o.seconds = now_s() - t0;
+    if (io) *io = o;
+    if (rc) throw Error(BFMF_E_NOCONV, "GMRES reached max_iter before convergence");
+  });
+}
+
+bfmf_status bfmf_solve(bfmf_handle h, int64_t nrhs, const double* B, int64_t ldb, double* X, int64_t ldx,
+                       int32_t mem, bfmf_solve_opts* io) {
+  return solve_common(h, nrhs, B, ldb, X, ldx, mem, io, false);
+}
+
+bfmf_status bfmf_apply_preconditioner(bfmf_handle h, int64_t nrhs, const double* B, int64_t ldb, double* X,
+                                      int64_t ldx, int32_t mem) {
+  return solve_common(h, nrhs, B, ldb, X, ldx, mem, nullptr, true);
+}
+
+bfmf_status bfmf_get_symbolic(bfmf_handle h, bfmf_symbolic_view* out) {
+  if (!h || !out) return BFMF_E_INVAL;
+  if (h->state == State::Created) return BFMF_E_STATE;
+  const Symbolic& s = h->sym;
+  out->n = s.n;
+  out->nfronts = s.nfronts();
+  out->nlevels = s.nlevels;
+  out->perm = s.perm.data();
+  out->sbeg = s.sbeg.data();
+  out->send = s.send.data();
+  out->parent = s.parent.data();
+  out->level = s.level.data();
+  out->child_ptr = s.child_ptr.data();
+  out->child_list = s.child_list.data();
+  out->iu_ptr = s.iu_ptr.data();
+  out->iu = s.iu.data();
+  out->map = s.map.data();
+  out->sep_ptr = s.sep_ptr.data();
+  out->sep_nodes = (const int32_t*)s.sep_nodes.data();
+  return BFMF_OK;
+}
+
+bfmf_status bfmf_get_stats(bfmf_handle h, bfmf_stats* out) {
+  if (!h || !out) return BFMF_E_INVAL;
+  *out = h->stats;
+  out->device_bytes_peak = std::max<uint64_t>(h->stats.device_bytes_peak, h->device_bytes());
+  return BFMF_OK;
+}
+
+bfmf_status bfmf_get_front(bfmf_handle h, int32_t front, int32_t what, void* out, int64_t ld) {
+  return guarded(h, [&] {
+    if (h->state != State::Factored) throw Error(BFMF_E_STATE, "get_front before factor");
+    if (front < 0 || front >= h->sym.nfronts() || !out) throw Error(BFMF_E_INVAL, "get_front: bad front");
+    const FrontPlan& p = h->fp[front];
+    const size_t elem = 2 * sizeof(double);
+    if (what == 2) {
+      HIPCHK(hipMemcpy(out, h->d_piv.as<int32_t>() + p.piv_off, p.ns * sizeof(int32_t), hipMemcpyDeviceToHost));
+      return;
+    }
+    if (ld < p.n) throw Error(BFMF_E_INVAL, "get_front: ld < n");
+    const DevBuf* src = nullptr;
+    if (what == 0) {
+      if (!h->fopts.keep_fronts) throw Error(BFMF_E_INVAL, "get_front: assembled fronts not kept");
+      src = &h->d_kept;
+    } else if (what == 1) {
+      src = &h->d_arena;
+    } else {
+      throw Error(BFMF_E_INVAL, "get_front: bad 'what'");
+    }
+    HIPCHK(hipMemcpy2D(out, ld * elem, src->as<char>() + p.f_off * elem, p.n * elem, p.n * elem, p.n,
+                       hipMemcpyDeviceToHost));
+  });
+}
+
+bfmf_status bfmf_get_kernel_stats(bfmf_handle h, int32_t kind, bfmf_kernel_stat* out) {
+  static const char* names[K_COUNT] = {"assemble", "panel_lu", "schur_gemm", "forward_sweep",
+                                       "backward_sweep", "spmv", "gmres_vector"};
+  if (!h || !out || kind < 0 || kind >= K_COUNT) return BFMF_E_INVAL;
+  std::memset(out, 0, sizeof(*out));
+  std::strncpy(out->name, names[kind], sizeof(out->name) - 1);
+  out->launches = h->timer.launches[kind];
+  out->seconds = h->timer.seconds[kind];
+  out->flops = h->timer.flops[kind];
+  out->bytes = h->timer.bytes[kind];
+  return BFMF_OK;
+}
+
+bfmf_status bfmf_reset_kernel_stats(bfmf_handle h) {
+  if (!h) return BFMF_E_INVAL;
+  h->timer.reset();
+  return BFMF_OK;
+}
+
+const char* bfmf_status_str(bfmf_status s) {
+  switch (s) {
+    case BFMF_OK: return "ok";
+    case BFMF_E_INVAL: return "invalid argument";
+    case BFMF_E_NOMEM: return "out of device memory";
+    case BFMF_E_STATE: return "call out of order";
+    case BFMF_E_SINGULAR: return "exact zero pivot";
+    case BFMF_E_NOCONV: return "GMRES did not converge";
+    case BFMF_E_DEVICE: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char* bfmf_last_error(bfmf_handle h) { return h ? h->last_error.c_str() : "null handle"; }
+
+void bfmf_destroy(bfmf_handle h) {
+  if (!h) return;
+  if (h->device >= 0) (void)hipSetDevice(h->device);
+  if (h->own_stream && h->stream) {
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipStreamDestroy(h->stream);
+  }
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,149 @@
+// The state behind a bfmf_handle: symbolic analysis, the device plan of the
+// dense fronts, device buffers and counters.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/bfmf.h"
+#include "analyze.hpp"
+#include "devtypes.hpp"
+
+namespace bfmf {
+
+// RAII device allocation
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const {
+    return (T*)p;
+  }
+};
+
+class Error : public std::exception {
+ public:
+  bfmf_status status;
+  std::string msg;
+  Error(bfmf_status s, std::string m) : status(s), msg(std::move(m)) {}
+  const char* what() const noexcept override { return msg.c_str(); }
+};
+
+#define HIPCHK(expr)                                                                           \
+  do {                                                                                         \
+    hipError_t e__ = (expr);                                                                   \
+    if (e__ != hipSuccess)                                                                     \
+      throw ::bfmf::Error(BFMF_E_DEVICE, std::string(#expr " failed: ") + hipGetErrorString(e__)); \
+  } while (0)
+
+enum class State { Created, Analyzed, Factored };
+
+enum KernelKind { K_ASSEMBLE = 0, K_LU = 1, K_SCHUR = 2, K_FWD = 3, K_BWD = 4, K_SPMV = 5, K_VEC = 6, K_COUNT = 7 };
+
+// HIP-event timing of kernel classes on the handle's stream.
+struct KernelTimer {
+  bool enabled = false;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<Rec> recs;
+  int64_t launches[K_COUNT] = {};
+  double seconds[K_COUNT] = {}, flops[K_COUNT] = {}, bytes[K_COUNT] = {};
+  hipEvent_t take();
+  int begin(hipStream_t s);
+  void end(int token, hipStream_t s, int kind, double fl, double by);
+  void collect();  // after the stream is synchronised
+  void reset();
+  ~KernelTimer();
+};
+
+// Host mirror of the per-front data that the kernels need.
+struct FrontPlan {
+  int32_t n = 0, ns = 0, nu = 0;
+  int32_t nchild = 0;
+  int32_t child[2] = {-1, -1};
+  int64_t f_off = 0;      // element offset of F in the front arena
+  int64_t inv_off[2] = {-1, -1};
+  int64_t aptr_off = 0;   // into a_ptr (n+1 entries)
+  int64_t piv_off = 0;    // into piv (ns entries)
+  int64_t iu_off = 0;     // into iu32 (nu entries)
+  int64_t w_off = 0;      // element offset of W per rhs column block (n entries per column)
+  bool compressed = false;
+};
+
+struct Context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  State state = State::Created;
+  std::string last_error;
+
+  // problem
+  int64_t n = 0, nnz = 0;
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> colind;
+  std::vector<double> values;  // interleaved complex128, 2 nnz
+  Symbolic sym;
+  double analyze_seconds = 0;
+
+  // plan
+  std::vector<FrontPlan> fp;
+  std::vector<int32_t> level_ptr, level_fronts;  // fronts grouped by level, deepest level first
+  int64_t arena_elems = 0;                       // sum of n_f^2
+  int64_t sum_n = 0;                             // sum of n_f
+  std::vector<int64_t> h_aptr;
+  std::vector<int32_t> h_arow;
+  std::vector<int64_t> h_avidx;
+  std::vector<int32_t> h_inv;
+
+  // device: matrix and plan
+  DevBuf d_rowptr, d_colind, d_values, d_perm;
+  DevBuf d_aptr, d_arow, d_avidx, d_inv, d_iu32, d_piv, d_status;
+  DevBuf d_fds;            // FrontDesc per front, in level order (level_fronts order)
+  std::vector<FrontDesc> h_fds;
+  std::vector<int32_t> desc_index;  // front id -> index in h_fds
+
+  // device: numeric
+  DevBuf d_arena;          // dense fronts
+  DevBuf d_kept;           // debug copies of assembled fronts
+  bfmf_factor_opts fopts{};
+  bfmf_stats stats{};
+
+  // device: solve workspaces
+  DevBuf d_W, d_y, d_x;
+  int64_t ws_nrhs = 0;
+  DevBuf g_B, g_X, g_V, g_w, g_r, g_scal, g_part, g_tmp;
+  int64_t g_nrhs = 0, g_restart = 0;
+
+  KernelTimer timer;
+
+  uint64_t device_bytes() const;
+};
+
+// plan.cpp
+void build_plan(Context& c);
+void upload_plan(Context& c);
+void upload_values(Context& c);
+// numeric.cpp
+void factor_dense(Context& c);
+void ensure_workspace(Context& c, int64_t nrhs);
+void apply_preconditioner_dev(Context& c, const void* dB, int64_t ldb, void* dX, int64_t ldx, int64_t nrhs);
+int gmres_dev(Context& c, const void* dB, int64_t ldb, void* dX, int64_t ldx, int64_t nrhs, bfmf_solve_opts& o);
+
+}  // namespace bfmf

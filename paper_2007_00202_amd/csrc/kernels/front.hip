@@ -1,0 +1,382 @@
+// Dense front kernels: extend-add assembly and partial LU with pivoting
+// restricted to F11 (paper Sec. 2, Alg. 1).
+//
+// The partial factorization of F = [F11 F12; F21 F22] (ns fully-summed
+// variables) is right-looking over the block row [F11 F12] in panels of
+// KB columns:
+//   panel   : LU with partial pivoting of F11(k0:ns, k0:k0+jb); the pivot is
+//             the first row maximising |Re| + |Im| (LAPACK getrf convention)
+//   laswp   : the panel's row interchanges applied to the other columns of
+//             rows 0..ns-1 (so F12 becomes P^T F12)
+//   trsm_ll : F(k0:k0+jb, k0+jb:n) <- L_kk^-1 F(k0:k0+jb, k0+jb:n)
+//   trsm_ru : F21(:, k0:k0+jb) <- F21(:, k0:k0+jb) U_kk^-1
+//   trailing: F11/F12 rows below the panel and F21 columns right of it get
+//             the rank-jb update (MFMA GEMM)
+// and finally the Schur complement C = F22 - F21 F12 is one GEMM of depth ns.
+// Pivot search never looks at F21 (Sec. 2: the pivoting in F11 does not use
+// the values of F21 and F12).
+#include "../devtypes.hpp"
+#include "common.hpp"
+#include "gemm.hpp"
+#include "kernels.hpp"
+
+namespace bfmf {
+
+// ---------------------------------------------------------------- assembly
+// F_tau = [A(Is,Is) A(Is,Iu); A(Iu,Is) 0] (+) C_nu1 (+) C_nu2, computed in
+// gather form: every entry is ((0 + a) + c1) + c2 in that order.  One wave
+// per front column; the column's few A entries are held in registers.
+template <class T, class TC>
+__global__ __launch_bounds__(256) void assemble_kernel(const FrontDesc* __restrict__ fds,
+                                                       const cplx<double>* __restrict__ values) {
+  const FrontDesc& fd = fds[blockIdx.y];
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int n = fd.n;
+  if (j >= n) return;
+  cplx<T>* F = (cplx<T>*)fd.F + (int64_t)j * n;
+  const int64_t a0 = fd.a_ptr[j], a1 = fd.a_ptr[j + 1];
+  const int inv1j = fd.nchild > 0 ? fd.inv[0][j] : -1;
+  const int inv2j = fd.nchild > 1 ? fd.inv[1][j] : -1;
+  const TC* cb1 = inv1j >= 0 ? (const TC*)fd.cb[0] + (int64_t)inv1j * fd.cb_ld[0] : nullptr;
+  const TC* cb2 = inv2j >= 0 ? (const TC*)fd.cb[1] + (int64_t)inv2j * fd.cb_ld[1] : nullptr;
+  const int na = (int)(a1 - a0);
+  for (int i0 = 0; i0 < n; i0 += 64) {
+    const int i = i0 + lane;
+    cplx<T> v = {0, 0};
+    // entries t0..t0+63 of this column, one per lane, broadcast by shuffles;
+    // every lane of the wave runs the same trip counts
+    for (int t0 = 0; t0 < na; t0 += 64) {
+      int myrow = -1;
+      double mr = 0, mi = 0;
+      if (t0 + lane < na) {
+        myrow = fd.a_row[a0 + t0 + lane];
+        const cplx<double> a = values[fd.a_vidx[a0 + t0 + lane]];
+        mr = a.re;
+        mi = a.im;
+      }
+      const int cnt = min(64, na - t0);
+      for (int t = 0; t < cnt; ++t) {
+        const int r = __shfl(myrow, t);
+        const double vr = __shfl(mr, t), vi = __shfl(mi, t);
+        if (r == i) {
+          v.re += (T)vr;
+          v.im += (T)vi;
+        }
+      }
+    }
+    if (i < n) {
+      if (cb1) {
+        const int k = fd.inv[0][i];
+        if (k >= 0) {
+          const TC c = cb1[k];
+          v.re += (T)c.re;
+          v.im += (T)c.im;
+        }
+      }
+      if (cb2) {
+        const int k = fd.inv[1][i];
+        if (k >= 0) {
+          const TC c = cb2[k];
+          v.re += (T)c.re;
+          v.im += (T)c.im;
+        }
+      }
+      F[i] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ panel
+// One workgroup per front: unblocked LU with partial pivoting of the
+// (ns-k0) x jb panel F11(k0:ns, k0:k0+jb).
+template <class T>
+__global__ __launch_bounds__(256) void panel_kernel(const FrontDesc* __restrict__ fds, int k0, int kb,
+                                                    int* __restrict__ status) {
+  const FrontDesc& fd = fds[blockIdx.x];
+  const int ns = fd.ns, n = fd.n;
+  if (k0 >= ns) return;
+  const int jb = min(kb, ns - k0);
+  cplx<T>* F = (cplx<T>*)fd.F;
+  const int tid = threadIdx.x;
+  __shared__ T rv[256];
+  __shared__ int ri[256];
+  for (int jj = 0; jj < jb; ++jj) {
+    const int col = k0 + jj;
+    cplx<T>* Fc = F + (int64_t)col * n;
+    T best = -1;
+    int bi = ns;
+    for (int r = col + tid; r < ns; r += 256) {
+      const T a = cabs1(Fc[r]);
+      if (a > best) {
+        best = a;
+        bi = r;
+      }
+    }
+    rv[tid] = best;
+    ri[tid] = bi;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) {
+        const T o = rv[tid + s];
+        const int oi = ri[tid + s];
+        if (o > rv[tid] || (o == rv[tid] && oi < ri[tid])) {
+          rv[tid] = o;
+          ri[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    int p = ri[0];
+    const T pv = rv[0];
+    __syncthreads();
+    const bool singular = !(pv > 0) || p >= ns;
+    if (singular) p = col;
+    if (tid == 0) {
+      fd.piv[col] = p;
+      if (singular && atomicCAS(&status[0], 0, 1) == 0) {
+        status[1] = fd.front;
+        status[2] = col;
+      }
+    }
+    if (p != col) {
+      for (int c = k0 + tid; c < k0 + jb; c += 256) {
+        cplx<T>* Fcc = F + (int64_t)c * n;
+        const cplx<T> t = Fcc[col];
+        Fcc[col] = Fcc[p];
+        Fcc[p] = t;
+      }
+    }
+    __syncthreads();
+    if (!singular) {
+      const cplx<T> d = Fc[col];
+      for (int r = col + 1 + tid; r < ns; r += 256) Fc[r] = cdiv(Fc[r], d);
+    }
+    __syncthreads();
+    for (int r = col + 1 + tid; r < ns; r += 256) {
+      const cplx<T> l = Fc[r];
+      for (int c = col + 1; c < k0 + jb; ++c) {
+        cplx<T>* Fcc = F + (int64_t)c * n;
+        Fcc[r] = csub(Fcc[r], cmul(l, Fcc[col]));
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Row interchanges of panel k0 applied to the columns outside the panel, rows
+// 0..ns-1 only (F21 rows are never swapped).
+template <class T>
+__global__ __launch_bounds__(256) void laswp_kernel(const FrontDesc* __restrict__ fds, int k0, int kb) {
+  const FrontDesc& fd = fds[blockIdx.y];
+  const int ns = fd.ns, n = fd.n;
+  if (k0 >= ns) return;
+  const int jb = min(kb, ns - k0);
+  int c = blockIdx.x * 256 + threadIdx.x;
+  // columns [0, k0) then [k0+jb, n)
+  if (c >= k0) c += jb;
+  if (c >= n) return;
+  cplx<T>* Fc = (cplx<T>*)fd.F + (int64_t)c * n;
+  for (int k = k0; k < k0 + jb; ++k) {
+    const int p = fd.piv[k];
+    if (p != k) {
+      const cplx<T> t = Fc[k];
+      Fc[k] = Fc[p];
+      Fc[p] = t;
+    }
+  }
+}
+
+// F(k0:k0+jb, c) <- L_kk^-1 F(k0:k0+jb, c) for c in [k0+jb, n): one wave per
+// column, lane i holds row k0+i, forward substitution with shuffles.
+template <class T, int KB>
+__global__ __launch_bounds__(256) void trsm_ll_kernel(const FrontDesc* __restrict__ fds, int k0) {
+  const FrontDesc& fd = fds[blockIdx.y];
+  const int ns = fd.ns, n = fd.n;
+  if (k0 >= ns) return;
+  const int jb = min(KB, ns - k0);
+  __shared__ cplx<T> L[KB][KB + 1];
+  cplx<T>* F = (cplx<T>*)fd.F;
+  for (int e = threadIdx.x; e < KB * KB; e += 256) {
+    const int i = e % KB, j = e / KB;
+    L[i][j] = (i < jb && j < jb) ? F[(int64_t)(k0 + i) + (int64_t)(k0 + j) * n] : cplx<T>{0, 0};
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int c = k0 + jb + blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= n) return;
+  cplx<T>* col = F + (int64_t)c * n + k0;
+  cplx<T> x = lane < jb ? col[lane] : cplx<T>{0, 0};
+  for (int j = 0; j < jb - 1; ++j) {
+    const T xr = __shfl(x.re, j), xi = __shfl(x.im, j);
+    if (lane > j && lane < jb) x = csub(x, cmul(L[lane][j], cplx<T>{xr, xi}));
+  }
+  if (lane < jb) col[lane] = x;
+}
+
+// F21(r, k0:k0+jb) <- F21(r, k0:k0+jb) U_kk^-1 for rows r in [ns, n): one
+// thread per row, the row vector kept in registers.
+template <class T, int KB>
+__global__ __launch_bounds__(256) void trsm_ru_kernel(const FrontDesc* __restrict__ fds, int k0) {
+  const FrontDesc& fd = fds[blockIdx.y];
+  const int ns = fd.ns, n = fd.n;
+  if (k0 >= ns) return;
+  const int jb = min(KB, ns - k0);
+  __shared__ cplx<T> U[KB][KB + 1];
+  cplx<T>* F = (cplx<T>*)fd.F;
+  for (int e = threadIdx.x; e < KB * KB; e += 256) {
+    const int i = e % KB, j = e / KB;
+    U[i][j] = (i < jb && j < jb) ? F[(int64_t)(k0 + i) + (int64_t)(k0 + j) * n] : cplx<T>{1, 0};
+  }
+  __syncthreads();
+  const int r = ns + blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+  cplx<T> x[KB];
+#pragma unroll
+  for (int c = 0; c < KB; ++c) x[c] = c < jb ? F[(int64_t)r + (int64_t)(k0 + c) * n] : cplx<T>{0, 0};
+#pragma unroll
+  for (int c = 0; c < KB; ++c) {
+    cplx<T> s = x[c];
+#pragma unroll
+    for (int d = 0; d < c; ++d) s = csub(s, cmul(x[d], U[d][c]));
+    x[c] = c < jb ? cdiv(s, U[c][c]) : s;
+  }
+#pragma unroll
+  for (int c = 0; c < KB; ++c)
+    if (c < jb) F[(int64_t)r + (int64_t)(k0 + c) * n] = x[c];
+}
+
+// Rank-jb update after panel k0: rows [k0+jb, ns) x cols [k0+jb, n) and
+// rows [ns, n) x cols [k0+jb, ns).
+template <class T>
+__global__ __launch_bounds__(256) void trailing_kernel(const FrontDesc* __restrict__ fds, int k0, int kb) {
+  __shared__ GemmSmem<T> sm;
+  const FrontDesc& fd = fds[blockIdx.y];
+  const int ns = fd.ns, n = fd.n;
+  if (k0 >= ns) return;
+  const int jb = min(kb, ns - k0);
+  const int r0 = k0 + jb;
+  cplx<T>* F = (cplx<T>*)fd.F;
+  const int M1 = ns - r0, N1 = n - r0;
+  const int M2 = n - ns, N2 = ns - r0;
+  const int tm1 = (M1 + GEMM_TM - 1) / GEMM_TM, tn1 = (N1 + GEMM_TN - 1) / GEMM_TN;
+  const int tm2 = (M2 + GEMM_TM - 1) / GEMM_TM, tn2 = (N2 + GEMM_TN - 1) / GEMM_TN;
+  const int t1 = (M1 > 0 && N1 > 0) ? tm1 * tn1 : 0;
+  const int t2 = (M2 > 0 && N2 > 0) ? tm2 * tn2 : 0;
+  int t = blockIdx.x;
+  const cplx<T> m1 = {-1, 0};
+  if (t < t1) {
+    gemm_tile<T>(F + r0 + (int64_t)k0 * n, n, OP_N, F + k0 + (int64_t)r0 * n, n, F + r0 + (int64_t)r0 * n, n, M1,
+                 N1, jb, m1, 1, t % tm1, t / tm1, sm);
+    return;
+  }
+  t -= t1;
+  if (t < t2) {
+    gemm_tile<T>(F + ns + (int64_t)k0 * n, n, OP_N, F + k0 + (int64_t)r0 * n, n, F + ns + (int64_t)r0 * n, n,
+                 M2, N2, jb, m1, 1, t % tm2, t / tm2, sm);
+  }
+}
+
+// Schur complement C = F22 - F21 F12 (depth ns).
+template <class T>
+__global__ __launch_bounds__(256) void schur_kernel(const FrontDesc* __restrict__ fds) {
+  __shared__ GemmSmem<T> sm;
+  const FrontDesc& fd = fds[blockIdx.y];
+  const int ns = fd.ns, n = fd.n, nu = n - ns;
+  if (nu <= 0 || ns <= 0) return;
+  const int tm = (nu + GEMM_TM - 1) / GEMM_TM, tn = tm;
+  const int t = blockIdx.x;
+  if (t >= tm * tn) return;
+  cplx<T>* F = (cplx<T>*)fd.F;
+  gemm_tile<T>(F + ns, n, OP_N, F + (int64_t)ns * n, n, F + ns + (int64_t)ns * n, n, nu, nu, ns, cplx<T>{-1, 0},
+               1, t % tm, t / tm, sm);
+}
+
+// ------------------------------------------------------------------ launchers
+#define KCHECK(expr)                       \
+  do {                                     \
+    hipError_t e__ = (expr);               \
+    if (e__ != hipSuccess) return e__;     \
+  } while (0)
+
+template <class T>
+hipError_t launch_assemble(const FrontDesc* d_fds, int nbatch, int maxn, const void* values, bool cb_single,
+                           hipStream_t s) {
+  if (nbatch == 0 || maxn == 0) return hipSuccess;
+  dim3 grid((maxn + 3) / 4, nbatch);
+  if (cb_single)
+    hipLaunchKernelGGL((assemble_kernel<T, cplx<float>>), grid, dim3(256), 0, s, d_fds,
+                       (const cplx<double>*)values);
+  else
+    hipLaunchKernelGGL((assemble_kernel<T, cplx<double>>), grid, dim3(256), 0, s, d_fds,
+                       (const cplx<double>*)values);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_partial_lu(const FrontDesc* d_fds, int nbatch, const int* h_n, const int* h_ns, int* d_status,
+                             hipStream_t s) {
+  if (nbatch == 0) return hipSuccess;
+  constexpr int KB = 32;
+  int maxns = 0, maxn = 0;
+  for (int b = 0; b < nbatch; ++b) {
+    maxns = h_ns[b] > maxns ? h_ns[b] : maxns;
+    maxn = h_n[b] > maxn ? h_n[b] : maxn;
+  }
+  for (int k0 = 0; k0 < maxns; k0 += KB) {
+    hipLaunchKernelGGL((panel_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, k0, KB, d_status);
+    KCHECK(hipGetLastError());
+    int ncols = maxn;  // upper bound on columns outside the panel
+    hipLaunchKernelGGL((laswp_kernel<T>), dim3((ncols + 255) / 256, nbatch), dim3(256), 0, s, d_fds, k0, KB);
+    KCHECK(hipGetLastError());
+    hipLaunchKernelGGL((trsm_ll_kernel<T, KB>), dim3((maxn - k0 + 3) / 4, nbatch), dim3(256), 0, s, d_fds, k0);
+    KCHECK(hipGetLastError());
+    int maxnu = 0, maxtiles = 0;
+    for (int b = 0; b < nbatch; ++b) {
+      if (k0 >= h_ns[b]) continue;
+      const int jb = (h_ns[b] - k0) < KB ? (h_ns[b] - k0) : KB;
+      const int r0 = k0 + jb;
+      const int nu = h_n[b] - h_ns[b];
+      maxnu = nu > maxnu ? nu : maxnu;
+      const int M1 = h_ns[b] - r0, N1 = h_n[b] - r0, M2 = nu, N2 = h_ns[b] - r0;
+      int t = 0;
+      if (M1 > 0 && N1 > 0) t += ((M1 + 63) / 64) * ((N1 + 63) / 64);
+      if (M2 > 0 && N2 > 0) t += ((M2 + 63) / 64) * ((N2 + 63) / 64);
+      maxtiles = t > maxtiles ? t : maxtiles;
+    }
+    if (maxnu > 0) {
+      hipLaunchKernelGGL((trsm_ru_kernel<T, KB>), dim3((maxnu + 255) / 256, nbatch), dim3(256), 0, s, d_fds, k0);
+      KCHECK(hipGetLastError());
+    }
+    if (maxtiles > 0) {
+      hipLaunchKernelGGL((trailing_kernel<T>), dim3(maxtiles, nbatch), dim3(256), 0, s, d_fds, k0, KB);
+      KCHECK(hipGetLastError());
+    }
+  }
+  return hipSuccess;
+}
+
+template <class T>
+hipError_t launch_schur(const FrontDesc* d_fds, int nbatch, const int* h_n, const int* h_ns, hipStream_t s) {
+  int maxtiles = 0;
+  for (int b = 0; b < nbatch; ++b) {
+    const int nu = h_n[b] - h_ns[b];
+    if (nu <= 0 || h_ns[b] <= 0) continue;
+    const int t = ((nu + 63) / 64) * ((nu + 63) / 64);
+    maxtiles = t > maxtiles ? t : maxtiles;
+  }
+  if (maxtiles > 0) {
+    hipLaunchKernelGGL((schur_kernel<T>), dim3(maxtiles, nbatch), dim3(256), 0, s, d_fds);
+    KCHECK(hipGetLastError());
+  }
+  return hipSuccess;
+}
+
+template hipError_t launch_assemble<double>(const FrontDesc*, int, int, const void*, bool, hipStream_t);
+template hipError_t launch_assemble<float>(const FrontDesc*, int, int, const void*, bool, hipStream_t);
+template hipError_t launch_partial_lu<double>(const FrontDesc*, int, const int*, const int*, int*, hipStream_t);
+template hipError_t launch_partial_lu<float>(const FrontDesc*, int, const int*, const int*, int*, hipStream_t);
+template hipError_t launch_schur<double>(const FrontDesc*, int, const int*, const int*, hipStream_t);
+template hipError_t launch_schur<float>(const FrontDesc*, int, const int*, const int*, hipStream_t);
+
+}  // namespace bfmf

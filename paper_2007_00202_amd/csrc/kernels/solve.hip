@@ -1,0 +1,353 @@
+// Forward / backward sweeps through the dense fronts (paper Sec. 2, Alg. 1
+// last step; Sec. 5: forward applies F11^-1 then F21 from the leaves to the
+// root, backward applies F12 then F11^-1 from the root to the leaves), and the
+// FP64 vector kernels of GMRES (Sec. 6).
+//
+// Sweeps are written in gather form: front f owns a workspace W_f (n x nrhs);
+// in the forward sweep rows ns..n-1 of W_f end up holding the update vector
+// that the parent extend-adds (through the same inverse maps as the
+// factorization), so no two fronts ever write the same memory.
+#include "../devtypes.hpp"
+#include "common.hpp"
+#include "gemm.hpp"
+#include "kernels.hpp"
+
+namespace bfmf {
+
+template <class T>
+__global__ void permute_in_kernel(const cplx<double>* __restrict__ B, int64_t ldb, cplx<T>* __restrict__ y,
+                                  const int64_t* __restrict__ perm, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= N) return;
+  const cplx<double> v = B[perm[i] + c * ldb];
+  y[i + c * N] = cplx<T>{(T)v.re, (T)v.im};
+}
+
+template <class T>
+__global__ void permute_out_kernel(const cplx<T>* __restrict__ x, cplx<double>* __restrict__ X, int64_t ldx,
+                                   const int64_t* __restrict__ perm, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= N) return;
+  const cplx<T> v = x[i + c * N];
+  X[perm[i] + c * ldx] = cplx<double>{(double)v.re, (double)v.im};
+}
+
+// W_f(i, c) = [y(sbeg + i, c) if i < ns] (+) child updates, in child order.
+template <class T>
+__global__ __launch_bounds__(256) void fwd_gather_kernel(const FrontDesc* __restrict__ fds,
+                                                         const cplx<T>* __restrict__ y, int64_t N, int nrhs) {
+  const FrontDesc& fd = fds[blockIdx.y];
+  const int n = fd.n, ns = fd.ns;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int k1 = fd.nchild > 0 ? fd.inv[0][i] : -1;
+  const int k2 = fd.nchild > 1 ? fd.inv[1][i] : -1;
+  cplx<T>* W = (cplx<T>*)fd.W;
+  for (int c = 0; c < nrhs; ++c) {
+    cplx<T> v = {0, 0};
+    if (i < ns) v = y[fd.sbeg + i + c * N];
+    if (k1 >= 0) v = cadd(v, ((const cplx<T>*)fd.cw[0])[k1 + c * fd.cw_ld[0]]);
+    if (k2 >= 0) v = cadd(v, ((const cplx<T>*)fd.cw[1])[k2 + c * fd.cw_ld[1]]);
+    W[i + (int64_t)c * n] = v;
+  }
+}
+
+// Row interchanges then unit-lower substitution on W_f(0:ns, :), one
+// workgroup per front; threads own rows, one synchronisation per column.
+template <class T>
+__global__ __launch_bounds__(256) void fwd_trsv_kernel(const FrontDesc* __restrict__ fds, int nrhs) {
+  const FrontDesc& fd = fds[blockIdx.x];
+  const int n = fd.n, ns = fd.ns;
+  if (ns == 0) return;
+  const cplx<T>* F = (const cplx<T>*)fd.F;
+  cplx<T>* W = (cplx<T>*)fd.W;
+  for (int c = threadIdx.x; c < nrhs; c += 256) {
+    cplx<T>* w = W + (int64_t)c * n;
+    for (int k = 0; k < ns; ++k) {
+      const int p = fd.piv[k];
+      if (p != k) {
+        const cplx<T> t = w[k];
+        w[k] = w[p];
+        w[p] = t;
+      }
+    }
+  }
+  __syncthreads();
+  for (int j = 0; j < ns - 1; ++j) {
+    const cplx<T>* Lj = F + (int64_t)j * n;
+    for (int r = j + 1 + threadIdx.x; r < ns; r += 256) {
+      const cplx<T> l = Lj[r];
+      for (int c = 0; c < nrhs; ++c) {
+        cplx<T>* w = W + (int64_t)c * n;
+        w[r] = csub(w[r], cmul(l, w[j]));
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Upper substitution on W_f(0:ns, :) and scatter of the result into x.
+template <class T>
+__global__ __launch_bounds__(256) void bwd_trsv_kernel(const FrontDesc* __restrict__ fds, cplx<T>* __restrict__ x,
+                                                       int64_t N, int nrhs) {
+  const FrontDesc& fd = fds[blockIdx.x];
+  const int n = fd.n, ns = fd.ns;
+  if (ns == 0) return;
+  const cplx<T>* F = (const cplx<T>*)fd.F;
+  cplx<T>* W = (cplx<T>*)fd.W;
+  for (int j = ns - 1; j >= 0; --j) {
+    const cplx<T>* Uj = F + (int64_t)j * n;
+    const cplx<T> d = Uj[j];
+    for (int c = threadIdx.x; c < nrhs; c += 256) {
+      cplx<T>* w = W + (int64_t)c * n;
+      w[j] = cdiv(w[j], d);
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < j; r += 256) {
+      const cplx<T> u = Uj[r];
+      for (int c = 0; c < nrhs; ++c) {
+        cplx<T>* w = W + (int64_t)c * n;
+        w[r] = csub(w[r], cmul(u, w[j]));
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < ns * nrhs; e += 256) {
+    const int r = e % ns, c = e / ns;
+    x[fd.sbeg + r + (int64_t)c * N] = W[r + (int64_t)c * n];
+  }
+}
+
+// W_f(ns + k, c) = x(I^u[k], c)
+template <class T>
+__global__ __launch_bounds__(256) void bwd_gather_kernel(const FrontDesc* __restrict__ fds,
+                                                         const cplx<T>* __restrict__ x, int64_t N, int nrhs) {
+  const FrontDesc& fd = fds[blockIdx.y];
+  const int n = fd.n, ns = fd.ns;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= n - ns) return;
+  const int64_t g = fd.iu[k];
+  cplx<T>* W = (cplx<T>*)fd.W;
+  for (int c = 0; c < nrhs; ++c) W[ns + k + (int64_t)c * n] = x[g + c * N];
+}
+
+// mode 0: W(ns:n) -= F21 W(0:ns)   (forward update)
+// mode 1: W(0:ns) -= F12 W(ns:n)   (backward update)
+template <class T>
+__global__ __launch_bounds__(256) void sweep_gemm_kernel(const FrontDesc* __restrict__ fds, int nrhs, int mode) {
+  __shared__ GemmSmem<T> sm;
+  const FrontDesc& fd = fds[blockIdx.y];
+  const int n = fd.n, ns = fd.ns, nu = n - ns;
+  if (ns == 0 || nu == 0) return;
+  const cplx<T>* F = (const cplx<T>*)fd.F;
+  cplx<T>* W = (cplx<T>*)fd.W;
+  const int M = mode == 0 ? nu : ns;
+  const int tm = (M + GEMM_TM - 1) / GEMM_TM, tn = (nrhs + GEMM_TN - 1) / GEMM_TN;
+  const int t = blockIdx.x;
+  if (t >= tm * tn) return;
+  if (mode == 0)
+    gemm_tile<T>(F + ns, n, OP_N, W, n, W + ns, n, nu, nrhs, ns, cplx<T>{-1, 0}, 1, t % tm, t / tm, sm);
+  else
+    gemm_tile<T>(F + (int64_t)ns * n, n, OP_N, W + ns, n, W, n, ns, nrhs, nu, cplx<T>{-1, 0}, 1, t % tm, t / tm,
+                 sm);
+}
+
+// ------------------------------------------------------------ GMRES vectors
+// Y = A X (alpha = 0) or Y = B - A X (residual), CSR complex128, nrhs columns
+__global__ void spmv_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+                            const cplx<double>* __restrict__ val, const cplx<double>* __restrict__ X, int64_t ldx,
+                            cplx<double>* __restrict__ Y, int64_t ldy, const cplx<double>* __restrict__ B, int64_t ldb,
+                            int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= N) return;
+  const cplx<double>* x = X + c * ldx;
+  cplx<double> s = {0, 0};
+  for (int64_t t = rowptr[i]; t < rowptr[i + 1]; ++t) s = cadd(s, cmul(val[t], x[colind[t]]));
+  if (B) s = csub(B[i + c * ldb], s);
+  Y[i + c * ldy] = s;
+}
+
+// partial[b, c] = sum over the block's rows of conj(V) W (or |W|^2 if V null)
+__global__ __launch_bounds__(256) void dot_partial_kernel(const cplx<double>* __restrict__ V, int64_t ldv,
+                                                          const cplx<double>* __restrict__ Wv, int64_t ldw, int64_t N,
+                                                          cplx<double>* __restrict__ partial) {
+  const int c = blockIdx.y;
+  __shared__ double sr[256], si[256];
+  double ar = 0, ai = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+    const cplx<double> w = Wv[i + c * ldw];
+    if (V) {
+      const cplx<double> v = V[i + c * ldv];
+      ar += v.re * w.re + v.im * w.im;
+      ai += v.re * w.im - v.im * w.re;
+    } else {
+      ar += w.re * w.re + w.im * w.im;
+    }
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      si[threadIdx.x] += si[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x + (int64_t)c * gridDim.x] = cplx<double>{sr[0], si[0]};
+}
+
+// out[c] = sum_b partial[b, c] in a fixed order (deterministic)
+__global__ void dot_final_kernel(const cplx<double>* __restrict__ partial, int nblk, int nrhs,
+                                 cplx<double>* __restrict__ out, int sqrt_mode) {
+  for (int c = threadIdx.x; c < nrhs; c += blockDim.x) {
+    cplx<double> s = {0, 0};
+    for (int b = 0; b < nblk; ++b) s = cadd(s, partial[b + (int64_t)c * nblk]);
+    if (sqrt_mode) s = cplx<double>{sqrt(s.re), 0};
+    out[c] = s;
+  }
+}
+
+// W(:, c) += sign * a[c] * V(:, c)
+__global__ void axpy_cols_kernel(const cplx<double>* __restrict__ a, double sign, const cplx<double>* __restrict__ V,
+                                 int64_t ldv, cplx<double>* __restrict__ Wv, int64_t ldw, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= N) return;
+  const cplx<double> s = {sign * a[c].re, sign * a[c].im};
+  Wv[i + c * ldw] = cadd(Wv[i + c * ldw], cmul(s, V[i + c * ldv]));
+}
+
+// V(:, c) = W(:, c) / nrm[c].re (0 if nrm is 0)
+__global__ void scale_cols_kernel(const cplx<double>* __restrict__ nrm, const cplx<double>* __restrict__ Wv,
+                                  int64_t ldw, cplx<double>* __restrict__ V, int64_t ldv, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= N) return;
+  const double d = nrm[c].re;
+  const double s = d > 0 ? 1.0 / d : 0.0;
+  const cplx<double> w = Wv[i + c * ldw];
+  V[i + c * ldv] = cplx<double>{w.re * s, w.im * s};
+}
+
+// X(:, c) += sum_{i < m} y[i, c] * Vbasis_i(:, c); basis i at V + i * vstride
+__global__ void basis_update_kernel(const cplx<double>* __restrict__ y, int ldy, int m,
+                                    const cplx<double>* __restrict__ V, int64_t vstride, int64_t ldv,
+                                    cplx<double>* __restrict__ X, int64_t ldx, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= N) return;
+  cplx<double> s = X[i + c * ldx];
+  for (int k = 0; k < m; ++k) s = cadd(s, cmul(y[k + c * ldy], V[k * vstride + i + c * ldv]));
+  X[i + c * ldx] = s;
+}
+
+// ------------------------------------------------------------------ launchers
+#define KCHECK(expr)                   \
+  do {                                 \
+    hipError_t e__ = (expr);           \
+    if (e__ != hipSuccess) return e__; \
+  } while (0)
+
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <class T>
+hipError_t launch_permute_in(const void* B, int64_t ldb, void* y, const int64_t* perm, int64_t N, int nrhs,
+                             hipStream_t s) {
+  hipLaunchKernelGGL((permute_in_kernel<T>), dim3(blocks_for(N, 256), nrhs), dim3(256), 0, s,
+                     (const cplx<double>*)B, ldb, (cplx<T>*)y, perm, N);
+  return hipGetLastError();
+}
+template <class T>
+hipError_t launch_permute_out(const void* x, void* X, int64_t ldx, const int64_t* perm, int64_t N, int nrhs,
+                              hipStream_t s) {
+  hipLaunchKernelGGL((permute_out_kernel<T>), dim3(blocks_for(N, 256), nrhs), dim3(256), 0, s,
+                     (const cplx<T>*)x, (cplx<double>*)X, ldx, perm, N);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_forward_level(const FrontDesc* d_fds, int nbatch, int maxn, int maxnu, const void* y, int64_t N,
+                                int nrhs, hipStream_t s) {
+  if (nbatch == 0) return hipSuccess;
+  (void)maxnu;
+  hipLaunchKernelGGL((fwd_gather_kernel<T>), dim3(blocks_for(maxn, 256), nbatch), dim3(256), 0, s, d_fds,
+                     (const cplx<T>*)y, N, nrhs);
+  KCHECK(hipGetLastError());
+  hipLaunchKernelGGL((fwd_trsv_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, nrhs);
+  KCHECK(hipGetLastError());
+  const int tiles = (int)(blocks_for(maxn, GEMM_TM) * blocks_for(nrhs, GEMM_TN));
+  hipLaunchKernelGGL((sweep_gemm_kernel<T>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs, 0);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_backward_level(const FrontDesc* d_fds, int nbatch, int maxn, int maxnu, void* x, int64_t N,
+                                 int nrhs, hipStream_t s) {
+  if (nbatch == 0) return hipSuccess;
+  if (maxnu > 0) {
+    hipLaunchKernelGGL((bwd_gather_kernel<T>), dim3(blocks_for(maxnu, 256), nbatch), dim3(256), 0, s, d_fds,
+                       (const cplx<T>*)x, N, nrhs);
+    KCHECK(hipGetLastError());
+    const int tiles = (int)(blocks_for(maxn, GEMM_TM) * blocks_for(nrhs, GEMM_TN));
+    hipLaunchKernelGGL((sweep_gemm_kernel<T>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs, 1);
+    KCHECK(hipGetLastError());
+  }
+  hipLaunchKernelGGL((bwd_trsv_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, (cplx<T>*)x, N, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv(const int64_t* rowptr, const int32_t* colind, const void* val, const void* X, int64_t ldx,
+                       void* Y, int64_t ldy, const void* B, int64_t ldb, int64_t N, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(spmv_kernel, dim3(blocks_for(N, 256), nrhs), dim3(256), 0, s, rowptr, colind,
+                     (const cplx<double>*)val, (const cplx<double>*)X, ldx, (cplx<double>*)Y, ldy,
+                     (const cplx<double>*)B, ldb, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_dots(const void* V, int64_t ldv, const void* Wv, int64_t ldw, int64_t N, int nrhs, void* partial,
+                       int nblk, void* out, bool norm, hipStream_t s) {
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(nblk, nrhs), dim3(256), 0, s, (const cplx<double>*)V, ldv,
+                     (const cplx<double>*)Wv, ldw, N, (cplx<double>*)partial);
+  KCHECK(hipGetLastError());
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(256), 0, s, (const cplx<double>*)partial, nblk, nrhs,
+                     (cplx<double>*)out, norm ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_cols(const void* a, double sign, const void* V, int64_t ldv, void* Wv, int64_t ldw, int64_t N,
+                            int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(axpy_cols_kernel, dim3(blocks_for(N, 256), nrhs), dim3(256), 0, s, (const cplx<double>*)a,
+                     sign, (const cplx<double>*)V, ldv, (cplx<double>*)Wv, ldw, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_cols(const void* nrm, const void* Wv, int64_t ldw, void* V, int64_t ldv, int64_t N, int nrhs,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(scale_cols_kernel, dim3(blocks_for(N, 256), nrhs), dim3(256), 0, s, (const cplx<double>*)nrm,
+                     (const cplx<double>*)Wv, ldw, (cplx<double>*)V, ldv, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_basis_update(const void* y, int ldy, int m, const void* V, int64_t vstride, int64_t ldv, void* X,
+                               int64_t ldx, int64_t N, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(basis_update_kernel, dim3(blocks_for(N, 256), nrhs), dim3(256), 0, s, (const cplx<double>*)y,
+                     ldy, m, (const cplx<double>*)V, vstride, ldv, (cplx<double>*)X, ldx, N);
+  return hipGetLastError();
+}
+
+template hipError_t launch_permute_in<double>(const void*, int64_t, void*, const int64_t*, int64_t, int, hipStream_t);
+template hipError_t launch_permute_in<float>(const void*, int64_t, void*, const int64_t*, int64_t, int, hipStream_t);
+template hipError_t launch_permute_out<double>(const void*, void*, int64_t, const int64_t*, int64_t, int, hipStream_t);
+template hipError_t launch_permute_out<float>(const void*, void*, int64_t, const int64_t*, int64_t, int, hipStream_t);
+template hipError_t launch_forward_level<double>(const FrontDesc*, int, int, int, const void*, int64_t, int,
+                                                 hipStream_t);
+template hipError_t launch_forward_level<float>(const FrontDesc*, int, int, int, const void*, int64_t, int,
+                                                hipStream_t);
+template hipError_t launch_backward_level<double>(const FrontDesc*, int, int, int, void*, int64_t, int, hipStream_t);
+template hipError_t launch_backward_level<float>(const FrontDesc*, int, int, int, void*, int64_t, int, hipStream_t);
+
+}  // namespace bfmf

@@ -1,0 +1,512 @@
+// Numerical factorization of the dense fronts, the preconditioner sweeps and
+// the FP64 GMRES driver.
+//
+// Factorization (Alg. 1): fronts are processed level by level from the
+// deepest level to the root.  With opts.batched every kernel of a level is one
+// launch over all fronts of the level; otherwise every front gets its own
+// launches (the plain form).  The arena keeps every front in place: F11 holds
+// L\U, F12 holds L^-1 P^T F12, F21 holds F21 U^-1 and F22 the contribution
+// block C that the parent reads during its extend-add.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+#include "context.hpp"
+#include "kernels/kernels.hpp"
+
+namespace bfmf {
+
+namespace {
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void alloc(DevBuf& b, size_t bytes) {
+  b.release();
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    throw Error(BFMF_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  b.bytes = bytes;
+}
+
+void check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Error(BFMF_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+hipEvent_t KernelTimer::take() {
+  if (used == pool.size()) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    pool.push_back(e);
+  }
+  return pool[used++];
+}
+
+int KernelTimer::begin(hipStream_t s) {
+  if (!enabled) return -1;
+  Rec r;
+  r.kind = -1;
+  r.a = take();
+  r.b = take();
+  r.flops = r.bytes = 0;
+  HIPCHK(hipEventRecord(r.a, s));
+  recs.push_back(r);
+  return (int)recs.size() - 1;
+}
+
+void KernelTimer::end(int token, hipStream_t s, int kind, double fl, double by) {
+  if (token < 0) return;
+  Rec& r = recs[token];
+  r.kind = kind;
+  r.flops = fl;
+  r.bytes = by;
+  HIPCHK(hipEventRecord(r.b, s));
+}
+
+void KernelTimer::collect() {
+  for (const Rec& r : recs) {
+    if (r.kind < 0) continue;
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    launches[r.kind] += 1;
+    seconds[r.kind] += ms * 1e-3;
+    flops[r.kind] += r.flops;
+    bytes[r.kind] += r.bytes;
+  }
+  recs.clear();
+  used = 0;
+}
+
+void KernelTimer::reset() {
+  recs.clear();
+  used = 0;
+  for (int k = 0; k < K_COUNT; ++k) {
+    launches[k] = 0;
+    seconds[k] = flops[k] = bytes[k] = 0;
+  }
+}
+
+KernelTimer::~KernelTimer() {
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
+void factor_dense(Context& c) {
+  const int32_t nf = c.sym.nfronts();
+  const size_t elem = sizeof(double) * 2;
+  const size_t need = (size_t)c.arena_elems * elem;
+  size_t free_b = 0, total_b = 0;
+  HIPCHK(hipMemGetInfo(&free_b, &total_b));
+  const uint64_t budget = c.fopts.hbm_budget ? c.fopts.hbm_budget : (uint64_t)free_b;
+  if (need > budget || need > free_b)
+    throw Error(BFMF_E_NOMEM, "dense front arena needs " + std::to_string(need) + " bytes, budget " +
+                                  std::to_string(std::min<uint64_t>(budget, free_b)));
+  if (c.d_arena.bytes < need) alloc(c.d_arena, need);
+  if (c.fopts.keep_fronts) {
+    if (c.d_kept.bytes < need) alloc(c.d_kept, need);
+  } else {
+    c.d_kept.release();
+  }
+  // descriptors in level order
+  char* arena = c.d_arena.as<char>();
+  c.h_fds.assign(nf, FrontDesc());
+  for (int32_t k = 0; k < nf; ++k) {
+    const int32_t f = c.level_fronts[k];
+    const FrontPlan& p = c.fp[f];
+    FrontDesc& d = c.h_fds[k];
+    std::memset(&d, 0, sizeof(d));
+    d.F = arena + p.f_off * elem;
+    d.n = p.n;
+    d.ns = p.ns;
+    d.nchild = p.nchild;
+    d.front = f;
+    d.sbeg = c.sym.sbeg[f];
+    for (int q = 0; q < p.nchild; ++q) {
+      const FrontPlan& cp = c.fp[p.child[q]];
+      d.inv[q] = c.d_inv.as<int32_t>() + p.inv_off[q];
+      d.cb[q] = arena + (cp.f_off + cp.ns + (int64_t)cp.ns * cp.n) * elem;
+      d.cb_ld[q] = cp.n;
+    }
+    d.a_ptr = c.d_aptr.as<int64_t>() + p.aptr_off;
+    d.a_row = c.d_arow.as<int32_t>();
+    d.a_vidx = c.d_avidx.as<int64_t>();
+    d.piv = c.d_piv.as<int32_t>() + p.piv_off;
+    d.iu = c.d_iu32.as<int32_t>() + p.iu_off;
+  }
+  if (c.d_fds.bytes < nf * sizeof(FrontDesc)) alloc(c.d_fds, nf * sizeof(FrontDesc));
+  HIPCHK(hipMemcpy(c.d_fds.p, c.h_fds.data(), nf * sizeof(FrontDesc), hipMemcpyHostToDevice));
+  HIPCHK(hipMemsetAsync(c.d_status.p, 0, 16, c.stream));
+
+  const double t0 = now();
+  FrontDesc* dfds = c.d_fds.as<FrontDesc>();
+  std::vector<int> hn, hns;
+  const int nlev = (int)c.level_ptr.size() - 1;
+  for (int L = 0; L < nlev; ++L) {
+    const int b = c.level_ptr[L], e = c.level_ptr[L + 1];
+    auto run = [&](int lo, int hi) {
+      hn.clear();
+      hns.clear();
+      int maxn = 0;
+      double asm_bytes = 0, lu_flops = 0, sch_flops = 0, sch_bytes = 0;
+      for (int k = lo; k < hi; ++k) {
+        const int32_t f = c.level_fronts[k];
+        const FrontPlan& p = c.fp[f];
+        hn.push_back(p.n);
+        hns.push_back(p.ns);
+        maxn = std::max(maxn, p.n);
+        const double n = p.n, ns = p.ns, nu = p.nu;
+        double cb = 0;
+        for (int q = 0; q < p.nchild; ++q) cb += (double)c.fp[p.child[q]].nu * c.fp[p.child[q]].nu;
+        const double na = (double)(c.h_aptr[p.aptr_off + p.n] - c.h_aptr[p.aptr_off]);
+        asm_bytes += elem * (n * n + cb) + 28.0 * na + 4.0 * n * p.nchild + 8.0 * (n + 1);
+        lu_flops += 8.0 / 3.0 * ns * ns * ns + 8.0 * ns * ns * nu;
+        sch_flops += 8.0 * ns * nu * nu;
+        sch_bytes += elem * (2.0 * ns * nu + 2.0 * nu * nu);
+      }
+      int tk = c.timer.begin(c.stream);
+      check(launch_assemble<double>(dfds + lo, hi - lo, maxn, c.d_values.p, false, c.stream), "assemble");
+      c.timer.end(tk, c.stream, K_ASSEMBLE, 0, asm_bytes);
+      if (c.fopts.keep_fronts) {
+        for (int k = lo; k < hi; ++k) {
+          const FrontPlan& p = c.fp[c.level_fronts[k]];
+          HIPCHK(hipMemcpyAsync(c.d_kept.as<char>() + p.f_off * elem, arena + p.f_off * elem,
+                                (size_t)p.n * p.n * elem, hipMemcpyDeviceToDevice, c.stream));
+        }
+      }
+      tk = c.timer.begin(c.stream);
+      check(launch_partial_lu<double>(dfds + lo, hi - lo, hn.data(), hns.data(), c.d_status.as<int>(), c.stream),
+            "partial LU");
+      c.timer.end(tk, c.stream, K_LU, lu_flops, 0);
+      tk = c.timer.begin(c.stream);
+      check(launch_schur<double>(dfds + lo, hi - lo, hn.data(), hns.data(), c.stream), "schur");
+      c.timer.end(tk, c.stream, K_SCHUR, sch_flops, sch_bytes);
+    };
+    if (c.fopts.batched) {
+      run(b, e);
+    } else {
+      for (int k = b; k < e; ++k) run(k, k + 1);
+    }
+  }
+  HIPCHK(hipStreamSynchronize(c.stream));
+  c.stats.factor_seconds = now() - t0;
+  c.timer.collect();
+  int st[3] = {0, 0, 0};
+  HIPCHK(hipMemcpy(st, c.d_status.p, sizeof(st), hipMemcpyDeviceToHost));
+  c.stats.singular_front = st[0] ? st[1] : -1;
+  c.stats.singular_index = st[0] ? st[2] : -1;
+  if (st[0]) throw Error(BFMF_E_SINGULAR, "exact zero pivot in front " + std::to_string(st[1]) + " at local index " +
+                                              std::to_string(st[2]));
+  double flops = 0, bytes = 0;
+  for (int32_t f = 0; f < nf; ++f) {
+    const double ns = c.fp[f].ns, nu = c.fp[f].nu;
+    flops += 8.0 / 3.0 * ns * ns * ns + 8.0 * ns * ns * nu + 8.0 * ns * nu * nu;
+    bytes += (ns * ns + 2 * ns * nu) * elem;
+  }
+  c.stats.factor_flops = flops;
+  c.stats.factor_bytes = bytes;
+  c.stats.dense_factor_bytes = bytes;
+  c.stats.nfronts = nf;
+  c.stats.compressed_fronts = 0;
+  c.stats.dense_fronts = nf;
+  c.stats.nlevels = nlev;
+  c.stats.solve_flops_per_rhs = 0;
+  for (int32_t f = 0; f < nf; ++f) {
+    const double ns = c.fp[f].ns, nu = c.fp[f].nu;
+    c.stats.solve_flops_per_rhs += 8.0 * (ns * ns + 2 * ns * nu);
+  }
+}
+
+void ensure_workspace(Context& c, int64_t nrhs) {
+  const size_t elem = sizeof(double) * 2;
+  if (c.ws_nrhs < nrhs) {
+    alloc(c.d_W, (size_t)c.sum_n * nrhs * elem);
+    alloc(c.d_y, (size_t)c.n * nrhs * elem);
+    alloc(c.d_x, (size_t)c.n * nrhs * elem);
+    c.ws_nrhs = nrhs;
+  }
+  // W pointers depend on nrhs: W_f at sum_{g<f} n_g * nrhs
+  char* W = c.d_W.as<char>();
+  const int32_t nf = c.sym.nfronts();
+  for (int32_t k = 0; k < nf; ++k) {
+    const int32_t f = c.level_fronts[k];
+    const FrontPlan& p = c.fp[f];
+    FrontDesc& d = c.h_fds[k];
+    d.W = W + p.w_off * nrhs * elem;
+    for (int q = 0; q < p.nchild; ++q) {
+      const FrontPlan& cp = c.fp[p.child[q]];
+      d.cw[q] = W + (cp.w_off * nrhs + cp.ns) * elem;
+      d.cw_ld[q] = cp.n;
+    }
+  }
+  HIPCHK(hipMemcpyAsync(c.d_fds.p, c.h_fds.data(), nf * sizeof(FrontDesc), hipMemcpyHostToDevice, c.stream));
+}
+
+void apply_preconditioner_dev(Context& c, const void* dB, int64_t ldb, void* dX, int64_t ldx, int64_t nrhs) {
+  ensure_workspace(c, nrhs);
+  FrontDesc* dfds = c.d_fds.as<FrontDesc>();
+  check(launch_permute_in<double>(dB, ldb, c.d_y.p, c.d_perm.as<int64_t>(), c.n, (int)nrhs, c.stream), "permute");
+  const int nlev = (int)c.level_ptr.size() - 1;
+  double lvl_bytes = 0, lvl_flops = 0;
+  const double elem = 16.0;
+  auto level_sizes = [&](int lo, int hi, int& maxn, int& maxnu) {
+    maxn = 0;
+    maxnu = 0;
+    lvl_bytes = lvl_flops = 0;
+    for (int k = lo; k < hi; ++k) {
+      const FrontPlan& p = c.fp[c.level_fronts[k]];
+      maxn = std::max(maxn, p.n);
+      maxnu = std::max(maxnu, p.nu);
+      const double ns = p.ns, nu = p.nu;
+      // half of F11 (L or U) plus F21 or F12, read once; vectors in and out
+      lvl_bytes += elem * (0.5 * ns * ns + ns * nu) + elem * 3.0 * (ns + nu) * nrhs;
+      lvl_flops += 8.0 * (0.5 * ns * ns + ns * nu) * nrhs;
+    }
+  };
+  for (int L = 0; L < nlev; ++L) {
+    const int b = c.level_ptr[L], e = c.level_ptr[L + 1];
+    if (c.fopts.batched) {
+      int mn, mu;
+      level_sizes(b, e, mn, mu);
+      const int tk = c.timer.begin(c.stream);
+      check(launch_forward_level<double>(dfds + b, e - b, mn, mu, c.d_y.p, c.n, (int)nrhs, c.stream), "fwd");
+      c.timer.end(tk, c.stream, K_FWD, lvl_flops, lvl_bytes);
+    } else {
+      for (int k = b; k < e; ++k) {
+        int mn, mu;
+        level_sizes(k, k + 1, mn, mu);
+        const int tk = c.timer.begin(c.stream);
+        check(launch_forward_level<double>(dfds + k, 1, mn, mu, c.d_y.p, c.n, (int)nrhs, c.stream), "fwd");
+        c.timer.end(tk, c.stream, K_FWD, lvl_flops, lvl_bytes);
+      }
+    }
+  }
+  for (int L = nlev - 1; L >= 0; --L) {
+    const int b = c.level_ptr[L], e = c.level_ptr[L + 1];
+    if (c.fopts.batched) {
+      int mn, mu;
+      level_sizes(b, e, mn, mu);
+      const int tk = c.timer.begin(c.stream);
+      check(launch_backward_level<double>(dfds + b, e - b, mn, mu, c.d_x.p, c.n, (int)nrhs, c.stream), "bwd");
+      c.timer.end(tk, c.stream, K_BWD, lvl_flops, lvl_bytes);
+    } else {
+      for (int k = e - 1; k >= b; --k) {
+        int mn, mu;
+        level_sizes(k, k + 1, mn, mu);
+        const int tk = c.timer.begin(c.stream);
+        check(launch_backward_level<double>(dfds + k, 1, mn, mu, c.d_x.p, c.n, (int)nrhs, c.stream), "bwd");
+        c.timer.end(tk, c.stream, K_BWD, lvl_flops, lvl_bytes);
+      }
+    }
+  }
+  check(launch_permute_out<double>(c.d_x.p, dX, ldx, c.d_perm.as<int64_t>(), c.n, (int)nrhs, c.stream), "permute");
+}
+
+// ------------------------------------------------------------------ GMRES
+int gmres_dev(Context& c, const void* dB, int64_t ldb, void* dX, int64_t ldx, int64_t nrhs, bfmf_solve_opts& o) {
+  typedef std::complex<double> cd;
+  const int64_t N = c.n;
+  const int m = std::max(1, o.restart);
+  const size_t elem = sizeof(cd);
+  const size_t blk = (size_t)N * nrhs * elem;
+  if (c.g_nrhs < nrhs || c.g_restart < m) {
+    alloc(c.g_V, blk * (m + 1));
+    alloc(c.g_w, blk);
+    alloc(c.g_r, blk);
+    alloc(c.g_tmp, blk);
+    alloc(c.g_scal, (size_t)(m + 2) * nrhs * elem * 2);
+    alloc(c.g_part, (size_t)256 * nrhs * elem);
+    c.g_nrhs = nrhs;
+    c.g_restart = m;
+  }
+  const int nblk = (int)std::min<int64_t>(256, (N + 255) / 256);
+  cd* V = c.g_V.as<cd>();
+  cd* w = c.g_w.as<cd>();
+  cd* r = c.g_r.as<cd>();
+  cd* tmp = c.g_tmp.as<cd>();
+  cd* hcol = c.g_scal.as<cd>();           // (m+2) x nrhs
+  cd* ydev = hcol + (size_t)(m + 2) * nrhs;  // m x nrhs
+  const int nr = (int)nrhs;
+  const int64_t vstride = N * nrhs;
+  auto Vi = [&](int i) { return V + (size_t)i * vstride; };
+  const int64_t* rp = c.d_rowptr.as<int64_t>();
+  const int32_t* ci = c.d_colind.as<int32_t>();
+  const void* va = c.d_values.p;
+  const double spmv_bytes = 20.0 * c.nnz + 8.0 * (N + 1) + 2.0 * elem * N * nrhs;
+  const double spmv_flops = 8.0 * c.nnz * nrhs;
+  auto spmv = [&](const void* X, int64_t ldx_, void* Y, int64_t ldy_, const void* B_, int64_t ldb_) {
+    const int tk = c.timer.begin(c.stream);
+    check(launch_spmv(rp, ci, va, X, ldx_, Y, ldy_, B_, ldb_, N, (int)nrhs, c.stream), "spmv");
+    c.timer.end(tk, c.stream, K_SPMV, spmv_flops, spmv_bytes);
+  };
+
+  for (int q = 0; q < nr; ++q) HIPCHK(hipMemsetAsync((cd*)dX + q * ldx, 0, N * elem, c.stream));
+  std::vector<cd> hb(nr);
+  check(launch_dots(nullptr, 0, dB, ldb, N, nr, c.g_part.p, nblk, hcol, true, c.stream), "norm");
+  HIPCHK(hipMemcpyAsync(hb.data(), hcol, nr * elem, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(hipStreamSynchronize(c.stream));
+  std::vector<double> bnorm(nr), u0(nr, -1), tol_c(nr, o.rtol);
+  for (int q = 0; q < nr; ++q) bnorm[q] = hb[q].real();
+  std::vector<char> done(nr, 0);
+  std::vector<int> iters(nr, 0);
+  std::vector<cd> H((size_t)(m + 1) * m * nr), g((size_t)(m + 1) * nr), cs((size_t)m * nr), sn((size_t)m * nr);
+  std::vector<cd> hh((size_t)(m + 2) * nr), yh((size_t)m * nr);
+  std::vector<int> steps(nr);
+  std::vector<double> relres(nr, 1.0);
+  int total = 0;
+  for (int q = 0; q < nr; ++q)
+    if (bnorm[q] == 0) done[q] = 1;
+
+  auto true_residual = [&]() {
+    spmv(dX, ldx, r, N, dB, ldb);
+    check(launch_dots(nullptr, 0, r, N, N, nr, c.g_part.p, nblk, hcol, true, c.stream), "norm");
+    HIPCHK(hipMemcpyAsync(hh.data(), hcol, nr * elem, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    for (int q = 0; q < nr; ++q) relres[q] = bnorm[q] > 0 ? hh[q].real() / bnorm[q] : 0.0;
+  };
+
+  while (total < o.max_iter) {
+    bool any = false;
+    for (int q = 0; q < nr; ++q) any |= !done[q];
+    if (!any) break;
+    // r = b - A x ; V0 = M^-1 r
+    spmv(dX, ldx, r, N, dB, ldb);
+    apply_preconditioner_dev(c, r, N, Vi(0), N, nr);
+    check(launch_dots(nullptr, 0, Vi(0), N, N, nr, c.g_part.p, nblk, hcol, true, c.stream), "norm");
+    HIPCHK(hipMemcpyAsync(hh.data(), hcol, nr * elem, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    std::vector<char> active(nr, 0);
+    for (int q = 0; q < nr; ++q) {
+      const double beta = hh[q].real();
+      if (u0[q] < 0) u0[q] = beta;
+      if (done[q]) continue;
+      if (beta <= o.atol || (u0[q] > 0 && beta / u0[q] <= tol_c[q])) {
+        done[q] = 1;
+        continue;
+      }
+      active[q] = 1;
+      std::fill(g.begin() + (size_t)q * (m + 1), g.begin() + (size_t)(q + 1) * (m + 1), cd(0));
+      g[(size_t)q * (m + 1)] = beta;
+      steps[q] = 0;
+    }
+    check(launch_scale_cols(hcol, Vi(0), N, Vi(0), N, N, nr, c.stream), "scale");
+    bool cycle_active = false;
+    for (int q = 0; q < nr; ++q) cycle_active |= active[q];
+    if (!cycle_active) break;
+    for (int j = 0; j < m && total < o.max_iter; ++j) {
+      spmv(Vi(j), N, tmp, N, nullptr, 0);
+      apply_preconditioner_dev(c, tmp, N, w, N, nr);
+      for (int i = 0; i <= j; ++i) {  // modified Gram-Schmidt
+        check(launch_dots(Vi(i), N, w, N, N, nr, c.g_part.p, nblk, hcol + (size_t)i * nr, false, c.stream), "dot");
+        check(launch_axpy_cols(hcol + (size_t)i * nr, -1.0, Vi(i), N, w, N, N, nr, c.stream), "axpy");
+      }
+      check(launch_dots(nullptr, 0, w, N, N, nr, c.g_part.p, nblk, hcol + (size_t)(j + 1) * nr, true, c.stream),
+            "norm");
+      check(launch_scale_cols(hcol + (size_t)(j + 1) * nr, w, N, Vi(j + 1), N, N, nr, c.stream), "scale");
+      HIPCHK(hipMemcpyAsync(hh.data(), hcol, (size_t)(j + 2) * nr * elem, hipMemcpyDeviceToHost, c.stream));
+      HIPCHK(hipStreamSynchronize(c.stream));
+      ++total;
+      bool still = false;
+      for (int q = 0; q < nr; ++q) {
+        if (!active[q]) continue;
+        cd* Hq = H.data() + (size_t)q * (m + 1) * m;
+        cd* gq = g.data() + (size_t)q * (m + 1);
+        cd* csq = cs.data() + (size_t)q * m;
+        cd* snq = sn.data() + (size_t)q * m;
+        for (int i = 0; i <= j + 1; ++i) Hq[i + (size_t)j * (m + 1)] = hh[(size_t)i * nr + q];
+        for (int i = 0; i < j; ++i) {  // previous rotations
+          cd a = Hq[i + (size_t)j * (m + 1)], b = Hq[i + 1 + (size_t)j * (m + 1)];
+          Hq[i + (size_t)j * (m + 1)] = csq[i] * a + snq[i] * b;
+          Hq[i + 1 + (size_t)j * (m + 1)] = -std::conj(snq[i]) * a + std::conj(csq[i]) * b;
+        }
+        cd a = Hq[j + (size_t)j * (m + 1)], b = Hq[j + 1 + (size_t)j * (m + 1)];
+        const double den = std::sqrt(std::norm(a) + std::norm(b));
+        if (den == 0) {
+          csq[j] = 1;
+          snq[j] = 0;
+        } else if (std::abs(a) == 0) {
+          csq[j] = 0;
+          snq[j] = std::conj(b) / den;
+        } else {
+          csq[j] = std::abs(a) / den;
+          snq[j] = (a / std::abs(a)) * std::conj(b) / den;
+        }
+        Hq[j + (size_t)j * (m + 1)] = csq[j] * a + snq[j] * b;
+        Hq[j + 1 + (size_t)j * (m + 1)] = 0;
+        gq[j + 1] = -std::conj(snq[j]) * gq[j];
+        gq[j] = csq[j] * gq[j];
+        steps[q] = j + 1;
+        iters[q]++;
+        const double res = std::abs(gq[j + 1]);
+        if (res <= o.atol || res / u0[q] <= tol_c[q] || hh[(size_t)(j + 1) * nr + q].real() == 0) {
+          active[q] = 0;
+        } else {
+          still = true;
+        }
+      }
+      if (!still) break;
+    }
+    // x += V y per column
+    int mmax = 0;
+    std::fill(yh.begin(), yh.end(), cd(0));
+    for (int q = 0; q < nr; ++q) {
+      const int k = steps[q];
+      if (k == 0) continue;
+      mmax = std::max(mmax, k);
+      cd* Hq = H.data() + (size_t)q * (m + 1) * m;
+      cd* gq = g.data() + (size_t)q * (m + 1);
+      for (int i = k - 1; i >= 0; --i) {
+        cd s = gq[i];
+        for (int l = i + 1; l < k; ++l) s -= Hq[i + (size_t)l * (m + 1)] * yh[l + (size_t)q * m];
+        yh[i + (size_t)q * m] = s / Hq[i + (size_t)i * (m + 1)];
+      }
+      steps[q] = 0;
+    }
+    if (mmax > 0) {
+      HIPCHK(hipMemcpyAsync(ydev, yh.data(), (size_t)m * nr * elem, hipMemcpyHostToDevice, c.stream));
+      check(launch_basis_update(ydev, m, mmax, V, vstride, N, dX, ldx, N, nr, c.stream), "update");
+    }
+    // columns that met the preconditioned criterion: check the true residual
+    bool need_true = o.true_rtol > 0;
+    bool all_done = true;
+    for (int q = 0; q < nr; ++q) all_done &= (bool)(done[q] || !active[q]);
+    if (need_true) {
+      true_residual();
+      for (int q = 0; q < nr; ++q) {
+        if (relres[q] > o.true_rtol) {
+          // the preconditioned stop came too early for this column: tighten it
+          if (done[q] || !active[q]) tol_c[q] *= 0.1;
+          done[q] = 0;
+        } else {
+          done[q] = 1;
+        }
+      }
+    } else {
+      for (int q = 0; q < nr; ++q)
+        if (!active[q]) done[q] = 1;
+    }
+    (void)all_done;
+  }
+  true_residual();
+  c.timer.collect();
+  o.iters_max = 0;
+  o.relres_max = 0;
+  for (int q = 0; q < nr; ++q) {
+    o.iters_max = std::max(o.iters_max, iters[q]);
+    o.relres_max = std::max(o.relres_max, relres[q]);
+  }
+  bool ok = true;
+  for (int q = 0; q < nr; ++q) ok &= (bool)done[q];
+  return ok ? 0 : 1;
+}
+
+}  // namespace bfmf

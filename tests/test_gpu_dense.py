@@ -1,0 +1,126 @@
+"""GPU parity of the dense multifrontal path through the C ABI.
+
+* Extend-add (kernel a): every assembled front equals the oracle's assembly of
+  the same A entries and the same child contribution blocks, bit for bit
+  (FP64, same addition order).
+* Partial LU (kernel d): the factored front matches the oracle's LAPACK
+  partial factorization of the same assembled front (pivots equal, values
+  to 1e-11 relative).
+* Sweeps (kernel e) and GMRES: x matches the oracle's solve to 1e-10; with
+  the exact factorization GMRES stops after one iteration.
+"""
+import numpy as np
+import pytest
+
+from workloads import helmholtz_7pt, make_problem, rng_for
+from oracle import nd
+from oracle.symbolic import symbolic
+from oracle import multifrontal as mf
+
+pytestmark = pytest.mark.gpu
+
+
+def maxabs(a):
+    return float(np.abs(a).max()) if a.size else 0.0
+
+
+def _setup(lib, dims, leaf, sl=16, batched=False, delta=0.05):
+    rp, ci, v, _ = helmholtz_7pt(dims, delta)
+    s = lib.Solver(0).analyze(rp, ci, v, dims=dims, leaf_max=leaf, sep_leaf=sl)
+    s.factor(n_min=0, batched=batched, keep_fronts=True)
+    od = nd.nd_grid(dims, leaf_max=leaf, sep_leaf=sl)
+    sym = symbolic(rp, ci, od)
+    return s, (rp, ci, v), od, sym
+
+
+@pytest.mark.parametrize("dims,leaf,batched", [((8, 8, 8), 64, False), ((9, 7, 6), 40, True),
+                                               ((24, 24, 24), 512, True)])
+def test_extend_add_bit_exact_and_partial_lu(gpu_lib, dims, leaf, batched):
+    s, (rp, ci, v), od, sym = _setup(gpu_lib, dims, leaf, batched=batched)
+    gpu_cb = {}
+    for f in range(od.nfronts):
+        ns = int(od.send[f] - od.sbeg[f])
+        Fa = s.front(f, 0)
+        Ff = s.front(f, 1)
+        piv = s.front(f, 2)
+        # oracle assembly of the same A entries and the GPU's child blocks
+        want = mf.assemble_front(rp, ci, v, od, sym, f, gpu_cb)
+        assert np.array_equal(Fa, want), f"front {f}: assembly differs"
+        lu, opiv, F12, F21, C = mf.partial_lu(want.copy(), ns)
+        assert np.array_equal(piv, opiv), f"front {f}: pivots differ"
+        scale = max(1.0, np.abs(want).max())
+        assert maxabs(Ff[:ns, :ns] - lu) <= 1e-11 * scale
+        assert maxabs(Ff[:ns, ns:] - F12) <= 1e-11 * scale
+        assert maxabs(Ff[ns:, :ns] - F21) <= 1e-11 * scale
+        assert maxabs(Ff[ns:, ns:] - C) <= 1e-11 * scale
+        gpu_cb[f] = Ff[ns:, ns:]
+    s.close()
+
+
+@pytest.mark.parametrize("dims,leaf,nrhs,batched", [((8, 8, 8), 64, 1, False), ((10, 9, 8), 64, 3, True),
+                                                    ((12, 12, 12), 100, 70, True), ((2, 2, 2), 512, 2, False)])
+def test_preconditioner_matches_oracle_solve(gpu_lib, dims, leaf, nrhs, batched):
+    rp, ci, v, _ = helmholtz_7pt(dims, 0.05)
+    od = nd.nd_grid(dims, leaf_max=leaf, sep_leaf=16)
+    fac = mf.factor(rp, ci, v, od)
+    rng = rng_for("test", "rhs", (nrhs,))
+    B = rng.standard_normal((od.n, nrhs)) + 1j * rng.standard_normal((od.n, nrhs))
+    s = gpu_lib.Solver(0).analyze(rp, ci, v, dims=dims, leaf_max=leaf, sep_leaf=16)
+    s.factor(n_min=0, batched=batched)
+    X = s.precondition(B)
+    Xo = mf.solve(fac, B)
+    assert np.linalg.norm(X - Xo) <= 1e-10 * np.linalg.norm(Xo)
+    Xg, info = s.solve(B)
+    assert info["status"] == 0 and info["iters"] <= 1
+    assert np.all(mf.rel_residual(rp, ci, v, Xg, B) <= 1e-12)
+    s.close()
+
+
+def test_batched_equals_plain_bitwise(gpu_lib):
+    dims = (10, 10, 10)
+    rp, ci, v, _ = helmholtz_7pt(dims, 0.05)
+    B = rng_for("test", "rhs").standard_normal((1000, 2)) + 0j
+    out = []
+    for batched in (False, True):
+        s = gpu_lib.Solver(0).analyze(rp, ci, v, dims=dims, leaf_max=64, sep_leaf=16)
+        s.factor(n_min=0, batched=batched)
+        out.append(s.precondition(B))
+        s.close()
+    assert np.array_equal(out[0], out[1])
+
+
+def test_helmholtz24_end_to_end(gpu_lib):
+    p = make_problem("helmholtz24")
+    od = nd.nd_grid(p.dims, leaf_max=512, sep_leaf=64)
+    fac = mf.factor(p.rowptr, p.colind, p.values, od)
+    Xo = mf.solve_refined(p.rowptr, p.colind, p.values, fac, p.rhs, steps=1)
+    s = gpu_lib.Solver(0).analyze(p.rowptr, p.colind, p.values, dims=p.dims)
+    s.factor(n_min=0, batched=True)
+    X, info = s.solve(p.rhs, true_rtol=1e-3)
+    assert info["status"] == 0
+    assert np.linalg.norm(X - Xo) <= 1e-10 * np.linalg.norm(Xo)
+    assert info["relres"] <= 1e-12
+    st = s.stats()
+    assert st["nfronts"] == 63 and st["factor_seconds"] > 0
+    s.close()
+
+
+def test_singular_matrix_reports_front(gpu_lib):
+    dims = (4, 4, 4)
+    rp, ci, v, _ = helmholtz_7pt(dims, 0.05)
+    z = np.zeros_like(v)
+    s = gpu_lib.Solver(0).analyze(rp, ci, z, dims=dims, leaf_max=8)
+    with pytest.raises(gpu_lib.BfmfError) as e:
+        s.factor(n_min=0)
+    assert e.value.status == gpu_lib.BFMF_E_SINGULAR
+    assert s.stats()["singular_front"] >= 0
+    # solve is refused after a failed factorization
+    with pytest.raises(gpu_lib.BfmfError) as e:
+        s.solve(np.ones(64))
+    assert e.value.status == gpu_lib.BFMF_E_STATE
+    # new values bring the handle back
+    gpu_lib.bfmf_set_values(s.h, v)
+    s.factor(n_min=0)
+    X, info = s.solve(np.ones(64))
+    assert info["status"] == 0
+    s.close()
