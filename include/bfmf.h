@@ -215,6 +215,25 @@ enum { BFMF_KERNEL_CLASSES = 7 };
 bfmf_status bfmf_get_kernel_stats(bfmf_handle h, int32_t kind, bfmf_kernel_stat* out);
 bfmf_status bfmf_reset_kernel_stats(bfmf_handle h);
 
+/* Butterfly compression of a caller-given dense matrix (Sec. 3), for
+ * checking the butterfly kernels on their own.  K: m x n complex128,
+ * column-major (ld >= m), host memory, copied.  L: levels of the row and
+ * column trees (halving bisection of [0, m) and [0, n)).  method 0: entry
+ * evaluation with alpha = 4 uniform proxies per block (Alg. 2); method 1:
+ * randomized products with K and K^H (Sec. 3.3), `samples` probes per tree
+ * node (doubled while an ID rank comes within 8 of it).  tol: ID tolerance.
+ * E_INVAL for bad sizes, E_DEVICE / E_NOMEM from the runtime. */
+typedef struct bfmf_bf bfmf_bf;
+bfmf_status bfmf_bf_compress_dense(int32_t device, int32_t m, int32_t n, const double* K, int64_t ldk, int32_t L,
+                                   double tol, int32_t method, int32_t samples, uint64_t seed, bfmf_bf** out);
+/* Y = K X (adjoint = 0, X n x nrhs, Y m x nrhs) or Y = K^H X (adjoint = 1),
+ * host arrays, interleaved complex128, column-major. */
+bfmf_status bfmf_bf_apply(bfmf_bf* b, int32_t adjoint, int32_t nrhs, const double* X, int64_t ldx, double* Y,
+                          int64_t ldy);
+/* levels, largest rank, number of stored complex entries */
+bfmf_status bfmf_bf_info(bfmf_bf* b, int32_t* L, int32_t* max_rank, int64_t* entries);
+void bfmf_bf_destroy(bfmf_bf* b);
+
 const char* bfmf_status_str(bfmf_status s);
 const char* bfmf_last_error(bfmf_handle h);
 void bfmf_destroy(bfmf_handle h);

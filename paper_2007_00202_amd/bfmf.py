@@ -87,6 +87,11 @@ _SIGS = {
     "bfmf_get_front": (C.c_int, [_h, C.c_int32, C.c_int32, _P, C.c_int64]),
     "bfmf_get_kernel_stats": (C.c_int, [_h, C.c_int32, C.POINTER(bfmf_kernel_stat)]),
     "bfmf_reset_kernel_stats": (C.c_int, [_h]),
+    "bfmf_bf_compress_dense": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, C.c_int32, C.c_double,
+                                         C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_P)]),
+    "bfmf_bf_apply": (C.c_int, [_P, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64]),
+    "bfmf_bf_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+    "bfmf_bf_destroy": (None, [_P]),
     "bfmf_status_str": (C.c_char_p, [C.c_int]),
     "bfmf_last_error": (C.c_char_p, [_h]),
     "bfmf_destroy": (None, [_h]),
@@ -256,6 +261,39 @@ def bfmf_last_error(h):
 
 def bfmf_destroy(h):
     _lib.bfmf_destroy(h)
+
+
+def bfmf_bf_compress_dense(K, L, tol, method=0, samples=64, seed=0, device=0):
+    K = np.asfortranarray(K, dtype=np.complex128)
+    m, n = K.shape
+    out = _P()
+    st = _lib.bfmf_bf_compress_dense(device, m, n, _ptr(K), m, L, tol, method, samples, seed, C.byref(out))
+    if st != BFMF_OK:
+        raise BfmfError(st, "bf_compress_dense")
+    return out, (m, n)
+
+
+def bfmf_bf_apply(b, shape, X, adjoint=False):
+    m, n = shape
+    X = np.asfortranarray(X, dtype=np.complex128)
+    if X.ndim == 1:
+        X = X[:, None]
+    rows_out = n if adjoint else m
+    Y = np.zeros((rows_out, X.shape[1]), dtype=np.complex128, order="F")
+    st = _lib.bfmf_bf_apply(b, int(adjoint), X.shape[1], _ptr(X), X.shape[0], _ptr(Y), rows_out)
+    if st != BFMF_OK:
+        raise BfmfError(st, "bf_apply")
+    return Y
+
+
+def bfmf_bf_info(b):
+    L, r, e = C.c_int32(), C.c_int32(), C.c_int64()
+    _lib.bfmf_bf_info(b, C.byref(L), C.byref(r), C.byref(e))
+    return {"L": L.value, "max_rank": r.value, "entries": e.value}
+
+
+def bfmf_bf_destroy(b):
+    _lib.bfmf_bf_destroy(b)
 
 
 # ------------------------------------------------------------ convenience

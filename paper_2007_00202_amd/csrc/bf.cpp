@@ -1,0 +1,1044 @@
+// Butterfly format, products and construction (paper Sec. 3).  See bf.hpp.
+#include "bf.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "kernels/kernels.hpp"
+
+namespace bfmf {
+
+namespace {
+void chk(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Error(BFMF_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+void dev_alloc(DevBuf& b, size_t bytes) {
+  b.release();
+  if (bytes == 0) bytes = 256;
+  if (hipMalloc(&b.p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    throw Error(BFMF_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed (butterfly)");
+  }
+  b.bytes = bytes;
+}
+template <class V>
+void* upload_tmp(Scratch& sc, const std::vector<V>& v, hipStream_t s) {
+  void* d = sc.take(std::max<size_t>(v.size() * sizeof(V), 16));
+  if (!v.empty()) chk(hipMemcpyAsync(d, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, s), "upload");
+  return d;
+}
+}  // namespace
+
+// ------------------------------------------------------------ device memory
+size_t DevPool::alloc(size_t bytes, hipStream_t s) {
+  const size_t off = (used + 255) & ~(size_t)255;
+  const size_t need = off + std::max<size_t>(bytes, 1);
+  if (need > buf.bytes) {
+    size_t cap = std::max<size_t>(need, buf.bytes * 2);
+    cap = std::max<size_t>(cap, (size_t)64 << 20);
+    DevBuf nb;
+    dev_alloc(nb, cap);
+    if (used) chk(hipMemcpyAsync(nb.p, buf.p, used, hipMemcpyDeviceToDevice, s), "pool grow");
+    chk(hipStreamSynchronize(s), "pool grow");
+    std::swap(buf.p, nb.p);
+    std::swap(buf.bytes, nb.bytes);
+  }
+  used = need;
+  return off;
+}
+
+void Scratch::release(const Mark& m) {
+  while (chunks.size() > m.nchunks) chunks.pop_back();
+  if (!chunks.empty()) chunks.back()->top = m.nchunks == chunks.size() ? m.top : chunks.back()->top;
+}
+
+void* Scratch::take(size_t bytes) {
+  bytes = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+  if (chunks.empty() || chunks.back()->top + bytes > chunks.back()->b.bytes) {
+    auto ch = std::make_unique<Chunk>();
+    dev_alloc(ch->b, std::max(bytes, chunk_bytes));
+    chunks.push_back(std::move(ch));
+  }
+  Chunk& c = *chunks.back();
+  void* p = c.b.as<char>() + c.top;
+  c.top += bytes;
+  return p;
+}
+
+// ------------------------------------------------------------------- trees
+int tree_depth(const TreeNode* nodes, int nnodes) {
+  if (!nodes || nnodes == 0) return 0;
+  std::function<int(int)> d = [&](int i) -> int {
+    if (nodes[i].left < 0) return 0;
+    return 1 + std::max(d(nodes[i].left), d(nodes[i].right));
+  };
+  return d(0);
+}
+
+BTree make_tree(int n, int L, const TreeNode* nodes, int nnodes) {
+  BTree t;
+  t.n = n;
+  t.L = L;
+  struct Cur {
+    int b, e, idx;
+  };
+  std::vector<Cur> cur{{0, n, (nodes && nnodes) ? 0 : -1}};
+  for (int l = 0; l <= L; ++l) {
+    std::vector<int32_t> bd;
+    for (auto& c : cur) bd.push_back(c.b);
+    bd.push_back(cur.back().e);
+    t.b.push_back(bd);
+    if (l == L) break;
+    std::vector<Cur> nx;
+    for (auto& c : cur) {
+      if (c.idx >= 0 && nodes[c.idx].left >= 0) {
+        const int li = nodes[c.idx].left, ri = nodes[c.idx].right;
+        const int mid = nodes[li].end - nodes[0].beg;
+        nx.push_back({c.b, mid, li});
+        nx.push_back({mid, c.e, ri});
+      } else {
+        const int mid = c.b + (c.e - c.b + 1) / 2;
+        nx.push_back({c.b, mid, -1});
+        nx.push_back({mid, c.e, -1});
+      }
+    }
+    cur.swap(nx);
+  }
+  return t;
+}
+
+int Butterfly::max_rank() const {
+  int r = 0;
+  for (auto& v : rl)
+    for (int x : v) r = std::max(r, x);
+  for (auto& v : rr)
+    for (int x : v) r = std::max(r, x);
+  return r;
+}
+
+// ------------------------------------------------------------- layouts
+namespace {
+
+// pairing: 0 single, 1 nu-siblings (blk ^ 1), 2 tau-siblings (t ^ 1, same v)
+VecLayout layout(const std::vector<int32_t>& r, int L, int l, int pairing, int nrhs) {
+  VecLayout lay;
+  const int nb = 1 << L;
+  lay.grp_of.assign(nb, -1);
+  lay.mem_row.assign(nb, 0);
+  const int vs = 1 << (L - l);  // column nodes at this level
+  int64_t off = 0;
+  auto add_group = [&](std::initializer_list<int> members) {
+    int g = (int)lay.grp_off.size();
+    int rows = 0;
+    for (int b : members) {
+      lay.grp_of[b] = g;
+      lay.mem_row[b] = rows;
+      rows += r[b];
+    }
+    lay.grp_off.push_back(off);
+    lay.grp_ld.push_back(rows);
+    off += (int64_t)rows * nrhs;
+  };
+  if (pairing == 1 && L - l >= 1) {
+    for (int b = 0; b < nb; b += 2) add_group({b, b + 1});
+  } else if (pairing == 2 && l >= 1) {
+    for (int t2 = 0; t2 < (1 << (l - 1)); ++t2)
+      for (int v = 0; v < vs; ++v) add_group({(2 * t2) * vs + v, (2 * t2 + 1) * vs + v});
+  } else {
+    for (int b = 0; b < nb; ++b) add_group({b});
+  }
+  lay.rows = off / std::max(nrhs, 1);
+  return lay;
+}
+
+GTask task(int64_t a_off, int64_t lda, int opA, int abase, int64_t b_off, int64_t ldb, int bbase, int64_t c_off,
+           int64_t ldc, int cbase, int M, int N, int K, double are, double aim, int beta) {
+  GTask t;
+  std::memset(&t, 0, sizeof(t));
+  t.a_off = a_off;
+  t.lda = std::max<int64_t>(lda, 1);
+  t.opA = (int8_t)opA;
+  t.opB = OP_N;
+  t.abase = (int8_t)abase;
+  t.b_off = b_off;
+  t.ldb = std::max<int64_t>(ldb, 1);
+  t.bbase = (int8_t)bbase;
+  t.c_off = c_off;
+  t.ldc = std::max<int64_t>(ldc, 1);
+  t.cbase = (int8_t)cbase;
+  t.M = M;
+  t.N = N;
+  t.K = K;
+  t.alpha_re = are;
+  t.alpha_im = aim;
+  t.beta = (int8_t)beta;
+  return t;
+}
+
+}  // namespace
+
+BfPlan make_plan(const std::vector<BfCall>& calls, bool adjoint, int nrhs, int64_t ldx, int64_t ldy,
+                 bool right_half_only) {
+  BfPlan plan;
+  int64_t ws = 0;
+  size_t maxph = 0;
+  for (auto& cl : calls) maxph = std::max<size_t>(maxph, (size_t)cl.bf->L + 3);
+  plan.phase.assign(maxph, {});
+  for (auto& cl : calls) {
+    const Butterfly& bf = *cl.bf;
+    const int L = bf.L, lc = bf.lc, nb = 1 << L;
+    // two ping-pong regions sized for the largest level
+    int64_t maxrows = 0;
+    for (int l = lc; l <= L; ++l) maxrows = std::max<int64_t>(maxrows, std::accumulate(bf.rl[l].begin(), bf.rl[l].end(), (int64_t)0));
+    for (int l = 0; l <= lc; ++l) maxrows = std::max<int64_t>(maxrows, std::accumulate(bf.rr[l].begin(), bf.rr[l].end(), (int64_t)0));
+    const int64_t region = maxrows * nrhs;
+    const int64_t w0 = ws, w1 = ws + region;
+    ws += 2 * region;
+    int ph = 0;
+    bool in0 = true;  // the current input lives in region 0
+    auto W = [&](bool r0) { return r0 ? w0 : w1; };
+    if (!adjoint) {
+      // V: t_0 = Vt X(S_v)
+      VecLayout out = layout(bf.rr[0], L, 0, 1, nrhs);
+      for (int v = 0; v < nb; ++v) {
+        const int M = bf.rr[0][v];
+        if (M == 0) continue;
+        plan.phase[ph].push_back(task(bf.offR[0][v], M, OP_N, 0, cl.x_off + bf.ts.beg(L, v), ldx, 1,
+                                      W(true) + out.grp_off[out.grp_of[v]] + out.mem_row[v], out.grp_ld[out.grp_of[v]], 3,
+                                      M, nrhs, bf.ts.size(L, v), 1, 0, 0));
+      }
+      ++ph;
+      VecLayout in = out;
+      in0 = true;
+      for (int l = 1; l <= lc; ++l) {
+        VecLayout o = layout(bf.rr[l], L, l, 1, nrhs);
+        const int vs = 1 << (L - l);
+        for (int t = 0; t < (1 << l); ++t)
+          for (int v = 0; v < vs; ++v) {
+            const int blk = t * vs + v;
+            const int M = bf.rr[l][blk];
+            if (M == 0) continue;
+            const int t2 = t / 2;
+            const int a = (2 * t2) * vs + v, b = (2 * t2 + 1) * vs + v;
+            const int q = t2 * vs + v;  // tau-pair id
+            const int wrows = bf.rr[l][a] + bf.rr[l][b];
+            const int row_off = (t & 1) ? bf.rr[l][a] : 0;
+            const int ia = t2 * (2 * vs) + 2 * v;  // input nu-pair members at level l-1
+            const int K = bf.rr[l - 1][ia] + bf.rr[l - 1][ia + 1];
+            const int gi = in.grp_of[ia];
+            plan.phase[ph].push_back(task(bf.offR[l][q] + row_off, wrows, OP_N, 0, W(in0) + in.grp_off[gi], in.grp_ld[gi],
+                                          3, W(!in0) + o.grp_off[o.grp_of[blk]] + o.mem_row[blk],
+                                          o.grp_ld[o.grp_of[blk]], 3, M, nrhs, K, 1, 0, 0));
+          }
+        ++ph;
+        in = o;
+        in0 = !in0;
+      }
+      if (right_half_only) {
+        plan.half_layout.push_back(in);
+        plan.half_off.push_back(W(in0));
+        continue;
+      }
+      // B: s_lc = B t_lc
+      {
+        VecLayout o = layout(bf.rl[lc], L, lc, 1, nrhs);
+        for (int blk = 0; blk < nb; ++blk) {
+          const int M = bf.rl[lc][blk], K = bf.rr[lc][blk];
+          if (M == 0) continue;
+          const int gi = in.grp_of[blk];
+          plan.phase[ph].push_back(task(bf.offB[blk], M, OP_N, 0, W(in0) + in.grp_off[gi] + in.mem_row[blk],
+                                        in.grp_ld[gi], 3, W(!in0) + o.grp_off[o.grp_of[blk]] + o.mem_row[blk],
+                                        o.grp_ld[o.grp_of[blk]], 3, M, nrhs, K, 1, 0, 0));
+        }
+        ++ph;
+        in = o;
+        in0 = !in0;
+      }
+      // R: s_{l+1} from nu-pairs of s_l
+      for (int l = lc; l < L; ++l) {
+        VecLayout o = layout(bf.rl[l + 1], L, l + 1, 1, nrhs);
+        const int vs1 = 1 << (L - l - 1);  // column nodes at level l+1
+        for (int t1 = 0; t1 < (1 << (l + 1)); ++t1)
+          for (int v1 = 0; v1 < vs1; ++v1) {
+            const int blk1 = t1 * vs1 + v1;
+            const int M = bf.rl[l + 1][blk1];
+            if (M == 0) continue;
+            const int pt = t1 / 2;
+            const int pair = pt * vs1 + v1;  // nu-pair id at level l (members 2 pair, 2 pair + 1)
+            const int top = bf.rl[l + 1][(2 * pt) * vs1 + v1];
+            const int rrows = top + bf.rl[l + 1][(2 * pt + 1) * vs1 + v1];
+            const int row_off = (t1 & 1) ? top : 0;
+            const int K = bf.rl[l][2 * pair] + bf.rl[l][2 * pair + 1];
+            const int gi = in.grp_of[2 * pair];
+            plan.phase[ph].push_back(task(bf.offL[l][pair] + row_off, rrows, OP_N, 0, W(in0) + in.grp_off[gi],
+                                          in.grp_ld[gi], 3, W(!in0) + o.grp_off[o.grp_of[blk1]] + o.mem_row[blk1],
+                                          o.grp_ld[o.grp_of[blk1]], 3, M, nrhs, K, 1, 0, 0));
+          }
+        ++ph;
+        in = o;
+        in0 = !in0;
+      }
+      // U: Y(O_t) = alpha U s_L + beta Y
+      for (int t = 0; t < nb; ++t) {
+        const int M = bf.to.size(L, t), K = bf.rl[L][t];
+        if (M == 0) continue;
+        const int gi = in.grp_of[t];
+        plan.phase[ph].push_back(task(bf.offL[L][t], M, OP_N, 0, W(in0) + in.grp_off[gi] + in.mem_row[t],
+                                      in.grp_ld[gi], 3, cl.y_off + bf.to.beg(L, t), ldy, 2, M, nrhs, K, cl.alpha_re,
+                                      cl.alpha_im, cl.beta));
+      }
+    } else {
+      // U^H: s_L = U^H X(O_t), tau-paired
+      VecLayout out = layout(bf.rl[L], L, L, 2, nrhs);
+      for (int t = 0; t < nb; ++t) {
+        const int M = bf.rl[L][t];
+        if (M == 0) continue;
+        plan.phase[ph].push_back(task(bf.offL[L][t], bf.to.size(L, t), OP_C, 0, cl.x_off + bf.to.beg(L, t), ldx, 1,
+                                      W(true) + out.grp_off[out.grp_of[t]] + out.mem_row[t], out.grp_ld[out.grp_of[t]],
+                                      3, M, nrhs, bf.to.size(L, t), 1, 0, 0));
+      }
+      ++ph;
+      VecLayout in = out;
+      in0 = true;
+      for (int l = L - 1; l >= lc; --l) {
+        VecLayout o = layout(bf.rl[l], L, l, 2, nrhs);
+        const int vs = 1 << (L - l), vs1 = vs / 2;
+        for (int t = 0; t < (1 << l); ++t)
+          for (int v = 0; v < vs; ++v) {
+            const int blk = t * vs + v;
+            const int M = bf.rl[l][blk];
+            if (M == 0) continue;
+            const int pair = blk / 2;  // nu-pair holding the combined R
+            const int a1 = (2 * t) * vs1 + v / 2, b1 = (2 * t + 1) * vs1 + v / 2;
+            const int rrows = bf.rl[l + 1][a1] + bf.rl[l + 1][b1];
+            const int col_off = (blk & 1) ? bf.rl[l][blk - 1] : 0;
+            const int gi = in.grp_of[a1];
+            plan.phase[ph].push_back(task(bf.offL[l][pair] + (int64_t)col_off * rrows, rrows, OP_C, 0,
+                                          W(in0) + in.grp_off[gi], in.grp_ld[gi], 3,
+                                          W(!in0) + o.grp_off[o.grp_of[blk]] + o.mem_row[blk], o.grp_ld[o.grp_of[blk]],
+                                          3, M, nrhs, rrows, 1, 0, 0));
+          }
+        ++ph;
+        in = o;
+        in0 = !in0;
+      }
+      {  // B^H
+        VecLayout o = layout(bf.rr[lc], L, lc, 2, nrhs);
+        for (int blk = 0; blk < nb; ++blk) {
+          const int M = bf.rr[lc][blk], K = bf.rl[lc][blk];
+          if (M == 0) continue;
+          const int gi = in.grp_of[blk];
+          plan.phase[ph].push_back(task(bf.offB[blk], std::max(K, 1), OP_C, 0, W(in0) + in.grp_off[gi] + in.mem_row[blk],
+                                        in.grp_ld[gi], 3, W(!in0) + o.grp_off[o.grp_of[blk]] + o.mem_row[blk],
+                                        o.grp_ld[o.grp_of[blk]], 3, M, nrhs, K, 1, 0, 0));
+        }
+        ++ph;
+        in = o;
+        in0 = !in0;
+      }
+      for (int l = lc; l >= 1; --l) {  // W^H: t_{l-1} from tau-pairs of t_l
+        VecLayout o = layout(bf.rr[l - 1], L, l - 1, 2, nrhs);
+        const int vs = 1 << (L - l), vs0 = 2 * vs;  // column nodes at levels l and l-1
+        for (int t0 = 0; t0 < (1 << (l - 1)); ++t0)
+          for (int v0 = 0; v0 < vs0; ++v0) {
+            const int blk0 = t0 * vs0 + v0;
+            const int M = bf.rr[l - 1][blk0];
+            if (M == 0) continue;
+            const int v = v0 / 2;
+            const int q = t0 * vs + v;  // tau-pair at level l: (2 t0, v), (2 t0 + 1, v)
+            const int a = (2 * t0) * vs + v, b = (2 * t0 + 1) * vs + v;
+            const int wrows = bf.rr[l][a] + bf.rr[l][b];
+            const int c1 = bf.rr[l - 1][t0 * vs0 + 2 * v];
+            const int col_off = (v0 & 1) ? c1 : 0;
+            const int gi = in.grp_of[a];
+            plan.phase[ph].push_back(task(bf.offR[l][q] + (int64_t)col_off * std::max(wrows, 1), wrows, OP_C, 0,
+                                          W(in0) + in.grp_off[gi], in.grp_ld[gi], 3,
+                                          W(!in0) + o.grp_off[o.grp_of[blk0]] + o.mem_row[blk0],
+                                          o.grp_ld[o.grp_of[blk0]], 3, M, nrhs, wrows, 1, 0, 0));
+          }
+        ++ph;
+        in = o;
+        in0 = !in0;
+      }
+      for (int v = 0; v < nb; ++v) {  // V^H: Y(S_v) = alpha conj(V) t_0 + beta Y
+        const int M = bf.ts.size(L, v), K = bf.rr[0][v];
+        if (M == 0) continue;
+        const int gi = in.grp_of[v];
+        plan.phase[ph].push_back(task(bf.offR[0][v], std::max(K, 1), OP_C, 0, W(in0) + in.grp_off[gi] + in.mem_row[v],
+                                      in.grp_ld[gi], 3, cl.y_off + bf.ts.beg(L, v), ldy, 2, M, nrhs, K, cl.alpha_re,
+                                      cl.alpha_im, cl.beta));
+      }
+    }
+  }
+  plan.ws_elems = ws;
+  return plan;
+}
+
+namespace {
+// largest element index touched by an operand stored rows x cols (ld), or -1
+int64_t footprint(int64_t off, int64_t rows, int64_t cols, int64_t ld) {
+  if (rows <= 0 || cols <= 0) return -1;
+  return off + (rows - 1) + (cols - 1) * ld;
+}
+}  // namespace
+
+template <class T>
+void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y, void* ws, hipStream_t s,
+              const int64_t lim[4]) {
+  (void)c;
+  void* bases[4] = {pool, const_cast<void*>(X), Y, ws};
+  for (auto& ph : plan.phase)
+    for (const GTask& t : ph) {
+      const int64_t fa = t.opA == OP_N ? footprint(t.a_off, t.M, t.K, t.lda) : footprint(t.a_off, t.K, t.M, t.lda);
+      const int64_t fb = t.opB == OP_N ? footprint(t.b_off, t.K, t.N, t.ldb) : footprint(t.b_off, t.N, t.K, t.ldb);
+      const int64_t fc = footprint(t.c_off, t.M, t.N, t.ldc);
+      bool bad = t.abase < 0 || t.abase > 3 || t.bbase < 0 || t.bbase > 3 || t.cbase < 0 || t.cbase > 3;
+      bad = bad || (fa >= 0 && (t.a_off < 0 || fa >= lim[t.abase] || !bases[t.abase]));
+      bad = bad || (fb >= 0 && (t.b_off < 0 || fb >= lim[t.bbase] || !bases[t.bbase]));
+      bad = bad || (fc >= 0 && (t.c_off < 0 || fc >= lim[t.cbase] || !bases[t.cbase]));
+      if (bad)
+        throw Error(BFMF_E_INVAL, "internal: butterfly product task outside its buffers (M " + std::to_string(t.M) +
+                                      " N " + std::to_string(t.N) + " K " + std::to_string(t.K) + ")");
+    }
+  // one upload for all phases: per phase its tasks then its tile starts
+  std::vector<char> blob;
+  std::vector<size_t> toff, soff;
+  std::vector<int64_t> ntiles;
+  for (auto& ph : plan.phase) {
+    std::vector<int64_t> start(ph.size());
+    int64_t tiles = 0;
+    for (size_t i = 0; i < ph.size(); ++i) {
+      start[i] = tiles;
+      tiles += (int64_t)((ph[i].M + 63) / 64) * ((ph[i].N + 63) / 64);
+    }
+    size_t o = (blob.size() + 15) & ~(size_t)15;
+    blob.resize(o + ph.size() * sizeof(GTask) + start.size() * sizeof(int64_t));
+    if (!ph.empty()) std::memcpy(blob.data() + o, ph.data(), ph.size() * sizeof(GTask));
+    if (!start.empty()) std::memcpy(blob.data() + o + ph.size() * sizeof(GTask), start.data(), start.size() * sizeof(int64_t));
+    toff.push_back(o);
+    soff.push_back(o + ph.size() * sizeof(GTask));
+    ntiles.push_back(tiles);
+  }
+  if (blob.empty()) return;
+  DevBuf d;
+  dev_alloc(d, blob.size());
+  chk(hipMemcpyAsync(d.p, blob.data(), blob.size(), hipMemcpyHostToDevice, s), "plan upload");
+  for (size_t k = 0; k < plan.phase.size(); ++k) {
+    if (plan.phase[k].empty()) continue;
+    chk(launch_grouped_gemm<T>((const GTask*)(d.as<char>() + toff[k]), (const int64_t*)(d.as<char>() + soff[k]),
+                               (int)plan.phase[k].size(), ntiles[k], bases, s),
+        "grouped gemm");
+  }
+  chk(hipStreamSynchronize(s), "grouped gemm");  // the task buffer is released at scope exit
+}
+
+template void run_plan<double>(const BfPlan&, Context&, char*, const void*, void*, void*, hipStream_t,
+                               const int64_t[4]);
+template void run_plan<float>(const BfPlan&, Context&, char*, const void*, void*, void*, hipStream_t,
+                              const int64_t[4]);
+
+template <class T>
+void BfRuntime<T>::apply(const Butterfly& bf, const void* X, int64_t ldx, void* Y, int64_t ldy, int nrhs, bool adjoint,
+                         double alpha, int beta) {
+  apply_set({BfCall{&bf, 0, 0, alpha, 0.0, beta}}, X, ldx, Y, ldy, nrhs, adjoint);
+}
+
+template <class T>
+void BfRuntime<T>::apply_set(const std::vector<BfCall>& calls, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                             int nrhs, bool adjoint) {
+  BfPlan plan = make_plan(calls, adjoint, nrhs, ldx, ldy);
+  auto mk = scratch.mark();
+  void* ws = scratch.take(std::max<int64_t>(plan.ws_elems, 1) * sizeof(cplx<T>));
+  int64_t rows_in = 0, rows_out = 0;
+  for (auto& cl : calls) {
+    rows_in = std::max<int64_t>(rows_in, cl.x_off + (adjoint ? cl.bf->m : cl.bf->n));
+    rows_out = std::max<int64_t>(rows_out, cl.y_off + (adjoint ? cl.bf->n : cl.bf->m));
+  }
+  if (rows_in > ldx || rows_out > ldy) throw Error(BFMF_E_INVAL, "internal: butterfly product leading dimension");
+  const int64_t lim[4] = {(int64_t)(pool.used / sizeof(cplx<T>)), ldx * nrhs, ldy * nrhs, std::max<int64_t>(plan.ws_elems, 1)};
+  run_plan<T>(plan, *c, pool_base(), X, Y, ws, s(), lim);
+  scratch.release(mk);
+}
+
+template struct BfRuntime<double>;
+template struct BfRuntime<float>;
+
+// ------------------------------------------------------------ construction
+namespace {
+
+// Level-by-level ID driver shared by both constructions.
+template <class T>
+struct IdLevel {
+  BfRuntime<T>& rt;
+  explicit IdLevel(BfRuntime<T>& r) : rt(r) {}
+  // blocks: A_i (q_i x p_i) already in device memory; returns ranks and perms
+  void run(const std::vector<void*>& A, const std::vector<int>& q, const std::vector<int>& p,
+           std::vector<int>& rank, std::vector<std::vector<int32_t>>& perm, std::vector<void*>& Tbuf,
+           std::vector<int>& maxrank, int rank_cap) {
+    const size_t nb = A.size();
+    hipStream_t s = rt.s();
+    std::vector<IdTask> tasks(nb);
+    int64_t tot_perm = 0;
+    for (size_t i = 0; i < nb; ++i) tot_perm += p[i];
+    int32_t* d_rank = rt.scratch.template take_n<int32_t>(nb);
+    int32_t* d_perm = rt.scratch.template take_n<int32_t>(std::max<int64_t>(tot_perm, 1));
+    Tbuf.assign(nb, nullptr);
+    maxrank.assign(nb, 0);
+    int64_t po = 0;
+    for (size_t i = 0; i < nb; ++i) {
+      if (p[i] > 512 || q[i] > 2048)
+        throw Error(BFMF_E_INVAL, "ID block too large (" + std::to_string(q[i]) + " x " + std::to_string(p[i]) + ")");
+      maxrank[i] = std::max(1, std::min({p[i], q[i], rank_cap}));
+      Tbuf[i] = rt.scratch.take((size_t)maxrank[i] * std::max(p[i], 1) * sizeof(cplx<T>));
+      tasks[i] = IdTask{A[i], std::max(q[i], 1), q[i], p[i], maxrank[i], d_rank + i, d_perm + po, Tbuf[i]};
+      po += p[i];
+    }
+    IdTask* dt = (IdTask*)upload_tmp(rt.scratch, tasks, s);
+    chk(launch_cpqr_id<T>(dt, (int)nb, rt.tol, s), "cpqr");
+    rank.assign(nb, 0);
+    std::vector<int32_t> hp(std::max<int64_t>(tot_perm, 1));
+    chk(hipMemcpyAsync(rank.data(), d_rank, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s), "rank");
+    chk(hipMemcpyAsync(hp.data(), d_perm, std::max<int64_t>(tot_perm, 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s),
+        "perm");
+    chk(hipStreamSynchronize(s), "id");
+    perm.assign(nb, {});
+    po = 0;
+    for (size_t i = 0; i < nb; ++i) {
+      if (rank[i] < 0) throw Error(BFMF_E_INVAL, "ID block refused by the kernel");
+      perm[i].assign(hp.begin() + po, hp.begin() + po + p[i]);
+      po += p[i];
+    }
+    d_tasks = dt;
+  }
+  // expand the interpolation matrices into outs (device, ld per block)
+  void expand(int nb, const std::vector<void*>& outs, const std::vector<int64_t>& ldo, bool transpose, bool conj) {
+    hipStream_t s = rt.s();
+    void** d_outs = (void**)upload_tmp(rt.scratch, outs, s);
+    int64_t* d_ldo = (int64_t*)upload_tmp(rt.scratch, ldo, s);
+    chk(launch_id_expand<T>(d_tasks, nb, d_outs, d_ldo, transpose, conj, s), "id expand");
+  }
+  IdTask* d_tasks = nullptr;
+};
+
+template <class T>
+struct FactorAlloc {
+  BfRuntime<T>& rt;
+  Butterfly& bf;
+  int64_t alloc(int64_t elems) {
+    const size_t off = rt.pool.alloc((size_t)std::max<int64_t>(elems, 1) * sizeof(cplx<T>), rt.s());
+    bf.elems += elems;
+    return (int64_t)(off / sizeof(cplx<T>));
+  }
+};
+
+void init_bf(Butterfly& bf, const BTree& to, const BTree& ts) {
+  if (to.L != ts.L) throw Error(BFMF_E_INVAL, "butterfly trees of different depth");
+  bf.to = to;
+  bf.ts = ts;
+  bf.m = to.n;
+  bf.n = ts.n;
+  bf.L = to.L;
+  bf.lc = bf.L / 2;
+  const int nb = 1 << bf.L;
+  bf.rl.assign(bf.L + 1, {});
+  bf.rr.assign(bf.L + 1, {});
+  bf.Ob.assign(bf.L + 1, {});
+  bf.Sb.assign(bf.L + 1, {});
+  bf.offL.assign(bf.L + 1, {});
+  bf.offR.assign(bf.L + 1, {});
+  for (int l = bf.lc; l <= bf.L; ++l) {
+    bf.rl[l].assign(nb, 0);
+    bf.Ob[l].assign(nb, {});
+  }
+  for (int l = 0; l <= bf.lc; ++l) {
+    bf.rr[l].assign(nb, 0);
+    bf.Sb[l].assign(nb, {});
+  }
+  bf.offB.assign(nb, 0);
+}
+
+// candidate rows of left block (l, t, v)
+std::vector<int32_t> left_rows(const Butterfly& bf, int l, int t, int v) {
+  std::vector<int32_t> rows;
+  if (l == bf.L) {
+    for (int i = bf.to.beg(l, t); i < bf.to.end(l, t); ++i) rows.push_back(i);
+  } else {
+    const int vs1 = 1 << (bf.L - l - 1);
+    const auto& a = bf.Ob[l + 1][(2 * t) * vs1 + v / 2];
+    const auto& b = bf.Ob[l + 1][(2 * t + 1) * vs1 + v / 2];
+    rows = a;
+    rows.insert(rows.end(), b.begin(), b.end());
+  }
+  return rows;
+}
+
+std::vector<int32_t> right_cols(const Butterfly& bf, int l, int t, int v) {
+  std::vector<int32_t> cols;
+  if (l == 0) {
+    for (int j = bf.ts.beg(bf.L, v); j < bf.ts.end(bf.L, v); ++j) cols.push_back(j);
+  } else {
+    const int vs0 = 1 << (bf.L - l + 1);
+    const auto& a = bf.Sb[l - 1][(t / 2) * vs0 + 2 * v];
+    const auto& b = bf.Sb[l - 1][(t / 2) * vs0 + 2 * v + 1];
+    cols = a;
+    cols.insert(cols.end(), b.begin(), b.end());
+  }
+  return cols;
+}
+
+// allocate level storage after the ranks of level l (left side) are known
+template <class T>
+void alloc_left(FactorAlloc<T>& fa, Butterfly& bf, int l, std::vector<void*>& outs, std::vector<int64_t>& ldo) {
+  const int nb = 1 << bf.L;
+  char* base = fa.rt.pool_base();
+  (void)base;
+  outs.assign(nb, nullptr);
+  ldo.assign(nb, 1);
+  if (l == bf.L) {
+    bf.offL[l].assign(nb, 0);
+    for (int t = 0; t < nb; ++t) bf.offL[l][t] = fa.alloc((int64_t)bf.to.size(l, t) * bf.rl[l][t]);
+  } else {
+    const int vs1 = 1 << (bf.L - l - 1);
+    bf.offL[l].assign(nb / 2, 0);
+    for (int pr = 0; pr < nb / 2; ++pr) {
+      const int t = pr / vs1, v1 = pr % vs1;
+      const int rows = bf.rl[l + 1][(2 * t) * vs1 + v1] + bf.rl[l + 1][(2 * t + 1) * vs1 + v1];
+      bf.offL[l][pr] = fa.alloc((int64_t)rows * (bf.rl[l][2 * pr] + bf.rl[l][2 * pr + 1]));
+    }
+  }
+}
+
+template <class T>
+void left_outs(BfRuntime<T>& rt, Butterfly& bf, int l, std::vector<void*>& outs, std::vector<int64_t>& ldo) {
+  const int nb = 1 << bf.L;
+  char* base = rt.pool_base();
+  outs.assign(nb, nullptr);
+  ldo.assign(nb, 1);
+  for (int blk = 0; blk < nb; ++blk) {
+    if (l == bf.L) {
+      outs[blk] = base + bf.offL[l][blk] * sizeof(cplx<T>);
+      ldo[blk] = std::max(1, bf.to.size(l, blk));
+    } else {
+      const int vs1 = 1 << (bf.L - l - 1);
+      const int pr = blk / 2, t = pr / vs1, v1 = pr % vs1;
+      const int rows = bf.rl[l + 1][(2 * t) * vs1 + v1] + bf.rl[l + 1][(2 * t + 1) * vs1 + v1];
+      const int col_off = (blk & 1) ? bf.rl[l][blk - 1] : 0;
+      outs[blk] = base + (bf.offL[l][pr] + (int64_t)col_off * rows) * sizeof(cplx<T>);
+      ldo[blk] = std::max(rows, 1);
+    }
+  }
+}
+
+template <class T>
+void alloc_right(FactorAlloc<T>& fa, Butterfly& bf, int l) {
+  const int nb = 1 << bf.L;
+  if (l == 0) {
+    bf.offR[0].assign(nb, 0);
+    for (int v = 0; v < nb; ++v) bf.offR[0][v] = fa.alloc((int64_t)bf.rr[0][v] * bf.ts.size(bf.L, v));
+  } else {
+    const int vs = 1 << (bf.L - l), vs0 = 2 * vs;
+    bf.offR[l].assign(nb / 2, 0);
+    for (int t2 = 0; t2 < (1 << (l - 1)); ++t2)
+      for (int v = 0; v < vs; ++v) {
+        const int q = t2 * vs + v;
+        const int a = (2 * t2) * vs + v, b = (2 * t2 + 1) * vs + v;
+        const int cols = bf.rr[l - 1][t2 * vs0 + 2 * v] + bf.rr[l - 1][t2 * vs0 + 2 * v + 1];
+        bf.offR[l][q] = fa.alloc((int64_t)(bf.rr[l][a] + bf.rr[l][b]) * cols);
+      }
+  }
+}
+
+template <class T>
+void right_outs(BfRuntime<T>& rt, Butterfly& bf, int l, std::vector<void*>& outs, std::vector<int64_t>& ldo) {
+  const int nb = 1 << bf.L;
+  char* base = rt.pool_base();
+  outs.assign(nb, nullptr);
+  ldo.assign(nb, 1);
+  const int vs = 1 << (bf.L - l);
+  for (int blk = 0; blk < nb; ++blk) {
+    if (l == 0) {
+      outs[blk] = base + bf.offR[0][blk] * sizeof(cplx<T>);
+      ldo[blk] = std::max(1, bf.rr[0][blk]);
+    } else {
+      const int t = blk / vs, v = blk % vs, t2 = t / 2;
+      const int q = t2 * vs + v;
+      const int a = (2 * t2) * vs + v, b = (2 * t2 + 1) * vs + v;
+      const int rows = bf.rr[l][a] + bf.rr[l][b];
+      const int row_off = (t & 1) ? bf.rr[l][a] : 0;
+      outs[blk] = base + (bf.offR[l][q] + row_off) * sizeof(cplx<T>);
+      ldo[blk] = std::max(rows, 1);
+    }
+  }
+}
+
+}  // namespace
+
+// ----------------------------------------------------------- Alg. 2
+template <class T>
+std::unique_ptr<Butterfly> bf_entry_eval(BfRuntime<T>& rt, EntrySource<T>& src, ProxySampler& ps, const BTree& to,
+                                         const BTree& ts) {
+  auto bfp = std::make_unique<Butterfly>();
+  Butterfly& bf = *bfp;
+  init_bf(bf, to, ts);
+  FactorAlloc<T> fa{rt, bf};
+  const int L = bf.L, lc = bf.lc, nb = 1 << L;
+  auto mk = rt.scratch.mark();
+  // left to middle: row IDs of K(rows, proxy columns)
+  for (int l = L; l >= lc; --l) {
+    const int vs = 1 << (L - l);
+    std::vector<std::vector<int32_t>> rows(nb), cols(nb);
+    std::vector<const std::vector<int32_t>*> pr(nb), pc(nb);
+    std::vector<void*> A(nb);
+    std::vector<int64_t> lda(nb);
+    std::vector<int> q(nb), p(nb);
+    for (int blk = 0; blk < nb; ++blk) {
+      const int t = blk / vs, v = blk % vs;
+      rows[blk] = left_rows(bf, l, t, v);
+      ps.columns(rows[blk], ts.beg(L - l, v), ts.end(L - l, v), cols[blk]);
+      p[blk] = (int)rows[blk].size();
+      q[blk] = (int)cols[blk].size();
+      A[blk] = rt.scratch.take((size_t)std::max(p[blk] * q[blk], 1) * sizeof(cplx<T>));
+      lda[blk] = std::max(q[blk], 1);
+      pr[blk] = &rows[blk];
+      pc[blk] = &cols[blk];
+    }
+    src.extract(pr, pc, A, lda, true);  // A = K(rows, cols)^T, q x p
+    IdLevel<T> idl(rt);
+    std::vector<int> rank, maxrank;
+    std::vector<std::vector<int32_t>> perm;
+    std::vector<void*> Tb;
+    idl.run(A, q, p, rank, perm, Tb, maxrank, 1 << 20);
+    for (int blk = 0; blk < nb; ++blk) {
+      bf.rl[l][blk] = rank[blk];
+      bf.Ob[l][blk].clear();
+      for (int k = 0; k < rank[blk]; ++k) bf.Ob[l][blk].push_back(rows[blk][perm[blk][k]]);
+    }
+    std::vector<void*> outs;
+    std::vector<int64_t> ldo;
+    alloc_left(fa, bf, l, outs, ldo);
+    left_outs(rt, bf, l, outs, ldo);
+    idl.expand(nb, outs, ldo, false, false);
+  }
+  // right to middle: column IDs of K(proxy rows, cols)
+  for (int l = 0; l <= lc; ++l) {
+    const int vs = 1 << (L - l);
+    std::vector<std::vector<int32_t>> rows(nb), cols(nb);
+    std::vector<const std::vector<int32_t>*> pr(nb), pc(nb);
+    std::vector<void*> A(nb);
+    std::vector<int64_t> lda(nb);
+    std::vector<int> q(nb), p(nb);
+    for (int blk = 0; blk < nb; ++blk) {
+      const int t = blk / vs, v = blk % vs;
+      cols[blk] = right_cols(bf, l, t, v);
+      ps.rows(cols[blk], to.beg(l, t), to.end(l, t), rows[blk]);
+      p[blk] = (int)cols[blk].size();
+      q[blk] = (int)rows[blk].size();
+      A[blk] = rt.scratch.take((size_t)std::max(p[blk] * q[blk], 1) * sizeof(cplx<T>));
+      lda[blk] = std::max(q[blk], 1);
+      pr[blk] = &rows[blk];
+      pc[blk] = &cols[blk];
+    }
+    src.extract(pr, pc, A, lda, false);  // A = K(rows, cols), q x p
+    IdLevel<T> idl(rt);
+    std::vector<int> rank, maxrank;
+    std::vector<std::vector<int32_t>> perm;
+    std::vector<void*> Tb;
+    idl.run(A, q, p, rank, perm, Tb, maxrank, 1 << 20);
+    for (int blk = 0; blk < nb; ++blk) {
+      bf.rr[l][blk] = rank[blk];
+      bf.Sb[l][blk].clear();
+      for (int k = 0; k < rank[blk]; ++k) bf.Sb[l][blk].push_back(cols[blk][perm[blk][k]]);
+    }
+    alloc_right(fa, bf, l);
+    std::vector<void*> outs;
+    std::vector<int64_t> ldo;
+    right_outs(rt, bf, l, outs, ldo);
+    idl.expand(nb, outs, ldo, true, false);
+  }
+  // centre: B = K(Obar, Sbar)
+  {
+    std::vector<const std::vector<int32_t>*> pr(nb), pc(nb);
+    std::vector<void*> outs(nb);
+    std::vector<int64_t> ldo(nb);
+    // allocate every block first: the pool may move while it grows
+    for (int blk = 0; blk < nb; ++blk) bf.offB[blk] = fa.alloc((int64_t)bf.rl[lc][blk] * bf.rr[lc][blk]);
+    for (int blk = 0; blk < nb; ++blk) {
+      pr[blk] = &bf.Ob[lc][blk];
+      pc[blk] = &bf.Sb[lc][blk];
+      outs[blk] = rt.pool_base() + bf.offB[blk] * sizeof(cplx<T>);
+      ldo[blk] = std::max(1, bf.rl[lc][blk]);
+    }
+    src.extract(pr, pc, outs, ldo, false);
+  }
+  chk(hipStreamSynchronize(rt.s()), "entry eval");
+  rt.scratch.release(mk);
+  rt.max_rank_seen = std::max(rt.max_rank_seen, bf.max_rank());
+  return bfp;
+}
+
+// ----------------------------------------------------------- Sec. 3.3
+template <class T>
+static std::unique_ptr<Butterfly> random_once(BfRuntime<T>& rt, Op<T>& op, const BTree& to, const BTree& ts, int S,
+                                              int& max_id_rank) {
+  auto bfp = std::make_unique<Butterfly>();
+  Butterfly& bf = *bfp;
+  init_bf(bf, to, ts);
+  FactorAlloc<T> fa{rt, bf};
+  const int L = bf.L, lc = bf.lc, nb = 1 << L;
+  const int m = to.n, n = ts.n;
+  hipStream_t s = rt.s();
+  auto mk = rt.scratch.mark();
+  // probe groups: left levels l = L..lc, column node v at level L-l
+  std::vector<int32_t> gb, ge;
+  std::vector<int> lcol0(L + 1, 0);
+  for (int l = L; l >= lc; --l) {
+    lcol0[l] = (int)gb.size() * S;
+    for (int v = 0; v < (1 << (L - l)); ++v) {
+      gb.push_back(ts.beg(L - l, v));
+      ge.push_back(ts.end(L - l, v));
+    }
+  }
+  const int ncl = (int)gb.size() * S;
+  std::vector<int32_t> hb2, he2;
+  std::vector<int> rcol0(lc + 1, 0);
+  for (int l = 0; l <= lc; ++l) {
+    rcol0[l] = (int)hb2.size() * S;
+    for (int t = 0; t < (1 << l); ++t) {
+      hb2.push_back(to.beg(l, t));
+      he2.push_back(to.end(l, t));
+    }
+  }
+  const int ncr = (int)hb2.size() * S;
+  void* Om = rt.scratch.take((size_t)std::max(n, 1) * ncl * sizeof(cplx<T>));
+  void* Y = rt.scratch.take((size_t)std::max(m, 1) * ncl * sizeof(cplx<T>));
+  void* Ps = rt.scratch.take((size_t)std::max(m, 1) * ncr * sizeof(cplx<T>));
+  void* Z = rt.scratch.take((size_t)std::max(n, 1) * ncr * sizeof(cplx<T>));
+  int32_t* d_gb = (int32_t*)upload_tmp(rt.scratch, gb, s);
+  int32_t* d_ge = (int32_t*)upload_tmp(rt.scratch, ge, s);
+  int32_t* d_hb = (int32_t*)upload_tmp(rt.scratch, hb2, s);
+  int32_t* d_he = (int32_t*)upload_tmp(rt.scratch, he2, s);
+  chk(launch_philox_gauss<T>(Om, std::max(n, 1), n, ncl, S, d_gb, d_ge, rt.seed, rt.stream_id++, s), "probes");
+  chk(launch_philox_gauss<T>(Ps, std::max(m, 1), m, ncr, S, d_hb, d_he, rt.seed, rt.stream_id++, s), "probes");
+  op.apply(Om, std::max(n, 1), Y, std::max(m, 1), ncl, false, 1.0, 0);
+  op.apply(Ps, std::max(m, 1), Z, std::max(n, 1), ncr, true, 1.0, 0);
+  max_id_rank = 0;
+  // left: row IDs of the sketch rows
+  for (int l = L; l >= lc; --l) {
+    const int vs = 1 << (L - l);
+    std::vector<std::vector<int32_t>> rows(nb), cols(nb);
+    std::vector<const std::vector<int32_t>*> pr(nb), pc(nb);
+    std::vector<void*> A(nb);
+    std::vector<int64_t> lda(nb);
+    std::vector<int> q(nb), p(nb);
+    std::vector<ExtractTask> tasks(nb);
+    for (int blk = 0; blk < nb; ++blk) {
+      const int t = blk / vs, v = blk % vs;
+      rows[blk] = left_rows(bf, l, t, v);
+      cols[blk].resize(S);
+      for (int k = 0; k < S; ++k) cols[blk][k] = lcol0[l] + v * S + k;
+      p[blk] = (int)rows[blk].size();
+      q[blk] = S;
+      A[blk] = rt.scratch.take((size_t)std::max(p[blk] * S, 1) * sizeof(cplx<T>));
+      lda[blk] = S;
+    }
+    // gather A = Y(rows, group)^T through the dense-source extraction
+    {
+      std::vector<int32_t> idx;
+      std::vector<int64_t> ro(nb), co(nb);
+      for (int blk = 0; blk < nb; ++blk) {
+        ro[blk] = (int64_t)idx.size();
+        idx.insert(idx.end(), rows[blk].begin(), rows[blk].end());
+        co[blk] = (int64_t)idx.size();
+        idx.insert(idx.end(), cols[blk].begin(), cols[blk].end());
+      }
+      int32_t* d_idx = (int32_t*)upload_tmp(rt.scratch, idx, s);
+      for (int blk = 0; blk < nb; ++blk) {
+        ExtractTask& e = tasks[blk];
+        std::memset(&e, 0, sizeof(e));
+        e.rows = d_idx + ro[blk];
+        e.cols = d_idx + co[blk];
+        e.nr = p[blk];
+        e.nc = S;
+        e.out = A[blk];
+        e.ldo = S;
+        e.trans = 1;
+        e.dense = Y;
+        e.ldd = std::max(m, 1);
+      }
+      ExtractTask* d_t = (ExtractTask*)upload_tmp(rt.scratch, tasks, s);
+      chk(launch_front_extract<T>(d_t, nb, 4, nullptr, nullptr, false, s), "gather");
+    }
+    IdLevel<T> idl(rt);
+    std::vector<int> rank, maxrank;
+    std::vector<std::vector<int32_t>> perm;
+    std::vector<void*> Tb;
+    idl.run(A, q, p, rank, perm, Tb, maxrank, 1 << 20);
+    for (int blk = 0; blk < nb; ++blk) {
+      bf.rl[l][blk] = rank[blk];
+      max_id_rank = std::max(max_id_rank, rank[blk]);
+      bf.Ob[l][blk].clear();
+      for (int k = 0; k < rank[blk]; ++k) bf.Ob[l][blk].push_back(rows[blk][perm[blk][k]]);
+    }
+    std::vector<void*> outs;
+    std::vector<int64_t> ldo;
+    alloc_left(fa, bf, l, outs, ldo);
+    left_outs(rt, bf, l, outs, ldo);
+    idl.expand(nb, outs, ldo, false, false);
+  }
+  // right: column IDs through K^H sketches (row IDs of Z rows)
+  for (int l = 0; l <= lc; ++l) {
+    const int vs = 1 << (L - l);
+    std::vector<std::vector<int32_t>> cols(nb), grp(nb);
+    std::vector<void*> A(nb);
+    std::vector<int> q(nb), p(nb);
+    std::vector<ExtractTask> tasks(nb);
+    std::vector<int32_t> idx;
+    std::vector<int64_t> ro(nb), co(nb);
+    for (int blk = 0; blk < nb; ++blk) {
+      const int t = blk / vs, v = blk % vs;
+      cols[blk] = right_cols(bf, l, t, v);
+      grp[blk].resize(S);
+      for (int k = 0; k < S; ++k) grp[blk][k] = rcol0[l] + t * S + k;
+      p[blk] = (int)cols[blk].size();
+      q[blk] = S;
+      A[blk] = rt.scratch.take((size_t)std::max(p[blk] * S, 1) * sizeof(cplx<T>));
+      ro[blk] = (int64_t)idx.size();
+      idx.insert(idx.end(), cols[blk].begin(), cols[blk].end());
+      co[blk] = (int64_t)idx.size();
+      idx.insert(idx.end(), grp[blk].begin(), grp[blk].end());
+    }
+    int32_t* d_idx = (int32_t*)upload_tmp(rt.scratch, idx, s);
+    for (int blk = 0; blk < nb; ++blk) {
+      ExtractTask& e = tasks[blk];
+      std::memset(&e, 0, sizeof(e));
+      e.rows = d_idx + ro[blk];
+      e.cols = d_idx + co[blk];
+      e.nr = p[blk];
+      e.nc = S;
+      e.out = A[blk];
+      e.ldo = S;
+      e.trans = 1;
+      e.dense = Z;
+      e.ldd = std::max(n, 1);
+    }
+    ExtractTask* d_t = (ExtractTask*)upload_tmp(rt.scratch, tasks, s);
+    chk(launch_front_extract<T>(d_t, nb, 4, nullptr, nullptr, false, s), "gather");
+    IdLevel<T> idl(rt);
+    std::vector<int> rank, maxrank;
+    std::vector<std::vector<int32_t>> perm;
+    std::vector<void*> Tb;
+    idl.run(A, q, p, rank, perm, Tb, maxrank, 1 << 20);
+    for (int blk = 0; blk < nb; ++blk) {
+      bf.rr[l][blk] = rank[blk];
+      max_id_rank = std::max(max_id_rank, rank[blk]);
+      bf.Sb[l][blk].clear();
+      for (int k = 0; k < rank[blk]; ++k) bf.Sb[l][blk].push_back(cols[blk][perm[blk][k]]);
+    }
+    alloc_right(fa, bf, l);
+    std::vector<void*> outs;
+    std::vector<int64_t> ldo;
+    right_outs(rt, bf, l, outs, ldo);
+    idl.expand(nb, outs, ldo, true, true);  // Vt = U_c^H
+  }
+  // centre: B G = Yc with G = (right half) Omega_lc, Yc = Y(Obar, group);
+  // normal equations B (G G^H) = Yc G^H solved per block
+  {
+    const int ncol = (1 << (L - lc)) * S;
+    const void* Olc = (const char*)Om + (size_t)lcol0[lc] * std::max(n, 1) * sizeof(cplx<T>);
+    BfPlan hp = make_plan({BfCall{&bf, 0, 0, 1.0, 0.0, 0}}, false, ncol, std::max(n, 1), 1, true);
+    const VecLayout& hl = hp.half_layout[0];
+    const int64_t hoff = hp.half_off[0];
+    const int vs = 1 << (L - lc);
+    // workspace: [half plan | M1 blocks | Yc blocks]
+    std::vector<int64_t> m1_off(nb), yc_off(nb);
+    int64_t cw = std::max<int64_t>(hp.ws_elems, 1);
+    for (int blk = 0; blk < nb; ++blk) {
+      m1_off[blk] = cw;
+      cw += (int64_t)std::max(bf.rr[lc][blk] * bf.rr[lc][blk], 1);
+    }
+    for (int blk = 0; blk < nb; ++blk) {
+      yc_off[blk] = cw;
+      cw += (int64_t)std::max(bf.rl[lc][blk] * S, 1);
+    }
+    cplx<T>* ws = (cplx<T>*)rt.scratch.take((size_t)cw * sizeof(cplx<T>));
+    {
+      const int64_t lim[4] = {(int64_t)(rt.pool.used / sizeof(cplx<T>)), (int64_t)std::max(n, 1) * ncol, 0, cw};
+      run_plan<T>(hp, *rt.c, rt.pool_base(), Olc, nullptr, ws, s, lim);
+    }
+    std::vector<int32_t> idx;
+    std::vector<int64_t> ro(nb);
+    for (int blk = 0; blk < nb; ++blk) {
+      ro[blk] = (int64_t)idx.size();
+      idx.insert(idx.end(), bf.Ob[lc][blk].begin(), bf.Ob[lc][blk].end());
+    }
+    int32_t* d_idx = (int32_t*)upload_tmp(rt.scratch, idx, s);
+    for (int blk = 0; blk < nb; ++blk) {
+      const int v = blk % vs, r = bf.rl[lc][blk];
+      if (r == 0) continue;
+      const void* Ysrc = (const char*)Y + (size_t)(lcol0[lc] + v * S) * std::max(m, 1) * sizeof(cplx<T>);
+      chk(launch_gather_rows<T>(Ysrc, std::max(m, 1), ws + yc_off[blk], r, d_idx + ro[blk], r, S, false, s), "gather");
+    }
+    std::vector<GTask> gt;
+    std::vector<SolveTask> st;
+    // allocate every block first: the pool may move while it grows
+    for (int blk = 0; blk < nb; ++blk) bf.offB[blk] = fa.alloc((int64_t)bf.rl[lc][blk] * bf.rr[lc][blk]);
+    for (int blk = 0; blk < nb; ++blk) {
+      const int v = blk % vs;
+      const int r = bf.rl[lc][blk], rp = bf.rr[lc][blk];
+      if (r == 0 || rp == 0) continue;
+      const int gi = hl.grp_of[blk];
+      const int64_t g_off = hoff + hl.grp_off[gi] + hl.mem_row[blk] + (int64_t)v * S * hl.grp_ld[gi];
+      const int64_t g_ld = std::max<int64_t>(hl.grp_ld[gi], 1);
+      GTask t1 = {};  // M1 = G G^H (rp x rp)
+      t1.a_off = g_off; t1.lda = g_ld; t1.opA = OP_N; t1.abase = 3;
+      t1.b_off = g_off; t1.ldb = g_ld; t1.opB = OP_C; t1.bbase = 3;
+      t1.c_off = m1_off[blk]; t1.ldc = rp; t1.cbase = 3;
+      t1.M = rp; t1.N = rp; t1.K = S; t1.alpha_re = 1; t1.beta = 0;
+      gt.push_back(t1);
+      GTask t2 = {};  // B = Yc G^H (r x rp), into the factor pool
+      t2.a_off = yc_off[blk]; t2.lda = r; t2.opA = OP_N; t2.abase = 3;
+      t2.b_off = g_off; t2.ldb = g_ld; t2.opB = OP_C; t2.bbase = 3;
+      t2.c_off = bf.offB[blk]; t2.ldc = r; t2.cbase = 0;
+      t2.M = r; t2.N = rp; t2.K = S; t2.alpha_re = 1; t2.beta = 0;
+      gt.push_back(t2);
+      st.push_back(SolveTask{ws + m1_off[blk], rp, rt.pool_base() + bf.offB[blk] * sizeof(cplx<T>), r, rp, r});
+    }
+    BfPlan gp;
+    gp.phase.push_back(gt);
+    const int64_t lim[4] = {(int64_t)(rt.pool.used / sizeof(cplx<T>)), 0, 0, cw};
+    run_plan<T>(gp, *rt.c, rt.pool_base(), nullptr, nullptr, ws, s, lim);
+    void* d_st = upload_tmp(rt.scratch, st, s);
+    chk(launch_small_solve_right<T>(d_st, (int)st.size(), s), "lsq");
+  }
+  chk(hipStreamSynchronize(s), "random matvec");
+  rt.scratch.release(mk);
+  return bfp;
+}
+
+template <class T>
+std::unique_ptr<Butterfly> bf_random_matvec(BfRuntime<T>& rt, Op<T>& op, const BTree& to, const BTree& ts) {
+  int S = std::max(8, rt.samples);
+  while (true) {
+    const size_t pool_mark = rt.pool.used;
+    int maxr = 0;
+    auto bf = random_once<T>(rt, op, to, ts, S, maxr);
+    if (maxr < S - 8 || S >= rt.max_samples) {
+      rt.max_rank_seen = std::max(rt.max_rank_seen, bf->max_rank());
+      return bf;
+    }
+    rt.pool.used = pool_mark;  // discard the factors of the attempt
+    S *= 2;
+  }
+}
+
+template std::unique_ptr<Butterfly> bf_entry_eval<double>(BfRuntime<double>&, EntrySource<double>&, ProxySampler&,
+                                                          const BTree&, const BTree&);
+template std::unique_ptr<Butterfly> bf_entry_eval<float>(BfRuntime<float>&, EntrySource<float>&, ProxySampler&,
+                                                         const BTree&, const BTree&);
+template std::unique_ptr<Butterfly> bf_random_matvec<double>(BfRuntime<double>&, Op<double>&, const BTree&,
+                                                             const BTree&);
+template std::unique_ptr<Butterfly> bf_random_matvec<float>(BfRuntime<float>&, Op<float>&, const BTree&, const BTree&);
+
+}  // namespace bfmf

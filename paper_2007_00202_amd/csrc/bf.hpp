@@ -1,0 +1,179 @@
+// Butterfly matrices on the device (paper Sec. 3).
+//
+// K ~= (U^L R^{L-1} .. R^{lc}) B^{lc} (W^{lc} .. W^1 V^0), lc = floor(L/2),
+// over a row tree T_O and a column tree T_S of depth L (complete binary trees
+// over contiguous index ranges).  Blocks at level l are indexed
+// blk = t * 2^(L-l) + v (t: node at level l of T_O, v: node at level L-l of
+// T_S).  Factor storage keeps the two R factors that share a parent column
+// node side by side (one matrix per "nu-pair") and the two W factors that share
+// a parent row node on top of each other (one matrix per "tau-pair"), so that
+// every factor level of a product K x or K^H x is a single grouped GEMM: the
+// partial products of sibling blocks are stored stacked and are consumed as
+// one operand.
+#pragma once
+#include <functional>
+#include <memory>
+#include <vector>
+
+#include "context.hpp"
+#include "devtypes.hpp"
+#include "kernels/common.hpp"
+
+namespace bfmf {
+
+// ------------------------------------------------------------ device memory
+// Growable device buffer addressed by byte offsets (growth copies the content
+// and keeps all offsets valid).
+struct DevPool {
+  DevBuf buf;
+  size_t used = 0;
+  size_t alloc(size_t bytes, hipStream_t s);  // 256-byte aligned byte offset
+  char* base() const { return buf.as<char>(); }
+  void reset() { used = 0; }
+};
+
+// Stack of device temporaries: chunks are never moved, release() frees all
+// allocations made after a mark.
+struct Scratch {
+  struct Chunk {
+    DevBuf b;
+    size_t top = 0;
+  };
+  std::vector<std::unique_ptr<Chunk>> chunks;
+  size_t chunk_bytes = (size_t)256 << 20;
+  struct Mark {
+    size_t nchunks, top;
+  };
+  Mark mark() const { return Mark{chunks.size(), chunks.empty() ? 0 : chunks.back()->top}; }
+  void release(const Mark& m);
+  void* take(size_t bytes);
+  template <class T>
+  T* take_n(size_t n) {
+    return (T*)take(n * sizeof(T));
+  }
+};
+
+// ------------------------------------------------------------------- trees
+struct BTree {
+  int n = 0, L = 0;
+  std::vector<std::vector<int32_t>> b;  // b[l]: 2^l + 1 boundaries
+  int beg(int l, int i) const { return b[l][i]; }
+  int end(int l, int i) const { return b[l][i + 1]; }
+  int size(int l, int i) const { return b[l][i + 1] - b[l][i]; }
+};
+// Complete tree of depth L over [0, n) following the bisection `nodes`
+// (preorder, relative ranges) where it has children, halving (first half
+// ceil) elsewhere.
+BTree make_tree(int n, int L, const TreeNode* nodes, int nnodes);
+int tree_depth(const TreeNode* nodes, int nnodes);
+
+// ------------------------------------------------------------- butterfly
+struct Butterfly {
+  int m = 0, n = 0, L = 0, lc = 0;
+  BTree to, ts;
+  std::vector<std::vector<int32_t>> rl, rr;               // ranks (left l in [lc, L], right l in [0, lc])
+  std::vector<std::vector<std::vector<int32_t>>> Ob, Sb;  // skeleton positions per level and block
+  std::vector<std::vector<int64_t>> offL, offR;           // element offsets in the pool
+  std::vector<int64_t> offB;
+  int64_t elems = 0;                                       // factor entries
+  int nblk() const { return 1 << L; }
+  int max_rank() const;
+};
+
+// Layout of the per-block partial products of one level: blocks grouped in
+// pairs (stacked rows) or alone.
+struct VecLayout {
+  std::vector<int64_t> grp_off;  // element offset of each group (per rhs block)
+  std::vector<int32_t> grp_ld;   // rows of each group
+  std::vector<int32_t> grp_of;   // group of each block
+  std::vector<int32_t> mem_row;  // row offset of each block in its group
+  int64_t rows = 0;              // total rows (elements per rhs column)
+};
+
+// One member of a butterfly product: Y(y_off:, :) = alpha op(K) X(x_off:, :) + beta Y
+struct BfCall {
+  const Butterfly* bf;
+  int64_t x_off, y_off;
+  double alpha_re, alpha_im;
+  int beta;
+};
+
+// Grouped-GEMM phases of the product of a set of butterflies.
+struct BfPlan {
+  std::vector<std::vector<GTask>> phase;
+  int64_t ws_elems = 0;  // workspace (base 3) in elements of complex<T>
+  // right-half-only plans: where each member's level-lc vectors ended up
+  std::vector<VecLayout> half_layout;
+  std::vector<int64_t> half_off;
+};
+
+// adjoint: K^H.  right_half_only: only V and W phases (forward), output left in
+// the workspace (used by the randomized construction of the centre blocks).
+BfPlan make_plan(const std::vector<BfCall>& calls, bool adjoint, int nrhs, int64_t ldx, int64_t ldy,
+                 bool right_half_only = false);
+
+// Runs a plan: bases 0 = factor pool, 1 = X, 2 = Y, 3 = workspace.  lim[i]
+// is the number of complex<T> elements addressable from base i; every task's
+// operand footprint is checked against it on the host before any launch.
+template <class T>
+void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y, void* ws, hipStream_t s,
+              const int64_t lim[4]);
+
+// ------------------------------------------------------------- operators
+// Y = alpha op(A) X + beta Y for a linear operator A (m x n), nrhs columns.
+template <class T>
+struct Op {
+  int m = 0, n = 0;
+  virtual ~Op() {}
+  virtual void apply(const void* X, int64_t ldx, void* Y, int64_t ldy, int nrhs, bool adjoint, double alpha,
+                     int beta) = 0;
+};
+
+// Runtime shared by all butterfly work of one factorization.
+template <class T>
+struct BfRuntime {
+  Context* c = nullptr;
+  DevPool pool;     // factors of every butterfly and dense leaf
+  Scratch scratch;  // temporaries
+  uint64_t seed = 0, stream_id = 0;
+  int samples = 64;
+  int max_samples = 1024;
+  double tol = 1e-3;
+  int max_rank_seen = 0;
+  hipStream_t s() const { return c->stream; }
+  char* pool_base() const { return pool.base(); }
+  // single-butterfly product Y = alpha op(K) X + beta Y
+  void apply(const Butterfly& bf, const void* X, int64_t ldx, void* Y, int64_t ldy, int nrhs, bool adjoint,
+             double alpha, int beta);
+  void apply_set(const std::vector<BfCall>& calls, const void* X, int64_t ldx, void* Y, int64_t ldy, int nrhs,
+                 bool adjoint);
+};
+
+// Source of matrix entries for entry-evaluation construction: submatrices by
+// (row positions, column positions) into device buffers.
+template <class T>
+struct EntrySource {
+  virtual ~EntrySource() {}
+  // out(i, j) = K(rows[i], cols[j]) (ld_out rows), or the transpose when trans.
+  virtual void extract(const std::vector<const std::vector<int32_t>*>& rows,
+                       const std::vector<const std::vector<int32_t>*>& cols, const std::vector<void*>& outs,
+                       const std::vector<int64_t>& ldo, bool trans) = 0;
+};
+
+// Proxy selection for entry evaluation (Sec. 3.2, Sec. 5.2): for a block with
+// the given skeleton/candidate indices, proxies inside node [beg, end).
+struct ProxySampler {
+  virtual ~ProxySampler() {}
+  virtual void columns(const std::vector<int32_t>& rows, int beg, int end, std::vector<int32_t>& out) = 0;
+  virtual void rows(const std::vector<int32_t>& cols, int beg, int end, std::vector<int32_t>& out) = 0;
+};
+
+// BF_entry_eval (Alg. 2)
+template <class T>
+std::unique_ptr<Butterfly> bf_entry_eval(BfRuntime<T>& rt, EntrySource<T>& src, ProxySampler& ps, const BTree& to,
+                                         const BTree& ts);
+// BF_random_matvec (Sec. 3.3): sketches with probes supported on one tree node
+template <class T>
+std::unique_ptr<Butterfly> bf_random_matvec(BfRuntime<T>& rt, Op<T>& op, const BTree& to, const BTree& ts);
+
+}  // namespace bfmf

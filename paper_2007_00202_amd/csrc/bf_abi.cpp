@@ -1,0 +1,180 @@
+// C ABI for butterflies of caller-given dense matrices: compression by entry
+// evaluation (Alg. 2) or by randomized products (Sec. 3.3), products K X and
+// K^H X, and decompression.  Used to check the butterfly kernels in isolation.
+#include <cstring>
+#include <random>
+
+#include "bf.hpp"
+#include "ops.hpp"
+
+using namespace bfmf;
+
+struct bfmf_bf {
+  Context ctx;
+  BfRuntime<double> rt;
+  DevBuf K;
+  std::unique_ptr<Butterfly> bf;
+  std::string err;
+};
+
+namespace {
+
+struct DenseSource : EntrySource<double> {
+  BfRuntime<double>& rt;
+  const void* K;
+  int64_t ldk;
+  DenseSource(BfRuntime<double>& r, const void* k, int64_t ld) : rt(r), K(k), ldk(ld) {}
+  void extract(const std::vector<const std::vector<int32_t>*>& rows, const std::vector<const std::vector<int32_t>*>& cols,
+               const std::vector<void*>& outs, const std::vector<int64_t>& ldo, bool trans) override {
+    const size_t nb = rows.size();
+    std::vector<int32_t> idx;
+    std::vector<int64_t> ro(nb), co(nb);
+    for (size_t i = 0; i < nb; ++i) {
+      ro[i] = (int64_t)idx.size();
+      idx.insert(idx.end(), rows[i]->begin(), rows[i]->end());
+      co[i] = (int64_t)idx.size();
+      idx.insert(idx.end(), cols[i]->begin(), cols[i]->end());
+    }
+    auto mk = rt.scratch.mark();
+    int32_t* d_idx = rt.scratch.take_n<int32_t>(std::max<size_t>(idx.size(), 1));
+    if (!idx.empty()) ochk(hipMemcpyAsync(d_idx, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, rt.s()), "idx");
+    std::vector<ExtractTask> tk(nb);
+    for (size_t i = 0; i < nb; ++i) {
+      ExtractTask& e = tk[i];
+      std::memset(&e, 0, sizeof(e));
+      e.rows = d_idx + ro[i];
+      e.cols = d_idx + co[i];
+      e.nr = (int32_t)rows[i]->size();
+      e.nc = (int32_t)cols[i]->size();
+      e.out = outs[i];
+      e.ldo = ldo[i];
+      e.trans = trans ? 1 : 0;
+      e.dense = K;
+      e.ldd = ldk;
+    }
+    ExtractTask* d_tk = (ExtractTask*)rt.scratch.take(tk.size() * sizeof(ExtractTask));
+    ochk(hipMemcpyAsync(d_tk, tk.data(), tk.size() * sizeof(ExtractTask), hipMemcpyHostToDevice, rt.s()), "tasks");
+    ochk(launch_front_extract<double>(d_tk, (int)nb, 4, nullptr, nullptr, false, rt.s()), "extract");
+    ochk(hipStreamSynchronize(rt.s()), "extract");
+    rt.scratch.release(mk);
+  }
+};
+
+// alpha * |given| uniform proxies (without replacement) inside the node
+struct UniformSampler : ProxySampler {
+  std::mt19937_64 g;
+  double alpha;
+  UniformSampler(uint64_t seed, double a) : g(seed), alpha(a) {}
+  void pick(size_t given, int beg, int end, std::vector<int32_t>& out) {
+    out.clear();
+    const int n = end - beg;
+    const int k = std::min(n, std::max(8, (int)(alpha * (double)given)));
+    std::vector<int32_t> all(n);
+    for (int i = 0; i < n; ++i) all[i] = beg + i;
+    for (int i = 0; i < k; ++i) {
+      std::uniform_int_distribution<int> d(i, n - 1);
+      std::swap(all[i], all[d(g)]);
+    }
+    out.assign(all.begin(), all.begin() + k);
+    std::sort(out.begin(), out.end());
+  }
+  void columns(const std::vector<int32_t>& rows, int beg, int end, std::vector<int32_t>& out) override {
+    pick(rows.size(), beg, end, out);
+  }
+  void rows(const std::vector<int32_t>& cols, int beg, int end, std::vector<int32_t>& out) override {
+    pick(cols.size(), beg, end, out);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+bfmf_status bfmf_bf_compress_dense(int32_t device, int32_t m, int32_t n, const double* K, int64_t ldk, int32_t L,
+                                   double tol, int32_t method, int32_t samples, uint64_t seed, bfmf_bf** out) {
+  if (!out || !K || m <= 0 || n <= 0 || ldk < m || L < 0 || L > 16 || !(tol > 0)) return BFMF_E_INVAL;
+  *out = nullptr;
+  bfmf_bf* b = new (std::nothrow) bfmf_bf();
+  if (!b) return BFMF_E_NOMEM;
+  try {
+    if (hipSetDevice(device) != hipSuccess) throw Error(BFMF_E_DEVICE, "set device");
+    b->ctx.device = device;
+    ochk(hipStreamCreateWithFlags(&b->ctx.stream, hipStreamNonBlocking), "stream");
+    b->ctx.own_stream = true;
+    b->rt.c = &b->ctx;
+    b->rt.tol = tol;
+    b->rt.seed = seed;
+    b->rt.samples = samples > 0 ? samples : 64;
+    const size_t bytes = (size_t)m * n * 16;
+    ochk(hipMalloc(&b->K.p, bytes), "malloc");
+    b->K.bytes = bytes;
+    ochk(hipMemcpy2D(b->K.p, (size_t)m * 16, K, (size_t)ldk * 16, (size_t)m * 16, n, hipMemcpyHostToDevice), "upload");
+    BTree to = make_tree(m, L, nullptr, 0), ts = make_tree(n, L, nullptr, 0);
+    if (method == 0) {
+      DenseSource src(b->rt, b->K.p, m);
+      UniformSampler ps(seed ^ 0x9e3779b97f4a7c15ull, 4.0);
+      b->bf = bf_entry_eval<double>(b->rt, src, ps, to, ts);
+    } else {
+      DenseOp<double> op(b->rt, b->K.p, m, m, n);
+      b->bf = bf_random_matvec<double>(b->rt, op, to, ts);
+    }
+    ochk(hipStreamSynchronize(b->ctx.stream), "compress");
+  } catch (const Error& e) {
+    bfmf_status st = e.status;
+    delete b;
+    return st;
+  }
+  *out = b;
+  return BFMF_OK;
+}
+
+bfmf_status bfmf_bf_apply(bfmf_bf* b, int32_t adjoint, int32_t nrhs, const double* X, int64_t ldx, double* Y,
+                          int64_t ldy) {
+  if (!b || !X || !Y || nrhs <= 0) return BFMF_E_INVAL;
+  const int nin = adjoint ? b->bf->m : b->bf->n, nout = adjoint ? b->bf->n : b->bf->m;
+  if (ldx < nin || ldy < nout) return BFMF_E_INVAL;
+  try {
+    ochk(hipSetDevice(b->ctx.device), "set device");
+    auto mk = b->rt.scratch.mark();
+    void* dx = b->rt.scratch.take((size_t)nin * nrhs * 16);
+    void* dy = b->rt.scratch.take((size_t)nout * nrhs * 16);
+    ochk(hipMemcpy2DAsync(dx, (size_t)nin * 16, X, (size_t)ldx * 16, (size_t)nin * 16, nrhs, hipMemcpyHostToDevice,
+                          b->ctx.stream),
+         "upload");
+    b->rt.apply(*b->bf, dx, nin, dy, nout, nrhs, adjoint != 0, 1.0, 0);
+    ochk(hipMemcpy2DAsync(Y, (size_t)ldy * 16, dy, (size_t)nout * 16, (size_t)nout * 16, nrhs, hipMemcpyDeviceToHost,
+                          b->ctx.stream),
+         "download");
+    ochk(hipStreamSynchronize(b->ctx.stream), "apply");
+    b->rt.scratch.release(mk);
+  } catch (const Error& e) {
+    b->err = e.msg;
+    return e.status;
+  }
+  return BFMF_OK;
+}
+
+bfmf_status bfmf_bf_info(bfmf_bf* b, int32_t* L, int32_t* max_rank, int64_t* entries) {
+  if (!b) return BFMF_E_INVAL;
+  if (L) *L = b->bf->L;
+  if (max_rank) *max_rank = b->bf->max_rank();
+  if (entries) *entries = b->bf->elems;
+  return BFMF_OK;
+}
+
+void bfmf_bf_destroy(bfmf_bf* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->ctx.device);
+  b->bf.reset();
+  b->rt.scratch.chunks.clear();
+  b->rt.pool.buf.release();
+  b->K.release();
+  if (b->ctx.stream) {
+    (void)hipStreamSynchronize(b->ctx.stream);
+    (void)hipStreamDestroy(b->ctx.stream);
+    b->ctx.stream = nullptr;
+  }
+  delete b;
+}
+
+}  // extern "C"

@@ -5,6 +5,9 @@
 
 namespace bfmf {
 
+// operand transformation of the GEMM kernels: none, transpose, conjugate transpose
+enum : int32_t { OP_N = 0, OP_T = 1, OP_C = 2 };
+
 // One dense front F (n x n, column-major, ld = n) of the multifrontal tree.
 // F = [F11 F12; F21 F22] with F11 of size ns (the fully-summed variables
 // I^s) and F22 of size n - ns (the update variables I^u).
@@ -25,6 +28,51 @@ struct FrontDesc {
   void* W;                 // solve workspace (n x nrhs, ld = n)
   const void* cw[2];       // children's solve workspaces (contribution part at row ns_c)
   int64_t cw_ld[2];
+};
+
+}  // namespace bfmf
+
+namespace bfmf {
+
+// One product of a grouped (ragged) GEMM: C = beta C + alpha op(A) op(B).
+// Operand addresses are element offsets from one of the base pointers the
+// launch receives (base[abase] + a_off, ...), so a task list can be reused
+// for other input/output buffers with the same layout.
+struct GTask {
+  int64_t a_off, b_off, c_off;
+  int64_t lda, ldb, ldc;
+  int32_t M, N, K;
+  int8_t opA, opB, abase, bbase, cbase, beta;
+  int8_t pad[2];
+  double alpha_re, alpha_im;
+};
+
+// Interpolative decomposition of one block: A is q x p (column-major, lda),
+// the transpose of the block whose rows are being selected.  Results: rank,
+// pivoted column order (perm, p entries) and T = R11^-1 R12 (rank x (p-rank),
+// ld = p) for the interpolation matrix.
+struct IdTask {
+  void* A;        // q x p workspace, overwritten
+  int64_t lda;
+  int32_t q, p;
+  int32_t maxrank;
+  int32_t* rank;  // output
+  int32_t* perm;  // output, p entries
+  void* T;        // output, maxrank x p (ld maxrank)
+};
+
+// Extraction of the dense submatrix F(rows, cols) of a front that is never
+// formed: A entries plus the children's contribution blocks.
+struct ExtractTask {
+  const int32_t* rows;  // front-local row indices
+  const int32_t* cols;  // front-local column indices
+  int32_t nr, nc;
+  void* out;            // nr x nc (ld nr), or nc x nr (ld nc) when trans
+  int64_t ldo;
+  int32_t trans;        // write the transpose
+  int32_t pad;
+  const void* dense;    // when not null: F is this dense matrix (ld ldd, complex<T>)
+  int64_t ldd;
 };
 
 }  // namespace bfmf

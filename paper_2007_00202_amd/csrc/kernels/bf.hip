@@ -1,0 +1,642 @@
+// Kernels of the butterfly algorithms (paper Sec. 3 and 4):
+//   grouped GEMM      every block-diagonal butterfly factor level is one
+//                     launch of independent ragged products (Sec. 3.1: a
+//                     butterfly matvec is a chain of block-diagonal factors)
+//   cpqr_id           interpolative decomposition of many small blocks by
+//                     truncated column-pivoted Householder QR (Sec. 3)
+//   id_expand         interpolation matrix U = P [I; (R11^-1 R12)^T]
+//   front_extract     entries of a compressed front from the sparse matrix and
+//                     the children's contribution blocks (Sec. 5, list routing)
+//   philox_gauss      complex Gaussian probe vectors supported on one tree node
+//   small_solve       X A = B for many small systems (least-squares centre)
+//   leaf_inverse      explicit inverses of the dense HOD-BF leaves (Alg. 4)
+#include "../devtypes.hpp"
+#include "common.hpp"
+#include "gemm.hpp"
+#include "kernels.hpp"
+
+namespace bfmf {
+
+// ------------------------------------------------------------ grouped GEMM
+template <class T>
+__global__ __launch_bounds__(256) void grouped_gemm_kernel(const GTask* __restrict__ tasks,
+                                                           const int64_t* __restrict__ tile_start, int ntasks,
+                                                           void* b0, void* b1, void* b2, void* b3) {
+  __shared__ GemmSmem<T> sm;
+  const int64_t tile = blockIdx.x;
+  // binary search: last task with tile_start <= tile
+  int lo = 0, hi = ntasks - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile_start[mid] <= tile)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const GTask& t = tasks[lo];
+  const int64_t local = tile - tile_start[lo];
+  const int tm = (t.M + GEMM_TM - 1) / GEMM_TM;
+  const int tn = (t.N + GEMM_TN - 1) / GEMM_TN;
+  if (local >= (int64_t)tm * tn || t.M <= 0 || t.N <= 0) return;
+  void* bases[4] = {b0, b1, b2, b3};
+  const cplx<T>* A = (const cplx<T>*)bases[t.abase] + t.a_off;
+  const cplx<T>* B = (const cplx<T>*)bases[t.bbase] + t.b_off;
+  cplx<T>* C = (cplx<T>*)bases[t.cbase] + t.c_off;
+  const cplx<T> alpha = {(T)t.alpha_re, (T)t.alpha_im};
+  gemm_tile<T>(A, t.lda, t.opA, B, t.ldb, C, t.ldc, t.M, t.N, t.K, alpha, t.beta, (int)(local % tm), (int)(local / tm),
+               sm, t.opB);
+}
+
+// ---------------------------------------------------------------- CPQR ID
+// One workgroup per block.  Columns of A (q x p) are pivoted by largest
+// remaining norm (first maximum); the factorization stops at the first
+// |R_kk| <= tol |R_00| (rank k) or at maxrank.  Householder vectors live in
+// LDS; one wave applies a reflector to one column at a time.
+constexpr int ID_MAXP = 512;
+constexpr int ID_MAXQ = 2048;
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void cpqr_id_kernel(const IdTask* __restrict__ tasks, double tol) {
+  const IdTask& tk = tasks[blockIdx.x];
+  const int q = tk.q, p = tk.p;
+  const int64_t lda = tk.lda;
+  cplx<T>* A = (cplx<T>*)tk.A;
+  if (q > ID_MAXQ || p > ID_MAXP || q < 0 || p < 0) {  // the host never sends these; refuse, never overflow LDS
+    if (threadIdx.x == 0) *tk.rank = -1;
+    return;
+  }
+  __shared__ double nrm[ID_MAXP];
+  __shared__ int perm[ID_MAXP];
+  __shared__ cplx<T> v[ID_MAXQ];
+  __shared__ double red_v[256];
+  __shared__ int red_i[256];
+  __shared__ double sh_ref;
+  __shared__ int sh_rank;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j = tid; j < p; j += 256) {
+    const cplx<T>* a = A + (int64_t)j * lda;
+    double s = 0;
+    for (int i = 0; i < q; ++i) s += (double)a[i].re * a[i].re + (double)a[i].im * a[i].im;
+    nrm[j] = s;
+    perm[j] = j;
+  }
+  if (tid == 0) {
+    sh_rank = 0;
+    sh_ref = 0;
+  }
+  __syncthreads();
+  const int kmax = min(min(p, q), tk.maxrank);
+  int k = 0;
+  for (; k < kmax; ++k) {
+    // pivot: largest remaining norm, first index on ties
+    double best = -1;
+    int bi = p;
+    for (int j = k + tid; j < p; j += 256)
+      if (nrm[j] > best) {
+        best = nrm[j];
+        bi = j;
+      }
+    red_v[tid] = best;
+    red_i[tid] = bi;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) {
+        const double o = red_v[tid + s];
+        const int oi = red_i[tid + s];
+        if (o > red_v[tid] || (o == red_v[tid] && oi < red_i[tid])) {
+          red_v[tid] = o;
+          red_i[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int jp = red_i[0];
+    __syncthreads();
+    if (jp != k && jp < p) {
+      cplx<T>* a = A + (int64_t)k * lda;
+      cplx<T>* b = A + (int64_t)jp * lda;
+      for (int i = tid; i < q; i += 256) {
+        const cplx<T> t = a[i];
+        a[i] = b[i];
+        b[i] = t;
+      }
+      if (tid == 0) {
+        const double tn = nrm[k];
+        nrm[k] = nrm[jp];
+        nrm[jp] = tn;
+        const int tp = perm[k];
+        perm[k] = perm[jp];
+        perm[jp] = tp;
+      }
+    }
+    __syncthreads();
+    // exact norm of the trailing part of column k
+    cplx<T>* ak = A + (int64_t)k * lda;
+    double s = 0;
+    for (int i = k + tid; i < q; i += 256) s += (double)ak[i].re * ak[i].re + (double)ak[i].im * ak[i].im;
+    red_v[tid] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (tid < st) red_v[tid] += red_v[tid + st];
+      __syncthreads();
+    }
+    const double alpha = sqrt(red_v[0]);
+    __syncthreads();
+    if (k == 0 && tid == 0) sh_ref = alpha;
+    __syncthreads();
+    if (!(alpha > tol * sh_ref) || alpha == 0) break;
+    // Householder vector v = x + s alpha e1, tau = 1 / (alpha (alpha + |x0|))
+    const cplx<T> x0 = ak[k];
+    const double ax0 = sqrt((double)x0.re * x0.re + (double)x0.im * x0.im);
+    const double sr = ax0 > 0 ? x0.re / ax0 : 1.0, si = ax0 > 0 ? x0.im / ax0 : 0.0;
+    const double tau = 1.0 / (alpha * (alpha + ax0));
+    for (int i = k + tid; i < q; i += 256) {
+      cplx<T> x = ak[i];
+      if (i == k) {
+        x.re = (T)(x.re + sr * alpha);
+        x.im = (T)(x.im + si * alpha);
+      }
+      v[i] = x;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      ak[k] = cplx<T>{(T)(-sr * alpha), (T)(-si * alpha)};  // R_kk
+    }
+    // apply H to columns k+1..p-1: a -= tau v (v^H a)
+    for (int j = k + 1 + wave; j < p; j += 4) {
+      cplx<T>* a = A + (int64_t)j * lda;
+      double wr = 0, wi = 0;
+      for (int i = k + lane; i < q; i += 64) {
+        const cplx<T> vi = v[i], ai = a[i];
+        wr += (double)vi.re * ai.re + (double)vi.im * ai.im;
+        wi += (double)vi.re * ai.im - (double)vi.im * ai.re;
+      }
+      wr = wave_sum(wr);
+      wi = wave_sum(wi);
+      const double cr = tau * wr, ci = tau * wi;
+      for (int i = k + lane; i < q; i += 64) {
+        const cplx<T> vi = v[i];
+        a[i].re -= (T)(vi.re * cr - vi.im * ci);
+        a[i].im -= (T)(vi.re * ci + vi.im * cr);
+      }
+    }
+    __syncthreads();
+    // downdate the remaining column norms with the new row k of R
+    for (int j = k + 1 + tid; j < p; j += 256) {
+      const cplx<T> r = A[k + (int64_t)j * lda];
+      const double d = nrm[j] - ((double)r.re * r.re + (double)r.im * r.im);
+      nrm[j] = d > 0 ? d : 0;
+    }
+    __syncthreads();
+  }
+  const int rank = k;
+  if (tid == 0) *tk.rank = rank;
+  for (int j = tid; j < p; j += 256) tk.perm[j] = perm[j];
+  // T = R11^-1 R12: back substitution, one thread per column of R12
+  cplx<T>* Tout = (cplx<T>*)tk.T;
+  const int ldt = tk.maxrank;
+  for (int j = rank + tid; j < p; j += 256) {
+    cplx<T>* tcol = Tout + (int64_t)(j - rank) * ldt;
+    for (int i = rank - 1; i >= 0; --i) {
+      cplx<T> s = A[i + (int64_t)j * lda];
+      for (int l = i + 1; l < rank; ++l) s = csub(s, cmul(A[i + (int64_t)l * lda], tcol[l]));
+      tcol[i] = cdiv(s, A[i + (int64_t)i * lda]);
+    }
+  }
+}
+
+// U (p x rank, ld p): U[perm[i], i] = 1 (i < rank), U[perm[rank + j], :] = T[:, j]^T,
+// or its conjugate transpose layout Ut (rank x p) when transpose_out (column ID).
+template <class T>
+__global__ void id_expand_kernel(const IdTask* __restrict__ tasks, void* const* __restrict__ outs,
+                                 const int64_t* __restrict__ ldo, int transpose_out, int conj_out) {
+  const IdTask& tk = tasks[blockIdx.x];
+  const int p = tk.p, rank = *tk.rank;
+  cplx<T>* U = (cplx<T>*)outs[blockIdx.x];
+  const int64_t ld = ldo[blockIdx.x];
+  const cplx<T>* Tm = (const cplx<T>*)tk.T;
+  const int ldt = tk.maxrank;
+  for (int e = threadIdx.x; e < p * rank; e += blockDim.x) {
+    const int row = e % p, col = e / p;  // position in the pivoted order, basis column
+    cplx<T> val;
+    if (row < rank)
+      val = cplx<T>{(T)(row == col ? 1 : 0), 0};
+    else
+      val = Tm[col + (int64_t)(row - rank) * ldt];
+    if (conj_out) val.im = -val.im;
+    const int r = tk.perm[row];
+    if (transpose_out)
+      U[col + (int64_t)r * ld] = val;
+    else
+      U[r + (int64_t)col * ld] = val;
+  }
+}
+
+// ------------------------------------------------------------ extraction
+// out(i, j) = F(rows[i], cols[j]) with F = [A(Is,Is) A(Is,Iu); A(Iu,Is) 0]
+// (+) C_nu1 (+) C_nu2; one workgroup per task, threads over entries.
+template <class T, class TC>
+__global__ __launch_bounds__(256) void front_extract_kernel(const ExtractTask* __restrict__ tasks,
+                                                            const FrontDesc* __restrict__ fd,
+                                                            const cplx<double>* __restrict__ values) {
+  const ExtractTask& tk = tasks[blockIdx.x];
+  cplx<T>* out = (cplx<T>*)tk.out;
+  const int nr = tk.nr, nc = tk.nc;
+  for (int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x; e < (int64_t)nr * nc; e += (int64_t)gridDim.y * 256) {
+    const int ii = (int)(e % nr), jj = (int)(e / nr);
+    const int i = tk.rows[ii], j = tk.cols[jj];
+    cplx<T>* dst = tk.trans ? out + jj + (int64_t)ii * tk.ldo : out + ii + (int64_t)jj * tk.ldo;
+    if (tk.dense) {
+      *dst = ((const cplx<T>*)tk.dense)[i + (int64_t)j * tk.ldd];
+      continue;
+    }
+    double vr = 0, vi = 0;
+    for (int64_t t = fd->a_ptr[j]; t < fd->a_ptr[j + 1]; ++t)
+      if (fd->a_row[t] == i) {
+        const cplx<double> a = values[fd->a_vidx[t]];
+        vr += a.re;
+        vi += a.im;
+      }
+    for (int c = 0; c < fd->nchild; ++c) {
+      const int ki = fd->inv[c][i], kj = fd->inv[c][j];
+      if (ki >= 0 && kj >= 0) {
+        const TC v = ((const TC*)fd->cb[c])[ki + (int64_t)kj * fd->cb_ld[c]];
+        vr += v.re;
+        vi += v.im;
+      }
+    }
+    *dst = cplx<T>{(T)vr, (T)vi};
+  }
+}
+
+// ------------------------------------------------------------ Philox probes
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of the
+// multiply-xor round function with the published multipliers and Weyl key
+// increments; a 4x32 counter gives 4 uniforms, Box-Muller turns 2 uniforms
+// into one complex Gaussian of unit variance (E|z|^2 = 1).
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)M0 * c[0];
+    const uint64_t p1 = (uint64_t)M1 * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n1 = lo1, n2 = hi0 ^ c[3] ^ k1, n3 = lo0;
+    c[0] = n0;
+    c[1] = n1;
+    c[2] = n2;
+    c[3] = n3;
+    k0 += W0;
+    k1 += W1;
+  }
+}
+
+// Omega (n x ncol, ld n): column c belongs to group g = c / width; group g is
+// supported on rows [gbeg[g], gend[g]) and zero elsewhere.
+template <class T>
+__global__ void philox_gauss_kernel(cplx<T>* __restrict__ Om, int64_t ld, int64_t n, int ncol, int width,
+                                    const int32_t* __restrict__ gbeg, const int32_t* __restrict__ gend,
+                                    uint64_t seed, uint64_t stream_id) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n || c >= ncol) return;
+  const int g = c / width;
+  cplx<T> z = {0, 0};
+  if (i >= gbeg[g] && i < gend[g]) {
+    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)(i >> 32), (uint32_t)c, (uint32_t)stream_id};
+    philox4x32_10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32) ^ (uint32_t)(stream_id >> 32));
+    const double u1 = ((double)ctr[0] + 1.0) * (1.0 / 4294967296.0);  // (0, 1]
+    const double u2 = (double)ctr[1] * (1.0 / 4294967296.0);
+    const double rad = sqrt(-log(u1));  // |z|^2 ~ Exp(1): unit variance complex
+    z.re = (T)(rad * cos(6.283185307179586 * u2));
+    z.im = (T)(rad * sin(6.283185307179586 * u2));
+  }
+  Om[i + (int64_t)c * ld] = z;
+}
+
+// ------------------------------------------------------------ small solves
+// X A = B for each task: A k x k (lda), B r x k (ldb, overwritten by X).
+// Gaussian elimination with partial pivoting on A^T, one workgroup per task,
+// A is destroyed.
+template <class T>
+__global__ __launch_bounds__(256) void small_solve_right_kernel(const SolveTask* __restrict__ tasks) {
+  const SolveTask& tk = tasks[blockIdx.x];
+  const int k = tk.k, r = tk.r;
+  cplx<T>* A = (cplx<T>*)tk.A;
+  cplx<T>* B = (cplx<T>*)tk.B;
+  const int64_t lda = tk.lda, ldb = tk.ldb;
+  // X A = B  <=>  A^T X^T = B^T.  Work on At(i, j) = A(j, i): rows of A^T are
+  // columns of A.  Eliminate with row pivoting on A^T == column pivoting of A.
+  __shared__ double rv[256];
+  __shared__ int ri[256];
+  const int tid = threadIdx.x;
+  for (int c = 0; c < k; ++c) {
+    // pivot among At rows c..k-1 of column c: At(i, c) = A(c, i)
+    double best = -1;
+    int bi = c;
+    for (int i = c + tid; i < k; i += 256) {
+      const double a = cabs1(A[c + (int64_t)i * lda]);
+      if (a > best) {
+        best = a;
+        bi = i;
+      }
+    }
+    rv[tid] = best;
+    ri[tid] = bi;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s && (rv[tid + s] > rv[tid] || (rv[tid + s] == rv[tid] && ri[tid + s] < ri[tid]))) {
+        rv[tid] = rv[tid + s];
+        ri[tid] = ri[tid + s];
+      }
+      __syncthreads();
+    }
+    const int pr = ri[0];
+    __syncthreads();
+    if (pr != c) {  // swap At rows c and pr: columns c, pr of A; columns c, pr of B
+      for (int j = tid; j < k; j += 256) {
+        const cplx<T> t = A[j + (int64_t)c * lda];
+        A[j + (int64_t)c * lda] = A[j + (int64_t)pr * lda];
+        A[j + (int64_t)pr * lda] = t;
+      }
+      for (int j = tid; j < r; j += 256) {
+        const cplx<T> t = B[j + (int64_t)c * ldb];
+        B[j + (int64_t)c * ldb] = B[j + (int64_t)pr * ldb];
+        B[j + (int64_t)pr * ldb] = t;
+      }
+    }
+    __syncthreads();
+    const cplx<T> d = A[c + (int64_t)c * lda];
+    const bool ok = cabs1(d) > 0;
+    // eliminate At rows i > c: At(i, :) -= l At(c, :), l = At(i, c) / At(c, c)
+    for (int i = c + 1 + tid; i < k; i += 256) {
+      const cplx<T> l = ok ? cdiv(A[c + (int64_t)i * lda], d) : cplx<T>{0, 0};
+      for (int j = c + 1; j < k; ++j) A[j + (int64_t)i * lda] = csub(A[j + (int64_t)i * lda], cmul(l, A[j + (int64_t)c * lda]));
+      A[c + (int64_t)i * lda] = l;
+    }
+    __syncthreads();
+    // same row operation on B^T: B(:, i) -= l B(:, c)
+    for (int e = tid; e < r * (k - c - 1); e += 256) {
+      const int row = e % r, i = c + 1 + e / r;
+      B[row + (int64_t)i * ldb] = csub(B[row + (int64_t)i * ldb], cmul(A[c + (int64_t)i * lda], B[row + (int64_t)c * ldb]));
+    }
+    __syncthreads();
+  }
+  // back substitution on the upper triangle of At, per row of B
+  for (int row = tid; row < r; row += 256) {
+    for (int c = k - 1; c >= 0; --c) {
+      cplx<T> s = B[row + (int64_t)c * ldb];
+      for (int j = c + 1; j < k; ++j) s = csub(s, cmul(A[j + (int64_t)c * lda], B[row + (int64_t)j * ldb]));
+      const cplx<T> d = A[c + (int64_t)c * lda];
+      B[row + (int64_t)c * ldb] = cabs1(d) > 0 ? cdiv(s, d) : cplx<T>{0, 0};
+    }
+  }
+}
+
+// ------------------------------------------------------------ leaf inverses
+// In-place inverse of many small dense blocks (Gauss-Jordan with partial
+// pivoting), n <= 128, one workgroup per block; records singular blocks.
+template <class T>
+__global__ __launch_bounds__(256) void leaf_inverse_kernel(const InvTask* __restrict__ tasks, int* status) {
+  const InvTask& tk = tasks[blockIdx.x];
+  const int n = tk.n;
+  cplx<T>* A = (cplx<T>*)tk.A;
+  const int64_t lda = tk.lda;
+  __shared__ int piv[128];
+  __shared__ double rv[256];
+  __shared__ int ri[256];
+  const int tid = threadIdx.x;
+  for (int c = 0; c < n; ++c) {
+    double best = -1;
+    int bi = c;
+    for (int i = c + tid; i < n; i += 256) {
+      const double a = cabs1(A[i + (int64_t)c * lda]);
+      if (a > best) {
+        best = a;
+        bi = i;
+      }
+    }
+    rv[tid] = best;
+    ri[tid] = bi;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s && (rv[tid + s] > rv[tid] || (rv[tid + s] == rv[tid] && ri[tid + s] < ri[tid]))) {
+        rv[tid] = rv[tid + s];
+        ri[tid] = ri[tid + s];
+      }
+      __syncthreads();
+    }
+    const int pr = ri[0];
+    const bool sing = !(rv[0] > 0);
+    __syncthreads();
+    if (tid == 0) {
+      piv[c] = pr;
+      if (sing && status) atomicExch(status, 1);
+    }
+    if (pr != c)
+      for (int j = tid; j < n; j += 256) {
+        const cplx<T> t = A[c + (int64_t)j * lda];
+        A[c + (int64_t)j * lda] = A[pr + (int64_t)j * lda];
+        A[pr + (int64_t)j * lda] = t;
+      }
+    __syncthreads();
+    const cplx<T> d = A[c + (int64_t)c * lda];
+    const cplx<T> dinv = sing ? cplx<T>{0, 0} : cdiv(cplx<T>{1, 0}, d);
+    __syncthreads();
+    // scale row c, then eliminate column c from every other row
+    for (int j = tid; j < n; j += 256) {
+      if (j == c)
+        A[c + (int64_t)j * lda] = dinv;
+      else
+        A[c + (int64_t)j * lda] = cmul(A[c + (int64_t)j * lda], dinv);
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += 256) {
+      const int i = e % n, j = e / n;
+      if (i == c) continue;
+      const cplx<T> f = A[i + (int64_t)c * lda];
+      if (j == c) continue;
+      A[i + (int64_t)j * lda] = csub(A[i + (int64_t)j * lda], cmul(f, A[c + (int64_t)j * lda]));
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += 256) {
+      if (i == c) continue;
+      A[i + (int64_t)c * lda] = cmul(cplx<T>{-A[i + (int64_t)c * lda].re, -A[i + (int64_t)c * lda].im}, dinv);
+    }
+    __syncthreads();
+  }
+  // undo the row interchanges as column interchanges, last first
+  for (int c = n - 1; c >= 0; --c) {
+    const int pr = piv[c];
+    if (pr != c)
+      for (int i = tid; i < n; i += 256) {
+        const cplx<T> t = A[i + (int64_t)c * lda];
+        A[i + (int64_t)c * lda] = A[i + (int64_t)pr * lda];
+        A[i + (int64_t)pr * lda] = t;
+      }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ misc
+// Y(i, c) = X(rows[i], c) (gather rows) or Y(rows[i], c) = X(i, c) (scatter)
+template <class T>
+__global__ void gather_rows_kernel(const cplx<T>* __restrict__ X, int64_t ldx, cplx<T>* __restrict__ Y, int64_t ldy,
+                                   const int32_t* __restrict__ rows, int nr, int ncol, int scatter) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= nr || c >= ncol) return;
+  if (scatter)
+    Y[rows[i] + (int64_t)c * ldy] = X[i + (int64_t)c * ldx];
+  else
+    Y[i + (int64_t)c * ldy] = X[rows[i] + (int64_t)c * ldx];
+}
+
+// Y = a X + b Y (elementwise, m x n blocks with lds)
+template <class T>
+__global__ void axpby_kernel(cplx<T>* __restrict__ Y, int64_t ldy, const cplx<T>* __restrict__ X, int64_t ldx,
+                             int64_t m, double a, double b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= m) return;
+  const cplx<T> x = X ? X[i + (int64_t)c * ldx] : cplx<T>{0, 0};
+  cplx<T> y = {0, 0};
+  if (b != 0) y = Y[i + (int64_t)c * ldy];  // b = 0 overwrites (old contents may be garbage)
+  y.re = (T)(a * x.re + b * y.re);
+  y.im = (T)(a * x.im + b * y.im);
+  Y[i + (int64_t)c * ldy] = y;
+}
+
+// Y (T1) = X (T2), elementwise conversion of an m x n block
+template <class T1, class T2>
+__global__ void convert_kernel(cplx<T1>* __restrict__ Y, int64_t ldy, const cplx<T2>* __restrict__ X, int64_t ldx,
+                               int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= m) return;
+  const cplx<T2> x = X[i + (int64_t)c * ldx];
+  Y[i + (int64_t)c * ldy] = cplx<T1>{(T1)x.re, (T1)x.im};
+}
+
+// ------------------------------------------------------------ launchers
+#define KCHECK(expr)                   \
+  do {                                 \
+    hipError_t e__ = (expr);           \
+    if (e__ != hipSuccess) return e__; \
+  } while (0)
+
+template <class T>
+hipError_t launch_grouped_gemm(const GTask* d_tasks, const int64_t* d_tile_start, int ntasks, int64_t ntiles,
+                               void* const bases[4], hipStream_t s) {
+  if (ntasks == 0 || ntiles == 0) return hipSuccess;
+  // grids are limited to 2^31 - 1 blocks in x
+  hipLaunchKernelGGL((grouped_gemm_kernel<T>), dim3((unsigned)ntiles), dim3(256), 0, s, d_tasks, d_tile_start, ntasks,
+                     bases[0], bases[1], bases[2], bases[3]);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_cpqr_id(const IdTask* d_tasks, int ntasks, double tol, hipStream_t s) {
+  if (ntasks == 0) return hipSuccess;
+  hipLaunchKernelGGL((cpqr_id_kernel<T>), dim3(ntasks), dim3(256), 0, s, d_tasks, tol);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_id_expand(const IdTask* d_tasks, int ntasks, void* const* d_outs, const int64_t* d_ldo,
+                            bool transpose_out, bool conj_out, hipStream_t s) {
+  if (ntasks == 0) return hipSuccess;
+  hipLaunchKernelGGL((id_expand_kernel<T>), dim3(ntasks), dim3(256), 0, s, d_tasks, d_outs, d_ldo,
+                     transpose_out ? 1 : 0, conj_out ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_front_extract(const ExtractTask* d_tasks, int ntasks, int yblocks, const FrontDesc* d_fd,
+                                const void* values, bool cb_single, hipStream_t s) {
+  if (ntasks == 0) return hipSuccess;
+  dim3 grid(ntasks, yblocks > 0 ? yblocks : 1);
+  if (cb_single)
+    hipLaunchKernelGGL((front_extract_kernel<T, cplx<float>>), grid, dim3(256), 0, s, d_tasks, d_fd,
+                       (const cplx<double>*)values);
+  else
+    hipLaunchKernelGGL((front_extract_kernel<T, cplx<double>>), grid, dim3(256), 0, s, d_tasks, d_fd,
+                       (const cplx<double>*)values);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_philox_gauss(void* Om, int64_t ld, int64_t n, int ncol, int width, const int32_t* d_gbeg,
+                               const int32_t* d_gend, uint64_t seed, uint64_t stream_id, hipStream_t s) {
+  if (ncol == 0 || n == 0) return hipSuccess;
+  hipLaunchKernelGGL((philox_gauss_kernel<T>), dim3((unsigned)((n + 255) / 256), ncol), dim3(256), 0, s,
+                     (cplx<T>*)Om, ld, n, ncol, width, d_gbeg, d_gend, seed, stream_id);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_small_solve_right(const void* d_tasks, int ntasks, hipStream_t s) {
+  if (ntasks == 0) return hipSuccess;
+  hipLaunchKernelGGL((small_solve_right_kernel<T>), dim3(ntasks), dim3(256), 0, s, (const SolveTask*)d_tasks);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_leaf_inverse(const void* d_tasks, int ntasks, int* d_status, hipStream_t s) {
+  if (ntasks == 0) return hipSuccess;
+  hipLaunchKernelGGL((leaf_inverse_kernel<T>), dim3(ntasks), dim3(256), 0, s, (const InvTask*)d_tasks, d_status);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_gather_rows(const void* X, int64_t ldx, void* Y, int64_t ldy, const int32_t* rows, int nr, int ncol,
+                              bool scatter, hipStream_t s) {
+  if (nr == 0 || ncol == 0) return hipSuccess;
+  hipLaunchKernelGGL((gather_rows_kernel<T>), dim3((nr + 255) / 256, ncol), dim3(256), 0, s, (const cplx<T>*)X, ldx,
+                     (cplx<T>*)Y, ldy, rows, nr, ncol, scatter ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_axpby(void* Y, int64_t ldy, const void* X, int64_t ldx, int64_t m, int ncol, double a, double b,
+                        hipStream_t s) {
+  if (m == 0 || ncol == 0) return hipSuccess;
+  hipLaunchKernelGGL((axpby_kernel<T>), dim3((unsigned)((m + 255) / 256), ncol), dim3(256), 0, s, (cplx<T>*)Y, ldy,
+                     (const cplx<T>*)X, ldx, m, a, b);
+  return hipGetLastError();
+}
+
+template <class T1, class T2>
+hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int64_t m, int ncol, hipStream_t s) {
+  if (m == 0 || ncol == 0) return hipSuccess;
+  hipLaunchKernelGGL((convert_kernel<T1, T2>), dim3((unsigned)((m + 255) / 256), ncol), dim3(256), 0, s,
+                     (cplx<T1>*)Y, ldy, (const cplx<T2>*)X, ldx, m);
+  return hipGetLastError();
+}
+
+#define INST(T)                                                                                                       \
+  template hipError_t launch_grouped_gemm<T>(const GTask*, const int64_t*, int, int64_t, void* const[4], hipStream_t); \
+  template hipError_t launch_cpqr_id<T>(const IdTask*, int, double, hipStream_t);                                     \
+  template hipError_t launch_id_expand<T>(const IdTask*, int, void* const*, const int64_t*, bool, bool, hipStream_t);  \
+  template hipError_t launch_front_extract<T>(const ExtractTask*, int, int, const FrontDesc*, const void*, bool,       \
+                                              hipStream_t);                                                          \
+  template hipError_t launch_philox_gauss<T>(void*, int64_t, int64_t, int, int, const int32_t*, const int32_t*,       \
+                                             uint64_t, uint64_t, hipStream_t);                                        \
+  template hipError_t launch_small_solve_right<T>(const void*, int, hipStream_t);                                     \
+  template hipError_t launch_leaf_inverse<T>(const void*, int, int*, hipStream_t);                                    \
+  template hipError_t launch_gather_rows<T>(const void*, int64_t, void*, int64_t, const int32_t*, int, int, bool,     \
+                                            hipStream_t);                                                             \
+  template hipError_t launch_axpby<T>(void*, int64_t, const void*, int64_t, int64_t, int, double, double, hipStream_t);
+INST(double)
+INST(float)
+template hipError_t launch_convert<double, float>(void*, int64_t, const void*, int64_t, int64_t, int, hipStream_t);
+template hipError_t launch_convert<float, double>(void*, int64_t, const void*, int64_t, int64_t, int, hipStream_t);
+template hipError_t launch_convert<double, double>(void*, int64_t, const void*, int64_t, int64_t, int, hipStream_t);
+
+}  // namespace bfmf

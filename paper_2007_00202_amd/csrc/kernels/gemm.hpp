@@ -9,8 +9,6 @@
 
 namespace bfmf {
 
-enum : int32_t { OP_N = 0, OP_T = 1, OP_C = 2 };
-
 constexpr int GEMM_TM = 64, GEMM_TN = 64, GEMM_TK = 16;
 
 template <class T>
@@ -20,12 +18,13 @@ struct GemmSmem {
 };
 
 // Computes tile (tm, tn).  opA: OP_N -> A is M x K (lda); OP_T / OP_C -> A is
-// stored K x M (lda) and used transposed / conjugate-transposed.
+// stored K x M (lda) and used transposed / conjugate-transposed.  opB: OP_N ->
+// B is K x N (ldb); OP_T / OP_C -> B is stored N x K.
 template <class T>
 __device__ __forceinline__ void gemm_tile(const cplx<T>* __restrict__ A, int64_t lda, int opA,
                                           const cplx<T>* __restrict__ B, int64_t ldb, cplx<T>* __restrict__ C,
                                           int64_t ldc, int M, int N, int K, cplx<T> alpha, int beta, int tm, int tn,
-                                          GemmSmem<T>& sm) {
+                                          GemmSmem<T>& sm, int opB = OP_N) {
   typedef typename Mfma<T>::acc_t acc_t;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -60,12 +59,21 @@ __device__ __forceinline__ void gemm_tile(const cplx<T>* __restrict__ A, int64_t
       }
     }
     // stage B: 16 k x 64 cols
-    {
+    if (opB == OP_N) {
       const int c = tid >> 2, kb = (tid & 3) * 4;
       const int gc = col0 + c;
       for (int q = 0; q < 4; ++q) {
         const int gk = k0 + kb + q;
         sm.b[kb + q][c] = (gk < K && gc < N) ? B[(int64_t)gk + (int64_t)gc * ldb] : zero;
+      }
+    } else {
+      const int k = tid >> 4, cb = (tid & 15) * 4;
+      const int gk = k0 + k;
+      for (int q = 0; q < 4; ++q) {
+        const int gc = col0 + cb + q;
+        cplx<T> v = (gk < K && gc < N) ? B[(int64_t)gc + (int64_t)gk * ldb] : zero;
+        if (opB == OP_C) v.im = -v.im;
+        sm.b[k][cb + q] = v;
       }
     }
     __syncthreads();

@@ -65,4 +65,57 @@ hipError_t launch_scale_cols(const void* nrm, const void* Wv, int64_t ldw, void*
 hipError_t launch_basis_update(const void* y, int ldy, int m, const void* V, int64_t vstride, int64_t ldv, void* X,
                                int64_t ldx, int64_t N, int nrhs, hipStream_t s);
 
+// ---- butterfly support (bf.hip)
+// grouped GEMM over ntasks tasks; tile_start[i] = first tile of task i
+template <class T>
+hipError_t launch_grouped_gemm(const GTask* d_tasks, const int64_t* d_tile_start, int ntasks, int64_t ntiles,
+                               void* const bases[4], hipStream_t s);
+// truncated column-pivoted QR of every task's q x p block (tol: |R_kk| > tol |R_00|)
+template <class T>
+hipError_t launch_cpqr_id(const IdTask* d_tasks, int ntasks, double tol, hipStream_t s);
+// interpolation matrices from the QR results into outs[i] (ld ldo[i]);
+// transpose_out writes the rank x p transpose (column ID), conj_out conjugates
+template <class T>
+hipError_t launch_id_expand(const IdTask* d_tasks, int ntasks, void* const* d_outs, const int64_t* d_ldo,
+                            bool transpose_out, bool conj_out, hipStream_t s);
+// submatrices of a front (A entries (+) children blocks) or of a dense matrix
+template <class T>
+hipError_t launch_front_extract(const ExtractTask* d_tasks, int ntasks, int yblocks, const FrontDesc* d_fd,
+                                const void* values, bool cb_single, hipStream_t s);
+// complex Gaussian probes (Philox4x32-10): column c nonzero on rows [gbeg[c/width], gend[c/width])
+template <class T>
+hipError_t launch_philox_gauss(void* Om, int64_t ld, int64_t n, int ncol, int width, const int32_t* d_gbeg,
+                               const int32_t* d_gend, uint64_t seed, uint64_t stream_id, hipStream_t s);
+// X A = B per task (tasks: SolveTask array), B overwritten
+template <class T>
+hipError_t launch_small_solve_right(const void* d_tasks, int ntasks, hipStream_t s);
+// in-place inverse of small dense blocks (tasks: InvTask array); *status = 1 on a zero pivot
+template <class T>
+hipError_t launch_leaf_inverse(const void* d_tasks, int ntasks, int* d_status, hipStream_t s);
+// Y(i, :) = X(rows[i], :) or, with scatter, Y(rows[i], :) = X(i, :)
+template <class T>
+hipError_t launch_gather_rows(const void* X, int64_t ldx, void* Y, int64_t ldy, const int32_t* rows, int nr, int ncol,
+                              bool scatter, hipStream_t s);
+// Y = a X + b Y (X may be null: Y = b Y)
+template <class T>
+hipError_t launch_axpby(void* Y, int64_t ldy, const void* X, int64_t ldx, int64_t m, int ncol, double a, double b,
+                        hipStream_t s);
+// Y (complex<T1>) = X (complex<T2>)
+template <class T1, class T2>
+hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int64_t m, int ncol, hipStream_t s);
+
+struct SolveTask {
+  void* A;
+  int64_t lda;
+  void* B;
+  int64_t ldb;
+  int32_t k, r;
+};
+struct InvTask {
+  void* A;
+  int64_t lda;
+  int32_t n;
+  int32_t pad;
+};
+
 }  // namespace bfmf

@@ -1,0 +1,93 @@
+"""GPU parity of the butterfly kernels on caller-given dense matrices.
+
+* Construction (kernel c): entry evaluation (Alg. 2) and randomized products
+  (Sec. 3.3) of a Fourier-type kernel and of the Helmholtz Green's function
+  between two separated planes reproduce the matrix within 10 * tol in the
+  Frobenius norm; an exactly rank-3 matrix is reproduced to rounding for
+  every level count L = 0..4 (ragged sizes, empty tree nodes).
+* Apply (kernel b): K X and K^H X from the factors equal the decompressed
+  matrix times X (decompression = the product applied to the identity), and
+  the adjoint product is the conjugate transpose of the forward one.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def fourier_kernel(n, band):
+    x = np.arange(n) / n
+    return np.exp(2j * np.pi * band * np.outer(x, x))
+
+
+def green_planes(k, wave, gap):
+    h = 1.0 / k
+    pts = []
+
+    def rec(x0, x1, y0, y1):
+        if (x1 - x0) * (y1 - y0) == 1:
+            pts.append((x0, y0))
+            return
+        if x1 - x0 >= y1 - y0:
+            m = x0 + (x1 - x0 + 1) // 2
+            rec(x0, m, y0, y1); rec(m, x1, y0, y1)
+        else:
+            m = y0 + (y1 - y0 + 1) // 2
+            rec(x0, x1, y0, m); rec(x0, x1, m, y1)
+    rec(0, k, 0, k)
+    P = np.array(pts, dtype=float) * h
+    X = np.column_stack([P, np.zeros(len(P))])
+    Y = np.column_stack([P, np.full(len(P), gap)])
+    r = np.linalg.norm(X[:, None, :] - Y[None, :, :], axis=2)
+    return np.exp(2j * np.pi * wave * r) / r
+
+
+def decompress(lib, b, shape):
+    return lib.bfmf_bf_apply(b, shape, np.eye(shape[1], dtype=np.complex128))
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("kind,tol", [("fourier", 1e-3), ("fourier", 1e-6), ("green", 1e-4)])
+def test_construction_and_apply(gpu_lib, method, kind, tol):
+    K = fourier_kernel(256, 16) if kind == "fourier" else green_planes(16, 4, 0.5)
+    b, shape = gpu_lib.bfmf_bf_compress_dense(K, 4, tol, method=method, samples=48, seed=5)
+    try:
+        D = decompress(gpu_lib, b, shape)
+        err = np.linalg.norm(K - D) / np.linalg.norm(K)
+        assert err <= 10 * tol, err
+        info = gpu_lib.bfmf_bf_info(b)
+        assert info["L"] == 4 and info["max_rank"] < 64
+        rng = np.random.default_rng(1)
+        X = rng.standard_normal((256, 5)) + 1j * rng.standard_normal((256, 5))
+        Y = gpu_lib.bfmf_bf_apply(b, shape, X)
+        assert np.linalg.norm(Y - D @ X) <= 1e-12 * np.linalg.norm(D @ X)
+        Yh = gpu_lib.bfmf_bf_apply(b, shape, X, adjoint=True)
+        assert np.linalg.norm(Yh - D.conj().T @ X) <= 1e-12 * np.linalg.norm(Yh)
+    finally:
+        gpu_lib.bfmf_bf_destroy(b)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_exact_low_rank_all_levels(gpu_lib, method):
+    rng = np.random.default_rng(2)
+    K = (rng.standard_normal((97, 3)) + 1j * rng.standard_normal((97, 3))) @ rng.standard_normal((3, 83))
+    for L in range(5):
+        b, shape = gpu_lib.bfmf_bf_compress_dense(K, L, 1e-12, method=method, samples=16, seed=L)
+        try:
+            D = decompress(gpu_lib, b, shape)
+            assert np.linalg.norm(D - K) <= 1e-9 * np.linalg.norm(K), L
+        finally:
+            gpu_lib.bfmf_bf_destroy(b)
+
+
+def test_rectangular_and_many_rhs(gpu_lib):
+    K = fourier_kernel(300, 8)[:, :200]
+    b, shape = gpu_lib.bfmf_bf_compress_dense(K, 3, 1e-8, method=0, seed=3)
+    try:
+        D = decompress(gpu_lib, b, shape)
+        assert np.linalg.norm(D - K) <= 1e-6 * np.linalg.norm(K)
+        X = np.random.default_rng(4).standard_normal((200, 130)) + 0j
+        Y = gpu_lib.bfmf_bf_apply(b, shape, X)
+        assert np.linalg.norm(Y - D @ X) <= 1e-12 * np.linalg.norm(Y)
+    finally:
+        gpu_lib.bfmf_bf_destroy(b)
