@@ -133,8 +133,24 @@ struct Context {
 
   KernelTimer timer;
 
+  // compressed fronts (Alg. 5): flag per front, dense fronts per level first
+  std::vector<uint8_t> compressed;
+  std::vector<int32_t> level_order;   // fronts in level order, dense first within a level
+  std::vector<int32_t> level_ndense;  // dense fronts of each level
+  void* comp = nullptr;               // CompState (compressed.cpp)
+
   uint64_t device_bytes() const;
+  ~Context();
 };
+
+// compressed.cpp
+void* comp_state_create(Context& c);
+void comp_state_destroy(void* p);
+void comp_state_reset(void* p, Context& c, int nfronts);
+void factor_compressed_front(void* state, Context& c, int f, const FrontDesc* d_fd, void* cb);
+void forward_compressed(void* state, Context& c, int f, void* W, int n, int nrhs);
+void backward_compressed(void* state, Context& c, int f, void* W, int n, int nrhs);
+void compressed_stats(void* state, double& bytes, int& maxrank);
 
 // plan.cpp
 void build_plan(Context& c);

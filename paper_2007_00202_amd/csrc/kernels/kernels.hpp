@@ -48,6 +48,15 @@ template <class T>
 hipError_t launch_backward_level(const FrontDesc* d_fds, int nbatch, int maxn, int maxnu, void* x, int64_t N,
                                  int nrhs, hipStream_t s);
 
+// Gather-only steps of the sweeps (for compressed fronts, whose F11^-1, F12
+// and F21 products run as butterfly applications).
+template <class T>
+hipError_t launch_fwd_gather(const FrontDesc* d_fds, int nbatch, int maxn, const void* y, int64_t N, int nrhs,
+                             hipStream_t s);
+template <class T>
+hipError_t launch_bwd_gather(const FrontDesc* d_fds, int nbatch, int maxnu, const void* x, int64_t N, int nrhs,
+                             hipStream_t s);
+
 // ---- GMRES vectors (solve.hip), complex128
 // Y = A X, or Y = B - A X when B is not null
 hipError_t launch_spmv(const int64_t* rowptr, const int32_t* colind, const void* val, const void* X, int64_t ldx,

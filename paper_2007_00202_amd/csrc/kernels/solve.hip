@@ -300,6 +300,24 @@ hipError_t launch_backward_level(const FrontDesc* d_fds, int nbatch, int maxn, i
   return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_fwd_gather(const FrontDesc* d_fds, int nbatch, int maxn, const void* y, int64_t N, int nrhs,
+                             hipStream_t s) {
+  if (nbatch == 0 || maxn == 0) return hipSuccess;
+  hipLaunchKernelGGL((fwd_gather_kernel<T>), dim3(blocks_for(maxn, 256), nbatch), dim3(256), 0, s, d_fds,
+                     (const cplx<T>*)y, N, nrhs);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_bwd_gather(const FrontDesc* d_fds, int nbatch, int maxnu, const void* x, int64_t N, int nrhs,
+                             hipStream_t s) {
+  if (nbatch == 0 || maxnu == 0) return hipSuccess;
+  hipLaunchKernelGGL((bwd_gather_kernel<T>), dim3(blocks_for(maxnu, 256), nbatch), dim3(256), 0, s, d_fds,
+                     (const cplx<T>*)x, N, nrhs);
+  return hipGetLastError();
+}
+
 hipError_t launch_spmv(const int64_t* rowptr, const int32_t* colind, const void* val, const void* X, int64_t ldx,
                        void* Y, int64_t ldy, const void* B, int64_t ldb, int64_t N, int nrhs, hipStream_t s) {
   hipLaunchKernelGGL(spmv_kernel, dim3(blocks_for(N, 256), nrhs), dim3(256), 0, s, rowptr, colind,
@@ -347,6 +365,8 @@ template hipError_t launch_forward_level<double>(const FrontDesc*, int, int, int
                                                  hipStream_t);
 template hipError_t launch_forward_level<float>(const FrontDesc*, int, int, int, const void*, int64_t, int,
                                                 hipStream_t);
+template hipError_t launch_fwd_gather<double>(const FrontDesc*, int, int, const void*, int64_t, int, hipStream_t);
+template hipError_t launch_bwd_gather<double>(const FrontDesc*, int, int, const void*, int64_t, int, hipStream_t);
 template hipError_t launch_backward_level<double>(const FrontDesc*, int, int, int, void*, int64_t, int, hipStream_t);
 template hipError_t launch_backward_level<float>(const FrontDesc*, int, int, int, void*, int64_t, int, hipStream_t);
 

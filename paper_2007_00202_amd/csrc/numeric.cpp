@@ -104,6 +104,33 @@ KernelTimer::~KernelTimer() {
 void factor_dense(Context& c) {
   const int32_t nf = c.sym.nfronts();
   const size_t elem = sizeof(double) * 2;
+  // fronts compressed by Alg. 5: separator fronts with #I^s >= n_min
+  c.compressed.assign(nf, 0);
+  int ncomp = 0;
+  for (int32_t f = 0; f < nf; ++f)
+    if (c.fopts.n_min > 0 && !c.sym.leaf[f] && c.fp[f].ns >= c.fopts.n_min) {
+      c.compressed[f] = 1;
+      ++ncomp;
+    }
+  // arena: dense fronts keep n^2 entries, compressed fronts only their nu^2 block
+  int64_t off = 0;
+  for (int32_t f = 0; f < nf; ++f) {
+    FrontPlan& p = c.fp[f];
+    p.f_off = off;
+    off += c.compressed[f] ? (int64_t)p.nu * p.nu : (int64_t)p.n * p.n;
+  }
+  c.arena_elems = off;
+  // level order with the dense fronts of a level first
+  const int nlev0 = (int)c.level_ptr.size() - 1;
+  c.level_order.clear();
+  c.level_ndense.assign(nlev0, 0);
+  for (int L = 0; L < nlev0; ++L) {
+    for (int k = c.level_ptr[L]; k < c.level_ptr[L + 1]; ++k)
+      if (!c.compressed[c.level_fronts[k]]) c.level_order.push_back(c.level_fronts[k]);
+    c.level_ndense[L] = (int)c.level_order.size() - c.level_ptr[L];
+    for (int k = c.level_ptr[L]; k < c.level_ptr[L + 1]; ++k)
+      if (c.compressed[c.level_fronts[k]]) c.level_order.push_back(c.level_fronts[k]);
+  }
   const size_t need = (size_t)c.arena_elems * elem;
   size_t free_b = 0, total_b = 0;
   HIPCHK(hipMemGetInfo(&free_b, &total_b));
@@ -117,11 +144,16 @@ void factor_dense(Context& c) {
   } else {
     c.d_kept.release();
   }
+  if (ncomp) {
+    if (!c.comp) c.comp = comp_state_create(c);
+    comp_state_reset(c.comp, c, nf);
+  }
   // descriptors in level order
   char* arena = c.d_arena.as<char>();
   c.h_fds.assign(nf, FrontDesc());
   for (int32_t k = 0; k < nf; ++k) {
-    const int32_t f = c.level_fronts[k];
+    const int32_t f = c.level_order[k];
+    c.desc_index[f] = k;
     const FrontPlan& p = c.fp[f];
     FrontDesc& d = c.h_fds[k];
     std::memset(&d, 0, sizeof(d));
@@ -134,8 +166,13 @@ void factor_dense(Context& c) {
     for (int q = 0; q < p.nchild; ++q) {
       const FrontPlan& cp = c.fp[p.child[q]];
       d.inv[q] = c.d_inv.as<int32_t>() + p.inv_off[q];
-      d.cb[q] = arena + (cp.f_off + cp.ns + (int64_t)cp.ns * cp.n) * elem;
-      d.cb_ld[q] = cp.n;
+      if (c.compressed[p.child[q]]) {  // contribution block stored alone (ld nu)
+        d.cb[q] = arena + cp.f_off * elem;
+        d.cb_ld[q] = std::max(cp.nu, 1);
+      } else {
+        d.cb[q] = arena + (cp.f_off + cp.ns + (int64_t)cp.ns * cp.n) * elem;
+        d.cb_ld[q] = cp.n;
+      }
     }
     d.a_ptr = c.d_aptr.as<int64_t>() + p.aptr_off;
     d.a_row = c.d_arow.as<int32_t>();
@@ -152,14 +189,15 @@ void factor_dense(Context& c) {
   std::vector<int> hn, hns;
   const int nlev = (int)c.level_ptr.size() - 1;
   for (int L = 0; L < nlev; ++L) {
-    const int b = c.level_ptr[L], e = c.level_ptr[L + 1];
+    const int b = c.level_ptr[L], e = b + c.level_ndense[L], e_all = c.level_ptr[L + 1];
     auto run = [&](int lo, int hi) {
+      if (hi <= lo) return;
       hn.clear();
       hns.clear();
       int maxn = 0;
       double asm_bytes = 0, lu_flops = 0, sch_flops = 0, sch_bytes = 0;
       for (int k = lo; k < hi; ++k) {
-        const int32_t f = c.level_fronts[k];
+        const int32_t f = c.level_order[k];
         const FrontPlan& p = c.fp[f];
         hn.push_back(p.n);
         hns.push_back(p.ns);
@@ -178,7 +216,7 @@ void factor_dense(Context& c) {
       c.timer.end(tk, c.stream, K_ASSEMBLE, 0, asm_bytes);
       if (c.fopts.keep_fronts) {
         for (int k = lo; k < hi; ++k) {
-          const FrontPlan& p = c.fp[c.level_fronts[k]];
+          const FrontPlan& p = c.fp[c.level_order[k]];
           HIPCHK(hipMemcpyAsync(c.d_kept.as<char>() + p.f_off * elem, arena + p.f_off * elem,
                                 (size_t)p.n * p.n * elem, hipMemcpyDeviceToDevice, c.stream));
         }
@@ -196,6 +234,12 @@ void factor_dense(Context& c) {
     } else {
       for (int k = b; k < e; ++k) run(k, k + 1);
     }
+    // compressed fronts of this level (Alg. 5), one at a time
+    for (int k = e; k < e_all; ++k) {
+      const int32_t f = c.level_order[k];
+      HIPCHK(hipStreamSynchronize(c.stream));
+      factor_compressed_front(c.comp, c, f, dfds + k, arena + c.fp[f].f_off * elem);
+    }
   }
   HIPCHK(hipStreamSynchronize(c.stream));
   c.stats.factor_seconds = now() - t0;
@@ -206,18 +250,28 @@ void factor_dense(Context& c) {
   c.stats.singular_index = st[0] ? st[2] : -1;
   if (st[0]) throw Error(BFMF_E_SINGULAR, "exact zero pivot in front " + std::to_string(st[1]) + " at local index " +
                                               std::to_string(st[2]));
-  double flops = 0, bytes = 0;
+  double flops = 0, bytes = 0, dense_bytes = 0;
   for (int32_t f = 0; f < nf; ++f) {
     const double ns = c.fp[f].ns, nu = c.fp[f].nu;
+    const double fb = (ns * ns + 2 * ns * nu) * elem;
+    dense_bytes += fb;
+    if (c.compressed[f]) continue;
     flops += 8.0 / 3.0 * ns * ns * ns + 8.0 * ns * ns * nu + 8.0 * ns * nu * nu;
-    bytes += (ns * ns + 2 * ns * nu) * elem;
+    bytes += fb;
+  }
+  int maxrank = 0;
+  if (ncomp) {
+    double cb = 0;
+    compressed_stats(c.comp, cb, maxrank);
+    bytes += cb;
   }
   c.stats.factor_flops = flops;
   c.stats.factor_bytes = bytes;
-  c.stats.dense_factor_bytes = bytes;
+  c.stats.dense_factor_bytes = dense_bytes;
+  c.stats.max_rank = maxrank;
   c.stats.nfronts = nf;
-  c.stats.compressed_fronts = 0;
-  c.stats.dense_fronts = nf;
+  c.stats.compressed_fronts = ncomp;
+  c.stats.dense_fronts = nf - ncomp;
   c.stats.nlevels = nlev;
   c.stats.solve_flops_per_rhs = 0;
   for (int32_t f = 0; f < nf; ++f) {
@@ -238,7 +292,7 @@ void ensure_workspace(Context& c, int64_t nrhs) {
   char* W = c.d_W.as<char>();
   const int32_t nf = c.sym.nfronts();
   for (int32_t k = 0; k < nf; ++k) {
-    const int32_t f = c.level_fronts[k];
+    const int32_t f = c.level_order[k];
     const FrontPlan& p = c.fp[f];
     FrontDesc& d = c.h_fds[k];
     d.W = W + p.w_off * nrhs * elem;
@@ -263,7 +317,7 @@ void apply_preconditioner_dev(Context& c, const void* dB, int64_t ldb, void* dX,
     maxnu = 0;
     lvl_bytes = lvl_flops = 0;
     for (int k = lo; k < hi; ++k) {
-      const FrontPlan& p = c.fp[c.level_fronts[k]];
+      const FrontPlan& p = c.fp[c.level_order[k]];
       maxn = std::max(maxn, p.n);
       maxnu = std::max(maxnu, p.nu);
       const double ns = p.ns, nu = p.nu;
@@ -273,8 +327,9 @@ void apply_preconditioner_dev(Context& c, const void* dB, int64_t ldb, void* dX,
     }
   };
   for (int L = 0; L < nlev; ++L) {
-    const int b = c.level_ptr[L], e = c.level_ptr[L + 1];
-    if (c.fopts.batched) {
+    const int b = c.level_ptr[L], e = b + c.level_ndense[L], e_all = c.level_ptr[L + 1];
+    if (e <= b) {
+    } else if (c.fopts.batched) {
       int mn, mu;
       level_sizes(b, e, mn, mu);
       const int tk = c.timer.begin(c.stream);
@@ -289,10 +344,24 @@ void apply_preconditioner_dev(Context& c, const void* dB, int64_t ldb, void* dX,
         c.timer.end(tk, c.stream, K_FWD, lvl_flops, lvl_bytes);
       }
     }
+    for (int k = e; k < e_all; ++k) {  // compressed fronts
+      const FrontPlan& p = c.fp[c.level_order[k]];
+      check(launch_fwd_gather<double>(dfds + k, 1, p.n, c.d_y.p, c.n, (int)nrhs, c.stream), "fwd gather");
+      forward_compressed(c.comp, c, c.level_order[k], c.h_fds[k].W, p.n, (int)nrhs);
+    }
   }
   for (int L = nlev - 1; L >= 0; --L) {
-    const int b = c.level_ptr[L], e = c.level_ptr[L + 1];
-    if (c.fopts.batched) {
+    const int b = c.level_ptr[L], e = b + c.level_ndense[L], e_all = c.level_ptr[L + 1];
+    for (int k = e; k < e_all; ++k) {  // compressed fronts
+      const FrontPlan& p = c.fp[c.level_order[k]];
+      check(launch_bwd_gather<double>(dfds + k, 1, p.nu, c.d_x.p, c.n, (int)nrhs, c.stream), "bwd gather");
+      backward_compressed(c.comp, c, c.level_order[k], c.h_fds[k].W, p.n, (int)nrhs);
+      check(launch_axpby<double>((char*)c.d_x.p + c.sym.sbeg[c.level_order[k]] * 16, c.n, c.h_fds[k].W, p.n, p.ns,
+                                 (int)nrhs, 1.0, 0.0, c.stream),
+            "scatter");
+    }
+    if (e <= b) {
+    } else if (c.fopts.batched) {
       int mn, mu;
       level_sizes(b, e, mn, mu);
       const int tk = c.timer.begin(c.stream);

@@ -154,6 +154,11 @@ void upload_plan(Context& c) {
   c.d_status.bytes = 16;
 }
 
+Context::~Context() {
+  if (comp) comp_state_destroy(comp);
+  comp = nullptr;
+}
+
 uint64_t Context::device_bytes() const {
   uint64_t t = 0;
   for (const DevBuf* b : {&d_rowptr, &d_colind, &d_values, &d_perm, &d_aptr, &d_arow, &d_avidx, &d_inv, &d_iu32,

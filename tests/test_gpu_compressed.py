@@ -1,0 +1,65 @@
+"""GPU parity of the compressed-front path (Alg. 5) through the C ABI.
+
+The oracle is the exact multifrontal solution (Alg. 1, FP64, CPU).  With
+butterfly tolerance eps the compressed factorization preconditions GMRES; the
+GMRES solution must match the oracle to 10 eps with a true relative residual
+at most 1e-3 (1e-2 / 1e-3 at eps = 1e-3).
+"""
+import numpy as np
+import pytest
+
+from workloads import make_problem, helmholtz_7pt, rng_for
+from oracle import nd
+from oracle import multifrontal as mf
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_solution(p, leaf=512, sep_leaf=64):
+    od = nd.nd_grid(p.dims, leaf_max=leaf, sep_leaf=sep_leaf)
+    fac = mf.factor(p.rowptr, p.colind, p.values, od)
+    return mf.solve_refined(p.rowptr, p.colind, p.values, fac, p.rhs, steps=1)
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_helmholtz24_compressed_top_fronts(gpu_lib, batched):
+    p = make_problem("helmholtz24")
+    x_or = oracle_solution(p)
+    s = gpu_lib.Solver(0).analyze(p.rowptr, p.colind, p.values, dims=p.dims)
+    s.factor(tol=1e-3, n_min=256, batched=batched)
+    st = s.stats()
+    assert st["compressed_fronts"] == 3 and st["dense_fronts"] == 60
+    assert 0 < st["max_rank"] < 576
+    X, info = s.solve(p.rhs, true_rtol=1e-3)
+    assert info["status"] == 0
+    err = np.linalg.norm(X - x_or) / np.linalg.norm(x_or)
+    res = mf.rel_residual(p.rowptr, p.colind, p.values, X, p.rhs).max()
+    assert err <= 1e-2 and res <= 1e-3, (err, res, info)
+    s.close()
+
+
+def test_nested_compressed_fronts_and_tolerance_trend(gpu_lib):
+    """Compressed fronts whose children are compressed; tighter eps -> fewer iterations."""
+    dims = (16, 16, 16)
+    rp, ci, v, _ = helmholtz_7pt(dims, 0.05)
+    rng = rng_for("test", "rhs", (16,))
+    b = rng.standard_normal((rp.shape[0] - 1, 2)) + 1j * rng.standard_normal((rp.shape[0] - 1, 2))
+    od = nd.nd_grid(dims, leaf_max=64, sep_leaf=32)
+    fac = mf.factor(rp, ci, v, od)
+    x_or = mf.solve(fac, b)
+    iters = []
+    for tol in (1e-2, 1e-5):
+        s = gpu_lib.Solver(0).analyze(rp, ci, v, dims=dims, leaf_max=64, sep_leaf=32)
+        s.factor(tol=tol, n_min=60, batched=True)
+        st = s.stats()
+        assert st["compressed_fronts"] >= 3  # the root and both its children at least
+        X, info = s.solve(b, true_rtol=1e-6, rtol=1e-9)
+        err = np.linalg.norm(X - x_or) / np.linalg.norm(x_or)
+        assert info["status"] == 0 and err <= 1e-4, (tol, err, info)
+        iters.append(info["iters"])
+        # the preconditioner alone: error of the order of eps times the
+        # amplification of the indefinite operator (a few hundred here)
+        Mx = s.precondition(b)
+        assert np.linalg.norm(Mx - x_or) / np.linalg.norm(x_or) <= 1000 * tol
+        s.close()
+    assert iters[1] <= iters[0]
