@@ -3,6 +3,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -77,6 +78,7 @@ bfmf_status bfmf_create(bfmf_handle* h, int32_t device, void* hip_stream) {
     c->own_stream = true;
   }
   bfmf_default_factor_opts(&c->fopts);
+  c->verbose = getenv("BFMF_VERBOSE") != nullptr;
   c->stats.singular_front = -1;
   c->stats.singular_index = -1;
   *h = c;

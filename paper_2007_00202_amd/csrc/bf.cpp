@@ -422,16 +422,18 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
     ntiles.push_back(tiles);
   }
   if (blob.empty()) return;
-  DevBuf d;
-  dev_alloc(d, blob.size());
-  chk(hipMemcpyAsync(d.p, blob.data(), blob.size(), hipMemcpyHostToDevice, s), "plan upload");
+  // the task blob lives in the stream-ordered staging area of the context
+  if (c.g_tmp_plan.bytes < blob.size()) dev_alloc(c.g_tmp_plan, std::max<size_t>(blob.size() * 2, (size_t)1 << 20));
+  char* d = c.g_tmp_plan.as<char>();
+  chk(hipMemcpyAsync(d, blob.data(), blob.size(), hipMemcpyHostToDevice, s), "plan upload");
   for (size_t k = 0; k < plan.phase.size(); ++k) {
     if (plan.phase[k].empty()) continue;
-    chk(launch_grouped_gemm<T>((const GTask*)(d.as<char>() + toff[k]), (const int64_t*)(d.as<char>() + soff[k]),
-                               (int)plan.phase[k].size(), ntiles[k], bases, s),
+    chk(launch_grouped_gemm<T>((const GTask*)(d + toff[k]), (const int64_t*)(d + soff[k]), (int)plan.phase[k].size(),
+                               ntiles[k], bases, s),
         "grouped gemm");
   }
-  chk(hipStreamSynchronize(s), "grouped gemm");  // the task buffer is released at scope exit
+  // the host blob and the staging area are reused by the next call
+  chk(hipStreamSynchronize(s), "grouped gemm");
 }
 
 template void run_plan<double>(const BfPlan&, Context&, char*, const void*, void*, void*, hipStream_t,
@@ -685,6 +687,7 @@ std::unique_ptr<Butterfly> bf_entry_eval(BfRuntime<T>& rt, EntrySource<T>& src, 
   FactorAlloc<T> fa{rt, bf};
   const int L = bf.L, lc = bf.lc, nb = 1 << L;
   auto mk = rt.scratch.mark();
+  ++rt.n_entry;
   // left to middle: row IDs of K(rows, proxy columns)
   for (int l = L; l >= lc; --l) {
     const int vs = 1 << (L - l);
@@ -1020,6 +1023,7 @@ static std::unique_ptr<Butterfly> random_once(BfRuntime<T>& rt, Op<T>& op, const
 template <class T>
 std::unique_ptr<Butterfly> bf_random_matvec(BfRuntime<T>& rt, Op<T>& op, const BTree& to, const BTree& ts) {
   int S = std::max(8, rt.samples);
+  ++rt.n_random;
   while (true) {
     const size_t pool_mark = rt.pool.used;
     int maxr = 0;

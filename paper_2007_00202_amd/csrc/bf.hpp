@@ -140,6 +140,7 @@ struct BfRuntime {
   int max_samples = 1024;
   double tol = 1e-3;
   int max_rank_seen = 0;
+  int64_t n_random = 0, n_entry = 0;  // constructions performed
   hipStream_t s() const { return c->stream; }
   char* pool_base() const { return pool.base(); }
   // single-butterfly product Y = alpha op(K) X + beta Y

@@ -5,6 +5,8 @@
 #include "compressed.hpp"
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <random>
@@ -246,6 +248,9 @@ struct HodbfInvOp : Op<T> {
   }
 };
 
+// blocks up to this size are inverted densely inside BF_SMW
+constexpr int kSmwDense = 512;
+
 struct SmwResult {
   std::unique_ptr<Butterfly> bf;
   int64_t dense_off = -1;
@@ -355,27 +360,48 @@ SmwResult bf_smw(BfRuntime<T>& rt, const std::vector<TreeNode>& nodes, int node,
   const int n = nd.end - nd.beg;
   const int d = depth_of(nodes, node);
   hipStream_t s = rt.s();
-  if (d == 0 || n <= 128) {
-    // dense: M = I + K, X = M^-1 - I
+  if (d == 0 || n <= kSmwDense) {
+    // dense: M = I + K, X = M^-1 - I.  M^-1 is the Schur complement of the
+    // bordered front [M I; -I 0] (partial LU with pivoting inside M).
     const size_t off = rt.pool.alloc((size_t)n * n * sizeof(cplx<T>), s);
     const int64_t eoff = (int64_t)(off / sizeof(cplx<T>));
     auto mk = rt.scratch.mark();
+    const int N2 = 2 * n;
+    cplx<T>* F = (cplx<T>*)rt.scratch.take((size_t)N2 * N2 * sizeof(cplx<T>));
+    std::vector<cplx<T>> border((size_t)N2 * N2, cplx<T>{0, 0});
+    for (int i = 0; i < n; ++i) {
+      border[(size_t)i * N2 + i] = cplx<T>{1, 0};                  // M = I + K: identity part
+      border[(size_t)(n + i) * N2 + i] = cplx<T>{1, 0};            // F12 = I
+      border[(size_t)i * N2 + n + i] = cplx<T>{-1, 0};             // F21 = -I
+    }
+    ochk(hipMemcpyAsync(F, border.data(), border.size() * sizeof(cplx<T>), hipMemcpyHostToDevice, s), "border");
+    // a separate identity (F12 is overwritten by the factorization)
     cplx<T>* I = (cplx<T>*)rt.scratch.take((size_t)n * n * sizeof(cplx<T>));
-    std::vector<cplx<T>> eye((size_t)n * n, cplx<T>{0, 0});
-    for (int i = 0; i < n; ++i) eye[(size_t)i * n + i] = cplx<T>{1, 0};
-    ochk(hipMemcpyAsync(I, eye.data(), eye.size() * sizeof(cplx<T>), hipMemcpyHostToDevice, s), "eye");
-    cplx<T>* M = (cplx<T>*)(rt.pool_base() + off);
-    Kfull->apply(I, n, M, n, n, false, 1.0, 0);
-    M = (cplx<T>*)(rt.pool_base() + off);  // the pool may have moved
-    axpby<T>(rt, M, n, I, n, n, n, 1.0, 1.0);
-    InvTask it{M, n, n, 0};
-    void* d_it = up(rt.scratch, std::vector<InvTask>{it}, s);
-    int* d_st = (int*)rt.scratch.take(16);
-    ochk(hipMemsetAsync(d_st, 0, 16, s), "status");
-    ochk(launch_leaf_inverse<T>(d_it, 1, d_st, s), "smw dense inverse");
-    axpby<T>(rt, M, n, I, n, n, n, -1.0, 1.0);
+    ochk(launch_axpby<T>(I, n, F + (size_t)n * N2, N2, n, n, 1.0, 0.0, s), "identity");
+    Kfull->apply(I, n, F, N2, n, false, 1.0, 1);                  // F11 = I + K
+    int32_t* piv = (int32_t*)rt.scratch.take((size_t)n * sizeof(int32_t));
+    int* dst = (int*)rt.scratch.take(16);
+    ochk(hipMemsetAsync(dst, 0, 16, s), "status");
+    FrontDesc fd;
+    std::memset(&fd, 0, sizeof(fd));
+    fd.F = F;
+    fd.n = N2;
+    fd.ns = n;
+    fd.front = -1;
+    fd.piv = piv;
+    void* d_fd = up(rt.scratch, std::vector<FrontDesc>{fd}, s);
+    const int hn = N2, hns = n;
+    ochk(launch_partial_lu<T>((const FrontDesc*)d_fd, 1, &hn, &hns, dst, s), "smw dense lu");
+    ochk(launch_schur<T>((const FrontDesc*)d_fd, 1, &hn, &hns, s), "smw dense schur");
+    cplx<T>* X = (cplx<T>*)(rt.pool_base() + off);
+    cplx<T>* C = F + n + (size_t)n * N2;  // M^-1
+    ochk(launch_axpby<T>(X, n, C, N2, n, n, 1.0, 0.0, s), "copy");
+    ochk(launch_axpby<T>(X, n, I, n, n, n, -1.0, 1.0, s), "minus identity");
+    int hst[3] = {0, 0, 0};
+    ochk(hipMemcpyAsync(hst, dst, 12, hipMemcpyDeviceToHost, s), "status");
     ochk(hipStreamSynchronize(s), "smw dense");
     rt.scratch.release(mk);
+    if (hst[0]) throw Error(BFMF_E_SINGULAR, "singular block in the HOD-BF inversion");
     res.dense_off = eoff;
     return res;
   }
@@ -526,6 +552,9 @@ void factor_compressed_front(void* state, Context& c, int f, const FrontDesc* d_
   cf->nu = (int)sy.nu(f);
   const int ns = cf->ns, nu = cf->nu;
   hipStream_t s = rt.s();
+  auto clock = [] { return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count(); };
+  double tph[6] = {clock(), 0, 0, 0, 0, 0};
+  const int64_t r0 = rt.n_random, e0 = rt.n_entry;
   // HOD-BF tree of F11: the separator bisection (P-hat), Sec. 5.1
   std::vector<TreeNode> nodes(sy.sep_nodes.begin() + sy.sep_ptr[f], sy.sep_nodes.begin() + sy.sep_ptr[f + 1]);
   Hodbf<T>& h = cf->f11;
@@ -600,6 +629,7 @@ void factor_compressed_front(void* state, Context& c, int f, const FrontDesc* d_
       nd.b21 = bf_entry_eval<T>(rt, src, ps, tb, ta);
     }
   }
+  tph[1] = clock();
   // HODBF_invert (Alg. 4): leaves, then every internal node bottom-up
   {
     std::vector<InvTask> it;
@@ -647,6 +677,7 @@ void factor_compressed_front(void* state, Context& c, int f, const FrontDesc* d_
       if (nd.x_dense) nd.inv_off = r.dense_off;
       nd.x_zero = r.zero;
     }
+  tph[2] = clock();
   if (nu > 0) {
     // F12 and F21 (Alg. 2), trees: separator bisection x balanced tree on I^u
     const int leaf = 64;
@@ -664,12 +695,14 @@ void factor_compressed_front(void* state, Context& c, int f, const FrontDesc* d_
       BfsSampler ps(nearall, ns, 0, knn, alpha, seed + 8888);
       cf->f21 = bf_entry_eval<T>(rt, src, ps, tu, ts_);
     }
+    tph[3] = clock();
     // S = F21 F11^-1 F12 (Sec. 3.3)
     HodbfInvOp<T> f11i(rt, h, 0);
     BfOp<T> f12(rt, cf->f12.get()), f21(rt, cf->f21.get());
     ProductOp<T> p1(rt, &f11i, &f12), p2(rt, &f21, &p1);
     BTree tuu = subtree(unodes, 0, Lu);
     cf->s = bf_random_matvec<T>(rt, p2, tuu, tuu);
+    tph[4] = clock();
     // C = (C_nu1 (+) C_nu2)(Iu, Iu) - S
     {
       std::vector<int32_t> r(nu);
@@ -689,6 +722,15 @@ void factor_compressed_front(void* state, Context& c, int f, const FrontDesc* d_
       ochk(hipStreamSynchronize(s), "cb");
       rt.scratch.release(mk);
     }
+  }
+  tph[5] = clock();
+  if (c.verbose) {
+    const double t3 = tph[3] > 0 ? tph[3] : tph[2], t4 = tph[4] > 0 ? tph[4] : t3;
+    fprintf(stderr,
+            "[bfmf] front %d ns %d nu %d: F11 %.3fs inv %.3fs F12/F21 %.3fs S %.3fs C %.3fs; constructions "
+            "random %lld entry %lld; max rank %d\n",
+            f, ns, nu, tph[1] - tph[0], tph[2] - tph[1], t3 - tph[2], t4 - t3, tph[5] - t4,
+            (long long)(rt.n_random - r0), (long long)(rt.n_entry - e0), rt.max_rank_seen);
   }
   st->fronts[f] = std::move(cf);
 }

@@ -129,6 +129,7 @@ struct Context {
   DevBuf d_W, d_y, d_x;
   int64_t ws_nrhs = 0;
   DevBuf g_B, g_X, g_V, g_w, g_r, g_scal, g_part, g_tmp;
+  DevBuf g_tmp_plan;  // staging of grouped-GEMM task lists
   int64_t g_nrhs = 0, g_restart = 0;
 
   KernelTimer timer;
@@ -138,6 +139,7 @@ struct Context {
   std::vector<int32_t> level_order;   // fronts in level order, dense first within a level
   std::vector<int32_t> level_ndense;  // dense fronts of each level
   void* comp = nullptr;               // CompState (compressed.cpp)
+  bool verbose = false;               // BFMF_VERBOSE: phase timings of compressed fronts on stderr
 
   uint64_t device_bytes() const;
   ~Context();
