@@ -235,6 +235,8 @@ bfmf_status bfmf_bf_info(bfmf_bf* b, int32_t* L, int32_t* max_rank, int64_t* ent
 void bfmf_bf_destroy(bfmf_bf* b);
 
 const char* bfmf_status_str(bfmf_status s);
+/* Message of the last failed call on h; with h == NULL, of the last failed
+ * call on this thread that returned no handle (bfmf_bf_compress_dense). */
 const char* bfmf_last_error(bfmf_handle h);
 void bfmf_destroy(bfmf_handle h);
 

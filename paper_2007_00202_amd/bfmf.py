@@ -14,6 +14,13 @@ LIB_PATH = os.path.join(_HERE, "lib", "libbfmf.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libbfmf.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+# One HIP runtime per process.  torch bundles its own libamdhip64 (same
+# SONAME as the system one) and loads it by file name; if this library were
+# loaded first it would bring the system runtime and torch would then add a
+# second one beside it, and the two cannot share the device.  Loading torch
+# first makes the library bind to torch's runtime.
+import torch  # noqa: E402,F401  (imported for its HIP runtime)
+
 _lib = C.CDLL(LIB_PATH)
 
 # --------------------------------------------------------------- constants
@@ -269,7 +276,7 @@ def bfmf_bf_compress_dense(K, L, tol, method=0, samples=64, seed=0, device=0):
     out = _P()
     st = _lib.bfmf_bf_compress_dense(device, m, n, _ptr(K), m, L, tol, method, samples, seed, C.byref(out))
     if st != BFMF_OK:
-        raise BfmfError(st, "bf_compress_dense")
+        raise BfmfError(st, "bf_compress_dense: " + _lib.bfmf_last_error(None).decode())
     return out, (m, n)
 
 

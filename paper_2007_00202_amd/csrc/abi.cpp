@@ -342,7 +342,7 @@ const char* bfmf_status_str(bfmf_status s) {
   return "unknown status";
 }
 
-const char* bfmf_last_error(bfmf_handle h) { return h ? h->last_error.c_str() : "null handle"; }
+const char* bfmf_last_error(bfmf_handle h) { return h ? h->last_error.c_str() : bfmf::g_thread_error.c_str(); }
 
 void bfmf_destroy(bfmf_handle h) {
   if (!h) return;

@@ -23,10 +23,11 @@ void dev_alloc(DevBuf& b, size_t bytes) {
   }
   b.bytes = bytes;
 }
-template <class V>
-void* upload_tmp(Scratch& sc, const std::vector<V>& v, hipStream_t s) {
-  void* d = sc.take(std::max<size_t>(v.size() * sizeof(V), 16));
-  if (!v.empty()) chk(hipMemcpyAsync(d, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, s), "upload");
+// copy of a host vector in scratch memory, uploaded through the pinned ring
+template <class R, class V>
+void* upload_tmp(R& rt, const std::vector<V>& v) {
+  void* d = rt.scratch.take(std::max<size_t>(v.size() * sizeof(V), 16));
+  rt.c->stage.put(d, v.data(), v.size() * sizeof(V), rt.s());
   return d;
 }
 }  // namespace
@@ -50,18 +51,25 @@ size_t DevPool::alloc(size_t bytes, hipStream_t s) {
 }
 
 void Scratch::release(const Mark& m) {
-  while (chunks.size() > m.nchunks) chunks.pop_back();
-  if (!chunks.empty()) chunks.back()->top = m.nchunks == chunks.size() ? m.top : chunks.back()->top;
+  cur = m.cur;
+  if (cur >= 0) chunks[cur]->top = m.top;
 }
 
 void* Scratch::take(size_t bytes) {
   bytes = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
-  if (chunks.empty() || chunks.back()->top + bytes > chunks.back()->b.bytes) {
-    auto ch = std::make_unique<Chunk>();
-    dev_alloc(ch->b, std::max(bytes, chunk_bytes));
-    chunks.push_back(std::move(ch));
+  if (cur < 0 || chunks[cur]->top + bytes > chunks[cur]->b.bytes) {
+    // next chunk: reuse the one above the top if it is large enough
+    const size_t next = (size_t)(cur + 1);
+    if (next < chunks.size() && chunks[next]->b.bytes < bytes) chunks.erase(chunks.begin() + next, chunks.end());
+    if (next == chunks.size()) {
+      auto ch = std::make_unique<Chunk>();
+      dev_alloc(ch->b, std::max(bytes, chunk_bytes));
+      chunks.push_back(std::move(ch));
+    }
+    cur = (int)next;
+    chunks[cur]->top = 0;
   }
-  Chunk& c = *chunks.back();
+  Chunk& c = *chunks[cur];
   void* p = c.b.as<char>() + c.top;
   c.top += bytes;
   return p;
@@ -425,15 +433,14 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
   // the task blob lives in the stream-ordered staging area of the context
   if (c.g_tmp_plan.bytes < blob.size()) dev_alloc(c.g_tmp_plan, std::max<size_t>(blob.size() * 2, (size_t)1 << 20));
   char* d = c.g_tmp_plan.as<char>();
-  chk(hipMemcpyAsync(d, blob.data(), blob.size(), hipMemcpyHostToDevice, s), "plan upload");
+  c.stage.put(d, blob.data(), blob.size(), s);
   for (size_t k = 0; k < plan.phase.size(); ++k) {
     if (plan.phase[k].empty()) continue;
     chk(launch_grouped_gemm<T>((const GTask*)(d + toff[k]), (const int64_t*)(d + soff[k]), (int)plan.phase[k].size(),
                                ntiles[k], bases, s),
         "grouped gemm");
   }
-  // the host blob and the staging area are reused by the next call
-  chk(hipStreamSynchronize(s), "grouped gemm");
+  // no synchronisation: the next plan's upload is ordered after these launches on the stream
 }
 
 template void run_plan<double>(const BfPlan&, Context&, char*, const void*, void*, void*, hipStream_t,
@@ -467,44 +474,85 @@ void BfRuntime<T>::apply_set(const std::vector<BfCall>& calls, const void* X, in
 template struct BfRuntime<double>;
 template struct BfRuntime<float>;
 
+// ------------------------------------------------------------ extraction
+void ExtractBatch::add(const FrontDesc* fd, const void* dense, int64_t ldd, const std::vector<int32_t>& rows, int r0,
+                       const std::vector<int32_t>& cols, int c0, void* out, int64_t ldo, bool trans) {
+  if (rows.empty() || cols.empty()) return;
+  ExtractTask e;
+  std::memset(&e, 0, sizeof(e));
+  e.rows = (const int32_t*)(intptr_t)idx.size();  // offsets into idx until the launch
+  for (int32_t r : rows) idx.push_back(r0 + r);
+  e.cols = (const int32_t*)(intptr_t)idx.size();
+  for (int32_t c : cols) idx.push_back(c0 + c);
+  e.nr = (int32_t)rows.size();
+  e.nc = (int32_t)cols.size();
+  e.out = out;
+  e.ldo = std::max<int64_t>(ldo, 1);
+  e.trans = trans ? 1 : 0;
+  e.dense = dense;
+  e.ldd = ldd;
+  e.fd = fd;
+  tasks.push_back(e);
+}
+
+template <class T>
+void run_extract(BfRuntime<T>& rt, ExtractBatch& b) {
+  if (b.tasks.empty()) {
+    b.idx.clear();
+    return;
+  }
+  int32_t* d_idx = (int32_t*)upload_tmp(rt, b.idx);
+  int64_t maxe = 0;
+  for (auto& e : b.tasks) {
+    e.rows = d_idx + (intptr_t)e.rows;
+    e.cols = d_idx + (intptr_t)e.cols;
+    maxe = std::max<int64_t>(maxe, (int64_t)e.nr * e.nc);
+  }
+  ExtractTask* d_t = (ExtractTask*)upload_tmp(rt, b.tasks);
+  const int yb = (int)std::min<int64_t>(32, std::max<int64_t>(1, (maxe + 2047) / 2048));
+  chk(launch_front_extract<T>(d_t, (int)b.tasks.size(), yb, rt.c->d_values.p, sizeof(T) == 4, rt.s()), "extract");
+  b.tasks.clear();
+  b.idx.clear();
+}
+
+template void run_extract<double>(BfRuntime<double>&, ExtractBatch&);
+template void run_extract<float>(BfRuntime<float>&, ExtractBatch&);
+
 // ------------------------------------------------------------ construction
 namespace {
 
-// Level-by-level ID driver shared by both constructions.
+// Interpolative decompositions of a list of blocks in one launch.
 template <class T>
 struct IdLevel {
   BfRuntime<T>& rt;
   explicit IdLevel(BfRuntime<T>& r) : rt(r) {}
   // blocks: A_i (q_i x p_i) already in device memory; returns ranks and perms
-  void run(const std::vector<void*>& A, const std::vector<int>& q, const std::vector<int>& p,
-           std::vector<int>& rank, std::vector<std::vector<int32_t>>& perm, std::vector<void*>& Tbuf,
-           std::vector<int>& maxrank, int rank_cap) {
+  void run(const std::vector<void*>& A, const std::vector<int>& q, const std::vector<int>& p, std::vector<int>& rank,
+           std::vector<std::vector<int32_t>>& perm) {
     const size_t nb = A.size();
     hipStream_t s = rt.s();
     std::vector<IdTask> tasks(nb);
     int64_t tot_perm = 0;
     for (size_t i = 0; i < nb; ++i) tot_perm += p[i];
-    int32_t* d_rank = rt.scratch.template take_n<int32_t>(nb);
+    int32_t* d_rank = rt.scratch.template take_n<int32_t>(std::max<size_t>(nb, 1));
     int32_t* d_perm = rt.scratch.template take_n<int32_t>(std::max<int64_t>(tot_perm, 1));
-    Tbuf.assign(nb, nullptr);
-    maxrank.assign(nb, 0);
     int64_t po = 0;
     for (size_t i = 0; i < nb; ++i) {
       if (p[i] > 512 || q[i] > 2048)
         throw Error(BFMF_E_INVAL, "ID block too large (" + std::to_string(q[i]) + " x " + std::to_string(p[i]) + ")");
-      maxrank[i] = std::max(1, std::min({p[i], q[i], rank_cap}));
-      Tbuf[i] = rt.scratch.take((size_t)maxrank[i] * std::max(p[i], 1) * sizeof(cplx<T>));
-      tasks[i] = IdTask{A[i], std::max(q[i], 1), q[i], p[i], maxrank[i], d_rank + i, d_perm + po, Tbuf[i]};
+      const int maxrank = std::max(1, std::min(p[i], q[i]));
+      void* Tb = rt.scratch.take((size_t)maxrank * std::max(p[i], 1) * sizeof(cplx<T>));
+      tasks[i] = IdTask{A[i], std::max(q[i], 1), q[i], p[i], maxrank, d_rank + i, d_perm + po, Tb};
       po += p[i];
     }
-    IdTask* dt = (IdTask*)upload_tmp(rt.scratch, tasks, s);
+    IdTask* dt = (IdTask*)upload_tmp(rt, tasks);
     chk(launch_cpqr_id<T>(dt, (int)nb, rt.tol, s), "cpqr");
     rank.assign(nb, 0);
     std::vector<int32_t> hp(std::max<int64_t>(tot_perm, 1));
     chk(hipMemcpyAsync(rank.data(), d_rank, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s), "rank");
     chk(hipMemcpyAsync(hp.data(), d_perm, std::max<int64_t>(tot_perm, 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s),
         "perm");
-    chk(hipStreamSynchronize(s), "id");
+    rt.c->stage.sync(s);
     perm.assign(nb, {});
     po = 0;
     for (size_t i = 0; i < nb; ++i) {
@@ -513,15 +561,17 @@ struct IdLevel {
       po += p[i];
     }
     d_tasks = dt;
+    ntasks = (int)nb;
   }
   // expand the interpolation matrices into outs (device, ld per block)
-  void expand(int nb, const std::vector<void*>& outs, const std::vector<int64_t>& ldo, bool transpose, bool conj) {
-    hipStream_t s = rt.s();
-    void** d_outs = (void**)upload_tmp(rt.scratch, outs, s);
-    int64_t* d_ldo = (int64_t*)upload_tmp(rt.scratch, ldo, s);
-    chk(launch_id_expand<T>(d_tasks, nb, d_outs, d_ldo, transpose, conj, s), "id expand");
+  void expand(const std::vector<void*>& outs, const std::vector<int64_t>& ldo, bool transpose, bool conj) {
+    if (ntasks == 0) return;
+    void** d_outs = (void**)upload_tmp(rt, outs);
+    int64_t* d_ldo = (int64_t*)upload_tmp(rt, ldo);
+    chk(launch_id_expand<T>(d_tasks, ntasks, d_outs, d_ldo, transpose, conj, rt.s()), "id expand");
   }
   IdTask* d_tasks = nullptr;
+  int ntasks = 0;
 };
 
 template <class T>
@@ -592,12 +642,8 @@ std::vector<int32_t> right_cols(const Butterfly& bf, int l, int t, int v) {
 
 // allocate level storage after the ranks of level l (left side) are known
 template <class T>
-void alloc_left(FactorAlloc<T>& fa, Butterfly& bf, int l, std::vector<void*>& outs, std::vector<int64_t>& ldo) {
+void alloc_left(FactorAlloc<T>& fa, Butterfly& bf, int l) {
   const int nb = 1 << bf.L;
-  char* base = fa.rt.pool_base();
-  (void)base;
-  outs.assign(nb, nullptr);
-  ldo.assign(nb, 1);
   if (l == bf.L) {
     bf.offL[l].assign(nb, 0);
     for (int t = 0; t < nb; ++t) bf.offL[l][t] = fa.alloc((int64_t)bf.to.size(l, t) * bf.rl[l][t]);
@@ -612,23 +658,22 @@ void alloc_left(FactorAlloc<T>& fa, Butterfly& bf, int l, std::vector<void*>& ou
   }
 }
 
+// destinations of the interpolation matrices of left level l (appended)
 template <class T>
 void left_outs(BfRuntime<T>& rt, Butterfly& bf, int l, std::vector<void*>& outs, std::vector<int64_t>& ldo) {
   const int nb = 1 << bf.L;
   char* base = rt.pool_base();
-  outs.assign(nb, nullptr);
-  ldo.assign(nb, 1);
   for (int blk = 0; blk < nb; ++blk) {
     if (l == bf.L) {
-      outs[blk] = base + bf.offL[l][blk] * sizeof(cplx<T>);
-      ldo[blk] = std::max(1, bf.to.size(l, blk));
+      outs.push_back(base + bf.offL[l][blk] * sizeof(cplx<T>));
+      ldo.push_back(std::max(1, bf.to.size(l, blk)));
     } else {
       const int vs1 = 1 << (bf.L - l - 1);
       const int pr = blk / 2, t = pr / vs1, v1 = pr % vs1;
       const int rows = bf.rl[l + 1][(2 * t) * vs1 + v1] + bf.rl[l + 1][(2 * t + 1) * vs1 + v1];
       const int col_off = (blk & 1) ? bf.rl[l][blk - 1] : 0;
-      outs[blk] = base + (bf.offL[l][pr] + (int64_t)col_off * rows) * sizeof(cplx<T>);
-      ldo[blk] = std::max(rows, 1);
+      outs.push_back(base + (bf.offL[l][pr] + (int64_t)col_off * rows) * sizeof(cplx<T>));
+      ldo.push_back(std::max(rows, 1));
     }
   }
 }
@@ -652,397 +697,492 @@ void alloc_right(FactorAlloc<T>& fa, Butterfly& bf, int l) {
   }
 }
 
+// destinations of the interpolation matrices of right level l (appended)
 template <class T>
 void right_outs(BfRuntime<T>& rt, Butterfly& bf, int l, std::vector<void*>& outs, std::vector<int64_t>& ldo) {
   const int nb = 1 << bf.L;
   char* base = rt.pool_base();
-  outs.assign(nb, nullptr);
-  ldo.assign(nb, 1);
   const int vs = 1 << (bf.L - l);
   for (int blk = 0; blk < nb; ++blk) {
     if (l == 0) {
-      outs[blk] = base + bf.offR[0][blk] * sizeof(cplx<T>);
-      ldo[blk] = std::max(1, bf.rr[0][blk]);
+      outs.push_back(base + bf.offR[0][blk] * sizeof(cplx<T>));
+      ldo.push_back(std::max(1, bf.rr[0][blk]));
     } else {
       const int t = blk / vs, v = blk % vs, t2 = t / 2;
       const int q = t2 * vs + v;
       const int a = (2 * t2) * vs + v, b = (2 * t2 + 1) * vs + v;
       const int rows = bf.rr[l][a] + bf.rr[l][b];
       const int row_off = (t & 1) ? bf.rr[l][a] : 0;
-      outs[blk] = base + (bf.offR[l][q] + row_off) * sizeof(cplx<T>);
-      ldo[blk] = std::max(rows, 1);
+      outs.push_back(base + (bf.offR[l][q] + row_off) * sizeof(cplx<T>));
+      ldo.push_back(std::max(rows, 1));
     }
   }
+}
+
+// One block of a construction step: its butterfly, position and candidates.
+struct StepBlock {
+  Butterfly* bf;
+  int blk, level;
+  std::vector<int32_t> cand;  // candidate rows (left) or columns (right)
+};
+
+// After the IDs of one step: record ranks and skeletons, allocate the level,
+// and expand the interpolation matrices of every block in one launch.
+template <class T>
+void finish_step(BfRuntime<T>& rt, IdLevel<T>& idl, std::vector<StepBlock>& blocks, const std::vector<int>& rank,
+                 const std::vector<std::vector<int32_t>>& perm, const std::vector<Butterfly*>& act,
+                 const std::vector<int>& act_level, bool left, bool conj) {
+  for (size_t b = 0; b < blocks.size(); ++b) {
+    Butterfly& bf = *blocks[b].bf;
+    const int blk = blocks[b].blk;
+    const int l = blocks[b].level;
+    auto& r = left ? bf.rl[l][blk] : bf.rr[l][blk];
+    auto& sk = left ? bf.Ob[l][blk] : bf.Sb[l][blk];
+    r = rank[b];
+    sk.clear();
+    for (int k = 0; k < rank[b]; ++k) sk.push_back(blocks[b].cand[perm[b][k]]);
+  }
+  // every allocation first: the pool may move while it grows
+  for (size_t a = 0; a < act.size(); ++a) {
+    FactorAlloc<T> fa{rt, *act[a]};
+    if (left)
+      alloc_left(fa, *act[a], act_level[a]);
+    else
+      alloc_right(fa, *act[a], act_level[a]);
+  }
+  std::vector<void*> outs;
+  std::vector<int64_t> ldo;
+  for (size_t a = 0; a < act.size(); ++a) {
+    if (left)
+      left_outs(rt, *act[a], act_level[a], outs, ldo);
+    else
+      right_outs(rt, *act[a], act_level[a], outs, ldo);
+  }
+  idl.expand(outs, ldo, !left, conj);
 }
 
 }  // namespace
 
 // ----------------------------------------------------------- Alg. 2
 template <class T>
+void bf_entry_eval_batch(BfRuntime<T>& rt, const std::vector<EntryJob<T>*>& jobs) {
+  if (jobs.empty()) return;
+  auto mk = rt.scratch.mark();
+  for (auto* j : jobs) {
+    j->out = std::make_unique<Butterfly>();
+    init_bf(*j->out, j->to, j->ts);
+    ++rt.n_entry;
+  }
+  // left to middle: row IDs of K(rows, proxy columns); step k works on level L - k of every butterfly
+  for (int k = 0;; ++k) {
+    auto smk = rt.scratch.mark();
+    ExtractBatch eb;
+    std::vector<StepBlock> blocks;
+    std::vector<void*> A;
+    std::vector<int> q, p;
+    std::vector<Butterfly*> act;
+    std::vector<int> act_level;
+    for (auto* j : jobs) {
+      Butterfly& bf = *j->out;
+      const int L = bf.L, l = L - k;
+      if (l < bf.lc) continue;
+      act.push_back(&bf);
+      act_level.push_back(l);
+      const int vs = 1 << (L - l);
+      for (int blk = 0; blk < (1 << L); ++blk) {
+        const int t = blk / vs, v = blk % vs;
+        StepBlock sb{&bf, blk, l, left_rows(bf, l, t, v)};
+        std::vector<int32_t> cols;
+        j->ps->columns(sb.cand, bf.ts.beg(L - l, v), bf.ts.end(L - l, v), cols);
+        const int pp = (int)sb.cand.size(), qq = (int)cols.size();
+        void* a = rt.scratch.take((size_t)std::max(pp * qq, 1) * sizeof(cplx<T>));
+        j->src->request(eb, sb.cand, cols, a, std::max(qq, 1), true);  // A = K(rows, cols)^T, q x p
+        A.push_back(a);
+        q.push_back(qq);
+        p.push_back(pp);
+        blocks.push_back(std::move(sb));
+      }
+    }
+    if (act.empty()) break;
+    run_extract(rt, eb);
+    IdLevel<T> idl(rt);
+    std::vector<int> rank;
+    std::vector<std::vector<int32_t>> perm;
+    idl.run(A, q, p, rank, perm);
+    finish_step(rt, idl, blocks, rank, perm, act, act_level, true, false);
+    rt.scratch.release(smk);
+  }
+  // right to middle: column IDs of K(proxy rows, cols); step k works on level k
+  for (int k = 0;; ++k) {
+    auto smk = rt.scratch.mark();
+    ExtractBatch eb;
+    std::vector<StepBlock> blocks;
+    std::vector<void*> A;
+    std::vector<int> q, p;
+    std::vector<Butterfly*> act;
+    std::vector<int> act_level;
+    for (auto* j : jobs) {
+      Butterfly& bf = *j->out;
+      const int L = bf.L, l = k;
+      if (l > bf.lc) continue;
+      act.push_back(&bf);
+      act_level.push_back(l);
+      const int vs = 1 << (L - l);
+      for (int blk = 0; blk < (1 << L); ++blk) {
+        const int t = blk / vs, v = blk % vs;
+        StepBlock sb{&bf, blk, l, right_cols(bf, l, t, v)};
+        std::vector<int32_t> rows;
+        j->ps->rows(sb.cand, bf.to.beg(l, t), bf.to.end(l, t), rows);
+        const int pp = (int)sb.cand.size(), qq = (int)rows.size();
+        void* a = rt.scratch.take((size_t)std::max(pp * qq, 1) * sizeof(cplx<T>));
+        j->src->request(eb, rows, sb.cand, a, std::max(qq, 1), false);  // A = K(rows, cols), q x p
+        A.push_back(a);
+        q.push_back(qq);
+        p.push_back(pp);
+        blocks.push_back(std::move(sb));
+      }
+    }
+    if (act.empty()) break;
+    run_extract(rt, eb);
+    IdLevel<T> idl(rt);
+    std::vector<int> rank;
+    std::vector<std::vector<int32_t>> perm;
+    idl.run(A, q, p, rank, perm);
+    finish_step(rt, idl, blocks, rank, perm, act, act_level, false, false);
+    rt.scratch.release(smk);
+  }
+  // centre: B = K(Obar, Sbar); every allocation first (the pool may move)
+  for (auto* j : jobs) {
+    Butterfly& bf = *j->out;
+    FactorAlloc<T> fa{rt, bf};
+    for (int blk = 0; blk < (1 << bf.L); ++blk) bf.offB[blk] = fa.alloc((int64_t)bf.rl[bf.lc][blk] * bf.rr[bf.lc][blk]);
+  }
+  ExtractBatch eb;
+  for (auto* j : jobs) {
+    Butterfly& bf = *j->out;
+    for (int blk = 0; blk < (1 << bf.L); ++blk)
+      j->src->request(eb, bf.Ob[bf.lc][blk], bf.Sb[bf.lc][blk], rt.pool_base() + bf.offB[blk] * sizeof(cplx<T>),
+                      std::max(1, bf.rl[bf.lc][blk]), false);
+  }
+  run_extract(rt, eb);
+  rt.scratch.release(mk);
+  for (auto* j : jobs) rt.max_rank_seen = std::max(rt.max_rank_seen, j->out->max_rank());
+}
+
+template <class T>
 std::unique_ptr<Butterfly> bf_entry_eval(BfRuntime<T>& rt, EntrySource<T>& src, ProxySampler& ps, const BTree& to,
                                          const BTree& ts) {
-  auto bfp = std::make_unique<Butterfly>();
-  Butterfly& bf = *bfp;
-  init_bf(bf, to, ts);
-  FactorAlloc<T> fa{rt, bf};
-  const int L = bf.L, lc = bf.lc, nb = 1 << L;
-  auto mk = rt.scratch.mark();
-  ++rt.n_entry;
-  // left to middle: row IDs of K(rows, proxy columns)
-  for (int l = L; l >= lc; --l) {
-    const int vs = 1 << (L - l);
-    std::vector<std::vector<int32_t>> rows(nb), cols(nb);
-    std::vector<const std::vector<int32_t>*> pr(nb), pc(nb);
-    std::vector<void*> A(nb);
-    std::vector<int64_t> lda(nb);
-    std::vector<int> q(nb), p(nb);
-    for (int blk = 0; blk < nb; ++blk) {
-      const int t = blk / vs, v = blk % vs;
-      rows[blk] = left_rows(bf, l, t, v);
-      ps.columns(rows[blk], ts.beg(L - l, v), ts.end(L - l, v), cols[blk]);
-      p[blk] = (int)rows[blk].size();
-      q[blk] = (int)cols[blk].size();
-      A[blk] = rt.scratch.take((size_t)std::max(p[blk] * q[blk], 1) * sizeof(cplx<T>));
-      lda[blk] = std::max(q[blk], 1);
-      pr[blk] = &rows[blk];
-      pc[blk] = &cols[blk];
-    }
-    src.extract(pr, pc, A, lda, true);  // A = K(rows, cols)^T, q x p
-    IdLevel<T> idl(rt);
-    std::vector<int> rank, maxrank;
-    std::vector<std::vector<int32_t>> perm;
-    std::vector<void*> Tb;
-    idl.run(A, q, p, rank, perm, Tb, maxrank, 1 << 20);
-    for (int blk = 0; blk < nb; ++blk) {
-      bf.rl[l][blk] = rank[blk];
-      bf.Ob[l][blk].clear();
-      for (int k = 0; k < rank[blk]; ++k) bf.Ob[l][blk].push_back(rows[blk][perm[blk][k]]);
-    }
-    std::vector<void*> outs;
-    std::vector<int64_t> ldo;
-    alloc_left(fa, bf, l, outs, ldo);
-    left_outs(rt, bf, l, outs, ldo);
-    idl.expand(nb, outs, ldo, false, false);
-  }
-  // right to middle: column IDs of K(proxy rows, cols)
-  for (int l = 0; l <= lc; ++l) {
-    const int vs = 1 << (L - l);
-    std::vector<std::vector<int32_t>> rows(nb), cols(nb);
-    std::vector<const std::vector<int32_t>*> pr(nb), pc(nb);
-    std::vector<void*> A(nb);
-    std::vector<int64_t> lda(nb);
-    std::vector<int> q(nb), p(nb);
-    for (int blk = 0; blk < nb; ++blk) {
-      const int t = blk / vs, v = blk % vs;
-      cols[blk] = right_cols(bf, l, t, v);
-      ps.rows(cols[blk], to.beg(l, t), to.end(l, t), rows[blk]);
-      p[blk] = (int)cols[blk].size();
-      q[blk] = (int)rows[blk].size();
-      A[blk] = rt.scratch.take((size_t)std::max(p[blk] * q[blk], 1) * sizeof(cplx<T>));
-      lda[blk] = std::max(q[blk], 1);
-      pr[blk] = &rows[blk];
-      pc[blk] = &cols[blk];
-    }
-    src.extract(pr, pc, A, lda, false);  // A = K(rows, cols), q x p
-    IdLevel<T> idl(rt);
-    std::vector<int> rank, maxrank;
-    std::vector<std::vector<int32_t>> perm;
-    std::vector<void*> Tb;
-    idl.run(A, q, p, rank, perm, Tb, maxrank, 1 << 20);
-    for (int blk = 0; blk < nb; ++blk) {
-      bf.rr[l][blk] = rank[blk];
-      bf.Sb[l][blk].clear();
-      for (int k = 0; k < rank[blk]; ++k) bf.Sb[l][blk].push_back(cols[blk][perm[blk][k]]);
-    }
-    alloc_right(fa, bf, l);
-    std::vector<void*> outs;
-    std::vector<int64_t> ldo;
-    right_outs(rt, bf, l, outs, ldo);
-    idl.expand(nb, outs, ldo, true, false);
-  }
-  // centre: B = K(Obar, Sbar)
-  {
-    std::vector<const std::vector<int32_t>*> pr(nb), pc(nb);
-    std::vector<void*> outs(nb);
-    std::vector<int64_t> ldo(nb);
-    // allocate every block first: the pool may move while it grows
-    for (int blk = 0; blk < nb; ++blk) bf.offB[blk] = fa.alloc((int64_t)bf.rl[lc][blk] * bf.rr[lc][blk]);
-    for (int blk = 0; blk < nb; ++blk) {
-      pr[blk] = &bf.Ob[lc][blk];
-      pc[blk] = &bf.Sb[lc][blk];
-      outs[blk] = rt.pool_base() + bf.offB[blk] * sizeof(cplx<T>);
-      ldo[blk] = std::max(1, bf.rl[lc][blk]);
-    }
-    src.extract(pr, pc, outs, ldo, false);
-  }
-  chk(hipStreamSynchronize(rt.s()), "entry eval");
-  rt.scratch.release(mk);
-  rt.max_rank_seen = std::max(rt.max_rank_seen, bf.max_rank());
-  return bfp;
+  EntryJob<T> j{&src, &ps, to, ts, nullptr};
+  bf_entry_eval_batch<T>(rt, {&j});
+  return std::move(j.out);
 }
 
 // ----------------------------------------------------------- Sec. 3.3
+namespace {
+
 template <class T>
-static std::unique_ptr<Butterfly> random_once(BfRuntime<T>& rt, Op<T>& op, const BTree& to, const BTree& ts, int S,
-                                              int& max_id_rank) {
-  auto bfp = std::make_unique<Butterfly>();
-  Butterfly& bf = *bfp;
-  init_bf(bf, to, ts);
-  FactorAlloc<T> fa{rt, bf};
-  const int L = bf.L, lc = bf.lc, nb = 1 << L;
-  const int m = to.n, n = ts.n;
+struct Sketch {
+  int ncl = 0, ncr = 0;
+  std::vector<int> lcol0, rcol0;
+  void *Om = nullptr, *Y = nullptr, *Ps = nullptr, *Z = nullptr;
+};
+
+// One attempt of the randomized construction for every job at its sample count.
+template <class T>
+void random_once_batch(BfRuntime<T>& rt, const std::vector<RandomJob<T>*>& jobs) {
   hipStream_t s = rt.s();
   auto mk = rt.scratch.mark();
-  // probe groups: left levels l = L..lc, column node v at level L-l
-  std::vector<int32_t> gb, ge;
-  std::vector<int> lcol0(L + 1, 0);
-  for (int l = L; l >= lc; --l) {
-    lcol0[l] = (int)gb.size() * S;
-    for (int v = 0; v < (1 << (L - l)); ++v) {
-      gb.push_back(ts.beg(L - l, v));
-      ge.push_back(ts.end(L - l, v));
-    }
-  }
-  const int ncl = (int)gb.size() * S;
-  std::vector<int32_t> hb2, he2;
-  std::vector<int> rcol0(lc + 1, 0);
-  for (int l = 0; l <= lc; ++l) {
-    rcol0[l] = (int)hb2.size() * S;
-    for (int t = 0; t < (1 << l); ++t) {
-      hb2.push_back(to.beg(l, t));
-      he2.push_back(to.end(l, t));
-    }
-  }
-  const int ncr = (int)hb2.size() * S;
-  void* Om = rt.scratch.take((size_t)std::max(n, 1) * ncl * sizeof(cplx<T>));
-  void* Y = rt.scratch.take((size_t)std::max(m, 1) * ncl * sizeof(cplx<T>));
-  void* Ps = rt.scratch.take((size_t)std::max(m, 1) * ncr * sizeof(cplx<T>));
-  void* Z = rt.scratch.take((size_t)std::max(n, 1) * ncr * sizeof(cplx<T>));
-  int32_t* d_gb = (int32_t*)upload_tmp(rt.scratch, gb, s);
-  int32_t* d_ge = (int32_t*)upload_tmp(rt.scratch, ge, s);
-  int32_t* d_hb = (int32_t*)upload_tmp(rt.scratch, hb2, s);
-  int32_t* d_he = (int32_t*)upload_tmp(rt.scratch, he2, s);
-  chk(launch_philox_gauss<T>(Om, std::max(n, 1), n, ncl, S, d_gb, d_ge, rt.seed, rt.stream_id++, s), "probes");
-  chk(launch_philox_gauss<T>(Ps, std::max(m, 1), m, ncr, S, d_hb, d_he, rt.seed, rt.stream_id++, s), "probes");
-  op.apply(Om, std::max(n, 1), Y, std::max(m, 1), ncl, false, 1.0, 0);
-  op.apply(Ps, std::max(m, 1), Z, std::max(n, 1), ncr, true, 1.0, 0);
-  max_id_rank = 0;
-  // left: row IDs of the sketch rows
-  for (int l = L; l >= lc; --l) {
-    const int vs = 1 << (L - l);
-    std::vector<std::vector<int32_t>> rows(nb), cols(nb);
-    std::vector<const std::vector<int32_t>*> pr(nb), pc(nb);
-    std::vector<void*> A(nb);
-    std::vector<int64_t> lda(nb);
-    std::vector<int> q(nb), p(nb);
-    std::vector<ExtractTask> tasks(nb);
-    for (int blk = 0; blk < nb; ++blk) {
-      const int t = blk / vs, v = blk % vs;
-      rows[blk] = left_rows(bf, l, t, v);
-      cols[blk].resize(S);
-      for (int k = 0; k < S; ++k) cols[blk][k] = lcol0[l] + v * S + k;
-      p[blk] = (int)rows[blk].size();
-      q[blk] = S;
-      A[blk] = rt.scratch.take((size_t)std::max(p[blk] * S, 1) * sizeof(cplx<T>));
-      lda[blk] = S;
-    }
-    // gather A = Y(rows, group)^T through the dense-source extraction
-    {
-      std::vector<int32_t> idx;
-      std::vector<int64_t> ro(nb), co(nb);
-      for (int blk = 0; blk < nb; ++blk) {
-        ro[blk] = (int64_t)idx.size();
-        idx.insert(idx.end(), rows[blk].begin(), rows[blk].end());
-        co[blk] = (int64_t)idx.size();
-        idx.insert(idx.end(), cols[blk].begin(), cols[blk].end());
+  const size_t nj = jobs.size();
+  std::vector<Sketch<T>> sk(nj);
+  // probes and sketches: Y = K Omega (column groups of left levels), Z = K^H Psi (row groups of right levels)
+  for (size_t ji = 0; ji < nj; ++ji) {
+    RandomJob<T>& j = *jobs[ji];
+    j.out = std::make_unique<Butterfly>();
+    Butterfly& bf = *j.out;
+    init_bf(bf, j.to, j.ts);
+    const int L = bf.L, lc = bf.lc, S = j.S, m = j.to.n, n = j.ts.n;
+    Sketch<T>& w = sk[ji];
+    std::vector<int32_t> gb, ge, hb, he;
+    w.lcol0.assign(L + 1, 0);
+    for (int l = L; l >= lc; --l) {
+      w.lcol0[l] = (int)gb.size() * S;
+      for (int v = 0; v < (1 << (L - l)); ++v) {
+        gb.push_back(j.ts.beg(L - l, v));
+        ge.push_back(j.ts.end(L - l, v));
       }
-      int32_t* d_idx = (int32_t*)upload_tmp(rt.scratch, idx, s);
-      for (int blk = 0; blk < nb; ++blk) {
-        ExtractTask& e = tasks[blk];
-        std::memset(&e, 0, sizeof(e));
-        e.rows = d_idx + ro[blk];
-        e.cols = d_idx + co[blk];
-        e.nr = p[blk];
-        e.nc = S;
-        e.out = A[blk];
-        e.ldo = S;
-        e.trans = 1;
-        e.dense = Y;
-        e.ldd = std::max(m, 1);
+    }
+    w.ncl = (int)gb.size() * S;
+    w.rcol0.assign(lc + 1, 0);
+    for (int l = 0; l <= lc; ++l) {
+      w.rcol0[l] = (int)hb.size() * S;
+      for (int t = 0; t < (1 << l); ++t) {
+        hb.push_back(j.to.beg(l, t));
+        he.push_back(j.to.end(l, t));
       }
-      ExtractTask* d_t = (ExtractTask*)upload_tmp(rt.scratch, tasks, s);
-      chk(launch_front_extract<T>(d_t, nb, 4, nullptr, nullptr, false, s), "gather");
     }
-    IdLevel<T> idl(rt);
-    std::vector<int> rank, maxrank;
-    std::vector<std::vector<int32_t>> perm;
-    std::vector<void*> Tb;
-    idl.run(A, q, p, rank, perm, Tb, maxrank, 1 << 20);
-    for (int blk = 0; blk < nb; ++blk) {
-      bf.rl[l][blk] = rank[blk];
-      max_id_rank = std::max(max_id_rank, rank[blk]);
-      bf.Ob[l][blk].clear();
-      for (int k = 0; k < rank[blk]; ++k) bf.Ob[l][blk].push_back(rows[blk][perm[blk][k]]);
-    }
-    std::vector<void*> outs;
-    std::vector<int64_t> ldo;
-    alloc_left(fa, bf, l, outs, ldo);
-    left_outs(rt, bf, l, outs, ldo);
-    idl.expand(nb, outs, ldo, false, false);
+    w.ncr = (int)hb.size() * S;
+    w.Om = rt.scratch.take((size_t)std::max(n, 1) * w.ncl * sizeof(cplx<T>));
+    w.Y = rt.scratch.take((size_t)std::max(m, 1) * w.ncl * sizeof(cplx<T>));
+    w.Ps = rt.scratch.take((size_t)std::max(m, 1) * w.ncr * sizeof(cplx<T>));
+    w.Z = rt.scratch.take((size_t)std::max(n, 1) * w.ncr * sizeof(cplx<T>));
+    int32_t* d_gb = (int32_t*)upload_tmp(rt, gb);
+    int32_t* d_ge = (int32_t*)upload_tmp(rt, ge);
+    int32_t* d_hb = (int32_t*)upload_tmp(rt, hb);
+    int32_t* d_he = (int32_t*)upload_tmp(rt, he);
+    chk(launch_philox_gauss<T>(w.Om, std::max(n, 1), n, w.ncl, S, d_gb, d_ge, rt.seed, rt.stream_id++, s), "probes");
+    chk(launch_philox_gauss<T>(w.Ps, std::max(m, 1), m, w.ncr, S, d_hb, d_he, rt.seed, rt.stream_id++, s), "probes");
+    j.op->apply(w.Om, std::max(n, 1), w.Y, std::max(m, 1), w.ncl, false, 1.0, 0);
+    j.op->apply(w.Ps, std::max(m, 1), w.Z, std::max(n, 1), w.ncr, true, 1.0, 0);
+    j.max_id_rank = 0;
   }
-  // right: column IDs through K^H sketches (row IDs of Z rows)
-  for (int l = 0; l <= lc; ++l) {
-    const int vs = 1 << (L - l);
-    std::vector<std::vector<int32_t>> cols(nb), grp(nb);
-    std::vector<void*> A(nb);
-    std::vector<int> q(nb), p(nb);
-    std::vector<ExtractTask> tasks(nb);
-    std::vector<int32_t> idx;
-    std::vector<int64_t> ro(nb), co(nb);
-    for (int blk = 0; blk < nb; ++blk) {
-      const int t = blk / vs, v = blk % vs;
-      cols[blk] = right_cols(bf, l, t, v);
-      grp[blk].resize(S);
-      for (int k = 0; k < S; ++k) grp[blk][k] = rcol0[l] + t * S + k;
-      p[blk] = (int)cols[blk].size();
-      q[blk] = S;
-      A[blk] = rt.scratch.take((size_t)std::max(p[blk] * S, 1) * sizeof(cplx<T>));
-      ro[blk] = (int64_t)idx.size();
-      idx.insert(idx.end(), cols[blk].begin(), cols[blk].end());
-      co[blk] = (int64_t)idx.size();
-      idx.insert(idx.end(), grp[blk].begin(), grp[blk].end());
+  // left: row IDs of the sketch rows; step k works on level L - k of every butterfly
+  for (int k = 0;; ++k) {
+    auto smk = rt.scratch.mark();
+    ExtractBatch eb;
+    std::vector<StepBlock> blocks;
+    std::vector<void*> A;
+    std::vector<int> q, p;
+    std::vector<Butterfly*> act;
+    std::vector<int> act_level;
+    std::vector<RandomJob<T>*> owner;
+    for (size_t ji = 0; ji < nj; ++ji) {
+      RandomJob<T>& j = *jobs[ji];
+      Butterfly& bf = *j.out;
+      const int L = bf.L, l = L - k, S = j.S;
+      if (l < bf.lc) continue;
+      act.push_back(&bf);
+      act_level.push_back(l);
+      const int vs = 1 << (L - l);
+      for (int blk = 0; blk < (1 << L); ++blk) {
+        const int t = blk / vs, v = blk % vs;
+        StepBlock sb{&bf, blk, l, left_rows(bf, l, t, v)};
+        std::vector<int32_t> grp(S);
+        for (int kk = 0; kk < S; ++kk) grp[kk] = sk[ji].lcol0[l] + v * S + kk;
+        const int pp = (int)sb.cand.size();
+        void* a = rt.scratch.take((size_t)std::max(pp * S, 1) * sizeof(cplx<T>));
+        eb.add(nullptr, sk[ji].Y, std::max(j.to.n, 1), sb.cand, 0, grp, 0, a, S, true);  // A = Y(rows, group)^T
+        A.push_back(a);
+        q.push_back(S);
+        p.push_back(pp);
+        owner.push_back(&j);
+        blocks.push_back(std::move(sb));
+      }
     }
-    int32_t* d_idx = (int32_t*)upload_tmp(rt.scratch, idx, s);
-    for (int blk = 0; blk < nb; ++blk) {
-      ExtractTask& e = tasks[blk];
-      std::memset(&e, 0, sizeof(e));
-      e.rows = d_idx + ro[blk];
-      e.cols = d_idx + co[blk];
-      e.nr = p[blk];
-      e.nc = S;
-      e.out = A[blk];
-      e.ldo = S;
-      e.trans = 1;
-      e.dense = Z;
-      e.ldd = std::max(n, 1);
-    }
-    ExtractTask* d_t = (ExtractTask*)upload_tmp(rt.scratch, tasks, s);
-    chk(launch_front_extract<T>(d_t, nb, 4, nullptr, nullptr, false, s), "gather");
+    if (act.empty()) break;
+    run_extract(rt, eb);
     IdLevel<T> idl(rt);
-    std::vector<int> rank, maxrank;
+    std::vector<int> rank;
     std::vector<std::vector<int32_t>> perm;
-    std::vector<void*> Tb;
-    idl.run(A, q, p, rank, perm, Tb, maxrank, 1 << 20);
-    for (int blk = 0; blk < nb; ++blk) {
-      bf.rr[l][blk] = rank[blk];
-      max_id_rank = std::max(max_id_rank, rank[blk]);
-      bf.Sb[l][blk].clear();
-      for (int k = 0; k < rank[blk]; ++k) bf.Sb[l][blk].push_back(cols[blk][perm[blk][k]]);
-    }
-    alloc_right(fa, bf, l);
-    std::vector<void*> outs;
-    std::vector<int64_t> ldo;
-    right_outs(rt, bf, l, outs, ldo);
-    idl.expand(nb, outs, ldo, true, true);  // Vt = U_c^H
+    idl.run(A, q, p, rank, perm);
+    for (size_t b = 0; b < blocks.size(); ++b) owner[b]->max_id_rank = std::max(owner[b]->max_id_rank, rank[b]);
+    finish_step(rt, idl, blocks, rank, perm, act, act_level, true, false);
+    rt.scratch.release(smk);
   }
-  // centre: B G = Yc with G = (right half) Omega_lc, Yc = Y(Obar, group);
-  // normal equations B (G G^H) = Yc G^H solved per block
-  {
+  // right: column IDs through K^H sketches (row IDs of the Z rows); step k works on level k
+  for (int k = 0;; ++k) {
+    auto smk = rt.scratch.mark();
+    ExtractBatch eb;
+    std::vector<StepBlock> blocks;
+    std::vector<void*> A;
+    std::vector<int> q, p;
+    std::vector<Butterfly*> act;
+    std::vector<int> act_level;
+    std::vector<RandomJob<T>*> owner;
+    for (size_t ji = 0; ji < nj; ++ji) {
+      RandomJob<T>& j = *jobs[ji];
+      Butterfly& bf = *j.out;
+      const int L = bf.L, l = k, S = j.S;
+      if (l > bf.lc) continue;
+      act.push_back(&bf);
+      act_level.push_back(l);
+      const int vs = 1 << (L - l);
+      for (int blk = 0; blk < (1 << L); ++blk) {
+        const int t = blk / vs, v = blk % vs;
+        StepBlock sb{&bf, blk, l, right_cols(bf, l, t, v)};
+        std::vector<int32_t> grp(S);
+        for (int kk = 0; kk < S; ++kk) grp[kk] = sk[ji].rcol0[l] + t * S + kk;
+        const int pp = (int)sb.cand.size();
+        void* a = rt.scratch.take((size_t)std::max(pp * S, 1) * sizeof(cplx<T>));
+        eb.add(nullptr, sk[ji].Z, std::max(j.ts.n, 1), sb.cand, 0, grp, 0, a, S, true);  // A = Z(cols, group)^T
+        A.push_back(a);
+        q.push_back(S);
+        p.push_back(pp);
+        owner.push_back(&j);
+        blocks.push_back(std::move(sb));
+      }
+    }
+    if (act.empty()) break;
+    run_extract(rt, eb);
+    IdLevel<T> idl(rt);
+    std::vector<int> rank;
+    std::vector<std::vector<int32_t>> perm;
+    idl.run(A, q, p, rank, perm);
+    for (size_t b = 0; b < blocks.size(); ++b) owner[b]->max_id_rank = std::max(owner[b]->max_id_rank, rank[b]);
+    finish_step(rt, idl, blocks, rank, perm, act, act_level, false, true);  // Vt = U_c^H
+    rt.scratch.release(smk);
+  }
+  // centre: B G = Yc with G = (right half) Omega_lc and Yc = Y(Obar, group);
+  // normal equations B (G G^H) = Yc G^H, solved per block
+  struct Centre {
+    BfPlan hp;
+    int64_t ws_off = 0, cw = 0;
+    std::vector<int64_t> m1_off, yc_off;
+  };
+  std::vector<Centre> ce(nj);
+  int64_t total = 0;
+  for (size_t ji = 0; ji < nj; ++ji) {
+    RandomJob<T>& j = *jobs[ji];
+    Butterfly& bf = *j.out;
+    const int L = bf.L, lc = bf.lc, nb = 1 << L, S = j.S, n = j.ts.n;
     const int ncol = (1 << (L - lc)) * S;
-    const void* Olc = (const char*)Om + (size_t)lcol0[lc] * std::max(n, 1) * sizeof(cplx<T>);
-    BfPlan hp = make_plan({BfCall{&bf, 0, 0, 1.0, 0.0, 0}}, false, ncol, std::max(n, 1), 1, true);
-    const VecLayout& hl = hp.half_layout[0];
-    const int64_t hoff = hp.half_off[0];
-    const int vs = 1 << (L - lc);
-    // workspace: [half plan | M1 blocks | Yc blocks]
-    std::vector<int64_t> m1_off(nb), yc_off(nb);
-    int64_t cw = std::max<int64_t>(hp.ws_elems, 1);
+    Centre& c = ce[ji];
+    c.hp = make_plan({BfCall{&bf, 0, 0, 1.0, 0.0, 0}}, false, ncol, std::max(n, 1), 1, true);
+    // workspace of the job: [half plan | M1 blocks | Yc blocks]
+    int64_t cw = std::max<int64_t>(c.hp.ws_elems, 1);
+    c.m1_off.assign(nb, 0);
+    c.yc_off.assign(nb, 0);
     for (int blk = 0; blk < nb; ++blk) {
-      m1_off[blk] = cw;
+      c.m1_off[blk] = cw;
       cw += (int64_t)std::max(bf.rr[lc][blk] * bf.rr[lc][blk], 1);
     }
     for (int blk = 0; blk < nb; ++blk) {
-      yc_off[blk] = cw;
+      c.yc_off[blk] = cw;
       cw += (int64_t)std::max(bf.rl[lc][blk] * S, 1);
     }
-    cplx<T>* ws = (cplx<T>*)rt.scratch.take((size_t)cw * sizeof(cplx<T>));
-    {
-      const int64_t lim[4] = {(int64_t)(rt.pool.used / sizeof(cplx<T>)), (int64_t)std::max(n, 1) * ncol, 0, cw};
-      run_plan<T>(hp, *rt.c, rt.pool_base(), Olc, nullptr, ws, s, lim);
-    }
-    std::vector<int32_t> idx;
-    std::vector<int64_t> ro(nb);
-    for (int blk = 0; blk < nb; ++blk) {
-      ro[blk] = (int64_t)idx.size();
-      idx.insert(idx.end(), bf.Ob[lc][blk].begin(), bf.Ob[lc][blk].end());
-    }
-    int32_t* d_idx = (int32_t*)upload_tmp(rt.scratch, idx, s);
+    c.ws_off = total;
+    c.cw = cw;
+    total += (cw + 15) & ~(int64_t)15;
+  }
+  cplx<T>* ws = (cplx<T>*)rt.scratch.take((size_t)std::max<int64_t>(total, 1) * sizeof(cplx<T>));
+  ExtractBatch eb;
+  for (size_t ji = 0; ji < nj; ++ji) {
+    RandomJob<T>& j = *jobs[ji];
+    Butterfly& bf = *j.out;
+    const int L = bf.L, lc = bf.lc, nb = 1 << L, S = j.S, m = j.to.n, n = j.ts.n;
+    const int ncol = (1 << (L - lc)) * S;
+    Centre& c = ce[ji];
+    const void* Olc = (const char*)sk[ji].Om + (size_t)sk[ji].lcol0[lc] * std::max(n, 1) * sizeof(cplx<T>);
+    const int64_t lim[4] = {(int64_t)(rt.pool.used / sizeof(cplx<T>)), (int64_t)std::max(n, 1) * ncol, 0, c.cw};
+    run_plan<T>(c.hp, *rt.c, rt.pool_base(), Olc, nullptr, ws + c.ws_off, s, lim);
+    std::vector<int32_t> grp(S);
+    for (int kk = 0; kk < S; ++kk) grp[kk] = kk;
+    const int vs = 1 << (L - lc);
     for (int blk = 0; blk < nb; ++blk) {
       const int v = blk % vs, r = bf.rl[lc][blk];
       if (r == 0) continue;
-      const void* Ysrc = (const char*)Y + (size_t)(lcol0[lc] + v * S) * std::max(m, 1) * sizeof(cplx<T>);
-      chk(launch_gather_rows<T>(Ysrc, std::max(m, 1), ws + yc_off[blk], r, d_idx + ro[blk], r, S, false, s), "gather");
+      const void* Ysrc = (const char*)sk[ji].Y + (size_t)(sk[ji].lcol0[lc] + v * S) * std::max(m, 1) * sizeof(cplx<T>);
+      eb.add(nullptr, Ysrc, std::max(m, 1), bf.Ob[lc][blk], 0, grp, 0, ws + c.ws_off + c.yc_off[blk], r, false);
     }
-    std::vector<GTask> gt;
-    std::vector<SolveTask> st;
-    // allocate every block first: the pool may move while it grows
-    for (int blk = 0; blk < nb; ++blk) bf.offB[blk] = fa.alloc((int64_t)bf.rl[lc][blk] * bf.rr[lc][blk]);
+  }
+  run_extract(rt, eb);
+  // every allocation first: the pool may move while it grows
+  for (size_t ji = 0; ji < nj; ++ji) {
+    Butterfly& bf = *jobs[ji]->out;
+    FactorAlloc<T> fa{rt, bf};
+    for (int blk = 0; blk < (1 << bf.L); ++blk) bf.offB[blk] = fa.alloc((int64_t)bf.rl[bf.lc][blk] * bf.rr[bf.lc][blk]);
+  }
+  std::vector<GTask> gt;
+  std::vector<SolveTask> st;
+  for (size_t ji = 0; ji < nj; ++ji) {
+    RandomJob<T>& j = *jobs[ji];
+    Butterfly& bf = *j.out;
+    const int L = bf.L, lc = bf.lc, nb = 1 << L, S = j.S;
+    Centre& c = ce[ji];
+    const VecLayout& hl = c.hp.half_layout[0];
+    const int64_t hoff = c.hp.half_off[0];
+    const int vs = 1 << (L - lc);
     for (int blk = 0; blk < nb; ++blk) {
       const int v = blk % vs;
       const int r = bf.rl[lc][blk], rp = bf.rr[lc][blk];
       if (r == 0 || rp == 0) continue;
       const int gi = hl.grp_of[blk];
-      const int64_t g_off = hoff + hl.grp_off[gi] + hl.mem_row[blk] + (int64_t)v * S * hl.grp_ld[gi];
+      const int64_t g_off = c.ws_off + hoff + hl.grp_off[gi] + hl.mem_row[blk] + (int64_t)v * S * hl.grp_ld[gi];
       const int64_t g_ld = std::max<int64_t>(hl.grp_ld[gi], 1);
       GTask t1 = {};  // M1 = G G^H (rp x rp)
       t1.a_off = g_off; t1.lda = g_ld; t1.opA = OP_N; t1.abase = 3;
       t1.b_off = g_off; t1.ldb = g_ld; t1.opB = OP_C; t1.bbase = 3;
-      t1.c_off = m1_off[blk]; t1.ldc = rp; t1.cbase = 3;
+      t1.c_off = c.ws_off + c.m1_off[blk]; t1.ldc = rp; t1.cbase = 3;
       t1.M = rp; t1.N = rp; t1.K = S; t1.alpha_re = 1; t1.beta = 0;
       gt.push_back(t1);
       GTask t2 = {};  // B = Yc G^H (r x rp), into the factor pool
-      t2.a_off = yc_off[blk]; t2.lda = r; t2.opA = OP_N; t2.abase = 3;
+      t2.a_off = c.ws_off + c.yc_off[blk]; t2.lda = r; t2.opA = OP_N; t2.abase = 3;
       t2.b_off = g_off; t2.ldb = g_ld; t2.opB = OP_C; t2.bbase = 3;
       t2.c_off = bf.offB[blk]; t2.ldc = r; t2.cbase = 0;
       t2.M = r; t2.N = rp; t2.K = S; t2.alpha_re = 1; t2.beta = 0;
       gt.push_back(t2);
-      st.push_back(SolveTask{ws + m1_off[blk], rp, rt.pool_base() + bf.offB[blk] * sizeof(cplx<T>), r, rp, r});
+      st.push_back(SolveTask{ws + c.ws_off + c.m1_off[blk], rp, rt.pool_base() + bf.offB[blk] * sizeof(cplx<T>), r, rp, r});
     }
+  }
+  if (!gt.empty()) {
     BfPlan gp;
     gp.phase.push_back(gt);
-    const int64_t lim[4] = {(int64_t)(rt.pool.used / sizeof(cplx<T>)), 0, 0, cw};
+    const int64_t lim[4] = {(int64_t)(rt.pool.used / sizeof(cplx<T>)), 0, 0, std::max<int64_t>(total, 1)};
     run_plan<T>(gp, *rt.c, rt.pool_base(), nullptr, nullptr, ws, s, lim);
-    void* d_st = upload_tmp(rt.scratch, st, s);
+    void* d_st = upload_tmp(rt, st);
     chk(launch_small_solve_right<T>(d_st, (int)st.size(), s), "lsq");
   }
-  chk(hipStreamSynchronize(s), "random matvec");
   rt.scratch.release(mk);
-  return bfp;
+}
+
+int size_bucket(int m, int n) {
+  int b = 0;
+  for (int x = std::max(std::max(m, n), 1); x > 1; x >>= 1) ++b;
+  return b;
+}
+
+}  // namespace
+
+template <class T>
+void bf_random_matvec_batch(BfRuntime<T>& rt, const std::vector<RandomJob<T>*>& jobs) {
+  std::vector<RandomJob<T>*> pending;
+  for (auto* j : jobs) {
+    const int b = size_bucket(j->to.n, j->ts.n);
+    // start at the sample count the last construction of this size settled on
+    const int hint = b < (int)rt.sample_hint.size() ? rt.sample_hint[b] : 0;
+    j->S = std::max({8, rt.samples, hint});
+    ++rt.n_random;
+    pending.push_back(j);
+  }
+  while (!pending.empty()) {
+    const size_t pool_mark = rt.pool.used;
+    random_once_batch<T>(rt, pending);
+    std::vector<RandomJob<T>*> again;
+    for (auto* j : pending) {
+      if (j->max_id_rank >= j->S - 8 && j->S < rt.max_samples) {
+        again.push_back(j);
+        continue;
+      }
+      const int b = size_bucket(j->to.n, j->ts.n);
+      if (b >= (int)rt.sample_hint.size()) rt.sample_hint.resize(b + 1, 0);
+      rt.sample_hint[b] = j->S;
+      rt.max_rank_seen = std::max(rt.max_rank_seen, j->out->max_rank());
+    }
+    if (again.size() == pending.size()) rt.pool.used = pool_mark;  // every attempt of this round is discarded
+    for (auto* j : again) {
+      j->out.reset();
+      j->S *= 2;
+    }
+    pending.swap(again);
+  }
 }
 
 template <class T>
 std::unique_ptr<Butterfly> bf_random_matvec(BfRuntime<T>& rt, Op<T>& op, const BTree& to, const BTree& ts) {
-  int S = std::max(8, rt.samples);
-  ++rt.n_random;
-  while (true) {
-    const size_t pool_mark = rt.pool.used;
-    int maxr = 0;
-    auto bf = random_once<T>(rt, op, to, ts, S, maxr);
-    if (maxr < S - 8 || S >= rt.max_samples) {
-      rt.max_rank_seen = std::max(rt.max_rank_seen, bf->max_rank());
-      return bf;
-    }
-    rt.pool.used = pool_mark;  // discard the factors of the attempt
-    S *= 2;
-  }
+  RandomJob<T> j;
+  j.op = &op;
+  j.to = to;
+  j.ts = ts;
+  bf_random_matvec_batch<T>(rt, {&j});
+  return std::move(j.out);
 }
 
-template std::unique_ptr<Butterfly> bf_entry_eval<double>(BfRuntime<double>&, EntrySource<double>&, ProxySampler&,
-                                                          const BTree&, const BTree&);
-template std::unique_ptr<Butterfly> bf_entry_eval<float>(BfRuntime<float>&, EntrySource<float>&, ProxySampler&,
-                                                         const BTree&, const BTree&);
-template std::unique_ptr<Butterfly> bf_random_matvec<double>(BfRuntime<double>&, Op<double>&, const BTree&,
-                                                             const BTree&);
-template std::unique_ptr<Butterfly> bf_random_matvec<float>(BfRuntime<float>&, Op<float>&, const BTree&, const BTree&);
+#define BF_INST(T)                                                                                                  \
+  template void bf_entry_eval_batch<T>(BfRuntime<T>&, const std::vector<EntryJob<T>*>&);                            \
+  template std::unique_ptr<Butterfly> bf_entry_eval<T>(BfRuntime<T>&, EntrySource<T>&, ProxySampler&, const BTree&, \
+                                                       const BTree&);                                               \
+  template void bf_random_matvec_batch<T>(BfRuntime<T>&, const std::vector<RandomJob<T>*>&);                        \
+  template std::unique_ptr<Butterfly> bf_random_matvec<T>(BfRuntime<T>&, Op<T>&, const BTree&, const BTree&);
+BF_INST(double)
+BF_INST(float)
 
 }  // namespace bfmf

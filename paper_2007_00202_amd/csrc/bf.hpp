@@ -32,21 +32,28 @@ struct DevPool {
   void reset() { used = 0; }
 };
 
-// Stack of device temporaries: chunks are never moved, release() frees all
-// allocations made after a mark.
+// Stack of device temporaries. Chunks are allocated on demand and kept for
+// the life of the runtime (freeing device memory synchronizes the device);
+// release() rewinds the stack to a mark so the memory is reused.
 struct Scratch {
   struct Chunk {
     DevBuf b;
     size_t top = 0;
   };
   std::vector<std::unique_ptr<Chunk>> chunks;
+  int cur = -1;  // chunk holding the top of the stack
   size_t chunk_bytes = (size_t)256 << 20;
   struct Mark {
-    size_t nchunks, top;
+    int cur;
+    size_t top;
   };
-  Mark mark() const { return Mark{chunks.size(), chunks.empty() ? 0 : chunks.back()->top}; }
+  Mark mark() const { return Mark{cur, cur >= 0 ? chunks[cur]->top : 0}; }
   void release(const Mark& m);
   void* take(size_t bytes);
+  void clear() {
+    chunks.clear();
+    cur = -1;
+  }
   template <class T>
   T* take_n(size_t n) {
     return (T*)take(n * sizeof(T));
@@ -141,6 +148,8 @@ struct BfRuntime {
   double tol = 1e-3;
   int max_rank_seen = 0;
   int64_t n_random = 0, n_entry = 0;  // constructions performed
+  std::vector<int> sample_hint;       // per log2 size: probes the last randomized construction settled on
+  bool batch = true;                  // construct sets of butterflies together (else one at a time)
   hipStream_t s() const { return c->stream; }
   char* pool_base() const { return pool.base(); }
   // single-butterfly product Y = alpha op(K) X + beta Y
@@ -150,15 +159,26 @@ struct BfRuntime {
                  bool adjoint);
 };
 
-// Source of matrix entries for entry-evaluation construction: submatrices by
-// (row positions, column positions) into device buffers.
+// Extraction requests gathered over many blocks (and butterflies, and
+// fronts) and served by one launch.
+struct ExtractBatch {
+  std::vector<ExtractTask> tasks;  // rows / cols hold offsets into idx until the launch
+  std::vector<int32_t> idx;
+  // out = F(r0 + rows, c0 + cols) of the front fd, or of the dense matrix
+  // (ld ldd) when dense is not null; the transpose when trans.
+  void add(const FrontDesc* fd, const void* dense, int64_t ldd, const std::vector<int32_t>& rows, int r0,
+           const std::vector<int32_t>& cols, int c0, void* out, int64_t ldo, bool trans);
+};
+template <class T>
+void run_extract(BfRuntime<T>& rt, ExtractBatch& b);
+
+// Source of matrix entries for entry-evaluation construction.
 template <class T>
 struct EntrySource {
   virtual ~EntrySource() {}
-  // out(i, j) = K(rows[i], cols[j]) (ld_out rows), or the transpose when trans.
-  virtual void extract(const std::vector<const std::vector<int32_t>*>& rows,
-                       const std::vector<const std::vector<int32_t>*>& cols, const std::vector<void*>& outs,
-                       const std::vector<int64_t>& ldo, bool trans) = 0;
+  // queue out(i, j) = K(rows[i], cols[j]) (ld ldo), or the transpose when trans
+  virtual void request(ExtractBatch& b, const std::vector<int32_t>& rows, const std::vector<int32_t>& cols, void* out,
+                       int64_t ldo, bool trans) = 0;
 };
 
 // Proxy selection for entry evaluation (Sec. 3.2, Sec. 5.2): for a block with
@@ -169,11 +189,37 @@ struct ProxySampler {
   virtual void rows(const std::vector<int32_t>& cols, int beg, int end, std::vector<int32_t>& out) = 0;
 };
 
-// BF_entry_eval (Alg. 2)
+// One butterfly K(to, ts) to construct by entry evaluation.
+template <class T>
+struct EntryJob {
+  EntrySource<T>* src;
+  ProxySampler* ps;
+  BTree to, ts;
+  std::unique_ptr<Butterfly> out;
+};
+
+// One butterfly to construct from products with the operator op (m x n).
+template <class T>
+struct RandomJob {
+  Op<T>* op = nullptr;
+  BTree to, ts;
+  std::unique_ptr<Butterfly> out;
+  int S = 0;            // probes per tree node of the last attempt
+  int max_id_rank = 0;  // largest ID rank of the last attempt
+};
+
+// BF_entry_eval (Alg. 2) for a set of butterflies: level k of every
+// butterfly is one extraction, one ID and one expansion launch.
+template <class T>
+void bf_entry_eval_batch(BfRuntime<T>& rt, const std::vector<EntryJob<T>*>& jobs);
 template <class T>
 std::unique_ptr<Butterfly> bf_entry_eval(BfRuntime<T>& rt, EntrySource<T>& src, ProxySampler& ps, const BTree& to,
                                          const BTree& ts);
-// BF_random_matvec (Sec. 3.3): sketches with probes supported on one tree node
+// BF_random_matvec (Sec. 3.3): sketches with probes supported on one tree
+// node, for a set of butterflies at once (the operator products run one
+// after another, the IDs and centre solves of all of them together).
+template <class T>
+void bf_random_matvec_batch(BfRuntime<T>& rt, const std::vector<RandomJob<T>*>& jobs);
 template <class T>
 std::unique_ptr<Butterfly> bf_random_matvec(BfRuntime<T>& rt, Op<T>& op, const BTree& to, const BTree& ts);
 

@@ -17,46 +17,19 @@ struct bfmf_bf {
   std::string err;
 };
 
+namespace bfmf {
+thread_local std::string g_thread_error;
+}
+
 namespace {
 
 struct DenseSource : EntrySource<double> {
-  BfRuntime<double>& rt;
   const void* K;
   int64_t ldk;
-  DenseSource(BfRuntime<double>& r, const void* k, int64_t ld) : rt(r), K(k), ldk(ld) {}
-  void extract(const std::vector<const std::vector<int32_t>*>& rows, const std::vector<const std::vector<int32_t>*>& cols,
-               const std::vector<void*>& outs, const std::vector<int64_t>& ldo, bool trans) override {
-    const size_t nb = rows.size();
-    std::vector<int32_t> idx;
-    std::vector<int64_t> ro(nb), co(nb);
-    for (size_t i = 0; i < nb; ++i) {
-      ro[i] = (int64_t)idx.size();
-      idx.insert(idx.end(), rows[i]->begin(), rows[i]->end());
-      co[i] = (int64_t)idx.size();
-      idx.insert(idx.end(), cols[i]->begin(), cols[i]->end());
-    }
-    auto mk = rt.scratch.mark();
-    int32_t* d_idx = rt.scratch.take_n<int32_t>(std::max<size_t>(idx.size(), 1));
-    if (!idx.empty()) ochk(hipMemcpyAsync(d_idx, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, rt.s()), "idx");
-    std::vector<ExtractTask> tk(nb);
-    for (size_t i = 0; i < nb; ++i) {
-      ExtractTask& e = tk[i];
-      std::memset(&e, 0, sizeof(e));
-      e.rows = d_idx + ro[i];
-      e.cols = d_idx + co[i];
-      e.nr = (int32_t)rows[i]->size();
-      e.nc = (int32_t)cols[i]->size();
-      e.out = outs[i];
-      e.ldo = ldo[i];
-      e.trans = trans ? 1 : 0;
-      e.dense = K;
-      e.ldd = ldk;
-    }
-    ExtractTask* d_tk = (ExtractTask*)rt.scratch.take(tk.size() * sizeof(ExtractTask));
-    ochk(hipMemcpyAsync(d_tk, tk.data(), tk.size() * sizeof(ExtractTask), hipMemcpyHostToDevice, rt.s()), "tasks");
-    ochk(launch_front_extract<double>(d_tk, (int)nb, 4, nullptr, nullptr, false, rt.s()), "extract");
-    ochk(hipStreamSynchronize(rt.s()), "extract");
-    rt.scratch.release(mk);
+  DenseSource(const void* k, int64_t ld) : K(k), ldk(ld) {}
+  void request(ExtractBatch& b, const std::vector<int32_t>& rows, const std::vector<int32_t>& cols, void* out,
+               int64_t ldo, bool trans) override {
+    b.add(nullptr, K, ldk, rows, 0, cols, 0, out, ldo, trans);
   }
 };
 
@@ -111,15 +84,16 @@ bfmf_status bfmf_bf_compress_dense(int32_t device, int32_t m, int32_t n, const d
     ochk(hipMemcpy2D(b->K.p, (size_t)m * 16, K, (size_t)ldk * 16, (size_t)m * 16, n, hipMemcpyHostToDevice), "upload");
     BTree to = make_tree(m, L, nullptr, 0), ts = make_tree(n, L, nullptr, 0);
     if (method == 0) {
-      DenseSource src(b->rt, b->K.p, m);
+      DenseSource src(b->K.p, m);
       UniformSampler ps(seed ^ 0x9e3779b97f4a7c15ull, 4.0);
       b->bf = bf_entry_eval<double>(b->rt, src, ps, to, ts);
     } else {
       DenseOp<double> op(b->rt, b->K.p, m, m, n);
       b->bf = bf_random_matvec<double>(b->rt, op, to, ts);
     }
-    ochk(hipStreamSynchronize(b->ctx.stream), "compress");
+    b->ctx.stage.sync(b->ctx.stream);
   } catch (const Error& e) {
+    g_thread_error = e.msg;
     bfmf_status st = e.status;
     delete b;
     return st;
@@ -145,7 +119,7 @@ bfmf_status bfmf_bf_apply(bfmf_bf* b, int32_t adjoint, int32_t nrhs, const doubl
     ochk(hipMemcpy2DAsync(Y, (size_t)ldy * 16, dy, (size_t)nout * 16, (size_t)nout * 16, nrhs, hipMemcpyDeviceToHost,
                           b->ctx.stream),
          "download");
-    ochk(hipStreamSynchronize(b->ctx.stream), "apply");
+    b->ctx.stage.sync(b->ctx.stream);
     b->rt.scratch.release(mk);
   } catch (const Error& e) {
     b->err = e.msg;
@@ -165,12 +139,12 @@ bfmf_status bfmf_bf_info(bfmf_bf* b, int32_t* L, int32_t* max_rank, int64_t* ent
 void bfmf_bf_destroy(bfmf_bf* b) {
   if (!b) return;
   (void)hipSetDevice(b->ctx.device);
+  if (b->ctx.stream) (void)hipStreamSynchronize(b->ctx.stream);  // queued work still uses the buffers
   b->bf.reset();
-  b->rt.scratch.chunks.clear();
+  b->rt.scratch.clear();
   b->rt.pool.buf.release();
   b->K.release();
   if (b->ctx.stream) {
-    (void)hipStreamSynchronize(b->ctx.stream);
     (void)hipStreamDestroy(b->ctx.stream);
     b->ctx.stream = nullptr;
   }

@@ -17,10 +17,11 @@ namespace bfmf {
 
 namespace {
 
-template <class V>
-void* up(Scratch& sc, const std::vector<V>& v, hipStream_t s) {
-  void* d = sc.take(std::max<size_t>(v.size() * sizeof(V), 16));
-  if (!v.empty()) ochk(hipMemcpyAsync(d, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, s), "upload");
+// copy of a host vector in scratch memory, uploaded through the pinned ring
+template <class T, class V>
+void* up(BfRuntime<T>& rt, const std::vector<V>& v) {
+  void* d = rt.scratch.take(std::max<size_t>(v.size() * sizeof(V), 16));
+  rt.c->stage.put(d, v.data(), v.size() * sizeof(V), rt.s());
   return d;
 }
 
@@ -68,41 +69,12 @@ int depth_of(const std::vector<TreeNode>& all, int i) {
 // contribution blocks of the children through the extend-add maps).
 template <class T>
 struct FrontSource : EntrySource<T> {
-  BfRuntime<T>& rt;
   const FrontDesc* d_fd;
-  const void* values;
   int row0, col0;
-  FrontSource(BfRuntime<T>& r, const FrontDesc* fd, const void* vals, int r0, int c0)
-      : rt(r), d_fd(fd), values(vals), row0(r0), col0(c0) {}
-  void extract(const std::vector<const std::vector<int32_t>*>& rows, const std::vector<const std::vector<int32_t>*>& cols,
-               const std::vector<void*>& outs, const std::vector<int64_t>& ldo, bool trans) override {
-    const size_t nb = rows.size();
-    std::vector<int32_t> idx;
-    std::vector<int64_t> ro(nb), co(nb);
-    for (size_t i = 0; i < nb; ++i) {
-      ro[i] = (int64_t)idx.size();
-      for (int32_t r : *rows[i]) idx.push_back(row0 + r);
-      co[i] = (int64_t)idx.size();
-      for (int32_t c : *cols[i]) idx.push_back(col0 + c);
-    }
-    auto mk = rt.scratch.mark();
-    int32_t* d_idx = (int32_t*)up(rt.scratch, idx, rt.s());
-    std::vector<ExtractTask> tk(nb);
-    for (size_t i = 0; i < nb; ++i) {
-      ExtractTask& e = tk[i];
-      std::memset(&e, 0, sizeof(e));
-      e.rows = d_idx + ro[i];
-      e.cols = d_idx + co[i];
-      e.nr = (int32_t)rows[i]->size();
-      e.nc = (int32_t)cols[i]->size();
-      e.out = outs[i];
-      e.ldo = ldo[i];
-      e.trans = trans ? 1 : 0;
-    }
-    ExtractTask* d_tk = (ExtractTask*)up(rt.scratch, tk, rt.s());
-    ochk(launch_front_extract<T>(d_tk, (int)nb, 8, d_fd, values, sizeof(T) == 4, rt.s()), "front extract");
-    ochk(hipStreamSynchronize(rt.s()), "front extract");
-    rt.scratch.release(mk);
+  FrontSource(const FrontDesc* fd, int r0, int c0) : d_fd(fd), row0(r0), col0(c0) {}
+  void request(ExtractBatch& b, const std::vector<int32_t>& rows, const std::vector<int32_t>& cols, void* out,
+               int64_t ldo, bool trans) override {
+    b.add(d_fd, nullptr, 0, rows, row0, cols, col0, out, ldo, trans);
   }
 };
 
@@ -353,110 +325,177 @@ template void hodbf_inv_apply<double>(BfRuntime<double>&, const Hodbf<double>&, 
 namespace {
 
 template <class T>
-SmwResult bf_smw(BfRuntime<T>& rt, const std::vector<TreeNode>& nodes, int node, Op<T>* K11, Op<T>* K12, Op<T>* K21,
-                 Op<T>* K22, Op<T>* Kfull) {
+struct SmwJob {
+  const std::vector<TreeNode>* nodes = nullptr;
+  int node = 0;
+  Op<T>*K11 = nullptr, *K12 = nullptr, *K21 = nullptr, *K22 = nullptr;  // null blocks are zero
+  Op<T>* Kfull = nullptr;
   SmwResult res;
-  const TreeNode& nd = nodes[node];
-  const int n = nd.end - nd.beg;
-  const int d = depth_of(nodes, node);
+};
+
+// Dense base case for a set of blocks: M = I + K, X = M^-1 - I, where M^-1 is
+// the Schur complement of the bordered front [M I; -I 0] (partial LU with
+// pivoting inside M, the same kernels as the dense fronts, all blocks in one
+// batched launch sequence).
+template <class T>
+void smw_dense_batch(BfRuntime<T>& rt, const std::vector<SmwJob<T>*>& jobs, int* d_status) {
+  if (jobs.empty()) return;
   hipStream_t s = rt.s();
-  if (d == 0 || n <= kSmwDense) {
-    // dense: M = I + K, X = M^-1 - I.  M^-1 is the Schur complement of the
-    // bordered front [M I; -I 0] (partial LU with pivoting inside M).
-    const size_t off = rt.pool.alloc((size_t)n * n * sizeof(cplx<T>), s);
-    const int64_t eoff = (int64_t)(off / sizeof(cplx<T>));
-    auto mk = rt.scratch.mark();
-    const int N2 = 2 * n;
+  auto mk = rt.scratch.mark();
+  const size_t nj = jobs.size();
+  std::vector<int> hn(nj), hns(nj);
+  std::vector<int64_t> eoff(nj);
+  for (size_t i = 0; i < nj; ++i) {  // every pool allocation first (the pool may move)
+    const TreeNode& nd = (*jobs[i]->nodes)[jobs[i]->node];
+    hns[i] = nd.end - nd.beg;
+    hn[i] = 2 * hns[i];
+    eoff[i] = (int64_t)(rt.pool.alloc((size_t)hns[i] * hns[i] * sizeof(cplx<T>), s) / sizeof(cplx<T>));
+  }
+  std::vector<FrontDesc> fds(nj);
+  std::vector<cplx<T>*> Fs(nj), Is(nj);
+  for (size_t i = 0; i < nj; ++i) {
+    const int n = hns[i], N2 = hn[i];
     cplx<T>* F = (cplx<T>*)rt.scratch.take((size_t)N2 * N2 * sizeof(cplx<T>));
-    std::vector<cplx<T>> border((size_t)N2 * N2, cplx<T>{0, 0});
-    for (int i = 0; i < n; ++i) {
-      border[(size_t)i * N2 + i] = cplx<T>{1, 0};                  // M = I + K: identity part
-      border[(size_t)(n + i) * N2 + i] = cplx<T>{1, 0};            // F12 = I
-      border[(size_t)i * N2 + n + i] = cplx<T>{-1, 0};             // F21 = -I
-    }
-    ochk(hipMemcpyAsync(F, border.data(), border.size() * sizeof(cplx<T>), hipMemcpyHostToDevice, s), "border");
-    // a separate identity (F12 is overwritten by the factorization)
     cplx<T>* I = (cplx<T>*)rt.scratch.take((size_t)n * n * sizeof(cplx<T>));
-    ochk(launch_axpby<T>(I, n, F + (size_t)n * N2, N2, n, n, 1.0, 0.0, s), "identity");
-    Kfull->apply(I, n, F, N2, n, false, 1.0, 1);                  // F11 = I + K
     int32_t* piv = (int32_t*)rt.scratch.take((size_t)n * sizeof(int32_t));
-    int* dst = (int*)rt.scratch.take(16);
-    ochk(hipMemsetAsync(dst, 0, 16, s), "status");
-    FrontDesc fd;
+    ochk(launch_set_eye<T>(F, N2, N2, N2, 0, 1.0, s), "border");                    // M = I + K: identity part
+    ochk(launch_set_eye<T>(F + n + (size_t)n * N2, N2, n, n, 0, 0.0, s), "border");  // F22 = 0
+    ochk(launch_set_eye<T>(F + (size_t)n * N2, N2, n, n, 0, 1.0, s), "border");      // F12 = I
+    ochk(launch_set_eye<T>(F + n, N2, n, n, 0, -1.0, s), "border");                  // F21 = -I
+    ochk(launch_set_eye<T>(I, n, n, n, 0, 1.0, s), "identity");
+    jobs[i]->Kfull->apply(I, n, F, N2, n, false, 1.0, 1);  // F11 = I + K
+    FrontDesc& fd = fds[i];
     std::memset(&fd, 0, sizeof(fd));
     fd.F = F;
     fd.n = N2;
     fd.ns = n;
     fd.front = -1;
     fd.piv = piv;
-    void* d_fd = up(rt.scratch, std::vector<FrontDesc>{fd}, s);
-    const int hn = N2, hns = n;
-    ochk(launch_partial_lu<T>((const FrontDesc*)d_fd, 1, &hn, &hns, dst, s), "smw dense lu");
-    ochk(launch_schur<T>((const FrontDesc*)d_fd, 1, &hn, &hns, s), "smw dense schur");
-    cplx<T>* X = (cplx<T>*)(rt.pool_base() + off);
-    cplx<T>* C = F + n + (size_t)n * N2;  // M^-1
-    ochk(launch_axpby<T>(X, n, C, N2, n, n, 1.0, 0.0, s), "copy");
-    ochk(launch_axpby<T>(X, n, I, n, n, n, -1.0, 1.0, s), "minus identity");
-    int hst[3] = {0, 0, 0};
-    ochk(hipMemcpyAsync(hst, dst, 12, hipMemcpyDeviceToHost, s), "status");
-    ochk(hipStreamSynchronize(s), "smw dense");
-    rt.scratch.release(mk);
-    if (hst[0]) throw Error(BFMF_E_SINGULAR, "singular block in the HOD-BF inversion");
-    res.dense_off = eoff;
-    return res;
+    Fs[i] = F;
+    Is[i] = I;
   }
-  const int c1 = nd.left, c2 = nd.right;
-  const int n1 = nodes[c1].end - nodes[c1].beg, n2 = n - n1;
-  std::vector<std::unique_ptr<Op<T>>> keep;
-  auto sub = [&](Op<T>* op, int r0, int cc0, int m, int nn) -> Op<T>* {
-    keep.push_back(std::make_unique<SubOp<T>>(rt, op, r0, cc0, m, nn));
-    return keep.back().get();
-  };
-  // children blocks of a general butterfly come from views of the full operator
-  Op<T>* k11 = K11;
-  Op<T>* k12 = K12;
-  Op<T>* k21 = K21;
-  Op<T>* k22 = K22;
-  // X22: (I + K22)^-1 = I + X22
-  SmwResult x22;
-  if (k22) {
-    // recursive call on the children of c2 uses views of K22
-    const int c21 = nodes[c2].left;
-    if (c21 >= 0) {
-      const int m1 = nodes[c21].end - nodes[c21].beg, m2 = n2 - m1;
-      x22 = bf_smw<T>(rt, nodes, c2, sub(k22, 0, 0, m1, m1), sub(k22, 0, m1, m1, m2), sub(k22, m1, 0, m2, m1),
-                      sub(k22, m1, m1, m2, m2), k22);
-    } else {
-      x22 = bf_smw<T>(rt, nodes, c2, nullptr, nullptr, nullptr, nullptr, k22);
+  const FrontDesc* d_fd = (const FrontDesc*)up(rt, fds);
+  ochk(launch_partial_lu<T>(d_fd, (int)nj, hn.data(), hns.data(), d_status, s), "smw dense lu");
+  ochk(launch_schur<T>(d_fd, (int)nj, hn.data(), hns.data(), s), "smw dense schur");
+  for (size_t i = 0; i < nj; ++i) {
+    const int n = hns[i], N2 = hn[i];
+    cplx<T>* X = (cplx<T>*)(rt.pool_base() + eoff[i] * sizeof(cplx<T>));
+    ochk(launch_axpby<T>(X, n, Fs[i] + n + (size_t)n * N2, N2, n, n, 1.0, 0.0, s), "copy");  // M^-1
+    ochk(launch_axpby<T>(X, n, Is[i], n, n, n, -1.0, 1.0, s), "minus identity");
+    jobs[i]->res.dense_off = eoff[i];
+  }
+  rt.scratch.release(mk);
+}
+
+// BF_SMW (Alg. 4) for a set of nodes: X with (I + K)^-1 = I + X, K given by
+// its 2 x 2 blocks over the node's children.  Every stage of the recursion
+// (X22 of all nodes, then the S11 constructions, then X11, then X) is one
+// batch.
+template <class T>
+void smw_batch(BfRuntime<T>& rt, const std::vector<SmwJob<T>*>& jobs, int* d_status) {
+  if (jobs.empty()) return;
+  if (!rt.batch && jobs.size() > 1) {
+    for (auto* j : jobs) smw_batch<T>(rt, {j}, d_status);
+    return;
+  }
+  std::vector<SmwJob<T>*> dense, rec;
+  for (auto* j : jobs) {
+    const TreeNode& nd = (*j->nodes)[j->node];
+    const bool base = depth_of(*j->nodes, j->node) == 0 || nd.end - nd.beg <= kSmwDense;
+    (base ? dense : rec).push_back(j);
+  }
+  smw_dense_batch<T>(rt, dense, d_status);
+  if (rec.empty()) return;
+  struct Rec {
+    int c1 = -1, c2 = -1, n1 = 0, n2 = 0, d = 0;
+    std::vector<std::unique_ptr<Op<T>>> keep;
+    SmwJob<T> sub22, sub11;
+    std::unique_ptr<IPlusX<T>> A22i, A11i;
+    std::unique_ptr<ProductOp<T>> a22k21, k12a22k21;
+    std::unique_ptr<SumOp<T>> s11op;
+    std::unique_ptr<BfOp<T>> s11b;
+    std::unique_ptr<SmwOp<T>> aop;
+    RandomJob<T> s11job, xjob;
+    Op<T>* view(BfRuntime<T>& r, Op<T>* op, int r0, int c0, int m, int n) {
+      keep.push_back(std::make_unique<SubOp<T>>(r, op, r0, c0, m, n));
+      return keep.back().get();
     }
-  } else {
-    x22.zero = true;
+  };
+  std::vector<std::unique_ptr<Rec>> R;
+  // children blocks of a general operator come from views of it
+  auto split = [&](Rec& r, SmwJob<T>& sub, Op<T>* K, int child) {
+    const auto& nodes = *sub.nodes;
+    sub.node = child;
+    sub.Kfull = K;
+    const int cl = nodes[child].left;
+    if (cl >= 0) {
+      const int n = nodes[child].end - nodes[child].beg;
+      const int m1 = nodes[cl].end - nodes[cl].beg, m2 = n - m1;
+      sub.K11 = r.view(rt, K, 0, 0, m1, m1);
+      sub.K12 = r.view(rt, K, 0, m1, m1, m2);
+      sub.K21 = r.view(rt, K, m1, 0, m2, m1);
+      sub.K22 = r.view(rt, K, m1, m1, m2, m2);
+    }
+  };
+  // X22: (I + K22)^-1 = I + X22
+  std::vector<SmwJob<T>*> sub;
+  for (auto* j : rec) {
+    auto r = std::make_unique<Rec>();
+    const auto& nodes = *j->nodes;
+    const TreeNode& nd = nodes[j->node];
+    r->c1 = nd.left;
+    r->c2 = nd.right;
+    r->n1 = nodes[r->c1].end - nodes[r->c1].beg;
+    r->n2 = (nd.end - nd.beg) - r->n1;
+    r->d = depth_of(nodes, j->node);
+    r->sub22.nodes = r->sub11.nodes = j->nodes;
+    if (j->K22) {
+      split(*r, r->sub22, j->K22, r->c2);
+      sub.push_back(&r->sub22);
+    } else {
+      r->sub22.res.zero = true;
+    }
+    R.push_back(std::move(r));
   }
-  IPlusX<T> A22i(rt, n2, x22.bf.get(), x22.zero ? -1 : x22.dense_off);
-  // S11 = K11 - K12 A22i K21 over T1 x T1
-  ProductOp<T> a22k21(rt, &A22i, k21);
-  ProductOp<T> k12a22k21(rt, k12, &a22k21);
-  SumOp<T> s11op(rt, n1, n1);
-  if (k11) s11op.add(k11, 1.0);
-  s11op.add(&k12a22k21, -1.0);
-  const int L11 = std::max(0, d - 2);  // children butterflies of L - 2 levels (Alg. 4)
-  BTree t1 = subtree(nodes, c1, L11);
-  auto s11 = bf_random_matvec<T>(rt, s11op, t1, t1);
-  BfOp<T> s11b(rt, s11.get());
-  SmwResult x11;
-  const int c11 = nodes[c1].left;
-  if (c11 >= 0) {
-    const int m1 = nodes[c11].end - nodes[c11].beg, m2 = n1 - m1;
-    x11 = bf_smw<T>(rt, nodes, c1, sub(&s11b, 0, 0, m1, m1), sub(&s11b, 0, m1, m1, m2), sub(&s11b, m1, 0, m2, m1),
-                    sub(&s11b, m1, m1, m2, m2), &s11b);
-  } else {
-    x11 = bf_smw<T>(rt, nodes, c1, nullptr, nullptr, nullptr, nullptr, &s11b);
+  smw_batch<T>(rt, sub, d_status);
+  // S11 = K11 - K12 A22i K21 over T1 x T1: children butterflies of L - 2 levels
+  std::vector<RandomJob<T>*> rj;
+  for (size_t i = 0; i < rec.size(); ++i) {
+    Rec& r = *R[i];
+    SmwJob<T>& j = *rec[i];
+    r.A22i = std::make_unique<IPlusX<T>>(rt, r.n2, r.sub22.res.bf.get(), r.sub22.res.zero ? -1 : r.sub22.res.dense_off);
+    r.a22k21 = std::make_unique<ProductOp<T>>(rt, r.A22i.get(), j.K21);
+    r.k12a22k21 = std::make_unique<ProductOp<T>>(rt, j.K12, r.a22k21.get());
+    r.s11op = std::make_unique<SumOp<T>>(rt, r.n1, r.n1);
+    if (j.K11) r.s11op->add(j.K11, 1.0);
+    r.s11op->add(r.k12a22k21.get(), -1.0);
+    r.s11job.op = r.s11op.get();
+    r.s11job.to = r.s11job.ts = subtree(*j.nodes, r.c1, std::max(0, r.d - 2));
+    rj.push_back(&r.s11job);
   }
-  IPlusX<T> A11i(rt, n1, x11.bf.get(), x11.zero ? -1 : x11.dense_off);
-  SmwOp<T> aop(rt, n1, n2, k12, k21, &A11i, &A22i);
-  BTree tt = subtree(nodes, node, d);
-  res.bf = bf_random_matvec<T>(rt, aop, tt, tt);
-  return res;
+  bf_random_matvec_batch<T>(rt, rj);
+  // X11 from S11
+  sub.clear();
+  for (size_t i = 0; i < rec.size(); ++i) {
+    Rec& r = *R[i];
+    r.s11b = std::make_unique<BfOp<T>>(rt, r.s11job.out.get());
+    split(r, r.sub11, r.s11b.get(), r.c1);
+    sub.push_back(&r.sub11);
+  }
+  smw_batch<T>(rt, sub, d_status);
+  // X = [I + K11, K12; K21, I + K22]^-1 - I by randomized construction
+  rj.clear();
+  for (size_t i = 0; i < rec.size(); ++i) {
+    Rec& r = *R[i];
+    SmwJob<T>& j = *rec[i];
+    r.A11i = std::make_unique<IPlusX<T>>(rt, r.n1, r.sub11.res.bf.get(), r.sub11.res.zero ? -1 : r.sub11.res.dense_off);
+    r.aop = std::make_unique<SmwOp<T>>(rt, r.n1, r.n2, j.K12, j.K21, r.A11i.get(), r.A22i.get());
+    r.xjob.op = r.aop.get();
+    r.xjob.to = r.xjob.ts = subtree(*j.nodes, j.node, r.d);
+    rj.push_back(&r.xjob);
+  }
+  bf_random_matvec_batch<T>(rt, rj);
+  for (size_t i = 0; i < rec.size(); ++i) rec[i]->res.bf = std::move(R[i]->xjob.out);
 }
 
 }  // namespace
@@ -466,6 +505,7 @@ template <class T>
 struct CompState {
   BfRuntime<T> rt;
   std::vector<std::unique_ptr<CompressedFront<T>>> fronts;  // by front id (null if dense)
+  DevBuf status;                                            // singular leaf or SMW block (int[4])
 };
 
 template struct CompState<double>;
@@ -489,6 +529,12 @@ void comp_state_reset(void* p, Context& c, int nfronts) {
   st->rt.seed = c.fopts.seed;
   st->rt.stream_id = 0;
   st->rt.max_rank_seen = 0;
+  st->rt.sample_hint.clear();
+  st->rt.batch = c.fopts.batched != 0;
+  if (!st->status.p) {
+    HIPCHK(hipMalloc(&st->status.p, 16));
+    st->status.bytes = 16;
+  }
 }
 
 // nearest-vertex lists by breadth-first search in the graph of A restricted
@@ -539,39 +585,75 @@ static void bfs_lists(const Context& c, int f, int limit, int K, std::vector<std
   }
 }
 
-// Compressed factorization of front f (its descriptor at d_fd on the device).
-// The contribution block goes to `cb` (nu x nu, ld nu).
-void factor_compressed_front(void* state, Context& c, int f, const FrontDesc* d_fd, void* cb) {
+namespace {
+
+// Work of one compressed front while its level is being factored.
+template <class T>
+struct FrontWork {
+  int f = -1;
+  const FrontDesc* d_fd = nullptr;
+  void* cb = nullptr;
+  std::unique_ptr<CompressedFront<T>> cf;
+  std::vector<TreeNode> nodes;  // separator bisection (P-hat), preorder
+  std::vector<TreeNode> unodes;  // balanced tree over I^u
+  std::vector<std::vector<int32_t>> near11, nearall;
+  uint64_t seed = 0;
+  std::vector<std::unique_ptr<EntrySource<T>>> srcs;
+  std::vector<std::unique_ptr<ProxySampler>> samplers;
+};
+
+}  // namespace
+
+// Compressed factorization (Alg. 5) of the fronts `fr` of one level of the
+// assembly tree: d_fds[i] is the device descriptor of fr[i], cbs[i] receives
+// its contribution block (nu x nu, ld nu).  With batching every phase runs
+// over all fronts of the level at once.
+void factor_compressed_level(void* state, Context& c, const std::vector<int>& fr,
+                             const std::vector<const FrontDesc*>& d_fds, const std::vector<void*>& cbs) {
   typedef double T;
   auto* st = (CompState<T>*)state;
   BfRuntime<T>& rt = st->rt;
+  if (fr.empty()) return;
+  if (!rt.batch && fr.size() > 1) {
+    for (size_t i = 0; i < fr.size(); ++i) factor_compressed_level(state, c, {fr[i]}, {d_fds[i]}, {cbs[i]});
+    return;
+  }
   const Symbolic& sy = c.sym;
-  auto cf = std::make_unique<CompressedFront<T>>();
-  cf->front = f;
-  cf->ns = (int)sy.ns(f);
-  cf->nu = (int)sy.nu(f);
-  const int ns = cf->ns, nu = cf->nu;
   hipStream_t s = rt.s();
+  int* d_status = st->status.as<int>();
+  ochk(hipMemsetAsync(d_status, 0, 16, s), "status");
   auto clock = [] { return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count(); };
   double tph[6] = {clock(), 0, 0, 0, 0, 0};
   const int64_t r0 = rt.n_random, e0 = rt.n_entry;
-  // HOD-BF tree of F11: the separator bisection (P-hat), Sec. 5.1
-  std::vector<TreeNode> nodes(sy.sep_nodes.begin() + sy.sep_ptr[f], sy.sep_nodes.begin() + sy.sep_ptr[f + 1]);
-  Hodbf<T>& h = cf->f11;
-  h.n = ns;
-  h.nodes.resize(nodes.size());
-  {
+  const double alpha = c.fopts.alpha > 0 ? c.fopts.alpha : 2.0;
+  const int knn = c.fopts.knn;
+  std::vector<std::unique_ptr<FrontWork<T>>> W;
+  for (size_t k = 0; k < fr.size(); ++k) {
+    auto w = std::make_unique<FrontWork<T>>();
+    const int f = fr[k];
+    w->f = f;
+    w->d_fd = d_fds[k];
+    w->cb = cbs[k];
+    w->cf = std::make_unique<CompressedFront<T>>();
+    w->cf->front = f;
+    w->cf->ns = (int)sy.ns(f);
+    w->cf->nu = (int)sy.nu(f);
+    // HOD-BF tree of F11: the separator bisection (P-hat), Sec. 5.1
+    w->nodes.assign(sy.sep_nodes.begin() + sy.sep_ptr[f], sy.sep_nodes.begin() + sy.sep_ptr[f + 1]);
+    Hodbf<T>& h = w->cf->f11;
+    h.n = w->cf->ns;
+    h.nodes.resize(w->nodes.size());
     std::vector<std::pair<int, int>> stck{{0, 0}};
     while (!stck.empty()) {
       auto [i, l] = stck.back();
       stck.pop_back();
       auto& hn = h.nodes[i];
-      hn.beg = nodes[i].beg;
-      hn.end = nodes[i].end;
-      hn.left = nodes[i].left;
-      hn.right = nodes[i].right;
+      hn.beg = w->nodes[i].beg;
+      hn.end = w->nodes[i].end;
+      hn.left = w->nodes[i].left;
+      hn.right = w->nodes[i].right;
       hn.level = l;
-      hn.depth = depth_of(nodes, i);
+      hn.depth = depth_of(w->nodes, i);
       h.max_level = std::max(h.max_level, l);
       if (hn.left >= 0) {
         stck.push_back({hn.left, l + 1});
@@ -580,159 +662,241 @@ void factor_compressed_front(void* state, Context& c, int f, const FrontDesc* d_
     }
     h.by_level.assign(h.max_level + 1, {});
     for (int i = 0; i < (int)h.nodes.size(); ++i) h.by_level[h.nodes[i].level].push_back(i);
+    bfs_lists(c, f, w->cf->ns, 32, w->near11);
+    bfs_lists(c, f, w->cf->ns + w->cf->nu, 32, w->nearall);
+    w->seed = c.fopts.seed * 1000003ull + (uint64_t)f;
+    W.push_back(std::move(w));
   }
-  std::vector<std::vector<int32_t>> near11, nearall;
-  bfs_lists(c, f, ns, 32, near11);
-  bfs_lists(c, f, ns + nu, 32, nearall);
-  const uint64_t seed = c.fopts.seed * 1000003ull + (uint64_t)f;
-  const double alpha = c.fopts.alpha > 0 ? c.fopts.alpha : 2.0;
-  const int knn = c.fopts.knn;
-  // leaves D = F11(leaf, leaf)
+  // leaves D = F11(leaf, leaf): every pool allocation first, then one extraction
   {
-    std::vector<std::vector<int32_t>> idx;
-    std::vector<int> leaves;
-    for (int i = 0; i < (int)h.nodes.size(); ++i)
-      if (h.nodes[i].left < 0) {
-        leaves.push_back(i);
-        const size_t off = rt.pool.alloc((size_t)h.nodes[i].size() * h.nodes[i].size() * sizeof(cplx<T>), s);
-        h.nodes[i].leaf_off = (int64_t)(off / sizeof(cplx<T>));
-        std::vector<int32_t> r(h.nodes[i].size());
-        for (int k = 0; k < h.nodes[i].size(); ++k) r[k] = h.nodes[i].beg + k;
-        idx.push_back(r);
-      }
-    std::vector<const std::vector<int32_t>*> pr;
-    std::vector<void*> outs;
-    std::vector<int64_t> ldo;
-    for (size_t k = 0; k < leaves.size(); ++k) {
-      pr.push_back(&idx[k]);
-      outs.push_back(rt.pool_base() + h.nodes[leaves[k]].leaf_off * sizeof(cplx<T>));
-      ldo.push_back(std::max(1, h.nodes[leaves[k]].size()));
-    }
-    FrontSource<T> src(rt, d_fd, c.d_values.p, 0, 0);
-    src.extract(pr, pr, outs, ldo, false);
+    for (auto& w : W)
+      for (auto& nd : w->cf->f11.nodes)
+        if (nd.left < 0) nd.leaf_off = (int64_t)(rt.pool.alloc((size_t)nd.size() * nd.size() * sizeof(cplx<T>), s) /
+                                                 sizeof(cplx<T>));
+    ExtractBatch eb;
+    for (auto& w : W)
+      for (auto& nd : w->cf->f11.nodes)
+        if (nd.left < 0) {
+          std::vector<int32_t> r(nd.size());
+          for (int k = 0; k < nd.size(); ++k) r[k] = nd.beg + k;
+          eb.add(w->d_fd, nullptr, 0, r, 0, r, 0, rt.pool_base() + nd.leaf_off * sizeof(cplx<T>), std::max(1, nd.size()),
+                 false);
+        }
+    run_extract<T>(rt, eb);
   }
-  // off-diagonal butterflies (Alg. 2 on F11 = A(Is,Is) (+) C_nu1 (+) C_nu2)
-  for (int i = 0; i < (int)h.nodes.size(); ++i) {
-    auto& nd = h.nodes[i];
-    if (nd.left < 0) continue;
-    const int a = nd.left, b = nd.right;
-    const int L = std::min(depth_of(nodes, a), depth_of(nodes, b));
-    BTree ta = subtree(nodes, a, L), tb = subtree(nodes, b, L);
-    {
-      FrontSource<T> src(rt, d_fd, c.d_values.p, nodes[a].beg, nodes[b].beg);
-      BfsSampler ps(near11, nodes[a].beg, nodes[b].beg, knn, alpha, seed + 2 * i);
-      nd.b12 = bf_entry_eval<T>(rt, src, ps, ta, tb);
+  // off-diagonal butterflies of F11 (Alg. 2 on F11 = A(Is,Is) (+) C_nu1 (+) C_nu2)
+  {
+    std::vector<std::unique_ptr<EntryJob<T>>> jobs;
+    std::vector<std::pair<HodbfNode<T>*, int>> dest;
+    for (auto& w : W) {
+      auto& nodes = w->nodes;
+      for (int i = 0; i < (int)nodes.size(); ++i) {
+        if (nodes[i].left < 0) continue;
+        const int a = nodes[i].left, b = nodes[i].right;
+        const int L = std::min(depth_of(nodes, a), depth_of(nodes, b));
+        BTree ta = subtree(nodes, a, L), tb = subtree(nodes, b, L);
+        for (int side = 0; side < 2; ++side) {
+          const int r = side ? b : a, cc = side ? a : b;
+          w->srcs.push_back(std::make_unique<FrontSource<T>>(w->d_fd, nodes[r].beg, nodes[cc].beg));
+          w->samplers.push_back(
+              std::make_unique<BfsSampler>(w->near11, nodes[r].beg, nodes[cc].beg, knn, alpha, w->seed + 2 * i + side));
+          jobs.push_back(std::make_unique<EntryJob<T>>(
+              EntryJob<T>{w->srcs.back().get(), w->samplers.back().get(), side ? tb : ta, side ? ta : tb, nullptr}));
+          dest.push_back({&w->cf->f11.nodes[i], side});
+        }
+      }
     }
-    {
-      FrontSource<T> src(rt, d_fd, c.d_values.p, nodes[b].beg, nodes[a].beg);
-      BfsSampler ps(near11, nodes[b].beg, nodes[a].beg, knn, alpha, seed + 2 * i + 1);
-      nd.b21 = bf_entry_eval<T>(rt, src, ps, tb, ta);
-    }
+    std::vector<EntryJob<T>*> jp;
+    for (auto& j : jobs) jp.push_back(j.get());
+    bf_entry_eval_batch<T>(rt, jp);
+    for (size_t k = 0; k < jobs.size(); ++k) (dest[k].second ? dest[k].first->b21 : dest[k].first->b12) = std::move(jobs[k]->out);
   }
   tph[1] = clock();
-  // HODBF_invert (Alg. 4): leaves, then every internal node bottom-up
+  // HODBF_invert (Alg. 4): leaf inverses, then the internal nodes by height
   {
+    for (auto& w : W)
+      for (auto& nd : w->cf->f11.nodes)
+        if (nd.left < 0) nd.inv_off = (int64_t)(rt.pool.alloc((size_t)nd.size() * nd.size() * sizeof(cplx<T>), s) /
+                                                sizeof(cplx<T>));
     std::vector<InvTask> it;
-    for (auto& nd : h.nodes)
-      if (nd.left < 0) {
-        const size_t off = rt.pool.alloc((size_t)nd.size() * nd.size() * sizeof(cplx<T>), s);
-        nd.inv_off = (int64_t)(off / sizeof(cplx<T>));
-      }
-    for (auto& nd : h.nodes)
-      if (nd.left < 0) {
-        ochk(hipMemcpyAsync(rt.pool_base() + nd.inv_off * sizeof(cplx<T>), rt.pool_base() + nd.leaf_off * sizeof(cplx<T>),
-                            (size_t)nd.size() * nd.size() * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s),
-             "leaf copy");
-        it.push_back(InvTask{rt.pool_base() + nd.inv_off * sizeof(cplx<T>), std::max(nd.size(), 1), nd.size(), 0});
-      }
+    for (auto& w : W)
+      for (auto& nd : w->cf->f11.nodes)
+        if (nd.left < 0) {
+          ochk(launch_axpby<T>(rt.pool_base() + nd.inv_off * sizeof(cplx<T>), nd.size(),
+                               rt.pool_base() + nd.leaf_off * sizeof(cplx<T>), nd.size(), nd.size(), nd.size(), 1.0, 0.0,
+                               s),
+               "leaf copy");
+          it.push_back(InvTask{rt.pool_base() + nd.inv_off * sizeof(cplx<T>), std::max(nd.size(), 1), nd.size(), 0});
+        }
     auto mk = rt.scratch.mark();
-    void* d_it = up(rt.scratch, it, s);
-    int* d_st = (int*)rt.scratch.take(16);
-    ochk(hipMemsetAsync(d_st, 0, 16, s), "status");
-    ochk(launch_leaf_inverse<T>(d_it, (int)it.size(), d_st, s), "leaf inverse");
-    int hst = 0;
-    ochk(hipMemcpyAsync(&hst, d_st, 4, hipMemcpyDeviceToHost, s), "status");
-    ochk(hipStreamSynchronize(s), "leaf inverse");
+    void* d_it = up(rt, it);
+    ochk(launch_leaf_inverse<T>(d_it, (int)it.size(), d_status, s), "leaf inverse");
     rt.scratch.release(mk);
-    if (hst) throw Error(BFMF_E_SINGULAR, "singular HOD-BF leaf in compressed front " + std::to_string(f));
   }
-  for (int l = h.max_level; l >= 0; --l)
-    for (int i : h.by_level[l]) {
-      auto& nd = h.nodes[i];
-      if (nd.left < 0) continue;
-      const int a = nd.left, b = nd.right;
-      const int na = h.nodes[a].size(), nb = h.nodes[b].size();
-      // B1' = D1^-1 B12, B2' = D2^-1 B21 by randomized construction
-      HodbfInvOp<T> d1(rt, h, a), d2(rt, h, b);
-      BfOp<T> b12(rt, nd.b12.get()), b21(rt, nd.b21.get());
-      ProductOp<T> p1(rt, &d1, &b12), p2(rt, &d2, &b21);
-      auto b1p = bf_random_matvec<T>(rt, p1, nd.b12->to, nd.b12->ts);
-      auto b2p = bf_random_matvec<T>(rt, p2, nd.b21->to, nd.b21->ts);
-      BfOp<T> k12(rt, b1p.get()), k21(rt, b2p.get());
-      // [I B1'; B2' I]^-1 = I + X (BF_SMW with zero diagonal blocks)
-      Block2Op<T> kfull(rt, na + nb, na + nb, na, na, nullptr, &k12, &k21, nullptr);
-      SmwResult r = bf_smw<T>(rt, nodes, i, nullptr, &k12, &k21, nullptr, &kfull);
-      nd.x = std::move(r.bf);
-      nd.x_dense = r.dense_off >= 0;
-      if (nd.x_dense) nd.inv_off = r.dense_off;
-      nd.x_zero = r.zero;
+  int H = 0;
+  for (auto& w : W)
+    for (auto& nd : w->cf->f11.nodes) H = std::max(H, nd.depth);
+  for (int hgt = 1; hgt <= H; ++hgt) {
+    struct NodeWork {
+      HodbfNode<T>* nd;
+      std::unique_ptr<HodbfInvOp<T>> d1, d2;
+      std::unique_ptr<BfOp<T>> b12, b21, k12, k21;
+      std::unique_ptr<ProductOp<T>> p1, p2;
+      std::unique_ptr<Block2Op<T>> kfull;
+      RandomJob<T> j1, j2;
+      SmwJob<T> smw;
+    };
+    std::vector<std::unique_ptr<NodeWork>> nw;
+    std::vector<RandomJob<T>*> rj;
+    for (auto& w : W) {
+      Hodbf<T>& h = w->cf->f11;
+      for (int i = 0; i < (int)h.nodes.size(); ++i) {
+        HodbfNode<T>& nd = h.nodes[i];
+        if (nd.left < 0 || nd.depth != hgt) continue;
+        auto x = std::make_unique<NodeWork>();
+        x->nd = &nd;
+        // B1' = D1^-1 B12, B2' = D2^-1 B21 by randomized construction
+        x->d1 = std::make_unique<HodbfInvOp<T>>(rt, h, nd.left);
+        x->d2 = std::make_unique<HodbfInvOp<T>>(rt, h, nd.right);
+        x->b12 = std::make_unique<BfOp<T>>(rt, nd.b12.get());
+        x->b21 = std::make_unique<BfOp<T>>(rt, nd.b21.get());
+        x->p1 = std::make_unique<ProductOp<T>>(rt, x->d1.get(), x->b12.get());
+        x->p2 = std::make_unique<ProductOp<T>>(rt, x->d2.get(), x->b21.get());
+        x->j1.op = x->p1.get();
+        x->j1.to = nd.b12->to;
+        x->j1.ts = nd.b12->ts;
+        x->j2.op = x->p2.get();
+        x->j2.to = nd.b21->to;
+        x->j2.ts = nd.b21->ts;
+        x->smw.nodes = &w->nodes;
+        x->smw.node = i;
+        rj.push_back(&x->j1);
+        rj.push_back(&x->j2);
+        nw.push_back(std::move(x));
+      }
     }
+    bf_random_matvec_batch<T>(rt, rj);
+    // [I B1'; B2' I]^-1 = I + X (BF_SMW with zero diagonal blocks)
+    std::vector<SmwJob<T>*> sj;
+    for (auto& x : nw) {
+      const int na = x->j1.to.n, nb = x->j2.to.n;
+      x->k12 = std::make_unique<BfOp<T>>(rt, x->j1.out.get());
+      x->k21 = std::make_unique<BfOp<T>>(rt, x->j2.out.get());
+      x->kfull = std::make_unique<Block2Op<T>>(rt, na + nb, na + nb, na, na, nullptr, x->k12.get(), x->k21.get(), nullptr);
+      x->smw.K12 = x->k12.get();
+      x->smw.K21 = x->k21.get();
+      x->smw.Kfull = x->kfull.get();
+      sj.push_back(&x->smw);
+    }
+    smw_batch<T>(rt, sj, d_status);
+    for (auto& x : nw) {
+      SmwResult& r = x->smw.res;
+      x->nd->x = std::move(r.bf);
+      x->nd->x_dense = r.dense_off >= 0;
+      if (x->nd->x_dense) x->nd->inv_off = r.dense_off;
+      x->nd->x_zero = r.zero;
+    }
+  }
   tph[2] = clock();
-  if (nu > 0) {
-    // F12 and F21 (Alg. 2), trees: separator bisection x balanced tree on I^u
-    const int leaf = 64;
-    std::vector<TreeNode> unodes = balanced_tree(nu, leaf);
-    const int Ls = depth_of(nodes, 0), Lu = depth_of(unodes, 0);
-    const int L = std::min(Ls, Lu);
-    BTree ts_ = subtree(nodes, 0, L), tu = subtree(unodes, 0, L);
-    {
-      FrontSource<T> src(rt, d_fd, c.d_values.p, 0, ns);
-      BfsSampler ps(nearall, 0, ns, knn, alpha, seed + 7777);
-      cf->f12 = bf_entry_eval<T>(rt, src, ps, ts_, tu);
+  // F12 and F21 (Alg. 2), trees: separator bisection x balanced tree on I^u
+  {
+    std::vector<std::unique_ptr<EntryJob<T>>> jobs;
+    std::vector<std::pair<CompressedFront<T>*, int>> dest;
+    for (auto& w : W) {
+      const int ns = w->cf->ns, nu = w->cf->nu;
+      if (nu == 0) continue;
+      w->unodes = balanced_tree(nu, 64);
+      const int L = std::min(depth_of(w->nodes, 0), depth_of(w->unodes, 0));
+      BTree ts_ = subtree(w->nodes, 0, L), tu = subtree(w->unodes, 0, L);
+      for (int side = 0; side < 2; ++side) {
+        const int r = side ? ns : 0, cc = side ? 0 : ns;
+        w->srcs.push_back(std::make_unique<FrontSource<T>>(w->d_fd, r, cc));
+        w->samplers.push_back(
+            std::make_unique<BfsSampler>(w->nearall, r, cc, knn, alpha, w->seed + (side ? 8888 : 7777)));
+        jobs.push_back(std::make_unique<EntryJob<T>>(
+            EntryJob<T>{w->srcs.back().get(), w->samplers.back().get(), side ? tu : ts_, side ? ts_ : tu, nullptr}));
+        dest.push_back({w->cf.get(), side});
+      }
     }
-    {
-      FrontSource<T> src(rt, d_fd, c.d_values.p, ns, 0);
-      BfsSampler ps(nearall, ns, 0, knn, alpha, seed + 8888);
-      cf->f21 = bf_entry_eval<T>(rt, src, ps, tu, ts_);
+    std::vector<EntryJob<T>*> jp;
+    for (auto& j : jobs) jp.push_back(j.get());
+    bf_entry_eval_batch<T>(rt, jp);
+    for (size_t k = 0; k < jobs.size(); ++k) (dest[k].second ? dest[k].first->f21 : dest[k].first->f12) = std::move(jobs[k]->out);
+  }
+  tph[3] = clock();
+  // S = F21 F11^-1 F12 (Sec. 3.3)
+  {
+    struct SWork {
+      std::unique_ptr<HodbfInvOp<T>> f11i;
+      std::unique_ptr<BfOp<T>> f12, f21;
+      std::unique_ptr<ProductOp<T>> p1, p2;
+      RandomJob<T> j;
+    };
+    std::vector<std::unique_ptr<SWork>> sw;
+    std::vector<RandomJob<T>*> rj;
+    std::vector<CompressedFront<T>*> dest;
+    for (auto& w : W) {
+      if (w->cf->nu == 0) continue;
+      auto x = std::make_unique<SWork>();
+      x->f11i = std::make_unique<HodbfInvOp<T>>(rt, w->cf->f11, 0);
+      x->f12 = std::make_unique<BfOp<T>>(rt, w->cf->f12.get());
+      x->f21 = std::make_unique<BfOp<T>>(rt, w->cf->f21.get());
+      x->p1 = std::make_unique<ProductOp<T>>(rt, x->f11i.get(), x->f12.get());
+      x->p2 = std::make_unique<ProductOp<T>>(rt, x->f21.get(), x->p1.get());
+      x->j.op = x->p2.get();
+      x->j.to = x->j.ts = subtree(w->unodes, 0, depth_of(w->unodes, 0));
+      rj.push_back(&x->j);
+      dest.push_back(w->cf.get());
+      sw.push_back(std::move(x));
     }
-    tph[3] = clock();
-    // S = F21 F11^-1 F12 (Sec. 3.3)
-    HodbfInvOp<T> f11i(rt, h, 0);
-    BfOp<T> f12(rt, cf->f12.get()), f21(rt, cf->f21.get());
-    ProductOp<T> p1(rt, &f11i, &f12), p2(rt, &f21, &p1);
-    BTree tuu = subtree(unodes, 0, Lu);
-    cf->s = bf_random_matvec<T>(rt, p2, tuu, tuu);
-    tph[4] = clock();
-    // C = (C_nu1 (+) C_nu2)(Iu, Iu) - S
-    {
+    bf_random_matvec_batch<T>(rt, rj);
+    for (size_t k = 0; k < sw.size(); ++k) dest[k]->s = std::move(sw[k]->j.out);
+  }
+  tph[4] = clock();
+  // C = (C_nu1 (+) C_nu2)(Iu, Iu) - S, S applied to identity columns
+  {
+    ExtractBatch eb;
+    int maxnu = 0;
+    for (auto& w : W) {
+      const int ns = w->cf->ns, nu = w->cf->nu;
+      if (nu == 0) continue;
+      maxnu = std::max(maxnu, nu);
       std::vector<int32_t> r(nu);
       for (int k = 0; k < nu; ++k) r[k] = k;
-      FrontSource<T> src(rt, d_fd, c.d_values.p, ns, ns);
-      src.extract({&r}, {&r}, {cb}, {std::max(nu, 1)}, false);
-      const int chunk = 1024;
-      auto mk = rt.scratch.mark();
-      cplx<T>* I = (cplx<T>*)rt.scratch.take((size_t)nu * chunk * sizeof(cplx<T>));
-      for (int c0 = 0; c0 < nu; c0 += chunk) {
-        const int w = std::min(chunk, nu - c0);
-        std::vector<cplx<T>> eye((size_t)nu * w, cplx<T>{0, 0});
-        for (int k = 0; k < w; ++k) eye[(size_t)k * nu + c0 + k] = cplx<T>{1, 0};
-        ochk(hipMemcpyAsync(I, eye.data(), eye.size() * sizeof(cplx<T>), hipMemcpyHostToDevice, s), "eye");
-        rt.apply(*cf->s, I, nu, (cplx<T>*)cb + (size_t)c0 * nu, nu, w, false, -1.0, 1);
-      }
-      ochk(hipStreamSynchronize(s), "cb");
-      rt.scratch.release(mk);
+      eb.add(w->d_fd, nullptr, 0, r, ns, r, ns, w->cb, nu, false);
     }
+    run_extract<T>(rt, eb);
+    const int chunk = 1024;
+    auto mk = rt.scratch.mark();
+    cplx<T>* I = (cplx<T>*)rt.scratch.take((size_t)std::max(maxnu, 1) * chunk * sizeof(cplx<T>));
+    for (auto& w : W) {
+      const int nu = w->cf->nu;
+      for (int c0 = 0; c0 < nu; c0 += chunk) {
+        const int wd = std::min(chunk, nu - c0);
+        ochk(launch_set_eye<T>(I, nu, nu, wd, c0, 1.0, s), "eye");
+        rt.apply(*w->cf->s, I, nu, (cplx<T>*)w->cb + (size_t)c0 * nu, nu, wd, false, -1.0, 1);
+      }
+    }
+    rt.scratch.release(mk);
   }
+  int hst[4] = {0, 0, 0, 0};
+  ochk(hipMemcpyAsync(hst, d_status, 16, hipMemcpyDeviceToHost, s), "status");
+  rt.c->stage.sync(s);
+  if (hst[0]) throw Error(BFMF_E_SINGULAR, "singular HOD-BF leaf or inversion block in a compressed front");
   tph[5] = clock();
   if (c.verbose) {
-    const double t3 = tph[3] > 0 ? tph[3] : tph[2], t4 = tph[4] > 0 ? tph[4] : t3;
+    int nsmax = 0, numax = 0;
+    for (auto& w : W) {
+      nsmax = std::max(nsmax, w->cf->ns);
+      numax = std::max(numax, w->cf->nu);
+    }
     fprintf(stderr,
-            "[bfmf] front %d ns %d nu %d: F11 %.3fs inv %.3fs F12/F21 %.3fs S %.3fs C %.3fs; constructions "
-            "random %lld entry %lld; max rank %d\n",
-            f, ns, nu, tph[1] - tph[0], tph[2] - tph[1], t3 - tph[2], t4 - t3, tph[5] - t4,
-            (long long)(rt.n_random - r0), (long long)(rt.n_entry - e0), rt.max_rank_seen);
+            "[bfmf] %zu compressed front(s), ns <= %d, nu <= %d: F11 %.3fs inv %.3fs F12/F21 %.3fs S %.3fs C %.3fs; "
+            "constructions random %lld entry %lld; max rank %d\n",
+            W.size(), nsmax, numax, tph[1] - tph[0], tph[2] - tph[1], tph[3] - tph[2], tph[4] - tph[3],
+            tph[5] - tph[4], (long long)(rt.n_random - r0), (long long)(rt.n_entry - e0), rt.max_rank_seen);
   }
-  st->fronts[f] = std::move(cf);
+  for (auto& w : W) st->fronts[w->f] = std::move(w->cf);
 }
 
 // ------------------------------------------------------------ sweeps
@@ -748,7 +912,7 @@ void forward_compressed(void* state, Context& c, int f, void* W, int n, int nrhs
   hodbf_inv_apply<T>(rt, cf.f11, 0, w, n, z, cf.ns, nrhs, false);
   axpby<T>(rt, w, n, z, cf.ns, cf.ns, nrhs, 1.0, 0.0);
   if (cf.nu > 0) rt.apply(*cf.f21, w, n, w + cf.ns, n, nrhs, false, -1.0, 1);
-  ochk(hipStreamSynchronize(rt.s()), "forward compressed");
+
   rt.scratch.release(mk);
   (void)c;
 }
@@ -767,7 +931,7 @@ void backward_compressed(void* state, Context& c, int f, void* W, int n, int nrh
   rt.apply(*cf.f12, w + cf.ns, n, t, cf.ns, nrhs, false, 1.0, 0);
   hodbf_inv_apply<T>(rt, cf.f11, 0, t, cf.ns, t2, cf.ns, nrhs, false);
   axpby<T>(rt, w, n, t2, cf.ns, cf.ns, nrhs, -1.0, 1.0);
-  ochk(hipStreamSynchronize(rt.s()), "backward compressed");
+
   rt.scratch.release(mk);
   (void)c;
 }

@@ -48,6 +48,22 @@ class Error : public std::exception {
       throw ::bfmf::Error(BFMF_E_DEVICE, std::string(#expr " failed: ") + hipGetErrorString(e__)); \
   } while (0)
 
+// Host-to-device uploads of task and index lists.  The host data is copied
+// into a pinned ring and the device copy is enqueued on the stream, so the
+// caller's vector may be freed at once and no synchronisation is needed.  The
+// ring is reused after the stream has been synchronised (sync()), or, when it
+// is full, after put() has synchronised the stream itself.
+struct Staging {
+  char* host = nullptr;
+  size_t cap = 0, head = 0;
+  void put(void* dst, const void* src, size_t bytes, hipStream_t s);
+  void sync(hipStream_t s);
+  Staging() = default;
+  Staging(const Staging&) = delete;
+  Staging& operator=(const Staging&) = delete;
+  ~Staging();
+};
+
 enum class State { Created, Analyzed, Factored };
 
 enum KernelKind { K_ASSEMBLE = 0, K_LU = 1, K_SCHUR = 2, K_FWD = 3, K_BWD = 4, K_SPMV = 5, K_VEC = 6, K_COUNT = 7 };
@@ -129,7 +145,8 @@ struct Context {
   DevBuf d_W, d_y, d_x;
   int64_t ws_nrhs = 0;
   DevBuf g_B, g_X, g_V, g_w, g_r, g_scal, g_part, g_tmp;
-  DevBuf g_tmp_plan;  // staging of grouped-GEMM task lists
+  DevBuf g_tmp_plan;  // device copy of the current grouped-GEMM task lists
+  Staging stage;      // pinned ring of host-to-device uploads
   int64_t g_nrhs = 0, g_restart = 0;
 
   KernelTimer timer;
@@ -145,11 +162,15 @@ struct Context {
   ~Context();
 };
 
+// message of the last failed call on this thread that had no handle to hold it
+extern thread_local std::string g_thread_error;
+
 // compressed.cpp
 void* comp_state_create(Context& c);
 void comp_state_destroy(void* p);
 void comp_state_reset(void* p, Context& c, int nfronts);
-void factor_compressed_front(void* state, Context& c, int f, const FrontDesc* d_fd, void* cb);
+void factor_compressed_level(void* state, Context& c, const std::vector<int>& fronts,
+                             const std::vector<const FrontDesc*>& d_fds, const std::vector<void*>& cbs);
 void forward_compressed(void* state, Context& c, int f, void* W, int n, int nrhs);
 void backward_compressed(void* state, Context& c, int f, void* W, int n, int nrhs);
 void compressed_stats(void* state, double& bytes, int& maxrank);

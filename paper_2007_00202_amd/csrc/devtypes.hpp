@@ -62,17 +62,19 @@ struct IdTask {
 };
 
 // Extraction of the dense submatrix F(rows, cols) of a front that is never
-// formed: A entries plus the children's contribution blocks.
+// formed (A entries plus the children's contribution blocks), or of a dense
+// matrix in device memory.
 struct ExtractTask {
   const int32_t* rows;  // front-local row indices
   const int32_t* cols;  // front-local column indices
   int32_t nr, nc;
-  void* out;            // nr x nc (ld nr), or nc x nr (ld nc) when trans
+  void* out;            // nr x nc (ld ldo), or nc x nr (ld ldo) when trans
   int64_t ldo;
   int32_t trans;        // write the transpose
   int32_t pad;
   const void* dense;    // when not null: F is this dense matrix (ld ldd, complex<T>)
   int64_t ldd;
+  const FrontDesc* fd;  // otherwise: the front (device descriptor)
 };
 
 }  // namespace bfmf

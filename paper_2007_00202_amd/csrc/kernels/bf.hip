@@ -243,9 +243,9 @@ __global__ void id_expand_kernel(const IdTask* __restrict__ tasks, void* const* 
 // (+) C_nu1 (+) C_nu2; one workgroup per task, threads over entries.
 template <class T, class TC>
 __global__ __launch_bounds__(256) void front_extract_kernel(const ExtractTask* __restrict__ tasks,
-                                                            const FrontDesc* __restrict__ fd,
                                                             const cplx<double>* __restrict__ values) {
   const ExtractTask& tk = tasks[blockIdx.x];
+  const FrontDesc* fd = tk.fd;
   cplx<T>* out = (cplx<T>*)tk.out;
   const int nr = tk.nr, nc = tk.nc;
   for (int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x; e < (int64_t)nr * nc; e += (int64_t)gridDim.y * 256) {
@@ -513,6 +513,15 @@ __global__ void axpby_kernel(cplx<T>* __restrict__ Y, int64_t ldy, const cplx<T>
   Y[i + (int64_t)c * ldy] = y;
 }
 
+// Y(i, j) = v if i == j + off, else 0, on an m x ncol block
+template <class T>
+__global__ void set_eye_kernel(cplx<T>* __restrict__ Y, int64_t ldy, int64_t m, int ncol, int64_t off, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  for (int c = blockIdx.y; c < ncol; c += gridDim.y)
+    Y[i + (int64_t)c * ldy] = cplx<T>{(T)(i == (int64_t)c + off ? v : 0.0), (T)0};
+}
+
 // Y (T1) = X (T2), elementwise conversion of an m x n block
 template <class T1, class T2>
 __global__ void convert_kernel(cplx<T1>* __restrict__ Y, int64_t ldy, const cplx<T2>* __restrict__ X, int64_t ldx,
@@ -558,15 +567,15 @@ hipError_t launch_id_expand(const IdTask* d_tasks, int ntasks, void* const* d_ou
 }
 
 template <class T>
-hipError_t launch_front_extract(const ExtractTask* d_tasks, int ntasks, int yblocks, const FrontDesc* d_fd,
-                                const void* values, bool cb_single, hipStream_t s) {
+hipError_t launch_front_extract(const ExtractTask* d_tasks, int ntasks, int yblocks, const void* values, bool cb_single,
+                                hipStream_t s) {
   if (ntasks == 0) return hipSuccess;
   dim3 grid(ntasks, yblocks > 0 ? yblocks : 1);
   if (cb_single)
-    hipLaunchKernelGGL((front_extract_kernel<T, cplx<float>>), grid, dim3(256), 0, s, d_tasks, d_fd,
+    hipLaunchKernelGGL((front_extract_kernel<T, cplx<float>>), grid, dim3(256), 0, s, d_tasks,
                        (const cplx<double>*)values);
   else
-    hipLaunchKernelGGL((front_extract_kernel<T, cplx<double>>), grid, dim3(256), 0, s, d_tasks, d_fd,
+    hipLaunchKernelGGL((front_extract_kernel<T, cplx<double>>), grid, dim3(256), 0, s, d_tasks,
                        (const cplx<double>*)values);
   return hipGetLastError();
 }
@@ -612,6 +621,14 @@ hipError_t launch_axpby(void* Y, int64_t ldy, const void* X, int64_t ldx, int64_
   return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_set_eye(void* Y, int64_t ldy, int64_t m, int ncol, int64_t off, double v, hipStream_t s) {
+  if (m == 0 || ncol == 0) return hipSuccess;
+  hipLaunchKernelGGL((set_eye_kernel<T>), dim3((unsigned)((m + 255) / 256), (unsigned)std::min(ncol, 65535)), dim3(256),
+                     0, s, (cplx<T>*)Y, ldy, m, ncol, off, v);
+  return hipGetLastError();
+}
+
 template <class T1, class T2>
 hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int64_t m, int ncol, hipStream_t s) {
   if (m == 0 || ncol == 0) return hipSuccess;
@@ -624,15 +641,15 @@ hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int6
   template hipError_t launch_grouped_gemm<T>(const GTask*, const int64_t*, int, int64_t, void* const[4], hipStream_t); \
   template hipError_t launch_cpqr_id<T>(const IdTask*, int, double, hipStream_t);                                     \
   template hipError_t launch_id_expand<T>(const IdTask*, int, void* const*, const int64_t*, bool, bool, hipStream_t);  \
-  template hipError_t launch_front_extract<T>(const ExtractTask*, int, int, const FrontDesc*, const void*, bool,       \
-                                              hipStream_t);                                                          \
+  template hipError_t launch_front_extract<T>(const ExtractTask*, int, int, const void*, bool, hipStream_t);          \
   template hipError_t launch_philox_gauss<T>(void*, int64_t, int64_t, int, int, const int32_t*, const int32_t*,       \
                                              uint64_t, uint64_t, hipStream_t);                                        \
   template hipError_t launch_small_solve_right<T>(const void*, int, hipStream_t);                                     \
   template hipError_t launch_leaf_inverse<T>(const void*, int, int*, hipStream_t);                                    \
   template hipError_t launch_gather_rows<T>(const void*, int64_t, void*, int64_t, const int32_t*, int, int, bool,     \
                                             hipStream_t);                                                             \
-  template hipError_t launch_axpby<T>(void*, int64_t, const void*, int64_t, int64_t, int, double, double, hipStream_t);
+  template hipError_t launch_axpby<T>(void*, int64_t, const void*, int64_t, int64_t, int, double, double, hipStream_t); \
+  template hipError_t launch_set_eye<T>(void*, int64_t, int64_t, int, int64_t, double, hipStream_t);
 INST(double)
 INST(float)
 template hipError_t launch_convert<double, float>(void*, int64_t, const void*, int64_t, int64_t, int, hipStream_t);

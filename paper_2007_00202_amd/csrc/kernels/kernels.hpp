@@ -89,8 +89,8 @@ hipError_t launch_id_expand(const IdTask* d_tasks, int ntasks, void* const* d_ou
                             bool transpose_out, bool conj_out, hipStream_t s);
 // submatrices of a front (A entries (+) children blocks) or of a dense matrix
 template <class T>
-hipError_t launch_front_extract(const ExtractTask* d_tasks, int ntasks, int yblocks, const FrontDesc* d_fd,
-                                const void* values, bool cb_single, hipStream_t s);
+hipError_t launch_front_extract(const ExtractTask* d_tasks, int ntasks, int yblocks, const void* values, bool cb_single,
+                                hipStream_t s);
 // complex Gaussian probes (Philox4x32-10): column c nonzero on rows [gbeg[c/width], gend[c/width])
 template <class T>
 hipError_t launch_philox_gauss(void* Om, int64_t ld, int64_t n, int ncol, int width, const int32_t* d_gbeg,
@@ -109,6 +109,9 @@ hipError_t launch_gather_rows(const void* X, int64_t ldx, void* Y, int64_t ldy, 
 template <class T>
 hipError_t launch_axpby(void* Y, int64_t ldy, const void* X, int64_t ldx, int64_t m, int ncol, double a, double b,
                         hipStream_t s);
+// Y(i, j) = v when i == j + off, else 0 (m x ncol block)
+template <class T>
+hipError_t launch_set_eye(void* Y, int64_t ldy, int64_t m, int ncol, int64_t off, double v, hipStream_t s);
 // Y (complex<T1>) = X (complex<T2>)
 template <class T1, class T2>
 hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int64_t m, int ncol, hipStream_t s);

@@ -234,11 +234,18 @@ void factor_dense(Context& c) {
     } else {
       for (int k = b; k < e; ++k) run(k, k + 1);
     }
-    // compressed fronts of this level (Alg. 5), one at a time
-    for (int k = e; k < e_all; ++k) {
-      const int32_t f = c.level_order[k];
-      HIPCHK(hipStreamSynchronize(c.stream));
-      factor_compressed_front(c.comp, c, f, dfds + k, arena + c.fp[f].f_off * elem);
+    // compressed fronts of this level (Alg. 5)
+    if (e_all > e) {
+      std::vector<int> cfr;
+      std::vector<const FrontDesc*> cfd;
+      std::vector<void*> ccb;
+      for (int k = e; k < e_all; ++k) {
+        const int32_t f = c.level_order[k];
+        cfr.push_back(f);
+        cfd.push_back(dfds + k);
+        ccb.push_back(arena + c.fp[f].f_off * elem);
+      }
+      factor_compressed_level(c.comp, c, cfr, cfd, ccb);
     }
   }
   HIPCHK(hipStreamSynchronize(c.stream));

@@ -154,6 +154,38 @@ void upload_plan(Context& c) {
   c.d_status.bytes = 16;
 }
 
+void Staging::put(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  const size_t need = (bytes + 255) & ~(size_t)255;
+  if (head + need > cap) {
+    sync(s);  // every earlier copy out of the ring has completed
+    if (need > cap) {
+      if (host) (void)hipHostFree(host);
+      host = nullptr;
+      cap = std::max(need, (size_t)64 << 20);
+      if (hipHostMalloc((void**)&host, cap, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        host = nullptr;
+        cap = 0;
+        throw Error(BFMF_E_NOMEM, "pinned host allocation of " + std::to_string(need) + " bytes failed");
+      }
+    }
+  }
+  char* h = host + head;
+  std::memcpy(h, src, bytes);
+  head += need;
+  HIPCHK(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, s));
+}
+
+void Staging::sync(hipStream_t s) {
+  HIPCHK(hipStreamSynchronize(s));
+  head = 0;
+}
+
+Staging::~Staging() {
+  if (host) (void)hipHostFree(host);
+}
+
 Context::~Context() {
   if (comp) comp_state_destroy(comp);
   comp = nullptr;

@@ -117,3 +117,17 @@ def test_error_paths_on_host_handle():
         assert bfmf.bfmf_status_str(bfmf.BFMF_E_NOCONV)
     finally:
         bfmf.bfmf_destroy(h)
+
+
+def test_one_hip_runtime_per_process():
+    """Importing the binding (before anything else) maps a single libamdhip64:
+    the library binds to the HIP runtime torch brings instead of adding a second."""
+    import subprocess
+    import sys
+    code = ("from paper_2007_00202_amd import bfmf\n"
+            "import torch\n"
+            "paths = set(l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l)\n"
+            "print(len(paths))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
