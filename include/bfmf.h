@@ -201,8 +201,12 @@ bfmf_status bfmf_get_front(bfmf_handle h, int32_t front, int32_t what, void* out
  * while bfmf_factor_opts.timing is set (factor and solve calls accumulate).
  * Classes: 0 assemble (extend-add), 1 panel LU loop (panel, interchanges,
  * triangular solves, rank-32 updates), 2 Schur GEMM C = F22 - F21 F12,
- * 3 forward sweep level, 4 backward sweep level, 5 SpMV, 6 GMRES vector ops.
- * flops / bytes are the algorithmic counts of the timed launches.
+ * 3 forward sweep level, 4 backward sweep level, 5 SpMV, 6 GMRES vector ops,
+ * 7 butterfly grouped GEMMs (products of butterflies and the GEMMs of their
+ * constructions), 8 interpolative decompositions, 9 entry extraction.
+ * launches counts the timed launches and launches_all every launch of the
+ * class; class 7 times one launch in eight, the others every launch.
+ * seconds, flops and bytes (algorithmic counts) cover the timed launches.
  * E_INVAL for an unknown class; bfmf_reset_kernel_stats clears all. */
 typedef struct {
     char name[32];
@@ -210,8 +214,9 @@ typedef struct {
     double seconds;
     double flops;
     double bytes;
+    int64_t launches_all;
 } bfmf_kernel_stat;
-enum { BFMF_KERNEL_CLASSES = 7 };
+enum { BFMF_KERNEL_CLASSES = 10 };
 bfmf_status bfmf_get_kernel_stats(bfmf_handle h, int32_t kind, bfmf_kernel_stat* out);
 bfmf_status bfmf_reset_kernel_stats(bfmf_handle h);
 

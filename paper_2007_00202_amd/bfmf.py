@@ -45,10 +45,10 @@ class bfmf_factor_opts(C.Structure):
 
 class bfmf_kernel_stat(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("seconds", C.c_double),
-                ("flops", C.c_double), ("bytes", C.c_double)]
+                ("flops", C.c_double), ("bytes", C.c_double), ("launches_all", C.c_int64)]
 
 
-BFMF_KERNEL_CLASSES = 7
+BFMF_KERNEL_CLASSES = 10
 
 
 class bfmf_solve_opts(C.Structure):
@@ -250,7 +250,7 @@ def bfmf_get_kernel_stats(h):
         st = bfmf_kernel_stat()
         _check(h, _lib.bfmf_get_kernel_stats(h, k, C.byref(st)))
         out[st.name.decode()] = {"launches": st.launches, "seconds": st.seconds, "flops": st.flops,
-                                 "bytes": st.bytes}
+                                 "bytes": st.bytes, "launches_all": st.launches_all}
     return out
 
 

@@ -311,12 +311,14 @@ bfmf_status bfmf_get_front(bfmf_handle h, int32_t front, int32_t what, void* out
 }
 
 bfmf_status bfmf_get_kernel_stats(bfmf_handle h, int32_t kind, bfmf_kernel_stat* out) {
-  static const char* names[K_COUNT] = {"assemble", "panel_lu", "schur_gemm", "forward_sweep",
-                                       "backward_sweep", "spmv", "gmres_vector"};
+  static const char* names[K_COUNT] = {"assemble",      "panel_lu",       "schur_gemm",     "forward_sweep",
+                                       "backward_sweep", "spmv",           "gmres_vector",   "butterfly_gemm",
+                                       "interp_decomp",  "entry_extract"};
   if (!h || !out || kind < 0 || kind >= K_COUNT) return BFMF_E_INVAL;
   std::memset(out, 0, sizeof(*out));
   std::strncpy(out->name, names[kind], sizeof(out->name) - 1);
   out->launches = h->timer.launches[kind];
+  out->launches_all = std::max(h->timer.issued[kind], h->timer.launches[kind]);  // classes timed at every launch
   out->seconds = h->timer.seconds[kind];
   out->flops = h->timer.flops[kind];
   out->bytes = h->timer.bytes[kind];

@@ -436,9 +436,19 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
   c.stage.put(d, blob.data(), blob.size(), s);
   for (size_t k = 0; k < plan.phase.size(); ++k) {
     if (plan.phase[k].empty()) continue;
+    const int tk = c.timer.want(K_BF_GEMM) ? c.timer.begin(s) : -1;
     chk(launch_grouped_gemm<T>((const GTask*)(d + toff[k]), (const int64_t*)(d + soff[k]), (int)plan.phase[k].size(),
                                ntiles[k], bases, s),
         "grouped gemm");
+    if (tk >= 0) {
+      double fl = 0, by = 0;
+      for (const GTask& t : plan.phase[k]) {
+        const double M = t.M, N = t.N, K = t.K;
+        fl += 8.0 * M * N * K;
+        by += sizeof(cplx<T>) * (M * K + K * N + M * N * (t.beta ? 2.0 : 1.0));
+      }
+      c.timer.end(tk, s, K_BF_GEMM, fl, by);
+    }
   }
   // no synchronisation: the next plan's upload is ordered after these launches on the stream
 }
@@ -510,7 +520,14 @@ void run_extract(BfRuntime<T>& rt, ExtractBatch& b) {
   }
   ExtractTask* d_t = (ExtractTask*)upload_tmp(rt, b.tasks);
   const int yb = (int)std::min<int64_t>(32, std::max<int64_t>(1, (maxe + 2047) / 2048));
+  KernelTimer& tm = rt.c->timer;
+  const int tk = tm.want(K_EXTRACT) ? tm.begin(rt.s()) : -1;
   chk(launch_front_extract<T>(d_t, (int)b.tasks.size(), yb, rt.c->d_values.p, sizeof(T) == 4, rt.s()), "extract");
+  if (tk >= 0) {
+    double by = 0;  // every output entry written once, plus its row and column index
+    for (auto& e : b.tasks) by += (double)e.nr * e.nc * sizeof(cplx<T>) + 4.0 * (e.nr + e.nc);
+    tm.end(tk, rt.s(), K_EXTRACT, 0, by);
+  }
   b.tasks.clear();
   b.idx.clear();
 }
@@ -546,7 +563,18 @@ struct IdLevel {
       po += p[i];
     }
     IdTask* dt = (IdTask*)upload_tmp(rt, tasks);
+    KernelTimer& tm = rt.c->timer;
+    const int tk = tm.want(K_ID) ? tm.begin(s) : -1;
     chk(launch_cpqr_id<T>(dt, (int)nb, rt.tol, s), "cpqr");
+    if (tk >= 0) {
+      double fl = 0, by = 0;  // pivoted QR of q x p truncated at rank k ~ min(p, q): 8 q p k flops, A read and written
+      for (size_t i = 0; i < nb; ++i) {
+        const double qq = q[i], pp = p[i], kk = std::min(q[i], p[i]);
+        fl += 8.0 * qq * pp * kk;
+        by += 2.0 * sizeof(cplx<T>) * qq * pp;
+      }
+      tm.end(tk, s, K_ID, fl, by);
+    }
     rank.assign(nb, 0);
     std::vector<int32_t> hp(std::max<int64_t>(tot_perm, 1));
     chk(hipMemcpyAsync(rank.data(), d_rank, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s), "rank");

@@ -232,14 +232,58 @@ struct SmwResult {
 }  // namespace
 
 // ------------------------------------------------------------ HOD-BF products
+namespace {
+
+// One grouped GEMM over dense diagonal blocks stored in the pool:
+// Y(r, :) = op(D_i) X(r, :) (+ Y(r, :) when accumulate) for the row ranges r
+// of the blocks; X and Y must not overlap.
+template <class T>
+void dense_blocks(BfRuntime<T>& rt, const std::vector<std::pair<int64_t, std::pair<int, int>>>& blocks, bool adjoint,
+                  const void* X, int64_t ldx, void* Y, int64_t ldy, int nrhs, bool accumulate) {
+  if (blocks.empty() || nrhs <= 0) return;
+  std::vector<GTask> ph;
+  int64_t rows = 0;
+  for (auto& b : blocks) {
+    const int64_t off = b.first;
+    const int r0 = b.second.first, n = b.second.second;
+    if (n <= 0) continue;
+    GTask t = {};
+    t.a_off = off;
+    t.lda = n;
+    t.opA = (int8_t)(adjoint ? OP_C : OP_N);
+    t.abase = 0;
+    t.b_off = r0;
+    t.ldb = ldx;
+    t.opB = OP_N;
+    t.bbase = 1;
+    t.c_off = r0;
+    t.ldc = ldy;
+    t.cbase = 2;
+    t.M = n;
+    t.N = nrhs;
+    t.K = n;
+    t.alpha_re = 1;
+    t.beta = (int8_t)(accumulate ? 1 : 0);
+    ph.push_back(t);
+    rows = std::max<int64_t>(rows, (int64_t)r0 + n);
+  }
+  if (ph.empty()) return;
+  BfPlan p;
+  p.phase.push_back(ph);
+  const int64_t lim[4] = {(int64_t)(rt.pool.used / sizeof(cplx<T>)), ldx * nrhs, ldy * nrhs, 0};
+  if (rows > ldx || rows > ldy) throw Error(BFMF_E_INVAL, "internal: dense block rows beyond the leading dimension");
+  run_plan<T>(p, *rt.c, rt.pool_base(), X, Y, nullptr, rt.s(), lim);
+}
+
+}  // namespace
+
 template <class T>
 void hodbf_apply(BfRuntime<T>& rt, const Hodbf<T>& h, const void* X, int64_t ldx, void* Y, int64_t ldy, int nrhs) {
-  const char* pool = rt.pool_base();
-  // leaves: y = D x
+  // leaves: y = D x, one grouped GEMM
+  std::vector<std::pair<int64_t, std::pair<int, int>>> lb;
   for (const auto& nd : h.nodes)
-    if (nd.left < 0)
-      gemm<T>(rt, pool + nd.leaf_off * sizeof(cplx<T>), nd.size(), OP_N, (const cplx<T>*)X + nd.beg, ldx, OP_N,
-              (cplx<T>*)Y + nd.beg, ldy, nd.size(), nrhs, nd.size(), 1.0, 0, 0);
+    if (nd.left < 0) lb.push_back({nd.leaf_off, {nd.beg, nd.size()}});
+  dense_blocks<T>(rt, lb, false, X, ldx, Y, ldy, nrhs, false);
   for (int l = h.max_level; l >= 0; --l) {
     std::vector<BfCall> calls;
     for (int i : h.by_level[l]) {
@@ -254,6 +298,10 @@ void hodbf_apply(BfRuntime<T>& rt, const Hodbf<T>& h, const void* X, int64_t ldx
   }
 }
 
+// y = D_node^-1 x (or D_node^-H x) with D^-1 = (I + X_t) diag(D1^-1, D2^-1)
+// per internal node t (Alg. 4): leaves in one grouped GEMM, then per level
+// the butterfly X_t in place (y_t += X_t y_t) and the dense X_t through a
+// copy.  x and y must not overlap.
 template <class T>
 void hodbf_inv_apply(BfRuntime<T>& rt, const Hodbf<T>& h, int node, const void* X, int64_t ldx, void* Y, int64_t ldy,
                      int nrhs, bool adjoint) {
@@ -271,48 +319,43 @@ void hodbf_inv_apply(BfRuntime<T>& rt, const Hodbf<T>& h, int node, const void* 
       st.push_back(h.nodes[i].right);
     }
   }
-  const char* pool = rt.pool_base();
   cplx<T>* y = (cplx<T>*)Y;
-  const cplx<T>* x = (const cplx<T>*)X;
   auto mk = rt.scratch.mark();
-  cplx<T>* tmp = (cplx<T>*)rt.scratch.take((size_t)std::max(n, 1) * nrhs * sizeof(cplx<T>));
-  auto leaves = [&](const cplx<T>* src, int64_t lds) {
-    for (int l = 0; l <= h.max_level; ++l)
-      for (int i : lv[l]) {
-        const auto& nd = h.nodes[i];
-        if (nd.left >= 0) continue;
-        gemm<T>(rt, pool + nd.inv_off * sizeof(cplx<T>), nd.size(), adjoint ? OP_C : OP_N, src + (nd.beg - base), lds,
-                OP_N, y + (nd.beg - base), ldy, nd.size(), nrhs, nd.size(), 1.0, 0, 0);
-      }
+  cplx<T>* tmp = nullptr;  // n x nrhs copy of y, for dense X_t and the adjoint leaves
+  auto copy_y = [&]() {
+    if (!tmp) tmp = (cplx<T>*)rt.scratch.take((size_t)std::max(n, 1) * nrhs * sizeof(cplx<T>));
+    axpby<T>(rt, tmp, n, y, ldy, n, nrhs, 1.0, 0.0);
   };
-  auto level_update = [&](int l) {  // y_t += X_t^(H) y_t for internal nodes of level l
+  std::vector<std::pair<int64_t, std::pair<int, int>>> leaves;
+  for (int l = 0; l <= h.max_level; ++l)
+    for (int i : lv[l])
+      if (h.nodes[i].left < 0) leaves.push_back({h.nodes[i].inv_off, {h.nodes[i].beg - base, h.nodes[i].size()}});
+  auto level_update = [&](int l) {  // y_t += X_t^(H) y_t for the internal nodes of level l
     std::vector<BfCall> calls;
+    std::vector<std::pair<int64_t, std::pair<int, int>>> dense;
     for (int i : lv[l]) {
       const auto& nd = h.nodes[i];
       if (nd.left < 0 || nd.x_zero) continue;
-      if (nd.x_dense) {
-        gemm<T>(rt, pool + nd.inv_off * sizeof(cplx<T>), nd.size(), adjoint ? OP_C : OP_N, y + (nd.beg - base), ldy,
-                OP_N, tmp + (nd.beg - base), n, nd.size(), nrhs, nd.size(), 1.0, 0, 0);
-      } else {
-        calls.push_back(BfCall{nd.x.get(), nd.beg - base, nd.beg - base, 1.0, 0.0, 0});
-      }
+      if (nd.x_dense)
+        dense.push_back({nd.inv_off, {nd.beg - base, nd.size()}});
+      else
+        calls.push_back(BfCall{nd.x.get(), nd.beg - base, nd.beg - base, 1.0, 0.0, 1});
     }
-    if (!calls.empty()) rt.apply_set(calls, y, ldy, tmp, n, nrhs, adjoint);
-    for (int i : lv[l]) {
-      const auto& nd = h.nodes[i];
-      if (nd.left < 0 || nd.x_zero) continue;
-      axpby<T>(rt, y + (nd.beg - base), ldy, tmp + (nd.beg - base), n, nd.size(), nrhs, 1.0, 1.0);
+    if (!dense.empty()) {
+      copy_y();
+      dense_blocks<T>(rt, dense, adjoint, tmp, n, y, ldy, nrhs, true);
     }
+    // in place: the first phase of a product reads y before its last phase writes it
+    if (!calls.empty()) rt.apply_set(calls, y, ldy, y, ldy, nrhs, adjoint);
   };
   if (!adjoint) {
-    leaves(x, ldx);
+    dense_blocks<T>(rt, leaves, false, X, ldx, y, ldy, nrhs, false);
     for (int l = h.max_level; l >= root.level; --l) level_update(l);
   } else {
-    axpby<T>(rt, y, ldy, x, ldx, n, nrhs, 1.0, 0.0);
+    axpby<T>(rt, y, ldy, X, ldx, n, nrhs, 1.0, 0.0);
     for (int l = root.level; l <= h.max_level; ++l) level_update(l);
-    // leaves: y_leaf = Dinv^H y_leaf (through tmp)
-    axpby<T>(rt, tmp, n, y, ldy, n, nrhs, 1.0, 0.0);
-    leaves(tmp, n);
+    copy_y();
+    dense_blocks<T>(rt, leaves, true, tmp, n, y, ldy, nrhs, false);
   }
   rt.scratch.release(mk);
 }

@@ -66,7 +66,19 @@ struct Staging {
 
 enum class State { Created, Analyzed, Factored };
 
-enum KernelKind { K_ASSEMBLE = 0, K_LU = 1, K_SCHUR = 2, K_FWD = 3, K_BWD = 4, K_SPMV = 5, K_VEC = 6, K_COUNT = 7 };
+enum KernelKind {
+  K_ASSEMBLE = 0,
+  K_LU = 1,
+  K_SCHUR = 2,
+  K_FWD = 3,
+  K_BWD = 4,
+  K_SPMV = 5,
+  K_VEC = 6,
+  K_BF_GEMM = 7,  // grouped GEMMs of butterfly products and constructions
+  K_ID = 8,       // interpolative decompositions
+  K_EXTRACT = 9,  // entry extraction from never-formed fronts and sketches
+  K_COUNT = 10
+};
 
 // HIP-event timing of kernel classes on the handle's stream.
 struct KernelTimer {
@@ -79,8 +91,14 @@ struct KernelTimer {
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   std::vector<Rec> recs;
-  int64_t launches[K_COUNT] = {};
+  int64_t launches[K_COUNT] = {};  // timed launches
+  int64_t issued[K_COUNT] = {};    // all launches while enabled
+  int sample_every[K_COUNT] = {1, 1, 1, 1, 1, 1, 1, 8, 1, 1};  // time one launch in this many
   double seconds[K_COUNT] = {}, flops[K_COUNT] = {}, bytes[K_COUNT] = {};
+  // timed butterfly GEMM launches by floor(log2(flops)): count, seconds, flops
+  double hist_n[64] = {}, hist_s[64] = {}, hist_f[64] = {};
+  // whether to time the next launch of this class (counts it either way)
+  bool want(int kind) { return enabled && (issued[kind]++ % sample_every[kind]) == 0; }
   hipEvent_t take();
   int begin(hipStream_t s);
   void end(int token, hipStream_t s, int kind, double fl, double by);

@@ -38,10 +38,11 @@ __global__ __launch_bounds__(256) void grouped_gemm_kernel(const GTask* __restri
   const int tm = (t.M + GEMM_TM - 1) / GEMM_TM;
   const int tn = (t.N + GEMM_TN - 1) / GEMM_TN;
   if (local >= (int64_t)tm * tn || t.M <= 0 || t.N <= 0) return;
-  void* bases[4] = {b0, b1, b2, b3};
-  const cplx<T>* A = (const cplx<T>*)bases[t.abase] + t.a_off;
-  const cplx<T>* B = (const cplx<T>*)bases[t.bbase] + t.b_off;
-  cplx<T>* C = (cplx<T>*)bases[t.cbase] + t.c_off;
+  // select the base pointers without an indexed (scratch) array
+  auto base = [&](int i) -> void* { return i == 0 ? b0 : i == 1 ? b1 : i == 2 ? b2 : b3; };
+  const cplx<T>* A = (const cplx<T>*)base(t.abase) + t.a_off;
+  const cplx<T>* B = (const cplx<T>*)base(t.bbase) + t.b_off;
+  cplx<T>* C = (cplx<T>*)base(t.cbase) + t.c_off;
   const cplx<T> alpha = {(T)t.alpha_re, (T)t.alpha_im};
   gemm_tile<T>(A, t.lda, t.opA, B, t.ldb, C, t.ldc, t.M, t.N, t.K, alpha, t.beta, (int)(local % tm), (int)(local / tm),
                sm, t.opB);

@@ -3,13 +3,23 @@
 // One 256-thread workgroup computes a 64x64 tile of C; each of the four
 // 64-wide waves owns a 32x32 quarter made of 2x2 MFMA 16x16 blocks, with the
 // real and imaginary parts in separate accumulators (4 real MFMAs per
-// complex multiply-add).  A and B tiles of depth 16 are staged through LDS.
+// complex multiply-add).  A and B tiles of depth 16 are staged through LDS,
+// the next one prefetched into registers while the current one is used.
 #pragma once
 #include "common.hpp"
 
 namespace bfmf {
 
 constexpr int GEMM_TM = 64, GEMM_TN = 64, GEMM_TK = 16;
+
+// *p when ok, else 0 (a guarded load: a select between the global address and
+// a local zero would put the zero in scratch memory)
+template <class T>
+__device__ __forceinline__ cplx<T> load_or_zero(const cplx<T>* p, bool ok) {
+  cplx<T> v = {0, 0};
+  if (ok) v = *p;
+  return v;
+}
 
 template <class T>
 struct GemmSmem {
@@ -32,56 +42,91 @@ __device__ __forceinline__ void gemm_tile(const cplx<T>* __restrict__ A, int64_t
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
   const int row0 = tm * GEMM_TM, col0 = tn * GEMM_TN;
   acc_t accr[2][2], acci[2][2];
+#pragma unroll
   for (int i = 0; i < 2; ++i)
+#pragma unroll
     for (int j = 0; j < 2; ++j)
+#pragma unroll
       for (int r = 0; r < 4; ++r) {
         accr[i][j][r] = 0;
         acci[i][j][r] = 0;
       }
-  const cplx<T> zero = {0, 0};
-  for (int k0 = 0; k0 < K; k0 += GEMM_TK) {
-    // stage A: 64 rows x 16 k
+  // Each thread stages 4 A and 4 B entries per k-block of depth 16.  The
+  // next block is fetched into registers before the MFMAs of the current
+  // block run, so its global-memory latency overlaps the arithmetic.
+  cplx<T> ra[4], rb[4];
+  auto fetch = [&](int k0) {
     if (opA == OP_N) {
-      const int k = tid >> 4, rb = (tid & 15) * 4;
+      const int k = tid >> 4, rb0 = (tid & 15) * 4;
       const int gk = k0 + k;
+#pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int gr = row0 + rb + q;
-        sm.a[k][rb + q] = (gk < K && gr < M) ? A[(int64_t)gr + (int64_t)gk * lda] : zero;
+        const int gr = row0 + rb0 + q;
+        ra[q] = load_or_zero(A + (int64_t)gr + (int64_t)gk * lda, gk < K && gr < M);
       }
     } else {
       const int r = tid >> 2, kb = (tid & 3) * 4;
       const int gr = row0 + r;
+#pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int gk = k0 + kb + q;
-        cplx<T> v = (gk < K && gr < M) ? A[(int64_t)gk + (int64_t)gr * lda] : zero;
+        cplx<T> v = load_or_zero(A + (int64_t)gk + (int64_t)gr * lda, gk < K && gr < M);
         if (opA == OP_C) v.im = -v.im;
-        sm.a[kb + q][r] = v;
+        ra[q] = v;
       }
     }
-    // stage B: 16 k x 64 cols
     if (opB == OP_N) {
       const int c = tid >> 2, kb = (tid & 3) * 4;
       const int gc = col0 + c;
+#pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int gk = k0 + kb + q;
-        sm.b[kb + q][c] = (gk < K && gc < N) ? B[(int64_t)gk + (int64_t)gc * ldb] : zero;
+        rb[q] = load_or_zero(B + (int64_t)gk + (int64_t)gc * ldb, gk < K && gc < N);
       }
     } else {
       const int k = tid >> 4, cb = (tid & 15) * 4;
       const int gk = k0 + k;
+#pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int gc = col0 + cb + q;
-        cplx<T> v = (gk < K && gc < N) ? B[(int64_t)gc + (int64_t)gk * ldb] : zero;
+        cplx<T> v = load_or_zero(B + (int64_t)gc + (int64_t)gk * ldb, gk < K && gc < N);
         if (opB == OP_C) v.im = -v.im;
-        sm.b[k][cb + q] = v;
+        rb[q] = v;
       }
     }
+  };
+  auto stage = [&]() {
+    if (opA == OP_N) {
+      const int k = tid >> 4, rb0 = (tid & 15) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sm.a[k][rb0 + q] = ra[q];
+    } else {
+      const int r = tid >> 2, kb = (tid & 3) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sm.a[kb + q][r] = ra[q];
+    }
+    if (opB == OP_N) {
+      const int c = tid >> 2, kb = (tid & 3) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sm.b[kb + q][c] = rb[q];
+    } else {
+      const int k = tid >> 4, cb = (tid & 15) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sm.b[k][cb + q] = rb[q];
+    }
+  };
+  if (K > 0) fetch(0);
+  for (int k0 = 0; k0 < K; k0 += GEMM_TK) {
+    stage();
     __syncthreads();
+    if (k0 + GEMM_TK < K) fetch(k0 + GEMM_TK);  // in flight during the MFMAs below
 #pragma unroll
     for (int kk = 0; kk < GEMM_TK; kk += 4) {
       const int k = kk + (lane >> 4);
       cplx<T> a[2], b[2];
+#pragma unroll
       for (int i = 0; i < 2; ++i) a[i] = sm.a[k][wr + i * 16 + (lane & 15)];
+#pragma unroll
       for (int j = 0; j < 2; ++j) b[j] = sm.b[k][wc + j * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -95,8 +140,11 @@ __device__ __forceinline__ void gemm_tile(const cplx<T>* __restrict__ A, int64_t
     }
     __syncthreads();
   }
+#pragma unroll
   for (int i = 0; i < 2; ++i)
+#pragma unroll
     for (int j = 0; j < 2; ++j)
+#pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gr = row0 + wr + i * 16 + Mfma<T>::row(lane, r);
         const int gc = col0 + wc + j * 16 + (lane & 15);

@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
 
 #include "context.hpp"
@@ -83,6 +84,12 @@ void KernelTimer::collect() {
     seconds[r.kind] += ms * 1e-3;
     flops[r.kind] += r.flops;
     bytes[r.kind] += r.bytes;
+    if (r.kind == K_BF_GEMM) {
+      const int b = r.flops >= 1 ? std::min(63, (int)std::log2(r.flops)) : 0;
+      hist_n[b] += 1;
+      hist_s[b] += ms * 1e-3;
+      hist_f[b] += r.flops;
+    }
   }
   recs.clear();
   used = 0;
@@ -92,9 +99,10 @@ void KernelTimer::reset() {
   recs.clear();
   used = 0;
   for (int k = 0; k < K_COUNT; ++k) {
-    launches[k] = 0;
+    launches[k] = issued[k] = 0;
     seconds[k] = flops[k] = bytes[k] = 0;
   }
+  for (int b = 0; b < 64; ++b) hist_n[b] = hist_s[b] = hist_f[b] = 0;
 }
 
 KernelTimer::~KernelTimer() {
@@ -251,6 +259,13 @@ void factor_dense(Context& c) {
   HIPCHK(hipStreamSynchronize(c.stream));
   c.stats.factor_seconds = now() - t0;
   c.timer.collect();
+  if (c.verbose && c.timer.enabled) {
+    fprintf(stderr, "[bfmf] butterfly GEMM launches (timed sample) by log2 flops: bucket count ms TFLOP/s\n");
+    for (int b = 0; b < 64; ++b)
+      if (c.timer.hist_n[b] > 0)
+        fprintf(stderr, "[bfmf]   2^%-2d %8.0f %9.2f %7.2f\n", b, c.timer.hist_n[b], 1e3 * c.timer.hist_s[b],
+                c.timer.hist_f[b] / std::max(c.timer.hist_s[b], 1e-30) / 1e12);
+  }
   int st[3] = {0, 0, 0};
   HIPCHK(hipMemcpy(st, c.d_status.p, sizeof(st), hipMemcpyDeviceToHost));
   c.stats.singular_front = st[0] ? st[1] : -1;
