@@ -2,6 +2,8 @@
 #include "bf.hpp"
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 
@@ -402,10 +404,14 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
       const int64_t fa = t.opA == OP_N ? footprint(t.a_off, t.M, t.K, t.lda) : footprint(t.a_off, t.K, t.M, t.lda);
       const int64_t fb = t.opB == OP_N ? footprint(t.b_off, t.K, t.N, t.ldb) : footprint(t.b_off, t.N, t.K, t.ldb);
       const int64_t fc = footprint(t.c_off, t.M, t.N, t.ldc);
-      bool bad = t.abase < 0 || t.abase > 3 || t.bbase < 0 || t.bbase > 3 || t.cbase < 0 || t.cbase > 3;
-      bad = bad || (fa >= 0 && (t.a_off < 0 || fa >= lim[t.abase] || !bases[t.abase]));
-      bad = bad || (fb >= 0 && (t.b_off < 0 || fb >= lim[t.bbase] || !bases[t.bbase]));
-      bad = bad || (fc >= 0 && (t.c_off < 0 || fc >= lim[t.cbase] || !bases[t.cbase]));
+      // base 4 (absolute addresses) is built only from allocations sized for the task; the others are checked
+      auto out_of = [&](int b, int64_t off, int64_t f) {
+        if (f < 0) return false;
+        if (b == 4) return off <= 0;
+        return off < 0 || f >= lim[b] || !bases[b];
+      };
+      bool bad = t.abase < 0 || t.abase > 4 || t.bbase < 0 || t.bbase > 4 || t.cbase < 0 || t.cbase > 4;
+      bad = bad || out_of(t.abase, t.a_off, fa) || out_of(t.bbase, t.b_off, fb) || out_of(t.cbase, t.c_off, fc);
       if (bad)
         throw Error(BFMF_E_INVAL, "internal: butterfly product task outside its buffers (M " + std::to_string(t.M) +
                                       " N " + std::to_string(t.N) + " K " + std::to_string(t.K) + ")");
@@ -559,13 +565,54 @@ struct IdLevel {
         throw Error(BFMF_E_INVAL, "ID block too large (" + std::to_string(q[i]) + " x " + std::to_string(p[i]) + ")");
       const int maxrank = std::max(1, std::min(p[i], q[i]));
       void* Tb = rt.scratch.take((size_t)maxrank * std::max(p[i], 1) * sizeof(cplx<T>));
-      tasks[i] = IdTask{A[i], std::max(q[i], 1), q[i], p[i], maxrank, d_rank + i, d_perm + po, Tb};
+      tasks[i] = IdTask{A[i], std::max(q[i], 1), q[i], p[i], maxrank, d_rank + i, d_perm + po, Tb, nullptr, nullptr};
       po += p[i];
     }
+    // Gram variant (FP64, tolerances where eps p / tol^2 is negligible): G_i = A_i^H A_i in one grouped GEMM
+    const bool gram = sizeof(T) == 8 && rt.tol >= 1e-4;
+    if (gram) {
+      std::vector<GTask> gt;
+      for (size_t i = 0; i < nb; ++i) {
+        const int pp = std::max(p[i], 1);
+        tasks[i].G = rt.scratch.take((size_t)pp * pp * sizeof(cplx<T>));
+        tasks[i].R = rt.scratch.take((size_t)tasks[i].maxrank * pp * sizeof(cplx<T>));
+        if (p[i] <= 0) continue;
+        GTask t = {};
+        t.a_off = (int64_t)((uintptr_t)A[i] / sizeof(cplx<T>));
+        t.lda = std::max(q[i], 1);
+        t.opA = OP_C;
+        t.abase = 4;
+        t.b_off = t.a_off;
+        t.ldb = t.lda;
+        t.opB = OP_N;
+        t.bbase = 4;
+        t.c_off = (int64_t)((uintptr_t)tasks[i].G / sizeof(cplx<T>));
+        t.ldc = p[i];
+        t.cbase = 4;
+        t.M = p[i];
+        t.N = p[i];
+        t.K = q[i];
+        t.alpha_re = 1;
+        t.beta = 0;
+        gt.push_back(t);
+      }
+      if (!gt.empty()) {
+        BfPlan gp;
+        gp.phase.push_back(gt);
+        const int64_t lim[4] = {0, 0, 0, 0};
+        run_plan<T>(gp, *rt.c, nullptr, nullptr, nullptr, nullptr, s, lim);
+      }
+    }
     IdTask* dt = (IdTask*)upload_tmp(rt, tasks);
+    const bool vb = rt.c->verbose;
+    if (vb) rt.c->stage.sync(s);
+    const auto t_id0 = std::chrono::steady_clock::now();
     KernelTimer& tm = rt.c->timer;
     const int tk = tm.want(K_ID) ? tm.begin(s) : -1;
-    chk(launch_cpqr_id<T>(dt, (int)nb, rt.tol, s), "cpqr");
+    if (gram)
+      chk(launch_gram_id<T>(dt, (int)nb, rt.tol, s), "gram id");
+    else
+      chk(launch_cpqr_id<T>(dt, (int)nb, rt.tol, s), "cpqr");
     if (tk >= 0) {
       double fl = 0, by = 0;  // pivoted QR of q x p truncated at rank k ~ min(p, q): 8 q p k flops, A read and written
       for (size_t i = 0; i < nb; ++i) {
@@ -581,6 +628,18 @@ struct IdLevel {
     chk(hipMemcpyAsync(hp.data(), d_perm, std::max<int64_t>(tot_perm, 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s),
         "perm");
     rt.c->stage.sync(s);
+    if (vb) {  // one line per ID launch: blocks, largest q, p and rank, wall time of launch + wait
+      int mq = 0, mp = 0, mr = 0;
+      double work = 0;
+      for (size_t i = 0; i < nb; ++i) {
+        mq = std::max(mq, q[i]);
+        mp = std::max(mp, p[i]);
+        mr = std::max(mr, rank[i]);
+        work = std::max(work, (double)q[i] * p[i] * rank[i]);
+      }
+      const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t_id0).count();
+      fprintf(stderr, "[bfmf-id] blocks %zu maxq %d maxp %d maxrank %d maxqpk %.3g us %.1f\n", nb, mq, mp, mr, work, us);
+    }
     perm.assign(nb, {});
     po = 0;
     for (size_t i = 0; i < nb; ++i) {

@@ -37,7 +37,9 @@ namespace bfmf {
 // One product of a grouped (ragged) GEMM: C = beta C + alpha op(A) op(B).
 // Operand addresses are element offsets from one of the base pointers the
 // launch receives (base[abase] + a_off, ...), so a task list can be reused
-// for other input/output buffers with the same layout.
+// for other input/output buffers with the same layout.  Base index 4 means
+// no base: the offset is the operand's device address divided by the
+// element size.
 struct GTask {
   int64_t a_off, b_off, c_off;
   int64_t lda, ldb, ldc;
@@ -59,6 +61,8 @@ struct IdTask {
   int32_t* rank;  // output
   int32_t* perm;  // output, p entries
   void* T;        // output, maxrank x p (ld maxrank)
+  void* G;        // Gram variant: G = A^H A (p x p, ld p), input
+  void* R;        // Gram variant: workspace, maxrank x p (row i at R + i p)
 };
 
 // Extraction of the dense submatrix F(rows, cols) of a front that is never

@@ -39,10 +39,15 @@ __global__ __launch_bounds__(256) void grouped_gemm_kernel(const GTask* __restri
   const int tn = (t.N + GEMM_TN - 1) / GEMM_TN;
   if (local >= (int64_t)tm * tn || t.M <= 0 || t.N <= 0) return;
   // select the base pointers without an indexed (scratch) array
-  auto base = [&](int i) -> void* { return i == 0 ? b0 : i == 1 ? b1 : i == 2 ? b2 : b3; };
-  const cplx<T>* A = (const cplx<T>*)base(t.abase) + t.a_off;
-  const cplx<T>* B = (const cplx<T>*)base(t.bbase) + t.b_off;
-  cplx<T>* C = (cplx<T>*)base(t.cbase) + t.c_off;
+  // operand address = base + offset, in integer arithmetic; base 4 is zero (the offset is the
+  // operand's address in elements, for operands scattered over several allocations)
+  auto addr = [&](int i, int64_t off) -> uintptr_t {
+    const uintptr_t b = i == 0 ? (uintptr_t)b0 : i == 1 ? (uintptr_t)b1 : i == 2 ? (uintptr_t)b2 : i == 3 ? (uintptr_t)b3 : 0;
+    return b + (uintptr_t)off * sizeof(cplx<T>);
+  };
+  const cplx<T>* A = (const cplx<T>*)addr(t.abase, t.a_off);
+  const cplx<T>* B = (const cplx<T>*)addr(t.bbase, t.b_off);
+  cplx<T>* C = (cplx<T>*)addr(t.cbase, t.c_off);
   const cplx<T> alpha = {(T)t.alpha_re, (T)t.alpha_im};
   gemm_tile<T>(A, t.lda, t.opA, B, t.ldb, C, t.ldc, t.M, t.N, t.K, alpha, t.beta, (int)(local % tm), (int)(local / tm),
                sm, t.opB);
@@ -208,6 +213,135 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const IdTask* __restrict__
       cplx<T> s = A[i + (int64_t)j * lda];
       for (int l = i + 1; l < rank; ++l) s = csub(s, cmul(A[i + (int64_t)l * lda], tcol[l]));
       tcol[i] = cdiv(s, A[i + (int64_t)i * lda]);
+    }
+  }
+}
+
+// ------------------------------------------------------------ Gram ID
+// The same decomposition from the Gram matrix G = A^H A = R^H R: pivoted
+// Cholesky, left-looking (row k of R from G's pivot column and the k rows
+// before it), chooses at each step the largest remaining squared column norm
+// d_j (first index on ties) and stops at the first d <= tol^2 d_0, which in
+// exact arithmetic are the pivots and the rank of the column-pivoted QR.
+// T = R11^-1 R12 by back substitution, one thread per remaining column.
+// Rounding in G limits the accuracy of T to about eps p / tol^2 (relative),
+// so the host uses this variant only for tolerances where that is small.
+template <class T>
+__device__ __forceinline__ void block_argmax(double v, int i, double* red_v, int* red_i, double& bv, int& bi) {
+  // wave maximum (first index on ties), then across the four waves
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(v, o);
+    const int oi = __shfl_xor(i, o);
+    if (ov > v || (ov == v && oi < i)) {
+      v = ov;
+      i = oi;
+    }
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red_v[wave] = v;
+    red_i[wave] = i;
+  }
+  __syncthreads();
+  bv = red_v[0];
+  bi = red_i[0];
+  for (int w = 1; w < 4; ++w)
+    if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bi)) {
+      bv = red_v[w];
+      bi = red_i[w];
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void gram_id_kernel(const IdTask* __restrict__ tasks, double tol) {
+  const IdTask& tk = tasks[blockIdx.x];
+  const int p = tk.p;
+  if (p > ID_MAXP || p < 0 || tk.q < 0) {  // the host never sends these; refuse, never overflow LDS
+    if (threadIdx.x == 0) *tk.rank = -1;
+    return;
+  }
+  const cplx<T>* G = (const cplx<T>*)tk.G;
+  cplx<T>* R = (cplx<T>*)tk.R;
+  __shared__ double d[ID_MAXP];
+  __shared__ int sel[ID_MAXP];   // step at which a column was chosen, or -1
+  __shared__ int piv[ID_MAXP];
+  __shared__ cplx<T> rc[ID_MAXP];  // R(0:k, pivot)
+  __shared__ double red_v[2][4];
+  __shared__ int red_i[2][4];
+  const int tid = threadIdx.x;
+  for (int j = tid; j < p; j += 256) {
+    d[j] = (double)G[j + (int64_t)j * p].re;
+    sel[j] = -1;
+  }
+  __syncthreads();
+  const int kmax = min(tk.maxrank, p);
+  double d0 = 0;
+  int k = 0;
+  for (; k < kmax; ++k) {
+    double v = -1;
+    int vi = p;
+    for (int j = tid; j < p; j += 256)
+      if (sel[j] < 0 && d[j] > v) {
+        v = d[j];
+        vi = j;
+      }
+    double dmax;
+    int pi;
+    block_argmax<T>(v, vi, red_v[k & 1], red_i[k & 1], dmax, pi);
+    if (k == 0) d0 = dmax;
+    if (!(dmax > tol * tol * d0) || !(dmax > 0) || pi >= p) break;
+    const double rkk = sqrt(dmax);
+    for (int i = tid; i < k; i += 256) rc[i] = R[(int64_t)i * p + pi];
+    __syncthreads();  // rc visible; every thread has read d and sel for this step
+    // row k: R(k, j) = (G(pi, j) - sum_i conj(R(i, pi)) R(i, j)) / rkk, G(pi, j) = conj(G(j, pi))
+    for (int j = tid; j < p; j += 256) {
+      cplx<T> out = {0, 0};
+      if (j == pi) {
+        out.re = (T)rkk;
+      } else if (sel[j] < 0) {
+        const cplx<T> g = G[j + (int64_t)pi * p];
+        double sr = g.re, si = -(double)g.im;
+        for (int i = 0; i < k; ++i) {
+          const cplx<T> a = rc[i], b = R[(int64_t)i * p + j];
+          sr -= (double)a.re * b.re + (double)a.im * b.im;  // conj(a) b
+          si -= (double)a.re * b.im - (double)a.im * b.re;
+        }
+        out.re = (T)(sr / rkk);
+        out.im = (T)(si / rkk);
+        const double nd = d[j] - (sr * sr + si * si) / dmax;
+        d[j] = nd > 0 ? nd : 0;
+      }
+      R[(int64_t)k * p + j] = out;
+    }
+    if (tid == 0) {
+      sel[pi] = k;
+      piv[k] = pi;
+    }
+    __syncthreads();
+  }
+  const int rank = k;
+  // perm: the pivots, then the other columns in ascending order
+  if (tid == 0) {
+    *tk.rank = rank;
+    int c = rank;
+    for (int j = 0; j < p; ++j) {
+      if (sel[j] >= 0)
+        tk.perm[sel[j]] = j;
+      else
+        tk.perm[c++] = j;
+    }
+  }
+  __syncthreads();
+  // T(:, c) = R11^-1 R(0:rank, perm[rank + c]), R11(i, m) = R(i, piv[m]) for m >= i
+  cplx<T>* Tout = (cplx<T>*)tk.T;
+  const int ldt = tk.maxrank;
+  for (int c = tid; c < p - rank; c += 256) {
+    const int j = tk.perm[rank + c];
+    cplx<T>* tcol = Tout + (int64_t)c * ldt;
+    for (int i = rank - 1; i >= 0; --i) {
+      cplx<T> s = R[(int64_t)i * p + j];
+      for (int m = i + 1; m < rank; ++m) s = csub(s, cmul(R[(int64_t)i * p + piv[m]], tcol[m]));
+      tcol[i] = cdiv(s, R[(int64_t)i * p + piv[i]]);
     }
   }
 }
@@ -559,6 +693,13 @@ hipError_t launch_cpqr_id(const IdTask* d_tasks, int ntasks, double tol, hipStre
 }
 
 template <class T>
+hipError_t launch_gram_id(const IdTask* d_tasks, int ntasks, double tol, hipStream_t s) {
+  if (ntasks == 0) return hipSuccess;
+  hipLaunchKernelGGL((gram_id_kernel<T>), dim3(ntasks), dim3(256), 0, s, d_tasks, tol);
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t launch_id_expand(const IdTask* d_tasks, int ntasks, void* const* d_outs, const int64_t* d_ldo,
                             bool transpose_out, bool conj_out, hipStream_t s) {
   if (ntasks == 0) return hipSuccess;
@@ -641,6 +782,7 @@ hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int6
 #define INST(T)                                                                                                       \
   template hipError_t launch_grouped_gemm<T>(const GTask*, const int64_t*, int, int64_t, void* const[4], hipStream_t); \
   template hipError_t launch_cpqr_id<T>(const IdTask*, int, double, hipStream_t);                                     \
+  template hipError_t launch_gram_id<T>(const IdTask*, int, double, hipStream_t);                                     \
   template hipError_t launch_id_expand<T>(const IdTask*, int, void* const*, const int64_t*, bool, bool, hipStream_t);  \
   template hipError_t launch_front_extract<T>(const ExtractTask*, int, int, const void*, bool, hipStream_t);          \
   template hipError_t launch_philox_gauss<T>(void*, int64_t, int64_t, int, int, const int32_t*, const int32_t*,       \
