@@ -56,7 +56,8 @@ def build(verbose=False, jobs=None):
     if bad:
         raise RuntimeError("hipcc failed for: " + ", ".join(os.path.relpath(b[0], ROOT) for b in bad))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *[r[1] for r in res]]
+    # every symbol resolved at link time: a missing template instantiation fails the build
+    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-Wl,--no-undefined", "-o", tmp, *[r[1] for r in res]]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)

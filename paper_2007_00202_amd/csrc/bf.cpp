@@ -396,7 +396,7 @@ int64_t footprint(int64_t off, int64_t rows, int64_t cols, int64_t ld) {
 
 template <class T>
 void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y, void* ws, hipStream_t s,
-              const int64_t lim[4]) {
+              const int64_t lim[4], int kind) {
   (void)c;
   void* bases[4] = {pool, const_cast<void*>(X), Y, ws};
   for (auto& ph : plan.phase)
@@ -442,7 +442,7 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
   c.stage.put(d, blob.data(), blob.size(), s);
   for (size_t k = 0; k < plan.phase.size(); ++k) {
     if (plan.phase[k].empty()) continue;
-    const int tk = c.timer.want(K_BF_GEMM) ? c.timer.begin(s) : -1;
+    const int tk = c.timer.want(kind) ? c.timer.begin(s) : -1;
     chk(launch_grouped_gemm<T>((const GTask*)(d + toff[k]), (const int64_t*)(d + soff[k]), (int)plan.phase[k].size(),
                                ntiles[k], bases, s),
         "grouped gemm");
@@ -453,16 +453,16 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
         fl += 8.0 * M * N * K;
         by += sizeof(cplx<T>) * (M * K + K * N + M * N * (t.beta ? 2.0 : 1.0));
       }
-      c.timer.end(tk, s, K_BF_GEMM, fl, by);
+      c.timer.end(tk, s, kind, fl, by);
     }
   }
   // no synchronisation: the next plan's upload is ordered after these launches on the stream
 }
 
 template void run_plan<double>(const BfPlan&, Context&, char*, const void*, void*, void*, hipStream_t,
-                               const int64_t[4]);
+                               const int64_t[4], int);
 template void run_plan<float>(const BfPlan&, Context&, char*, const void*, void*, void*, hipStream_t,
-                              const int64_t[4]);
+                              const int64_t[4], int);
 
 template <class T>
 void BfRuntime<T>::apply(const Butterfly& bf, const void* X, int64_t ldx, void* Y, int64_t ldy, int nrhs, bool adjoint,
@@ -511,8 +511,8 @@ void ExtractBatch::add(const FrontDesc* fd, const void* dense, int64_t ldd, cons
   tasks.push_back(e);
 }
 
-template <class T>
-void run_extract(BfRuntime<T>& rt, ExtractBatch& b) {
+template <class TO, class T>
+void run_extract_to(BfRuntime<T>& rt, ExtractBatch& b, bool src_single) {
   if (b.tasks.empty()) {
     b.idx.clear();
     return;
@@ -528,23 +528,33 @@ void run_extract(BfRuntime<T>& rt, ExtractBatch& b) {
   const int yb = (int)std::min<int64_t>(32, std::max<int64_t>(1, (maxe + 2047) / 2048));
   KernelTimer& tm = rt.c->timer;
   const int tk = tm.want(K_EXTRACT) ? tm.begin(rt.s()) : -1;
-  chk(launch_front_extract<T>(d_t, (int)b.tasks.size(), yb, rt.c->d_values.p, sizeof(T) == 4, rt.s()), "extract");
+  chk(launch_front_extract<TO>(d_t, (int)b.tasks.size(), yb, rt.c->d_values.p, src_single, rt.s()), "extract");
   if (tk >= 0) {
     double by = 0;  // every output entry written once, plus its row and column index
-    for (auto& e : b.tasks) by += (double)e.nr * e.nc * sizeof(cplx<T>) + 4.0 * (e.nr + e.nc);
+    for (auto& e : b.tasks) by += (double)e.nr * e.nc * sizeof(cplx<TO>) + 4.0 * (e.nr + e.nc);
     tm.end(tk, rt.s(), K_EXTRACT, 0, by);
   }
   b.tasks.clear();
   b.idx.clear();
 }
 
+template <class T>
+void run_extract(BfRuntime<T>& rt, ExtractBatch& b) {
+  run_extract_to<T, T>(rt, b, false);
+}
+
 template void run_extract<double>(BfRuntime<double>&, ExtractBatch&);
 template void run_extract<float>(BfRuntime<float>&, ExtractBatch&);
+template void run_extract_to<double, double>(BfRuntime<double>&, ExtractBatch&, bool);
+template void run_extract_to<double, float>(BfRuntime<float>&, ExtractBatch&, bool);
+template void run_extract_to<float, float>(BfRuntime<float>&, ExtractBatch&, bool);
 
 // ------------------------------------------------------------ construction
 namespace {
 
-// Interpolative decompositions of a list of blocks in one launch.
+// Interpolative decompositions of a list of blocks in one launch, in FP64
+// whatever the runtime's precision: the blocks A_i are complex<double>; the
+// expansion writes the interpolation matrices in the runtime's precision.
 template <class T>
 struct IdLevel {
   BfRuntime<T>& rt;
@@ -564,21 +574,21 @@ struct IdLevel {
       if (p[i] > 512 || q[i] > 2048)
         throw Error(BFMF_E_INVAL, "ID block too large (" + std::to_string(q[i]) + " x " + std::to_string(p[i]) + ")");
       const int maxrank = std::max(1, std::min(p[i], q[i]));
-      void* Tb = rt.scratch.take((size_t)maxrank * std::max(p[i], 1) * sizeof(cplx<T>));
+      void* Tb = rt.scratch.take((size_t)maxrank * std::max(p[i], 1) * sizeof(cplx<double>));
       tasks[i] = IdTask{A[i], std::max(q[i], 1), q[i], p[i], maxrank, d_rank + i, d_perm + po, Tb, nullptr, nullptr};
       po += p[i];
     }
     // Gram variant (FP64, tolerances where eps p / tol^2 is negligible): G_i = A_i^H A_i in one grouped GEMM
-    const bool gram = sizeof(T) == 8 && rt.tol >= 1e-4;
+    const bool gram = rt.tol >= 1e-4;
     if (gram) {
       std::vector<GTask> gt;
       for (size_t i = 0; i < nb; ++i) {
         const int pp = std::max(p[i], 1);
-        tasks[i].G = rt.scratch.take((size_t)pp * pp * sizeof(cplx<T>));
-        tasks[i].R = rt.scratch.take((size_t)tasks[i].maxrank * pp * sizeof(cplx<T>));
+        tasks[i].G = rt.scratch.take((size_t)pp * pp * sizeof(cplx<double>));
+        tasks[i].R = rt.scratch.take((size_t)tasks[i].maxrank * pp * sizeof(cplx<double>));
         if (p[i] <= 0) continue;
         GTask t = {};
-        t.a_off = (int64_t)((uintptr_t)A[i] / sizeof(cplx<T>));
+        t.a_off = (int64_t)((uintptr_t)A[i] / sizeof(cplx<double>));
         t.lda = std::max(q[i], 1);
         t.opA = OP_C;
         t.abase = 4;
@@ -586,7 +596,7 @@ struct IdLevel {
         t.ldb = t.lda;
         t.opB = OP_N;
         t.bbase = 4;
-        t.c_off = (int64_t)((uintptr_t)tasks[i].G / sizeof(cplx<T>));
+        t.c_off = (int64_t)((uintptr_t)tasks[i].G / sizeof(cplx<double>));
         t.ldc = p[i];
         t.cbase = 4;
         t.M = p[i];
@@ -600,7 +610,7 @@ struct IdLevel {
         BfPlan gp;
         gp.phase.push_back(gt);
         const int64_t lim[4] = {0, 0, 0, 0};
-        run_plan<T>(gp, *rt.c, nullptr, nullptr, nullptr, nullptr, s, lim);
+        run_plan<double>(gp, *rt.c, nullptr, nullptr, nullptr, nullptr, s, lim, K_ID);
       }
     }
     IdTask* dt = (IdTask*)upload_tmp(rt, tasks);
@@ -610,15 +620,15 @@ struct IdLevel {
     KernelTimer& tm = rt.c->timer;
     const int tk = tm.want(K_ID) ? tm.begin(s) : -1;
     if (gram)
-      chk(launch_gram_id<T>(dt, (int)nb, rt.tol, s), "gram id");
+      chk(launch_gram_id<double>(dt, (int)nb, rt.tol, s), "gram id");
     else
-      chk(launch_cpqr_id<T>(dt, (int)nb, rt.tol, s), "cpqr");
+      chk(launch_cpqr_id<double>(dt, (int)nb, rt.tol, s), "cpqr");
     if (tk >= 0) {
       double fl = 0, by = 0;  // pivoted QR of q x p truncated at rank k ~ min(p, q): 8 q p k flops, A read and written
       for (size_t i = 0; i < nb; ++i) {
         const double qq = q[i], pp = p[i], kk = std::min(q[i], p[i]);
         fl += 8.0 * qq * pp * kk;
-        by += 2.0 * sizeof(cplx<T>) * qq * pp;
+        by += 2.0 * sizeof(cplx<double>) * qq * pp;
       }
       tm.end(tk, s, K_ID, fl, by);
     }
@@ -882,7 +892,7 @@ void bf_entry_eval_batch(BfRuntime<T>& rt, const std::vector<EntryJob<T>*>& jobs
         std::vector<int32_t> cols;
         j->ps->columns(sb.cand, bf.ts.beg(L - l, v), bf.ts.end(L - l, v), cols);
         const int pp = (int)sb.cand.size(), qq = (int)cols.size();
-        void* a = rt.scratch.take((size_t)std::max(pp * qq, 1) * sizeof(cplx<T>));
+        void* a = rt.scratch.take((size_t)std::max(pp * qq, 1) * sizeof(cplx<double>));
         j->src->request(eb, sb.cand, cols, a, std::max(qq, 1), true);  // A = K(rows, cols)^T, q x p
         A.push_back(a);
         q.push_back(qq);
@@ -891,7 +901,7 @@ void bf_entry_eval_batch(BfRuntime<T>& rt, const std::vector<EntryJob<T>*>& jobs
       }
     }
     if (act.empty()) break;
-    run_extract(rt, eb);
+    run_extract_to<double>(rt, eb, false);
     IdLevel<T> idl(rt);
     std::vector<int> rank;
     std::vector<std::vector<int32_t>> perm;
@@ -921,7 +931,7 @@ void bf_entry_eval_batch(BfRuntime<T>& rt, const std::vector<EntryJob<T>*>& jobs
         std::vector<int32_t> rows;
         j->ps->rows(sb.cand, bf.to.beg(l, t), bf.to.end(l, t), rows);
         const int pp = (int)sb.cand.size(), qq = (int)rows.size();
-        void* a = rt.scratch.take((size_t)std::max(pp * qq, 1) * sizeof(cplx<T>));
+        void* a = rt.scratch.take((size_t)std::max(pp * qq, 1) * sizeof(cplx<double>));
         j->src->request(eb, rows, sb.cand, a, std::max(qq, 1), false);  // A = K(rows, cols), q x p
         A.push_back(a);
         q.push_back(qq);
@@ -930,7 +940,7 @@ void bf_entry_eval_batch(BfRuntime<T>& rt, const std::vector<EntryJob<T>*>& jobs
       }
     }
     if (act.empty()) break;
-    run_extract(rt, eb);
+    run_extract_to<double>(rt, eb, false);
     IdLevel<T> idl(rt);
     std::vector<int> rank;
     std::vector<std::vector<int32_t>> perm;
@@ -1046,7 +1056,7 @@ void random_once_batch(BfRuntime<T>& rt, const std::vector<RandomJob<T>*>& jobs)
         std::vector<int32_t> grp(S);
         for (int kk = 0; kk < S; ++kk) grp[kk] = sk[ji].lcol0[l] + v * S + kk;
         const int pp = (int)sb.cand.size();
-        void* a = rt.scratch.take((size_t)std::max(pp * S, 1) * sizeof(cplx<T>));
+        void* a = rt.scratch.take((size_t)std::max(pp * S, 1) * sizeof(cplx<double>));
         eb.add(nullptr, sk[ji].Y, std::max(j.to.n, 1), sb.cand, 0, grp, 0, a, S, true);  // A = Y(rows, group)^T
         A.push_back(a);
         q.push_back(S);
@@ -1056,7 +1066,7 @@ void random_once_batch(BfRuntime<T>& rt, const std::vector<RandomJob<T>*>& jobs)
       }
     }
     if (act.empty()) break;
-    run_extract(rt, eb);
+    run_extract_to<double>(rt, eb, sizeof(T) == 4);  // sketch rows, to FP64 for the ID
     IdLevel<T> idl(rt);
     std::vector<int> rank;
     std::vector<std::vector<int32_t>> perm;
@@ -1089,7 +1099,7 @@ void random_once_batch(BfRuntime<T>& rt, const std::vector<RandomJob<T>*>& jobs)
         std::vector<int32_t> grp(S);
         for (int kk = 0; kk < S; ++kk) grp[kk] = sk[ji].rcol0[l] + t * S + kk;
         const int pp = (int)sb.cand.size();
-        void* a = rt.scratch.take((size_t)std::max(pp * S, 1) * sizeof(cplx<T>));
+        void* a = rt.scratch.take((size_t)std::max(pp * S, 1) * sizeof(cplx<double>));
         eb.add(nullptr, sk[ji].Z, std::max(j.ts.n, 1), sb.cand, 0, grp, 0, a, S, true);  // A = Z(cols, group)^T
         A.push_back(a);
         q.push_back(S);
@@ -1099,7 +1109,7 @@ void random_once_batch(BfRuntime<T>& rt, const std::vector<RandomJob<T>*>& jobs)
       }
     }
     if (act.empty()) break;
-    run_extract(rt, eb);
+    run_extract_to<double>(rt, eb, sizeof(T) == 4);
     IdLevel<T> idl(rt);
     std::vector<int> rank;
     std::vector<std::vector<int32_t>> perm;
@@ -1161,7 +1171,7 @@ void random_once_batch(BfRuntime<T>& rt, const std::vector<RandomJob<T>*>& jobs)
       eb.add(nullptr, Ysrc, std::max(m, 1), bf.Ob[lc][blk], 0, grp, 0, ws + c.ws_off + c.yc_off[blk], r, false);
     }
   }
-  run_extract(rt, eb);
+  run_extract_to<T>(rt, eb, sizeof(T) == 4);
   // every allocation first: the pool may move while it grows
   for (size_t ji = 0; ji < nj; ++ji) {
     Butterfly& bf = *jobs[ji]->out;

@@ -124,7 +124,7 @@ BfPlan make_plan(const std::vector<BfCall>& calls, bool adjoint, int nrhs, int64
 // operand footprint is checked against it on the host before any launch.
 template <class T>
 void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y, void* ws, hipStream_t s,
-              const int64_t lim[4]);
+              const int64_t lim[4], int kind = K_BF_GEMM);
 
 // ------------------------------------------------------------- operators
 // Y = alpha op(A) X + beta Y for a linear operator A (m x n), nrhs columns.
@@ -169,6 +169,11 @@ struct ExtractBatch {
   void add(const FrontDesc* fd, const void* dense, int64_t ldd, const std::vector<int32_t>& rows, int r0,
            const std::vector<int32_t>& cols, int c0, void* out, int64_t ldo, bool trans);
 };
+// Entries written as complex<TO>; src_single: the dense sources (and the
+// contribution blocks) of the batch are complex<float>, else complex<double>.
+template <class TO, class T>
+void run_extract_to(BfRuntime<T>& rt, ExtractBatch& b, bool src_single);
+// front or FP64 dense sources, entries in the runtime's precision
 template <class T>
 void run_extract(BfRuntime<T>& rt, ExtractBatch& b);
 

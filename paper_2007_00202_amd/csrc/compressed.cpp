@@ -363,6 +363,9 @@ void hodbf_inv_apply(BfRuntime<T>& rt, const Hodbf<T>& h, int node, const void* 
 template void hodbf_apply<double>(BfRuntime<double>&, const Hodbf<double>&, const void*, int64_t, void*, int64_t, int);
 template void hodbf_inv_apply<double>(BfRuntime<double>&, const Hodbf<double>&, int, const void*, int64_t, void*,
                                       int64_t, int, bool);
+template void hodbf_apply<float>(BfRuntime<float>&, const Hodbf<float>&, const void*, int64_t, void*, int64_t, int);
+template void hodbf_inv_apply<float>(BfRuntime<float>&, const Hodbf<float>&, int, const void*, int64_t, void*,
+                                     int64_t, int, bool);
 
 // ------------------------------------------------------------ BF_SMW
 namespace {
@@ -395,7 +398,8 @@ void smw_dense_batch(BfRuntime<T>& rt, const std::vector<SmwJob<T>*>& jobs, int*
     eoff[i] = (int64_t)(rt.pool.alloc((size_t)hns[i] * hns[i] * sizeof(cplx<T>), s) / sizeof(cplx<T>));
   }
   std::vector<FrontDesc> fds(nj);
-  std::vector<cplx<T>*> Fs(nj), Is(nj);
+  std::vector<cplx<double>*> Fs(nj);  // the bordered fronts, factored in FP64
+  std::vector<cplx<T>*> Is(nj);
   for (size_t i = 0; i < nj; ++i) {
     const int n = hns[i], N2 = hn[i];
     cplx<T>* F = (cplx<T>*)rt.scratch.take((size_t)N2 * N2 * sizeof(cplx<T>));
@@ -407,23 +411,28 @@ void smw_dense_batch(BfRuntime<T>& rt, const std::vector<SmwJob<T>*>& jobs, int*
     ochk(launch_set_eye<T>(F + n, N2, n, n, 0, -1.0, s), "border");                  // F21 = -I
     ochk(launch_set_eye<T>(I, n, n, n, 0, 1.0, s), "identity");
     jobs[i]->Kfull->apply(I, n, F, N2, n, false, 1.0, 1);  // F11 = I + K
+    cplx<double>* F64 = (cplx<double>*)F;
+    if (sizeof(T) != 8) {  // pivot blocks in FP64
+      F64 = (cplx<double>*)rt.scratch.take((size_t)N2 * N2 * sizeof(cplx<double>));
+      ochk(launch_convert<double, T>(F64, N2, F, N2, N2, N2, s), "border to FP64");
+    }
     FrontDesc& fd = fds[i];
     std::memset(&fd, 0, sizeof(fd));
-    fd.F = F;
+    fd.F = F64;
     fd.n = N2;
     fd.ns = n;
     fd.front = -1;
     fd.piv = piv;
-    Fs[i] = F;
+    Fs[i] = F64;
     Is[i] = I;
   }
   const FrontDesc* d_fd = (const FrontDesc*)up(rt, fds);
-  ochk(launch_partial_lu<T>(d_fd, (int)nj, hn.data(), hns.data(), d_status, s), "smw dense lu");
-  ochk(launch_schur<T>(d_fd, (int)nj, hn.data(), hns.data(), s), "smw dense schur");
+  ochk(launch_partial_lu<double>(d_fd, (int)nj, hn.data(), hns.data(), d_status, s), "smw dense lu");
+  ochk(launch_schur<double>(d_fd, (int)nj, hn.data(), hns.data(), s), "smw dense schur");
   for (size_t i = 0; i < nj; ++i) {
     const int n = hns[i], N2 = hn[i];
     cplx<T>* X = (cplx<T>*)(rt.pool_base() + eoff[i] * sizeof(cplx<T>));
-    ochk(launch_axpby<T>(X, n, Fs[i] + n + (size_t)n * N2, N2, n, n, 1.0, 0.0, s), "copy");  // M^-1
+    ochk(launch_convert<T, double>(X, n, Fs[i] + n + (size_t)n * N2, N2, n, n, s), "copy");  // M^-1
     ochk(launch_axpby<T>(X, n, Is[i], n, n, n, -1.0, 1.0, s), "minus identity");
     jobs[i]->res.dense_off = eoff[i];
   }
@@ -552,31 +561,54 @@ struct CompState {
 };
 
 template struct CompState<double>;
+template struct CompState<float>;
+
+// The compressed-front state of a handle, in the precision of the last
+// factorization: complex128 throughout, or complex64 butterflies with FP64
+// pivot blocks, decompositions, contribution blocks and solve vectors.
+struct CompHolder {
+  bool single = false;
+  std::unique_ptr<CompState<double>> d;
+  std::unique_ptr<CompState<float>> f;
+};
 
 void* comp_state_create(Context& c) {
-  auto* st = new CompState<double>();
-  st->rt.c = &c;
-  return st;
+  (void)c;
+  return new CompHolder();
 }
 
-void comp_state_destroy(void* p) { delete (CompState<double>*)p; }
+void comp_state_destroy(void* p) { delete (CompHolder*)p; }
+
+template <class T>
+static void reset_state(CompState<T>& st, Context& c, int nfronts) {
+  st.fronts.clear();
+  st.fronts.resize(nfronts);
+  st.rt.c = &c;
+  st.rt.pool.reset();
+  st.rt.tol = c.fopts.tol;
+  st.rt.samples = c.fopts.samples > 0 ? c.fopts.samples : 64;
+  st.rt.seed = c.fopts.seed;
+  st.rt.stream_id = 0;
+  st.rt.max_rank_seen = 0;
+  st.rt.sample_hint.clear();
+  st.rt.batch = c.fopts.batched != 0;
+  if (!st.status.p) {
+    HIPCHK(hipMalloc(&st.status.p, 16));
+    st.status.bytes = 16;
+  }
+}
 
 void comp_state_reset(void* p, Context& c, int nfronts) {
-  auto* st = (CompState<double>*)p;
-  st->fronts.clear();
-  st->fronts.resize(nfronts);
-  st->rt.c = &c;
-  st->rt.pool.reset();
-  st->rt.tol = c.fopts.tol;
-  st->rt.samples = c.fopts.samples > 0 ? c.fopts.samples : 64;
-  st->rt.seed = c.fopts.seed;
-  st->rt.stream_id = 0;
-  st->rt.max_rank_seen = 0;
-  st->rt.sample_hint.clear();
-  st->rt.batch = c.fopts.batched != 0;
-  if (!st->status.p) {
-    HIPCHK(hipMalloc(&st->status.p, 16));
-    st->status.bytes = 16;
+  auto* h = (CompHolder*)p;
+  h->single = c.fopts.precision == BFMF_C64_MIXED;
+  if (h->single) {
+    h->d.reset();  // release the other precision's pools
+    if (!h->f) h->f = std::make_unique<CompState<float>>();
+    reset_state(*h->f, c, nfronts);
+  } else {
+    h->f.reset();
+    if (!h->d) h->d = std::make_unique<CompState<double>>();
+    reset_state(*h->d, c, nfronts);
   }
 }
 
@@ -651,19 +683,18 @@ struct FrontWork {
 // assembly tree: d_fds[i] is the device descriptor of fr[i], cbs[i] receives
 // its contribution block (nu x nu, ld nu).  With batching every phase runs
 // over all fronts of the level at once.
-void factor_compressed_level(void* state, Context& c, const std::vector<int>& fr,
-                             const std::vector<const FrontDesc*>& d_fds, const std::vector<void*>& cbs) {
-  typedef double T;
-  auto* st = (CompState<T>*)state;
+template <class T>
+static void factor_level(CompState<T>* st, Context& c, const std::vector<int>& fr,
+                         const std::vector<const FrontDesc*>& d_fds, const std::vector<void*>& cbs) {
   BfRuntime<T>& rt = st->rt;
   if (fr.empty()) return;
   if (!rt.batch && fr.size() > 1) {
-    for (size_t i = 0; i < fr.size(); ++i) factor_compressed_level(state, c, {fr[i]}, {d_fds[i]}, {cbs[i]});
+    for (size_t i = 0; i < fr.size(); ++i) factor_level<T>(st, c, {fr[i]}, {d_fds[i]}, {cbs[i]});
     return;
   }
   const Symbolic& sy = c.sym;
   hipStream_t s = rt.s();
-  int* d_status = st->status.as<int>();
+  int* d_status = (int*)st->status.p;
   ochk(hipMemsetAsync(d_status, 0, 16, s), "status");
   auto clock = [] { return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count(); };
   double tph[6] = {clock(), 0, 0, 0, 0, 0};
@@ -762,18 +793,40 @@ void factor_compressed_level(void* state, Context& c, const std::vector<int>& fr
         if (nd.left < 0) nd.inv_off = (int64_t)(rt.pool.alloc((size_t)nd.size() * nd.size() * sizeof(cplx<T>), s) /
                                                 sizeof(cplx<T>));
     std::vector<InvTask> it;
-    for (auto& w : W)
-      for (auto& nd : w->cf->f11.nodes)
-        if (nd.left < 0) {
-          ochk(launch_axpby<T>(rt.pool_base() + nd.inv_off * sizeof(cplx<T>), nd.size(),
-                               rt.pool_base() + nd.leaf_off * sizeof(cplx<T>), nd.size(), nd.size(), nd.size(), 1.0, 0.0,
-                               s),
-               "leaf copy");
-          it.push_back(InvTask{rt.pool_base() + nd.inv_off * sizeof(cplx<T>), std::max(nd.size(), 1), nd.size(), 0});
-        }
     auto mk = rt.scratch.mark();
-    void* d_it = up(rt, it);
-    ochk(launch_leaf_inverse<T>(d_it, (int)it.size(), d_status, s), "leaf inverse");
+    if (sizeof(T) == 8) {  // invert the leaves in place of a copy
+      for (auto& w : W)
+        for (auto& nd : w->cf->f11.nodes)
+          if (nd.left < 0) {
+            ochk(launch_axpby<T>(rt.pool_base() + nd.inv_off * sizeof(cplx<T>), nd.size(),
+                                 rt.pool_base() + nd.leaf_off * sizeof(cplx<T>), nd.size(), nd.size(), nd.size(), 1.0,
+                                 0.0, s),
+                 "leaf copy");
+            it.push_back(InvTask{rt.pool_base() + nd.inv_off * sizeof(cplx<T>), std::max(nd.size(), 1), nd.size(), 0});
+          }
+      void* d_it = up(rt, it);
+      ochk(launch_leaf_inverse<double>(d_it, (int)it.size(), d_status, s), "leaf inverse");
+    } else {  // pivot blocks in FP64: extract the leaves again in FP64, invert, store in complex64
+      ExtractBatch eb;
+      std::vector<std::pair<void*, HodbfNode<T>*>> tmp;
+      for (auto& w : W)
+        for (auto& nd : w->cf->f11.nodes)
+          if (nd.left < 0) {
+            void* d = rt.scratch.take((size_t)std::max(nd.size(), 1) * nd.size() * sizeof(cplx<double>));
+            std::vector<int32_t> r(nd.size());
+            for (int k = 0; k < nd.size(); ++k) r[k] = nd.beg + k;
+            eb.add(w->d_fd, nullptr, 0, r, 0, r, 0, d, std::max(1, nd.size()), false);
+            it.push_back(InvTask{d, std::max(nd.size(), 1), nd.size(), 0});
+            tmp.push_back({d, &nd});
+          }
+      run_extract_to<double>(rt, eb, false);
+      void* d_it = up(rt, it);
+      ochk(launch_leaf_inverse<double>(d_it, (int)it.size(), d_status, s), "leaf inverse");
+      for (auto& t : tmp)
+        ochk(launch_convert<T, double>(rt.pool_base() + t.second->inv_off * sizeof(cplx<T>), t.second->size(), t.first,
+                                       t.second->size(), t.second->size(), t.second->size(), s),
+             "leaf convert");
+    }
     rt.scratch.release(mk);
   }
   int H = 0;
@@ -908,16 +961,24 @@ void factor_compressed_level(void* state, Context& c, const std::vector<int>& fr
       for (int k = 0; k < nu; ++k) r[k] = k;
       eb.add(w->d_fd, nullptr, 0, r, ns, r, ns, w->cb, nu, false);
     }
-    run_extract<T>(rt, eb);
+    run_extract_to<double>(rt, eb, false);  // C_nu1 (+) C_nu2 on I^u x I^u, FP64
     const int chunk = 1024;
     auto mk = rt.scratch.mark();
     cplx<T>* I = (cplx<T>*)rt.scratch.take((size_t)std::max(maxnu, 1) * chunk * sizeof(cplx<T>));
+    cplx<T>* St = sizeof(T) == 8 ? nullptr
+                                 : (cplx<T>*)rt.scratch.take((size_t)std::max(maxnu, 1) * chunk * sizeof(cplx<T>));
     for (auto& w : W) {
       const int nu = w->cf->nu;
       for (int c0 = 0; c0 < nu; c0 += chunk) {
         const int wd = std::min(chunk, nu - c0);
         ochk(launch_set_eye<T>(I, nu, nu, wd, c0, 1.0, s), "eye");
-        rt.apply(*w->cf->s, I, nu, (cplx<T>*)w->cb + (size_t)c0 * nu, nu, wd, false, -1.0, 1);
+        cplx<double>* cbc = (cplx<double>*)w->cb + (size_t)c0 * nu;  // contribution blocks stay FP64
+        if (sizeof(T) == 8) {
+          rt.apply(*w->cf->s, I, nu, cbc, nu, wd, false, -1.0, 1);
+        } else {
+          rt.apply(*w->cf->s, I, nu, St, nu, wd, false, 1.0, 0);
+          ochk(launch_axpby_mixed<double, T>(cbc, nu, St, nu, nu, wd, -1.0, 1.0, s), "cb update");
+        }
       }
     }
     rt.scratch.release(mk);
@@ -943,46 +1004,93 @@ void factor_compressed_level(void* state, Context& c, const std::vector<int>& fr
 }
 
 // ------------------------------------------------------------ sweeps
-// forward: W(0:ns) <- F11^-1 W(0:ns); W(ns:n) -= F21 W(0:ns)
-void forward_compressed(void* state, Context& c, int f, void* W, int n, int nrhs) {
-  typedef double T;
-  auto* st = (CompState<T>*)state;
-  BfRuntime<T>& rt = st->rt;
-  CompressedFront<T>& cf = *st->fronts[f];
-  cplx<T>* w = (cplx<T>*)W;
+// forward: W(0:ns) <- F11^-1 W(0:ns); W(ns:n) -= F21 W(0:ns).  W is FP64; in
+// the complex64 form the front's part goes through complex64 copies.
+template <class T>
+static void forward_front(CompState<T>& st, int f, void* W, int n, int nrhs) {
+  BfRuntime<T>& rt = st.rt;
+  CompressedFront<T>& cf = *st.fronts[f];
+  cplx<double>* w = (cplx<double>*)W;
+  hipStream_t s = rt.s();
   auto mk = rt.scratch.mark();
   cplx<T>* z = (cplx<T>*)rt.scratch.take((size_t)std::max(cf.ns, 1) * nrhs * sizeof(cplx<T>));
-  hodbf_inv_apply<T>(rt, cf.f11, 0, w, n, z, cf.ns, nrhs, false);
-  axpby<T>(rt, w, n, z, cf.ns, cf.ns, nrhs, 1.0, 0.0);
-  if (cf.nu > 0) rt.apply(*cf.f21, w, n, w + cf.ns, n, nrhs, false, -1.0, 1);
-
+  if (sizeof(T) == 8) {
+    hodbf_inv_apply<T>(rt, cf.f11, 0, w, n, z, cf.ns, nrhs, false);
+    ochk(launch_axpby<double>(w, n, z, cf.ns, cf.ns, nrhs, 1.0, 0.0, s), "copy");
+    if (cf.nu > 0) rt.apply(*cf.f21, w, n, w + cf.ns, n, nrhs, false, -1.0, 1);
+  } else {
+    cplx<T>* ws = (cplx<T>*)rt.scratch.take((size_t)std::max(cf.ns, 1) * nrhs * sizeof(cplx<T>));
+    ochk(launch_convert<T, double>(ws, cf.ns, w, n, cf.ns, nrhs, s), "to c64");
+    hodbf_inv_apply<T>(rt, cf.f11, 0, ws, cf.ns, z, cf.ns, nrhs, false);
+    ochk(launch_convert<double, T>(w, n, z, cf.ns, cf.ns, nrhs, s), "to c128");
+    if (cf.nu > 0) {
+      cplx<T>* t = (cplx<T>*)rt.scratch.take((size_t)std::max(cf.nu, 1) * nrhs * sizeof(cplx<T>));
+      rt.apply(*cf.f21, z, cf.ns, t, cf.nu, nrhs, false, 1.0, 0);
+      ochk(launch_axpby_mixed<double, T>(w + cf.ns, n, t, cf.nu, cf.nu, nrhs, -1.0, 1.0, s), "update");
+    }
+  }
   rt.scratch.release(mk);
-  (void)c;
 }
 
 // backward: W(0:ns) -= F11^-1 F12 W(ns:n)   (W(ns:n) already holds x(I^u))
-void backward_compressed(void* state, Context& c, int f, void* W, int n, int nrhs) {
-  typedef double T;
-  auto* st = (CompState<T>*)state;
-  BfRuntime<T>& rt = st->rt;
-  CompressedFront<T>& cf = *st->fronts[f];
-  cplx<T>* w = (cplx<T>*)W;
+template <class T>
+static void backward_front(CompState<T>& st, int f, void* W, int n, int nrhs) {
+  BfRuntime<T>& rt = st.rt;
+  CompressedFront<T>& cf = *st.fronts[f];
+  cplx<double>* w = (cplx<double>*)W;
   if (cf.nu == 0) return;
+  hipStream_t s = rt.s();
   auto mk = rt.scratch.mark();
   cplx<T>* t = (cplx<T>*)rt.scratch.take((size_t)std::max(cf.ns, 1) * nrhs * sizeof(cplx<T>));
   cplx<T>* t2 = (cplx<T>*)rt.scratch.take((size_t)std::max(cf.ns, 1) * nrhs * sizeof(cplx<T>));
-  rt.apply(*cf.f12, w + cf.ns, n, t, cf.ns, nrhs, false, 1.0, 0);
+  if (sizeof(T) == 8) {
+    rt.apply(*cf.f12, w + cf.ns, n, t, cf.ns, nrhs, false, 1.0, 0);
+  } else {
+    cplx<T>* u = (cplx<T>*)rt.scratch.take((size_t)std::max(cf.nu, 1) * nrhs * sizeof(cplx<T>));
+    ochk(launch_convert<T, double>(u, cf.nu, w + cf.ns, n, cf.nu, nrhs, s), "to c64");
+    rt.apply(*cf.f12, u, cf.nu, t, cf.ns, nrhs, false, 1.0, 0);
+  }
   hodbf_inv_apply<T>(rt, cf.f11, 0, t, cf.ns, t2, cf.ns, nrhs, false);
-  axpby<T>(rt, w, n, t2, cf.ns, cf.ns, nrhs, -1.0, 1.0);
-
+  ochk(launch_axpby_mixed<double, T>(w, n, t2, cf.ns, cf.ns, nrhs, -1.0, 1.0, s), "update");
   rt.scratch.release(mk);
+}
+
+void factor_compressed_level(void* state, Context& c, const std::vector<int>& fronts,
+                             const std::vector<const FrontDesc*>& d_fds, const std::vector<void*>& cbs) {
+  auto* h = (CompHolder*)state;
+  if (h->single)
+    factor_level<float>(h->f.get(), c, fronts, d_fds, cbs);
+  else
+    factor_level<double>(h->d.get(), c, fronts, d_fds, cbs);
+}
+
+void forward_compressed(void* state, Context& c, int f, void* W, int n, int nrhs) {
+  auto* h = (CompHolder*)state;
   (void)c;
+  if (h->single)
+    forward_front<float>(*h->f, f, W, n, nrhs);
+  else
+    forward_front<double>(*h->d, f, W, n, nrhs);
+}
+
+void backward_compressed(void* state, Context& c, int f, void* W, int n, int nrhs) {
+  auto* h = (CompHolder*)state;
+  (void)c;
+  if (h->single)
+    backward_front<float>(*h->f, f, W, n, nrhs);
+  else
+    backward_front<double>(*h->d, f, W, n, nrhs);
 }
 
 void compressed_stats(void* state, double& bytes, int& maxrank) {
-  auto* st = (CompState<double>*)state;
-  bytes = (double)st->rt.pool.used;
-  maxrank = st->rt.max_rank_seen;
+  auto* h = (CompHolder*)state;
+  if (h->single) {
+    bytes = (double)h->f->rt.pool.used;
+    maxrank = h->f->rt.max_rank_seen;
+  } else {
+    bytes = (double)h->d->rt.pool.used;
+    maxrank = h->d->rt.max_rank_seen;
+  }
 }
 
 }  // namespace bfmf

@@ -355,15 +355,17 @@ __global__ void id_expand_kernel(const IdTask* __restrict__ tasks, void* const* 
   const int p = tk.p, rank = *tk.rank;
   cplx<T>* U = (cplx<T>*)outs[blockIdx.x];
   const int64_t ld = ldo[blockIdx.x];
-  const cplx<T>* Tm = (const cplx<T>*)tk.T;
+  const cplx<double>* Tm = (const cplx<double>*)tk.T;  // decompositions are computed in FP64
   const int ldt = tk.maxrank;
   for (int e = threadIdx.x; e < p * rank; e += blockDim.x) {
     const int row = e % p, col = e / p;  // position in the pivoted order, basis column
     cplx<T> val;
-    if (row < rank)
+    if (row < rank) {
       val = cplx<T>{(T)(row == col ? 1 : 0), 0};
-    else
-      val = Tm[col + (int64_t)(row - rank) * ldt];
+    } else {
+      const cplx<double> t = Tm[col + (int64_t)(row - rank) * ldt];
+      val = cplx<T>{(T)t.re, (T)t.im};
+    }
     if (conj_out) val.im = -val.im;
     const int r = tk.perm[row];
     if (transpose_out)
@@ -387,8 +389,9 @@ __global__ __launch_bounds__(256) void front_extract_kernel(const ExtractTask* _
     const int ii = (int)(e % nr), jj = (int)(e / nr);
     const int i = tk.rows[ii], j = tk.cols[jj];
     cplx<T>* dst = tk.trans ? out + jj + (int64_t)ii * tk.ldo : out + ii + (int64_t)jj * tk.ldo;
-    if (tk.dense) {
-      *dst = ((const cplx<T>*)tk.dense)[i + (int64_t)j * tk.ldd];
+    if (tk.dense) {  // dense source of the launch's source type
+      const TC v = ((const TC*)tk.dense)[i + (int64_t)j * tk.ldd];
+      *dst = cplx<T>{(T)v.re, (T)v.im};
       continue;
     }
     double vr = 0, vi = 0;
@@ -657,6 +660,23 @@ __global__ void set_eye_kernel(cplx<T>* __restrict__ Y, int64_t ldy, int64_t m, 
     Y[i + (int64_t)c * ldy] = cplx<T>{(T)(i == (int64_t)c + off ? v : 0.0), (T)0};
 }
 
+// Y (T1) = a X (T2) + b Y on an m x ncol block (b = 0 overwrites)
+template <class T1, class T2>
+__global__ void axpby_mixed_kernel(cplx<T1>* __restrict__ Y, int64_t ldy, const cplx<T2>* __restrict__ X, int64_t ldx,
+                                   int64_t m, double a, double b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= m) return;
+  const cplx<T2> x = X[i + (int64_t)c * ldx];
+  double yr = 0, yi = 0;
+  if (b != 0) {
+    const cplx<T1> y = Y[i + (int64_t)c * ldy];
+    yr = b * (double)y.re;
+    yi = b * (double)y.im;
+  }
+  Y[i + (int64_t)c * ldy] = cplx<T1>{(T1)(a * (double)x.re + yr), (T1)(a * (double)x.im + yi)};
+}
+
 // Y (T1) = X (T2), elementwise conversion of an m x n block
 template <class T1, class T2>
 __global__ void convert_kernel(cplx<T1>* __restrict__ Y, int64_t ldy, const cplx<T2>* __restrict__ X, int64_t ldx,
@@ -709,11 +729,11 @@ hipError_t launch_id_expand(const IdTask* d_tasks, int ntasks, void* const* d_ou
 }
 
 template <class T>
-hipError_t launch_front_extract(const ExtractTask* d_tasks, int ntasks, int yblocks, const void* values, bool cb_single,
+hipError_t launch_front_extract(const ExtractTask* d_tasks, int ntasks, int yblocks, const void* values, bool src_single,
                                 hipStream_t s) {
   if (ntasks == 0) return hipSuccess;
   dim3 grid(ntasks, yblocks > 0 ? yblocks : 1);
-  if (cb_single)
+  if (src_single)
     hipLaunchKernelGGL((front_extract_kernel<T, cplx<float>>), grid, dim3(256), 0, s, d_tasks,
                        (const cplx<double>*)values);
   else
@@ -772,6 +792,15 @@ hipError_t launch_set_eye(void* Y, int64_t ldy, int64_t m, int ncol, int64_t off
 }
 
 template <class T1, class T2>
+hipError_t launch_axpby_mixed(void* Y, int64_t ldy, const void* X, int64_t ldx, int64_t m, int ncol, double a,
+                              double b, hipStream_t s) {
+  if (m == 0 || ncol == 0) return hipSuccess;
+  hipLaunchKernelGGL((axpby_mixed_kernel<T1, T2>), dim3((unsigned)((m + 255) / 256), ncol), dim3(256), 0, s,
+                     (cplx<T1>*)Y, ldy, (const cplx<T2>*)X, ldx, m, a, b);
+  return hipGetLastError();
+}
+
+template <class T1, class T2>
 hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int64_t m, int ncol, hipStream_t s) {
   if (m == 0 || ncol == 0) return hipSuccess;
   hipLaunchKernelGGL((convert_kernel<T1, T2>), dim3((unsigned)((m + 255) / 256), ncol), dim3(256), 0, s,
@@ -795,6 +824,12 @@ hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int6
   template hipError_t launch_set_eye<T>(void*, int64_t, int64_t, int, int64_t, double, hipStream_t);
 INST(double)
 INST(float)
+template hipError_t launch_axpby_mixed<double, float>(void*, int64_t, const void*, int64_t, int64_t, int, double,
+                                                      double, hipStream_t);
+template hipError_t launch_axpby_mixed<float, double>(void*, int64_t, const void*, int64_t, int64_t, int, double,
+                                                      double, hipStream_t);
+template hipError_t launch_axpby_mixed<double, double>(void*, int64_t, const void*, int64_t, int64_t, int, double,
+                                                       double, hipStream_t);
 template hipError_t launch_convert<double, float>(void*, int64_t, const void*, int64_t, int64_t, int, hipStream_t);
 template hipError_t launch_convert<float, double>(void*, int64_t, const void*, int64_t, int64_t, int, hipStream_t);
 template hipError_t launch_convert<double, double>(void*, int64_t, const void*, int64_t, int64_t, int, hipStream_t);

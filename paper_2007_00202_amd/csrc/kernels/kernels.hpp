@@ -92,7 +92,7 @@ hipError_t launch_id_expand(const IdTask* d_tasks, int ntasks, void* const* d_ou
                             bool transpose_out, bool conj_out, hipStream_t s);
 // submatrices of a front (A entries (+) children blocks) or of a dense matrix
 template <class T>
-hipError_t launch_front_extract(const ExtractTask* d_tasks, int ntasks, int yblocks, const void* values, bool cb_single,
+hipError_t launch_front_extract(const ExtractTask* d_tasks, int ntasks, int yblocks, const void* values, bool src_single,
                                 hipStream_t s);
 // complex Gaussian probes (Philox4x32-10): column c nonzero on rows [gbeg[c/width], gend[c/width])
 template <class T>
@@ -118,6 +118,10 @@ hipError_t launch_set_eye(void* Y, int64_t ldy, int64_t m, int ncol, int64_t off
 // Y (complex<T1>) = X (complex<T2>)
 template <class T1, class T2>
 hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int64_t m, int ncol, hipStream_t s);
+// Y (complex<T1>) = a X (complex<T2>) + b Y, arithmetic in FP64 (b = 0 overwrites)
+template <class T1, class T2>
+hipError_t launch_axpby_mixed(void* Y, int64_t ldy, const void* X, int64_t ldx, int64_t m, int ncol, double a,
+                              double b, hipStream_t s);
 
 struct SolveTask {
   void* A;

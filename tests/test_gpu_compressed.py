@@ -63,3 +63,48 @@ def test_nested_compressed_fronts_and_tolerance_trend(gpu_lib):
         assert np.linalg.norm(Mx - x_or) / np.linalg.norm(x_or) <= 1000 * tol
         s.close()
     assert iters[1] <= iters[0]
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_helmholtz24_mixed_precision(gpu_lib, batched):
+    """Complex64 butterflies and sketches, FP64 pivot blocks and GMRES: the same
+    bound against the FP64 oracle, and the preconditioner within a small factor
+    of the complex128 one."""
+    p = make_problem("helmholtz24")
+    x_or = oracle_solution(p)
+    pre = {}
+    for prec in (gpu_lib.BFMF_C128, gpu_lib.BFMF_C64_MIXED):
+        s = gpu_lib.Solver(0).analyze(p.rowptr, p.colind, p.values, dims=p.dims)
+        s.factor(tol=1e-3, n_min=256, batched=batched, precision=prec)
+        st = s.stats()
+        assert st["compressed_fronts"] == 3
+        X, info = s.solve(p.rhs, true_rtol=1e-3)
+        assert info["status"] == 0
+        err = np.linalg.norm(X - x_or) / np.linalg.norm(x_or)
+        res = mf.rel_residual(p.rowptr, p.colind, p.values, X, p.rhs).max()
+        assert err <= 1e-2 and res <= 1e-3, (prec, err, res, info)
+        Mx = s.precondition(p.rhs)
+        pre[prec] = np.linalg.norm(Mx - x_or) / np.linalg.norm(x_or)
+        if prec == gpu_lib.BFMF_C64_MIXED:
+            # complex64 factors take half the bytes of complex128 ones, and less than the dense fronts
+            assert st["factor_bytes"] < st["dense_factor_bytes"]
+        s.close()
+    assert pre[gpu_lib.BFMF_C64_MIXED] <= 3 * pre[gpu_lib.BFMF_C128] + 1e-5, pre
+
+
+def test_nested_compressed_mixed_precision(gpu_lib):
+    """Nested compressed fronts in the complex64 form converge to the FP64 solution."""
+    dims = (16, 16, 16)
+    rp, ci, v, _ = helmholtz_7pt(dims, 0.05)
+    rng = rng_for("test", "rhs", (16,))
+    b = rng.standard_normal((rp.shape[0] - 1, 2)) + 1j * rng.standard_normal((rp.shape[0] - 1, 2))
+    od = nd.nd_grid(dims, leaf_max=64, sep_leaf=32)
+    fac = mf.factor(rp, ci, v, od)
+    x_or = mf.solve(fac, b)
+    s = gpu_lib.Solver(0).analyze(rp, ci, v, dims=dims, leaf_max=64, sep_leaf=32)
+    s.factor(tol=1e-3, n_min=60, batched=True, precision=gpu_lib.BFMF_C64_MIXED)
+    assert s.stats()["compressed_fronts"] >= 3
+    X, info = s.solve(b, true_rtol=1e-6, rtol=1e-9)
+    err = np.linalg.norm(X - x_or) / np.linalg.norm(x_or)
+    assert info["status"] == 0 and err <= 1e-4, (err, info)
+    s.close()
