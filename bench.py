@@ -28,11 +28,15 @@ def parse():
     ap.add_argument("--config", default="helmholtz100")
     ap.add_argument("--n", type=int, default=None, help="override the grid size")
     ap.add_argument("--form", default="batched", choices=["batched", "plain"])
-    ap.add_argument("--precision", default="c128", choices=["c128", "c64"])
+    ap.add_argument("--precision", default=None, choices=["c128", "c64"], help="default: the workload's")
     ap.add_argument("--n-min", type=int, default=None, help="compression threshold (0: exact)")
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--cpu-baseline-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison step")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-seconds", type=float, default=0.25, help="arrival window of the serving run")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="mean request arrivals per second")
     return ap.parse_args()
 
 
@@ -85,6 +89,125 @@ def _partial_solve(fac, B, nfr):
     return y
 
 
+def run_form(bfmf, s, prob, nrhs, dB, dX, steps, warmup, form, precision, n_min, tol, timing=True):
+    """Factor + GMRES solve of the RHS block, `steps` timed steps after `warmup` untimed ones."""
+    import torch
+    prec = bfmf.BFMF_C128 if precision == "c128" else bfmf.BFMF_C64_MIXED
+    so = bfmf.bfmf_default_solve_opts()
+    so.true_rtol = 1e-3
+
+    def step():
+        s.factor(tol=tol, n_min=n_min, precision=prec, batched=(form == "batched"), timing=timing)
+        o, st = bfmf.bfmf_solve_device(s.h, dB.data_ptr(), prob.n, dX.data_ptr(), prob.n, nrhs, so)
+        if st != 0:
+            raise RuntimeError(f"solve did not converge ({form}, {precision}): relres {o.relres_max}")
+        return o
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    bfmf.bfmf_reset_kernel_stats(s.h)
+    t0 = time.perf_counter()
+    fsec, ssec, iters, relres = [], [], [], []
+    for _ in range(steps):
+        o = step()
+        fsec.append(s.stats()["factor_seconds"])
+        ssec.append(o.seconds)
+        iters.append(o.iters_max)
+        relres.append(o.relres_max)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    st = s.stats()
+    return {"T": T, "value": nrhs * steps / T, "ms_per_step": 1e3 * T / steps,
+            "factor_s": float(np.mean(fsec)), "solve_s": float(np.mean(ssec)),
+            "solve_rhs_per_s": nrhs / float(np.mean(ssec)), "gmres_iters": int(max(iters)),
+            "relres_max": float(max(relres)), "factor_flops": st["factor_flops"],
+            "factor_bytes": st["factor_bytes"], "dense_factor_bytes": st["dense_factor_bytes"],
+            "max_rank": st["max_rank"], "kernels": s.kernel_stats()}
+
+
+def roofline(ks, steps, precision):
+    """Roofline of the dominant single-kernel class (estimated total time; sampled classes scaled)."""
+    single = {"assemble": "hbm", "schur_gemm": "mfma", "butterfly_gemm": "mfma", "interp_decomp": "alu",
+              "entry_extract": "hbm"}
+
+    def total_s(k):
+        v = ks[k]
+        return v["seconds"] * v["launches_all"] / max(v["launches"], 1)
+
+    dom = max(single, key=total_s)
+    kk = ks[dom]
+    per_launch_s = kk["seconds"] / max(kk["launches"], 1)
+    bound = single[dom]
+    fp_peak = PEAKS["fp64_tflops"] if precision == "c128" else PEAKS["fp32_tflops"]
+    if bound == "hbm":
+        ach = kk["bytes"] / max(kk["seconds"], 1e-30) / 1e9
+        peak, unit = PEAKS["hbm_gbs"], "GB/s"
+    else:  # MFMA contraction, or FP64 vector arithmetic (the ID kernel) against the FP64 peak
+        ach = kk["flops"] / max(kk["seconds"], 1e-30) / 1e12
+        peak, unit = (fp_peak if bound == "mfma" else PEAKS["fp64_tflops"]), "TFLOP/s"
+    rf = {"bound": bound, "kernel": dom, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+          "traffic": None, "timed_launches": kk["launches"], "launches": kk["launches_all"],
+          "avg_launch_ms": 1e3 * per_launch_s}
+    kernels = {k: {"ms": 1e3 * total_s(k) / steps, "launches": v["launches_all"] // max(steps, 1),
+                   "timed_launches": v["launches"] // max(steps, 1),
+                   "tflops": v["flops"] / max(v["seconds"], 1e-30) / 1e12,
+                   "gbs": v["bytes"] / max(v["seconds"], 1e-30) / 1e9}
+               for k, v in ks.items() if v["launches_all"]}
+    return rf, kernels
+
+
+def run_serving(bfmf, seconds, rate, max_rhs, precision):
+    """Three resident factorizations (48^3, 64^3, 80^3) answer a seeded Poisson
+    stream of point-source requests; latency from submission to solution."""
+    import threading
+    from workloads import make_problem, request_stream, rng_for
+    from workloads.configs import serving_grids
+    prec = bfmf.BFMF_C128 if precision == "c128" else bfmf.BFMF_C64_MIXED
+    solvers, sizes = [], []
+    for g in serving_grids():
+        p = make_problem("helmholtz100", n=g, nrhs=1, config_id="serving")
+        sv = bfmf.Solver(0).analyze(p.rowptr, p.colind, p.values, dims=p.dims)
+        sv.factor(tol=1e-3, n_min=1024, precision=prec, batched=True)
+        solvers.append(sv)
+        sizes.append(p.n)
+    srv = bfmf.Server(0, max_batch_rhs=max_rhs, result_bytes=24 << 30, true_rtol=1e-3)
+    ids = [srv.attach(sv) for sv in solvers]
+    stream = request_stream(rate, seconds, sizes, max_rhs, rng_for("serving", "arrivals"))
+    tickets = [None] * len(stream)
+    base = srv.clock()
+
+    def producer():
+        for k, (t, m, rows) in enumerate(stream):
+            dt = base + t - srv.clock()
+            if dt > 0:
+                time.sleep(dt)
+            tickets[k] = srv.submit_points(ids[m], rows)
+
+    th = threading.Thread(target=producer)
+    th.start()
+    infos = []
+    for k in range(len(stream)):
+        while tickets[k] is None:
+            time.sleep(0.0005)
+        infos.append(srv.wait(tickets[k]))
+    th.join()
+    srv.close()
+    for sv in solvers:
+        sv.close()
+    bad = [i for i in infos if i["status"] != 0]
+    lat = np.array([i["t_done"] - i["t_submit"] for i in infos])
+    first = min(i["t_submit"] for i in infos)
+    last = max(i["t_done"] for i in infos)
+    nrhs = sum(i["nrhs"] for i in infos)
+    return {"grids": [f"{g}^3" for g in serving_grids()], "precision": precision, "offered_req_per_s": rate,
+            "window_s": seconds, "requests": len(infos), "rhs": int(nrhs), "failed": len(bad),
+            "rhs_per_s": nrhs / (last - first), "makespan_s": last - first,
+            "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+            "mean_batch_rhs": float(np.mean([i["batch_rhs"] for i in infos])),
+            "max_iters": int(max(i["iters"] for i in infos)), "max_relres": float(max(i["relres"] for i in infos))}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -98,81 +221,41 @@ def main():
     prob = make_problem(a.config, n=a.n)
     n_min = cfg["n_min"] if a.n_min is None else a.n_min
     tol = cfg["tol"] if a.tol is None else a.tol
-    prec = bfmf.BFMF_C128 if a.precision == "c128" else bfmf.BFMF_C64_MIXED
+    precision = a.precision or cfg["precision"]
     nrhs = prob.rhs.shape[1]
     s = bfmf.Solver(0).analyze(prob.rowptr, prob.colind, prob.values, dims=prob.dims)
     dB = torch.from_numpy(np.ascontiguousarray(prob.rhs.T)).to("cuda")  # column-major (N, nrhs)
     dX = torch.zeros_like(dB)
-    so = bfmf.bfmf_default_solve_opts()
-    so.true_rtol = 1e-3
-
-    def step():
-        s.factor(tol=tol, n_min=n_min, precision=prec, batched=(a.form == "batched"), timing=True)
-        o, st = bfmf.bfmf_solve_device(s.h, dB.data_ptr(), prob.n, dX.data_ptr(), prob.n, nrhs, so)
-        return o, st
-
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    bfmf.bfmf_reset_kernel_stats(s.h)
-    t0 = time.perf_counter()
-    fsec, ssec, iters, relres = [], [], [], []
-    for _ in range(a.steps):
-        o, st = step()
-        fsec.append(s.stats()["factor_seconds"])
-        ssec.append(o.seconds)
-        iters.append(o.iters_max)
-        relres.append(o.relres_max)
-    torch.cuda.synchronize()
-    T = time.perf_counter() - t0
-    ks = s.kernel_stats()
-    st = s.stats()
-    # dominant single-kernel class by estimated total time (sampled classes scaled to all launches)
-    single = {"assemble": "hbm", "schur_gemm": "mfma", "butterfly_gemm": "mfma", "interp_decomp": "alu",
-              "entry_extract": "hbm"}
-
-    def total_s(k):
-        v = ks[k]
-        return v["seconds"] * v["launches_all"] / max(v["launches"], 1)
-
-    dom = max(single, key=total_s)
-    kk = ks[dom]
-    per_launch_s = kk["seconds"] / max(kk["launches"], 1)
-    bound = single[dom]
-    fp_peak = PEAKS["fp64_tflops"] if a.precision == "c128" else PEAKS["fp32_tflops"]
-    if bound == "hbm":
-        ach = kk["bytes"] / max(kk["seconds"], 1e-30) / 1e9
-        peak, unit = PEAKS["hbm_gbs"], "GB/s"
-    else:  # MFMA contraction, or FP64 vector arithmetic (the ID kernel) against the same FP64 peak
-        ach = kk["flops"] / max(kk["seconds"], 1e-30) / 1e12
-        peak, unit = (fp_peak if bound == "mfma" else PEAKS["fp64_tflops"]), "TFLOP/s"
+    r = run_form(bfmf, s, prob, nrhs, dB, dX, a.steps, a.warmup, a.form, precision, n_min, tol)
+    rf, kernels = roofline(r["kernels"], a.steps, precision)
     out = {
         "metric": "factor time + RHS/s at rel-residual <=1e-3",
-        "value": nrhs * a.steps / T,
+        "value": r["value"],
         "unit": "RHS/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": 1e3 * T / a.steps,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c128" if a.precision == "c128" else "c64+f64",
+        "dtype": "c128" if precision == "c128" else "c64+f64",
         "data": "synthetic",
         "config": {"workload": f"{a.config}: 3D Helmholtz 7-pt {prob.dims[0]}^3 (N={prob.n}), {nrhs} RHS",
-                   "form": a.form, "n_min": n_min, "tol": tol, "precision": a.precision},
-        "factor_s": float(np.mean(fsec)), "solve_s": float(np.mean(ssec)),
-        "solve_rhs_per_s": nrhs / float(np.mean(ssec)), "gmres_iters": int(max(iters)),
-        "relres_max": float(max(relres)),
-        "factor_tflops": st["factor_flops"] / float(np.mean(fsec)) / 1e12,
-        "roofline": {"bound": bound, "kernel": dom, "achieved": ach, "peak": peak, "unit": unit,
-                     "frac": ach / peak, "traffic": None, "timed_launches": kk["launches"],
-                     "launches": kk["launches_all"], "avg_launch_ms": 1e3 * per_launch_s},
-        "kernels": {k: {"ms": 1e3 * total_s(k) / a.steps, "launches": v["launches_all"] // max(a.steps, 1),
-                        "timed_launches": v["launches"] // max(a.steps, 1),
-                        "tflops": v["flops"] / max(v["seconds"], 1e-30) / 1e12,
-                        "gbs": v["bytes"] / max(v["seconds"], 1e-30) / 1e9}
-                    for k, v in ks.items() if v["launches_all"]},
+                   "form": a.form, "n_min": n_min, "tol": tol, "precision": precision},
+        "factor_s": r["factor_s"], "solve_s": r["solve_s"], "solve_rhs_per_s": r["solve_rhs_per_s"],
+        "gmres_iters": r["gmres_iters"], "relres_max": r["relres_max"],
+        "factor_tflops": r["factor_flops"] / r["factor_s"] / 1e12,
+        "factor_gb": r["factor_bytes"] / 1e9, "dense_factor_gb": r["dense_factor_bytes"] / 1e9,
+        "max_rank": r["max_rank"],
+        "roofline": rf,
+        "kernels": kernels,
     }
+    if not a.no_plain:  # the plain GPU form: complex128, fronts and constructions one at a time
+        p = run_form(bfmf, s, prob, nrhs, dB, dX, 1, 0, "plain", "c128", n_min, tol, timing=False)
+        out["plain"] = {"form": "plain", "precision": "c128", "value": p["value"], "factor_s": p["factor_s"],
+                        "solve_s": p["solve_s"], "gmres_iters": p["gmres_iters"], "relres_max": p["relres_max"]}
+    s.close()
+    if not a.no_serve:
+        out["serving"] = run_serving(bfmf, a.serve_seconds, a.serve_rate, 64, precision)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, a.cpu_baseline_seconds, nrhs)
-    s.close()
     print(json.dumps(out))
 
 

@@ -239,6 +239,56 @@ bfmf_status bfmf_bf_apply(bfmf_bf* b, int32_t adjoint, int32_t nrhs, const doubl
 bfmf_status bfmf_bf_info(bfmf_bf* b, int32_t* L, int32_t* max_rank, int64_t* entries);
 void bfmf_bf_destroy(bfmf_bf* b);
 
+/* ------------------------------------------------------------------ serving
+ * Several factored handles stay resident on one device and answer a stream
+ * of right-hand-side requests.  Each attached handle gets a worker thread on
+ * its own stream; the worker takes every queued request of its model that
+ * fits max_batch_rhs columns and the result arena, solves them together with
+ * one GMRES call (columns are independent: a request's result does not depend
+ * on the other requests of its batch beyond rounding), and keeps each
+ * request's solution in the arena until bfmf_server_wait fetches it.
+ * Requests arriving while a batch runs join the next batch of their model;
+ * models run concurrently.  Factors, batch workspaces and the arena are
+ * charged against hbm_budget when models are attached (E_NOMEM beyond it).
+ * A handle attached to a server must not be used by the caller afterwards,
+ * and must outlive the server.  Not for graph capture. */
+typedef struct bfmf_server_s* bfmf_server;
+typedef struct {
+    int32_t max_batch_rhs;   /* columns of one batch solve (default 64); wider requests are refused */
+    int32_t reserved0;
+    uint64_t hbm_budget;     /* bytes for all models and the arena (0: the device's free memory) */
+    uint64_t result_bytes;   /* arena for solutions awaiting bfmf_server_wait (default 4 GiB) */
+    bfmf_solve_opts solve;   /* every batch solve (default: true_rtol 1e-3) */
+} bfmf_server_opts;
+typedef struct {
+    double t_submit, t_start, t_done;  /* seconds on the server clock: queued, batch started, solution ready */
+    int32_t model, nrhs;
+    int32_t batch_rhs;                 /* columns of the batch that solved the request */
+    int32_t batch_requests;            /* requests in that batch */
+    int32_t iters;                     /* GMRES iterations of the batch (largest over its columns) */
+    int32_t status;                    /* bfmf_status of the solve */
+    double relres;                     /* largest true relative residual of the batch's columns */
+} bfmf_request_info;
+void bfmf_default_server_opts(bfmf_server_opts* o);
+bfmf_status bfmf_server_create(int32_t device, const bfmf_server_opts* o, bfmf_server* out);
+/* h: a factored handle on the server's device; model receives its id */
+bfmf_status bfmf_server_attach(bfmf_server s, bfmf_handle h, int32_t* model);
+/* A request of nrhs columns given as compressed sparse columns: column q has
+ * the entries rowind[colptr[q] .. colptr[q+1]) with interleaved complex
+ * values (host arrays, copied; duplicates summed).  Never blocks; E_INVAL
+ * for bad indices, non-finite values or nrhs > max_batch_rhs. */
+bfmf_status bfmf_server_submit(bfmf_server s, int32_t model, int32_t nrhs, const int64_t* colptr,
+                               const int64_t* rowind, const double* values, uint64_t* ticket);
+/* Blocks until the request is solved; copies its solution (n x nrhs) to X
+ * (ld ldx, host or device memory by mem; X == NULL discards it), fills info
+ * and releases the request.  Returns the solve's status. */
+bfmf_status bfmf_server_wait(bfmf_server s, uint64_t ticket, bfmf_request_info* info, double* X, int64_t ldx,
+                             int32_t mem);
+double bfmf_server_clock(bfmf_server s);
+const char* bfmf_server_last_error(bfmf_server s);
+/* stops the workers after the admitted batches; queued requests fail */
+void bfmf_server_destroy(bfmf_server s);
+
 const char* bfmf_status_str(bfmf_status s);
 /* Message of the last failed call on h; with h == NULL, of the last failed
  * call on this thread that returned no handle (bfmf_bf_compress_dense). */

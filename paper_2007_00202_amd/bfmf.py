@@ -77,6 +77,18 @@ class bfmf_stats(C.Structure):
                 ("reserved", C.c_double * 8)]
 
 
+class bfmf_server_opts(C.Structure):
+    _fields_ = [("max_batch_rhs", C.c_int32), ("reserved0", C.c_int32), ("hbm_budget", C.c_uint64),
+                ("result_bytes", C.c_uint64), ("solve", bfmf_solve_opts)]
+
+
+class bfmf_request_info(C.Structure):
+    _fields_ = [("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
+                ("model", C.c_int32), ("nrhs", C.c_int32), ("batch_rhs", C.c_int32),
+                ("batch_requests", C.c_int32), ("iters", C.c_int32), ("status", C.c_int32),
+                ("relres", C.c_double)]
+
+
 _h = C.c_void_p
 _P = C.c_void_p
 _SIGS = {
@@ -99,6 +111,14 @@ _SIGS = {
     "bfmf_bf_apply": (C.c_int, [_P, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64]),
     "bfmf_bf_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     "bfmf_bf_destroy": (None, [_P]),
+    "bfmf_default_server_opts": (None, [C.POINTER(bfmf_server_opts)]),
+    "bfmf_server_create": (C.c_int, [C.c_int32, C.POINTER(bfmf_server_opts), C.POINTER(_P)]),
+    "bfmf_server_attach": (C.c_int, [_P, _h, C.POINTER(C.c_int32)]),
+    "bfmf_server_submit": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, C.POINTER(C.c_uint64)]),
+    "bfmf_server_wait": (C.c_int, [_P, C.c_uint64, C.POINTER(bfmf_request_info), _P, C.c_int64, C.c_int32]),
+    "bfmf_server_clock": (C.c_double, [_P]),
+    "bfmf_server_last_error": (C.c_char_p, [_P]),
+    "bfmf_server_destroy": (None, [_P]),
     "bfmf_status_str": (C.c_char_p, [C.c_int]),
     "bfmf_last_error": (C.c_char_p, [_h]),
     "bfmf_destroy": (None, [_h]),
@@ -364,3 +384,79 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ serving
+def bfmf_default_server_opts():
+    o = bfmf_server_opts()
+    _lib.bfmf_default_server_opts(C.byref(o))
+    return o
+
+
+class Server:
+    """Resident factorizations answering right-hand-side requests (continuous
+    batching per model, models concurrent); see bfmf_server_* in bfmf.h."""
+
+    def __init__(self, device=0, max_batch_rhs=64, hbm_budget=0, result_bytes=4 << 30, restart=30, max_iter=300,
+                 rtol=1e-6, atol=1e-10, true_rtol=1e-3):
+        o = bfmf_default_server_opts()
+        o.max_batch_rhs, o.hbm_budget, o.result_bytes = max_batch_rhs, hbm_budget, result_bytes
+        o.solve.restart, o.solve.max_iter, o.solve.rtol = restart, max_iter, rtol
+        o.solve.atol, o.solve.true_rtol = atol, true_rtol
+        self.s = _P()
+        st = _lib.bfmf_server_create(device, C.byref(o), C.byref(self.s))
+        if st != BFMF_OK:
+            raise BfmfError(st, "server_create: " + _lib.bfmf_last_error(None).decode())
+        self.n = {}
+
+    def _err(self, st, what):
+        raise BfmfError(st, what + ": " + _lib.bfmf_server_last_error(self.s).decode())
+
+    def attach(self, solver):
+        m = C.c_int32()
+        st = _lib.bfmf_server_attach(self.s, solver.h, C.byref(m))
+        if st != BFMF_OK:
+            self._err(st, "server_attach")
+        self.n[m.value] = solver.n
+        return m.value
+
+    def submit(self, model, colptr, rowind, values):
+        """colptr (nrhs+1), rowind, complex values: the request's right-hand sides as sparse columns."""
+        colptr = np.ascontiguousarray(colptr, dtype=np.int64)
+        rowind = np.ascontiguousarray(rowind, dtype=np.int64)
+        values = np.ascontiguousarray(values, dtype=np.complex128)
+        t = C.c_uint64()
+        st = _lib.bfmf_server_submit(self.s, model, colptr.shape[0] - 1, _ptr(colptr), _ptr(rowind), _ptr(values),
+                                     C.byref(t))
+        if st != BFMF_OK:
+            self._err(st, "server_submit")
+        return t.value
+
+    def submit_points(self, model, rows, values=None):
+        """One point source per column: column q is values[q] (default 1) at row rows[q]."""
+        rows = np.asarray(rows, dtype=np.int64)
+        vals = np.ones(rows.shape[0], dtype=np.complex128) if values is None else np.asarray(values)
+        return self.submit(model, np.arange(rows.shape[0] + 1, dtype=np.int64), rows, vals)
+
+    def wait(self, ticket, out=None, device_ptr=None, ld=None):
+        """Waits for a request; its solution goes to the host array `out`
+        (n x nrhs, column-major), to device memory at device_ptr (leading
+        dimension ld), or is discarded.  Returns the request's info dict."""
+        info = bfmf_request_info()
+        if out is not None:
+            st = _lib.bfmf_server_wait(self.s, ticket, C.byref(info), _ptr(out), out.shape[0], BFMF_HOST)
+        elif device_ptr is not None:
+            st = _lib.bfmf_server_wait(self.s, ticket, C.byref(info), C.c_void_p(device_ptr), ld, BFMF_DEVICE)
+        else:
+            st = _lib.bfmf_server_wait(self.s, ticket, C.byref(info), None, 0, BFMF_HOST)
+        d = {k: getattr(info, k) for k, _ in bfmf_request_info._fields_}
+        d["status"] = st
+        return d
+
+    def clock(self):
+        return _lib.bfmf_server_clock(self.s)
+
+    def close(self):
+        if self.s:
+            _lib.bfmf_server_destroy(self.s)
+            self.s = None

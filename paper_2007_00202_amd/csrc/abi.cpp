@@ -11,8 +11,6 @@
 
 using namespace bfmf;
 
-struct bfmf_ctx : public Context {};
-
 namespace {
 
 double now_s() {

@@ -1082,6 +1082,19 @@ void backward_compressed(void* state, Context& c, int f, void* W, int n, int nrh
     backward_front<double>(*h->d, f, W, n, nrhs);
 }
 
+template <class T>
+static uint64_t state_bytes(const CompState<T>& st) {
+  uint64_t b = st.rt.pool.buf.bytes + st.status.bytes;
+  for (auto& ch : st.rt.scratch.chunks) b += ch->b.bytes;
+  return b;
+}
+
+uint64_t comp_state_bytes(void* state) {
+  auto* h = (CompHolder*)state;
+  if (!h) return 0;
+  return (h->d ? state_bytes(*h->d) : 0) + (h->f ? state_bytes(*h->f) : 0);
+}
+
 void compressed_stats(void* state, double& bytes, int& maxrank) {
   auto* h = (CompHolder*)state;
   if (h->single) {

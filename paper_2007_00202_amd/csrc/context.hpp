@@ -192,6 +192,7 @@ void factor_compressed_level(void* state, Context& c, const std::vector<int>& fr
 void forward_compressed(void* state, Context& c, int f, void* W, int n, int nrhs);
 void backward_compressed(void* state, Context& c, int f, void* W, int n, int nrhs);
 void compressed_stats(void* state, double& bytes, int& maxrank);
+uint64_t comp_state_bytes(void* state);  // device bytes held by the compressed fronts' pools
 
 // plan.cpp
 void build_plan(Context& c);
@@ -202,5 +203,10 @@ void factor_dense(Context& c);
 void ensure_workspace(Context& c, int64_t nrhs);
 void apply_preconditioner_dev(Context& c, const void* dB, int64_t ldb, void* dX, int64_t ldx, int64_t nrhs);
 int gmres_dev(Context& c, const void* dB, int64_t ldb, void* dX, int64_t ldx, int64_t nrhs, bfmf_solve_opts& o);
+// device buffers of GMRES(m) for nrhs columns (grown, never shrunk)
+void gmres_workspace(Context& c, int64_t nrhs, int m);
 
 }  // namespace bfmf
+
+// the opaque handle of the C ABI
+struct bfmf_ctx : public bfmf::Context {};

@@ -41,12 +41,12 @@ hipError_t launch_permute_out(const void* x, void* X, int64_t ldx, const int64_t
                               hipStream_t s);
 // Forward sweep over the fronts of one level (children done before).
 template <class T>
-hipError_t launch_forward_level(const FrontDesc* d_fds, int nbatch, int maxn, int maxnu, const void* y, int64_t N,
-                                int nrhs, hipStream_t s);
+hipError_t launch_forward_level(const FrontDesc* d_fds, int nbatch, int maxn, int maxnu, int maxns, const void* y,
+                                int64_t N, int nrhs, hipStream_t s);
 // Backward sweep over the fronts of one level (ancestors done before).
 template <class T>
-hipError_t launch_backward_level(const FrontDesc* d_fds, int nbatch, int maxn, int maxnu, void* x, int64_t N,
-                                 int nrhs, hipStream_t s);
+hipError_t launch_backward_level(const FrontDesc* d_fds, int nbatch, int maxn, int maxnu, int maxns, void* x,
+                                 int64_t N, int nrhs, hipStream_t s);
 
 // Gather-only steps of the sweeps (for compressed fronts, whose F11^-1, F12
 // and F21 products run as butterfly applications).
@@ -136,5 +136,9 @@ struct InvTask {
   int32_t n;
   int32_t pad;
 };
+
+// B(rows[e], cols[e]) = (vals[2e], vals[2e+1]) for e < nnz (complex128 block, ld ldb)
+hipError_t launch_scatter_nz(void* B, int64_t ldb, const int32_t* rows, const int32_t* cols, const double* vals,
+                             int64_t nnz, hipStream_t s);
 
 }  // namespace bfmf

@@ -88,6 +88,120 @@ __global__ __launch_bounds__(256) void fwd_trsv_kernel(const FrontDesc* __restri
   }
 }
 
+// ------------------------------------------------------------ blocked sweeps
+// The same substitutions with the front's right-hand sides held in LDS: a
+// workgroup takes up to `nc` columns of one front (ns <= TRSV_MAXNS), thread t
+// owns rows t, t+256, ...; each elimination step reads one column of L (U) from
+// HBM, prefetched into registers during the previous step, and costs one
+// barrier.
+constexpr int TRSV_MAXNS = 1024;
+constexpr int TRSV_LDS = 6144;  // complex<double> entries (96 KB)
+
+template <class T>
+__global__ __launch_bounds__(256) void fwd_trsv_lds_kernel(const FrontDesc* __restrict__ fds, int nrhs, int nc) {
+  const FrontDesc& fd = fds[blockIdx.x];
+  const int n = fd.n, ns = fd.ns;
+  const int c0 = blockIdx.y * nc, ncl = min(nc, nrhs - c0);
+  if (ns == 0 || ncl <= 0 || ns > TRSV_MAXNS || ns * ncl > TRSV_LDS) return;  // the host never sends these
+  __shared__ cplx<T> w[TRSV_LDS];  // w[r + c ns]
+  const cplx<T>* F = (const cplx<T>*)fd.F;
+  cplx<T>* W = (cplx<T>*)fd.W + (int64_t)c0 * n;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < ns * ncl; e += 256) w[e] = W[e % ns + (int64_t)(e / ns) * n];
+  __syncthreads();
+  if (tid < ncl)  // row interchanges, in order, one thread per column
+    for (int k = 0; k < ns; ++k) {
+      const int p = fd.piv[k];
+      if (p != k) {
+        const cplx<T> t = w[k + tid * ns];
+        w[k + tid * ns] = w[p + tid * ns];
+        w[p + tid * ns] = t;
+      }
+    }
+  cplx<T> lc[4], ln[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = tid + 256 * q;
+    lc[q] = load_or_zero(F + r, r > 0 && r < ns);
+  }
+  __syncthreads();
+  for (int j = 0; j < ns - 1; ++j) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {  // next column of L, in flight during this step
+      const int r = tid + 256 * q;
+      ln[q] = load_or_zero(F + r + (int64_t)(j + 1) * n, r > j + 1 && r < ns);
+    }
+    for (int c = 0; c < ncl; ++c) {
+      const cplx<T> wj = w[j + c * ns];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = tid + 256 * q;
+        if (r > j && r < ns) w[r + c * ns] = csub(w[r + c * ns], cmul(lc[q], wj));
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) lc[q] = ln[q];
+  }
+  for (int e = tid; e < ns * ncl; e += 256) W[e % ns + (int64_t)(e / ns) * n] = w[e];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void bwd_trsv_lds_kernel(const FrontDesc* __restrict__ fds, cplx<T>* __restrict__ x,
+                                                           int64_t N, int nrhs, int nc) {
+  const FrontDesc& fd = fds[blockIdx.x];
+  const int n = fd.n, ns = fd.ns;
+  const int c0 = blockIdx.y * nc, ncl = min(nc, nrhs - c0);
+  if (ns == 0 || ncl <= 0 || ns > TRSV_MAXNS || ns * ncl > TRSV_LDS) return;  // the host never sends these
+  __shared__ cplx<T> w[TRSV_LDS];
+  const cplx<T>* F = (const cplx<T>*)fd.F;
+  const cplx<T>* W = (const cplx<T>*)fd.W + (int64_t)c0 * n;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < ns * ncl; e += 256) w[e] = W[e % ns + (int64_t)(e / ns) * n];
+  cplx<T> uc[4], un[4];
+  cplx<T> dc = F[(ns - 1) + (int64_t)(ns - 1) * n], dn = {0, 0};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = tid + 256 * q;
+    uc[q] = load_or_zero(F + r + (int64_t)(ns - 1) * n, r < ns - 1);
+  }
+  __syncthreads();
+  for (int j = ns - 1; j >= 0; --j) {
+    if (j > 0) {  // column j-1 of U and its diagonal, in flight during this step
+      dn = F[(j - 1) + (int64_t)(j - 1) * n];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = tid + 256 * q;
+        un[q] = load_or_zero(F + r + (int64_t)(j - 1) * n, r < j - 1);
+      }
+    }
+    // every thread forms x_j = w_j / U_jj itself; w_j stays unscaled (a store here would race with
+    // the reads of other waves) and is divided when the result is written out
+    for (int c = 0; c < ncl; ++c) {
+      const cplx<T> wj = cdiv(w[j + c * ns], dc);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = tid + 256 * q;
+        if (r < j) w[r + c * ns] = csub(w[r + c * ns], cmul(uc[q], wj));
+      }
+    }
+    __syncthreads();
+    dc = dn;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) uc[q] = un[q];
+  }
+  for (int e = tid; e < ns * ncl; e += 256) {
+    const int r = e % ns;
+    x[fd.sbeg + r + (int64_t)(c0 + e / ns) * N] = cdiv(w[e], F[r + (int64_t)r * n]);
+  }
+}
+
+// columns per workgroup of the LDS sweeps for fronts of at most maxns rows (0: use the plain kernels)
+static int trsv_lds_cols(int maxns, int nrhs) {
+  if (maxns <= 0 || maxns > TRSV_MAXNS) return 0;
+  return std::max(1, std::min(nrhs, std::min(16, TRSV_LDS / maxns)));
+}
+
 // Upper substitution on W_f(0:ns, :) and scatter of the result into x.
 template <class T>
 __global__ __launch_bounds__(256) void bwd_trsv_kernel(const FrontDesc* __restrict__ fds, cplx<T>* __restrict__ x,
@@ -270,14 +384,18 @@ hipError_t launch_permute_out(const void* x, void* X, int64_t ldx, const int64_t
 }
 
 template <class T>
-hipError_t launch_forward_level(const FrontDesc* d_fds, int nbatch, int maxn, int maxnu, const void* y, int64_t N,
-                                int nrhs, hipStream_t s) {
+hipError_t launch_forward_level(const FrontDesc* d_fds, int nbatch, int maxn, int maxnu, int maxns, const void* y,
+                                int64_t N, int nrhs, hipStream_t s) {
   if (nbatch == 0) return hipSuccess;
   (void)maxnu;
   hipLaunchKernelGGL((fwd_gather_kernel<T>), dim3(blocks_for(maxn, 256), nbatch), dim3(256), 0, s, d_fds,
                      (const cplx<T>*)y, N, nrhs);
   KCHECK(hipGetLastError());
-  hipLaunchKernelGGL((fwd_trsv_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, nrhs);
+  const int nc = sizeof(T) == 8 ? trsv_lds_cols(maxns, nrhs) : 0;
+  if (nc > 0)
+    hipLaunchKernelGGL((fwd_trsv_lds_kernel<T>), dim3(nbatch, (nrhs + nc - 1) / nc), dim3(256), 0, s, d_fds, nrhs, nc);
+  else
+    hipLaunchKernelGGL((fwd_trsv_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, nrhs);
   KCHECK(hipGetLastError());
   const int tiles = (int)(blocks_for(maxn, GEMM_TM) * blocks_for(nrhs, GEMM_TN));
   hipLaunchKernelGGL((sweep_gemm_kernel<T>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs, 0);
@@ -285,8 +403,8 @@ hipError_t launch_forward_level(const FrontDesc* d_fds, int nbatch, int maxn, in
 }
 
 template <class T>
-hipError_t launch_backward_level(const FrontDesc* d_fds, int nbatch, int maxn, int maxnu, void* x, int64_t N,
-                                 int nrhs, hipStream_t s) {
+hipError_t launch_backward_level(const FrontDesc* d_fds, int nbatch, int maxn, int maxnu, int maxns, void* x,
+                                 int64_t N, int nrhs, hipStream_t s) {
   if (nbatch == 0) return hipSuccess;
   if (maxnu > 0) {
     hipLaunchKernelGGL((bwd_gather_kernel<T>), dim3(blocks_for(maxnu, 256), nbatch), dim3(256), 0, s, d_fds,
@@ -296,7 +414,12 @@ hipError_t launch_backward_level(const FrontDesc* d_fds, int nbatch, int maxn, i
     hipLaunchKernelGGL((sweep_gemm_kernel<T>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs, 1);
     KCHECK(hipGetLastError());
   }
-  hipLaunchKernelGGL((bwd_trsv_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, (cplx<T>*)x, N, nrhs);
+  const int nc = sizeof(T) == 8 ? trsv_lds_cols(maxns, nrhs) : 0;
+  if (nc > 0)
+    hipLaunchKernelGGL((bwd_trsv_lds_kernel<T>), dim3(nbatch, (nrhs + nc - 1) / nc), dim3(256), 0, s, d_fds,
+                       (cplx<T>*)x, N, nrhs, nc);
+  else
+    hipLaunchKernelGGL((bwd_trsv_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, (cplx<T>*)x, N, nrhs);
   return hipGetLastError();
 }
 
@@ -361,13 +484,28 @@ template hipError_t launch_permute_in<double>(const void*, int64_t, void*, const
 template hipError_t launch_permute_in<float>(const void*, int64_t, void*, const int64_t*, int64_t, int, hipStream_t);
 template hipError_t launch_permute_out<double>(const void*, void*, int64_t, const int64_t*, int64_t, int, hipStream_t);
 template hipError_t launch_permute_out<float>(const void*, void*, int64_t, const int64_t*, int64_t, int, hipStream_t);
-template hipError_t launch_forward_level<double>(const FrontDesc*, int, int, int, const void*, int64_t, int,
-                                                 hipStream_t);
-template hipError_t launch_forward_level<float>(const FrontDesc*, int, int, int, const void*, int64_t, int,
-                                                hipStream_t);
+template hipError_t launch_forward_level<double>(const FrontDesc*, int, int, int, int, const void*, int64_t, int, hipStream_t);
+template hipError_t launch_forward_level<float>(const FrontDesc*, int, int, int, int, const void*, int64_t, int, hipStream_t);
 template hipError_t launch_fwd_gather<double>(const FrontDesc*, int, int, const void*, int64_t, int, hipStream_t);
 template hipError_t launch_bwd_gather<double>(const FrontDesc*, int, int, const void*, int64_t, int, hipStream_t);
-template hipError_t launch_backward_level<double>(const FrontDesc*, int, int, int, void*, int64_t, int, hipStream_t);
-template hipError_t launch_backward_level<float>(const FrontDesc*, int, int, int, void*, int64_t, int, hipStream_t);
+template hipError_t launch_backward_level<double>(const FrontDesc*, int, int, int, int, void*, int64_t, int, hipStream_t);
+template hipError_t launch_backward_level<float>(const FrontDesc*, int, int, int, int, void*, int64_t, int, hipStream_t);
+
+// B(rows[e], cols[e]) = vals[e] for the nonzeros of a block of right-hand
+// sides (each (row, column) once)
+__global__ void scatter_nz_kernel(cplx<double>* __restrict__ B, int64_t ldb, const int32_t* __restrict__ rows,
+                                  const int32_t* __restrict__ cols, const double* __restrict__ vals, int64_t nnz) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  B[rows[e] + (int64_t)cols[e] * ldb] = cplx<double>{vals[2 * e], vals[2 * e + 1]};
+}
+
+hipError_t launch_scatter_nz(void* B, int64_t ldb, const int32_t* rows, const int32_t* cols, const double* vals,
+                             int64_t nnz, hipStream_t s) {
+  if (nnz <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_nz_kernel, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, (cplx<double>*)B, ldb,
+                     rows, cols, vals, nnz);
+  return hipGetLastError();
+}
 
 }  // namespace bfmf

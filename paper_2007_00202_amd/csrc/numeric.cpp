@@ -334,14 +334,17 @@ void apply_preconditioner_dev(Context& c, const void* dB, int64_t ldb, void* dX,
   const int nlev = (int)c.level_ptr.size() - 1;
   double lvl_bytes = 0, lvl_flops = 0;
   const double elem = 16.0;
+  int maxns = 0;
   auto level_sizes = [&](int lo, int hi, int& maxn, int& maxnu) {
     maxn = 0;
     maxnu = 0;
+    maxns = 0;
     lvl_bytes = lvl_flops = 0;
     for (int k = lo; k < hi; ++k) {
       const FrontPlan& p = c.fp[c.level_order[k]];
       maxn = std::max(maxn, p.n);
       maxnu = std::max(maxnu, p.nu);
+      maxns = std::max(maxns, p.ns);
       const double ns = p.ns, nu = p.nu;
       // half of F11 (L or U) plus F21 or F12, read once; vectors in and out
       lvl_bytes += elem * (0.5 * ns * ns + ns * nu) + elem * 3.0 * (ns + nu) * nrhs;
@@ -355,14 +358,14 @@ void apply_preconditioner_dev(Context& c, const void* dB, int64_t ldb, void* dX,
       int mn, mu;
       level_sizes(b, e, mn, mu);
       const int tk = c.timer.begin(c.stream);
-      check(launch_forward_level<double>(dfds + b, e - b, mn, mu, c.d_y.p, c.n, (int)nrhs, c.stream), "fwd");
+      check(launch_forward_level<double>(dfds + b, e - b, mn, mu, maxns, c.d_y.p, c.n, (int)nrhs, c.stream), "fwd");
       c.timer.end(tk, c.stream, K_FWD, lvl_flops, lvl_bytes);
     } else {
       for (int k = b; k < e; ++k) {
         int mn, mu;
         level_sizes(k, k + 1, mn, mu);
         const int tk = c.timer.begin(c.stream);
-        check(launch_forward_level<double>(dfds + k, 1, mn, mu, c.d_y.p, c.n, (int)nrhs, c.stream), "fwd");
+        check(launch_forward_level<double>(dfds + k, 1, mn, mu, maxns, c.d_y.p, c.n, (int)nrhs, c.stream), "fwd");
         c.timer.end(tk, c.stream, K_FWD, lvl_flops, lvl_bytes);
       }
     }
@@ -387,14 +390,14 @@ void apply_preconditioner_dev(Context& c, const void* dB, int64_t ldb, void* dX,
       int mn, mu;
       level_sizes(b, e, mn, mu);
       const int tk = c.timer.begin(c.stream);
-      check(launch_backward_level<double>(dfds + b, e - b, mn, mu, c.d_x.p, c.n, (int)nrhs, c.stream), "bwd");
+      check(launch_backward_level<double>(dfds + b, e - b, mn, mu, maxns, c.d_x.p, c.n, (int)nrhs, c.stream), "bwd");
       c.timer.end(tk, c.stream, K_BWD, lvl_flops, lvl_bytes);
     } else {
       for (int k = e - 1; k >= b; --k) {
         int mn, mu;
         level_sizes(k, k + 1, mn, mu);
         const int tk = c.timer.begin(c.stream);
-        check(launch_backward_level<double>(dfds + k, 1, mn, mu, c.d_x.p, c.n, (int)nrhs, c.stream), "bwd");
+        check(launch_backward_level<double>(dfds + k, 1, mn, mu, maxns, c.d_x.p, c.n, (int)nrhs, c.stream), "bwd");
         c.timer.end(tk, c.stream, K_BWD, lvl_flops, lvl_bytes);
       }
     }
@@ -403,12 +406,9 @@ void apply_preconditioner_dev(Context& c, const void* dB, int64_t ldb, void* dX,
 }
 
 // ------------------------------------------------------------------ GMRES
-int gmres_dev(Context& c, const void* dB, int64_t ldb, void* dX, int64_t ldx, int64_t nrhs, bfmf_solve_opts& o) {
-  typedef std::complex<double> cd;
-  const int64_t N = c.n;
-  const int m = std::max(1, o.restart);
-  const size_t elem = sizeof(cd);
-  const size_t blk = (size_t)N * nrhs * elem;
+void gmres_workspace(Context& c, int64_t nrhs, int m) {
+  const size_t elem = 2 * sizeof(double);
+  const size_t blk = (size_t)c.n * nrhs * elem;
   if (c.g_nrhs < nrhs || c.g_restart < m) {
     alloc(c.g_V, blk * (m + 1));
     alloc(c.g_w, blk);
@@ -419,6 +419,14 @@ int gmres_dev(Context& c, const void* dB, int64_t ldb, void* dX, int64_t ldx, in
     c.g_nrhs = nrhs;
     c.g_restart = m;
   }
+}
+
+int gmres_dev(Context& c, const void* dB, int64_t ldb, void* dX, int64_t ldx, int64_t nrhs, bfmf_solve_opts& o) {
+  typedef std::complex<double> cd;
+  const int64_t N = c.n;
+  const int m = std::max(1, o.restart);
+  const size_t elem = sizeof(cd);
+  gmres_workspace(c, nrhs, m);
   const int nblk = (int)std::min<int64_t>(256, (N + 255) / 256);
   cd* V = c.g_V.as<cd>();
   cd* w = c.g_w.as<cd>();

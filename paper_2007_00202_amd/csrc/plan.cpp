@@ -197,6 +197,8 @@ uint64_t Context::device_bytes() const {
                           &d_piv, &d_status, &d_fds, &d_arena, &d_kept, &d_W, &d_y, &d_x, &g_B, &g_X, &g_V, &g_w,
                           &g_r, &g_scal, &g_part, &g_tmp})
     t += b->bytes;
+  t += stage.cap;  // pinned host ring (counted with the handle's memory)
+  if (comp) t += comp_state_bytes(comp);
   return t;
 }
 

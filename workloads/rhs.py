@@ -28,3 +28,19 @@ def point_sources(n, nrhs, rng):
 def random_edge_dipoles(n_edges, nrhs, rng):
     """Unit current on a uniformly random edge per column."""
     return point_sources(n_edges, nrhs, rng)
+
+
+def request_stream(rate, seconds, sizes, max_rhs, rng):
+    """Serving requests: Poisson arrivals at `rate` per second during `seconds`;
+    each request picks a model uniformly among len(sizes) and carries 1..max_rhs
+    (uniform) unit point sources at distinct uniformly random unknowns of that
+    model.  Returns a list of (arrival time, model, rows)."""
+    out = []
+    t = rng.exponential(1.0 / rate)
+    while t < seconds:
+        m = int(rng.integers(0, len(sizes)))
+        k = int(rng.integers(1, max_rhs + 1))
+        rows = rng.choice(sizes[m], size=k, replace=False)
+        out.append((float(t), m, rows))
+        t += rng.exponential(1.0 / rate)
+    return out
