@@ -448,11 +448,16 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
         "grouped gemm");
     if (tk >= 0) {
       double fl = 0, by = 0;
+      int mm = 0, mn = 0, mk = 0;
       for (const GTask& t : plan.phase[k]) {
         const double M = t.M, N = t.N, K = t.K;
         fl += 8.0 * M * N * K;
         by += sizeof(cplx<T>) * (M * K + K * N + M * N * (t.beta ? 2.0 : 1.0));
+        mm = std::max(mm, t.M);
+        mn = std::max(mn, t.N);
+        mk = std::max(mk, t.K);
       }
+      c.timer.set_shape(tk, (int)plan.phase[k].size(), mm, mn, mk);
       c.timer.end(tk, s, kind, fl, by);
     }
   }

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <array>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -87,6 +89,7 @@ struct KernelTimer {
     int kind;
     hipEvent_t a, b;
     double flops, bytes;
+    int shape[4];  // butterfly GEMM launches: tasks, largest M, N, K
   };
   std::vector<hipEvent_t> pool;
   size_t used = 0;
@@ -97,6 +100,12 @@ struct KernelTimer {
   double seconds[K_COUNT] = {}, flops[K_COUNT] = {}, bytes[K_COUNT] = {};
   // timed butterfly GEMM launches by floor(log2(flops)): count, seconds, flops
   double hist_n[64] = {}, hist_s[64] = {}, hist_f[64] = {};
+  // timed butterfly GEMM launches by log2 of (tasks, M, N, K): count, seconds, flops
+  std::map<std::array<int, 4>, std::array<double, 3>> shapes;
+  void set_shape(int token, int ntasks, int m, int n, int k) {
+    if (token >= 0) recs[token].shape[0] = ntasks, recs[token].shape[1] = m, recs[token].shape[2] = n,
+                    recs[token].shape[3] = k;
+  }
   // whether to time the next launch of this class (counts it either way)
   bool want(int kind) { return enabled && (issued[kind]++ % sample_every[kind]) == 0; }
   hipEvent_t take();

@@ -61,6 +61,7 @@ int KernelTimer::begin(hipStream_t s) {
   r.a = take();
   r.b = take();
   r.flops = r.bytes = 0;
+  r.shape[0] = r.shape[1] = r.shape[2] = r.shape[3] = 0;
   HIPCHK(hipEventRecord(r.a, s));
   recs.push_back(r);
   return (int)recs.size() - 1;
@@ -89,6 +90,12 @@ void KernelTimer::collect() {
       hist_n[b] += 1;
       hist_s[b] += ms * 1e-3;
       hist_f[b] += r.flops;
+      std::array<int, 4> key;
+      for (int q = 0; q < 4; ++q) key[q] = r.shape[q] > 0 ? (int)std::log2((double)r.shape[q]) : -1;
+      auto& v = shapes[key];
+      v[0] += 1;
+      v[1] += ms * 1e-3;
+      v[2] += r.flops;
     }
   }
   recs.clear();
@@ -103,6 +110,7 @@ void KernelTimer::reset() {
     seconds[k] = flops[k] = bytes[k] = 0;
   }
   for (int b = 0; b < 64; ++b) hist_n[b] = hist_s[b] = hist_f[b] = 0;
+  shapes.clear();
 }
 
 KernelTimer::~KernelTimer() {
@@ -265,6 +273,16 @@ void factor_dense(Context& c) {
       if (c.timer.hist_n[b] > 0)
         fprintf(stderr, "[bfmf]   2^%-2d %8.0f %9.2f %7.2f\n", b, c.timer.hist_n[b], 1e3 * c.timer.hist_s[b],
                 c.timer.hist_f[b] / std::max(c.timer.hist_s[b], 1e-30) / 1e12);
+    std::vector<std::pair<double, std::array<int, 4>>> top;
+    for (auto& kv : c.timer.shapes) top.push_back({kv.second[1], kv.first});
+    std::sort(top.rbegin(), top.rend());
+    fprintf(stderr, "[bfmf] butterfly GEMM launch classes by time (log2 of tasks, max M, N, K): count ms TFLOP/s\n");
+    for (size_t q = 0; q < std::min<size_t>(top.size(), 25); ++q) {
+      const auto& v = c.timer.shapes[top[q].second];
+      const auto& k = top[q].second;
+      fprintf(stderr, "[bfmf]   %2d %2d %2d %2d %7.0f %8.2f %7.2f\n", k[0], k[1], k[2], k[3], v[0], 1e3 * v[1],
+              v[2] / std::max(v[1], 1e-30) / 1e12);
+    }
   }
   int st[3] = {0, 0, 0};
   HIPCHK(hipMemcpy(st, c.d_status.p, sizeof(st), hipMemcpyDeviceToHost));

@@ -1,0 +1,58 @@
+"""GPU parity on the other workload shapes: the Yee curl-curl operator
+(indefinite, piecewise permittivity, edge nested dissection) and the
+Helmholtz operator with a heterogeneous Gaussian-random-field velocity.
+
+Compressed fronts in both precisions against the exact FP64 oracle: the
+GMRES solution within 10 tol and a true residual at most 1e-3."""
+import numpy as np
+import pytest
+
+from workloads import make_problem, rng_for
+from workloads.maxwell import yee_curlcurl, block_permittivity
+from oracle import nd
+from oracle import multifrontal as mf
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_maxwell_yee_compressed(gpu_lib, precision):
+    cells = 10
+    eps = block_permittivity(cells, 4, rng_for("test", "coef", (cells,)))
+    rp, ci, v, meta = yee_curlcurl(cells, 0.03, eps_cells=eps)
+    n = rp.shape[0] - 1
+    rng = rng_for("test", "rhs", (cells,))
+    B = np.zeros((n, 3), dtype=np.complex128)
+    B[rng.choice(n, 3, replace=False), np.arange(3)] = 1.0
+    od = nd.nd_yee(cells, meta["coords"], leaf_max=64, sep_leaf=32)
+    x_or = mf.solve(mf.factor(rp, ci, v, od), B)
+    s = gpu_lib.Solver(0).analyze(rp, ci, v, coords=meta["coords"], cells=cells, leaf_max=64, sep_leaf=32)
+    prec = gpu_lib.BFMF_C128 if precision == "c128" else gpu_lib.BFMF_C64_MIXED
+    s.factor(tol=1e-3, n_min=100, batched=True, precision=prec)
+    st = s.stats()
+    assert st["compressed_fronts"] >= 1
+    X, info = s.solve(B, true_rtol=1e-3)
+    err = np.linalg.norm(X - x_or) / np.linalg.norm(x_or)
+    res = mf.rel_residual(rp, ci, v, X, B).max()
+    assert info["status"] == 0 and err <= 1e-2 and res <= 1e-3, (err, res, info, st["compressed_fronts"])
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_grf_velocity_compressed(gpu_lib, precision):
+    p = make_problem("helmholtz128grf", n=16, nrhs=4)
+    # the velocity from the diagonal 6 - (omega h / c)^2 (1 + i delta): heterogeneous, within [1, 2]
+    A = mf.csr_matrix(p.rowptr, p.colind, p.values)
+    c = p.meta["omega"] * p.meta["h"] / np.sqrt(6.0 - A.diagonal().real)
+    assert c.min() >= 1.0 - 1e-9 and c.max() <= 2.0 + 1e-9 and c.max() - c.min() > 0.2
+    od = nd.nd_grid(p.dims, leaf_max=64, sep_leaf=32)
+    x_or = mf.solve(mf.factor(p.rowptr, p.colind, p.values, od), p.rhs)
+    s = gpu_lib.Solver(0).analyze(p.rowptr, p.colind, p.values, dims=p.dims, leaf_max=64, sep_leaf=32)
+    prec = gpu_lib.BFMF_C128 if precision == "c128" else gpu_lib.BFMF_C64_MIXED
+    s.factor(tol=1e-3, n_min=60, batched=True, precision=prec)
+    assert s.stats()["compressed_fronts"] >= 3
+    X, info = s.solve(p.rhs, true_rtol=1e-3)
+    err = np.linalg.norm(X - x_or) / np.linalg.norm(x_or)
+    res = mf.rel_residual(p.rowptr, p.colind, p.values, X, p.rhs).max()
+    assert info["status"] == 0 and err <= 1e-2 and res <= 1e-3, (err, res, info)
+    s.close()
