@@ -1,5 +1,6 @@
 // Butterfly format, products and construction (paper Sec. 3).  See bf.hpp.
 #include "bf.hpp"
+#include "ops.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -199,11 +200,16 @@ BfPlan make_plan(const std::vector<BfCall>& calls, bool adjoint, int nrhs, int64
   for (auto& cl : calls) {
     const Butterfly& bf = *cl.bf;
     const int L = bf.L, lc = bf.lc, nb = 1 << L;
+    // this call's input and output: shared buffers (bases 1, 2) or its own (base 4, absolute)
+    const int nr = cl.nrhs > 0 ? cl.nrhs : nrhs;
+    const int xb = cl.x_abs >= 0 ? 4 : 1, yb = cl.y_abs >= 0 ? 4 : 2;
+    const int64_t xo = (cl.x_abs >= 0 ? cl.x_abs : 0) + cl.x_off, yo = (cl.y_abs >= 0 ? cl.y_abs : 0) + cl.y_off;
+    const int64_t lx = cl.ldx > 0 ? cl.ldx : ldx, ly = cl.ldy > 0 ? cl.ldy : ldy;
     // two ping-pong regions sized for the largest level
     int64_t maxrows = 0;
     for (int l = lc; l <= L; ++l) maxrows = std::max<int64_t>(maxrows, std::accumulate(bf.rl[l].begin(), bf.rl[l].end(), (int64_t)0));
     for (int l = 0; l <= lc; ++l) maxrows = std::max<int64_t>(maxrows, std::accumulate(bf.rr[l].begin(), bf.rr[l].end(), (int64_t)0));
-    const int64_t region = maxrows * nrhs;
+    const int64_t region = maxrows * nr;
     const int64_t w0 = ws, w1 = ws + region;
     ws += 2 * region;
     int ph = 0;
@@ -211,19 +217,19 @@ BfPlan make_plan(const std::vector<BfCall>& calls, bool adjoint, int nrhs, int64
     auto W = [&](bool r0) { return r0 ? w0 : w1; };
     if (!adjoint) {
       // V: t_0 = Vt X(S_v)
-      VecLayout out = layout(bf.rr[0], L, 0, 1, nrhs);
+      VecLayout out = layout(bf.rr[0], L, 0, 1, nr);
       for (int v = 0; v < nb; ++v) {
         const int M = bf.rr[0][v];
         if (M == 0) continue;
-        plan.phase[ph].push_back(task(bf.offR[0][v], M, OP_N, 0, cl.x_off + bf.ts.beg(L, v), ldx, 1,
+        plan.phase[ph].push_back(task(bf.offR[0][v], M, OP_N, 0, xo + bf.ts.beg(L, v), lx, xb,
                                       W(true) + out.grp_off[out.grp_of[v]] + out.mem_row[v], out.grp_ld[out.grp_of[v]], 3,
-                                      M, nrhs, bf.ts.size(L, v), 1, 0, 0));
+                                      M, nr, bf.ts.size(L, v), 1, 0, 0));
       }
       ++ph;
       VecLayout in = out;
       in0 = true;
       for (int l = 1; l <= lc; ++l) {
-        VecLayout o = layout(bf.rr[l], L, l, 1, nrhs);
+        VecLayout o = layout(bf.rr[l], L, l, 1, nr);
         const int vs = 1 << (L - l);
         for (int t = 0; t < (1 << l); ++t)
           for (int v = 0; v < vs; ++v) {
@@ -240,7 +246,7 @@ BfPlan make_plan(const std::vector<BfCall>& calls, bool adjoint, int nrhs, int64
             const int gi = in.grp_of[ia];
             plan.phase[ph].push_back(task(bf.offR[l][q] + row_off, wrows, OP_N, 0, W(in0) + in.grp_off[gi], in.grp_ld[gi],
                                           3, W(!in0) + o.grp_off[o.grp_of[blk]] + o.mem_row[blk],
-                                          o.grp_ld[o.grp_of[blk]], 3, M, nrhs, K, 1, 0, 0));
+                                          o.grp_ld[o.grp_of[blk]], 3, M, nr, K, 1, 0, 0));
           }
         ++ph;
         in = o;
@@ -253,14 +259,14 @@ BfPlan make_plan(const std::vector<BfCall>& calls, bool adjoint, int nrhs, int64
       }
       // B: s_lc = B t_lc
       {
-        VecLayout o = layout(bf.rl[lc], L, lc, 1, nrhs);
+        VecLayout o = layout(bf.rl[lc], L, lc, 1, nr);
         for (int blk = 0; blk < nb; ++blk) {
           const int M = bf.rl[lc][blk], K = bf.rr[lc][blk];
           if (M == 0) continue;
           const int gi = in.grp_of[blk];
           plan.phase[ph].push_back(task(bf.offB[blk], M, OP_N, 0, W(in0) + in.grp_off[gi] + in.mem_row[blk],
                                         in.grp_ld[gi], 3, W(!in0) + o.grp_off[o.grp_of[blk]] + o.mem_row[blk],
-                                        o.grp_ld[o.grp_of[blk]], 3, M, nrhs, K, 1, 0, 0));
+                                        o.grp_ld[o.grp_of[blk]], 3, M, nr, K, 1, 0, 0));
         }
         ++ph;
         in = o;
@@ -268,7 +274,7 @@ BfPlan make_plan(const std::vector<BfCall>& calls, bool adjoint, int nrhs, int64
       }
       // R: s_{l+1} from nu-pairs of s_l
       for (int l = lc; l < L; ++l) {
-        VecLayout o = layout(bf.rl[l + 1], L, l + 1, 1, nrhs);
+        VecLayout o = layout(bf.rl[l + 1], L, l + 1, 1, nr);
         const int vs1 = 1 << (L - l - 1);  // column nodes at level l+1
         for (int t1 = 0; t1 < (1 << (l + 1)); ++t1)
           for (int v1 = 0; v1 < vs1; ++v1) {
@@ -284,7 +290,7 @@ BfPlan make_plan(const std::vector<BfCall>& calls, bool adjoint, int nrhs, int64
             const int gi = in.grp_of[2 * pair];
             plan.phase[ph].push_back(task(bf.offL[l][pair] + row_off, rrows, OP_N, 0, W(in0) + in.grp_off[gi],
                                           in.grp_ld[gi], 3, W(!in0) + o.grp_off[o.grp_of[blk1]] + o.mem_row[blk1],
-                                          o.grp_ld[o.grp_of[blk1]], 3, M, nrhs, K, 1, 0, 0));
+                                          o.grp_ld[o.grp_of[blk1]], 3, M, nr, K, 1, 0, 0));
           }
         ++ph;
         in = o;
@@ -296,24 +302,24 @@ BfPlan make_plan(const std::vector<BfCall>& calls, bool adjoint, int nrhs, int64
         if (M == 0) continue;
         const int gi = in.grp_of[t];
         plan.phase[ph].push_back(task(bf.offL[L][t], M, OP_N, 0, W(in0) + in.grp_off[gi] + in.mem_row[t],
-                                      in.grp_ld[gi], 3, cl.y_off + bf.to.beg(L, t), ldy, 2, M, nrhs, K, cl.alpha_re,
+                                      in.grp_ld[gi], 3, yo + bf.to.beg(L, t), ly, yb, M, nr, K, cl.alpha_re,
                                       cl.alpha_im, cl.beta));
       }
     } else {
       // U^H: s_L = U^H X(O_t), tau-paired
-      VecLayout out = layout(bf.rl[L], L, L, 2, nrhs);
+      VecLayout out = layout(bf.rl[L], L, L, 2, nr);
       for (int t = 0; t < nb; ++t) {
         const int M = bf.rl[L][t];
         if (M == 0) continue;
-        plan.phase[ph].push_back(task(bf.offL[L][t], bf.to.size(L, t), OP_C, 0, cl.x_off + bf.to.beg(L, t), ldx, 1,
+        plan.phase[ph].push_back(task(bf.offL[L][t], bf.to.size(L, t), OP_C, 0, xo + bf.to.beg(L, t), lx, xb,
                                       W(true) + out.grp_off[out.grp_of[t]] + out.mem_row[t], out.grp_ld[out.grp_of[t]],
-                                      3, M, nrhs, bf.to.size(L, t), 1, 0, 0));
+                                      3, M, nr, bf.to.size(L, t), 1, 0, 0));
       }
       ++ph;
       VecLayout in = out;
       in0 = true;
       for (int l = L - 1; l >= lc; --l) {
-        VecLayout o = layout(bf.rl[l], L, l, 2, nrhs);
+        VecLayout o = layout(bf.rl[l], L, l, 2, nr);
         const int vs = 1 << (L - l), vs1 = vs / 2;
         for (int t = 0; t < (1 << l); ++t)
           for (int v = 0; v < vs; ++v) {
@@ -328,28 +334,28 @@ BfPlan make_plan(const std::vector<BfCall>& calls, bool adjoint, int nrhs, int64
             plan.phase[ph].push_back(task(bf.offL[l][pair] + (int64_t)col_off * rrows, rrows, OP_C, 0,
                                           W(in0) + in.grp_off[gi], in.grp_ld[gi], 3,
                                           W(!in0) + o.grp_off[o.grp_of[blk]] + o.mem_row[blk], o.grp_ld[o.grp_of[blk]],
-                                          3, M, nrhs, rrows, 1, 0, 0));
+                                          3, M, nr, rrows, 1, 0, 0));
           }
         ++ph;
         in = o;
         in0 = !in0;
       }
       {  // B^H
-        VecLayout o = layout(bf.rr[lc], L, lc, 2, nrhs);
+        VecLayout o = layout(bf.rr[lc], L, lc, 2, nr);
         for (int blk = 0; blk < nb; ++blk) {
           const int M = bf.rr[lc][blk], K = bf.rl[lc][blk];
           if (M == 0) continue;
           const int gi = in.grp_of[blk];
           plan.phase[ph].push_back(task(bf.offB[blk], std::max(K, 1), OP_C, 0, W(in0) + in.grp_off[gi] + in.mem_row[blk],
                                         in.grp_ld[gi], 3, W(!in0) + o.grp_off[o.grp_of[blk]] + o.mem_row[blk],
-                                        o.grp_ld[o.grp_of[blk]], 3, M, nrhs, K, 1, 0, 0));
+                                        o.grp_ld[o.grp_of[blk]], 3, M, nr, K, 1, 0, 0));
         }
         ++ph;
         in = o;
         in0 = !in0;
       }
       for (int l = lc; l >= 1; --l) {  // W^H: t_{l-1} from tau-pairs of t_l
-        VecLayout o = layout(bf.rr[l - 1], L, l - 1, 2, nrhs);
+        VecLayout o = layout(bf.rr[l - 1], L, l - 1, 2, nr);
         const int vs = 1 << (L - l), vs0 = 2 * vs;  // column nodes at levels l and l-1
         for (int t0 = 0; t0 < (1 << (l - 1)); ++t0)
           for (int v0 = 0; v0 < vs0; ++v0) {
@@ -366,7 +372,7 @@ BfPlan make_plan(const std::vector<BfCall>& calls, bool adjoint, int nrhs, int64
             plan.phase[ph].push_back(task(bf.offR[l][q] + (int64_t)col_off * std::max(wrows, 1), wrows, OP_C, 0,
                                           W(in0) + in.grp_off[gi], in.grp_ld[gi], 3,
                                           W(!in0) + o.grp_off[o.grp_of[blk0]] + o.mem_row[blk0],
-                                          o.grp_ld[o.grp_of[blk0]], 3, M, nrhs, wrows, 1, 0, 0));
+                                          o.grp_ld[o.grp_of[blk0]], 3, M, nr, wrows, 1, 0, 0));
           }
         ++ph;
         in = o;
@@ -377,7 +383,7 @@ BfPlan make_plan(const std::vector<BfCall>& calls, bool adjoint, int nrhs, int64
         if (M == 0) continue;
         const int gi = in.grp_of[v];
         plan.phase[ph].push_back(task(bf.offR[0][v], std::max(K, 1), OP_C, 0, W(in0) + in.grp_off[gi] + in.mem_row[v],
-                                      in.grp_ld[gi], 3, cl.y_off + bf.ts.beg(L, v), ldy, 2, M, nrhs, K, cl.alpha_re,
+                                      in.grp_ld[gi], 3, yo + bf.ts.beg(L, v), ly, yb, M, nr, K, cl.alpha_re,
                                       cl.alpha_im, cl.beta));
       }
     }
@@ -489,6 +495,23 @@ void BfRuntime<T>::apply_set(const std::vector<BfCall>& calls, const void* X, in
   if (rows_in > ldx || rows_out > ldy) throw Error(BFMF_E_INVAL, "internal: butterfly product leading dimension");
   const int64_t lim[4] = {(int64_t)(pool.used / sizeof(cplx<T>)), ldx * nrhs, ldy * nrhs, std::max<int64_t>(plan.ws_elems, 1)};
   run_plan<T>(plan, *c, pool_base(), X, Y, ws, s(), lim);
+  scratch.release(mk);
+}
+
+template <class T>
+void BfRuntime<T>::apply_calls(const std::vector<BfCall>& calls, bool adjoint) {
+  if (calls.empty()) return;
+  for (auto& cl : calls) {
+    const int64_t rows_in = cl.x_off + (adjoint ? cl.bf->m : cl.bf->n);
+    const int64_t rows_out = cl.y_off + (adjoint ? cl.bf->n : cl.bf->m);
+    if (cl.x_abs < 0 || cl.y_abs < 0 || cl.nrhs <= 0 || rows_in > cl.ldx || rows_out > cl.ldy)
+      throw Error(BFMF_E_INVAL, "internal: butterfly call without its own buffers");
+  }
+  BfPlan plan = make_plan(calls, adjoint, 1, 1, 1);
+  auto mk = scratch.mark();
+  void* ws = scratch.take(std::max<int64_t>(plan.ws_elems, 1) * sizeof(cplx<T>));
+  const int64_t lim[4] = {(int64_t)(pool.used / sizeof(cplx<T>)), 0, 0, std::max<int64_t>(plan.ws_elems, 1)};
+  run_plan<T>(plan, *c, pool_base(), nullptr, nullptr, ws, s(), lim);
   scratch.release(mk);
 }
 
@@ -1033,9 +1056,21 @@ void random_once_batch(BfRuntime<T>& rt, const std::vector<RandomJob<T>*>& jobs)
     int32_t* d_he = (int32_t*)upload_tmp(rt, he);
     chk(launch_philox_gauss<T>(w.Om, std::max(n, 1), n, w.ncl, S, d_gb, d_ge, rt.seed, rt.stream_id++, s), "probes");
     chk(launch_philox_gauss<T>(w.Ps, std::max(m, 1), m, w.ncr, S, d_hb, d_he, rt.seed, rt.stream_id++, s), "probes");
-    j.op->apply(w.Om, std::max(n, 1), w.Y, std::max(m, 1), w.ncl, false, 1.0, 0);
-    j.op->apply(w.Ps, std::max(m, 1), w.Z, std::max(n, 1), w.ncr, true, 1.0, 0);
     j.max_id_rank = 0;
+  }
+  // the sketches of every job: operators of one structure are applied together (apply_all)
+  {
+    std::vector<Op<T>*> ops;
+    std::vector<ApplyArg> fw, bw;
+    for (size_t ji = 0; ji < nj; ++ji) {
+      RandomJob<T>& j = *jobs[ji];
+      const int m = j.to.n, n = j.ts.n;
+      ops.push_back(j.op);
+      fw.push_back(ApplyArg{sk[ji].Om, std::max(n, 1), sk[ji].Y, std::max(m, 1), sk[ji].ncl});
+      bw.push_back(ApplyArg{sk[ji].Ps, std::max(m, 1), sk[ji].Z, std::max(n, 1), sk[ji].ncr});
+    }
+    apply_all<T>(rt, ops, fw, false, 1.0, 0);
+    apply_all<T>(rt, ops, bw, true, 1.0, 0);
   }
   // left: row IDs of the sketch rows; step k works on level L - k of every butterfly
   for (int k = 0;; ++k) {

@@ -103,6 +103,11 @@ struct BfCall {
   int64_t x_off, y_off;
   double alpha_re, alpha_im;
   int beta;
+  // a call with its own input/output: element addresses (address / sizeof element; -1: the plan's
+  // shared X / Y), their leading dimensions and its number of columns (0: the plan's)
+  int64_t x_abs = -1, y_abs = -1;
+  int64_t ldx = 0, ldy = 0;
+  int nrhs = 0;
 };
 
 // Grouped-GEMM phases of the product of a set of butterflies.
@@ -127,6 +132,18 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
               const int64_t lim[4], int kind = K_BF_GEMM);
 
 // ------------------------------------------------------------- operators
+template <class T>
+struct BfRuntime;
+
+// One application of a batch: input X (ld ldx), output Y (ld ldy), nrhs columns.
+struct ApplyArg {
+  const void* X;
+  int64_t ldx;
+  void* Y;
+  int64_t ldy;
+  int nrhs;
+};
+
 // Y = alpha op(A) X + beta Y for a linear operator A (m x n), nrhs columns.
 template <class T>
 struct Op {
@@ -134,6 +151,16 @@ struct Op {
   virtual ~Op() {}
   virtual void apply(const void* X, int64_t ldx, void* Y, int64_t ldy, int nrhs, bool adjoint, double alpha,
                      int beta) = 0;
+  // Operators of the same dynamic type and key have the same structure and can be applied together.
+  virtual uint64_t key() const { return 0; }
+  // ops[i] (all of this dynamic type and key) applied to args[i], independent outputs; the default runs
+  // them one after another, the operator types override it with launches shared by the whole batch.
+  virtual void apply_many(BfRuntime<T>& rt, const std::vector<Op<T>*>& ops, const std::vector<ApplyArg>& args,
+                          bool adjoint, double alpha, int beta) {
+    (void)rt;
+    for (size_t i = 0; i < ops.size(); ++i)
+      ops[i]->apply(args[i].X, args[i].ldx, args[i].Y, args[i].ldy, args[i].nrhs, adjoint, alpha, beta);
+  }
 };
 
 // Runtime shared by all butterfly work of one factorization.
@@ -157,6 +184,8 @@ struct BfRuntime {
              double alpha, int beta);
   void apply_set(const std::vector<BfCall>& calls, const void* X, int64_t ldx, void* Y, int64_t ldy, int nrhs,
                  bool adjoint);
+  // products of calls that each name their own input and output (x_abs, y_abs, ldx, ldy, nrhs)
+  void apply_calls(const std::vector<BfCall>& calls, bool adjoint);
 };
 
 // Extraction requests gathered over many blocks (and butterflies, and

@@ -152,6 +152,59 @@ struct IPlusX : Op<T> {
     }
     axpby<T>(rt, Y, ldy, X, ldx, n, nrhs, alpha, 1.0);
   }
+  uint64_t key() const override { return bf ? 0 : (dense_off >= 0 ? 1 : 2); }
+  void apply_many(BfRuntime<T>& r, const std::vector<Op<T>*>& all, const std::vector<ApplyArg>& args, bool adj,
+                  double alpha, int beta) override {
+    std::vector<AxpbyTask> id;
+    for (size_t q = 0; q < all.size(); ++q)
+      id.push_back(axt(args[q].Y, args[q].ldy, args[q].X, args[q].ldx, all[q]->n, args[q].nrhs));
+    if (bf) {  // Y = alpha K X + beta Y for every item, then Y += alpha X
+      std::vector<BfCall> calls;
+      for (size_t q = 0; q < all.size(); ++q) {
+        BfCall c{static_cast<IPlusX<T>*>(all[q])->bf, 0, 0, alpha, 0.0, beta};
+        c.x_abs = eaddr<T>(args[q].X);
+        c.y_abs = eaddr<T>(args[q].Y);
+        c.ldx = args[q].ldx;
+        c.ldy = args[q].ldy;
+        c.nrhs = args[q].nrhs;
+        calls.push_back(c);
+      }
+      r.apply_calls(calls, adj);
+      axpby_many<T>(r, id, alpha, 1.0);
+    } else if (dense_off >= 0) {
+      std::vector<GTask> ph;
+      for (size_t q = 0; q < all.size(); ++q) {
+        auto* o = static_cast<IPlusX<T>*>(all[q]);
+        const int n = o->n;
+        GTask t = {};
+        t.a_off = o->dense_off;
+        t.lda = std::max(n, 1);
+        t.opA = (int8_t)(adj ? OP_C : OP_N);
+        t.abase = 0;
+        t.b_off = eaddr<T>(args[q].X);
+        t.ldb = std::max<int64_t>(args[q].ldx, 1);
+        t.bbase = 4;
+        t.c_off = eaddr<T>(args[q].Y);
+        t.ldc = std::max<int64_t>(args[q].ldy, 1);
+        t.cbase = 4;
+        t.M = n;
+        t.N = args[q].nrhs;
+        t.K = n;
+        t.alpha_re = alpha;
+        t.beta = (int8_t)beta;
+        if (n > 0) ph.push_back(t);
+      }
+      if (!ph.empty()) {
+        BfPlan p;
+        p.phase.push_back(ph);
+        const int64_t lim[4] = {(int64_t)(r.pool.used / sizeof(cplx<T>)), 0, 0, 0};
+        run_plan<T>(p, *r.c, r.pool_base(), nullptr, nullptr, nullptr, r.s(), lim);
+      }
+      axpby_many<T>(r, id, alpha, 1.0);
+    } else {
+      axpby_many<T>(r, id, alpha, beta ? 1.0 : 0.0);
+    }
+  }
 };
 
 // A^-1 - I for A = [I + K11, K12; K21, I + K22] from the factored form
@@ -195,6 +248,73 @@ struct SmwOp : Op<T> {
     (void)y;
     rt.scratch.release(mk);
   }
+  // the same sequence with each step applied to every item at once
+  void apply_many(BfRuntime<T>& r, const std::vector<Op<T>*>& all, const std::vector<ApplyArg>& args, bool adj,
+                  double alpha, int beta) override {
+    auto mk = r.scratch.mark();
+    const size_t nq = all.size();
+    std::vector<SmwOp<T>*> o(nq);
+    std::vector<cplx<T>*> w(nq), t(nq);
+    for (size_t q = 0; q < nq; ++q) {
+      o[q] = static_cast<SmwOp<T>*>(all[q]);
+      const int nn = o[q]->n1 + o[q]->n2;
+      w[q] = (cplx<T>*)r.scratch.take((size_t)nn * args[q].nrhs * sizeof(cplx<T>));
+      t[q] = (cplx<T>*)r.scratch.take((size_t)std::max(o[q]->n1, o[q]->n2) * args[q].nrhs * sizeof(cplx<T>));
+    }
+    auto X = [&](size_t q) { return (const cplx<T>*)args[q].X; };
+    auto nn = [&](size_t q) { return (int64_t)(o[q]->n1 + o[q]->n2); };
+    // step(op selector, input, input ld, output, output ld, alpha, beta)
+    auto step = [&](auto pick, auto in, auto ldi, auto out, auto ldo, double a, int b) {
+      std::vector<Op<T>*> ops;
+      std::vector<ApplyArg> aa;
+      for (size_t q = 0; q < nq; ++q) {
+        ops.push_back(pick(q));
+        aa.push_back(ApplyArg{in(q), ldi(q), out(q), ldo(q), args[q].nrhs});
+      }
+      apply_all<T>(r, ops, aa, adj, a, b);
+    };
+    auto ax = [&](auto y, auto ldy, auto x, auto ldx, auto m, double a, double b) {
+      std::vector<AxpbyTask> tk;
+      for (size_t q = 0; q < nq; ++q) tk.push_back(axt(y(q), ldy(q), x(q), ldx(q), m(q), args[q].nrhs));
+      axpby_many<T>(r, tk, a, b);
+    };
+    auto n1 = [&](size_t q) { return (int64_t)o[q]->n1; };
+    auto n2 = [&](size_t q) { return (int64_t)o[q]->n2; };
+    auto w1 = [&](size_t q) { return w[q]; };
+    auto w2 = [&](size_t q) { return w[q] + o[q]->n1; };
+    auto tt = [&](size_t q) { return t[q]; };
+    auto x1 = [&](size_t q) { return X(q); };
+    auto x2 = [&](size_t q) { return X(q) + o[q]->n1; };
+    auto ldx = [&](size_t q) { return args[q].ldx; };
+    auto A11i = [&](size_t q) { return o[q]->A11i; };
+    auto A22i = [&](size_t q) { return o[q]->A22i; };
+    auto K12 = [&](size_t q) { return o[q]->K12; };
+    auto K21 = [&](size_t q) { return o[q]->K21; };
+    if (!adj) {
+      step(A22i, x2, ldx, w2, nn, 1.0, 0);  // u2 = A22i x2
+      step(K12, w2, nn, tt, n1, 1.0, 0);    // t = K12 u2
+      ax(tt, n1, x1, ldx, n1, 1.0, -1.0);   // t = x1 - K12 u2
+      step(A11i, tt, n1, w1, nn, 1.0, 0);   // w1 = A11i t
+      step(K21, w1, nn, tt, n2, 1.0, 0);    // t = K21 w1
+      step(A22i, tt, n2, w2, nn, -1.0, 1);  // w2 = u2 - A22i K21 w1
+    } else {
+      step(A22i, x2, ldx, w2, nn, 1.0, 0);  // s = A22i^H x2
+      step(K21, w2, nn, tt, n1, 1.0, 0);    // t = K21^H s
+      ax(tt, n1, x1, ldx, n1, 1.0, -1.0);   // t = x1 - K21^H A22i^H x2
+      step(A11i, tt, n1, w1, nn, 1.0, 0);   // w1 = A11i^H t
+      step(K12, w1, nn, tt, n2, 1.0, 0);    // t = K12^H w1
+      step(A22i, x2, ldx, w2, nn, 1.0, 0);  // w2 = A22i^H x2
+      step(A22i, tt, n2, w2, nn, -1.0, 1);  // w2 -= A22i^H K12^H w1
+    }
+    auto wall = [&](size_t q) { return w[q]; };
+    auto xall = [&](size_t q) { return X(q); };
+    ax(wall, nn, xall, ldx, nn, -1.0, 1.0);  // minus the identity
+    auto yall = [&](size_t q) { return (cplx<T>*)args[q].Y; };
+    auto ldy = [&](size_t q) { return args[q].ldy; };
+    auto wconst = [&](size_t q) { return (const cplx<T>*)w[q]; };
+    ax(yall, ldy, wconst, nn, nn, alpha, beta ? 1.0 : 0.0);
+    r.scratch.release(mk);
+  }
 };
 
 // y = D_node^-1 x as an operator on the rows of `node`
@@ -217,6 +337,27 @@ struct HodbfInvOp : Op<T> {
     hodbf_inv_apply<T>(rt, h, node, X, ldx, t, n, nrhs, adj);
     axpby<T>(rt, Y, ldy, t, n, n, nrhs, alpha, beta ? 1.0 : 0.0);
     rt.scratch.release(mk);
+  }
+  void apply_many(BfRuntime<T>& r, const std::vector<Op<T>*>& all, const std::vector<ApplyArg>& args, bool adj,
+                  double alpha, int beta) override {
+    auto mk = r.scratch.mark();
+    std::vector<HodbfInvItem<T>> items;
+    std::vector<AxpbyTask> fin;
+    const bool direct = alpha == 1.0 && !beta;
+    for (size_t q = 0; q < all.size(); ++q) {
+      auto* o = static_cast<HodbfInvOp<T>*>(all[q]);
+      HodbfInvItem<T> it{&o->h, o->node, args[q].X, args[q].ldx, args[q].Y, args[q].ldy, args[q].nrhs};
+      if (!direct) {
+        const int n = o->n;
+        it.Y = r.scratch.take((size_t)std::max(n, 1) * args[q].nrhs * sizeof(cplx<T>));
+        it.ldy = std::max(n, 1);
+        fin.push_back(axt(args[q].Y, args[q].ldy, it.Y, it.ldy, n, args[q].nrhs));
+      }
+      items.push_back(it);
+    }
+    hodbf_inv_apply_many<T>(r, items, adj);
+    if (!direct) axpby_many<T>(r, fin, alpha, beta ? 1.0 : 0.0);
+    r.scratch.release(mk);
   }
 };
 
@@ -299,65 +440,153 @@ void hodbf_apply(BfRuntime<T>& rt, const Hodbf<T>& h, const void* X, int64_t ldx
 }
 
 // y = D_node^-1 x (or D_node^-H x) with D^-1 = (I + X_t) diag(D1^-1, D2^-1)
-// per internal node t (Alg. 4): leaves in one grouped GEMM, then per level
-// the butterfly X_t in place (y_t += X_t y_t) and the dense X_t through a
-// copy.  x and y must not overlap.
+// per internal node t (Alg. 4), for several (tree, node, x, y) at once: the
+// leaf inverses of all items in one grouped GEMM, then level by level (the
+// absolute level in each tree) the butterfly X_t of every item in place
+// (y_t += X_t y_t) and the dense X_t through a copy.  x and y of an item must
+// not overlap; different items are independent.
+template <class T>
+void hodbf_inv_apply_many(BfRuntime<T>& rt, const std::vector<HodbfInvItem<T>>& items, bool adjoint) {
+  if (items.empty()) return;
+  const size_t nq = items.size();
+  struct Sub {
+    std::vector<std::vector<int>> lv;
+    int base = 0, n = 0, root_level = 0, max_level = -1;
+    cplx<T>* tmp = nullptr;
+  };
+  std::vector<Sub> sub(nq);
+  int lo = 1 << 30, hi = -1;
+  for (size_t q = 0; q < nq; ++q) {
+    const Hodbf<T>& h = *items[q].h;
+    const HodbfNode<T>& root = h.nodes[items[q].node];
+    Sub& u = sub[q];
+    u.base = root.beg;
+    u.n = root.size();
+    u.root_level = root.level;
+    u.lv.assign(h.max_level + 1, {});
+    std::vector<int> st{items[q].node};
+    while (!st.empty()) {
+      const int i = st.back();
+      st.pop_back();
+      u.lv[h.nodes[i].level].push_back(i);
+      u.max_level = std::max(u.max_level, h.nodes[i].level);
+      if (h.nodes[i].left >= 0) {
+        st.push_back(h.nodes[i].left);
+        st.push_back(h.nodes[i].right);
+      }
+    }
+    lo = std::min(lo, u.root_level);
+    hi = std::max(hi, u.max_level);
+  }
+  auto mk = rt.scratch.mark();
+  auto tmp_of = [&](size_t q) {
+    if (!sub[q].tmp)
+      sub[q].tmp = (cplx<T>*)rt.scratch.take((size_t)std::max(sub[q].n, 1) * items[q].nrhs * sizeof(cplx<T>));
+    return sub[q].tmp;
+  };
+  // dense blocks D (pool offset, rows r0..r0+nb of the item): Y = op(D) S (+ Y)
+  struct DenseBlock {
+    size_t q;
+    int64_t off;
+    int r0, nb;
+  };
+  auto run_dense = [&](const std::vector<DenseBlock>& bl, bool from_tmp, bool accumulate) {
+    std::vector<GTask> ph;
+    for (auto& b : bl) {
+      if (b.nb <= 0) continue;
+      const HodbfInvItem<T>& it = items[b.q];
+      GTask t = {};
+      t.a_off = b.off;
+      t.lda = b.nb;
+      t.opA = (int8_t)(adjoint ? OP_C : OP_N);
+      t.abase = 0;
+      t.b_off = from_tmp ? eaddr<T>(sub[b.q].tmp) + b.r0 : eaddr<T>(it.X) + b.r0;
+      t.ldb = from_tmp ? std::max(sub[b.q].n, 1) : it.ldx;
+      t.bbase = 4;
+      t.c_off = eaddr<T>(it.Y) + b.r0;
+      t.ldc = it.ldy;
+      t.cbase = 4;
+      t.M = b.nb;
+      t.N = it.nrhs;
+      t.K = b.nb;
+      t.alpha_re = 1;
+      t.beta = (int8_t)(accumulate ? 1 : 0);
+      ph.push_back(t);
+    }
+    if (ph.empty()) return;
+    BfPlan p;
+    p.phase.push_back(ph);
+    const int64_t lim[4] = {(int64_t)(rt.pool.used / sizeof(cplx<T>)), 0, 0, 0};
+    run_plan<T>(p, *rt.c, rt.pool_base(), nullptr, nullptr, nullptr, rt.s(), lim);
+  };
+  std::vector<DenseBlock> leaves;
+  for (size_t q = 0; q < nq; ++q)
+    for (auto& lvl : sub[q].lv)
+      for (int i : lvl) {
+        const auto& nd = items[q].h->nodes[i];
+        if (nd.left < 0) leaves.push_back(DenseBlock{q, nd.inv_off, nd.beg - sub[q].base, nd.size()});
+      }
+  auto copy_all = [&](const std::vector<size_t>& qs, bool x_to_y) {  // y = x, or tmp = y
+    std::vector<AxpbyTask> tk;
+    for (size_t q : qs) {
+      const HodbfInvItem<T>& it = items[q];
+      if (x_to_y)
+        tk.push_back(axt(it.Y, it.ldy, it.X, it.ldx, sub[q].n, it.nrhs));
+      else
+        tk.push_back(axt(tmp_of(q), std::max(sub[q].n, 1), it.Y, it.ldy, sub[q].n, it.nrhs));
+    }
+    axpby_many<T>(rt, tk, 1.0, 0.0);
+  };
+  auto level_update = [&](int l) {  // y_t += X_t^(H) y_t for the internal nodes of level l of every item
+    std::vector<BfCall> calls;
+    std::vector<DenseBlock> dense;
+    std::vector<size_t> need_copy;
+    for (size_t q = 0; q < nq; ++q) {
+      if (l < sub[q].root_level || l > sub[q].max_level) continue;
+      const HodbfInvItem<T>& it = items[q];
+      bool copied = false;
+      for (int i : sub[q].lv[l]) {
+        const auto& nd = it.h->nodes[i];
+        if (nd.left < 0 || nd.x_zero) continue;
+        const int r0 = nd.beg - sub[q].base;
+        if (nd.x_dense) {
+          if (!copied) need_copy.push_back(q);
+          copied = true;
+          dense.push_back(DenseBlock{q, nd.inv_off, r0, nd.size()});
+        } else {
+          // in place: the first phase of a product reads y before its last phase writes it
+          BfCall c{nd.x.get(), r0, r0, 1.0, 0.0, 1};
+          c.x_abs = c.y_abs = eaddr<T>(it.Y);
+          c.ldx = c.ldy = it.ldy;
+          c.nrhs = it.nrhs;
+          calls.push_back(c);
+        }
+      }
+    }
+    if (!dense.empty()) {
+      copy_all(need_copy, false);
+      run_dense(dense, true, true);
+    }
+    rt.apply_calls(calls, adjoint);
+  };
+  std::vector<size_t> all(nq);
+  for (size_t q = 0; q < nq; ++q) all[q] = q;
+  if (!adjoint) {
+    run_dense(leaves, false, false);
+    for (int l = hi; l >= lo; --l) level_update(l);
+  } else {
+    copy_all(all, true);
+    for (int l = lo; l <= hi; ++l) level_update(l);
+    copy_all(all, false);
+    run_dense(leaves, true, false);
+  }
+  rt.scratch.release(mk);
+}
+
 template <class T>
 void hodbf_inv_apply(BfRuntime<T>& rt, const Hodbf<T>& h, int node, const void* X, int64_t ldx, void* Y, int64_t ldy,
                      int nrhs, bool adjoint) {
-  const HodbfNode<T>& root = h.nodes[node];
-  const int base = root.beg, n = root.size();
-  // nodes of the subtree grouped by level
-  std::vector<std::vector<int>> lv(h.max_level + 1);
-  std::vector<int> st{node};
-  while (!st.empty()) {
-    int i = st.back();
-    st.pop_back();
-    lv[h.nodes[i].level].push_back(i);
-    if (h.nodes[i].left >= 0) {
-      st.push_back(h.nodes[i].left);
-      st.push_back(h.nodes[i].right);
-    }
-  }
-  cplx<T>* y = (cplx<T>*)Y;
-  auto mk = rt.scratch.mark();
-  cplx<T>* tmp = nullptr;  // n x nrhs copy of y, for dense X_t and the adjoint leaves
-  auto copy_y = [&]() {
-    if (!tmp) tmp = (cplx<T>*)rt.scratch.take((size_t)std::max(n, 1) * nrhs * sizeof(cplx<T>));
-    axpby<T>(rt, tmp, n, y, ldy, n, nrhs, 1.0, 0.0);
-  };
-  std::vector<std::pair<int64_t, std::pair<int, int>>> leaves;
-  for (int l = 0; l <= h.max_level; ++l)
-    for (int i : lv[l])
-      if (h.nodes[i].left < 0) leaves.push_back({h.nodes[i].inv_off, {h.nodes[i].beg - base, h.nodes[i].size()}});
-  auto level_update = [&](int l) {  // y_t += X_t^(H) y_t for the internal nodes of level l
-    std::vector<BfCall> calls;
-    std::vector<std::pair<int64_t, std::pair<int, int>>> dense;
-    for (int i : lv[l]) {
-      const auto& nd = h.nodes[i];
-      if (nd.left < 0 || nd.x_zero) continue;
-      if (nd.x_dense)
-        dense.push_back({nd.inv_off, {nd.beg - base, nd.size()}});
-      else
-        calls.push_back(BfCall{nd.x.get(), nd.beg - base, nd.beg - base, 1.0, 0.0, 1});
-    }
-    if (!dense.empty()) {
-      copy_y();
-      dense_blocks<T>(rt, dense, adjoint, tmp, n, y, ldy, nrhs, true);
-    }
-    // in place: the first phase of a product reads y before its last phase writes it
-    if (!calls.empty()) rt.apply_set(calls, y, ldy, y, ldy, nrhs, adjoint);
-  };
-  if (!adjoint) {
-    dense_blocks<T>(rt, leaves, false, X, ldx, y, ldy, nrhs, false);
-    for (int l = h.max_level; l >= root.level; --l) level_update(l);
-  } else {
-    axpby<T>(rt, y, ldy, X, ldx, n, nrhs, 1.0, 0.0);
-    for (int l = root.level; l <= h.max_level; ++l) level_update(l);
-    copy_y();
-    dense_blocks<T>(rt, leaves, true, tmp, n, y, ldy, nrhs, false);
-  }
-  rt.scratch.release(mk);
+  hodbf_inv_apply_many<T>(rt, {HodbfInvItem<T>{&h, node, X, ldx, Y, ldy, nrhs}}, adjoint);
 }
 
 template void hodbf_apply<double>(BfRuntime<double>&, const Hodbf<double>&, const void*, int64_t, void*, int64_t, int);
@@ -366,6 +595,8 @@ template void hodbf_inv_apply<double>(BfRuntime<double>&, const Hodbf<double>&, 
 template void hodbf_apply<float>(BfRuntime<float>&, const Hodbf<float>&, const void*, int64_t, void*, int64_t, int);
 template void hodbf_inv_apply<float>(BfRuntime<float>&, const Hodbf<float>&, int, const void*, int64_t, void*,
                                      int64_t, int, bool);
+template void hodbf_inv_apply_many<double>(BfRuntime<double>&, const std::vector<HodbfInvItem<double>>&, bool);
+template void hodbf_inv_apply_many<float>(BfRuntime<float>&, const std::vector<HodbfInvItem<float>>&, bool);
 
 // ------------------------------------------------------------ BF_SMW
 namespace {

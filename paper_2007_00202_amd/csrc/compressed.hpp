@@ -56,4 +56,18 @@ template <class T>
 void hodbf_inv_apply(BfRuntime<T>& rt, const Hodbf<T>& h, int node, const void* X, int64_t ldx, void* Y, int64_t ldy,
                      int nrhs, bool adjoint);
 
+// one (tree, node, x, y) of a batched inverse product
+template <class T>
+struct HodbfInvItem {
+  const Hodbf<T>* h;
+  int node;
+  const void* X;
+  int64_t ldx;
+  void* Y;
+  int64_t ldy;
+  int nrhs;
+};
+template <class T>
+void hodbf_inv_apply_many(BfRuntime<T>& rt, const std::vector<HodbfInvItem<T>>& items, bool adjoint);
+
 }  // namespace bfmf

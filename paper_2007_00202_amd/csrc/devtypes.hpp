@@ -81,4 +81,12 @@ struct ExtractTask {
   const FrontDesc* fd;  // otherwise: the front (device descriptor)
 };
 
+// One y = a x + b y of a batch (complex<T> blocks m x ncol; x may be null: y = b y)
+struct AxpbyTask {
+  void* Y;
+  const void* X;
+  int64_t ldy, ldx, m;
+  int32_t ncol, pad;
+};
+
 }  // namespace bfmf

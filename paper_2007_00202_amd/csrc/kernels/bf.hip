@@ -651,6 +651,25 @@ __global__ void axpby_kernel(cplx<T>* __restrict__ Y, int64_t ldy, const cplx<T>
   Y[i + (int64_t)c * ldy] = y;
 }
 
+// y_t = a x_t + b y_t for every task t of a batch (b = 0 overwrites); blockIdx.x
+// is the task, the threads of blockIdx.y stride over its entries
+template <class T>
+__global__ __launch_bounds__(256) void axpby_batch_kernel(const AxpbyTask* __restrict__ tasks, double a, double b) {
+  const AxpbyTask& t = tasks[blockIdx.x];
+  const int64_t tot = t.m * t.ncol;
+  cplx<T>* Y = (cplx<T>*)t.Y;
+  const cplx<T>* X = (const cplx<T>*)t.X;
+  for (int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.y * 256) {
+    const int64_t i = e % t.m, c = e / t.m;
+    const cplx<T> x = X ? X[i + c * t.ldx] : cplx<T>{0, 0};
+    cplx<T> y = {0, 0};
+    if (b != 0) y = Y[i + c * t.ldy];
+    y.re = (T)(a * x.re + b * y.re);
+    y.im = (T)(a * x.im + b * y.im);
+    Y[i + c * t.ldy] = y;
+  }
+}
+
 // Y(i, j) = v if i == j + off, else 0, on an m x ncol block
 template <class T>
 __global__ void set_eye_kernel(cplx<T>* __restrict__ Y, int64_t ldy, int64_t m, int ncol, int64_t off, double v) {
@@ -784,6 +803,15 @@ hipError_t launch_axpby(void* Y, int64_t ldy, const void* X, int64_t ldx, int64_
 }
 
 template <class T>
+hipError_t launch_axpby_batch(const AxpbyTask* d_tasks, int ntasks, int64_t max_entries, double a, double b,
+                              hipStream_t s) {
+  if (ntasks == 0 || max_entries == 0) return hipSuccess;
+  const unsigned yb = (unsigned)std::min<int64_t>(64, std::max<int64_t>(1, (max_entries + 4095) / 4096));
+  hipLaunchKernelGGL((axpby_batch_kernel<T>), dim3(ntasks, yb), dim3(256), 0, s, d_tasks, a, b);
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t launch_set_eye(void* Y, int64_t ldy, int64_t m, int ncol, int64_t off, double v, hipStream_t s) {
   if (m == 0 || ncol == 0) return hipSuccess;
   hipLaunchKernelGGL((set_eye_kernel<T>), dim3((unsigned)((m + 255) / 256), (unsigned)std::min(ncol, 65535)), dim3(256),
@@ -821,7 +849,8 @@ hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int6
   template hipError_t launch_gather_rows<T>(const void*, int64_t, void*, int64_t, const int32_t*, int, int, bool,     \
                                             hipStream_t);                                                             \
   template hipError_t launch_axpby<T>(void*, int64_t, const void*, int64_t, int64_t, int, double, double, hipStream_t); \
-  template hipError_t launch_set_eye<T>(void*, int64_t, int64_t, int, int64_t, double, hipStream_t);
+  template hipError_t launch_set_eye<T>(void*, int64_t, int64_t, int, int64_t, double, hipStream_t);               \
+  template hipError_t launch_axpby_batch<T>(const AxpbyTask*, int, int64_t, double, double, hipStream_t);
 INST(double)
 INST(float)
 template hipError_t launch_axpby_mixed<double, float>(void*, int64_t, const void*, int64_t, int64_t, int, double,

@@ -112,6 +112,10 @@ hipError_t launch_gather_rows(const void* X, int64_t ldx, void* Y, int64_t ldy, 
 template <class T>
 hipError_t launch_axpby(void* Y, int64_t ldy, const void* X, int64_t ldx, int64_t m, int ncol, double a, double b,
                         hipStream_t s);
+// y_t = a x_t + b y_t for a batch of blocks (max_entries: the largest m ncol)
+template <class T>
+hipError_t launch_axpby_batch(const AxpbyTask* d_tasks, int ntasks, int64_t max_entries, double a, double b,
+                              hipStream_t s);
 // Y(i, j) = v when i == j + off, else 0 (m x ncol block)
 template <class T>
 hipError_t launch_set_eye(void* Y, int64_t ldy, int64_t m, int ncol, int64_t off, double v, hipStream_t s);
