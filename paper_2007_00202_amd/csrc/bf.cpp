@@ -426,12 +426,17 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
   std::vector<char> blob;
   std::vector<size_t> toff, soff;
   std::vector<int64_t> ntiles;
+  std::vector<char> skinny;
   for (auto& ph : plan.phase) {
+    // at most 16 columns and no transposes: 256-row streaming tiles, else 64 x 64 tiles
+    bool sk = !ph.empty();
+    for (const GTask& t : ph) sk = sk && t.N <= 16 && t.opA == OP_N && t.opB == OP_N;
+    skinny.push_back(sk ? 1 : 0);
     std::vector<int64_t> start(ph.size());
     int64_t tiles = 0;
     for (size_t i = 0; i < ph.size(); ++i) {
       start[i] = tiles;
-      tiles += (int64_t)((ph[i].M + 63) / 64) * ((ph[i].N + 63) / 64);
+      tiles += sk ? (int64_t)((ph[i].M + 255) / 256) : (int64_t)((ph[i].M + 63) / 64) * ((ph[i].N + 63) / 64);
     }
     size_t o = (blob.size() + 15) & ~(size_t)15;
     blob.resize(o + ph.size() * sizeof(GTask) + start.size() * sizeof(int64_t));
@@ -450,7 +455,7 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
     if (plan.phase[k].empty()) continue;
     const int tk = c.timer.want(kind) ? c.timer.begin(s) : -1;
     chk(launch_grouped_gemm<T>((const GTask*)(d + toff[k]), (const int64_t*)(d + soff[k]), (int)plan.phase[k].size(),
-                               ntiles[k], bases, s),
+                               ntiles[k], bases, skinny[k] != 0, s),
         "grouped gemm");
     if (tk >= 0) {
       double fl = 0, by = 0;

@@ -18,14 +18,9 @@
 namespace bfmf {
 
 // ------------------------------------------------------------ grouped GEMM
-template <class T>
-__global__ __launch_bounds__(256) void grouped_gemm_kernel(const GTask* __restrict__ tasks,
-                                                           const int64_t* __restrict__ tile_start, int ntasks,
-                                                           void* b0, void* b1, void* b2, void* b3) {
-  __shared__ GemmSmem<T> sm;
-  const int64_t tile = blockIdx.x;
-  // binary search: last task with tile_start <= tile
-  int lo = 0, hi = ntasks - 1;
+// the task owning grid tile `tile` (tile_start: first tile of each task) and the tile's index in it
+__device__ __forceinline__ int find_task(const int64_t* __restrict__ tile_start, int ntasks, int64_t tile) {
+  int lo = 0, hi = ntasks - 1;  // last task with tile_start <= tile
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (tile_start[mid] <= tile)
@@ -33,24 +28,53 @@ __global__ __launch_bounds__(256) void grouped_gemm_kernel(const GTask* __restri
     else
       hi = mid - 1;
   }
+  return lo;
+}
+
+// operand address = base + offset, in integer arithmetic; base 4 is zero (the offset is the
+// operand's address in elements, for operands scattered over several allocations)
+template <class T>
+__device__ __forceinline__ uintptr_t task_addr(int i, int64_t off, void* b0, void* b1, void* b2, void* b3) {
+  const uintptr_t b = i == 0 ? (uintptr_t)b0 : i == 1 ? (uintptr_t)b1 : i == 2 ? (uintptr_t)b2 : i == 3 ? (uintptr_t)b3 : 0;
+  return b + (uintptr_t)off * sizeof(cplx<T>);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void grouped_gemm_kernel(const GTask* __restrict__ tasks,
+                                                           const int64_t* __restrict__ tile_start, int ntasks,
+                                                           void* b0, void* b1, void* b2, void* b3) {
+  __shared__ GemmSmem<T> sm;
+  const int64_t tile = blockIdx.x;
+  const int lo = find_task(tile_start, ntasks, tile);
   const GTask& t = tasks[lo];
   const int64_t local = tile - tile_start[lo];
   const int tm = (t.M + GEMM_TM - 1) / GEMM_TM;
   const int tn = (t.N + GEMM_TN - 1) / GEMM_TN;
   if (local >= (int64_t)tm * tn || t.M <= 0 || t.N <= 0) return;
-  // select the base pointers without an indexed (scratch) array
-  // operand address = base + offset, in integer arithmetic; base 4 is zero (the offset is the
-  // operand's address in elements, for operands scattered over several allocations)
-  auto addr = [&](int i, int64_t off) -> uintptr_t {
-    const uintptr_t b = i == 0 ? (uintptr_t)b0 : i == 1 ? (uintptr_t)b1 : i == 2 ? (uintptr_t)b2 : i == 3 ? (uintptr_t)b3 : 0;
-    return b + (uintptr_t)off * sizeof(cplx<T>);
-  };
-  const cplx<T>* A = (const cplx<T>*)addr(t.abase, t.a_off);
-  const cplx<T>* B = (const cplx<T>*)addr(t.bbase, t.b_off);
-  cplx<T>* C = (cplx<T>*)addr(t.cbase, t.c_off);
+  const cplx<T>* A = (const cplx<T>*)task_addr<T>(t.abase, t.a_off, b0, b1, b2, b3);
+  const cplx<T>* B = (const cplx<T>*)task_addr<T>(t.bbase, t.b_off, b0, b1, b2, b3);
+  cplx<T>* C = (cplx<T>*)task_addr<T>(t.cbase, t.c_off, b0, b1, b2, b3);
   const cplx<T> alpha = {(T)t.alpha_re, (T)t.alpha_im};
   gemm_tile<T>(A, t.lda, t.opA, B, t.ldb, C, t.ldc, t.M, t.N, t.K, alpha, t.beta, (int)(local % tm), (int)(local / tm),
                sm, t.opB);
+}
+
+// phases whose tasks are all C = beta C + alpha A B (no transposes) with N <= 16: 256-row tiles
+template <class T>
+__global__ __launch_bounds__(256) void grouped_gemm_skinny_kernel(const GTask* __restrict__ tasks,
+                                                                  const int64_t* __restrict__ tile_start, int ntasks,
+                                                                  void* b0, void* b1, void* b2, void* b3) {
+  const int64_t tile = blockIdx.x;
+  const int lo = find_task(tile_start, ntasks, tile);
+  const GTask& t = tasks[lo];
+  const int64_t local = tile - tile_start[lo];
+  const int tm = (t.M + SKINNY_TM - 1) / SKINNY_TM;
+  if (local >= tm || t.M <= 0 || t.N <= 0 || t.N > SKINNY_TN) return;
+  const cplx<T>* A = (const cplx<T>*)task_addr<T>(t.abase, t.a_off, b0, b1, b2, b3);
+  const cplx<T>* B = (const cplx<T>*)task_addr<T>(t.bbase, t.b_off, b0, b1, b2, b3);
+  cplx<T>* C = (cplx<T>*)task_addr<T>(t.cbase, t.c_off, b0, b1, b2, b3);
+  const cplx<T> alpha = {(T)t.alpha_re, (T)t.alpha_im};
+  gemm_tile_skinny<T>(A, t.lda, B, t.ldb, C, t.ldc, t.M, t.N, t.K, alpha, t.beta, (int)local);
 }
 
 // ---------------------------------------------------------------- CPQR ID
@@ -716,11 +740,15 @@ __global__ void convert_kernel(cplx<T1>* __restrict__ Y, int64_t ldy, const cplx
 
 template <class T>
 hipError_t launch_grouped_gemm(const GTask* d_tasks, const int64_t* d_tile_start, int ntasks, int64_t ntiles,
-                               void* const bases[4], hipStream_t s) {
+                               void* const bases[4], bool skinny, hipStream_t s) {
   if (ntasks == 0 || ntiles == 0) return hipSuccess;
   // grids are limited to 2^31 - 1 blocks in x
-  hipLaunchKernelGGL((grouped_gemm_kernel<T>), dim3((unsigned)ntiles), dim3(256), 0, s, d_tasks, d_tile_start, ntasks,
-                     bases[0], bases[1], bases[2], bases[3]);
+  if (skinny)
+    hipLaunchKernelGGL((grouped_gemm_skinny_kernel<T>), dim3((unsigned)ntiles), dim3(256), 0, s, d_tasks,
+                       d_tile_start, ntasks, bases[0], bases[1], bases[2], bases[3]);
+  else
+    hipLaunchKernelGGL((grouped_gemm_kernel<T>), dim3((unsigned)ntiles), dim3(256), 0, s, d_tasks, d_tile_start,
+                       ntasks, bases[0], bases[1], bases[2], bases[3]);
   return hipGetLastError();
 }
 
@@ -837,7 +865,8 @@ hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int6
 }
 
 #define INST(T)                                                                                                       \
-  template hipError_t launch_grouped_gemm<T>(const GTask*, const int64_t*, int, int64_t, void* const[4], hipStream_t); \
+  template hipError_t launch_grouped_gemm<T>(const GTask*, const int64_t*, int, int64_t, void* const[4], bool,        \
+                                             hipStream_t);                                                            \
   template hipError_t launch_cpqr_id<T>(const IdTask*, int, double, hipStream_t);                                     \
   template hipError_t launch_gram_id<T>(const IdTask*, int, double, hipStream_t);                                     \
   template hipError_t launch_id_expand<T>(const IdTask*, int, void* const*, const int64_t*, bool, bool, hipStream_t);  \

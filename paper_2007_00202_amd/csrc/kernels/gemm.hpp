@@ -158,4 +158,82 @@ __device__ __forceinline__ void gemm_tile(const cplx<T>* __restrict__ A, int64_t
       }
 }
 
+// Skinny product for at most 16 right-hand sides: C = beta C + alpha A B with
+// A (M x K, column-major, not transposed) streamed from memory once.  A
+// workgroup computes rows [256 tm, 256 tm + 256) and all N <= 16 columns; wave
+// w owns 64 rows as four 16x16 MFMA blocks and loads its A operands straight
+// into registers in the MFMA layout (lane l: row l%16, k l/16: 16 consecutive
+// rows per k, coalesced), four k-steps ahead of their use.  No LDS.
+constexpr int SKINNY_TM = 256, SKINNY_TN = 16;
+
+template <class T>
+__device__ __forceinline__ void gemm_tile_skinny(const cplx<T>* __restrict__ A, int64_t lda,
+                                                 const cplx<T>* __restrict__ B, int64_t ldb, cplx<T>* __restrict__ C,
+                                                 int64_t ldc, int M, int N, int K, cplx<T> alpha, int beta, int tm) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rbase = tm * SKINNY_TM + wave * 64;
+  if (rbase >= M) return;  // no barrier below: idle waves may leave
+  const int lr = lane & 15, lk = lane >> 4;
+  acc_t accr[4], acci[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      accr[i][r] = 0;
+      acci[i][r] = 0;
+    }
+  constexpr int U = 4;  // k-steps of 4 per batch of loads
+  cplx<T> a0[U][4], b0[U], a1[U][4], b1[U];  // two named batches: no dynamically indexed registers
+  auto load = [&](cplx<T>(&aa)[U][4], cplx<T>(&bb)[U], int k0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + 4 * u + lk;
+      const bool kin = k < K;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = rbase + 16 * i + lr;
+        aa[u][i] = load_or_zero(A + (int64_t)row + (int64_t)k * lda, kin && row < M);
+      }
+      bb[u] = load_or_zero(B + (int64_t)k + (int64_t)lr * ldb, kin && lr < N);
+    }
+  };
+  auto mma = [&](cplx<T>(&aa)[U][4], cplx<T>(&bb)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const cplx<T> bv = bb[u];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const cplx<T> av = aa[u][i];
+        accr[i] = Mfma<T>::step(av.re, bv.re, accr[i]);
+        accr[i] = Mfma<T>::step(-av.im, bv.im, accr[i]);
+        acci[i] = Mfma<T>::step(av.re, bv.im, acci[i]);
+        acci[i] = Mfma<T>::step(av.im, bv.re, acci[i]);
+      }
+    }
+  };
+  if (K > 0) load(a0, b0, 0);
+  for (int k0 = 0; k0 < K; k0 += 8 * U) {
+    if (k0 + 4 * U < K) load(a1, b1, k0 + 4 * U);  // in flight during the MFMAs of a0
+    mma(a0, b0);
+    if (k0 + 4 * U >= K) break;
+    if (k0 + 8 * U < K) load(a0, b0, k0 + 8 * U);  // in flight during the MFMAs of a1
+    mma(a1, b1);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gr = rbase + 16 * i + Mfma<T>::row(lane, r);
+      const int gc = lr;
+      if (gr < M && gc < N) {
+        const T pr = accr[i][r], pi = acci[i][r];
+        cplx<T> v = {alpha.re * pr - alpha.im * pi, alpha.re * pi + alpha.im * pr};
+        cplx<T>* dst = C + (int64_t)gr + (int64_t)gc * ldc;
+        if (beta) v = cadd(*dst, v);
+        *dst = v;
+      }
+    }
+}
+
 }  // namespace bfmf

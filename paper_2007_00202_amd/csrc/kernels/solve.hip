@@ -95,15 +95,17 @@ __global__ __launch_bounds__(256) void fwd_trsv_kernel(const FrontDesc* __restri
 // HBM, prefetched into registers during the previous step, and costs one
 // barrier.
 constexpr int TRSV_MAXNS = 1024;
-constexpr int TRSV_LDS = 6144;  // complex<double> entries (96 KB)
+constexpr int TRSV_LDS = 6144;  // most complex<double> entries of one workgroup's block (96 KB)
 
 template <class T>
-__global__ __launch_bounds__(256) void fwd_trsv_lds_kernel(const FrontDesc* __restrict__ fds, int nrhs, int nc) {
+__global__ __launch_bounds__(256) void fwd_trsv_lds_kernel(const FrontDesc* __restrict__ fds, int nrhs, int nc,
+                                                           int cap) {
   const FrontDesc& fd = fds[blockIdx.x];
   const int n = fd.n, ns = fd.ns;
   const int c0 = blockIdx.y * nc, ncl = min(nc, nrhs - c0);
-  if (ns == 0 || ncl <= 0 || ns > TRSV_MAXNS || ns * ncl > TRSV_LDS) return;  // the host never sends these
-  __shared__ cplx<T> w[TRSV_LDS];  // w[r + c ns]
+  if (ns == 0 || ncl <= 0 || ns > TRSV_MAXNS || ns * ncl > cap) return;  // the host never sends these
+  extern __shared__ __align__(16) unsigned char trsv_smem[];
+  cplx<T>* w = (cplx<T>*)trsv_smem;  // w[r + c ns], cap entries (dynamic, sized for the level)
   const cplx<T>* F = (const cplx<T>*)fd.F;
   cplx<T>* W = (cplx<T>*)fd.W + (int64_t)c0 * n;
   const int tid = threadIdx.x;
@@ -118,77 +120,91 @@ __global__ __launch_bounds__(256) void fwd_trsv_lds_kernel(const FrontDesc* __re
         w[p + tid * ns] = t;
       }
     }
-  cplx<T> lc[4], ln[4];
+  // columns j .. j+7 of L (this thread's rows) in a register ring, refilled 8 columns ahead
+  constexpr int D = 8;
+  cplx<T> ring[D][4];
+  auto fetch = [&](cplx<T>(&c)[4], int j) {
+    const int jj = j < ns ? j : 0;  // addresses stay inside the front
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int r = tid + 256 * q;
-    lc[q] = load_or_zero(F + r, r > 0 && r < ns);
-  }
-  __syncthreads();
-  for (int j = 0; j < ns - 1; ++j) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {  // next column of L, in flight during this step
+    for (int q = 0; q < 4; ++q) {
       const int r = tid + 256 * q;
-      ln[q] = load_or_zero(F + r + (int64_t)(j + 1) * n, r > j + 1 && r < ns);
+      const bool ok = j < ns && r > j && r < ns;
+      c[q] = load_or_zero(F + (ok ? r : 0) + (int64_t)jj * n, ok);
     }
-    for (int c = 0; c < ncl; ++c) {
-      const cplx<T> wj = w[j + c * ns];
+  };
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = tid + 256 * q;
-        if (r > j && r < ns) w[r + c * ns] = csub(w[r + c * ns], cmul(lc[q], wj));
+  for (int u = 0; u < D; ++u) fetch(ring[u], u);
+  __syncthreads();
+  for (int j0 = 0; j0 < ns - 1; j0 += D) {
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      const int j = j0 + u;
+      if (j < ns - 1) {  // uniform across the workgroup
+        for (int c = 0; c < ncl; ++c) {
+          const cplx<T> wj = w[j + c * ns];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = tid + 256 * q;
+            if (r > j && r < ns) w[r + c * ns] = csub(w[r + c * ns], cmul(ring[u][q], wj));
+          }
+        }
+        fetch(ring[u], j + D);
+        __syncthreads();
       }
     }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) lc[q] = ln[q];
   }
   for (int e = tid; e < ns * ncl; e += 256) W[e % ns + (int64_t)(e / ns) * n] = w[e];
 }
 
 template <class T>
 __global__ __launch_bounds__(256) void bwd_trsv_lds_kernel(const FrontDesc* __restrict__ fds, cplx<T>* __restrict__ x,
-                                                           int64_t N, int nrhs, int nc) {
+                                                           int64_t N, int nrhs, int nc, int cap) {
   const FrontDesc& fd = fds[blockIdx.x];
   const int n = fd.n, ns = fd.ns;
   const int c0 = blockIdx.y * nc, ncl = min(nc, nrhs - c0);
-  if (ns == 0 || ncl <= 0 || ns > TRSV_MAXNS || ns * ncl > TRSV_LDS) return;  // the host never sends these
-  __shared__ cplx<T> w[TRSV_LDS];
+  if (ns == 0 || ncl <= 0 || ns > TRSV_MAXNS || ns * ncl > cap) return;  // the host never sends these
+  extern __shared__ __align__(16) unsigned char trsv_smem[];
+  cplx<T>* w = (cplx<T>*)trsv_smem;
   const cplx<T>* F = (const cplx<T>*)fd.F;
   const cplx<T>* W = (const cplx<T>*)fd.W + (int64_t)c0 * n;
   const int tid = threadIdx.x;
   for (int e = tid; e < ns * ncl; e += 256) w[e] = W[e % ns + (int64_t)(e / ns) * n];
-  cplx<T> uc[4], un[4];
-  cplx<T> dc = F[(ns - 1) + (int64_t)(ns - 1) * n], dn = {0, 0};
+  // columns j, j-1, ..., j-7 of U (this thread's rows) and their diagonals in a register ring,
+  // refilled 8 columns ahead
+  constexpr int D = 8;
+  cplx<T> ring[D][4], dg[D];
+  auto fetch = [&](cplx<T>(&c)[4], cplx<T>& d, int j) {
+    const int jj = j >= 0 ? j : 0;  // addresses stay inside the front
+    d = load_or_zero(F + jj + (int64_t)jj * n, j >= 0);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int r = tid + 256 * q;
-    uc[q] = load_or_zero(F + r + (int64_t)(ns - 1) * n, r < ns - 1);
-  }
+    for (int q = 0; q < 4; ++q) {
+      const int r = tid + 256 * q;
+      const bool ok = j >= 0 && r < j;
+      c[q] = load_or_zero(F + (ok ? r : 0) + (int64_t)jj * n, ok);
+    }
+  };
+#pragma unroll
+  for (int u = 0; u < D; ++u) fetch(ring[u], dg[u], ns - 1 - u);
   __syncthreads();
-  for (int j = ns - 1; j >= 0; --j) {
-    if (j > 0) {  // column j-1 of U and its diagonal, in flight during this step
-      dn = F[(j - 1) + (int64_t)(j - 1) * n];
+  for (int j0 = ns - 1; j0 >= 0; j0 -= D) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = tid + 256 * q;
-        un[q] = load_or_zero(F + r + (int64_t)(j - 1) * n, r < j - 1);
+    for (int u = 0; u < D; ++u) {
+      const int j = j0 - u;
+      if (j >= 0) {  // uniform across the workgroup
+        // every thread forms x_j = w_j / U_jj itself; w_j stays unscaled (a store here would race with
+        // the reads of other waves) and is divided when the result is written out
+        for (int c = 0; c < ncl; ++c) {
+          const cplx<T> wj = cdiv(w[j + c * ns], dg[u]);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = tid + 256 * q;
+            if (r < j) w[r + c * ns] = csub(w[r + c * ns], cmul(ring[u][q], wj));
+          }
+        }
+        fetch(ring[u], dg[u], j - D);
+        __syncthreads();
       }
     }
-    // every thread forms x_j = w_j / U_jj itself; w_j stays unscaled (a store here would race with
-    // the reads of other waves) and is divided when the result is written out
-    for (int c = 0; c < ncl; ++c) {
-      const cplx<T> wj = cdiv(w[j + c * ns], dc);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = tid + 256 * q;
-        if (r < j) w[r + c * ns] = csub(w[r + c * ns], cmul(uc[q], wj));
-      }
-    }
-    __syncthreads();
-    dc = dn;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) uc[q] = un[q];
   }
   for (int e = tid; e < ns * ncl; e += 256) {
     const int r = e % ns;
@@ -266,6 +282,23 @@ __global__ __launch_bounds__(256) void sweep_gemm_kernel(const FrontDesc* __rest
   else
     gemm_tile<T>(F + (int64_t)ns * n, n, OP_N, W + ns, n, W, n, ns, nrhs, nu, cplx<T>{-1, 0}, 1, t % tm, t / tm,
                  sm);
+}
+
+// the same products for at most 16 right-hand sides: 256-row streaming tiles (F21 / F12 read once)
+template <class T>
+__global__ __launch_bounds__(256) void sweep_gemm_skinny_kernel(const FrontDesc* __restrict__ fds, int nrhs, int mode) {
+  const FrontDesc& fd = fds[blockIdx.y];
+  const int n = fd.n, ns = fd.ns, nu = n - ns;
+  if (ns == 0 || nu == 0 || nrhs > SKINNY_TN) return;
+  const cplx<T>* F = (const cplx<T>*)fd.F;
+  cplx<T>* W = (cplx<T>*)fd.W;
+  const int M = mode == 0 ? nu : ns;
+  const int t = blockIdx.x;
+  if (t * SKINNY_TM >= M) return;
+  if (mode == 0)
+    gemm_tile_skinny<T>(F + ns, n, W, n, W + ns, n, nu, nrhs, ns, cplx<T>{-1, 0}, 1, t);
+  else
+    gemm_tile_skinny<T>(F + (int64_t)ns * n, n, W + ns, n, W, n, ns, nrhs, nu, cplx<T>{-1, 0}, 1, t);
 }
 
 // ------------------------------------------------------------ GMRES vectors
@@ -392,13 +425,19 @@ hipError_t launch_forward_level(const FrontDesc* d_fds, int nbatch, int maxn, in
                      (const cplx<T>*)y, N, nrhs);
   KCHECK(hipGetLastError());
   const int nc = sizeof(T) == 8 ? trsv_lds_cols(maxns, nrhs) : 0;
-  if (nc > 0)
-    hipLaunchKernelGGL((fwd_trsv_lds_kernel<T>), dim3(nbatch, (nrhs + nc - 1) / nc), dim3(256), 0, s, d_fds, nrhs, nc);
+  if (nc > 0)  // LDS sized to the level's largest front: small fronts share a CU
+    hipLaunchKernelGGL((fwd_trsv_lds_kernel<T>), dim3(nbatch, (nrhs + nc - 1) / nc), dim3(256),
+                       (size_t)maxns * nc * sizeof(cplx<T>), s, d_fds, nrhs, nc, maxns * nc);
   else
     hipLaunchKernelGGL((fwd_trsv_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, nrhs);
   KCHECK(hipGetLastError());
-  const int tiles = (int)(blocks_for(maxn, GEMM_TM) * blocks_for(nrhs, GEMM_TN));
-  hipLaunchKernelGGL((sweep_gemm_kernel<T>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs, 0);
+  if (nrhs <= SKINNY_TN) {
+    hipLaunchKernelGGL((sweep_gemm_skinny_kernel<T>), dim3((unsigned)blocks_for(maxn, SKINNY_TM), nbatch), dim3(256), 0,
+                       s, d_fds, nrhs, 0);
+  } else {
+    const int tiles = (int)(blocks_for(maxn, GEMM_TM) * blocks_for(nrhs, GEMM_TN));
+    hipLaunchKernelGGL((sweep_gemm_kernel<T>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs, 0);
+  }
   return hipGetLastError();
 }
 
@@ -410,14 +449,19 @@ hipError_t launch_backward_level(const FrontDesc* d_fds, int nbatch, int maxn, i
     hipLaunchKernelGGL((bwd_gather_kernel<T>), dim3(blocks_for(maxnu, 256), nbatch), dim3(256), 0, s, d_fds,
                        (const cplx<T>*)x, N, nrhs);
     KCHECK(hipGetLastError());
-    const int tiles = (int)(blocks_for(maxn, GEMM_TM) * blocks_for(nrhs, GEMM_TN));
-    hipLaunchKernelGGL((sweep_gemm_kernel<T>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs, 1);
+    if (nrhs <= SKINNY_TN) {
+      hipLaunchKernelGGL((sweep_gemm_skinny_kernel<T>), dim3((unsigned)blocks_for(maxn, SKINNY_TM), nbatch), dim3(256),
+                         0, s, d_fds, nrhs, 1);
+    } else {
+      const int tiles = (int)(blocks_for(maxn, GEMM_TM) * blocks_for(nrhs, GEMM_TN));
+      hipLaunchKernelGGL((sweep_gemm_kernel<T>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs, 1);
+    }
     KCHECK(hipGetLastError());
   }
   const int nc = sizeof(T) == 8 ? trsv_lds_cols(maxns, nrhs) : 0;
   if (nc > 0)
-    hipLaunchKernelGGL((bwd_trsv_lds_kernel<T>), dim3(nbatch, (nrhs + nc - 1) / nc), dim3(256), 0, s, d_fds,
-                       (cplx<T>*)x, N, nrhs, nc);
+    hipLaunchKernelGGL((bwd_trsv_lds_kernel<T>), dim3(nbatch, (nrhs + nc - 1) / nc), dim3(256),
+                       (size_t)maxns * nc * sizeof(cplx<T>), s, d_fds, (cplx<T>*)x, N, nrhs, nc, maxns * nc);
   else
     hipLaunchKernelGGL((bwd_trsv_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, (cplx<T>*)x, N, nrhs);
   return hipGetLastError();

@@ -56,3 +56,21 @@ def test_grf_velocity_compressed(gpu_lib, precision):
     res = mf.rel_residual(p.rowptr, p.colind, p.values, X, p.rhs).max()
     assert info["status"] == 0 and err <= 1e-2 and res <= 1e-3, (err, res, info)
     s.close()
+
+
+def test_poisson_compressed(gpu_lib):
+    """omega = 0 (3D Poisson) on the same path, beside the Helmholtz operator of the same grid:
+    both compressed solves within the bound."""
+    for name in ("poisson100", "helmholtz100"):
+        p = make_problem(name, n=20, nrhs=2)
+        od = nd.nd_grid(p.dims, leaf_max=64, sep_leaf=32)
+        x_or = mf.solve(mf.factor(p.rowptr, p.colind, p.values, od), p.rhs)
+        s = gpu_lib.Solver(0).analyze(p.rowptr, p.colind, p.values, dims=p.dims, leaf_max=64, sep_leaf=32)
+        s.factor(tol=1e-3, n_min=100, batched=True, precision=gpu_lib.BFMF_C64_MIXED)
+        st = s.stats()
+        assert st["compressed_fronts"] >= 3
+        X, info = s.solve(p.rhs, true_rtol=1e-3)
+        err = np.linalg.norm(X - x_or) / np.linalg.norm(x_or)
+        res = mf.rel_residual(p.rowptr, p.colind, p.values, X, p.rhs).max()
+        assert info["status"] == 0 and err <= 1e-2 and res <= 1e-3, (name, err, res, info)
+        s.close()

@@ -41,6 +41,10 @@ CONFIGS = {
     # 128^3 GRF velocity, batched levels, 32 RHS (damping not stated: 0.02 as above)
     "helmholtz128grf": dict(kind="grid", n=128, delta=0.02, nrhs=32, rhs="points",
                             n_min=1024, tol=1e-3, precision="c64", samples=64, grf=True),
+    # 3D Poisson (omega = 0) on the same path: the separator ranks grow far more slowly than at
+    # high frequency, the first comparison workload after the Helmholtz runs
+    "poisson100": dict(kind="grid", n=100, delta=0.0, nrhs=8, rhs="points", omega=0.0,
+                       n_min=1024, tol=1e-3, precision="c64", samples=64),
     # Yee curl-curl 64^3 cells, eps on 8^3 blocks in U[1,4], delta 0.03, 16 RHS
     "maxwell64": dict(kind="yee", n=64, delta=0.03, nrhs=16, rhs="dipoles",
                       n_min=1024, tol=1e-3, precision="c64", samples=64),
@@ -63,6 +67,8 @@ def make_problem(name, n=None, nrhs=None, delta=None, grf=None, config_id=None,
     if grf is not None:
         cfg["grf"] = grf
     seed_cfg = name if config_id is None else config_id
+    if omega is None:
+        omega = cfg.get("omega")
     nn = cfg["n"]
     if cfg["kind"] == "grid":
         dims = (nn, nn, nn)

@@ -14,6 +14,7 @@ CONFIG_IDS = {
     "helmholtz128grf": 3, # 128^3 heterogeneous velocity, batched levels
     "maxwell64": 4,       # Yee curl-curl on 64^3 cells
     "serving": 5,         # three resident factorizations
+    "poisson100": 6,      # 3D Poisson, omega = 0
     "test": 99,           # small grids used by the test-suite
 }
 
