@@ -83,7 +83,8 @@ typedef struct {
     double alpha;        /* uniform over-sampling factor for proxy sampling */
     uint64_t seed;       /* seed of the device Philox probe generator */
     uint64_t hbm_budget; /* bytes the factorization may use; 0 = all free memory */
-    int32_t keep_fronts; /* debug: keep a copy of every assembled dense front */
+    int32_t keep_fronts; /* debug: keep a copy of every assembled dense front, and every
+                            factored front whole (no reuse of the level workspaces) */
     int32_t timing;      /* 1: time every kernel class with HIP events (bfmf_get_kernel_stats) */
     int32_t reserved[6];
 } bfmf_factor_opts;
@@ -190,7 +191,9 @@ bfmf_status bfmf_get_stats(bfmf_handle h, bfmf_stats* out);
 
 /* Debug access to a dense front after bfmf_factor, copied to host memory:
  *   what = 0: the assembled front F (needs keep_fronts), n x n
- *   what = 1: the factored front [LU F12'; F21' C], n x n
+ *   what = 1: the factored front [LU F12'; F21' C], n x n; the contribution
+ *             block C only with keep_fronts, zeros otherwise (it lives in a
+ *             level workspace that later levels reuse)
  *   what = 2: the pivot sequence of F11 (ns int32 values, 0-based, LAPACK
  *             interchange convention), written to out as int32
  * n = #I^s + #I^u of the front; out has leading dimension ld >= n.
@@ -203,7 +206,8 @@ bfmf_status bfmf_get_front(bfmf_handle h, int32_t front, int32_t what, void* out
  * triangular solves, rank-32 updates), 2 Schur GEMM C = F22 - F21 F12,
  * 3 forward sweep level, 4 backward sweep level, 5 SpMV, 6 GMRES vector ops,
  * 7 butterfly grouped GEMMs (products of butterflies and the GEMMs of their
- * constructions), 8 interpolative decompositions, 9 entry extraction.
+ * constructions), 8 interpolative decompositions, 9 entry extraction,
+ * 10 copy of the dense fronts' factors out of the level workspace.
  * launches counts the timed launches and launches_all every launch of the
  * class; class 7 times one launch in eight, the others every launch.
  * seconds, flops and bytes (algorithmic counts) cover the timed launches.
@@ -216,7 +220,7 @@ typedef struct {
     double bytes;
     int64_t launches_all;
 } bfmf_kernel_stat;
-enum { BFMF_KERNEL_CLASSES = 10 };
+enum { BFMF_KERNEL_CLASSES = 11 };
 bfmf_status bfmf_get_kernel_stats(bfmf_handle h, int32_t kind, bfmf_kernel_stat* out);
 bfmf_status bfmf_reset_kernel_stats(bfmf_handle h);
 

@@ -48,7 +48,7 @@ class bfmf_kernel_stat(C.Structure):
                 ("flops", C.c_double), ("bytes", C.c_double), ("launches_all", C.c_int64)]
 
 
-BFMF_KERNEL_CLASSES = 10
+BFMF_KERNEL_CLASSES = 11
 
 
 class bfmf_solve_opts(C.Structure):

@@ -148,7 +148,8 @@ bfmf_status bfmf_analyze(bfmf_handle h, int64_t n, const int64_t* rowptr, const 
     if (!symbolic_phase(n, rowptr, colind, h->sym, err)) throw Error(BFMF_E_INVAL, err);
     build_plan(*h);
     if (h->device >= 0) upload_plan(*h);
-    h->d_arena.release();
+    h->d_work.release();
+    h->d_fac.release();
     h->d_kept.release();
     h->analyze_seconds = now_s() - t0;
     h->stats.analyze_seconds = h->analyze_seconds;
@@ -294,24 +295,31 @@ bfmf_status bfmf_get_front(bfmf_handle h, int32_t front, int32_t what, void* out
       return;
     }
     if (ld < p.n) throw Error(BFMF_E_INVAL, "get_front: ld < n");
-    const DevBuf* src = nullptr;
-    if (what == 0) {
-      if (!h->fopts.keep_fronts) throw Error(BFMF_E_INVAL, "get_front: assembled fronts not kept");
-      src = &h->d_kept;
-    } else if (what == 1) {
-      src = &h->d_arena;
-    } else {
-      throw Error(BFMF_E_INVAL, "get_front: bad 'what'");
+    if (h->compressed[front]) throw Error(BFMF_E_INVAL, "get_front: front is compressed");
+    if (what == 0 && !h->fopts.keep_fronts) throw Error(BFMF_E_INVAL, "get_front: assembled fronts not kept");
+    if (what != 0 && what != 1) throw Error(BFMF_E_INVAL, "get_front: bad 'what'");
+    if (h->fopts.keep_fronts) {  // whole fronts, each in a slot of its own
+      const DevBuf& src = what == 0 ? h->d_kept : h->d_work;
+      HIPCHK(hipMemcpy2D(out, ld * elem, src.as<char>() + p.f_off * elem, p.n * elem, p.n * elem, p.n,
+                         hipMemcpyDeviceToHost));
+      return;
     }
-    HIPCHK(hipMemcpy2D(out, ld * elem, src->as<char>() + p.f_off * elem, p.n * elem, p.n * elem, p.n,
-                       hipMemcpyDeviceToHost));
+    // the kept factor: [L U; F21'] then F12'; the contribution block has been reused
+    char* o = (char*)out;
+    for (int64_t j = 0; j < p.n; ++j) std::memset(o + j * ld * elem, 0, p.n * elem);
+    const char* P = h->d_fac.as<char>() + p.p_off * elem;
+    if (p.ns > 0)
+      HIPCHK(hipMemcpy2D(o, ld * elem, P, p.n * elem, p.n * elem, p.ns, hipMemcpyDeviceToHost));
+    if (p.ns > 0 && p.nu > 0)
+      HIPCHK(hipMemcpy2D(o + p.ns * ld * elem, ld * elem, P + (int64_t)p.n * p.ns * elem, p.ns * elem, p.ns * elem,
+                         p.nu, hipMemcpyDeviceToHost));
   });
 }
 
 bfmf_status bfmf_get_kernel_stats(bfmf_handle h, int32_t kind, bfmf_kernel_stat* out) {
   static const char* names[K_COUNT] = {"assemble",      "panel_lu",       "schur_gemm",     "forward_sweep",
                                        "backward_sweep", "spmv",           "gmres_vector",   "butterfly_gemm",
-                                       "interp_decomp",  "entry_extract"};
+                                       "interp_decomp",  "entry_extract",  "factor_store"};
   if (!h || !out || kind < 0 || kind >= K_COUNT) return BFMF_E_INVAL;
   std::memset(out, 0, sizeof(*out));
   std::strncpy(out->name, names[kind], sizeof(out->name) - 1);

@@ -79,7 +79,8 @@ enum KernelKind {
   K_BF_GEMM = 7,  // grouped GEMMs of butterfly products and constructions
   K_ID = 8,       // interpolative decompositions
   K_EXTRACT = 9,  // entry extraction from never-formed fronts and sketches
-  K_COUNT = 10
+  K_STORE = 10,   // copy of the dense factors out of the level workspace
+  K_COUNT = 11
 };
 
 // HIP-event timing of kernel classes on the handle's stream.
@@ -96,7 +97,7 @@ struct KernelTimer {
   std::vector<Rec> recs;
   int64_t launches[K_COUNT] = {};  // timed launches
   int64_t issued[K_COUNT] = {};    // all launches while enabled
-  int sample_every[K_COUNT] = {1, 1, 1, 1, 1, 1, 1, 8, 1, 1};  // time one launch in this many
+  int sample_every[K_COUNT] = {1, 1, 1, 1, 1, 1, 1, 8, 1, 1, 1};  // time one launch in this many
   double seconds[K_COUNT] = {}, flops[K_COUNT] = {}, bytes[K_COUNT] = {};
   // timed butterfly GEMM launches by floor(log2(flops)): count, seconds, flops
   double hist_n[64] = {}, hist_s[64] = {}, hist_f[64] = {};
@@ -121,7 +122,8 @@ struct FrontPlan {
   int32_t n = 0, ns = 0, nu = 0;
   int32_t nchild = 0;
   int32_t child[2] = {-1, -1};
-  int64_t f_off = 0;      // element offset of F in the front arena
+  int64_t f_off = 0;      // element offset of F in the level workspace (dense: n^2, compressed: nu^2 block)
+  int64_t p_off = -1;     // element offset of the kept factor (dense fronts: n*ns + ns*nu entries)
   int64_t inv_off[2] = {-1, -1};
   int64_t aptr_off = 0;   // into a_ptr (n+1 entries)
   int64_t piv_off = 0;    // into piv (ns entries)
@@ -148,7 +150,8 @@ struct Context {
   // plan
   std::vector<FrontPlan> fp;
   std::vector<int32_t> level_ptr, level_fronts;  // fronts grouped by level, deepest level first
-  int64_t arena_elems = 0;                       // sum of n_f^2
+  int64_t work_elems = 0;                        // level workspaces (both depth parities)
+  int64_t fac_elems = 0;                         // kept factors of the dense fronts
   int64_t sum_n = 0;                             // sum of n_f
   std::vector<int64_t> h_aptr;
   std::vector<int32_t> h_arow;
@@ -163,7 +166,8 @@ struct Context {
   std::vector<int32_t> desc_index;  // front id -> index in h_fds
 
   // device: numeric
-  DevBuf d_arena;          // dense fronts
+  DevBuf d_work;           // fronts from assembly until the parent level is assembled
+  DevBuf d_fac;            // factors of the dense fronts, kept for the sweeps
   DevBuf d_kept;           // debug copies of assembled fronts
   bfmf_factor_opts fopts{};
   bfmf_stats stats{};

@@ -12,7 +12,10 @@ enum : int32_t { OP_N = 0, OP_T = 1, OP_C = 2 };
 // F = [F11 F12; F21 F22] with F11 of size ns (the fully-summed variables
 // I^s) and F22 of size n - ns (the update variables I^u).
 struct FrontDesc {
-  void* F;            // complex<T> storage, n*n elements
+  void* F;            // complex<T> working storage during the factorization, n*n elements (ld n)
+  void* P;            // kept factor after it: [L and U packed; F21'] (n x ns, ld n) ...
+  void* F12;          // ... and F12' (ns x nu, ld ld12); both null for compressed fronts
+  int64_t ld12;
   int32_t n, ns;
   int32_t nchild;     // 0..2
   int32_t front;      // front id (postorder)

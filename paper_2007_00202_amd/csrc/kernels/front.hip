@@ -372,6 +372,38 @@ hipError_t launch_schur(const FrontDesc* d_fds, int nbatch, const int* h_n, cons
   return hipSuccess;
 }
 
+// Kept factor of one front from its working storage: the first ns columns
+// ([L U; F21'], contiguous since ld = n) and F12' (rows 0..ns of the last nu
+// columns) repacked with ld = ns.  One grid row per front; the element index
+// runs over both parts, so consecutive threads touch consecutive addresses of
+// both source and destination except at column ends of F12'.
+template <class T>
+__global__ __launch_bounds__(256) void store_factor_kernel(const FrontDesc* __restrict__ fds) {
+  const FrontDesc& fd = fds[blockIdx.y];
+  const int64_t n = fd.n, ns = fd.ns, nu = n - ns;
+  const int64_t panel = n * ns, total = panel + ns * nu;
+  const cplx<T>* F = (const cplx<T>*)fd.F;
+  cplx<T>* P = (cplx<T>*)fd.P;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    if (e < panel) {
+      P[e] = F[e];
+    } else {
+      const int64_t q = e - panel, r = q % ns, c = q / ns;
+      P[e] = F[r + (ns + c) * n];
+    }
+  }
+}
+
+template <class T>
+hipError_t launch_store_factor(const FrontDesc* d_fds, int nbatch, int64_t max_elems, hipStream_t s) {
+  if (nbatch == 0 || max_elems == 0) return hipSuccess;
+  // about 8 elements per thread for the largest front, at most 1024 workgroups per front
+  const int64_t gx = std::min<int64_t>(1024, std::max<int64_t>(1, (max_elems + 2047) / 2048));
+  hipLaunchKernelGGL((store_factor_kernel<T>), dim3((unsigned)gx, nbatch), dim3(256), 0, s, d_fds);
+  return hipGetLastError();
+}
+
+template hipError_t launch_store_factor<double>(const FrontDesc*, int, int64_t, hipStream_t);
 template hipError_t launch_assemble<double>(const FrontDesc*, int, int, const void*, bool, hipStream_t);
 template hipError_t launch_assemble<float>(const FrontDesc*, int, int, const void*, bool, hipStream_t);
 template hipError_t launch_partial_lu<double>(const FrontDesc*, int, const int*, const int*, int*, hipStream_t);

@@ -29,6 +29,9 @@ hipError_t launch_partial_lu(const FrontDesc* d_fds, int nbatch, const int* h_n,
 // Schur complement C = F22 - F21 F12 of nbatch fronts (after the LU loop).
 template <class T>
 hipError_t launch_schur(const FrontDesc* d_fds, int nbatch, const int* h_n, const int* h_ns, hipStream_t s);
+// copy of the factor panels of dense fronts from F to P / F12 (null P: the host never sends these)
+template <class T>
+hipError_t launch_store_factor(const FrontDesc* d_fds, int nbatch, int64_t max_elems, hipStream_t s);
 
 // ---- solve sweeps (solve.hip); workspaces in FrontDesc::W (n x nrhs, ld n)
 // y(i, c) = B(perm[i], c) (B complex128, y complex<T>, ld N)

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void fwd_trsv_kernel(const FrontDesc* __restri
   const FrontDesc& fd = fds[blockIdx.x];
   const int n = fd.n, ns = fd.ns;
   if (ns == 0) return;
-  const cplx<T>* F = (const cplx<T>*)fd.F;
+  const cplx<T>* F = (const cplx<T>*)fd.P;  // [L U; F21'], ld n
   cplx<T>* W = (cplx<T>*)fd.W;
   for (int c = threadIdx.x; c < nrhs; c += 256) {
     cplx<T>* w = W + (int64_t)c * n;
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void fwd_trsv_lds_kernel(const FrontDesc* __re
   if (ns == 0 || ncl <= 0 || ns > TRSV_MAXNS || ns * ncl > cap) return;  // the host never sends these
   extern __shared__ __align__(16) unsigned char trsv_smem[];
   cplx<T>* w = (cplx<T>*)trsv_smem;  // w[r + c ns], cap entries (dynamic, sized for the level)
-  const cplx<T>* F = (const cplx<T>*)fd.F;
+  const cplx<T>* F = (const cplx<T>*)fd.P;  // [L U; F21'], ld n
   cplx<T>* W = (cplx<T>*)fd.W + (int64_t)c0 * n;
   const int tid = threadIdx.x;
   for (int e = tid; e < ns * ncl; e += 256) w[e] = W[e % ns + (int64_t)(e / ns) * n];
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256) void bwd_trsv_lds_kernel(const FrontDesc* __re
   if (ns == 0 || ncl <= 0 || ns > TRSV_MAXNS || ns * ncl > cap) return;  // the host never sends these
   extern __shared__ __align__(16) unsigned char trsv_smem[];
   cplx<T>* w = (cplx<T>*)trsv_smem;
-  const cplx<T>* F = (const cplx<T>*)fd.F;
+  const cplx<T>* F = (const cplx<T>*)fd.P;  // [L U; F21'], ld n
   const cplx<T>* W = (const cplx<T>*)fd.W + (int64_t)c0 * n;
   const int tid = threadIdx.x;
   for (int e = tid; e < ns * ncl; e += 256) w[e] = W[e % ns + (int64_t)(e / ns) * n];
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(256) void bwd_trsv_kernel(const FrontDesc* __restri
   const FrontDesc& fd = fds[blockIdx.x];
   const int n = fd.n, ns = fd.ns;
   if (ns == 0) return;
-  const cplx<T>* F = (const cplx<T>*)fd.F;
+  const cplx<T>* F = (const cplx<T>*)fd.P;  // [L U; F21'], ld n
   cplx<T>* W = (cplx<T>*)fd.W;
   for (int j = ns - 1; j >= 0; --j) {
     const cplx<T>* Uj = F + (int64_t)j * n;
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(256) void sweep_gemm_kernel(const FrontDesc* __rest
   const FrontDesc& fd = fds[blockIdx.y];
   const int n = fd.n, ns = fd.ns, nu = n - ns;
   if (ns == 0 || nu == 0) return;
-  const cplx<T>* F = (const cplx<T>*)fd.F;
+  const cplx<T>* F = (const cplx<T>*)fd.P;  // [L U; F21'], ld n
   cplx<T>* W = (cplx<T>*)fd.W;
   const int M = mode == 0 ? nu : ns;
   const int tm = (M + GEMM_TM - 1) / GEMM_TM, tn = (nrhs + GEMM_TN - 1) / GEMM_TN;
@@ -280,8 +280,8 @@ __global__ __launch_bounds__(256) void sweep_gemm_kernel(const FrontDesc* __rest
   if (mode == 0)
     gemm_tile<T>(F + ns, n, OP_N, W, n, W + ns, n, nu, nrhs, ns, cplx<T>{-1, 0}, 1, t % tm, t / tm, sm);
   else
-    gemm_tile<T>(F + (int64_t)ns * n, n, OP_N, W + ns, n, W, n, ns, nrhs, nu, cplx<T>{-1, 0}, 1, t % tm, t / tm,
-                 sm);
+    gemm_tile<T>((const cplx<T>*)fd.F12, fd.ld12, OP_N, W + ns, n, W, n, ns, nrhs, nu, cplx<T>{-1, 0}, 1, t % tm,
+                 t / tm, sm);
 }
 
 // the same products for at most 16 right-hand sides: 256-row streaming tiles (F21 / F12 read once)
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256) void sweep_gemm_skinny_kernel(const FrontDesc*
   const FrontDesc& fd = fds[blockIdx.y];
   const int n = fd.n, ns = fd.ns, nu = n - ns;
   if (ns == 0 || nu == 0 || nrhs > SKINNY_TN) return;
-  const cplx<T>* F = (const cplx<T>*)fd.F;
+  const cplx<T>* F = (const cplx<T>*)fd.P;  // [L U; F21'], ld n
   cplx<T>* W = (cplx<T>*)fd.W;
   const int M = mode == 0 ? nu : ns;
   const int t = blockIdx.x;
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(256) void sweep_gemm_skinny_kernel(const FrontDesc*
   if (mode == 0)
     gemm_tile_skinny<T>(F + ns, n, W, n, W + ns, n, nu, nrhs, ns, cplx<T>{-1, 0}, 1, t);
   else
-    gemm_tile_skinny<T>(F + (int64_t)ns * n, n, W + ns, n, W, n, ns, nrhs, nu, cplx<T>{-1, 0}, 1, t);
+    gemm_tile_skinny<T>((const cplx<T>*)fd.F12, fd.ld12, W + ns, n, W, n, ns, nrhs, nu, cplx<T>{-1, 0}, 1, t);
 }
 
 // ------------------------------------------------------------ GMRES vectors

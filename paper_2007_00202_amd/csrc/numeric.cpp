@@ -128,14 +128,6 @@ void factor_dense(Context& c) {
       c.compressed[f] = 1;
       ++ncomp;
     }
-  // arena: dense fronts keep n^2 entries, compressed fronts only their nu^2 block
-  int64_t off = 0;
-  for (int32_t f = 0; f < nf; ++f) {
-    FrontPlan& p = c.fp[f];
-    p.f_off = off;
-    off += c.compressed[f] ? (int64_t)p.nu * p.nu : (int64_t)p.n * p.n;
-  }
-  c.arena_elems = off;
   // level order with the dense fronts of a level first
   const int nlev0 = (int)c.level_ptr.size() - 1;
   c.level_order.clear();
@@ -147,16 +139,58 @@ void factor_dense(Context& c) {
     for (int k = c.level_ptr[L]; k < c.level_ptr[L + 1]; ++k)
       if (c.compressed[c.level_fronts[k]]) c.level_order.push_back(c.level_fronts[k]);
   }
-  const size_t need = (size_t)c.arena_elems * elem;
+  // Memory.  A front lives in a level workspace from its assembly until the
+  // level above has been assembled from its contribution block: dense fronts
+  // take n^2 entries there, compressed fronts only their nu^2 block.  Children
+  // are exactly one level below their parent, so two workspaces alternating
+  // with the level's parity suffice.  The factor panels of a dense front
+  // ([L U; F21'] and F12', n*ns + ns*nu entries) are copied to the kept
+  // factor store after its Schur complement.  With keep_fronts every front
+  // gets a workspace slot of its own (nothing reused), so its contribution
+  // block stays readable.
+  auto wsize = [&](int32_t f) {
+    const FrontPlan& p = c.fp[f];
+    return c.compressed[f] ? (int64_t)p.nu * p.nu : (int64_t)p.n * p.n;
+  };
+  int64_t par_max[2] = {0, 0}, uniq = 0;
+  for (int L = 0; L < nlev0; ++L) {
+    int64_t lvl = 0;
+    for (int k = c.level_ptr[L]; k < c.level_ptr[L + 1]; ++k) lvl += wsize(c.level_fronts[k]);
+    par_max[L & 1] = std::max(par_max[L & 1], lvl);
+    uniq += lvl;
+  }
+  int64_t fac = 0;
+  for (int L = 0; L < nlev0; ++L) {
+    int64_t off = c.fopts.keep_fronts ? 0 : ((L & 1) ? par_max[0] : 0);
+    if (c.fopts.keep_fronts)
+      for (int M = 0; M < L; ++M)
+        for (int k = c.level_ptr[M]; k < c.level_ptr[M + 1]; ++k) off += wsize(c.level_fronts[k]);
+    for (int k = c.level_ptr[L]; k < c.level_ptr[L + 1]; ++k) {
+      const int32_t f = c.level_order[k];
+      FrontPlan& p = c.fp[f];
+      p.f_off = off;
+      off += wsize(f);
+      p.p_off = -1;
+      if (!c.compressed[f]) {
+        p.p_off = fac;
+        fac += (int64_t)p.n * p.ns + (int64_t)p.ns * p.nu;
+      }
+    }
+  }
+  c.work_elems = c.fopts.keep_fronts ? uniq : par_max[0] + par_max[1];
+  c.fac_elems = fac;
+  const size_t need = (size_t)(c.work_elems + c.fac_elems + (c.fopts.keep_fronts ? uniq : 0)) * elem;
   size_t free_b = 0, total_b = 0;
   HIPCHK(hipMemGetInfo(&free_b, &total_b));
-  const uint64_t budget = c.fopts.hbm_budget ? c.fopts.hbm_budget : (uint64_t)free_b;
-  if (need > budget || need > free_b)
-    throw Error(BFMF_E_NOMEM, "dense front arena needs " + std::to_string(need) + " bytes, budget " +
-                                  std::to_string(std::min<uint64_t>(budget, free_b)));
-  if (c.d_arena.bytes < need) alloc(c.d_arena, need);
+  const size_t have = free_b + c.d_work.bytes + c.d_fac.bytes + c.d_kept.bytes;  // reused on a new factor
+  const uint64_t budget = c.fopts.hbm_budget ? c.fopts.hbm_budget : (uint64_t)have;
+  if (need > budget || need > have)
+    throw Error(BFMF_E_NOMEM, "front workspaces and dense factors need " + std::to_string(need) + " bytes, budget " +
+                                  std::to_string(std::min<uint64_t>(budget, have)));
+  if (c.d_work.bytes < (size_t)c.work_elems * elem) alloc(c.d_work, (size_t)c.work_elems * elem);
+  if (c.d_fac.bytes < (size_t)c.fac_elems * elem) alloc(c.d_fac, std::max<size_t>((size_t)c.fac_elems * elem, 16));
   if (c.fopts.keep_fronts) {
-    if (c.d_kept.bytes < need) alloc(c.d_kept, need);
+    if (c.d_kept.bytes < (size_t)uniq * elem) alloc(c.d_kept, (size_t)uniq * elem);
   } else {
     c.d_kept.release();
   }
@@ -165,7 +199,8 @@ void factor_dense(Context& c) {
     comp_state_reset(c.comp, c, nf);
   }
   // descriptors in level order
-  char* arena = c.d_arena.as<char>();
+  char* arena = c.d_work.as<char>();
+  char* facs = c.d_fac.as<char>();
   c.h_fds.assign(nf, FrontDesc());
   for (int32_t k = 0; k < nf; ++k) {
     const int32_t f = c.level_order[k];
@@ -174,6 +209,11 @@ void factor_dense(Context& c) {
     FrontDesc& d = c.h_fds[k];
     std::memset(&d, 0, sizeof(d));
     d.F = arena + p.f_off * elem;
+    if (p.p_off >= 0) {
+      d.P = facs + p.p_off * elem;
+      d.F12 = facs + (p.p_off + (int64_t)p.n * p.ns) * elem;
+      d.ld12 = std::max(p.ns, 1);
+    }
     d.n = p.n;
     d.ns = p.ns;
     d.nchild = p.nchild;
@@ -211,7 +251,8 @@ void factor_dense(Context& c) {
       hn.clear();
       hns.clear();
       int maxn = 0;
-      double asm_bytes = 0, lu_flops = 0, sch_flops = 0, sch_bytes = 0;
+      double asm_bytes = 0, lu_flops = 0, sch_flops = 0, sch_bytes = 0, store_bytes = 0;
+      int64_t maxstore = 0;
       for (int k = lo; k < hi; ++k) {
         const int32_t f = c.level_order[k];
         const FrontPlan& p = c.fp[f];
@@ -226,6 +267,8 @@ void factor_dense(Context& c) {
         lu_flops += 8.0 / 3.0 * ns * ns * ns + 8.0 * ns * ns * nu;
         sch_flops += 8.0 * ns * nu * nu;
         sch_bytes += elem * (2.0 * ns * nu + 2.0 * nu * nu);
+        store_bytes += 2.0 * elem * (n * ns + ns * nu);
+        maxstore = std::max(maxstore, (int64_t)p.n * p.ns + (int64_t)p.ns * p.nu);
       }
       int tk = c.timer.begin(c.stream);
       check(launch_assemble<double>(dfds + lo, hi - lo, maxn, c.d_values.p, false, c.stream), "assemble");
@@ -244,6 +287,9 @@ void factor_dense(Context& c) {
       tk = c.timer.begin(c.stream);
       check(launch_schur<double>(dfds + lo, hi - lo, hn.data(), hns.data(), c.stream), "schur");
       c.timer.end(tk, c.stream, K_SCHUR, sch_flops, sch_bytes);
+      tk = c.timer.begin(c.stream);
+      check(launch_store_factor<double>(dfds + lo, hi - lo, maxstore, c.stream), "factor store");
+      c.timer.end(tk, c.stream, K_STORE, 0, store_bytes);
     };
     if (c.fopts.batched) {
       run(b, e);

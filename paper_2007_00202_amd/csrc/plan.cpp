@@ -1,4 +1,4 @@
-// Device plan of the dense fronts: arena offsets, inverse extend-add maps,
+// Device plan of the dense fronts: inverse extend-add maps,
 // per-front lists of the A entries each front assembles, level schedule.
 //
 // Entry A(i, j) (new numbering) is assembled in the front tau whose I^s
@@ -26,7 +26,7 @@ void build_plan(Context& c) {
   Symbolic& s = c.sym;
   const int32_t nf = s.nfronts();
   c.fp.assign(nf, FrontPlan());
-  int64_t off = 0, aptr = 0, piv = 0, iu = 0, woff = 0;
+  int64_t aptr = 0, piv = 0, iu = 0, woff = 0;
   for (int32_t f = 0; f < nf; ++f) {
     FrontPlan& p = c.fp[f];
     p.ns = (int32_t)s.ns(f);
@@ -35,8 +35,6 @@ void build_plan(Context& c) {
     p.nchild = s.child_ptr[f + 1] - s.child_ptr[f];
     if (p.nchild > 2) throw Error(BFMF_E_INVAL, "assembly tree node with more than two children");
     for (int k = 0; k < p.nchild; ++k) p.child[k] = s.child_list[s.child_ptr[f] + k];
-    p.f_off = off;
-    off += (int64_t)p.n * p.n;
     p.aptr_off = aptr;
     aptr += p.n + 1;
     p.piv_off = piv;
@@ -46,7 +44,6 @@ void build_plan(Context& c) {
     p.w_off = woff;
     woff += p.n;
   }
-  c.arena_elems = off;
   c.sum_n = woff;
 
   // inverse maps: parent-local -> child-local (or -1)
@@ -194,7 +191,7 @@ Context::~Context() {
 uint64_t Context::device_bytes() const {
   uint64_t t = 0;
   for (const DevBuf* b : {&d_rowptr, &d_colind, &d_values, &d_perm, &d_aptr, &d_arow, &d_avidx, &d_inv, &d_iu32,
-                          &d_piv, &d_status, &d_fds, &d_arena, &d_kept, &d_W, &d_y, &d_x, &g_B, &g_X, &g_V, &g_w,
+                          &d_piv, &d_status, &d_fds, &d_work, &d_fac, &d_kept, &d_W, &d_y, &d_x, &g_B, &g_X, &g_V, &g_w,
                           &g_r, &g_scal, &g_part, &g_tmp})
     t += b->bytes;
   t += stage.cap;  // pinned host ring (counted with the handle's memory)

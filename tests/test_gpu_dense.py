@@ -89,6 +89,35 @@ def test_batched_equals_plain_bitwise(gpu_lib):
     assert np.array_equal(out[0], out[1])
 
 
+@pytest.mark.parametrize("n_min", [0, 60])
+def test_level_workspace_reuse(gpu_lib, n_min):
+    """Fronts share two level workspaces (alternating with the level's parity) unless
+    keep_fronts gives each its own slot: the factors and the preconditioner are the same
+    bit for bit, dense and with nested compressed fronts."""
+    dims = (16, 16, 16)
+    rp, ci, v, _ = helmholtz_7pt(dims, 0.05)
+    B = rng_for("test", "rhs").standard_normal((4096, 3)) + 0j
+    out, fronts = [], []
+    for keep in (True, False):
+        s = gpu_lib.Solver(0).analyze(rp, ci, v, dims=dims, leaf_max=64, sep_leaf=32)
+        s.factor(tol=1e-3, n_min=n_min, batched=True, keep_fronts=keep)
+        out.append(s.precondition(B))
+        sym = s.symbolic()
+        ns = sym["send"] - sym["sbeg"]
+        leaf = np.diff(sym["child_ptr"]) == 0
+        dense = [f for f in range(len(ns)) if n_min == 0 or leaf[f] or ns[f] < n_min]
+        fr = []
+        for f in dense[:: max(1, len(dense) // 12)]:
+            F = s.front(f, 1)
+            k = int(ns[f])
+            fr.append((F[:, :k].copy(), F[:k, k:].copy()))
+        fronts.append(fr)
+        s.close()
+    assert np.array_equal(out[0], out[1])
+    for (a0, b0), (a1, b1) in zip(*fronts):
+        assert np.array_equal(a0, a1) and np.array_equal(b0, b1)
+
+
 def test_helmholtz24_end_to_end(gpu_lib):
     p = make_problem("helmholtz24")
     od = nd.nd_grid(p.dims, leaf_max=512, sep_leaf=64)

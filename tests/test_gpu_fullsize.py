@@ -1,0 +1,81 @@
+"""Parity at the full sizes of the measured workloads, in the launch
+configuration the benchmark times: batched form, complex64 butterflies with
+FP64 pivot blocks and GMRES, tol 1e-3, fronts with #I^s >= 1024 compressed,
+64 samples per block.
+
+The oracle cannot factor these grids whole, so the checks are
+  * sampled outputs it computes one by one: dense fronts (leaves, and parents
+    of leaves) assembled and factored by the oracle (Alg. 1: the leaves from
+    A alone, the parents from A and the oracle's own leaf contribution
+    blocks); the GPU's factor panels [L U; F21'], F12' and pivots must agree;
+  * properties that hold at any size: every column's true FP64 residual at
+    most 1e-3 after GMRES (Sec. 6 stopping rule), every front with
+    #I^s >= n_min compressed, compressed factors smaller than exact ones.
+"""
+import numpy as np
+import pytest
+
+from workloads import make_problem
+from oracle import nd
+from oracle import multifrontal as mf
+from oracle.symbolic import symbolic
+
+pytestmark = pytest.mark.gpu
+
+N_MIN = 1024
+
+
+def _analyze(gpu_lib, p):
+    s = gpu_lib.Solver(0)
+    if p.kind == "grid":
+        s.analyze(p.rowptr, p.colind, p.values, dims=p.dims)
+        od = nd.nd_grid(p.dims, leaf_max=512, sep_leaf=64)
+    else:
+        s.analyze(p.rowptr, p.colind, p.values, coords=p.coords, cells=p.cells)
+        od = nd.nd_yee(p.cells, p.coords, leaf_max=512, sep_leaf=64)
+    return s, od
+
+
+def _sampled_fronts(od):
+    leaves = [f for f in range(od.nfronts) if od.leaf[f]]
+    parents = [f for f in range(od.nfronts)
+               if not od.leaf[f] and od.children[f] and all(od.leaf[c] for c in od.children[f])]
+    pick = lambda xs: sorted({xs[0], xs[len(xs) // 2], xs[-1]})
+    return pick(leaves) + pick(parents)
+
+
+@pytest.mark.parametrize("name", ["helmholtz100", "helmholtz128grf", "maxwell64"])
+def test_full_size_workload(gpu_lib, name):
+    p = make_problem(name)
+    print(f"\n[fullsize] {name}: N={p.n} nrhs={p.rhs.shape[1]}", flush=True)
+    s, od = _analyze(gpu_lib, p)
+    try:
+        s.factor(tol=1e-3, n_min=N_MIN, precision=gpu_lib.BFMF_C64_MIXED, batched=True)
+        st = s.stats()
+        ns = od.send - od.sbeg
+        assert st["compressed_fronts"] == int(np.sum(ns >= N_MIN))
+        assert st["factor_bytes"] < st["dense_factor_bytes"]
+        X, info = s.solve(p.rhs, true_rtol=1e-3)
+        res = mf.rel_residual(p.rowptr, p.colind, p.values, X, p.rhs)
+        print(f"[fullsize] {name}: iters {info['iters']} relres max {res.max():.2e} "
+              f"compressed {st['compressed_fronts']} max rank {st['max_rank']}", flush=True)
+        assert info["status"] == 0 and res.max() <= 1e-3, (res.max(), info)
+
+        sym = symbolic(p.rowptr, p.colind, od)
+        for f in _sampled_fronts(od):
+            nsf = int(ns[f])
+            cbs = {}
+            for c in od.children[f]:  # leaves: assembled from A alone
+                Fc = mf.assemble_front(p.rowptr, p.colind, p.values, od, sym, c, {})
+                cbs[c] = mf.partial_lu(Fc, int(ns[c]))[4]
+            want = mf.assemble_front(p.rowptr, p.colind, p.values, od, sym, f, cbs)
+            lu, opiv, F12, F21, _ = mf.partial_lu(want.copy(), nsf)
+            Ff = s.front(f, 1)
+            piv = s.front(f, 2)
+            assert np.array_equal(piv, opiv), f"front {f}: pivots differ"
+            scale = max(1.0, np.abs(want).max())
+            for got, ref in ((Ff[:nsf, :nsf], lu), (Ff[:nsf, nsf:], F12), (Ff[nsf:, :nsf], F21)):
+                assert np.abs(got - ref).max(initial=0.0) <= 1e-11 * scale, f"front {f}"
+            assert not np.any(Ff[nsf:, nsf:]), "contribution block is not kept without keep_fronts"
+    finally:
+        s.close()
