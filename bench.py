@@ -37,7 +37,26 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-seconds", type=float, default=0.25, help="arrival window of the serving run")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean request arrivals per second")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run two streaming kernels of known size (an elementwise negation and a "
+                         "device copy, each reading and writing this many MiB) to scale HBM byte counters")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    """Streaming kernels of known traffic: dst = -src (an elementwise kernel) and dst = src (a
+    device-to-device copy), each reading mib MiB and writing mib MiB."""
+    import torch
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.neg(src, out=dst)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    torch.cuda.empty_cache()
+    print(f"[bench] calibration kernels: {mib} MiB read + {mib} MiB written each", file=sys.stderr, flush=True)
 
 
 def cpu_baseline(prob, budget_s, nrhs):
@@ -216,6 +235,9 @@ def main():
     import torch
     from paper_2007_00202_amd import bfmf
     from workloads import make_problem, CONFIGS
+
+    if a.calibrate_copy_mib > 0:
+        calibrate_copy(a.calibrate_copy_mib)
 
     cfg = CONFIGS[a.config]
     prob = make_problem(a.config, n=a.n)

@@ -208,9 +208,14 @@ bfmf_status bfmf_get_front(bfmf_handle h, int32_t front, int32_t what, void* out
  * 7 butterfly grouped GEMMs (products of butterflies and the GEMMs of their
  * constructions), 8 interpolative decompositions, 9 entry extraction,
  * 10 copy of the dense fronts' factors out of the level workspace.
+ * Class 7 times about one launch in eight, chosen quasi-randomly (the
+ * fractional parts of i times the golden ratio below 1/8, i = launch index),
+ * with the kernel's own start and end timestamps (events attached to the
+ * dispatch); the other classes time every launch with events recorded on
+ * the stream around it, which also covers the gaps between dispatches.
  * launches counts the timed launches and launches_all every launch of the
- * class; class 7 times one launch in eight, the others every launch.
- * seconds, flops and bytes (algorithmic counts) cover the timed launches.
+ * class; seconds, flops and bytes (algorithmic counts) cover the timed
+ * launches.
  * E_INVAL for an unknown class; bfmf_reset_kernel_stats clears all. */
 typedef struct {
     char name[32];

@@ -453,9 +453,10 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
   c.stage.put(d, blob.data(), blob.size(), s);
   for (size_t k = 0; k < plan.phase.size(); ++k) {
     if (plan.phase[k].empty()) continue;
-    const int tk = c.timer.want(kind) ? c.timer.begin(s) : -1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const int tk = c.timer.want(kind) ? c.timer.begin_ext(&e0, &e1) : -1;
     chk(launch_grouped_gemm<T>((const GTask*)(d + toff[k]), (const int64_t*)(d + soff[k]), (int)plan.phase[k].size(),
-                               ntiles[k], bases, skinny[k] != 0, s),
+                               ntiles[k], bases, skinny[k] != 0, s, e0, e1),
         "grouped gemm");
     if (tk >= 0) {
       double fl = 0, by = 0;
@@ -469,7 +470,7 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
         mk = std::max(mk, t.K);
       }
       c.timer.set_shape(tk, (int)plan.phase[k].size(), mm, mn, mk);
-      c.timer.end(tk, s, kind, fl, by);
+      c.timer.end_ext(tk, kind, fl, by);
     }
   }
   // no synchronisation: the next plan's upload is ordered after these launches on the stream

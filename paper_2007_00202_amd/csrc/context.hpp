@@ -108,10 +108,23 @@ struct KernelTimer {
                     recs[token].shape[3] = k;
   }
   // whether to time the next launch of this class (counts it either way)
-  bool want(int kind) { return enabled && (issued[kind]++ % sample_every[kind]) == 0; }
+  // Launches to time: with sample_every = k > 1, a launch is taken when the
+  // fractional part of i * (golden ratio) lies below 1/k (i = the class's
+  // launch counter): about one in k, spread quasi-randomly, so the sample
+  // does not alias with periodic launch sequences.
+  bool want(int kind) {
+    if (!enabled) return false;
+    const uint64_t i = (uint64_t)issued[kind]++;
+    if (sample_every[kind] <= 1) return true;
+    const double frac = (double)((i * 0x9E3779B97F4A7C15ull) >> 11) * 0x1.0p-53;
+    return frac * sample_every[kind] < 1.0;
+  }
   hipEvent_t take();
   int begin(hipStream_t s);
   void end(int token, hipStream_t s, int kind, double fl, double by);
+  // a record whose two events the caller hands to a launch that timestamps them itself
+  int begin_ext(hipEvent_t* start, hipEvent_t* stop);
+  void end_ext(int token, int kind, double fl, double by);
   void collect();  // after the stream is synchronised
   void reset();
   ~KernelTimer();

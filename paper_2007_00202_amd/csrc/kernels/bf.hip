@@ -10,6 +10,8 @@
 //   philox_gauss      complex Gaussian probe vectors supported on one tree node
 //   small_solve       X A = B for many small systems (least-squares centre)
 //   leaf_inverse      explicit inverses of the dense HOD-BF leaves (Alg. 4)
+#include <hip/hip_ext.h>
+
 #include "../devtypes.hpp"
 #include "common.hpp"
 #include "gemm.hpp"
@@ -740,15 +742,25 @@ __global__ void convert_kernel(cplx<T1>* __restrict__ Y, int64_t ldy, const cplx
 
 template <class T>
 hipError_t launch_grouped_gemm(const GTask* d_tasks, const int64_t* d_tile_start, int ntasks, int64_t ntiles,
-                               void* const bases[4], bool skinny, hipStream_t s) {
+                               void* const bases[4], bool skinny, hipStream_t s, hipEvent_t ev_start,
+                               hipEvent_t ev_stop) {
   if (ntasks == 0 || ntiles == 0) return hipSuccess;
   // grids are limited to 2^31 - 1 blocks in x
-  if (skinny)
-    hipLaunchKernelGGL((grouped_gemm_skinny_kernel<T>), dim3((unsigned)ntiles), dim3(256), 0, s, d_tasks,
-                       d_tile_start, ntasks, bases[0], bases[1], bases[2], bases[3]);
-  else
-    hipLaunchKernelGGL((grouped_gemm_kernel<T>), dim3((unsigned)ntiles), dim3(256), 0, s, d_tasks, d_tile_start,
-                       ntasks, bases[0], bases[1], bases[2], bases[3]);
+  const dim3 grid((unsigned)ntiles);
+  if (ev_start) {
+    if (skinny)
+      hipExtLaunchKernelGGL((grouped_gemm_skinny_kernel<T>), grid, dim3(256), 0, s, ev_start, ev_stop, 0, d_tasks,
+                            d_tile_start, ntasks, bases[0], bases[1], bases[2], bases[3]);
+    else
+      hipExtLaunchKernelGGL((grouped_gemm_kernel<T>), grid, dim3(256), 0, s, ev_start, ev_stop, 0, d_tasks,
+                            d_tile_start, ntasks, bases[0], bases[1], bases[2], bases[3]);
+  } else if (skinny) {
+    hipLaunchKernelGGL((grouped_gemm_skinny_kernel<T>), grid, dim3(256), 0, s, d_tasks, d_tile_start, ntasks,
+                       bases[0], bases[1], bases[2], bases[3]);
+  } else {
+    hipLaunchKernelGGL((grouped_gemm_kernel<T>), grid, dim3(256), 0, s, d_tasks, d_tile_start, ntasks, bases[0],
+                       bases[1], bases[2], bases[3]);
+  }
   return hipGetLastError();
 }
 
@@ -866,7 +878,7 @@ hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int6
 
 #define INST(T)                                                                                                       \
   template hipError_t launch_grouped_gemm<T>(const GTask*, const int64_t*, int, int64_t, void* const[4], bool,        \
-                                             hipStream_t);                                                            \
+                                             hipStream_t, hipEvent_t, hipEvent_t);                                    \
   template hipError_t launch_cpqr_id<T>(const IdTask*, int, double, hipStream_t);                                     \
   template hipError_t launch_gram_id<T>(const IdTask*, int, double, hipStream_t);                                     \
   template hipError_t launch_id_expand<T>(const IdTask*, int, void* const*, const int64_t*, bool, bool, hipStream_t);  \

@@ -78,10 +78,13 @@ hipError_t launch_basis_update(const void* y, int ldy, int m, const void* V, int
                                int64_t ldx, int64_t N, int nrhs, hipStream_t s);
 
 // ---- butterfly support (bf.hip)
-// grouped GEMM over ntasks tasks; tile_start[i] = first tile of task i
+// grouped GEMM over ntasks tasks; tile_start[i] = first tile of task i.  With
+// events given, they take the kernel's own start and end timestamps (attached
+// to the dispatch, so the time excludes the gaps between dispatches).
 template <class T>
 hipError_t launch_grouped_gemm(const GTask* d_tasks, const int64_t* d_tile_start, int ntasks, int64_t ntiles,
-                               void* const bases[4], bool skinny, hipStream_t s);
+                               void* const bases[4], bool skinny, hipStream_t s, hipEvent_t ev_start = nullptr,
+                               hipEvent_t ev_stop = nullptr);
 // truncated column-pivoted QR of every task's q x p block (tol: |R_kk| > tol |R_00|)
 template <class T>
 hipError_t launch_cpqr_id(const IdTask* d_tasks, int ntasks, double tol, hipStream_t s);

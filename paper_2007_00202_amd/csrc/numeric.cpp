@@ -67,6 +67,28 @@ int KernelTimer::begin(hipStream_t s) {
   return (int)recs.size() - 1;
 }
 
+int KernelTimer::begin_ext(hipEvent_t* start, hipEvent_t* stop) {
+  if (!enabled) return -1;
+  Rec r;
+  r.kind = -1;
+  r.a = take();
+  r.b = take();
+  r.flops = r.bytes = 0;
+  r.shape[0] = r.shape[1] = r.shape[2] = r.shape[3] = 0;
+  *start = r.a;
+  *stop = r.b;
+  recs.push_back(r);
+  return (int)recs.size() - 1;
+}
+
+void KernelTimer::end_ext(int token, int kind, double fl, double by) {
+  if (token < 0) return;
+  Rec& r = recs[token];
+  r.kind = kind;
+  r.flops = fl;
+  r.bytes = by;
+}
+
 void KernelTimer::end(int token, hipStream_t s, int kind, double fl, double by) {
   if (token < 0) return;
   Rec& r = recs[token];
