@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-seconds", type=float, default=0.25, help="arrival window of the serving run")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean request arrivals per second")
+    ap.add_argument("--gemm-tile", type=int, default=-1,
+                    help="force one grouped-GEMM tile shape (0..5; -1: the autotuned choice per launch)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run two streaming kernels of known size (an elementwise negation and a "
                          "device copy, each reading and writing this many MiB) to scale HBM byte counters")
@@ -142,7 +144,7 @@ def run_form(bfmf, s, prob, nrhs, dB, dX, steps, warmup, form, precision, n_min,
             "solve_rhs_per_s": nrhs / float(np.mean(ssec)), "gmres_iters": int(max(iters)),
             "relres_max": float(max(relres)), "factor_flops": st["factor_flops"],
             "factor_bytes": st["factor_bytes"], "dense_factor_bytes": st["dense_factor_bytes"],
-            "max_rank": st["max_rank"], "kernels": s.kernel_stats()}
+            "max_rank": st["max_rank"], "kernels": s.kernel_stats(), "gemm_tiles": s.gemm_tile_launches()}
 
 
 def roofline(ks, steps, precision):
@@ -238,6 +240,8 @@ def main():
 
     if a.calibrate_copy_mib > 0:
         calibrate_copy(a.calibrate_copy_mib)
+    if a.gemm_tile >= 0:
+        bfmf.bfmf_set_gemm_tile(a.gemm_tile)
 
     cfg = CONFIGS[a.config]
     prob = make_problem(a.config, n=a.n)
@@ -268,6 +272,7 @@ def main():
         "max_rank": r["max_rank"],
         "roofline": rf,
         "kernels": kernels,
+        "gemm_tile_launches": {k: v // max(a.steps, 1) for k, v in r["gemm_tiles"].items()},
     }
     if not a.no_plain:  # the plain GPU form: complex128, fronts and constructions one at a time
         p = run_form(bfmf, s, prob, nrhs, dB, dX, 1, 0, "plain", "c128", n_min, tol, timing=False)

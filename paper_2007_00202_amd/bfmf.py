@@ -106,6 +106,8 @@ _SIGS = {
     "bfmf_get_front": (C.c_int, [_h, C.c_int32, C.c_int32, _P, C.c_int64]),
     "bfmf_get_kernel_stats": (C.c_int, [_h, C.c_int32, C.POINTER(bfmf_kernel_stat)]),
     "bfmf_reset_kernel_stats": (C.c_int, [_h]),
+    "bfmf_set_gemm_tile": (C.c_int, [C.c_int32]),
+    "bfmf_get_gemm_tile_launches": (C.c_int, [_h, C.POINTER(C.c_int64), C.c_int32]),
     "bfmf_bf_compress_dense": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, C.c_int32, C.c_double,
                                          C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_P)]),
     "bfmf_bf_apply": (C.c_int, [_P, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64]),
@@ -278,6 +280,21 @@ def bfmf_reset_kernel_stats(h):
     _check(h, _lib.bfmf_reset_kernel_stats(h))
 
 
+BFMF_GEMM_TILES = 6
+GEMM_TILE_SHAPES = ["64x64", "32x128", "128x32", "16x256", "256x16", "256x16 streaming"]
+
+
+def bfmf_set_gemm_tile(cfg):
+    """Force one grouped-GEMM tile shape for the process (-1: the autotuned choice)."""
+    _check(None, _lib.bfmf_set_gemm_tile(cfg))
+
+
+def bfmf_get_gemm_tile_launches(h):
+    out = (C.c_int64 * BFMF_GEMM_TILES)()
+    _check(h, _lib.bfmf_get_gemm_tile_launches(h, out, BFMF_GEMM_TILES))
+    return {GEMM_TILE_SHAPES[i]: int(out[i]) for i in range(BFMF_GEMM_TILES)}
+
+
 def bfmf_status_str(st):
     return _lib.bfmf_status_str(st).decode()
 
@@ -366,6 +383,9 @@ class Solver:
 
     def kernel_stats(self):
         return bfmf_get_kernel_stats(self.h)
+
+    def gemm_tile_launches(self):
+        return bfmf_get_gemm_tile_launches(self.h)
 
     def front(self, f, what):
         sym = self.symbolic()

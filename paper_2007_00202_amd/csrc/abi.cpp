@@ -8,6 +8,7 @@
 #include <new>
 
 #include "context.hpp"
+#include "kernels/kernels.hpp"
 
 using namespace bfmf;
 
@@ -334,6 +335,19 @@ bfmf_status bfmf_get_kernel_stats(bfmf_handle h, int32_t kind, bfmf_kernel_stat*
 bfmf_status bfmf_reset_kernel_stats(bfmf_handle h) {
   if (!h) return BFMF_E_INVAL;
   h->timer.reset();
+  for (int64_t& v : h->gemm_cfg_launches) v = 0;
+  return BFMF_OK;
+}
+
+bfmf_status bfmf_set_gemm_tile(int32_t cfg) {
+  if (cfg < -1 || cfg >= GEMM_CFGS) return BFMF_E_INVAL;
+  set_gemm_tile_override(cfg);
+  return BFMF_OK;
+}
+
+bfmf_status bfmf_get_gemm_tile_launches(bfmf_handle h, int64_t* out, int32_t n) {
+  if (!h || !out || n < GEMM_CFGS) return BFMF_E_INVAL;
+  for (int i = 0; i < n; ++i) out[i] = i < GEMM_CFGS ? h->gemm_cfg_launches[i] : 0;
   return BFMF_OK;
 }
 

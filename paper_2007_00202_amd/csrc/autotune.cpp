@@ -1,0 +1,223 @@
+// Tile-shape autotuner of the grouped GEMM that carries every butterfly
+// product (the per-level block-diagonal products of an apply, Sec. 3, and the
+// products of the constructions).
+//
+// On first use per device and precision, every tile shape is timed on
+// synthetic grouped launches over a grid of task shapes: M (rows of a block),
+// N (right-hand sides or probe columns) and K (inner dimension) in buckets.
+// Each timing is the kernel's own duration (events attached to the dispatch)
+// of a launch of P equal tasks, P chosen to fill the device, divided by P.  A
+// launch then takes the shape whose predicted time, summed over its tasks from
+// that table, is least.  All shapes add the products of an entry in the same
+// order, so the choice changes the speed and never the result.
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <mutex>
+
+#include "context.hpp"
+#include "kernels/kernels.hpp"
+
+namespace bfmf {
+
+namespace {
+
+constexpr int NM = 5, NN = 6, NK = 4;
+constexpr int MB[NM] = {16, 32, 64, 128, 256};
+constexpr int NB[NN] = {16, 32, 64, 128, 256, 1024};
+constexpr int KB[NK] = {16, 64, 256, 1024};
+
+struct Table {
+  bool ready = false;
+  double us[GEMM_CFGS][NM][NN][NK];  // microseconds per task
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, int>, Table> g_tables;  // (device, element size)
+std::atomic<int> g_override{-1};
+
+int bucket(const int* b, int n, int v) {
+  for (int i = 0; i < n; ++i)
+    if (v <= b[i]) return i;
+  return n - 1;
+}
+
+void tchk(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Error(BFMF_E_DEVICE, std::string("autotune: ") + what + ": " + hipGetErrorString(e));
+}
+
+// equal tasks of one shape: enough to fill the device with the 64 x 64 shape,
+// at most 2^30 multiply-adds and 2^24 operand entries per launch
+int tasks_for(int m, int n, int k) {
+  const int64_t tiles = gemm_cfg_tiles(0, m, n);
+  int64_t p = std::max<int64_t>(4, (2048 + tiles - 1) / tiles);
+  p = std::min<int64_t>(p, std::max<int64_t>(4, ((int64_t)1 << 30) / ((int64_t)m * n * k)));
+  p = std::min<int64_t>(p, std::max<int64_t>(1, ((int64_t)1 << 24) / ((int64_t)m * k + (int64_t)k * n + (int64_t)m * n)));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(p, 4096));
+}
+
+template <class T>
+void build_table(Table& t, hipStream_t s) {
+  const size_t esz = 2 * sizeof(T);  // one complex entry
+  // one buffer for the largest launch: P tasks with their own A, B and C
+  int64_t max_elems = 0, max_tasks = 0, max_tiles = 0;
+  for (int m : MB)
+    for (int n : NB)
+      for (int k : KB) {
+        const int p = tasks_for(m, n, k);
+        max_elems = std::max<int64_t>(max_elems, (int64_t)p * ((int64_t)m * k + (int64_t)k * n + (int64_t)m * n));
+        max_tasks = std::max<int64_t>(max_tasks, p);
+        for (int cfg = 0; cfg < GEMM_CFGS; ++cfg) max_tiles = std::max<int64_t>(max_tiles, p * gemm_cfg_tiles(cfg, m, n));
+      }
+  void* buf = nullptr;
+  void* dtask = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  tchk(hipMalloc(&buf, (size_t)max_elems * esz), "operand buffer");
+  tchk(hipMalloc(&dtask, (size_t)max_tasks * (sizeof(GTask) + sizeof(int64_t)) + 64), "task buffer");
+  tchk(hipMemsetAsync(buf, 0, (size_t)max_elems * esz, s), "clear");
+  tchk(hipEventCreate(&e0), "event");
+  tchk(hipEventCreate(&e1), "event");
+  void* bases[4] = {buf, nullptr, nullptr, nullptr};
+  std::vector<GTask> tasks;
+  std::vector<int64_t> start;
+  for (int mi = 0; mi < NM; ++mi)
+    for (int ni = 0; ni < NN; ++ni)
+      for (int ki = 0; ki < NK; ++ki) {
+        const int m = MB[mi], n = NB[ni], k = KB[ki];
+        const int p = tasks_for(m, n, k);
+        tasks.assign(p, GTask());
+        const int64_t stride = (int64_t)m * k + (int64_t)k * n + (int64_t)m * n;
+        for (int i = 0; i < p; ++i) {
+          GTask& g = tasks[i];
+          std::memset(&g, 0, sizeof(g));
+          g.a_off = i * stride;
+          g.b_off = g.a_off + (int64_t)m * k;
+          g.c_off = g.b_off + (int64_t)k * n;
+          g.lda = m;
+          g.ldb = k;
+          g.ldc = m;
+          g.M = m;
+          g.N = n;
+          g.K = k;
+          g.opA = OP_N;
+          g.opB = OP_N;
+          g.abase = g.bbase = g.cbase = 0;
+          g.beta = 1;
+          g.alpha_re = 1.0;
+        }
+        tchk(hipMemcpyAsync(dtask, tasks.data(), p * sizeof(GTask), hipMemcpyHostToDevice, s), "tasks");
+        int64_t* dstart = (int64_t*)((char*)dtask + p * sizeof(GTask));
+        for (int cfg = 0; cfg < GEMM_CFGS; ++cfg) {
+          double& out = t.us[cfg][mi][ni][ki];
+          out = std::numeric_limits<double>::infinity();
+          if (cfg == GEMM_CFG_SKINNY && n > GEMM_CFG_TN[GEMM_CFG_SKINNY]) continue;
+          start.assign(p, 0);
+          int64_t tiles = 0;
+          for (int i = 0; i < p; ++i) {
+            start[i] = tiles;
+            tiles += gemm_cfg_tiles(cfg, m, n);
+          }
+          tchk(hipMemcpyAsync(dstart, start.data(), p * sizeof(int64_t), hipMemcpyHostToDevice, s), "tile starts");
+          float best = std::numeric_limits<float>::infinity();
+          for (int rep = 0; rep < 2; ++rep) {
+            tchk(launch_grouped_gemm<T>((const GTask*)dtask, dstart, p, tiles, bases, cfg, s, e0, e1), "launch");
+            tchk(hipEventSynchronize(e1), "sync");
+            float ms = 0;
+            tchk(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+            if (rep > 0) best = std::min(best, ms);  // the first launch warms code and caches
+          }
+          out = 1e3 * best / p;
+        }
+        tchk(hipStreamSynchronize(s), "sync");  // the host vectors are reused
+      }
+  (void)max_tiles;
+  tchk(hipStreamSynchronize(s), "sync");
+  if (std::getenv("BFMF_VERBOSE")) {  // fastest shape and its time per task for every bucket
+    for (int mi = 0; mi < NM; ++mi)
+      for (int ni = 0; ni < NN; ++ni) {
+        std::fprintf(stderr, "[bfmf-tune] %s M %3d N %4d:", sizeof(T) == 8 ? "c128" : "c64 ", MB[mi], NB[ni]);
+        for (int ki = 0; ki < NK; ++ki) {
+          int b = 0;
+          for (int cfg = 1; cfg < GEMM_CFGS; ++cfg)
+            if (t.us[cfg][mi][ni][ki] < t.us[b][mi][ni][ki]) b = cfg;
+          std::fprintf(stderr, "  K %4d: %dx%d %7.2f us (64x64 %7.2f)", KB[ki], GEMM_CFG_TM[b], GEMM_CFG_TN[b],
+                       t.us[b][mi][ni][ki], t.us[0][mi][ni][ki]);
+        }
+        std::fprintf(stderr, "\n");
+      }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(dtask);
+  (void)hipFree(buf);
+  t.ready = true;
+}
+
+template <class T>
+const Table& table_for(int device, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  Table& t = g_tables[{device, (int)sizeof(T)}];
+  if (!t.ready) build_table<T>(t, s);
+  return t;
+}
+
+double predict(const Table& t, int cfg, const GTask& g) {
+  const int mi = bucket(MB, NM, g.M), ni = bucket(NB, NN, g.N), ki = bucket(KB, NK, g.K);
+  double v = t.us[cfg][mi][ni][ki];
+  if (g.M > MB[NM - 1]) v *= (double)g.M / MB[NM - 1];
+  if (g.N > NB[NN - 1]) v *= (double)g.N / NB[NN - 1];
+  if (g.K > KB[NK - 1]) v *= (double)g.K / KB[NK - 1];
+  return v;
+}
+
+}  // namespace
+
+void set_gemm_tile_override(int cfg) { g_override = cfg; }
+
+template <class T>
+void gemm_autotune(int device, hipStream_t s) {
+  (void)table_for<T>(device, s);
+}
+
+template <class T>
+int choose_gemm_cfg(int device, hipStream_t s, const std::vector<GTask>& ph) {
+  bool skinny_ok = !ph.empty();
+  for (const GTask& g : ph)
+    skinny_ok = skinny_ok && g.N <= GEMM_CFG_TN[GEMM_CFG_SKINNY] && g.opA == OP_N && g.opB == OP_N;
+  const int ov = g_override.load();
+  if (ov >= 0 && ov < GEMM_CFGS) return (ov == GEMM_CFG_SKINNY && !skinny_ok) ? 0 : ov;
+  const Table& t = table_for<T>(device, s);
+  // at most 64 tasks, evenly spaced, enter the prediction
+  const size_t stride = std::max<size_t>(1, ph.size() / 64);
+  int arg = 0;
+  double best = std::numeric_limits<double>::infinity();
+  for (int cfg = 0; cfg < GEMM_CFGS; ++cfg) {
+    if (cfg == GEMM_CFG_SKINNY && !skinny_ok) continue;
+    double cost = 0;
+    for (size_t i = 0; i < ph.size(); i += stride) cost += predict(t, cfg, ph[i]);
+    if (cost < best) {
+      best = cost;
+      arg = cfg;
+    }
+  }
+  return arg;
+}
+
+template <class T>
+void gemm_tune_table(int device, hipStream_t s, std::vector<double>& out) {
+  const Table& t = table_for<T>(device, s);
+  out.assign((const double*)t.us, (const double*)t.us + GEMM_CFGS * NM * NN * NK);
+}
+
+template void gemm_autotune<double>(int, hipStream_t);
+template void gemm_autotune<float>(int, hipStream_t);
+template int choose_gemm_cfg<double>(int, hipStream_t, const std::vector<GTask>&);
+template int choose_gemm_cfg<float>(int, hipStream_t, const std::vector<GTask>&);
+template void gemm_tune_table<double>(int, hipStream_t, std::vector<double>&);
+template void gemm_tune_table<float>(int, hipStream_t, std::vector<double>&);
+
+}  // namespace bfmf

@@ -192,6 +192,7 @@ GTask task(int64_t a_off, int64_t lda, int opA, int abase, int64_t b_off, int64_
 
 BfPlan make_plan(const std::vector<BfCall>& calls, bool adjoint, int nrhs, int64_t ldx, int64_t ldy,
                  bool right_half_only) {
+  HostTimer ht(HP_PLAN);
   BfPlan plan;
   int64_t ws = 0;
   size_t maxph = 0;
@@ -403,7 +404,7 @@ int64_t footprint(int64_t off, int64_t rows, int64_t cols, int64_t ld) {
 template <class T>
 void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y, void* ws, hipStream_t s,
               const int64_t lim[4], int kind) {
-  (void)c;
+  HostTimer ht_run(HP_RUN);
   void* bases[4] = {pool, const_cast<void*>(X), Y, ws};
   for (auto& ph : plan.phase)
     for (const GTask& t : ph) {
@@ -426,18 +427,18 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
   std::vector<char> blob;
   std::vector<size_t> toff, soff;
   std::vector<int64_t> ntiles;
-  std::vector<char> skinny;
+  std::vector<int> cfgs;
   for (auto& ph : plan.phase) {
-    // at most 16 columns and no transposes: 256-row streaming tiles, else 64 x 64 tiles
-    bool sk = !ph.empty();
-    for (const GTask& t : ph) sk = sk && t.N <= 16 && t.opA == OP_N && t.opB == OP_N;
-    skinny.push_back(sk ? 1 : 0);
+    // tile shape from the autotuned table (all shapes give the same result)
+    const int cfg = ph.empty() ? 0 : choose_gemm_cfg<T>(c.device, s, ph);
+    cfgs.push_back(cfg);
     std::vector<int64_t> start(ph.size());
     int64_t tiles = 0;
     for (size_t i = 0; i < ph.size(); ++i) {
       start[i] = tiles;
-      tiles += sk ? (int64_t)((ph[i].M + 255) / 256) : (int64_t)((ph[i].M + 63) / 64) * ((ph[i].N + 63) / 64);
+      tiles += gemm_cfg_tiles(cfg, ph[i].M, ph[i].N);
     }
+    if (tiles >= ((int64_t)1 << 31)) throw Error(BFMF_E_INVAL, "internal: grouped GEMM launch with 2^31 tiles");
     size_t o = (blob.size() + 15) & ~(size_t)15;
     blob.resize(o + ph.size() * sizeof(GTask) + start.size() * sizeof(int64_t));
     if (!ph.empty()) std::memcpy(blob.data() + o, ph.data(), ph.size() * sizeof(GTask));
@@ -455,9 +456,13 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
     if (plan.phase[k].empty()) continue;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const int tk = c.timer.want(kind) ? c.timer.begin_ext(&e0, &e1) : -1;
-    chk(launch_grouped_gemm<T>((const GTask*)(d + toff[k]), (const int64_t*)(d + soff[k]), (int)plan.phase[k].size(),
-                               ntiles[k], bases, skinny[k] != 0, s, e0, e1),
-        "grouped gemm");
+    {
+      HostTimer ht(HP_LAUNCH);
+      chk(launch_grouped_gemm<T>((const GTask*)(d + toff[k]), (const int64_t*)(d + soff[k]),
+                                 (int)plan.phase[k].size(), ntiles[k], bases, cfgs[k], s, e0, e1),
+          "grouped gemm");
+    }
+    c.gemm_cfg_launches[cfgs[k]] += 1;
     if (tk >= 0) {
       double fl = 0, by = 0;
       int mm = 0, mn = 0, mk = 0;
@@ -1025,7 +1030,11 @@ void random_once_batch(BfRuntime<T>& rt, const std::vector<RandomJob<T>*>& jobs)
   auto mk = rt.scratch.mark();
   const size_t nj = jobs.size();
   std::vector<Sketch<T>> sk(nj);
-  // probes and sketches: Y = K Omega (column groups of left levels), Z = K^H Psi (row groups of right levels)
+  // probes and sketches: Y = K Omega (column groups of left levels), Z = K^H Psi (row groups of right levels);
+  // the probe blocks of every job are drawn in one launch (each keeps its own generator stream)
+  std::vector<ProbeTask> ptasks;
+  std::vector<int32_t> gbeg, gend;
+  int64_t pmax = 0;
   for (size_t ji = 0; ji < nj; ++ji) {
     RandomJob<T>& j = *jobs[ji];
     j.out = std::make_unique<Butterfly>();
@@ -1056,13 +1065,24 @@ void random_once_batch(BfRuntime<T>& rt, const std::vector<RandomJob<T>*>& jobs)
     w.Y = rt.scratch.take((size_t)std::max(m, 1) * w.ncl * sizeof(cplx<T>));
     w.Ps = rt.scratch.take((size_t)std::max(m, 1) * w.ncr * sizeof(cplx<T>));
     w.Z = rt.scratch.take((size_t)std::max(n, 1) * w.ncr * sizeof(cplx<T>));
-    int32_t* d_gb = (int32_t*)upload_tmp(rt, gb);
-    int32_t* d_ge = (int32_t*)upload_tmp(rt, ge);
-    int32_t* d_hb = (int32_t*)upload_tmp(rt, hb);
-    int32_t* d_he = (int32_t*)upload_tmp(rt, he);
-    chk(launch_philox_gauss<T>(w.Om, std::max(n, 1), n, w.ncl, S, d_gb, d_ge, rt.seed, rt.stream_id++, s), "probes");
-    chk(launch_philox_gauss<T>(w.Ps, std::max(m, 1), m, w.ncr, S, d_hb, d_he, rt.seed, rt.stream_id++, s), "probes");
+    ProbeTask po{w.Om, std::max(n, 1), n, w.ncl, S, (int32_t)gbeg.size(), 0, rt.stream_id++};
+    gbeg.insert(gbeg.end(), gb.begin(), gb.end());
+    gend.insert(gend.end(), ge.begin(), ge.end());
+    ProbeTask pp{w.Ps, std::max(m, 1), m, w.ncr, S, (int32_t)gbeg.size(), 0, rt.stream_id++};
+    gbeg.insert(gbeg.end(), hb.begin(), hb.end());
+    gend.insert(gend.end(), he.begin(), he.end());
+    for (const ProbeTask& p : {po, pp})
+      if (p.n > 0 && p.ncol > 0) {
+        ptasks.push_back(p);
+        pmax = std::max<int64_t>(pmax, p.n * p.ncol);
+      }
     j.max_id_rank = 0;
+  }
+  if (!ptasks.empty()) {
+    const int32_t* d_gb = (const int32_t*)upload_tmp(rt, gbeg);
+    const int32_t* d_ge = (const int32_t*)upload_tmp(rt, gend);
+    const ProbeTask* d_pt = (const ProbeTask*)upload_tmp(rt, ptasks);
+    chk(launch_philox_gauss_batch<T>(d_pt, (int)ptasks.size(), pmax, d_gb, d_ge, rt.seed, s), "probes");
   }
   // the sketches of every job: operators of one structure are applied together (apply_all)
   {

@@ -630,22 +630,24 @@ void smw_dense_batch(BfRuntime<T>& rt, const std::vector<SmwJob<T>*>& jobs, int*
   }
   std::vector<FrontDesc> fds(nj);
   std::vector<cplx<double>*> Fs(nj);  // the bordered fronts, factored in FP64
-  std::vector<cplx<T>*> Is(nj);
+  std::vector<cplx<T>*> Fw(nj);        // the same in the working precision, before the LU
+  std::vector<AxpbyTask> border(nj), widen, finish(nj);
+  std::vector<Op<T>*> kops(nj);
+  std::vector<ApplyArg> kargs(nj);
+  int64_t maxn = 0;
   for (size_t i = 0; i < nj; ++i) {
     const int n = hns[i], N2 = hn[i];
+    maxn = std::max<int64_t>(maxn, n);
     cplx<T>* F = (cplx<T>*)rt.scratch.take((size_t)N2 * N2 * sizeof(cplx<T>));
     cplx<T>* I = (cplx<T>*)rt.scratch.take((size_t)n * n * sizeof(cplx<T>));
     int32_t* piv = (int32_t*)rt.scratch.take((size_t)n * sizeof(int32_t));
-    ochk(launch_set_eye<T>(F, N2, N2, N2, 0, 1.0, s), "border");                    // M = I + K: identity part
-    ochk(launch_set_eye<T>(F + n + (size_t)n * N2, N2, n, n, 0, 0.0, s), "border");  // F22 = 0
-    ochk(launch_set_eye<T>(F + (size_t)n * N2, N2, n, n, 0, 1.0, s), "border");      // F12 = I
-    ochk(launch_set_eye<T>(F + n, N2, n, n, 0, -1.0, s), "border");                  // F21 = -I
-    ochk(launch_set_eye<T>(I, n, n, n, 0, 1.0, s), "identity");
-    jobs[i]->Kfull->apply(I, n, F, N2, n, false, 1.0, 1);  // F11 = I + K
+    border[i] = AxpbyTask{F, I, N2, n, n, n, 0};  // F = [I I; -I 0], I = identity
+    kops[i] = jobs[i]->Kfull;
+    kargs[i] = ApplyArg{I, n, F, N2, n};  // F11 += K
     cplx<double>* F64 = (cplx<double>*)F;
     if (sizeof(T) != 8) {  // pivot blocks in FP64
       F64 = (cplx<double>*)rt.scratch.take((size_t)N2 * N2 * sizeof(cplx<double>));
-      ochk(launch_convert<double, T>(F64, N2, F, N2, N2, N2, s), "border to FP64");
+      widen.push_back(AxpbyTask{F64, F, N2, N2, N2, N2, 0});
     }
     FrontDesc& fd = fds[i];
     std::memset(&fd, 0, sizeof(fd));
@@ -655,18 +657,25 @@ void smw_dense_batch(BfRuntime<T>& rt, const std::vector<SmwJob<T>*>& jobs, int*
     fd.front = -1;
     fd.piv = piv;
     Fs[i] = F64;
-    Is[i] = I;
+    Fw[i] = F;
   }
+  ochk(launch_smw_border<T>((const AxpbyTask*)up(rt, border), (int)nj, maxn, s), "border");
+  apply_all<T>(rt, kops, kargs, false, 1.0, 1);
+  if (!widen.empty())
+    ochk(launch_mix_batch<double, T>((const AxpbyTask*)up(rt, widen), (int)widen.size(), 4 * maxn * maxn, 1.0, 0.0,
+                                     0.0, s),
+         "border to FP64");
   const FrontDesc* d_fd = (const FrontDesc*)up(rt, fds);
   ochk(launch_partial_lu<double>(d_fd, (int)nj, hn.data(), hns.data(), d_status, s), "smw dense lu");
   ochk(launch_schur<double>(d_fd, (int)nj, hn.data(), hns.data(), s), "smw dense schur");
   for (size_t i = 0; i < nj; ++i) {
     const int n = hns[i], N2 = hn[i];
     cplx<T>* X = (cplx<T>*)(rt.pool_base() + eoff[i] * sizeof(cplx<T>));
-    ochk(launch_convert<T, double>(X, n, Fs[i] + n + (size_t)n * N2, N2, n, n, s), "copy");  // M^-1
-    ochk(launch_axpby<T>(X, n, Is[i], n, n, n, -1.0, 1.0, s), "minus identity");
+    finish[i] = AxpbyTask{X, Fs[i] + n + (size_t)n * N2, n, N2, n, n, 0};  // X = M^-1 - I
     jobs[i]->res.dense_off = eoff[i];
   }
+  ochk(launch_mix_batch<T, double>((const AxpbyTask*)up(rt, finish), (int)nj, maxn * maxn, 1.0, 0.0, -1.0, s),
+       "M^-1 - I");
   rt.scratch.release(mk);
 }
 
@@ -1025,16 +1034,21 @@ static void factor_level(CompState<T>* st, Context& c, const std::vector<int>& f
                                                 sizeof(cplx<T>));
     std::vector<InvTask> it;
     auto mk = rt.scratch.mark();
+    std::vector<AxpbyTask> cp;  // copies / conversions of all leaves in one launch
+    int64_t maxe = 0;
     if (sizeof(T) == 8) {  // invert the leaves in place of a copy
       for (auto& w : W)
         for (auto& nd : w->cf->f11.nodes)
           if (nd.left < 0) {
-            ochk(launch_axpby<T>(rt.pool_base() + nd.inv_off * sizeof(cplx<T>), nd.size(),
-                                 rt.pool_base() + nd.leaf_off * sizeof(cplx<T>), nd.size(), nd.size(), nd.size(), 1.0,
-                                 0.0, s),
-                 "leaf copy");
+            cp.push_back(AxpbyTask{rt.pool_base() + nd.inv_off * sizeof(cplx<T>),
+                                   rt.pool_base() + nd.leaf_off * sizeof(cplx<T>), std::max(nd.size(), 1),
+                                   std::max(nd.size(), 1), nd.size(), nd.size(), 0});
+            maxe = std::max<int64_t>(maxe, (int64_t)nd.size() * nd.size());
             it.push_back(InvTask{rt.pool_base() + nd.inv_off * sizeof(cplx<T>), std::max(nd.size(), 1), nd.size(), 0});
           }
+      if (!cp.empty())
+        ochk(launch_mix_batch<double, double>((const AxpbyTask*)up(rt, cp), (int)cp.size(), maxe, 1.0, 0.0, 0.0, s),
+             "leaf copy");
       void* d_it = up(rt, it);
       ochk(launch_leaf_inverse<double>(d_it, (int)it.size(), d_status, s), "leaf inverse");
     } else {  // pivot blocks in FP64: extract the leaves again in FP64, invert, store in complex64
@@ -1053,9 +1067,14 @@ static void factor_level(CompState<T>* st, Context& c, const std::vector<int>& f
       run_extract_to<double>(rt, eb, false);
       void* d_it = up(rt, it);
       ochk(launch_leaf_inverse<double>(d_it, (int)it.size(), d_status, s), "leaf inverse");
-      for (auto& t : tmp)
-        ochk(launch_convert<T, double>(rt.pool_base() + t.second->inv_off * sizeof(cplx<T>), t.second->size(), t.first,
-                                       t.second->size(), t.second->size(), t.second->size(), s),
+      for (auto& t : tmp) {
+        const int sz = t.second->size();
+        cp.push_back(AxpbyTask{rt.pool_base() + t.second->inv_off * sizeof(cplx<T>), t.first, std::max(sz, 1),
+                               std::max(sz, 1), sz, sz, 0});
+        maxe = std::max<int64_t>(maxe, (int64_t)sz * sz);
+      }
+      if (!cp.empty())
+        ochk(launch_mix_batch<T, double>((const AxpbyTask*)up(rt, cp), (int)cp.size(), maxe, 1.0, 0.0, 0.0, s),
              "leaf convert");
     }
     rt.scratch.release(mk);
@@ -1193,24 +1212,56 @@ static void factor_level(CompState<T>* st, Context& c, const std::vector<int>& f
       eb.add(w->d_fd, nullptr, 0, r, ns, r, ns, w->cb, nu, false);
     }
     run_extract_to<double>(rt, eb, false);  // C_nu1 (+) C_nu2 on I^u x I^u, FP64
+    // S applied to identity columns in chunks of 1024, chunk c0 of every front in one product
     const int chunk = 1024;
     auto mk = rt.scratch.mark();
-    cplx<T>* I = (cplx<T>*)rt.scratch.take((size_t)std::max(maxnu, 1) * chunk * sizeof(cplx<T>));
-    cplx<T>* St = sizeof(T) == 8 ? nullptr
-                                 : (cplx<T>*)rt.scratch.take((size_t)std::max(maxnu, 1) * chunk * sizeof(cplx<T>));
-    for (auto& w : W) {
-      const int nu = w->cf->nu;
-      for (int c0 = 0; c0 < nu; c0 += chunk) {
+    std::vector<cplx<T>*> I(W.size(), nullptr), St(W.size(), nullptr);
+    for (size_t k = 0; k < W.size(); ++k) {
+      const int nu = W[k]->cf->nu;
+      if (nu == 0) continue;
+      I[k] = (cplx<T>*)rt.scratch.take((size_t)nu * std::min(chunk, nu) * sizeof(cplx<T>));
+      if (sizeof(T) != 8) St[k] = (cplx<T>*)rt.scratch.take((size_t)nu * std::min(chunk, nu) * sizeof(cplx<T>));
+    }
+    const int64_t esz = (int64_t)sizeof(cplx<T>);
+    for (int c0 = 0; c0 < maxnu; c0 += chunk) {
+      std::vector<AxpbyTask> eye, upd;
+      std::vector<BfCall> calls;
+      int64_t maxe = 0;
+      for (size_t k = 0; k < W.size(); ++k) {
+        const int nu = W[k]->cf->nu;
+        if (nu <= c0) continue;
         const int wd = std::min(chunk, nu - c0);
-        ochk(launch_set_eye<T>(I, nu, nu, wd, c0, 1.0, s), "eye");
-        cplx<double>* cbc = (cplx<double>*)w->cb + (size_t)c0 * nu;  // contribution blocks stay FP64
-        if (sizeof(T) == 8) {
-          rt.apply(*w->cf->s, I, nu, cbc, nu, wd, false, -1.0, 1);
-        } else {
-          rt.apply(*w->cf->s, I, nu, St, nu, wd, false, 1.0, 0);
-          ochk(launch_axpby_mixed<double, T>(cbc, nu, St, nu, nu, wd, -1.0, 1.0, s), "cb update");
+        maxe = std::max<int64_t>(maxe, (int64_t)nu * wd);
+        eye.push_back(AxpbyTask{I[k], nullptr, nu, nu, nu, wd, c0});  // I(i, c) = 1 where i == c0 + c
+        cplx<double>* cbc = (cplx<double>*)W[k]->cb + (size_t)c0 * nu;  // contribution blocks stay FP64
+        BfCall cl;
+        cl.bf = W[k]->cf->s.get();
+        cl.x_off = cl.y_off = 0;
+        cl.alpha_im = 0;
+        cl.x_abs = (int64_t)((uintptr_t)I[k] / esz);
+        cl.ldx = cl.ldy = nu;
+        cl.nrhs = wd;
+        if (sizeof(T) == 8) {  // C -= S I
+          cl.alpha_re = -1.0;
+          cl.beta = 1;
+          cl.y_abs = (int64_t)((uintptr_t)cbc / esz);
+        } else {  // St = S I, then C -= St in FP64
+          cl.alpha_re = 1.0;
+          cl.beta = 0;
+          cl.y_abs = (int64_t)((uintptr_t)St[k] / esz);
+          upd.push_back(AxpbyTask{cbc, St[k], nu, nu, nu, wd, 0});
         }
+        calls.push_back(cl);
       }
+      ochk(launch_mix_batch<T, T>((const AxpbyTask*)up(rt, eye), (int)eye.size(), maxe, 0.0, 0.0, 1.0, s), "eye");
+      if (rt.batch) {
+        rt.apply_calls(calls, false);
+      } else {  // the plain form: one front after another
+        for (const BfCall& cl : calls) rt.apply_calls({cl}, false);
+      }
+      if (!upd.empty())
+        ochk(launch_mix_batch<double, T>((const AxpbyTask*)up(rt, upd), (int)upd.size(), maxe, -1.0, 1.0, 0.0, s),
+             "cb update");
     }
     rt.scratch.release(mk);
   }

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <array>
+#include <chrono>
 #include <map>
 #include <memory>
 #include <string>
@@ -55,6 +56,29 @@ class Error : public std::exception {
 // caller's vector may be freed at once and no synchronisation is needed.  The
 // ring is reused after the stream has been synchronised (sync()), or, when it
 // is full, after put() has synchronised the stream itself.
+// Host-side time of a factorization by activity (BFMF_VERBOSE diagnostics).
+enum HostSlot { HP_SYNC = 0, HP_PUT, HP_LAUNCH, HP_PLAN, HP_RUN, HP_COUNT };
+struct HostProf {
+  double sec[HP_COUNT] = {};
+  int64_t n[HP_COUNT] = {};
+  void reset() {
+    for (int i = 0; i < HP_COUNT; ++i) sec[i] = 0, n[i] = 0;
+  }
+};
+extern thread_local HostProf* g_hprof;  // the profile of the call in progress on this thread, or null
+struct HostTimer {
+  int slot;
+  std::chrono::steady_clock::time_point t0;
+  explicit HostTimer(int sl) : slot(sl) {
+    if (g_hprof) t0 = std::chrono::steady_clock::now();
+  }
+  ~HostTimer() {
+    if (!g_hprof) return;
+    g_hprof->sec[slot] += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    g_hprof->n[slot] += 1;
+  }
+};
+
 struct Staging {
   char* host = nullptr;
   size_t cap = 0, head = 0;
@@ -183,6 +207,7 @@ struct Context {
   DevBuf d_fac;            // factors of the dense fronts, kept for the sweeps
   DevBuf d_kept;           // debug copies of assembled fronts
   bfmf_factor_opts fopts{};
+  int64_t gemm_cfg_launches[8] = {};  // grouped-GEMM launches per tile shape (since the last stats reset)
   bfmf_stats stats{};
 
   // device: solve workspaces
@@ -201,6 +226,7 @@ struct Context {
   std::vector<int32_t> level_ndense;  // dense fronts of each level
   void* comp = nullptr;               // CompState (compressed.cpp)
   bool verbose = false;               // BFMF_VERBOSE: phase timings of compressed fronts on stderr
+  HostProf hprof;                     // host time of the last factorization by activity (verbose only)
 
   uint64_t device_bytes() const;
   ~Context();
@@ -208,6 +234,16 @@ struct Context {
 
 // message of the last failed call on this thread that had no handle to hold it
 extern thread_local std::string g_thread_error;
+
+// autotune.cpp: tile shape of a grouped-GEMM launch (measured table per device
+// and precision, built on first use); a process-wide override (-1: autotuned)
+template <class T>
+void gemm_autotune(int device, hipStream_t s);
+template <class T>
+int choose_gemm_cfg(int device, hipStream_t s, const std::vector<GTask>& ph);
+template <class T>
+void gemm_tune_table(int device, hipStream_t s, std::vector<double>& out);
+void set_gemm_tile_override(int cfg);
 
 // compressed.cpp
 void* comp_state_create(Context& c);

@@ -92,4 +92,15 @@ struct AxpbyTask {
   int32_t ncol, pad;
 };
 
+// One block of Gaussian probe columns: Om (n x ncol, ld); column c belongs to
+// group g0 + c / width, supported on the rows [gbeg[g], gend[g]) of the
+// launch's group arrays; entries from the counter-based generator keyed by
+// (seed, stream_id, row, column).
+struct ProbeTask {
+  void* Om;
+  int64_t ld, n;
+  int32_t ncol, width, g0, pad;
+  uint64_t stream_id;
+};
+
 }  // namespace bfmf

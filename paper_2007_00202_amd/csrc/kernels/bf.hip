@@ -41,25 +41,38 @@ __device__ __forceinline__ uintptr_t task_addr(int i, int64_t off, void* b0, voi
   return b + (uintptr_t)off * sizeof(cplx<T>);
 }
 
-template <class T>
+template <class T, class C>
 __global__ __launch_bounds__(256) void grouped_gemm_kernel(const GTask* __restrict__ tasks,
                                                            const int64_t* __restrict__ tile_start, int ntasks,
                                                            void* b0, void* b1, void* b2, void* b3) {
-  __shared__ GemmSmem<T> sm;
+  __shared__ TileSmem<T, C> sm;
   const int64_t tile = blockIdx.x;
   const int lo = find_task(tile_start, ntasks, tile);
   const GTask& t = tasks[lo];
   const int64_t local = tile - tile_start[lo];
-  const int tm = (t.M + GEMM_TM - 1) / GEMM_TM;
-  const int tn = (t.N + GEMM_TN - 1) / GEMM_TN;
+  const int tm = (t.M + C::TM - 1) / C::TM;
+  const int tn = (t.N + C::TN - 1) / C::TN;
   if (local >= (int64_t)tm * tn || t.M <= 0 || t.N <= 0) return;
   const cplx<T>* A = (const cplx<T>*)task_addr<T>(t.abase, t.a_off, b0, b1, b2, b3);
   const cplx<T>* B = (const cplx<T>*)task_addr<T>(t.bbase, t.b_off, b0, b1, b2, b3);
-  cplx<T>* C = (cplx<T>*)task_addr<T>(t.cbase, t.c_off, b0, b1, b2, b3);
+  cplx<T>* Cm = (cplx<T>*)task_addr<T>(t.cbase, t.c_off, b0, b1, b2, b3);
   const cplx<T> alpha = {(T)t.alpha_re, (T)t.alpha_im};
-  gemm_tile<T>(A, t.lda, t.opA, B, t.ldb, C, t.ldc, t.M, t.N, t.K, alpha, t.beta, (int)(local % tm), (int)(local / tm),
-               sm, t.opB);
+  gemm_tile_cfg<T, C>(A, t.lda, t.opA, B, t.ldb, t.opB, Cm, t.ldc, t.M, t.N, t.K, alpha, t.beta, (int)(local % tm),
+                      (int)(local / tm), sm);
 }
+
+// the LDS tile shapes of the launcher's cfg index (GEMM_CFG_TM / GEMM_CFG_TN)
+typedef TileCfg<2, 2, 2, 2> Tile64x64;
+typedef TileCfg<2, 2, 1, 4> Tile32x128;
+typedef TileCfg<2, 2, 4, 1> Tile128x32;
+typedef TileCfg<1, 4, 1, 4> Tile16x256;
+typedef TileCfg<4, 1, 4, 1> Tile256x16;
+static_assert(Tile64x64::TM == GEMM_CFG_TM[0] && Tile64x64::TN == GEMM_CFG_TN[0], "tile table");
+static_assert(Tile32x128::TM == GEMM_CFG_TM[1] && Tile32x128::TN == GEMM_CFG_TN[1], "tile table");
+static_assert(Tile128x32::TM == GEMM_CFG_TM[2] && Tile128x32::TN == GEMM_CFG_TN[2], "tile table");
+static_assert(Tile16x256::TM == GEMM_CFG_TM[3] && Tile16x256::TN == GEMM_CFG_TN[3], "tile table");
+static_assert(Tile256x16::TM == GEMM_CFG_TM[4] && Tile256x16::TN == GEMM_CFG_TN[4], "tile table");
+static_assert(SKINNY_TM == GEMM_CFG_TM[GEMM_CFG_SKINNY] && SKINNY_TN == GEMM_CFG_TN[GEMM_CFG_SKINNY], "tile table");
 
 // phases whose tasks are all C = beta C + alpha A B (no transposes) with N <= 16: 256-row tiles
 template <class T>
@@ -464,6 +477,16 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
 // Omega (n x ncol, ld n): column c belongs to group g = c / width; group g is
 // supported on rows [gbeg[g], gend[g]) and zero elsewhere.
 template <class T>
+__device__ __forceinline__ cplx<T> probe_entry(int64_t i, int c, uint64_t seed, uint64_t stream_id) {
+  uint32_t ctr[4] = {(uint32_t)i, (uint32_t)(i >> 32), (uint32_t)c, (uint32_t)stream_id};
+  philox4x32_10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32) ^ (uint32_t)(stream_id >> 32));
+  const double u1 = ((double)ctr[0] + 1.0) * (1.0 / 4294967296.0);  // (0, 1]
+  const double u2 = (double)ctr[1] * (1.0 / 4294967296.0);
+  const double rad = sqrt(-log(u1));  // |z|^2 ~ Exp(1): unit variance complex
+  return cplx<T>{(T)(rad * cos(6.283185307179586 * u2)), (T)(rad * sin(6.283185307179586 * u2))};
+}
+
+template <class T>
 __global__ void philox_gauss_kernel(cplx<T>* __restrict__ Om, int64_t ld, int64_t n, int ncol, int width,
                                     const int32_t* __restrict__ gbeg, const int32_t* __restrict__ gend,
                                     uint64_t seed, uint64_t stream_id) {
@@ -472,16 +495,26 @@ __global__ void philox_gauss_kernel(cplx<T>* __restrict__ Om, int64_t ld, int64_
   if (i >= n || c >= ncol) return;
   const int g = c / width;
   cplx<T> z = {0, 0};
-  if (i >= gbeg[g] && i < gend[g]) {
-    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)(i >> 32), (uint32_t)c, (uint32_t)stream_id};
-    philox4x32_10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32) ^ (uint32_t)(stream_id >> 32));
-    const double u1 = ((double)ctr[0] + 1.0) * (1.0 / 4294967296.0);  // (0, 1]
-    const double u2 = (double)ctr[1] * (1.0 / 4294967296.0);
-    const double rad = sqrt(-log(u1));  // |z|^2 ~ Exp(1): unit variance complex
-    z.re = (T)(rad * cos(6.283185307179586 * u2));
-    z.im = (T)(rad * sin(6.283185307179586 * u2));
-  }
+  if (i >= gbeg[g] && i < gend[g]) z = probe_entry<T>(i, c, seed, stream_id);
   Om[i + (int64_t)c * ld] = z;
+}
+
+// the same probe blocks for many tasks in one launch (grid row = task)
+template <class T>
+__global__ __launch_bounds__(256) void philox_gauss_batch_kernel(const ProbeTask* __restrict__ tasks,
+                                                                 const int32_t* __restrict__ gbeg,
+                                                                 const int32_t* __restrict__ gend, uint64_t seed) {
+  const ProbeTask& t = tasks[blockIdx.x];
+  const int64_t tot = t.n * t.ncol;
+  cplx<T>* Om = (cplx<T>*)t.Om;
+  for (int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.y * 256) {
+    const int64_t i = e % t.n;
+    const int c = (int)(e / t.n);
+    const int g = t.g0 + c / t.width;
+    cplx<T> z = {0, 0};
+    if (i >= gbeg[g] && i < gend[g]) z = probe_entry<T>(i, c, seed, t.stream_id);
+    Om[i + (int64_t)c * t.ld] = z;
+  }
 }
 
 // ------------------------------------------------------------ small solves
@@ -696,6 +729,56 @@ __global__ __launch_bounds__(256) void axpby_batch_kernel(const AxpbyTask* __res
   }
 }
 
+// Y (T1) = a X (T2) + b Y + diag E on each task's m x ncol block, in double,
+// with E(i, c) = 1 where i == c + task.pad (X null: zero; b = 0 overwrites Y);
+// grid row = task
+template <class T1, class T2>
+__global__ __launch_bounds__(256) void mix_batch_kernel(const AxpbyTask* __restrict__ tasks, double a, double b,
+                                                        double diag) {
+  const AxpbyTask& t = tasks[blockIdx.x];
+  const int64_t tot = t.m * t.ncol;
+  cplx<T1>* Y = (cplx<T1>*)t.Y;
+  const cplx<T2>* X = (const cplx<T2>*)t.X;
+  for (int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.y * 256) {
+    const int64_t i = e % t.m, c = e / t.m;
+    double xr = 0, xi = 0, yr = 0, yi = 0;
+    if (X) {
+      const cplx<T2> x = X[i + c * t.ldx];
+      xr = x.re;
+      xi = x.im;
+    }
+    if (b != 0) {
+      const cplx<T1> y = Y[i + c * t.ldy];
+      yr = y.re;
+      yi = y.im;
+    }
+    Y[i + c * t.ldy] = cplx<T1>{(T1)(a * xr + b * yr + (i == c + t.pad ? diag : 0.0)), (T1)(a * xi + b * yi)};
+  }
+}
+
+// Bordered fronts of the SMW dense base, one per task (Y: 2n x 2n, ld 2n; X:
+// n x n, ld n, written too; n = m): F = [I I; -I 0] and E = I.  The caller
+// then adds K to the leading block (F11 = I + K).
+template <class T>
+__global__ __launch_bounds__(256) void smw_border_kernel(const AxpbyTask* __restrict__ tasks) {
+  const AxpbyTask& t = tasks[blockIdx.x];
+  const int64_t n = t.m, n2 = 2 * t.m, tot = n2 * n2;
+  cplx<T>* F = (cplx<T>*)t.Y;
+  cplx<T>* E = (cplx<T>*)const_cast<void*>(t.X);
+  for (int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.y * 256) {
+    const int64_t i = e % n2, c = e / n2;
+    T v = 0;
+    if (i < n && c < n)
+      v = i == c ? (T)1 : (T)0;
+    else if (i < n)
+      v = c - n == i ? (T)1 : (T)0;
+    else if (c < n)
+      v = i - n == c ? (T)-1 : (T)0;
+    F[i + c * n2] = cplx<T>{v, (T)0};
+    if (i < n && c < n) E[i + c * n] = cplx<T>{i == c ? (T)1 : (T)0, (T)0};
+  }
+}
+
 // Y(i, j) = v if i == j + off, else 0, on an m x ncol block
 template <class T>
 __global__ void set_eye_kernel(cplx<T>* __restrict__ Y, int64_t ldy, int64_t m, int ncol, int64_t off, double v) {
@@ -742,24 +825,27 @@ __global__ void convert_kernel(cplx<T1>* __restrict__ Y, int64_t ldy, const cplx
 
 template <class T>
 hipError_t launch_grouped_gemm(const GTask* d_tasks, const int64_t* d_tile_start, int ntasks, int64_t ntiles,
-                               void* const bases[4], bool skinny, hipStream_t s, hipEvent_t ev_start,
+                               void* const bases[4], int cfg, hipStream_t s, hipEvent_t ev_start,
                                hipEvent_t ev_stop) {
   if (ntasks == 0 || ntiles == 0) return hipSuccess;
-  // grids are limited to 2^31 - 1 blocks in x
-  const dim3 grid((unsigned)ntiles);
-  if (ev_start) {
-    if (skinny)
-      hipExtLaunchKernelGGL((grouped_gemm_skinny_kernel<T>), grid, dim3(256), 0, s, ev_start, ev_stop, 0, d_tasks,
-                            d_tile_start, ntasks, bases[0], bases[1], bases[2], bases[3]);
+  if (cfg < 0 || cfg >= GEMM_CFGS) return hipErrorInvalidValue;
+  // grids are limited to 2^31 - 1 blocks in x (the host checks ntiles)
+  const dim3 grid((unsigned)ntiles), block(256);
+  auto go = [&](auto kernel) {
+    if (ev_start)
+      hipExtLaunchKernelGGL(kernel, grid, block, 0, s, ev_start, ev_stop, 0, d_tasks, d_tile_start, ntasks, bases[0],
+                            bases[1], bases[2], bases[3]);
     else
-      hipExtLaunchKernelGGL((grouped_gemm_kernel<T>), grid, dim3(256), 0, s, ev_start, ev_stop, 0, d_tasks,
-                            d_tile_start, ntasks, bases[0], bases[1], bases[2], bases[3]);
-  } else if (skinny) {
-    hipLaunchKernelGGL((grouped_gemm_skinny_kernel<T>), grid, dim3(256), 0, s, d_tasks, d_tile_start, ntasks,
-                       bases[0], bases[1], bases[2], bases[3]);
-  } else {
-    hipLaunchKernelGGL((grouped_gemm_kernel<T>), grid, dim3(256), 0, s, d_tasks, d_tile_start, ntasks, bases[0],
-                       bases[1], bases[2], bases[3]);
+      hipLaunchKernelGGL(kernel, grid, block, 0, s, d_tasks, d_tile_start, ntasks, bases[0], bases[1], bases[2],
+                         bases[3]);
+  };
+  switch (cfg) {
+    case 0: go(grouped_gemm_kernel<T, Tile64x64>); break;
+    case 1: go(grouped_gemm_kernel<T, Tile32x128>); break;
+    case 2: go(grouped_gemm_kernel<T, Tile128x32>); break;
+    case 3: go(grouped_gemm_kernel<T, Tile16x256>); break;
+    case 4: go(grouped_gemm_kernel<T, Tile256x16>); break;
+    default: go(grouped_gemm_skinny_kernel<T>); break;
   }
   return hipGetLastError();
 }
@@ -851,6 +937,35 @@ hipError_t launch_axpby_batch(const AxpbyTask* d_tasks, int ntasks, int64_t max_
   return hipGetLastError();
 }
 
+static unsigned batch_rows(int64_t max_entries) {
+  return (unsigned)std::min<int64_t>(64, std::max<int64_t>(1, (max_entries + 4095) / 4096));
+}
+
+template <class T1, class T2>
+hipError_t launch_mix_batch(const AxpbyTask* d_tasks, int ntasks, int64_t max_entries, double a, double b,
+                            double diag, hipStream_t s) {
+  if (ntasks == 0 || max_entries == 0) return hipSuccess;
+  hipLaunchKernelGGL((mix_batch_kernel<T1, T2>), dim3(ntasks, batch_rows(max_entries)), dim3(256), 0, s, d_tasks, a,
+                     b, diag);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_smw_border(const AxpbyTask* d_tasks, int ntasks, int64_t max_n, hipStream_t s) {
+  if (ntasks == 0 || max_n == 0) return hipSuccess;
+  hipLaunchKernelGGL((smw_border_kernel<T>), dim3(ntasks, batch_rows(4 * max_n * max_n)), dim3(256), 0, s, d_tasks);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_philox_gauss_batch(const ProbeTask* d_tasks, int ntasks, int64_t max_entries,
+                                     const int32_t* d_gbeg, const int32_t* d_gend, uint64_t seed, hipStream_t s) {
+  if (ntasks == 0 || max_entries == 0) return hipSuccess;
+  hipLaunchKernelGGL((philox_gauss_batch_kernel<T>), dim3(ntasks, batch_rows(max_entries)), dim3(256), 0, s, d_tasks,
+                     d_gbeg, d_gend, seed);
+  return hipGetLastError();
+}
+
 template <class T>
 hipError_t launch_set_eye(void* Y, int64_t ldy, int64_t m, int ncol, int64_t off, double v, hipStream_t s) {
   if (m == 0 || ncol == 0) return hipSuccess;
@@ -877,7 +992,7 @@ hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int6
 }
 
 #define INST(T)                                                                                                       \
-  template hipError_t launch_grouped_gemm<T>(const GTask*, const int64_t*, int, int64_t, void* const[4], bool,        \
+  template hipError_t launch_grouped_gemm<T>(const GTask*, const int64_t*, int, int64_t, void* const[4], int,         \
                                              hipStream_t, hipEvent_t, hipEvent_t);                                    \
   template hipError_t launch_cpqr_id<T>(const IdTask*, int, double, hipStream_t);                                     \
   template hipError_t launch_gram_id<T>(const IdTask*, int, double, hipStream_t);                                     \
@@ -891,9 +1006,20 @@ hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int6
                                             hipStream_t);                                                             \
   template hipError_t launch_axpby<T>(void*, int64_t, const void*, int64_t, int64_t, int, double, double, hipStream_t); \
   template hipError_t launch_set_eye<T>(void*, int64_t, int64_t, int, int64_t, double, hipStream_t);               \
-  template hipError_t launch_axpby_batch<T>(const AxpbyTask*, int, int64_t, double, double, hipStream_t);
+  template hipError_t launch_axpby_batch<T>(const AxpbyTask*, int, int64_t, double, double, hipStream_t);           \
+  template hipError_t launch_smw_border<T>(const AxpbyTask*, int, int64_t, hipStream_t);                             \
+  template hipError_t launch_philox_gauss_batch<T>(const ProbeTask*, int, int64_t, const int32_t*, const int32_t*,    \
+                                                   uint64_t, hipStream_t);
 INST(double)
 INST(float)
+template hipError_t launch_mix_batch<double, double>(const AxpbyTask*, int, int64_t, double, double, double,
+                                                     hipStream_t);
+template hipError_t launch_mix_batch<double, float>(const AxpbyTask*, int, int64_t, double, double, double,
+                                                    hipStream_t);
+template hipError_t launch_mix_batch<float, double>(const AxpbyTask*, int, int64_t, double, double, double,
+                                                    hipStream_t);
+template hipError_t launch_mix_batch<float, float>(const AxpbyTask*, int, int64_t, double, double, double,
+                                                   hipStream_t);
 template hipError_t launch_axpby_mixed<double, float>(void*, int64_t, const void*, int64_t, int64_t, int, double,
                                                       double, hipStream_t);
 template hipError_t launch_axpby_mixed<float, double>(void*, int64_t, const void*, int64_t, int64_t, int, double,

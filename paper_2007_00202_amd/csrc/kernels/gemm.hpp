@@ -158,6 +158,146 @@ __device__ __forceinline__ void gemm_tile(const cplx<T>* __restrict__ A, int64_t
       }
 }
 
+// ------------------------------------------------------------ tile shapes
+// The grouped GEMM of butterfly products runs one of several tile shapes
+// per launch.  A 256-thread workgroup (four waves) computes a TM x TN tile of
+// C; the waves form a WI x WJ grid and each wave computes BI x BJ blocks of
+// 16 x 16 (MFMA 16x16x4, four real MFMAs per complex multiply-add).  Every
+// shape adds the products of an output entry in the same order (k in steps of
+// 16 through LDS, 4 per MFMA), so all shapes give the same result bit for bit.
+template <int BI_, int BJ_, int WI_, int WJ_>
+struct TileCfg {
+  static constexpr int BI = BI_, BJ = BJ_, WI = WI_, WJ = WJ_;
+  static constexpr int TM = 16 * BI * WI, TN = 16 * BJ * WJ, TK = 16;
+  static_assert(WI * WJ == 4, "four waves per workgroup");
+  static_assert(TM * TK % 256 == 0 && TN * TK % 256 == 0, "whole staging loads per thread");
+};
+
+// One padding entry per row: operands stored with k contiguous (B untransposed,
+// A transposed) are written down a column, 16 lanes at a row stride that
+// would otherwise map them all to the same LDS banks.
+template <class T, class C>
+struct TileSmem {
+  cplx<T> a[C::TK][C::TM + 1];
+  cplx<T> b[C::TK][C::TN + 1];
+};
+
+// Tile (tm, tn) of C = beta C + alpha op(A) op(B); operand conventions as in gemm_tile.
+template <class T, class C>
+__device__ __forceinline__ void gemm_tile_cfg(const cplx<T>* __restrict__ A, int64_t lda, int opA,
+                                              const cplx<T>* __restrict__ B, int64_t ldb, int opB,
+                                              cplx<T>* __restrict__ Cm, int64_t ldc, int M, int N, int K,
+                                              cplx<T> alpha, int beta, int tm, int tn, TileSmem<T, C>& sm) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int TM = C::TM, TN = C::TN, TK = C::TK, BI = C::BI, BJ = C::BJ;
+  constexpr int NA = TM * TK / 256, NB = TN * TK / 256;  // staged entries per thread
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = (wave % C::WI) * 16 * BI, wc = (wave / C::WI) * 16 * BJ;
+  const int row0 = tm * TM, col0 = tn * TN;
+  acc_t accr[BI][BJ], acci[BI][BJ];
+#pragma unroll
+  for (int i = 0; i < BI; ++i)
+#pragma unroll
+    for (int j = 0; j < BJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        accr[i][j][r] = 0;
+        acci[i][j][r] = 0;
+      }
+  // staged entry e = tid + 256 q: consecutive threads take consecutive
+  // addresses of the operand's contiguous dimension
+  cplx<T> ra[NA], rb[NB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
+      if (opA == OP_N) {
+        const int gr = row0 + e % TM, gk = k0 + e / TM;
+        ra[q] = load_or_zero(A + (int64_t)gr + (int64_t)gk * lda, gk < K && gr < M);
+      } else {
+        const int gk = k0 + e % TK, gr = row0 + e / TK;
+        cplx<T> v = load_or_zero(A + (int64_t)gk + (int64_t)gr * lda, gk < K && gr < M);
+        if (opA == OP_C) v.im = -v.im;
+        ra[q] = v;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 256 * q;
+      if (opB == OP_N) {
+        const int gk = k0 + e % TK, gc = col0 + e / TK;
+        rb[q] = load_or_zero(B + (int64_t)gk + (int64_t)gc * ldb, gk < K && gc < N);
+      } else {
+        const int gc = col0 + e % TN, gk = k0 + e / TN;
+        cplx<T> v = load_or_zero(B + (int64_t)gc + (int64_t)gk * ldb, gk < K && gc < N);
+        if (opB == OP_C) v.im = -v.im;
+        rb[q] = v;
+      }
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
+      if (opA == OP_N)
+        sm.a[e / TM][e % TM] = ra[q];
+      else
+        sm.a[e % TK][e / TK] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 256 * q;
+      if (opB == OP_N)
+        sm.b[e % TK][e / TK] = rb[q];
+      else
+        sm.b[e / TN][e % TN] = rb[q];
+    }
+  };
+  if (K > 0) fetch(0);
+  for (int k0 = 0; k0 < K; k0 += TK) {
+    stage();
+    __syncthreads();
+    if (k0 + TK < K) fetch(k0 + TK);  // in flight during the MFMAs below
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 4) {
+      const int k = kk + (lane >> 4);
+      cplx<T> a[BI], b[BJ];
+#pragma unroll
+      for (int i = 0; i < BI; ++i) a[i] = sm.a[k][wr + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < BJ; ++j) b[j] = sm.b[k][wc + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < BI; ++i)
+#pragma unroll
+        for (int j = 0; j < BJ; ++j) {
+          accr[i][j] = Mfma<T>::step(a[i].re, b[j].re, accr[i][j]);
+          accr[i][j] = Mfma<T>::step(-a[i].im, b[j].im, accr[i][j]);
+          acci[i][j] = Mfma<T>::step(a[i].re, b[j].im, acci[i][j]);
+          acci[i][j] = Mfma<T>::step(a[i].im, b[j].re, acci[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < BI; ++i)
+#pragma unroll
+    for (int j = 0; j < BJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = row0 + wr + i * 16 + Mfma<T>::row(lane, r);
+        const int gc = col0 + wc + j * 16 + (lane & 15);
+        if (gr < M && gc < N) {
+          const T pr = accr[i][j][r], pi = acci[i][j][r];
+          cplx<T> v = {alpha.re * pr - alpha.im * pi, alpha.re * pi + alpha.im * pr};
+          cplx<T>* dst = Cm + (int64_t)gr + (int64_t)gc * ldc;
+          if (beta) v = cadd(*dst, v);
+          *dst = v;
+        }
+      }
+}
+
 // Skinny product for at most 16 right-hand sides: C = beta C + alpha A B with
 // A (M x K, column-major, not transposed) streamed from memory once.  A
 // workgroup computes rows [256 tm, 256 tm + 256) and all N <= 16 columns; wave

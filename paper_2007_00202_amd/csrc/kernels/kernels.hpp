@@ -78,12 +78,25 @@ hipError_t launch_basis_update(const void* y, int ldy, int m, const void* V, int
                                int64_t ldx, int64_t N, int nrhs, hipStream_t s);
 
 // ---- butterfly support (bf.hip)
-// grouped GEMM over ntasks tasks; tile_start[i] = first tile of task i.  With
-// events given, they take the kernel's own start and end timestamps (attached
-// to the dispatch, so the time excludes the gaps between dispatches).
+// Tile shapes of the grouped GEMM (rows x columns of C per 256-thread
+// workgroup).  0..4 stage A and B through LDS; 5 is the skinny shape (no LDS,
+// only for tasks with N <= 16 and no transposes).  All give identical results.
+constexpr int GEMM_CFGS = 6;
+constexpr int GEMM_CFG_SKINNY = 5;
+constexpr int GEMM_CFG_TM[GEMM_CFGS] = {64, 32, 128, 16, 256, 256};
+constexpr int GEMM_CFG_TN[GEMM_CFGS] = {64, 128, 32, 256, 16, 16};
+inline int64_t gemm_cfg_tiles(int cfg, int M, int N) {
+  if (M <= 0 || N <= 0) return 0;
+  return (int64_t)((M + GEMM_CFG_TM[cfg] - 1) / GEMM_CFG_TM[cfg]) * ((N + GEMM_CFG_TN[cfg] - 1) / GEMM_CFG_TN[cfg]);
+}
+
+// grouped GEMM over ntasks tasks in tile shape cfg; tile_start[i] = first tile
+// of task i (tiles counted with gemm_cfg_tiles).  With events given, they take
+// the kernel's own start and end timestamps (attached to the dispatch, so the
+// time excludes the gaps between dispatches).
 template <class T>
 hipError_t launch_grouped_gemm(const GTask* d_tasks, const int64_t* d_tile_start, int ntasks, int64_t ntiles,
-                               void* const bases[4], bool skinny, hipStream_t s, hipEvent_t ev_start = nullptr,
+                               void* const bases[4], int cfg, hipStream_t s, hipEvent_t ev_start = nullptr,
                                hipEvent_t ev_stop = nullptr);
 // truncated column-pivoted QR of every task's q x p block (tol: |R_kk| > tol |R_00|)
 template <class T>
@@ -119,6 +132,18 @@ template <class T>
 hipError_t launch_axpby(void* Y, int64_t ldy, const void* X, int64_t ldx, int64_t m, int ncol, double a, double b,
                         hipStream_t s);
 // y_t = a x_t + b y_t for a batch of blocks (max_entries: the largest m ncol)
+// Y (T1) = a X (T2) + b Y + diag E per task (AxpbyTask; X null: zero; E(i, c) = 1 where
+// i == c + pad), arithmetic in double
+template <class T1, class T2>
+hipError_t launch_mix_batch(const AxpbyTask* d_tasks, int ntasks, int64_t max_entries, double a, double b,
+                            double diag, hipStream_t s);
+// bordered fronts [I I; -I 0] (Y, 2m x 2m) and identities (X, m x m) per task
+template <class T>
+hipError_t launch_smw_border(const AxpbyTask* d_tasks, int ntasks, int64_t max_n, hipStream_t s);
+// Gaussian probe blocks per task (ProbeTask), groups from one pair of row-range arrays
+template <class T>
+hipError_t launch_philox_gauss_batch(const ProbeTask* d_tasks, int ntasks, int64_t max_entries,
+                                     const int32_t* d_gbeg, const int32_t* d_gend, uint64_t seed, hipStream_t s);
 template <class T>
 hipError_t launch_axpby_batch(const AxpbyTask* d_tasks, int ntasks, int64_t max_entries, double a, double b,
                               hipStream_t s);

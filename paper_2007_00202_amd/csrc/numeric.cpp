@@ -219,6 +219,9 @@ void factor_dense(Context& c) {
   if (ncomp) {
     if (!c.comp) c.comp = comp_state_create(c);
     comp_state_reset(c.comp, c, nf);
+    // grouped-GEMM tile tables of this device, measured once per process (before the factor clock starts)
+    gemm_autotune<double>(c.device, c.stream);
+    if (c.fopts.precision == BFMF_C64_MIXED) gemm_autotune<float>(c.device, c.stream);
   }
   // descriptors in level order
   char* arena = c.d_work.as<char>();
@@ -263,6 +266,10 @@ void factor_dense(Context& c) {
   HIPCHK(hipMemsetAsync(c.d_status.p, 0, 16, c.stream));
 
   const double t0 = now();
+  if (c.verbose) {
+    c.hprof.reset();
+    g_hprof = &c.hprof;
+  }
   FrontDesc* dfds = c.d_fds.as<FrontDesc>();
   std::vector<int> hn, hns;
   const int nlev = (int)c.level_ptr.size() - 1;
@@ -334,6 +341,16 @@ void factor_dense(Context& c) {
   }
   HIPCHK(hipStreamSynchronize(c.stream));
   c.stats.factor_seconds = now() - t0;
+  if (c.verbose) {
+    g_hprof = nullptr;
+    const HostProf& h = c.hprof;
+    fprintf(stderr,
+            "[bfmf-host] factor %.3f s: blocked in syncs %.3f s (%lld), staging puts %.3f s (%lld), GEMM launch calls "
+            "%.3f s (%lld), plan building %.3f s (%lld), run_plan total %.3f s (%lld)\n",
+            c.stats.factor_seconds, h.sec[HP_SYNC], (long long)h.n[HP_SYNC], h.sec[HP_PUT], (long long)h.n[HP_PUT],
+            h.sec[HP_LAUNCH], (long long)h.n[HP_LAUNCH], h.sec[HP_PLAN], (long long)h.n[HP_PLAN], h.sec[HP_RUN],
+            (long long)h.n[HP_RUN]);
+  }
   c.timer.collect();
   if (c.verbose && c.timer.enabled) {
     fprintf(stderr, "[bfmf] butterfly GEMM launches (timed sample) by log2 flops: bucket count ms TFLOP/s\n");

@@ -151,8 +151,11 @@ void upload_plan(Context& c) {
   c.d_status.bytes = 16;
 }
 
+thread_local HostProf* g_hprof = nullptr;
+
 void Staging::put(void* dst, const void* src, size_t bytes, hipStream_t s) {
   if (bytes == 0) return;
+  HostTimer ht(HP_PUT);
   const size_t need = (bytes + 255) & ~(size_t)255;
   if (head + need > cap) {
     sync(s);  // every earlier copy out of the ring has completed
@@ -175,6 +178,7 @@ void Staging::put(void* dst, const void* src, size_t bytes, hipStream_t s) {
 }
 
 void Staging::sync(hipStream_t s) {
+  HostTimer ht(HP_SYNC);
   HIPCHK(hipStreamSynchronize(s));
   head = 0;
 }

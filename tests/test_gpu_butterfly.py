@@ -91,3 +91,37 @@ def test_rectangular_and_many_rhs(gpu_lib):
         assert np.linalg.norm(Y - D @ X) <= 1e-12 * np.linalg.norm(Y)
     finally:
         gpu_lib.bfmf_bf_destroy(b)
+
+
+def test_every_gemm_tile_shape_gives_the_same_result(gpu_lib):
+    """The grouped GEMM behind every butterfly product runs in one of six tile
+    shapes (autotuned per launch); each adds the products of an entry in the
+    same order, so forcing any shape reproduces the autotuned result bit for
+    bit: for applies of K and K^H with 1, 16 and 130 right-hand sides, and for
+    a construction by randomized products."""
+    K = green_planes(16, 3.0, 0.25)
+    rng = np.random.default_rng(7)
+    X = {nr: rng.standard_normal((K.shape[1], nr)) + 1j * rng.standard_normal((K.shape[1], nr))
+         for nr in (1, 16, 130)}
+    ref, ref_d = None, None
+    try:
+        for cfg in [-1, 0, 1, 2, 3, 4, 5]:
+            gpu_lib.bfmf_set_gemm_tile(cfg)
+            b, shape = gpu_lib.bfmf_bf_compress_dense(K, 3, 1e-6, method=1, seed=5)
+            try:
+                got = {nr: (gpu_lib.bfmf_bf_apply(b, shape, x), gpu_lib.bfmf_bf_apply(b, shape, x, adjoint=True))
+                       for nr, x in X.items()}
+                D = decompress(gpu_lib, b, shape)
+            finally:
+                gpu_lib.bfmf_bf_destroy(b)
+            if ref is None:
+                ref, ref_d = got, D
+                assert np.linalg.norm(D - K) <= 1e-4 * np.linalg.norm(K)
+                continue
+            assert np.array_equal(D, ref_d), cfg
+            for nr in X:
+                assert np.array_equal(got[nr][0], ref[nr][0]) and np.array_equal(got[nr][1], ref[nr][1]), (cfg, nr)
+    finally:
+        gpu_lib.bfmf_set_gemm_tile(-1)
+    with pytest.raises(gpu_lib.BfmfError):
+        gpu_lib.bfmf_set_gemm_tile(6)

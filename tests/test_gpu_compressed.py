@@ -108,3 +108,28 @@ def test_nested_compressed_mixed_precision(gpu_lib):
     err = np.linalg.norm(X - x_or) / np.linalg.norm(x_or)
     assert info["status"] == 0 and err <= 1e-4, (err, info)
     s.close()
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_autotuned_tiles_match_a_fixed_tile(gpu_lib, precision):
+    """Factor and preconditioner with autotuned grouped-GEMM tile shapes equal those
+    with the 64 x 64 shape forced for every launch, bit for bit."""
+    dims = (16, 16, 16)
+    rp, ci, v, _ = helmholtz_7pt(dims, 0.05)
+    b = rng_for("test", "rhs", (16,)).standard_normal((rp.shape[0] - 1, 3)) + 0j
+    prec = gpu_lib.BFMF_C128 if precision == "c128" else gpu_lib.BFMF_C64_MIXED
+    out, used = [], []
+    try:
+        for cfg in (-1, 0):
+            gpu_lib.bfmf_set_gemm_tile(cfg)
+            s = gpu_lib.Solver(0).analyze(rp, ci, v, dims=dims, leaf_max=64, sep_leaf=32)
+            gpu_lib.bfmf_reset_kernel_stats(s.h)
+            s.factor(tol=1e-3, n_min=60, batched=True, precision=prec)
+            out.append(s.precondition(b))
+            used.append(s.gemm_tile_launches())
+            s.close()
+    finally:
+        gpu_lib.bfmf_set_gemm_tile(-1)
+    assert np.array_equal(out[0], out[1])
+    assert sum(used[1].values()) == used[1]["64x64"] > 0
+    assert sum(used[0].values()) == sum(used[1].values())
