@@ -101,7 +101,9 @@ typedef struct {
     double true_rtol;    /* e.g. 1e-3; 0 disables */
     /* outputs */
     int32_t iters_max;   /* largest iteration count over the columns */
-    int32_t reserved0;
+    int32_t graphs;      /* input: 1 (default) replays the preconditioner of the GMRES
+                            iterations from a HIP graph captured once per call (same
+                            results as 0, which launches every sweep from the host) */
     double relres_max;   /* largest true relative residual over the columns */
     double seconds;      /* wall time of the call */
 } bfmf_solve_opts;
@@ -207,7 +209,10 @@ bfmf_status bfmf_get_front(bfmf_handle h, int32_t front, int32_t what, void* out
  * 3 forward sweep level, 4 backward sweep level, 5 SpMV, 6 GMRES vector ops,
  * 7 butterfly grouped GEMMs (products of butterflies and the GEMMs of their
  * constructions), 8 interpolative decompositions, 9 entry extraction,
- * 10 copy of the dense fronts' factors out of the level workspace.
+ * 10 copy of the dense fronts' factors out of the level workspace,
+ * 11 replays of the captured preconditioner (forward and backward sweeps of
+ * the GMRES iterations when bfmf_solve_opts.graphs is set; the sweeps of
+ * eager applications count in classes 3, 4 and 7-9).
  * Class 7 times about one launch in eight, chosen quasi-randomly (the
  * fractional parts of i times the golden ratio below 1/8, i = launch index),
  * with the kernel's own start and end timestamps (events attached to the
@@ -225,7 +230,7 @@ typedef struct {
     double bytes;
     int64_t launches_all;
 } bfmf_kernel_stat;
-enum { BFMF_KERNEL_CLASSES = 11 };
+enum { BFMF_KERNEL_CLASSES = 12 };
 bfmf_status bfmf_get_kernel_stats(bfmf_handle h, int32_t kind, bfmf_kernel_stat* out);
 bfmf_status bfmf_reset_kernel_stats(bfmf_handle h);
 

@@ -48,13 +48,13 @@ class bfmf_kernel_stat(C.Structure):
                 ("flops", C.c_double), ("bytes", C.c_double), ("launches_all", C.c_int64)]
 
 
-BFMF_KERNEL_CLASSES = 11
+BFMF_KERNEL_CLASSES = 12
 
 
 class bfmf_solve_opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("rtol", C.c_double),
                 ("atol", C.c_double), ("true_rtol", C.c_double), ("iters_max", C.c_int32),
-                ("reserved0", C.c_int32), ("relres_max", C.c_double), ("seconds", C.c_double)]
+                ("graphs", C.c_int32), ("relres_max", C.c_double), ("seconds", C.c_double)]
 
 
 class bfmf_symbolic_view(C.Structure):
@@ -366,9 +366,10 @@ class Solver:
         bfmf_factor(self.h, o)
         return self
 
-    def solve(self, B, restart=30, max_iter=300, rtol=1e-6, atol=1e-10, true_rtol=0.0):
+    def solve(self, B, restart=30, max_iter=300, rtol=1e-6, atol=1e-10, true_rtol=0.0, graphs=True):
         o = bfmf_default_solve_opts()
         o.restart, o.max_iter, o.rtol, o.atol, o.true_rtol = restart, max_iter, rtol, atol, true_rtol
+        o.graphs = int(bool(graphs))
         X, o, st = bfmf_solve(self.h, B, o)
         return X, {"iters": o.iters_max, "relres": o.relres_max, "seconds": o.seconds, "status": st}
 

@@ -106,6 +106,7 @@ void bfmf_default_solve_opts(bfmf_solve_opts* o) {
   o->rtol = 1e-6;
   o->atol = 1e-10;
   o->true_rtol = 0;
+  o->graphs = 1;
 }
 
 bfmf_status bfmf_analyze(bfmf_handle h, int64_t n, const int64_t* rowptr, const int32_t* colind,
@@ -320,7 +321,7 @@ bfmf_status bfmf_get_front(bfmf_handle h, int32_t front, int32_t what, void* out
 bfmf_status bfmf_get_kernel_stats(bfmf_handle h, int32_t kind, bfmf_kernel_stat* out) {
   static const char* names[K_COUNT] = {"assemble",      "panel_lu",       "schur_gemm",     "forward_sweep",
                                        "backward_sweep", "spmv",           "gmres_vector",   "butterfly_gemm",
-                                       "interp_decomp",  "entry_extract",  "factor_store"};
+                                       "interp_decomp",  "entry_extract",  "factor_store",   "preconditioner_graph"};
   if (!h || !out || kind < 0 || kind >= K_COUNT) return BFMF_E_INVAL;
   std::memset(out, 0, sizeof(*out));
   std::strncpy(out->name, names[kind], sizeof(out->name) - 1);
@@ -369,10 +370,9 @@ const char* bfmf_last_error(bfmf_handle h) { return h ? h->last_error.c_str() : 
 void bfmf_destroy(bfmf_handle h) {
   if (!h) return;
   if (h->device >= 0) (void)hipSetDevice(h->device);
-  if (h->own_stream && h->stream) {
-    (void)hipStreamSynchronize(h->stream);
-    (void)hipStreamDestroy(h->stream);
-  }
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  h->pgraph.release();
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
 }
 

@@ -658,8 +658,13 @@ struct IdLevel {
     const auto t_id0 = std::chrono::steady_clock::now();
     KernelTimer& tm = rt.c->timer;
     const int tk = tm.want(K_ID) ? tm.begin(s) : -1;
+    int lds_entries = 0;  // the largest R (kmax x p) that fits the LDS budget sizes the launch's LDS
+    for (const IdTask& t : tasks) {
+      const int64_t e = (int64_t)std::min(t.maxrank, t.p) * t.p;
+      if (e <= GRAM_LDS_MAX) lds_entries = std::max<int>(lds_entries, (int)e);
+    }
     if (gram)
-      chk(launch_gram_id<double>(dt, (int)nb, rt.tol, s), "gram id");
+      chk(launch_gram_id<double>(dt, (int)nb, rt.tol, lds_entries, s), "gram id");
     else
       chk(launch_cpqr_id<double>(dt, (int)nb, rt.tol, s), "cpqr");
     if (tk >= 0) {

@@ -82,6 +82,11 @@ struct HostTimer {
 struct Staging {
   char* host = nullptr;
   size_t cap = 0, head = 0;
+  // while a graph is captured, puts go to this arena instead (never reused: the graph's copies read it
+  // on every replay); put_bytes counts the ring's bytes since the last reset (sizes such an arena)
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_head = 0;
+  size_t put_bytes = 0;
   void put(void* dst, const void* src, size_t bytes, hipStream_t s);
   void sync(hipStream_t s);
   Staging() = default;
@@ -104,7 +109,8 @@ enum KernelKind {
   K_ID = 8,       // interpolative decompositions
   K_EXTRACT = 9,  // entry extraction from never-formed fronts and sketches
   K_STORE = 10,   // copy of the dense factors out of the level workspace
-  K_COUNT = 11
+  K_PGRAPH = 11,  // one replay of the captured preconditioner (forward and backward sweeps)
+  K_COUNT = 12
 };
 
 // HIP-event timing of kernel classes on the handle's stream.
@@ -121,7 +127,7 @@ struct KernelTimer {
   std::vector<Rec> recs;
   int64_t launches[K_COUNT] = {};  // timed launches
   int64_t issued[K_COUNT] = {};    // all launches while enabled
-  int sample_every[K_COUNT] = {1, 1, 1, 1, 1, 1, 1, 8, 1, 1, 1};  // time one launch in this many
+  int sample_every[K_COUNT] = {1, 1, 1, 1, 1, 1, 1, 8, 1, 1, 1, 1};  // time one launch in this many
   double seconds[K_COUNT] = {}, flops[K_COUNT] = {}, bytes[K_COUNT] = {};
   // timed butterfly GEMM launches by floor(log2(flops)): count, seconds, flops
   double hist_n[64] = {}, hist_s[64] = {}, hist_f[64] = {};
@@ -169,6 +175,23 @@ struct FrontPlan {
   bool compressed = false;
 };
 
+// The preconditioner application in -> out (nrhs columns) captured as a HIP
+// graph, replayed by the GMRES iterations; valid for one factorization and
+// one set of solve workspaces.
+struct PrecGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  char* host = nullptr;  // pinned task lists that the graph's copies read
+  size_t host_cap = 0;
+  const void* in = nullptr;
+  void* out = nullptr;
+  int64_t nrhs = 0;
+  uint64_t gen = 0, ws_gen = 0;
+  uint64_t failed_gen = ~0ull;  // factorization for which capture failed (eager from then on)
+  void release();
+  ~PrecGraph() { release(); }
+};
+
 struct Context {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -213,6 +236,10 @@ struct Context {
   // device: solve workspaces
   DevBuf d_W, d_y, d_x;
   int64_t ws_nrhs = 0;
+  int64_t fds_nrhs = -1;       // nrhs the device descriptors' workspace pointers are set for
+  uint64_t factor_gen = 0;     // bumped by every factorization
+  uint64_t ws_gen = 0;         // bumped when the solve workspaces move
+  PrecGraph pgraph;
   DevBuf g_B, g_X, g_V, g_w, g_r, g_scal, g_part, g_tmp;
   DevBuf g_tmp_plan;  // device copy of the current grouped-GEMM task lists
   Staging stage;      // pinned ring of host-to-device uploads

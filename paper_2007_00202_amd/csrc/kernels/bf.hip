@@ -262,7 +262,7 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const IdTask* __restrict__
 // before it), chooses at each step the largest remaining squared column norm
 // d_j (first index on ties) and stops at the first d <= tol^2 d_0, which in
 // exact arithmetic are the pivots and the rank of the column-pivoted QR.
-// T = R11^-1 R12 by back substitution, one thread per remaining column.
+// T = R11^-1 R12 by back substitution over the whole workgroup.
 // Rounding in G limits the accuracy of T to about eps p / tol^2 (relative),
 // so the host uses this variant only for tolerances where that is small.
 template <class T>
@@ -291,20 +291,18 @@ __device__ __forceinline__ void block_argmax(double v, int i, double* red_v, int
     }
 }
 
+// R (rows 0 .. kmax-1 of the factor, row i at R + i p) lives in LDS when it fits
+// the launch's dynamic LDS, else in the task's workspace; the body is the same.
 template <class T>
-__global__ __launch_bounds__(256) void gram_id_kernel(const IdTask* __restrict__ tasks, double tol) {
-  const IdTask& tk = tasks[blockIdx.x];
+__device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<T>* __restrict__ R) {
   const int p = tk.p;
-  if (p > ID_MAXP || p < 0 || tk.q < 0) {  // the host never sends these; refuse, never overflow LDS
-    if (threadIdx.x == 0) *tk.rank = -1;
-    return;
-  }
   const cplx<T>* G = (const cplx<T>*)tk.G;
-  cplx<T>* R = (cplx<T>*)tk.R;
   __shared__ double d[ID_MAXP];
   __shared__ int sel[ID_MAXP];   // step at which a column was chosen, or -1
   __shared__ int piv[ID_MAXP];
-  __shared__ cplx<T> rc[ID_MAXP];  // R(0:k, pivot)
+  __shared__ int pl[ID_MAXP];    // the permutation
+  __shared__ cplx<T> rc[ID_MAXP];  // R(0:k, pivot) of the step
+  __shared__ cplx<T> tl[ID_MAXP];  // row i of T in the back substitution
   __shared__ double red_v[2][4];
   __shared__ int red_i[2][4];
   const int tid = threadIdx.x;
@@ -365,24 +363,55 @@ __global__ __launch_bounds__(256) void gram_id_kernel(const IdTask* __restrict__
     int c = rank;
     for (int j = 0; j < p; ++j) {
       if (sel[j] >= 0)
-        tk.perm[sel[j]] = j;
+        pl[sel[j]] = j;
       else
-        tk.perm[c++] = j;
+        pl[c++] = j;
     }
   }
   __syncthreads();
-  // T(:, c) = R11^-1 R(0:rank, perm[rank + c]), R11(i, m) = R(i, piv[m]) for m >= i
+  for (int j = tid; j < p; j += 256) tk.perm[j] = pl[j];
+  // T = R11^-1 R12 with R11(i, m) = R(i, piv[m]) (upper triangular) and R12(:, c) = R(:, pl[rank + c]):
+  // back substitution by columns of R11, every (row, column) update of a step in parallel
   cplx<T>* Tout = (cplx<T>*)tk.T;
   const int ldt = tk.maxrank;
-  for (int c = tid; c < p - rank; c += 256) {
-    const int j = tk.perm[rank + c];
-    cplx<T>* tcol = Tout + (int64_t)c * ldt;
-    for (int i = rank - 1; i >= 0; --i) {
-      cplx<T> s = R[(int64_t)i * p + j];
-      for (int m = i + 1; m < rank; ++m) s = csub(s, cmul(R[(int64_t)i * p + piv[m]], tcol[m]));
-      tcol[i] = cdiv(s, R[(int64_t)i * p + piv[i]]);
-    }
+  const int nc = p - rank;
+  for (int e = tid; e < rank * nc; e += 256) {
+    const int i = e % rank, c = e / rank;
+    Tout[i + (int64_t)c * ldt] = R[(int64_t)i * p + pl[rank + c]];
   }
+  __syncthreads();
+  for (int i = rank - 1; i >= 0; --i) {
+    const cplx<T> rii = R[(int64_t)i * p + piv[i]];
+    for (int c = tid; c < nc; c += 256) {
+      cplx<T>* tp = Tout + i + (int64_t)c * ldt;
+      const cplx<T> t = cdiv(*tp, rii);
+      *tp = t;
+      tl[c] = t;
+    }
+    for (int m = tid; m < i; m += 256) rc[m] = R[(int64_t)m * p + piv[i]];
+    __syncthreads();
+    for (int e = tid; e < i * nc; e += 256) {
+      const int m = e % i, c = e / i;
+      cplx<T>* tp = Tout + m + (int64_t)c * ldt;
+      *tp = csub(*tp, cmul(rc[m], tl[c]));
+    }
+    __syncthreads();
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void gram_id_kernel(const IdTask* __restrict__ tasks, double tol, int lds_entries) {
+  extern __shared__ __align__(16) unsigned char gram_smem[];
+  const IdTask& tk = tasks[blockIdx.x];
+  const int p = tk.p;
+  if (p > ID_MAXP || p < 0 || tk.q < 0) {  // the host never sends these; refuse, never overflow LDS
+    if (threadIdx.x == 0) *tk.rank = -1;
+    return;
+  }
+  if ((int64_t)min(tk.maxrank, p) * p <= lds_entries)
+    gram_id_body<T>(tk, tol, (cplx<T>*)gram_smem);
+  else
+    gram_id_body<T>(tk, tol, (cplx<T>*)tk.R);
 }
 
 // U (p x rank, ld p): U[perm[i], i] = 1 (i < rank), U[perm[rank + j], :] = T[:, j]^T,
@@ -858,9 +887,11 @@ hipError_t launch_cpqr_id(const IdTask* d_tasks, int ntasks, double tol, hipStre
 }
 
 template <class T>
-hipError_t launch_gram_id(const IdTask* d_tasks, int ntasks, double tol, hipStream_t s) {
+hipError_t launch_gram_id(const IdTask* d_tasks, int ntasks, double tol, int lds_entries, hipStream_t s) {
   if (ntasks == 0) return hipSuccess;
-  hipLaunchKernelGGL((gram_id_kernel<T>), dim3(ntasks), dim3(256), 0, s, d_tasks, tol);
+  if (lds_entries < 0 || lds_entries > GRAM_LDS_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((gram_id_kernel<T>), dim3(ntasks), dim3(256), (size_t)lds_entries * sizeof(cplx<T>), s, d_tasks,
+                     tol, lds_entries);
   return hipGetLastError();
 }
 
@@ -995,7 +1026,7 @@ hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int6
   template hipError_t launch_grouped_gemm<T>(const GTask*, const int64_t*, int, int64_t, void* const[4], int,         \
                                              hipStream_t, hipEvent_t, hipEvent_t);                                    \
   template hipError_t launch_cpqr_id<T>(const IdTask*, int, double, hipStream_t);                                     \
-  template hipError_t launch_gram_id<T>(const IdTask*, int, double, hipStream_t);                                     \
+  template hipError_t launch_gram_id<T>(const IdTask*, int, double, int, hipStream_t);                                \
   template hipError_t launch_id_expand<T>(const IdTask*, int, void* const*, const int64_t*, bool, bool, hipStream_t);  \
   template hipError_t launch_front_extract<T>(const ExtractTask*, int, int, const void*, bool, hipStream_t);          \
   template hipError_t launch_philox_gauss<T>(void*, int64_t, int64_t, int, int, const int32_t*, const int32_t*,       \

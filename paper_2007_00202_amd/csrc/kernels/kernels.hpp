@@ -101,9 +101,12 @@ hipError_t launch_grouped_gemm(const GTask* d_tasks, const int64_t* d_tile_start
 // truncated column-pivoted QR of every task's q x p block (tol: |R_kk| > tol |R_00|)
 template <class T>
 hipError_t launch_cpqr_id(const IdTask* d_tasks, int ntasks, double tol, hipStream_t s);
-// the same decompositions from G = A^H A (IdTask.G) by pivoted Cholesky (IdTask.R workspace)
+// the same decompositions from G = A^H A (IdTask.G) by pivoted Cholesky: the rows of R in
+// lds_entries complex entries of dynamic LDS per workgroup where min(maxrank, p) * p fits, else
+// in IdTask.R
+constexpr int GRAM_LDS_MAX = 4096;
 template <class T>
-hipError_t launch_gram_id(const IdTask* d_tasks, int ntasks, double tol, hipStream_t s);
+hipError_t launch_gram_id(const IdTask* d_tasks, int ntasks, double tol, int lds_entries, hipStream_t s);
 // interpolation matrices from the QR results into outs[i] (ld ldo[i]);
 // transpose_out writes the rank x p transpose (column ID), conj_out conjugates
 template <class T>

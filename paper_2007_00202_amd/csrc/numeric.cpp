@@ -263,6 +263,8 @@ void factor_dense(Context& c) {
   }
   if (c.d_fds.bytes < nf * sizeof(FrontDesc)) alloc(c.d_fds, nf * sizeof(FrontDesc));
   HIPCHK(hipMemcpy(c.d_fds.p, c.h_fds.data(), nf * sizeof(FrontDesc), hipMemcpyHostToDevice));
+  c.fds_nrhs = -1;  // solve workspaces not set in these descriptors
+  ++c.factor_gen;   // a captured preconditioner of the previous factorization is stale
   HIPCHK(hipMemsetAsync(c.d_status.p, 0, 16, c.stream));
 
   const double t0 = now();
@@ -412,7 +414,10 @@ void ensure_workspace(Context& c, int64_t nrhs) {
     alloc(c.d_y, (size_t)c.n * nrhs * elem);
     alloc(c.d_x, (size_t)c.n * nrhs * elem);
     c.ws_nrhs = nrhs;
+    ++c.ws_gen;
+    c.fds_nrhs = -1;
   }
+  if (c.fds_nrhs == nrhs) return;  // the device descriptors already point into these workspaces
   // W pointers depend on nrhs: W_f at sum_{g<f} n_g * nrhs
   char* W = c.d_W.as<char>();
   const int32_t nf = c.sym.nfronts();
@@ -428,6 +433,8 @@ void ensure_workspace(Context& c, int64_t nrhs) {
     }
   }
   HIPCHK(hipMemcpyAsync(c.d_fds.p, c.h_fds.data(), nf * sizeof(FrontDesc), hipMemcpyHostToDevice, c.stream));
+  HIPCHK(hipStreamSynchronize(c.stream));  // the host copy of the descriptors is rewritten on the next change
+  c.fds_nrhs = nrhs;
 }
 
 void apply_preconditioner_dev(Context& c, const void* dB, int64_t ldb, void* dX, int64_t ldx, int64_t nrhs) {
@@ -508,6 +515,67 @@ void apply_preconditioner_dev(Context& c, const void* dB, int64_t ldb, void* dX,
   check(launch_permute_out<double>(c.d_x.p, dX, ldx, c.d_perm.as<int64_t>(), c.n, (int)nrhs, c.stream), "permute");
 }
 
+// The preconditioner application in -> out replayed from a HIP graph.  The
+// graph is captured from one application (after an eager one with the same
+// sizes, so that no workspace grows while capturing), with the staged task
+// lists copied from a pinned arena that the graph owns; it is rebuilt for
+// other buffers, another column count, a new factorization or moved
+// workspaces.  Returns false (and the caller applies eagerly) when capture is
+// not possible; after a failed capture the factorization stays eager.
+static bool apply_preconditioner_graph(Context& c, const void* in, void* out, int64_t nrhs, size_t stage_bytes) {
+  PrecGraph& g = c.pgraph;
+  if (!c.stream || g.failed_gen == c.factor_gen) return false;
+  ensure_workspace(c, nrhs);
+  const bool valid = g.exec && g.in == in && g.out == out && g.nrhs == nrhs && g.gen == c.factor_gen &&
+                     g.ws_gen == c.ws_gen;
+  if (!valid) {
+    HIPCHK(hipStreamSynchronize(c.stream));  // no replay of the old graph in flight
+    g.release();
+    g.host_cap = stage_bytes + ((size_t)1 << 20);
+    if (hipHostMalloc((void**)&g.host, g.host_cap, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      g.host = nullptr;
+      g.failed_gen = c.factor_gen;
+      return false;
+    }
+    c.stage.arena = g.host;
+    c.stage.arena_cap = g.host_cap;
+    c.stage.arena_head = 0;
+    const bool timing = c.timer.enabled;
+    c.timer.enabled = false;
+    bool ok = hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+    if (ok) {
+      try {
+        apply_preconditioner_dev(c, in, c.n, out, c.n, nrhs);
+      } catch (const std::exception&) {
+        ok = false;
+      }
+      hipGraph_t graph = nullptr;
+      const hipError_t ee = hipStreamEndCapture(c.stream, &graph);
+      ok = ok && ee == hipSuccess && graph;
+      if (ok && hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) != hipSuccess) ok = false;
+      if (graph) g.graph = graph;
+    }
+    c.stage.arena = nullptr;
+    c.timer.enabled = timing;
+    if (!ok) {
+      (void)hipGetLastError();
+      g.release();
+      g.failed_gen = c.factor_gen;
+      return false;
+    }
+    g.in = in;
+    g.out = out;
+    g.nrhs = nrhs;
+    g.gen = c.factor_gen;
+    g.ws_gen = c.ws_gen;
+  }
+  const int tk = c.timer.begin(c.stream);
+  HIPCHK(hipGraphLaunch(g.exec, c.stream));
+  c.timer.end(tk, c.stream, K_PGRAPH, 0, 0);
+  return true;
+}
+
 // ------------------------------------------------------------------ GMRES
 void gmres_workspace(Context& c, int64_t nrhs, int m) {
   const size_t elem = 2 * sizeof(double);
@@ -530,6 +598,8 @@ int gmres_dev(Context& c, const void* dB, int64_t ldb, void* dX, int64_t ldx, in
   const int m = std::max(1, o.restart);
   const size_t elem = sizeof(cd);
   gmres_workspace(c, nrhs, m);
+  const bool use_graph = o.graphs != 0;  // replay the preconditioner of the iterations from a HIP graph
+  size_t stage_bytes = 0;
   const int nblk = (int)std::min<int64_t>(256, (N + 255) / 256);
   cd* V = c.g_V.as<cd>();
   cd* w = c.g_w.as<cd>();
@@ -580,9 +650,11 @@ int gmres_dev(Context& c, const void* dB, int64_t ldb, void* dX, int64_t ldx, in
     bool any = false;
     for (int q = 0; q < nr; ++q) any |= !done[q];
     if (!any) break;
-    // r = b - A x ; V0 = M^-1 r
+    // r = b - A x ; V0 = M^-1 r (eager: it also sizes the staged task lists of one application)
     spmv(dX, ldx, r, N, dB, ldb);
+    const size_t put0 = c.stage.put_bytes;
     apply_preconditioner_dev(c, r, N, Vi(0), N, nr);
+    stage_bytes = std::max(stage_bytes, c.stage.put_bytes - put0);
     check(launch_dots(nullptr, 0, Vi(0), N, N, nr, c.g_part.p, nblk, hcol, true, c.stream), "norm");
     HIPCHK(hipMemcpyAsync(hh.data(), hcol, nr * elem, hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
@@ -606,7 +678,8 @@ int gmres_dev(Context& c, const void* dB, int64_t ldb, void* dX, int64_t ldx, in
     if (!cycle_active) break;
     for (int j = 0; j < m && total < o.max_iter; ++j) {
       spmv(Vi(j), N, tmp, N, nullptr, 0);
-      apply_preconditioner_dev(c, tmp, N, w, N, nr);
+      if (!(use_graph && apply_preconditioner_graph(c, tmp, w, nr, stage_bytes)))
+        apply_preconditioner_dev(c, tmp, N, w, N, nr);
       for (int i = 0; i <= j; ++i) {  // modified Gram-Schmidt
         check(launch_dots(Vi(i), N, w, N, N, nr, c.g_part.p, nblk, hcol + (size_t)i * nr, false, c.stream), "dot");
         check(launch_axpy_cols(hcol + (size_t)i * nr, -1.0, Vi(i), N, w, N, N, nr, c.stream), "axpy");

@@ -157,6 +157,15 @@ void Staging::put(void* dst, const void* src, size_t bytes, hipStream_t s) {
   if (bytes == 0) return;
   HostTimer ht(HP_PUT);
   const size_t need = (bytes + 255) & ~(size_t)255;
+  if (arena) {  // graph capture: a region of its own for every copy
+    if (arena_head + need > arena_cap) throw Error(BFMF_E_NOMEM, "graph capture: task-list arena full");
+    char* h = arena + arena_head;
+    std::memcpy(h, src, bytes);
+    arena_head += need;
+    HIPCHK(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, s));
+    return;
+  }
+  put_bytes += need;
   if (head + need > cap) {
     sync(s);  // every earlier copy out of the ring has completed
     if (need > cap) {
@@ -187,7 +196,21 @@ Staging::~Staging() {
   if (host) (void)hipHostFree(host);
 }
 
+void PrecGraph::release() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (host) (void)hipHostFree(host);
+  exec = nullptr;
+  graph = nullptr;
+  host = nullptr;
+  host_cap = 0;
+  in = nullptr;
+  out = nullptr;
+  nrhs = 0;
+}
+
 Context::~Context() {
+  pgraph.release();  // the stream has been synchronised by the handle's destruction
   if (comp) comp_state_destroy(comp);
   comp = nullptr;
 }

@@ -133,3 +133,29 @@ def test_autotuned_tiles_match_a_fixed_tile(gpu_lib, precision):
     assert np.array_equal(out[0], out[1])
     assert sum(used[1].values()) == used[1]["64x64"] > 0
     assert sum(used[0].values()) == sum(used[1].values())
+
+
+@pytest.mark.parametrize("precision,n_min", [("c128", 60), ("c64", 60), ("c64", 120)])
+def test_graph_replayed_sweeps_equal_eager_sweeps(gpu_lib, precision, n_min):
+    """GMRES with the preconditioner of its iterations replayed from a captured HIP
+    graph gives the same iterates, bit for bit, as launching every sweep from the
+    host: restarts every 3 iterations put eager applications, host synchronisations
+    and the Krylov updates between the replays, and every replay feeds the result."""
+    dims = (16, 16, 16)
+    rp, ci, v, _ = helmholtz_7pt(dims, 0.05)
+    b = rng_for("test", "rhs", (16,)).standard_normal((rp.shape[0] - 1, 4)) + 0j
+    prec = gpu_lib.BFMF_C128 if precision == "c128" else gpu_lib.BFMF_C64_MIXED
+    s = gpu_lib.Solver(0).analyze(rp, ci, v, dims=dims, leaf_max=64, sep_leaf=32)
+    s.factor(tol=1e-2, n_min=n_min, batched=True, precision=prec, timing=True)
+    out = {}
+    for graphs in (False, True, True):
+        gpu_lib.bfmf_reset_kernel_stats(s.h)
+        X, info = s.solve(b, restart=3, rtol=1e-11, true_rtol=1e-8, max_iter=100, graphs=graphs)
+        replays = s.kernel_stats()["preconditioner_graph"]["launches"]
+        assert info["status"] == 0 and info["iters"] > 3, info
+        assert (replays > 0) == graphs, replays
+        if graphs in out:
+            assert np.array_equal(X, out[graphs][0])  # a second call reuses or rebuilds the graph
+        out[graphs] = (X, info["iters"])
+    assert np.array_equal(out[True][0], out[False][0]) and out[True][1] == out[False][1]
+    s.close()
