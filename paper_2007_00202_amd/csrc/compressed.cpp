@@ -1337,6 +1337,131 @@ static void backward_front(CompState<T>& st, int f, void* W, int n, int nrhs) {
   rt.scratch.release(mk);
 }
 
+// The same sweeps for all compressed fronts of a level at once (batched form):
+// the F11^-1 products of every front in one HOD-BF inverse application, the
+// F21 / F12 products in one butterfly plan, conversions and updates in single
+// launches.  Same arithmetic as the per-front sweeps, so the same result.
+template <class T>
+static void forward_level(CompState<T>& st, const std::vector<int>& fs, const std::vector<void*>& Ws,
+                          const std::vector<int>& ns_, int nrhs) {
+  BfRuntime<T>& rt = st.rt;
+  hipStream_t s = rt.s();
+  auto mk = rt.scratch.mark();
+  const int64_t esz = (int64_t)sizeof(cplx<T>);
+  std::vector<HodbfInvItem<T>> inv;
+  std::vector<AxpbyTask> to_low, back, upd;
+  std::vector<BfCall> calls;
+  int64_t maxe = 0;
+  for (size_t k = 0; k < fs.size(); ++k) {
+    CompressedFront<T>& cf = *st.fronts[fs[k]];
+    cplx<double>* w = (cplx<double>*)Ws[k];
+    const int n = ns_[k];
+    maxe = std::max<int64_t>(maxe, (int64_t)std::max(cf.ns, cf.nu) * nrhs);
+    cplx<T>* z = (cplx<T>*)rt.scratch.take((size_t)std::max(cf.ns, 1) * nrhs * sizeof(cplx<T>));
+    const void* x = w;
+    int64_t ldx = n;
+    if (sizeof(T) != 8) {
+      cplx<T>* wl = (cplx<T>*)rt.scratch.take((size_t)std::max(cf.ns, 1) * nrhs * sizeof(cplx<T>));
+      to_low.push_back(AxpbyTask{wl, w, cf.ns, n, cf.ns, nrhs, 0});
+      x = wl;
+      ldx = cf.ns;
+    }
+    inv.push_back(HodbfInvItem<T>{&cf.f11, 0, x, ldx, z, cf.ns, nrhs});
+    back.push_back(AxpbyTask{w, z, n, cf.ns, cf.ns, nrhs, 0});  // W(0:ns) = F11^-1 W(0:ns)
+    if (cf.nu > 0) {
+      BfCall cl;
+      cl.bf = cf.f21.get();
+      cl.x_off = cl.y_off = 0;
+      cl.alpha_im = 0;
+      cl.nrhs = nrhs;
+      if (sizeof(T) == 8) {  // W(ns:n) -= F21 W(0:ns) in place
+        cl.alpha_re = -1.0;
+        cl.beta = 1;
+        cl.x_abs = (int64_t)((uintptr_t)w / esz);
+        cl.ldx = n;
+        cl.y_abs = (int64_t)((uintptr_t)(w + cf.ns) / esz);
+        cl.ldy = n;
+      } else {  // t = F21 z, then W(ns:n) -= t in FP64
+        cplx<T>* t = (cplx<T>*)rt.scratch.take((size_t)std::max(cf.nu, 1) * nrhs * sizeof(cplx<T>));
+        cl.alpha_re = 1.0;
+        cl.beta = 0;
+        cl.x_abs = (int64_t)((uintptr_t)z / esz);
+        cl.ldx = cf.ns;
+        cl.y_abs = (int64_t)((uintptr_t)t / esz);
+        cl.ldy = cf.nu;
+        upd.push_back(AxpbyTask{w + cf.ns, t, n, cf.nu, cf.nu, nrhs, 0});
+      }
+      calls.push_back(cl);
+    }
+  }
+  if (!to_low.empty())
+    ochk(launch_mix_batch<T, double>((const AxpbyTask*)up(rt, to_low), (int)to_low.size(), maxe, 1.0, 0.0, 0.0, s),
+         "to c64");
+  hodbf_inv_apply_many<T>(rt, inv, false);
+  ochk(launch_mix_batch<double, T>((const AxpbyTask*)up(rt, back), (int)back.size(), maxe, 1.0, 0.0, 0.0, s),
+       "copy back");
+  if (!calls.empty()) rt.apply_calls(calls, false);
+  if (!upd.empty())
+    ochk(launch_mix_batch<double, T>((const AxpbyTask*)up(rt, upd), (int)upd.size(), maxe, -1.0, 1.0, 0.0, s),
+         "update");
+  rt.scratch.release(mk);
+}
+
+template <class T>
+static void backward_level(CompState<T>& st, const std::vector<int>& fs, const std::vector<void*>& Ws,
+                           const std::vector<int>& ns_, int nrhs) {
+  BfRuntime<T>& rt = st.rt;
+  hipStream_t s = rt.s();
+  auto mk = rt.scratch.mark();
+  const int64_t esz = (int64_t)sizeof(cplx<T>);
+  std::vector<HodbfInvItem<T>> inv;
+  std::vector<AxpbyTask> to_low, upd;
+  std::vector<BfCall> calls;
+  int64_t maxe = 0;
+  for (size_t k = 0; k < fs.size(); ++k) {
+    CompressedFront<T>& cf = *st.fronts[fs[k]];
+    if (cf.nu == 0) continue;
+    cplx<double>* w = (cplx<double>*)Ws[k];
+    const int n = ns_[k];
+    maxe = std::max<int64_t>(maxe, (int64_t)std::max(cf.ns, cf.nu) * nrhs);
+    cplx<T>* t = (cplx<T>*)rt.scratch.take((size_t)std::max(cf.ns, 1) * nrhs * sizeof(cplx<T>));
+    cplx<T>* t2 = (cplx<T>*)rt.scratch.take((size_t)std::max(cf.ns, 1) * nrhs * sizeof(cplx<T>));
+    BfCall cl;
+    cl.bf = cf.f12.get();
+    cl.x_off = cl.y_off = 0;
+    cl.alpha_re = 1.0;
+    cl.alpha_im = 0;
+    cl.beta = 0;
+    cl.nrhs = nrhs;
+    cl.y_abs = (int64_t)((uintptr_t)t / esz);
+    cl.ldy = cf.ns;
+    if (sizeof(T) == 8) {  // t = F12 W(ns:n)
+      cl.x_abs = (int64_t)((uintptr_t)(w + cf.ns) / esz);
+      cl.ldx = n;
+    } else {  // u = W(ns:n) in complex64, t = F12 u
+      cplx<T>* u = (cplx<T>*)rt.scratch.take((size_t)std::max(cf.nu, 1) * nrhs * sizeof(cplx<T>));
+      to_low.push_back(AxpbyTask{u, w + cf.ns, cf.nu, n, cf.nu, nrhs, 0});
+      cl.x_abs = (int64_t)((uintptr_t)u / esz);
+      cl.ldx = cf.nu;
+    }
+    calls.push_back(cl);
+    inv.push_back(HodbfInvItem<T>{&cf.f11, 0, t, cf.ns, t2, cf.ns, nrhs});
+    upd.push_back(AxpbyTask{w, t2, n, cf.ns, cf.ns, nrhs, 0});  // W(0:ns) -= F11^-1 t
+  }
+  if (calls.empty()) {
+    rt.scratch.release(mk);
+    return;
+  }
+  if (!to_low.empty())
+    ochk(launch_mix_batch<T, double>((const AxpbyTask*)up(rt, to_low), (int)to_low.size(), maxe, 1.0, 0.0, 0.0, s),
+         "to c64");
+  rt.apply_calls(calls, false);
+  hodbf_inv_apply_many<T>(rt, inv, false);
+  ochk(launch_mix_batch<double, T>((const AxpbyTask*)up(rt, upd), (int)upd.size(), maxe, -1.0, 1.0, 0.0, s),
+       "update");
+  rt.scratch.release(mk);
+}
+
 void factor_compressed_level(void* state, Context& c, const std::vector<int>& fronts,
                              const std::vector<const FrontDesc*>& d_fds, const std::vector<void*>& cbs) {
   auto* h = (CompHolder*)state;
@@ -1362,6 +1487,26 @@ void backward_compressed(void* state, Context& c, int f, void* W, int n, int nrh
     backward_front<float>(*h->f, f, W, n, nrhs);
   else
     backward_front<double>(*h->d, f, W, n, nrhs);
+}
+
+void forward_compressed_level(void* state, Context& c, const std::vector<int>& fs, const std::vector<void*>& Ws,
+                              const std::vector<int>& ns, int nrhs) {
+  auto* h = (CompHolder*)state;
+  (void)c;
+  if (h->single)
+    forward_level<float>(*h->f, fs, Ws, ns, nrhs);
+  else
+    forward_level<double>(*h->d, fs, Ws, ns, nrhs);
+}
+
+void backward_compressed_level(void* state, Context& c, const std::vector<int>& fs, const std::vector<void*>& Ws,
+                               const std::vector<int>& ns, int nrhs) {
+  auto* h = (CompHolder*)state;
+  (void)c;
+  if (h->single)
+    backward_level<float>(*h->f, fs, Ws, ns, nrhs);
+  else
+    backward_level<double>(*h->d, fs, Ws, ns, nrhs);
 }
 
 template <class T>

@@ -242,6 +242,7 @@ struct Context {
   PrecGraph pgraph;
   DevBuf g_B, g_X, g_V, g_w, g_r, g_scal, g_part, g_tmp;
   DevBuf g_tmp_plan;  // device copy of the current grouped-GEMM task lists
+  DevBuf g_tmp_scatter;  // task list of a level's batched scatter in the backward sweep (one per front)
   Staging stage;      // pinned ring of host-to-device uploads
   int64_t g_nrhs = 0, g_restart = 0;
 
@@ -280,6 +281,11 @@ void factor_compressed_level(void* state, Context& c, const std::vector<int>& fr
                              const std::vector<const FrontDesc*>& d_fds, const std::vector<void*>& cbs);
 void forward_compressed(void* state, Context& c, int f, void* W, int n, int nrhs);
 void backward_compressed(void* state, Context& c, int f, void* W, int n, int nrhs);
+// all compressed fronts of a level at once (front ids, their workspaces W_f and sizes n_f)
+void forward_compressed_level(void* state, Context& c, const std::vector<int>& fronts, const std::vector<void*>& Ws,
+                              const std::vector<int>& ns, int nrhs);
+void backward_compressed_level(void* state, Context& c, const std::vector<int>& fronts,
+                               const std::vector<void*>& Ws, const std::vector<int>& ns, int nrhs);
 void compressed_stats(void* state, double& bytes, int& maxrank);
 uint64_t comp_state_bytes(void* state);  // device bytes held by the compressed fronts' pools
 

@@ -263,6 +263,7 @@ void factor_dense(Context& c) {
   }
   if (c.d_fds.bytes < nf * sizeof(FrontDesc)) alloc(c.d_fds, nf * sizeof(FrontDesc));
   HIPCHK(hipMemcpy(c.d_fds.p, c.h_fds.data(), nf * sizeof(FrontDesc), hipMemcpyHostToDevice));
+  if (c.g_tmp_scatter.bytes < nf * sizeof(AxpbyTask)) alloc(c.g_tmp_scatter, nf * sizeof(AxpbyTask));
   c.fds_nrhs = -1;  // solve workspaces not set in these descriptors
   ++c.factor_gen;   // a captured preconditioner of the previous factorization is stale
   HIPCHK(hipMemsetAsync(c.d_status.p, 0, 16, c.stream));
@@ -479,21 +480,60 @@ void apply_preconditioner_dev(Context& c, const void* dB, int64_t ldb, void* dX,
         c.timer.end(tk, c.stream, K_FWD, lvl_flops, lvl_bytes);
       }
     }
-    for (int k = e; k < e_all; ++k) {  // compressed fronts
-      const FrontPlan& p = c.fp[c.level_order[k]];
-      check(launch_fwd_gather<double>(dfds + k, 1, p.n, c.d_y.p, c.n, (int)nrhs, c.stream), "fwd gather");
-      forward_compressed(c.comp, c, c.level_order[k], c.h_fds[k].W, p.n, (int)nrhs);
+    if (e_all > e && c.fopts.batched) {  // compressed fronts of the level together
+      std::vector<int> fs, ns;
+      std::vector<void*> Ws;
+      int maxn = 0;
+      for (int k = e; k < e_all; ++k) {
+        fs.push_back(c.level_order[k]);
+        ns.push_back(c.fp[c.level_order[k]].n);
+        Ws.push_back(c.h_fds[k].W);
+        maxn = std::max(maxn, c.fp[c.level_order[k]].n);
+      }
+      check(launch_fwd_gather<double>(dfds + e, e_all - e, maxn, c.d_y.p, c.n, (int)nrhs, c.stream), "fwd gather");
+      forward_compressed_level(c.comp, c, fs, Ws, ns, (int)nrhs);
+    } else {
+      for (int k = e; k < e_all; ++k) {  // compressed fronts one after another
+        const FrontPlan& p = c.fp[c.level_order[k]];
+        check(launch_fwd_gather<double>(dfds + k, 1, p.n, c.d_y.p, c.n, (int)nrhs, c.stream), "fwd gather");
+        forward_compressed(c.comp, c, c.level_order[k], c.h_fds[k].W, p.n, (int)nrhs);
+      }
     }
   }
   for (int L = nlev - 1; L >= 0; --L) {
     const int b = c.level_ptr[L], e = b + c.level_ndense[L], e_all = c.level_ptr[L + 1];
-    for (int k = e; k < e_all; ++k) {  // compressed fronts
-      const FrontPlan& p = c.fp[c.level_order[k]];
-      check(launch_bwd_gather<double>(dfds + k, 1, p.nu, c.d_x.p, c.n, (int)nrhs, c.stream), "bwd gather");
-      backward_compressed(c.comp, c, c.level_order[k], c.h_fds[k].W, p.n, (int)nrhs);
-      check(launch_axpby<double>((char*)c.d_x.p + c.sym.sbeg[c.level_order[k]] * 16, c.n, c.h_fds[k].W, p.n, p.ns,
-                                 (int)nrhs, 1.0, 0.0, c.stream),
-            "scatter");
+    if (e_all > e && c.fopts.batched) {  // compressed fronts of the level together
+      std::vector<int> fs, ns;
+      std::vector<void*> Ws;
+      std::vector<AxpbyTask> sc;
+      int maxnu = 0;
+      int64_t maxe = 0;
+      for (int k = e; k < e_all; ++k) {
+        const FrontPlan& p = c.fp[c.level_order[k]];
+        fs.push_back(c.level_order[k]);
+        ns.push_back(p.n);
+        Ws.push_back(c.h_fds[k].W);
+        maxnu = std::max(maxnu, p.nu);
+        maxe = std::max<int64_t>(maxe, (int64_t)p.ns * nrhs);
+        sc.push_back(AxpbyTask{(char*)c.d_x.p + c.sym.sbeg[c.level_order[k]] * 16, c.h_fds[k].W, c.n, p.n, p.ns,
+                               (int32_t)nrhs, 0});  // x(I^s) = W(0:ns)
+      }
+      check(launch_bwd_gather<double>(dfds + e, e_all - e, maxnu, c.d_x.p, c.n, (int)nrhs, c.stream), "bwd gather");
+      backward_compressed_level(c.comp, c, fs, Ws, ns, (int)nrhs);
+      AxpbyTask* d_sc = (AxpbyTask*)c.g_tmp_scatter.p;
+      if (c.g_tmp_scatter.bytes < sc.size() * sizeof(AxpbyTask))
+        throw Error(BFMF_E_INVAL, "internal: scatter task buffer too small");
+      c.stage.put(d_sc, sc.data(), sc.size() * sizeof(AxpbyTask), c.stream);
+      check(launch_mix_batch<double, double>(d_sc, (int)sc.size(), maxe, 1.0, 0.0, 0.0, c.stream), "scatter");
+    } else {
+      for (int k = e; k < e_all; ++k) {  // compressed fronts one after another
+        const FrontPlan& p = c.fp[c.level_order[k]];
+        check(launch_bwd_gather<double>(dfds + k, 1, p.nu, c.d_x.p, c.n, (int)nrhs, c.stream), "bwd gather");
+        backward_compressed(c.comp, c, c.level_order[k], c.h_fds[k].W, p.n, (int)nrhs);
+        check(launch_axpby<double>((char*)c.d_x.p + c.sym.sbeg[c.level_order[k]] * 16, c.n, c.h_fds[k].W, p.n, p.ns,
+                                   (int)nrhs, 1.0, 0.0, c.stream),
+              "scatter");
+      }
     }
     if (e <= b) {
     } else if (c.fopts.batched) {

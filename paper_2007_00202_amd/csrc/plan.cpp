@@ -218,7 +218,7 @@ Context::~Context() {
 uint64_t Context::device_bytes() const {
   uint64_t t = 0;
   for (const DevBuf* b : {&d_rowptr, &d_colind, &d_values, &d_perm, &d_aptr, &d_arow, &d_avidx, &d_inv, &d_iu32,
-                          &d_piv, &d_status, &d_fds, &d_work, &d_fac, &d_kept, &d_W, &d_y, &d_x, &g_B, &g_X, &g_V, &g_w,
+                          &d_piv, &d_status, &d_fds, &d_work, &d_fac, &d_kept, &d_W, &d_y, &d_x, &g_B, &g_X, &g_V, &g_w, &g_tmp_scatter,
                           &g_r, &g_scal, &g_part, &g_tmp})
     t += b->bytes;
   t += stage.cap;  // pinned host ring (counted with the handle's memory)
