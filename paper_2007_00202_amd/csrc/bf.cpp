@@ -552,6 +552,7 @@ void ExtractBatch::add(const FrontDesc* fd, const void* dense, int64_t ldd, cons
 
 template <class TO, class T>
 void run_extract_to(BfRuntime<T>& rt, ExtractBatch& b, bool src_single) {
+  HostTimer ht(HP_EXTRACT);
   if (b.tasks.empty()) {
     b.idx.clear();
     return;
@@ -908,6 +909,7 @@ void finish_step(BfRuntime<T>& rt, IdLevel<T>& idl, std::vector<StepBlock>& bloc
 template <class T>
 void bf_entry_eval_batch(BfRuntime<T>& rt, const std::vector<EntryJob<T>*>& jobs) {
   if (jobs.empty()) return;
+  HostTimer ht(HP_ENTRY);
   auto mk = rt.scratch.mark();
   for (auto* j : jobs) {
     j->out = std::make_unique<Butterfly>();
@@ -1302,6 +1304,7 @@ int size_bucket(int m, int n) {
 
 template <class T>
 void bf_random_matvec_batch(BfRuntime<T>& rt, const std::vector<RandomJob<T>*>& jobs) {
+  HostTimer ht(HP_RANDOM);
   std::vector<RandomJob<T>*> pending;
   for (auto* j : jobs) {
     const int b = size_bucket(j->to.n, j->ts.n);

@@ -89,12 +89,15 @@ struct BfsSampler : ProxySampler {
   BfsSampler(const std::vector<std::vector<int32_t>>& nr, int r0, int c0, int k, double a, uint64_t seed)
       : near(nr), row0(r0), col0(c0), knn(k), alpha(a), g(seed) {}
   void pick(const std::vector<int32_t>& given, int given0, int beg, int end, int node0, std::vector<int32_t>& out) {
+    HostTimer ht(HP_SAMPLE);
     out.clear();
     const int n = end - beg;
     if (n <= 0) return;
     const int cap = 2048;
     const int k = std::min(n, std::max(8, (int)(alpha * (double)given.size())));
-    std::vector<char> mark(n, 0);
+    // membership marks in a buffer kept between calls (cleared entry by entry afterwards)
+    static thread_local std::vector<char> mark;
+    if ((int)mark.size() < n) mark.assign(n, 0);
     int cnt = 0;
     // nearest neighbours first
     for (int32_t gi : given) {
@@ -104,6 +107,7 @@ struct BfsSampler : ProxySampler {
         if (p >= beg && p < end) {
           if (!mark[p - beg] && cnt < cap) {
             mark[p - beg] = 1;
+            out.push_back(p);
             ++cnt;
           }
           if (++found >= knn) break;
@@ -116,11 +120,12 @@ struct BfsSampler : ProxySampler {
       const int p = d(g);
       if (!mark[p]) {
         mark[p] = 1;
+        out.push_back(beg + p);
         ++cnt;
       }
     }
-    for (int i = 0; i < n; ++i)
-      if (mark[i]) out.push_back(beg + i);
+    for (int32_t v : out) mark[v - beg] = 0;
+    std::sort(out.begin(), out.end());  // ascending, as the proxy lists are used
   }
   void columns(const std::vector<int32_t>& rows, int beg, int end, std::vector<int32_t>& out) override {
     pick(rows, row0, beg, end, col0, out);

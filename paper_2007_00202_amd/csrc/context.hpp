@@ -57,7 +57,7 @@ class Error : public std::exception {
 // ring is reused after the stream has been synchronised (sync()), or, when it
 // is full, after put() has synchronised the stream itself.
 // Host-side time of a factorization by activity (BFMF_VERBOSE diagnostics).
-enum HostSlot { HP_SYNC = 0, HP_PUT, HP_LAUNCH, HP_PLAN, HP_RUN, HP_COUNT };
+enum HostSlot { HP_SYNC = 0, HP_PUT, HP_LAUNCH, HP_PLAN, HP_RUN, HP_ENTRY, HP_RANDOM, HP_EXTRACT, HP_SAMPLE, HP_COUNT };
 struct HostProf {
   double sec[HP_COUNT] = {};
   int64_t n[HP_COUNT] = {};

@@ -312,6 +312,9 @@ __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<
   }
   __syncthreads();
   const int kmax = min(tk.maxrank, p);
+  // lanes per column in the row update: 256 / p rounded down to a power of two, at most 8
+  const int tpc = p <= 32 ? 8 : p <= 64 ? 4 : p <= 128 ? 2 : 1;
+  const int pcols = (p + 256 / tpc - 1) / (256 / tpc) * (256 / tpc);  // columns padded to whole passes
   double d0 = 0;
   int k = 0;
   for (; k < kmax; ++k) {
@@ -330,25 +333,37 @@ __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<
     const double rkk = sqrt(dmax);
     for (int i = tid; i < k; i += 256) rc[i] = R[(int64_t)i * p + pi];
     __syncthreads();  // rc visible; every thread has read d and sel for this step
-    // row k: R(k, j) = (G(pi, j) - sum_i conj(R(i, pi)) R(i, j)) / rkk, G(pi, j) = conj(G(j, pi))
-    for (int j = tid; j < p; j += 256) {
-      cplx<T> out = {0, 0};
-      if (j == pi) {
-        out.re = (T)rkk;
-      } else if (sel[j] < 0) {
-        const cplx<T> g = G[j + (int64_t)pi * p];
-        double sr = g.re, si = -(double)g.im;
-        for (int i = 0; i < k; ++i) {
+    // row k: R(k, j) = (G(pi, j) - sum_i conj(R(i, pi)) R(i, j)) / rkk, G(pi, j) = conj(G(j, pi));
+    // tpc adjacent lanes share a column's sum (lane part takes i = part, part + tpc, ...)
+    const int part = tid & (tpc - 1);
+    for (int j0 = tid / tpc; j0 < pcols; j0 += 256 / tpc) {
+      const int j = j0;
+      const bool live = j < p && j != pi && sel[j] < 0;
+      double sr = 0, si = 0;
+      if (live)
+        for (int i = part; i < k; i += tpc) {
           const cplx<T> a = rc[i], b = R[(int64_t)i * p + j];
-          sr -= (double)a.re * b.re + (double)a.im * b.im;  // conj(a) b
-          si -= (double)a.re * b.im - (double)a.im * b.re;
+          sr += (double)a.re * b.re + (double)a.im * b.im;  // conj(a) b
+          si += (double)a.re * b.im - (double)a.im * b.re;
         }
-        out.re = (T)(sr / rkk);
-        out.im = (T)(si / rkk);
-        const double nd = d[j] - (sr * sr + si * si) / dmax;
-        d[j] = nd > 0 ? nd : 0;
+      for (int o = 1; o < tpc; o <<= 1) {  // lanes of one column are adjacent within a wave
+        sr += __shfl_xor(sr, o);
+        si += __shfl_xor(si, o);
       }
-      R[(int64_t)k * p + j] = out;
+      if (part == 0 && j < p) {
+        cplx<T> out = {0, 0};
+        if (j == pi) {
+          out.re = (T)rkk;
+        } else if (live) {
+          const cplx<T> g = G[j + (int64_t)pi * p];
+          const double gr = (double)g.re - sr, gi = -(double)g.im - si;
+          out.re = (T)(gr / rkk);
+          out.im = (T)(gi / rkk);
+          const double nd = d[j] - (gr * gr + gi * gi) / dmax;
+          d[j] = nd > 0 ? nd : 0;
+        }
+        R[(int64_t)k * p + j] = out;
+      }
     }
     if (tid == 0) {
       sel[pi] = k;

@@ -349,10 +349,13 @@ void factor_dense(Context& c) {
     const HostProf& h = c.hprof;
     fprintf(stderr,
             "[bfmf-host] factor %.3f s: blocked in syncs %.3f s (%lld), staging puts %.3f s (%lld), GEMM launch calls "
-            "%.3f s (%lld), plan building %.3f s (%lld), run_plan total %.3f s (%lld)\n",
+            "%.3f s (%lld), plan building %.3f s (%lld), run_plan total %.3f s (%lld); inclusive: entry "
+            "constructions %.3f s, random constructions %.3f s, extraction %.3f s (%lld), proxy sampling %.3f s "
+            "(%lld)\n",
             c.stats.factor_seconds, h.sec[HP_SYNC], (long long)h.n[HP_SYNC], h.sec[HP_PUT], (long long)h.n[HP_PUT],
             h.sec[HP_LAUNCH], (long long)h.n[HP_LAUNCH], h.sec[HP_PLAN], (long long)h.n[HP_PLAN], h.sec[HP_RUN],
-            (long long)h.n[HP_RUN]);
+            (long long)h.n[HP_RUN], h.sec[HP_ENTRY], h.sec[HP_RANDOM], h.sec[HP_EXTRACT], (long long)h.n[HP_EXTRACT],
+            h.sec[HP_SAMPLE], (long long)h.n[HP_SAMPLE]);
   }
   c.timer.collect();
   if (c.verbose && c.timer.enabled) {
