@@ -147,6 +147,38 @@ def run_form(bfmf, s, prob, nrhs, dB, dX, steps, warmup, form, precision, n_min,
             "max_rank": st["max_rank"], "kernels": s.kernel_stats(), "gemm_tiles": s.gemm_tile_launches()}
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "kernels_helmholtz100_c64.md")
+
+
+def library_sources_sha256():
+    """Hash of every library source (kernels, launch plans, tile tables): traffic counted by the
+    profiler describes these sources only."""
+    import hashlib
+    base = os.path.join(ROOT, "paper_2007_00202_amd", "csrc")
+    h = hashlib.sha256()
+    for dirpath, _, files in sorted(os.walk(base)):
+        for f in sorted(files):
+            if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+                path = os.path.join(dirpath, f)
+                h.update(os.path.relpath(path, base).encode())
+                h.update(open(path, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, precision):
+    """HBM bytes per launch of `kernel` from the committed profiler record (FETCH_SIZE and
+    WRITE_SIZE scaled by a copy of known size), or None when the record is missing, is for
+    another kernel or precision, or the library sources changed since it was taken."""
+    if precision != "c64" or not os.path.exists(TRAFFIC_RECORD):
+        return None
+    for line in open(TRAFFIC_RECORD):
+        if line.startswith("* record: "):
+            rec = json.loads(line[len("* record: "):])
+            if rec.get("kernel") == kernel and rec.get("sources_sha256") == library_sources_sha256():
+                return rec.get("traffic_bytes_per_launch")
+    return None
+
+
 def roofline(ks, steps, precision):
     """Roofline of the dominant single-kernel class (estimated total time; sampled classes scaled)."""
     single = {"assemble": "hbm", "schur_gemm": "mfma", "butterfly_gemm": "mfma", "interp_decomp": "alu",
@@ -168,7 +200,8 @@ def roofline(ks, steps, precision):
         ach = kk["flops"] / max(kk["seconds"], 1e-30) / 1e12
         peak, unit = (fp_peak if bound == "mfma" else PEAKS["fp64_tflops"]), "TFLOP/s"
     rf = {"bound": bound, "kernel": dom, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
-          "traffic": None, "timed_launches": kk["launches"], "launches": kk["launches_all"],
+          "traffic": measured_traffic(dom, precision), "timed_launches": kk["launches"],
+          "launches": kk["launches_all"],
           "avg_launch_ms": 1e3 * per_launch_s}
     kernels = {k: {"ms": 1e3 * total_s(k) / steps, "launches": v["launches_all"] // max(steps, 1),
                    "timed_launches": v["launches"] // max(steps, 1),
