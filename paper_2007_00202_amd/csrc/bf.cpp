@@ -1,5 +1,6 @@
 // Butterfly format, products and construction (paper Sec. 3).  See bf.hpp.
 #include "bf.hpp"
+#include "host_pool.hpp"
 #include "ops.hpp"
 
 #include <algorithm>
@@ -906,6 +907,13 @@ void finish_step(BfRuntime<T>& rt, IdLevel<T>& idl, std::vector<StepBlock>& bloc
 }  // namespace
 
 // ----------------------------------------------------------- Alg. 2
+// one construction step of one job: its blocks (candidates) and their proxies
+struct JobStep {
+  int l = -1;
+  std::vector<StepBlock> blocks;
+  std::vector<std::vector<int32_t>> prox;
+};
+
 template <class T>
 void bf_entry_eval_batch(BfRuntime<T>& rt, const std::vector<EntryJob<T>*>& jobs) {
   if (jobs.empty()) return;
@@ -925,18 +933,33 @@ void bf_entry_eval_batch(BfRuntime<T>& rt, const std::vector<EntryJob<T>*>& jobs
     std::vector<int> q, p;
     std::vector<Butterfly*> act;
     std::vector<int> act_level;
-    for (auto* j : jobs) {
-      Butterfly& bf = *j->out;
+    // candidates and proxy columns of every block, in parallel over the jobs (a job's sampler stays on
+    // one thread and runs in block order, so the proxies do not depend on the threads)
+    std::vector<JobStep> js(jobs.size());
+    HostPool::get().parallel_for(jobs.size(), [&](size_t ji) {
+      Butterfly& bf = *jobs[ji]->out;
       const int L = bf.L, l = L - k;
-      if (l < bf.lc) continue;
-      act.push_back(&bf);
-      act_level.push_back(l);
+      JobStep& st = js[ji];
+      st.l = l < bf.lc ? -1 : l;
+      if (st.l < 0) return;
       const int vs = 1 << (L - l);
+      st.blocks.reserve(1 << L);
+      st.prox.resize(1 << L);
       for (int blk = 0; blk < (1 << L); ++blk) {
         const int t = blk / vs, v = blk % vs;
-        StepBlock sb{&bf, blk, l, left_rows(bf, l, t, v)};
-        std::vector<int32_t> cols;
-        j->ps->columns(sb.cand, bf.ts.beg(L - l, v), bf.ts.end(L - l, v), cols);
+        st.blocks.push_back(StepBlock{&bf, blk, l, left_rows(bf, l, t, v)});
+        jobs[ji]->ps->columns(st.blocks.back().cand, bf.ts.beg(L - l, v), bf.ts.end(L - l, v), st.prox[blk]);
+      }
+    });
+    for (size_t ji = 0; ji < jobs.size(); ++ji) {
+      auto* j = jobs[ji];
+      JobStep& st = js[ji];
+      if (st.l < 0) continue;
+      act.push_back(j->out.get());
+      act_level.push_back(st.l);
+      for (size_t blk = 0; blk < st.blocks.size(); ++blk) {
+        StepBlock& sb = st.blocks[blk];
+        const std::vector<int32_t>& cols = st.prox[blk];
         const int pp = (int)sb.cand.size(), qq = (int)cols.size();
         void* a = rt.scratch.take((size_t)std::max(pp * qq, 1) * sizeof(cplx<double>));
         j->src->request(eb, sb.cand, cols, a, std::max(qq, 1), true);  // A = K(rows, cols)^T, q x p
@@ -964,18 +987,31 @@ void bf_entry_eval_batch(BfRuntime<T>& rt, const std::vector<EntryJob<T>*>& jobs
     std::vector<int> q, p;
     std::vector<Butterfly*> act;
     std::vector<int> act_level;
-    for (auto* j : jobs) {
-      Butterfly& bf = *j->out;
+    std::vector<JobStep> js(jobs.size());
+    HostPool::get().parallel_for(jobs.size(), [&](size_t ji) {
+      Butterfly& bf = *jobs[ji]->out;
       const int L = bf.L, l = k;
-      if (l > bf.lc) continue;
-      act.push_back(&bf);
-      act_level.push_back(l);
+      JobStep& st = js[ji];
+      st.l = l > bf.lc ? -1 : l;
+      if (st.l < 0) return;
       const int vs = 1 << (L - l);
+      st.blocks.reserve(1 << L);
+      st.prox.resize(1 << L);
       for (int blk = 0; blk < (1 << L); ++blk) {
         const int t = blk / vs, v = blk % vs;
-        StepBlock sb{&bf, blk, l, right_cols(bf, l, t, v)};
-        std::vector<int32_t> rows;
-        j->ps->rows(sb.cand, bf.to.beg(l, t), bf.to.end(l, t), rows);
+        st.blocks.push_back(StepBlock{&bf, blk, l, right_cols(bf, l, t, v)});
+        jobs[ji]->ps->rows(st.blocks.back().cand, bf.to.beg(l, t), bf.to.end(l, t), st.prox[blk]);
+      }
+    });
+    for (size_t ji = 0; ji < jobs.size(); ++ji) {
+      auto* j = jobs[ji];
+      JobStep& st = js[ji];
+      if (st.l < 0) continue;
+      act.push_back(j->out.get());
+      act_level.push_back(st.l);
+      for (size_t blk = 0; blk < st.blocks.size(); ++blk) {
+        StepBlock& sb = st.blocks[blk];
+        const std::vector<int32_t>& rows = st.prox[blk];
         const int pp = (int)sb.cand.size(), qq = (int)rows.size();
         void* a = rt.scratch.take((size_t)std::max(pp * qq, 1) * sizeof(cplx<double>));
         j->src->request(eb, rows, sb.cand, a, std::max(qq, 1), false);  // A = K(rows, cols), q x p
