@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-seconds", type=float, default=0.25, help="arrival window of the serving run")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean request arrivals per second")
+    ap.add_argument("--sep-leaf", type=int, default=None,
+                    help="separators are bisected down to this many nodes (HOD-BF leaves); default: the workload's")
     ap.add_argument("--gemm-tile", type=int, default=-1,
                     help="force one grouped-GEMM tile shape (0..5; -1: the autotuned choice per launch)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -282,7 +284,8 @@ def main():
     tol = cfg["tol"] if a.tol is None else a.tol
     precision = a.precision or cfg["precision"]
     nrhs = prob.rhs.shape[1]
-    s = bfmf.Solver(0).analyze(prob.rowptr, prob.colind, prob.values, dims=prob.dims)
+    sep_leaf = a.sep_leaf or cfg.get("sep_leaf", 64)
+    s = bfmf.Solver(0).analyze(prob.rowptr, prob.colind, prob.values, dims=prob.dims, sep_leaf=sep_leaf)
     dB = torch.from_numpy(np.ascontiguousarray(prob.rhs.T)).to("cuda")  # column-major (N, nrhs)
     dX = torch.zeros_like(dB)
     r = run_form(bfmf, s, prob, nrhs, dB, dX, a.steps, a.warmup, a.form, precision, n_min, tol)
@@ -297,7 +300,7 @@ def main():
         "dtype": "c128" if precision == "c128" else "c64+f64",
         "data": "synthetic",
         "config": {"workload": f"{a.config}: 3D Helmholtz 7-pt {prob.dims[0]}^3 (N={prob.n}), {nrhs} RHS",
-                   "form": a.form, "n_min": n_min, "tol": tol, "precision": precision},
+                   "form": a.form, "n_min": n_min, "tol": tol, "precision": precision, "sep_leaf": sep_leaf},
         "factor_s": r["factor_s"], "solve_s": r["solve_s"], "solve_rhs_per_s": r["solve_rhs_per_s"],
         "gmres_iters": r["gmres_iters"], "relres_max": r["relres_max"],
         "factor_tflops": r["factor_flops"] / r["factor_s"] / 1e12,

@@ -5,6 +5,7 @@
 #include "compressed.hpp"
 
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <cstdio>
 #include <cstring>
@@ -366,8 +367,15 @@ struct HodbfInvOp : Op<T> {
   }
 };
 
-// blocks up to this size are inverted densely inside BF_SMW
-constexpr int kSmwDense = 512;
+// blocks up to this size are inverted densely inside BF_SMW (BFMF_SMW_DENSE overrides, for tuning)
+int smw_dense_limit() {
+  static const int v = [] {
+    const char* e = std::getenv("BFMF_SMW_DENSE");
+    const int x = e ? std::atoi(e) : 0;
+    return x >= 16 ? x : 1024;  // measured on the 100^3 workload: 1024 beats 128, 256, 512 and 2048
+  }();
+  return v;
+}
 
 struct SmwResult {
   std::unique_ptr<Butterfly> bf;
@@ -698,7 +706,7 @@ void smw_batch(BfRuntime<T>& rt, const std::vector<SmwJob<T>*>& jobs, int* d_sta
   std::vector<SmwJob<T>*> dense, rec;
   for (auto* j : jobs) {
     const TreeNode& nd = (*j->nodes)[j->node];
-    const bool base = depth_of(*j->nodes, j->node) == 0 || nd.end - nd.beg <= kSmwDense;
+    const bool base = depth_of(*j->nodes, j->node) == 0 || nd.end - nd.beg <= smw_dense_limit();
     (base ? dense : rec).push_back(j);
   }
   smw_dense_batch<T>(rt, dense, d_status);

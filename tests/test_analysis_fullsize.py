@@ -18,16 +18,17 @@ bfmf = pytest.importorskip("paper_2007_00202_amd.bfmf")
 pytestmark = pytest.mark.slow
 
 
-def _check(p):
+def _check(p, sl=None):
     h = bfmf.bfmf_create(-1)
+    sl = sl or p.opts.get("sep_leaf", 64)
     try:
         if p.kind == "grid":
-            bfmf.bfmf_analyze(h, p.rowptr, p.colind, p.values, dims=p.dims)
-            od = nd.nd_grid(p.dims, leaf_max=512, sep_leaf=64)
+            bfmf.bfmf_analyze(h, p.rowptr, p.colind, p.values, dims=p.dims, sep_leaf=sl)
+            od = nd.nd_grid(p.dims, leaf_max=512, sep_leaf=sl)
         else:
             bfmf.bfmf_analyze(h, p.rowptr, p.colind, p.values, kind=bfmf.BFMF_ORD_YEE, dims=(p.cells, 0, 0),
-                              coords=p.coords)
-            od = nd.nd_yee(p.cells, p.coords, leaf_max=512, sep_leaf=64)
+                              coords=p.coords, sep_leaf=sl)
+            od = nd.nd_yee(p.cells, p.coords, leaf_max=512, sep_leaf=sl)
         sym = symbolic(p.rowptr, p.colind, od)
         s = bfmf.bfmf_get_symbolic(h)
         assert np.array_equal(s["perm"], od.perm)
@@ -62,4 +63,9 @@ def test_full_size_analysis_matches_oracle(name, root_ns, nfronts):
 
 @pytest.mark.parametrize("g", serving_grids())
 def test_serving_grids_analysis_matches_oracle(g):
-    _check(make_problem("helmholtz100", n=g, nrhs=1, config_id="serving"))
+    _check(make_problem("helmholtz100", n=g, nrhs=1, config_id="serving"), sl=64)
+
+
+def test_full_size_analysis_default_leaf():
+    """The 100^3 grid with the default separator leaf size (64) as well."""
+    _check(make_problem("helmholtz100"), sl=64)

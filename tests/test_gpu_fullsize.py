@@ -1,7 +1,7 @@
 """Parity at the full sizes of the measured workloads, in the launch
 configuration the benchmark times: batched form, complex64 butterflies with
 FP64 pivot blocks and GMRES, tol 1e-3, fronts with #I^s >= 1024 compressed,
-64 samples per block.
+64 samples per block, separators bisected down to the workload's leaf size.
 
 The oracle cannot factor these grids whole, so the checks are
   * sampled outputs it computes one by one: dense fronts (leaves, and parents
@@ -27,12 +27,13 @@ N_MIN = 1024
 
 def _analyze(gpu_lib, p):
     s = gpu_lib.Solver(0)
+    sl = p.opts.get("sep_leaf", 64)
     if p.kind == "grid":
-        s.analyze(p.rowptr, p.colind, p.values, dims=p.dims)
-        od = nd.nd_grid(p.dims, leaf_max=512, sep_leaf=64)
+        s.analyze(p.rowptr, p.colind, p.values, dims=p.dims, sep_leaf=sl)
+        od = nd.nd_grid(p.dims, leaf_max=512, sep_leaf=sl)
     else:
-        s.analyze(p.rowptr, p.colind, p.values, coords=p.coords, cells=p.cells)
-        od = nd.nd_yee(p.cells, p.coords, leaf_max=512, sep_leaf=64)
+        s.analyze(p.rowptr, p.colind, p.values, coords=p.coords, cells=p.cells, sep_leaf=sl)
+        od = nd.nd_yee(p.cells, p.coords, leaf_max=512, sep_leaf=sl)
     return s, od
 
 

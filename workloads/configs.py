@@ -35,9 +35,11 @@ CONFIGS = {
     # 24^3, delta 0.05, leaves <= 512, compress separators >= 256, tol 1e-3, c128, 1 RHS
     "helmholtz24": dict(kind="grid", n=24, delta=0.05, nrhs=1, rhs="center_noise",
                         n_min=256, tol=1e-3, precision="c128", samples=64),
-    # 100^3, delta 0.02, compress >= 1024, 64 probes per block, c64 bulk, 8 RHS
+    # 100^3, delta 0.02, compress >= 1024, 64 probes per block, c64 bulk, 8 RHS; separators bisected
+    # down to 128 nodes (the HOD-BF leaf size, a tuning parameter: 128 measured faster than 64; the
+    # larger separators of the 128^3 and Yee grids exceed the ID kernels' 512 columns at 128)
     "helmholtz100": dict(kind="grid", n=100, delta=0.02, nrhs=8, rhs="points",
-                         n_min=1024, tol=1e-3, precision="c64", samples=64),
+                         n_min=1024, tol=1e-3, precision="c64", samples=64, sep_leaf=128),
     # 128^3 GRF velocity, batched levels, 32 RHS (damping not stated: 0.02 as above)
     "helmholtz128grf": dict(kind="grid", n=128, delta=0.02, nrhs=32, rhs="points",
                             n_min=1024, tol=1e-3, precision="c64", samples=64, grf=True),
