@@ -611,16 +611,16 @@ struct IdLevel {
     int32_t* d_rank = rt.scratch.template take_n<int32_t>(std::max<size_t>(nb, 1));
     int32_t* d_perm = rt.scratch.template take_n<int32_t>(std::max<int64_t>(tot_perm, 1));
     int64_t po = 0;
+    const bool gram = rt.tol >= 1e-4;  // Gram variant for tolerances where eps p / tol^2 is negligible
     for (size_t i = 0; i < nb; ++i) {
-      if (p[i] > 512 || q[i] > 2048)
+      if (p[i] > (gram ? GRAM_MAXP : 512) || q[i] > 2048)
         throw Error(BFMF_E_INVAL, "ID block too large (" + std::to_string(q[i]) + " x " + std::to_string(p[i]) + ")");
       const int maxrank = std::max(1, std::min(p[i], q[i]));
       void* Tb = rt.scratch.take((size_t)maxrank * std::max(p[i], 1) * sizeof(cplx<double>));
       tasks[i] = IdTask{A[i], std::max(q[i], 1), q[i], p[i], maxrank, d_rank + i, d_perm + po, Tb, nullptr, nullptr};
       po += p[i];
     }
-    // Gram variant (FP64, tolerances where eps p / tol^2 is negligible): G_i = A_i^H A_i in one grouped GEMM
-    const bool gram = rt.tol >= 1e-4;
+    // Gram variant (FP64): G_i = A_i^H A_i in one grouped GEMM
     if (gram) {
       std::vector<GTask> gt;
       for (size_t i = 0; i < nb; ++i) {
@@ -661,12 +661,14 @@ struct IdLevel {
     KernelTimer& tm = rt.c->timer;
     const int tk = tm.want(K_ID) ? tm.begin(s) : -1;
     int lds_entries = 0;  // the largest R (kmax x p) that fits the LDS budget sizes the launch's LDS
+    int maxp = 16;
     for (const IdTask& t : tasks) {
       const int64_t e = (int64_t)std::min(t.maxrank, t.p) * t.p;
       if (e <= GRAM_LDS_MAX) lds_entries = std::max<int>(lds_entries, (int)e);
+      maxp = std::max(maxp, (t.p + 15) / 16 * 16);
     }
     if (gram)
-      chk(launch_gram_id<double>(dt, (int)nb, rt.tol, lds_entries, s), "gram id");
+      chk(launch_gram_id<double>(dt, (int)nb, rt.tol, lds_entries, maxp, s), "gram id");
     else
       chk(launch_cpqr_id<double>(dt, (int)nb, rt.tol, s), "cpqr");
     if (tk >= 0) {

@@ -294,15 +294,17 @@ __device__ __forceinline__ void block_argmax(double v, int i, double* red_v, int
 // R (rows 0 .. kmax-1 of the factor, row i at R + i p) lives in LDS when it fits
 // the launch's dynamic LDS, else in the task's workspace; the body is the same.
 template <class T>
-__device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<T>* __restrict__ R) {
+__device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<T>* __restrict__ R,
+                                             unsigned char* __restrict__ aux, int maxp) {
   const int p = tk.p;
   const cplx<T>* G = (const cplx<T>*)tk.G;
-  __shared__ double d[ID_MAXP];
-  __shared__ int sel[ID_MAXP];   // step at which a column was chosen, or -1
-  __shared__ int piv[ID_MAXP];
-  __shared__ int pl[ID_MAXP];    // the permutation
-  __shared__ cplx<T> rc[ID_MAXP];  // R(0:k, pivot) of the step
-  __shared__ cplx<T> tl[ID_MAXP];  // row i of T in the back substitution
+  // per-column state in the launch's dynamic LDS (maxp entries each; maxp is a multiple of 16)
+  cplx<T>* rc = (cplx<T>*)aux;  // R(0:k, pivot) of the step
+  cplx<T>* tl = rc + maxp;      // row i of T in the back substitution
+  double* d = (double*)(tl + maxp);
+  int* sel = (int*)(d + maxp);  // step at which a column was chosen, or -1
+  int* piv = sel + maxp;
+  int* pl = piv + maxp;         // the permutation
   __shared__ double red_v[2][4];
   __shared__ int red_i[2][4];
   const int tid = threadIdx.x;
@@ -415,18 +417,21 @@ __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void gram_id_kernel(const IdTask* __restrict__ tasks, double tol, int lds_entries) {
+__global__ __launch_bounds__(256) void gram_id_kernel(const IdTask* __restrict__ tasks, double tol, int lds_entries,
+                                                      int maxp) {
   extern __shared__ __align__(16) unsigned char gram_smem[];
   const IdTask& tk = tasks[blockIdx.x];
   const int p = tk.p;
-  if (p > ID_MAXP || p < 0 || tk.q < 0) {  // the host never sends these; refuse, never overflow LDS
+  if (p > maxp || p > GRAM_MAXP || p < 0 || tk.q < 0) {  // the host never sends these; refuse, never overflow LDS
     if (threadIdx.x == 0) *tk.rank = -1;
     return;
   }
+  unsigned char* aux = gram_smem;
+  cplx<T>* Rl = (cplx<T>*)(gram_smem + gram_aux_bytes(maxp));
   if ((int64_t)min(tk.maxrank, p) * p <= lds_entries)
-    gram_id_body<T>(tk, tol, (cplx<T>*)gram_smem);
+    gram_id_body<T>(tk, tol, Rl, aux, maxp);
   else
-    gram_id_body<T>(tk, tol, (cplx<T>*)tk.R);
+    gram_id_body<T>(tk, tol, (cplx<T>*)tk.R, aux, maxp);
 }
 
 // U (p x rank, ld p): U[perm[i], i] = 1 (i < rank), U[perm[rank + j], :] = T[:, j]^T,
@@ -902,11 +907,13 @@ hipError_t launch_cpqr_id(const IdTask* d_tasks, int ntasks, double tol, hipStre
 }
 
 template <class T>
-hipError_t launch_gram_id(const IdTask* d_tasks, int ntasks, double tol, int lds_entries, hipStream_t s) {
+hipError_t launch_gram_id(const IdTask* d_tasks, int ntasks, double tol, int lds_entries, int maxp, hipStream_t s) {
   if (ntasks == 0) return hipSuccess;
-  if (lds_entries < 0 || lds_entries > GRAM_LDS_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((gram_id_kernel<T>), dim3(ntasks), dim3(256), (size_t)lds_entries * sizeof(cplx<T>), s, d_tasks,
-                     tol, lds_entries);
+  if (lds_entries < 0 || lds_entries > GRAM_LDS_MAX || maxp <= 0 || maxp > GRAM_MAXP || maxp % 16 != 0 ||
+      sizeof(cplx<T>) != 16)
+    return hipErrorInvalidValue;
+  const size_t bytes = gram_aux_bytes(maxp) + (size_t)lds_entries * sizeof(cplx<T>);
+  hipLaunchKernelGGL((gram_id_kernel<T>), dim3(ntasks), dim3(256), bytes, s, d_tasks, tol, lds_entries, maxp);
   return hipGetLastError();
 }
 
@@ -1041,7 +1048,7 @@ hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int6
   template hipError_t launch_grouped_gemm<T>(const GTask*, const int64_t*, int, int64_t, void* const[4], int,         \
                                              hipStream_t, hipEvent_t, hipEvent_t);                                    \
   template hipError_t launch_cpqr_id<T>(const IdTask*, int, double, hipStream_t);                                     \
-  template hipError_t launch_gram_id<T>(const IdTask*, int, double, int, hipStream_t);                                \
+  template hipError_t launch_gram_id<T>(const IdTask*, int, double, int, int, hipStream_t);                           \
   template hipError_t launch_id_expand<T>(const IdTask*, int, void* const*, const int64_t*, bool, bool, hipStream_t);  \
   template hipError_t launch_front_extract<T>(const ExtractTask*, int, int, const void*, bool, hipStream_t);          \
   template hipError_t launch_philox_gauss<T>(void*, int64_t, int64_t, int, int, const int32_t*, const int32_t*,       \

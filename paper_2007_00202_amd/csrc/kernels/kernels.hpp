@@ -105,8 +105,12 @@ hipError_t launch_cpqr_id(const IdTask* d_tasks, int ntasks, double tol, hipStre
 // lds_entries complex entries of dynamic LDS per workgroup where min(maxrank, p) * p fits, else
 // in IdTask.R
 constexpr int GRAM_LDS_MAX = 4096;
+constexpr int GRAM_MAXP = 1024;  // most columns of a Gram ID block (the Householder kernel takes 512)
+// dynamic LDS of a Gram ID launch whose blocks have at most maxp columns (maxp a multiple of 16): per-column
+// state (pivot search, selection, permutation: 20 bytes; two complex<double> rows: 32 bytes), then the R rows
+__host__ __device__ inline size_t gram_aux_bytes(int maxp) { return (size_t)maxp * 52; }
 template <class T>
-hipError_t launch_gram_id(const IdTask* d_tasks, int ntasks, double tol, int lds_entries, hipStream_t s);
+hipError_t launch_gram_id(const IdTask* d_tasks, int ntasks, double tol, int lds_entries, int maxp, hipStream_t s);
 // interpolation matrices from the QR results into outs[i] (ld ldo[i]);
 // transpose_out writes the rank x p transpose (column ID), conj_out conjugates
 template <class T>

@@ -36,20 +36,19 @@ CONFIGS = {
     "helmholtz24": dict(kind="grid", n=24, delta=0.05, nrhs=1, rhs="center_noise",
                         n_min=256, tol=1e-3, precision="c128", samples=64),
     # 100^3, delta 0.02, compress >= 1024, 64 probes per block, c64 bulk, 8 RHS; separators bisected
-    # down to 128 nodes (the HOD-BF leaf size, a tuning parameter: 128 measured faster than 64; the
-    # larger separators of the 128^3 and Yee grids exceed the ID kernels' 512 columns at 128)
+    # down to 128 nodes (the HOD-BF leaf size, a tuning parameter: 128 measured faster than 64)
     "helmholtz100": dict(kind="grid", n=100, delta=0.02, nrhs=8, rhs="points",
                          n_min=1024, tol=1e-3, precision="c64", samples=64, sep_leaf=128),
     # 128^3 GRF velocity, batched levels, 32 RHS (damping not stated: 0.02 as above)
     "helmholtz128grf": dict(kind="grid", n=128, delta=0.02, nrhs=32, rhs="points",
-                            n_min=1024, tol=1e-3, precision="c64", samples=64, grf=True),
+                            n_min=1024, tol=1e-3, precision="c64", samples=64, grf=True, sep_leaf=128),
     # 3D Poisson (omega = 0) on the same path: the separator ranks grow far more slowly than at
     # high frequency, the first comparison workload after the Helmholtz runs
     "poisson100": dict(kind="grid", n=100, delta=0.0, nrhs=8, rhs="points", omega=0.0,
                        n_min=1024, tol=1e-3, precision="c64", samples=64),
     # Yee curl-curl 64^3 cells, eps on 8^3 blocks in U[1,4], delta 0.03, 16 RHS
     "maxwell64": dict(kind="yee", n=64, delta=0.03, nrhs=16, rhs="dipoles",
-                      n_min=1024, tol=1e-3, precision="c64", samples=64),
+                      n_min=1024, tol=1e-3, precision="c64", samples=64, sep_leaf=128),
 }
 
 
