@@ -317,34 +317,61 @@ __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<
   // lanes per column in the row update: 256 / p rounded down to a power of two, at most 8
   const int tpc = p <= 32 ? 8 : p <= 64 ? 4 : p <= 128 ? 2 : 1;
   const int pcols = (p + 256 / tpc - 1) / (256 / tpc) * (256 / tpc);  // columns padded to whole passes
-  double d0 = 0;
-  int k = 0;
-  for (; k < kmax; ++k) {
+  const int part = tid & (tpc - 1);
+  const int wave = tid >> 6, lane = tid & 63;
+  // the pivot search of a step: each thread's candidate (largest d, first index on ties), the wave's
+  // by shuffles, the four waves' through a double-buffered exchange behind the step's one barrier
+  auto publish = [&](double v, int vi, int buf) {
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(v, o);
+      const int oi = __shfl_xor(vi, o);
+      if (ov > v || (ov == v && oi < vi)) {
+        v = ov;
+        vi = oi;
+      }
+    }
+    if (lane == 0) {
+      red_v[buf][wave] = v;
+      red_i[buf][wave] = vi;
+    }
+  };
+  {
     double v = -1;
     int vi = p;
     for (int j = tid; j < p; j += 256)
-      if (sel[j] < 0 && d[j] > v) {
+      if (d[j] > v) {
         v = d[j];
         vi = j;
       }
-    double dmax;
-    int pi;
-    block_argmax<T>(v, vi, red_v[k & 1], red_i[k & 1], dmax, pi);
+    publish(v, vi, 0);
+  }
+  __syncthreads();
+  double d0 = 0;
+  int k = 0;
+  for (; k < kmax; ++k) {
+    double dmax = red_v[k & 1][0];
+    int pi = red_i[k & 1][0];
+    for (int w = 1; w < 4; ++w)
+      if (red_v[k & 1][w] > dmax || (red_v[k & 1][w] == dmax && red_i[k & 1][w] < pi)) {
+        dmax = red_v[k & 1][w];
+        pi = red_i[k & 1][w];
+      }
     if (k == 0) d0 = dmax;
-    if (!(dmax > tol * tol * d0) || !(dmax > 0) || pi >= p) break;
+    if (!(dmax > tol * tol * d0) || !(dmax > 0) || pi >= p) break;  // the same decision in every thread
     const double rkk = sqrt(dmax);
-    for (int i = tid; i < k; i += 256) rc[i] = R[(int64_t)i * p + pi];
-    __syncthreads();  // rc visible; every thread has read d and sel for this step
     // row k: R(k, j) = (G(pi, j) - sum_i conj(R(i, pi)) R(i, j)) / rkk, G(pi, j) = conj(G(j, pi));
     // tpc adjacent lanes share a column's sum (lane part takes i = part, part + tpc, ...)
-    const int part = tid & (tpc - 1);
-    for (int j0 = tid / tpc; j0 < pcols; j0 += 256 / tpc) {
-      const int j = j0;
+    double v = -1;  // this thread's candidate for the next pivot
+    int vi = p;
+    for (int j = tid / tpc; j < pcols; j += 256 / tpc) {
       const bool live = j < p && j != pi && sel[j] < 0;
+      // G(j, pi) requested before the sum so that its latency overlaps the sum
+      cplx<T> g = {0, 0};
+      if (live && part == 0) g = G[j + (int64_t)pi * p];
       double sr = 0, si = 0;
       if (live)
         for (int i = part; i < k; i += tpc) {
-          const cplx<T> a = rc[i], b = R[(int64_t)i * p + j];
+          const cplx<T> a = R[(int64_t)i * p + pi], b = R[(int64_t)i * p + j];
           sr += (double)a.re * b.re + (double)a.im * b.im;  // conj(a) b
           si += (double)a.re * b.im - (double)a.im * b.re;
         }
@@ -357,12 +384,16 @@ __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<
         if (j == pi) {
           out.re = (T)rkk;
         } else if (live) {
-          const cplx<T> g = G[j + (int64_t)pi * p];
           const double gr = (double)g.re - sr, gi = -(double)g.im - si;
           out.re = (T)(gr / rkk);
           out.im = (T)(gi / rkk);
-          const double nd = d[j] - (gr * gr + gi * gi) / dmax;
-          d[j] = nd > 0 ? nd : 0;
+          double nd = d[j] - (gr * gr + gi * gi) / dmax;
+          nd = nd > 0 ? nd : 0;
+          d[j] = nd;
+          if (nd > v) {  // columns are visited in ascending order: the first on ties is kept
+            v = nd;
+            vi = j;
+          }
         }
         R[(int64_t)k * p + j] = out;
       }
@@ -371,7 +402,8 @@ __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<
       sel[pi] = k;
       piv[k] = pi;
     }
-    __syncthreads();
+    publish(v, vi, (k + 1) & 1);
+    __syncthreads();  // row k, d, sel and the next pivot are visible
   }
   const int rank = k;
   // perm: the pivots, then the other columns in ascending order

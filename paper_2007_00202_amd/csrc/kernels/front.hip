@@ -89,7 +89,11 @@ __global__ __launch_bounds__(256) void assemble_kernel(const FrontDesc* __restri
 
 // ------------------------------------------------------------------ panel
 // One workgroup per front: unblocked LU with partial pivoting of the
-// (ns-k0) x jb panel F11(k0:ns, k0:k0+jb).
+// (ns-k0) x jb panel F11(k0:ns, k0:k0+jb).  Per column: the pivot (largest
+// |Re| + |Im|, first row on ties) by wave shuffles and one exchange between
+// the four waves; the row interchange inside the panel; then every thread
+// scales its rows of the column and updates the same rows of the panel's
+// remaining columns.  Three barriers per column.
 template <class T>
 __global__ __launch_bounds__(256) void panel_kernel(const FrontDesc* __restrict__ fds, int k0, int kb,
                                                     int* __restrict__ status) {
@@ -98,9 +102,9 @@ __global__ __launch_bounds__(256) void panel_kernel(const FrontDesc* __restrict_
   if (k0 >= ns) return;
   const int jb = min(kb, ns - k0);
   cplx<T>* F = (cplx<T>*)fd.F;
-  const int tid = threadIdx.x;
-  __shared__ T rv[256];
-  __shared__ int ri[256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ T red_v[2][4];
+  __shared__ int red_i[2][4];
   for (int jj = 0; jj < jb; ++jj) {
     const int col = k0 + jj;
     cplx<T>* Fc = F + (int64_t)col * n;
@@ -113,23 +117,29 @@ __global__ __launch_bounds__(256) void panel_kernel(const FrontDesc* __restrict_
         bi = r;
       }
     }
-    rv[tid] = best;
-    ri[tid] = bi;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s) {
-        const T o = rv[tid + s];
-        const int oi = ri[tid + s];
-        if (o > rv[tid] || (o == rv[tid] && oi < ri[tid])) {
-          rv[tid] = o;
-          ri[tid] = oi;
-        }
+    for (int o = 32; o > 0; o >>= 1) {  // wave maximum, first index on ties
+      const T ov = __shfl_xor(best, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
       }
-      __syncthreads();
     }
-    int p = ri[0];
-    const T pv = rv[0];
+    if (lane == 0) {
+      red_v[jj & 1][wave] = best;
+      red_i[jj & 1][wave] = bi;
+    }
     __syncthreads();
+    T pv = red_v[jj & 1][0];
+    int p = red_i[jj & 1][0];
+    for (int w = 1; w < 4; ++w) {
+      const T ov = red_v[jj & 1][w];
+      const int oi = red_i[jj & 1][w];
+      if (ov > pv || (ov == pv && oi < p)) {
+        pv = ov;
+        p = oi;
+      }
+    }
     const bool singular = !(pv > 0) || p >= ns;
     if (singular) p = col;
     if (tid == 0) {
@@ -147,20 +157,20 @@ __global__ __launch_bounds__(256) void panel_kernel(const FrontDesc* __restrict_
         Fcc[p] = t;
       }
     }
-    __syncthreads();
-    if (!singular) {
-      const cplx<T> d = Fc[col];
-      for (int r = col + 1 + tid; r < ns; r += 256) Fc[r] = cdiv(Fc[r], d);
-    }
-    __syncthreads();
+    __syncthreads();  // the interchanged rows are visible
+    const cplx<T> d = Fc[col];
     for (int r = col + 1 + tid; r < ns; r += 256) {
-      const cplx<T> l = Fc[r];
+      cplx<T> l = Fc[r];
+      if (!singular) {
+        l = cdiv(l, d);
+        Fc[r] = l;
+      }
       for (int c = col + 1; c < k0 + jb; ++c) {
         cplx<T>* Fcc = F + (int64_t)c * n;
         Fcc[r] = csub(Fcc[r], cmul(l, Fcc[col]));
       }
     }
-    __syncthreads();
+    __syncthreads();  // the updated panel is visible to the next pivot search
   }
 }
 
