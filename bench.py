@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean request arrivals per second")
     ap.add_argument("--sep-leaf", type=int, default=None,
                     help="separators are bisected down to this many nodes (HOD-BF leaves); default: the workload's")
+    ap.add_argument("--direct", action="store_true",
+                    help="direct mode: X = M^-1 B from the factorization, no GMRES (use with a tight --tol)")
     ap.add_argument("--gemm-tile", type=int, default=-1,
                     help="force one grouped-GEMM tile shape (0..5; -1: the autotuned choice per launch)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -112,12 +114,15 @@ def _partial_solve(fac, B, nfr):
     return y
 
 
-def run_form(bfmf, s, prob, nrhs, dB, dX, steps, warmup, form, precision, n_min, tol, timing=True):
-    """Factor + GMRES solve of the RHS block, `steps` timed steps after `warmup` untimed ones."""
+def run_form(bfmf, s, prob, nrhs, dB, dX, steps, warmup, form, precision, n_min, tol, timing=True, direct=False):
+    """Factor + GMRES solve of the RHS block (or, direct, one application of the factorization),
+    `steps` timed steps after `warmup` untimed ones."""
     import torch
     prec = bfmf.BFMF_C128 if precision == "c128" else bfmf.BFMF_C64_MIXED
     so = bfmf.bfmf_default_solve_opts()
     so.true_rtol = 1e-3
+    if direct:
+        so.max_iter = -1
 
     def step():
         s.factor(tol=tol, n_min=n_min, precision=prec, batched=(form == "batched"), timing=timing)
@@ -288,7 +293,7 @@ def main():
     s = bfmf.Solver(0).analyze(prob.rowptr, prob.colind, prob.values, dims=prob.dims, sep_leaf=sep_leaf)
     dB = torch.from_numpy(np.ascontiguousarray(prob.rhs.T)).to("cuda")  # column-major (N, nrhs)
     dX = torch.zeros_like(dB)
-    r = run_form(bfmf, s, prob, nrhs, dB, dX, a.steps, a.warmup, a.form, precision, n_min, tol)
+    r = run_form(bfmf, s, prob, nrhs, dB, dX, a.steps, a.warmup, a.form, precision, n_min, tol, direct=a.direct)
     rf, kernels = roofline(r["kernels"], a.steps, precision)
     out = {
         "metric": "factor time + RHS/s at rel-residual <=1e-3",
@@ -300,7 +305,8 @@ def main():
         "dtype": "c128" if precision == "c128" else "c64+f64",
         "data": "synthetic",
         "config": {"workload": f"{a.config}: 3D Helmholtz 7-pt {prob.dims[0]}^3 (N={prob.n}), {nrhs} RHS",
-                   "form": a.form, "n_min": n_min, "tol": tol, "precision": precision, "sep_leaf": sep_leaf},
+                   "form": a.form, "n_min": n_min, "tol": tol, "precision": precision, "sep_leaf": sep_leaf,
+                   "solver": "direct" if a.direct else "gmres"},
         "factor_s": r["factor_s"], "solve_s": r["solve_s"], "solve_rhs_per_s": r["solve_rhs_per_s"],
         "gmres_iters": r["gmres_iters"], "relres_max": r["relres_max"],
         "factor_tflops": r["factor_flops"] / r["factor_s"] / 1e12,

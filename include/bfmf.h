@@ -96,7 +96,9 @@ typedef struct {
  * column is also at most true_rtol. */
 typedef struct {
     int32_t restart;     /* default 30 */
-    int32_t max_iter;    /* default 300 */
+    int32_t max_iter;    /* default 300 (0 also means 300); negative: direct solve, X = M^-1 B
+                            with the approximate factorization and no iteration, the true
+                            residual in relres_max, E_NOCONV when it exceeds true_rtol > 0 */
     double rtol, atol;   /* defaults 1e-6, 1e-10 */
     double true_rtol;    /* e.g. 1e-3; 0 disables */
     /* outputs */

@@ -204,7 +204,7 @@ static bfmf_status solve_common(bfmf_handle h, int64_t nrhs, const double* B, in
     else
       bfmf_default_solve_opts(&o);
     if (o.restart <= 0) o.restart = 30;
-    if (o.max_iter <= 0) o.max_iter = 300;
+    if (o.max_iter == 0) o.max_iter = 300;  // negative: direct solve
     const double t0 = now_s();
     const size_t elem = 2 * sizeof(double);
     const void* dB = B;

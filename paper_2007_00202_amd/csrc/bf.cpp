@@ -613,7 +613,7 @@ struct IdLevel {
     int64_t po = 0;
     const bool gram = rt.tol >= 1e-4;  // Gram variant for tolerances where eps p / tol^2 is negligible
     for (size_t i = 0; i < nb; ++i) {
-      if (p[i] > (gram ? GRAM_MAXP : 512) || q[i] > 2048)
+      if (p[i] > GRAM_MAXP || q[i] > 2048)  // both ID kernels take up to 1024 columns and 2048 rows
         throw Error(BFMF_E_INVAL, "ID block too large (" + std::to_string(q[i]) + " x " + std::to_string(p[i]) + ")");
       const int maxrank = std::max(1, std::min(p[i], q[i]));
       void* Tb = rt.scratch.take((size_t)maxrank * std::max(p[i], 1) * sizeof(cplx<double>));

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void grouped_gemm_skinny_kernel(const GTask* _
 // remaining norm (first maximum); the factorization stops at the first
 // |R_kk| <= tol |R_00| (rank k) or at maxrank.  Householder vectors live in
 // LDS; one wave applies a reflector to one column at a time.
-constexpr int ID_MAXP = 512;
+constexpr int ID_MAXP = 1024;  // columns of a Householder ID block (the same limit as the Gram variant)
 constexpr int ID_MAXQ = 2048;
 
 template <class T>

@@ -689,6 +689,20 @@ int gmres_dev(Context& c, const void* dB, int64_t ldb, void* dX, int64_t ldx, in
     for (int q = 0; q < nr; ++q) relres[q] = bnorm[q] > 0 ? hh[q].real() / bnorm[q] : 0.0;
   };
 
+  if (o.max_iter < 0) {  // direct solve: X = M^-1 B with the approximate factorization, no refinement
+    apply_preconditioner_dev(c, dB, ldb, dX, ldx, nrhs);
+    true_residual();
+    c.timer.collect();
+    o.iters_max = 0;
+    o.relres_max = 0;
+    bool ok = true;
+    for (int q = 0; q < nr; ++q) {
+      o.relres_max = std::max(o.relres_max, relres[q]);
+      ok &= !(o.true_rtol > 0) || relres[q] <= o.true_rtol;
+    }
+    return ok ? 0 : 1;
+  }
+
   while (total < o.max_iter) {
     bool any = false;
     for (int q = 0; q < nr; ++q) any |= !done[q];

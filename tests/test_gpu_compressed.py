@@ -159,3 +159,26 @@ def test_graph_replayed_sweeps_equal_eager_sweeps(gpu_lib, precision, n_min):
         out[graphs] = (X, info["iters"])
     assert np.array_equal(out[True][0], out[False][0]) and out[True][1] == out[False][1]
     s.close()
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_direct_mode_and_tolerance_trend(gpu_lib, precision):
+    """The compressed factorization used directly (no GMRES, max_iter < 0) at tol 1e-6, the
+    direct mode of the paper's tolerance study: the solution matches the FP64 oracle to
+    100 tol (complex128; 1e-3 with complex64 butterflies), and tightening tol from 1e-3 to
+    1e-6 reduces the direct solve's error at least tenfold."""
+    p = make_problem("helmholtz24")
+    x_or = oracle_solution(p)
+    prec = gpu_lib.BFMF_C128 if precision == "c128" else gpu_lib.BFMF_C64_MIXED
+    err = {}
+    for tol in (1e-3, 1e-6):
+        s = gpu_lib.Solver(0).analyze(p.rowptr, p.colind, p.values, dims=p.dims)
+        s.factor(tol=tol, n_min=256, batched=True, precision=prec)
+        X, info = s.solve(p.rhs, max_iter=-1)
+        assert info["iters"] == 0
+        err[tol] = np.linalg.norm(X - x_or) / np.linalg.norm(x_or)
+        res = mf.rel_residual(p.rowptr, p.colind, p.values, X, p.rhs).max()
+        assert abs(res - info["relres"]) <= 1e-3 * res + 1e-14, (res, info)
+        s.close()
+    bound = 1e-4 if precision == "c128" else 1e-3
+    assert err[1e-6] <= bound and err[1e-6] * 10 <= err[1e-3], err
