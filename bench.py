@@ -44,9 +44,21 @@ def parse():
     ap.add_argument("--gemm-tile", type=int, default=-1,
                     help="force one grouped-GEMM tile shape (0..5; -1: the autotuned choice per launch)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
-                    help="first run two streaming kernels of known size (an elementwise negation and a "
-                         "device copy, each reading and writing this many MiB) to scale HBM byte counters")
+                    help="profiling: measure the tile tables on a small problem, then run two streaming kernels "
+                         "of known size (an elementwise negation and a device copy, each reading and writing this "
+                         "many MiB) that scale HBM byte counters and mark where the workload's dispatches begin")
     return ap.parse_args()
+
+
+def prime_tile_tables(bfmf):
+    """A small compressed factorization in both precisions: the grouped-GEMM tile tables of this
+    device are measured here, so that a profile taken after it sees only the workload's launches."""
+    from workloads import helmholtz_7pt
+    rp, ci, v, _ = helmholtz_7pt((12, 12, 12), 0.05)
+    for prec in (bfmf.BFMF_C128, bfmf.BFMF_C64_MIXED):
+        s = bfmf.Solver(0).analyze(rp, ci, v, dims=(12, 12, 12), leaf_max=64, sep_leaf=16)
+        s.factor(tol=1e-3, n_min=40, batched=True, precision=prec)
+        s.close()
 
 
 def calibrate_copy(mib):
@@ -278,7 +290,8 @@ def main():
     from paper_2007_00202_amd import bfmf
     from workloads import make_problem, CONFIGS
 
-    if a.calibrate_copy_mib > 0:
+    if a.calibrate_copy_mib > 0:  # profiling: tile tables first, then the calibration kernels as a marker
+        prime_tile_tables(bfmf)
         calibrate_copy(a.calibrate_copy_mib)
     if a.gemm_tile >= 0:
         bfmf.bfmf_set_gemm_tile(a.gemm_tile)

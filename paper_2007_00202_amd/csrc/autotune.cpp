@@ -18,6 +18,7 @@
 #include <limits>
 #include <map>
 #include <mutex>
+#include <string>
 
 #include "context.hpp"
 #include "kernels/kernels.hpp"
@@ -157,11 +158,57 @@ void build_table(Table& t, hipStream_t s) {
   t.ready = true;
 }
 
+// BFMF_TILE_TABLE=path keeps the measured table in path.<bytes per complex entry>: a process finds the
+// table there instead of measuring it (so that several processes, e.g. a benchmark and its profiled
+// reruns, choose the same shapes); a missing or mismatched file is measured and written.
+struct TableFile {
+  char magic[8];
+  int32_t cfgs, nm, nn, nk, esz, pad;
+  double us[GEMM_CFGS][NM][NN][NK];
+};
+
+bool load_table(Table& t, const std::string& path, int esz) {
+  FILE* f = std::fopen(path.c_str(), "rb");
+  if (!f) return false;
+  TableFile tf;
+  const bool ok = std::fread(&tf, sizeof(tf), 1, f) == 1 && std::memcmp(tf.magic, "bfmftile", 8) == 0 &&
+                  tf.cfgs == GEMM_CFGS && tf.nm == NM && tf.nn == NN && tf.nk == NK && tf.esz == esz;
+  std::fclose(f);
+  if (!ok) return false;
+  std::memcpy(t.us, tf.us, sizeof(t.us));
+  t.ready = true;
+  return true;
+}
+
+void save_table(const Table& t, const std::string& path, int esz) {
+  TableFile tf;
+  std::memset(&tf, 0, sizeof(tf));
+  std::memcpy(tf.magic, "bfmftile", 8);
+  tf.cfgs = GEMM_CFGS;
+  tf.nm = NM;
+  tf.nn = NN;
+  tf.nk = NK;
+  tf.esz = esz;
+  std::memcpy(tf.us, t.us, sizeof(t.us));
+  if (FILE* f = std::fopen(path.c_str(), "wb")) {
+    (void)std::fwrite(&tf, sizeof(tf), 1, f);
+    std::fclose(f);
+  }
+}
+
 template <class T>
 const Table& table_for(int device, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_mu);
   Table& t = g_tables[{device, (int)sizeof(T)}];
-  if (!t.ready) build_table<T>(t, s);
+  if (!t.ready) {
+    const char* env = std::getenv("BFMF_TILE_TABLE");
+    const int esz = (int)(2 * sizeof(T));
+    const std::string path = env ? std::string(env) + "." + std::to_string(esz) : std::string();
+    if (path.empty() || !load_table(t, path, esz)) {
+      build_table<T>(t, s);
+      if (!path.empty()) save_table(t, path, esz);
+    }
+  }
   return t;
 }
 
