@@ -45,7 +45,7 @@ def _sampled_fronts(od):
     return pick(leaves) + pick(parents)
 
 
-@pytest.mark.parametrize("name", ["helmholtz100", "helmholtz128grf", "maxwell64"])
+@pytest.mark.parametrize("name", ["helmholtz100", "helmholtz128grf", "maxwell64", "acoustic64"])
 def test_full_size_workload(gpu_lib, name):
     p = make_problem(name)
     print(f"\n[fullsize] {name}: N={p.n} nrhs={p.rhs.shape[1]}", flush=True)

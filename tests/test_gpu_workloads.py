@@ -1,6 +1,7 @@
 """GPU parity on the other workload shapes: the Yee curl-curl operator
-(indefinite, piecewise permittivity, edge nested dissection) and the
-Helmholtz operator with a heterogeneous Gaussian-random-field velocity.
+(indefinite, piecewise permittivity, edge nested dissection), the Helmholtz
+operator with a heterogeneous Gaussian-random-field velocity, and the
+27-point visco-acoustic operator with absorbing layers.
 
 Compressed fronts in both precisions against the exact FP64 oracle: the
 GMRES solution within 10 tol and a true residual at most 1e-3."""
@@ -74,3 +75,49 @@ def test_poisson_compressed(gpu_lib):
         res = mf.rel_residual(p.rowptr, p.colind, p.values, X, p.rhs).max()
         assert info["status"] == 0 and err <= 1e-2 and res <= 1e-3, (name, err, res, info)
         s.close()
+
+
+def _acoustic_small(n, pml):
+    from workloads import acoustic_27pt, grf_velocity
+    dims = (n, n, n)
+    c = grf_velocity(dims, rng_for("test", "coef", (n, pml)))
+    rp, ci, v, _ = acoustic_27pt(dims, c=c, pml=pml)
+    N = rp.shape[0] - 1
+    rng = rng_for("test", "rhs", (n, pml))
+    B = np.zeros((N, 3), dtype=np.complex128)
+    B[rng.choice(N, 3, replace=False), np.arange(3)] = 1.0
+    return dims, rp, ci, v, B
+
+
+def test_acoustic27_exact_matches_oracle(gpu_lib):
+    """27-point visco-acoustic operator with absorbing layers, no compression:
+    the GPU's multifrontal solve equals the oracle's (Alg. 1) to rounding."""
+    dims, rp, ci, v, B = _acoustic_small(16, 3)
+    od = nd.nd_grid(dims, leaf_max=64, sep_leaf=32)
+    x_or = mf.solve(mf.factor(rp, ci, v, od), B)
+    s = gpu_lib.Solver(0).analyze(rp, ci, v, dims=dims, leaf_max=64, sep_leaf=32)
+    s.factor(tol=1e-3, n_min=1 << 30, batched=True, precision=gpu_lib.BFMF_C128)
+    assert s.stats()["compressed_fronts"] == 0
+    X, info = s.solve(B, true_rtol=1e-10)
+    assert info["status"] == 0
+    assert np.linalg.norm(X - x_or) <= 1e-10 * np.linalg.norm(x_or)
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_acoustic27_compressed(gpu_lib, precision):
+    """Compressed separator fronts on the 27-point operator (GRF velocity, 4
+    absorbing layers per face) against the exact FP64 oracle."""
+    dims, rp, ci, v, B = _acoustic_small(20, 4)
+    od = nd.nd_grid(dims, leaf_max=64, sep_leaf=32)
+    x_or = mf.solve(mf.factor(rp, ci, v, od), B)
+    s = gpu_lib.Solver(0).analyze(rp, ci, v, dims=dims, leaf_max=64, sep_leaf=32)
+    prec = gpu_lib.BFMF_C128 if precision == "c128" else gpu_lib.BFMF_C64_MIXED
+    s.factor(tol=1e-3, n_min=100, batched=True, precision=prec)
+    st = s.stats()
+    assert st["compressed_fronts"] >= 3
+    X, info = s.solve(B, true_rtol=1e-3)
+    err = np.linalg.norm(X - x_or) / np.linalg.norm(x_or)
+    res = mf.rel_residual(rp, ci, v, X, B).max()
+    assert info["status"] == 0 and err <= 1e-2 and res <= 1e-3, (err, res, info, st["compressed_fronts"])
+    s.close()

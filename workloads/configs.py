@@ -4,13 +4,15 @@ The paper's own experiments use a 27-point staggered stencil with PML, the
 Marmousi2 model and a Nedelec finite-element mesh; none of those inputs are
 available, so these synthetic problems of the same structure stand in for
 them (3D cube, planar nested-dissection separators, point-source
-excitations, heterogeneous velocity, indefinite curl-curl).
+excitations, heterogeneous velocity, indefinite curl-curl, and a 27-point
+visco-acoustic stencil with absorbing layers derived here).
 """
 from dataclasses import dataclass, field
 import numpy as np
 
 from .seeds import rng_for
 from .helmholtz import helmholtz_7pt, grf_velocity
+from .acoustic import acoustic_27pt
 from .maxwell import yee_curlcurl, block_permittivity
 from .rhs import center_source_with_noise, point_sources, random_edge_dipoles
 
@@ -46,6 +48,12 @@ CONFIGS = {
     # high frequency, the first comparison workload after the Helmholtz runs
     "poisson100": dict(kind="grid", n=100, delta=0.0, nrhs=8, rhs="points", omega=0.0,
                        n_min=1024, tol=1e-3, precision="c64", samples=64),
+    # visco-acoustic 27-point stencil, 64^3 nodes including 8 absorbing layers per face, GRF
+    # velocity in [1, 2], q = 1e4 (the paper's heterogeneous-media setting), 8 points per
+    # wavelength at the slowest velocity, 8 point sources
+    "acoustic64": dict(kind="grid", op="acoustic27", n=64, delta=0.0, nrhs=8, rhs="points",
+                       n_min=1024, tol=1e-3, precision="c64", samples=64, grf=True, q=1e4, pml=8,
+                       sep_leaf=128),
     # Yee curl-curl 64^3 cells, eps on 8^3 blocks in U[1,4], delta 0.03, 16 RHS
     "maxwell64": dict(kind="yee", n=64, delta=0.03, nrhs=16, rhs="dipoles",
                       n_min=1024, tol=1e-3, precision="c64", samples=64, sep_leaf=128),
@@ -76,7 +84,10 @@ def make_problem(name, n=None, nrhs=None, delta=None, grf=None, config_id=None,
         c = None
         if cfg.get("grf"):
             c = grf_velocity(dims, rng_for(seed_cfg, "coef"))
-        rowptr, colind, values, meta = helmholtz_7pt(dims, cfg["delta"], c=c, omega=omega)
+        if cfg.get("op") == "acoustic27":
+            rowptr, colind, values, meta = acoustic_27pt(dims, c=c, q=cfg["q"], pml=cfg["pml"], omega=omega)
+        else:
+            rowptr, colind, values, meta = helmholtz_7pt(dims, cfg["delta"], c=c, omega=omega)
         N = nn ** 3
         if cfg["rhs"] == "center_noise":
             b = center_source_with_noise(dims, rng_for(seed_cfg, "rhs"))

@@ -15,6 +15,7 @@ CONFIG_IDS = {
     "maxwell64": 4,       # Yee curl-curl on 64^3 cells
     "serving": 5,         # three resident factorizations
     "poisson100": 6,      # 3D Poisson, omega = 0
+    "acoustic64": 7,      # 27-point visco-acoustic stencil with absorbing layers
     "test": 99,           # small grids used by the test-suite
 }
 
