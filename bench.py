@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean request arrivals per second")
     ap.add_argument("--sep-leaf", type=int, default=None,
                     help="separators are bisected down to this many nodes (HOD-BF leaves); default: the workload's")
+    ap.add_argument("--parallel-levels", type=int, default=0,
+                    help="separator variant: the top levels of the dissection cut across one axis (parallel planes)")
     ap.add_argument("--direct", action="store_true",
                     help="direct mode: X = M^-1 B from the factorization, no GMRES (use with a tight --tol)")
     ap.add_argument("--gemm-tile", type=int, default=-1,
@@ -77,13 +79,13 @@ def calibrate_copy(mib):
     print(f"[bench] calibration kernels: {mib} MiB read + {mib} MiB written each", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(prob, budget_s, nrhs):
+def cpu_baseline(prob, budget_s, nrhs, parallel_levels=0):
     """Oracle (NumPy/SciPy FP64) factorization of the same workload, stopped
     after about budget_s seconds of fronts in postorder; scaled to the whole
     factorization by algorithmic flops, plus the sampled solve cost."""
     from oracle import nd, multifrontal as mf
     from oracle.symbolic import symbolic
-    od = nd.nd_grid(prob.dims, leaf_max=512, sep_leaf=64)
+    od = nd.nd_grid(prob.dims, leaf_max=512, sep_leaf=64, parallel_levels=parallel_levels)
     sym = symbolic(prob.rowptr, prob.colind, od)
     total = sum(mf.front_flops(od, sym, f) for f in range(od.nfronts))
     t0 = time.perf_counter()
@@ -314,7 +316,8 @@ def main():
     precision = a.precision or cfg["precision"]
     nrhs = prob.rhs.shape[1]
     sep_leaf = a.sep_leaf or cfg.get("sep_leaf", 64)
-    s = bfmf.Solver(0).analyze(prob.rowptr, prob.colind, prob.values, dims=prob.dims, sep_leaf=sep_leaf)
+    s = bfmf.Solver(0).analyze(prob.rowptr, prob.colind, prob.values, dims=prob.dims, sep_leaf=sep_leaf,
+                               parallel_levels=a.parallel_levels)
     dB = torch.from_numpy(np.ascontiguousarray(prob.rhs.T)).to("cuda")  # column-major (N, nrhs)
     dX = torch.zeros_like(dB)
     r = run_form(bfmf, s, prob, nrhs, dB, dX, a.steps, a.warmup, a.form, precision, n_min, tol, direct=a.direct)
@@ -330,6 +333,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{a.config}: {operator_label(cfg)} {prob.dims[0]}^3 (N={prob.n}), {nrhs} RHS",
                    "form": a.form, "n_min": n_min, "tol": tol, "precision": precision, "sep_leaf": sep_leaf,
+                   "parallel_levels": a.parallel_levels,
                    "solver": "direct" if a.direct else "gmres"},
         "factor_s": r["factor_s"], "solve_s": r["solve_s"], "solve_rhs_per_s": r["solve_rhs_per_s"],
         "gmres_iters": r["gmres_iters"], "relres_max": r["relres_max"],
@@ -348,7 +352,7 @@ def main():
     if not a.no_serve:
         out["serving"] = run_serving(bfmf, a.serve_seconds, a.serve_rate, 64, precision)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, a.cpu_baseline_seconds, nrhs)
+        out["cpu_baseline"] = cpu_baseline(prob, a.cpu_baseline_seconds, nrhs, a.parallel_levels)
     print(json.dumps(out))
 
 

@@ -63,13 +63,20 @@ enum { BFMF_HOST = 0, BFMF_DEVICE = 1 };
  *       holds the doubled coordinate of edge i along axis d (one odd entry).
  * sep_leaf: leaf size of the recursive separator bisection that defines the
  *       HOD-BF tree of F11 and the permutation P-hat (Sec. 5.1); also the leaf
- *       size of the balanced tree on I^u. */
+ *       size of the balanced tree on I^u.
+ * parallel_levels (GRID only, default 0): separator variant of the Sec. 6
+ *       remark on high frequencies.  The boxes at the top parallel_levels
+ *       levels of the tree are cut across the grid's longest axis (while its
+ *       extent in the box is at least 3), so those separators are parallel
+ *       planes: F12/F21 of their fronts couple well-separated planes.  E_INVAL
+ *       if negative, or nonzero with YEE. */
 typedef struct {
     int32_t kind;
     int32_t nx, ny, nz;
     const int32_t* coords;
     int32_t leaf_max; /* default 512 */
     int32_t sep_leaf; /* default 64 */
+    int32_t parallel_levels; /* default 0 */
 } bfmf_ordering;
 
 /* Numerical factorization options (Alg. 5; Sec. 3.1 for alpha and k_nn). */

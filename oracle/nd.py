@@ -84,10 +84,17 @@ def _bisect_tree(count_fn, emit_fn, split_fn, box, sep_leaf, nodes, base):
     return me
 
 
-def nd_grid(dims, leaf_max=512, sep_leaf=64):
-    """Nested dissection of an nx*ny*nz node grid (natural index x fastest)."""
+def nd_grid(dims, leaf_max=512, sep_leaf=64, parallel_levels=0):
+    """Nested dissection of an nx*ny*nz node grid (natural index x fastest).
+
+    parallel_levels > 0 is the separator variant of the Sec. 6 remark on high
+    frequencies: a box at depth < parallel_levels is cut across the longest
+    axis of the whole grid (while the box's extent there is at least 3), so
+    the separators of the top levels are parallel planes.
+    """
     nx, ny, nz = dims
     od = Ordering(nx * ny * nz)
+    fixed = int(np.argmax([nx, ny, nz]))
 
     def count(box):
         lo, hi = box
@@ -105,7 +112,7 @@ def nd_grid(dims, leaf_max=512, sep_leaf=64):
         lo2 = list(lo); lo2[a] = lo[a] + first
         return (list(lo), hi1), (lo2, list(hi))
 
-    def rec(lo, hi):
+    def rec(lo, hi, depth):
         vol = count((lo, hi))
         if vol == 0:
             return None
@@ -119,10 +126,12 @@ def nd_grid(dims, leaf_max=512, sep_leaf=64):
             return f
         ext = [hi[d] - lo[d] for d in range(3)]
         a = int(np.argmax(ext))
+        if depth < parallel_levels and ext[fixed] >= 3:
+            a = fixed
         p = lo[a] + ext[a] // 2
         hl = list(hi); hl[a] = p
         lr = list(lo); lr[a] = p + 1
-        kids = [c for c in (rec(list(lo), hl), rec(lr, list(hi))) if c is not None]
+        kids = [c for c in (rec(list(lo), hl, depth + 1), rec(lr, list(hi), depth + 1)) if c is not None]
         slo = list(lo); slo[a] = p
         shi = list(hi); shi[a] = p + 1
         beg = len(od.perm)
@@ -136,7 +145,7 @@ def nd_grid(dims, leaf_max=512, sep_leaf=64):
             od.parent[c] = f
         return f
 
-    rec([0, 0, 0], [nx, ny, nz])
+    rec([0, 0, 0], [nx, ny, nz], 0)
     return od.finish()
 
 

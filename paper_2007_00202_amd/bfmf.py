@@ -33,7 +33,8 @@ BFMF_HOST, BFMF_DEVICE = 0, 1
 
 class bfmf_ordering(C.Structure):
     _fields_ = [("kind", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
-                ("coords", C.POINTER(C.c_int32)), ("leaf_max", C.c_int32), ("sep_leaf", C.c_int32)]
+                ("coords", C.POINTER(C.c_int32)), ("leaf_max", C.c_int32), ("sep_leaf", C.c_int32),
+                ("parallel_levels", C.c_int32)]
 
 
 class bfmf_factor_opts(C.Structure):
@@ -159,14 +160,14 @@ def bfmf_create(device=0, stream=None):
 
 
 def bfmf_analyze(h, rowptr, colind, values, kind=BFMF_ORD_GRID, dims=(0, 0, 0), coords=None,
-                 leaf_max=512, sep_leaf=64):
+                 leaf_max=512, sep_leaf=64, parallel_levels=0):
     rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
     colind = np.ascontiguousarray(colind, dtype=np.int32)
     vals = None if values is None else np.ascontiguousarray(values, dtype=np.complex128)
     cc = None if coords is None else np.ascontiguousarray(coords, dtype=np.int32)
     o = bfmf_ordering(kind, dims[0], dims[1], dims[2],
                       cc.ctypes.data_as(C.POINTER(C.c_int32)) if cc is not None else None,
-                      leaf_max, sep_leaf)
+                      leaf_max, sep_leaf, parallel_levels)
     _check(h, _lib.bfmf_analyze(h, rowptr.shape[0] - 1, _ptr(rowptr), _ptr(colind), _ptr(vals), C.byref(o)))
 
 
@@ -348,11 +349,14 @@ class Solver:
         self.h = bfmf_create(device, stream)
         self.n = None
 
-    def analyze(self, rowptr, colind, values, dims=None, coords=None, cells=None, leaf_max=512, sep_leaf=64):
+    def analyze(self, rowptr, colind, values, dims=None, coords=None, cells=None, leaf_max=512, sep_leaf=64,
+                parallel_levels=0):
         if coords is not None:
-            bfmf_analyze(self.h, rowptr, colind, values, BFMF_ORD_YEE, (cells, 0, 0), coords, leaf_max, sep_leaf)
+            bfmf_analyze(self.h, rowptr, colind, values, BFMF_ORD_YEE, (cells, 0, 0), coords, leaf_max, sep_leaf,
+                         parallel_levels)
         else:
-            bfmf_analyze(self.h, rowptr, colind, values, BFMF_ORD_GRID, dims, None, leaf_max, sep_leaf)
+            bfmf_analyze(self.h, rowptr, colind, values, BFMF_ORD_GRID, dims, None, leaf_max, sep_leaf,
+                         parallel_levels)
         self.n = rowptr.shape[0] - 1
         return self
 

@@ -140,8 +140,9 @@ bfmf_status bfmf_analyze(bfmf_handle h, int64_t n, const int64_t* rowptr, const 
     bool ok;
     if (ord->kind == BFMF_ORD_GRID) {
       if ((int64_t)ord->nx * ord->ny * ord->nz != n) throw Error(BFMF_E_INVAL, "analyze: nx*ny*nz != n");
-      ok = nd_grid(ord->nx, ord->ny, ord->nz, leaf, sl, h->sym, err);
+      ok = nd_grid(ord->nx, ord->ny, ord->nz, leaf, sl, ord->parallel_levels, h->sym, err);
     } else if (ord->kind == BFMF_ORD_YEE) {
+      if (ord->parallel_levels != 0) throw Error(BFMF_E_INVAL, "analyze: parallel_levels applies to GRID orderings");
       ok = nd_yee(ord->nx, n, ord->coords, leaf, sl, h->sym, err);
     } else {
       throw Error(BFMF_E_INVAL, "analyze: unknown ordering kind");

@@ -8,6 +8,12 @@
 // A separator is ordered by recursive bisection along its longest in-plane
 // extent with ceil(ext/2) planes in the first half (Sec. 5.1, P-hat), down to
 // sep_leaf nodes, natural order (x fastest) inside a leaf.
+//
+// Separator variant (the remark of Sec. 6 on ranks of F12/F21 at high
+// frequency): a box at depth d < parallel_levels of the dissection tree is
+// cut across the axis of largest extent of the whole grid instead of its
+// own (while that extent is at least 3), so the top levels' separators are
+// parallel planes and never cross.
 #include "analyze.hpp"
 
 #include <algorithm>
@@ -90,12 +96,18 @@ int32_t bisect(const R& r, int32_t sep_leaf, C& count, E& emit, S& split, std::v
 
 }  // namespace
 
-bool nd_grid(int32_t nx, int32_t ny, int32_t nz, int32_t leaf_max, int32_t sep_leaf, Symbolic& s,
-             std::string& err) {
+bool nd_grid(int32_t nx, int32_t ny, int32_t nz, int32_t leaf_max, int32_t sep_leaf, int32_t parallel_levels,
+             Symbolic& s, std::string& err) {
   if (nx <= 0 || ny <= 0 || nz <= 0 || leaf_max <= 0 || sep_leaf <= 0) {
     err = "nd_grid: dimensions and leaf sizes must be positive";
     return false;
   }
+  if (parallel_levels < 0) {
+    err = "nd_grid: parallel_levels must be >= 0";
+    return false;
+  }
+  const int64_t gext[3] = {nx, ny, nz};
+  const int fixed_axis = argmax3(gext);
   s = Symbolic();
   s.n = (int64_t)nx * ny * nz;
   s.perm.reserve(s.n);
@@ -121,7 +133,7 @@ bool nd_grid(int32_t nx, int32_t ny, int32_t nz, int32_t leaf_max, int32_t sep_l
     b2.lo[a] = b.lo[a] + first;
   };
 
-  std::function<int32_t(const Box&)> rec = [&](const Box& b) -> int32_t {
+  std::function<int32_t(const Box&, int32_t)> rec = [&](const Box& b, int32_t depth) -> int32_t {
     int64_t vol = count(b);
     if (vol == 0) return -1;
     if (vol <= leaf_max) {
@@ -131,6 +143,7 @@ bool nd_grid(int32_t nx, int32_t ny, int32_t nz, int32_t leaf_max, int32_t sep_l
     }
     int64_t ext[3] = {b.hi[0] - b.lo[0], b.hi[1] - b.lo[1], b.hi[2] - b.lo[2]};
     int a = argmax3(ext);
+    if (depth < parallel_levels && ext[fixed_axis] >= 3) a = fixed_axis;
     int32_t p = b.lo[a] + (int32_t)(ext[a] / 2);
     Box left = b, right = b, sep = b;
     left.hi[a] = p;
@@ -138,9 +151,9 @@ bool nd_grid(int32_t nx, int32_t ny, int32_t nz, int32_t leaf_max, int32_t sep_l
     sep.lo[a] = p;
     sep.hi[a] = p + 1;
     std::vector<int32_t> ch;
-    int32_t c1 = rec(left);
+    int32_t c1 = rec(left, depth + 1);
     if (c1 >= 0) ch.push_back(c1);
-    int32_t c2 = rec(right);
+    int32_t c2 = rec(right, depth + 1);
     if (c2 >= 0) ch.push_back(c2);
     int64_t beg = (int64_t)s.perm.size();
     std::vector<TreeNode> nodes;
@@ -148,7 +161,7 @@ bool nd_grid(int32_t nx, int32_t ny, int32_t nz, int32_t leaf_max, int32_t sep_l
     bisect(sep, sep_leaf, count, emit, split, nodes, base);
     return fb.add_front(beg, false, ch, nodes);
   };
-  rec(Box{{0, 0, 0}, {nx, ny, nz}});
+  rec(Box{{0, 0, 0}, {nx, ny, nz}}, 0);
   fb.finish();
   return true;
 }

@@ -35,8 +35,11 @@ struct Symbolic {
 };
 
 // Geometric nested dissection of an nx*ny*nz node grid (natural index
-// x + nx*(y + ny*z)).  Returns false with a message on bad arguments.
-bool nd_grid(int32_t nx, int32_t ny, int32_t nz, int32_t leaf_max, int32_t sep_leaf,
+// x + nx*(y + ny*z)).  The boxes at the top `parallel_levels` levels of the
+// tree are all cut across the grid's longest axis, so their separators are
+// parallel planes (the separator variant of the Sec. 6 remark on high
+// frequencies).  Returns false with a message on bad arguments.
+bool nd_grid(int32_t nx, int32_t ny, int32_t nz, int32_t leaf_max, int32_t sep_leaf, int32_t parallel_levels,
              Symbolic& s, std::string& err);
 
 // Nested dissection of the interior edges of an ncell^3 Yee grid given the

@@ -613,7 +613,8 @@ struct IdLevel {
     int64_t po = 0;
     const bool gram = rt.tol >= 1e-4;  // Gram variant for tolerances where eps p / tol^2 is negligible
     for (size_t i = 0; i < nb; ++i) {
-      if (p[i] > GRAM_MAXP || q[i] > 2048)  // both ID kernels take up to 1024 columns and 2048 rows
+      // the Gram kernel takes up to 2048 columns, the Householder kernel 1024; both up to 2048 rows
+      if (p[i] > (gram ? GRAM_MAXP : CPQR_MAXP) || q[i] > 2048)
         throw Error(BFMF_E_INVAL, "ID block too large (" + std::to_string(q[i]) + " x " + std::to_string(p[i]) + ")");
       const int maxrank = std::max(1, std::min(p[i], q[i]));
       void* Tb = rt.scratch.take((size_t)maxrank * std::max(p[i], 1) * sizeof(cplx<double>));
@@ -660,12 +661,14 @@ struct IdLevel {
     const auto t_id0 = std::chrono::steady_clock::now();
     KernelTimer& tm = rt.c->timer;
     const int tk = tm.want(K_ID) ? tm.begin(s) : -1;
-    int lds_entries = 0;  // the largest R (kmax x p) that fits the LDS budget sizes the launch's LDS
     int maxp = 16;
+    for (const IdTask& t : tasks) maxp = std::max(maxp, (t.p + 15) / 16 * 16);
+    // the largest R (kmax x p) that fits the LDS left beside the per-column state sizes the launch's LDS
+    const int64_t lds_cap = std::min<int64_t>(GRAM_LDS_MAX, (int64_t)(GRAM_LDS_BYTES - gram_aux_bytes(maxp)) / 16);
+    int lds_entries = 0;
     for (const IdTask& t : tasks) {
       const int64_t e = (int64_t)std::min(t.maxrank, t.p) * t.p;
-      if (e <= GRAM_LDS_MAX) lds_entries = std::max<int>(lds_entries, (int)e);
-      maxp = std::max(maxp, (t.p + 15) / 16 * 16);
+      if (e <= lds_cap) lds_entries = std::max<int>(lds_entries, (int)e);
     }
     if (gram)
       chk(launch_gram_id<double>(dt, (int)nb, rt.tol, lds_entries, maxp, s), "gram id");

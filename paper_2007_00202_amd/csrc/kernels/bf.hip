@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void grouped_gemm_skinny_kernel(const GTask* _
 // remaining norm (first maximum); the factorization stops at the first
 // |R_kk| <= tol |R_00| (rank k) or at maxrank.  Householder vectors live in
 // LDS; one wave applies a reflector to one column at a time.
-constexpr int ID_MAXP = 1024;  // columns of a Householder ID block (the same limit as the Gram variant)
+constexpr int ID_MAXP = CPQR_MAXP;  // columns of a Householder ID block
 constexpr int ID_MAXQ = 2048;
 
 template <class T>
@@ -945,6 +945,7 @@ hipError_t launch_gram_id(const IdTask* d_tasks, int ntasks, double tol, int lds
       sizeof(cplx<T>) != 16)
     return hipErrorInvalidValue;
   const size_t bytes = gram_aux_bytes(maxp) + (size_t)lds_entries * sizeof(cplx<T>);
+  if (bytes > GRAM_LDS_BYTES) return hipErrorInvalidValue;
   hipLaunchKernelGGL((gram_id_kernel<T>), dim3(ntasks), dim3(256), bytes, s, d_tasks, tol, lds_entries, maxp);
   return hipGetLastError();
 }

@@ -105,7 +105,9 @@ hipError_t launch_cpqr_id(const IdTask* d_tasks, int ntasks, double tol, hipStre
 // lds_entries complex entries of dynamic LDS per workgroup where min(maxrank, p) * p fits, else
 // in IdTask.R
 constexpr int GRAM_LDS_MAX = 4096;
-constexpr int GRAM_MAXP = 1024;  // most columns of an ID block (both kernels)
+constexpr int GRAM_MAXP = 2048;  // most columns of a Gram ID block
+constexpr int CPQR_MAXP = 1024;  // most columns of a Householder ID block
+constexpr size_t GRAM_LDS_BYTES = 159 * 1024;  // the dynamic LDS of a Gram ID launch at most (one CU's 160 KiB, less the static part)
 // dynamic LDS of a Gram ID launch whose blocks have at most maxp columns (maxp a multiple of 16): per-column
 // state (pivot search, selection, permutation: 20 bytes; two complex<double> rows: 32 bytes), then the R rows
 __host__ __device__ inline size_t gram_aux_bytes(int maxp) { return (size_t)maxp * 52; }

@@ -125,3 +125,20 @@ def test_every_gemm_tile_shape_gives_the_same_result(gpu_lib):
         gpu_lib.bfmf_set_gemm_tile(-1)
     with pytest.raises(gpu_lib.BfmfError):
         gpu_lib.bfmf_set_gemm_tile(6)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_interpolative_decomposition_over_1296_columns(gpu_lib, method):
+    """The Gram ID kernel takes blocks of up to 2048 columns: a 1296 x 1296
+    Green's-function block compressed with L = 0 (one ID over all 1296
+    columns, tol 1e-3) by entry evaluation and by random products."""
+    K = green_planes(36, 2, 0.5)
+    assert K.shape == (1296, 1296)
+    b, shape = gpu_lib.bfmf_bf_compress_dense(K, 0, 1e-3, method=method, samples=48, seed=11)
+    try:
+        D = decompress(gpu_lib, b, shape)
+        err = np.linalg.norm(K - D) / np.linalg.norm(K)
+        assert err <= 1e-2, err
+        assert gpu_lib.bfmf_bf_info(b)["max_rank"] < 400
+    finally:
+        gpu_lib.bfmf_bf_destroy(b)

@@ -121,3 +121,26 @@ def test_acoustic27_compressed(gpu_lib, precision):
     res = mf.rel_residual(rp, ci, v, X, B).max()
     assert info["status"] == 0 and err <= 1e-2 and res <= 1e-3, (err, res, info, st["compressed_fronts"])
     s.close()
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_parallel_separators_compressed(gpu_lib, precision):
+    """Separator variant (Sec. 6 remark): the top two levels of the dissection
+    cut across one axis; the compressed solve on that ordering against the
+    exact FP64 oracle on the same ordering."""
+    p = make_problem("helmholtz100", n=20, nrhs=2)
+    od = nd.nd_grid(p.dims, leaf_max=64, sep_leaf=32, parallel_levels=2)
+    x_or = mf.solve(mf.factor(p.rowptr, p.colind, p.values, od), p.rhs)
+    s = gpu_lib.Solver(0).analyze(p.rowptr, p.colind, p.values, dims=p.dims, leaf_max=64, sep_leaf=32,
+                                  parallel_levels=2)
+    sy = gpu_lib.bfmf_get_symbolic(s.h)
+    assert np.array_equal(sy["perm"], od.perm)
+    prec = gpu_lib.BFMF_C128 if precision == "c128" else gpu_lib.BFMF_C64_MIXED
+    s.factor(tol=1e-3, n_min=100, batched=True, precision=prec)
+    st = s.stats()
+    assert st["compressed_fronts"] >= 3
+    X, info = s.solve(p.rhs, true_rtol=1e-3)
+    err = np.linalg.norm(X - x_or) / np.linalg.norm(x_or)
+    res = mf.rel_residual(p.rowptr, p.colind, p.values, X, p.rhs).max()
+    assert info["status"] == 0 and err <= 1e-2 and res <= 1e-3, (err, res, info)
+    s.close()
