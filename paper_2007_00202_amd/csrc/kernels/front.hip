@@ -174,6 +174,191 @@ __global__ __launch_bounds__(256) void panel_kernel(const FrontDesc* __restrict_
   }
 }
 
+// The same factorization of a panel of at most PR_ROWS rows, held in registers.
+// 512 threads; thread t owns panel rows t and t + 512 (relative to k0) of a
+// half-panel of up to 16 columns at a time, rotated so that the current column
+// is always register slot 0 (no register index depends on the column).  A
+// finished column goes to memory at once; later row interchanges are applied
+// to the finished columns in memory (thread c swaps column c).
+//   left half : columns k0 .. k0+15 factored column by column as above;
+//   right half: loaded with all of the left half's row interchanges applied
+//               (each row read from its source position), then the left
+//               half's rank-1 updates in column order (the interchanges of a
+//               later column only exchange rows below the current one, so
+//               every entry receives the same operations in the same order as
+//               in panel_kernel), then factored like the left half.
+// Every arithmetic operation is panel_kernel's in the same order, so the two
+// kernels give identical factors and pivots.  A column costs two barriers: the
+// pivot exchange, then the pivot-row broadcast (double-buffered LDS slots).
+constexpr int PR_THREADS = 512, PR_ROWS = 2 * PR_THREADS, PR_HALF = 16;
+
+template <class T>
+__global__ __launch_bounds__(PR_THREADS) void panel_reg_kernel(const FrontDesc* __restrict__ fds, int k0, int kb,
+                                                               int* __restrict__ status) {
+  const FrontDesc& fd = fds[blockIdx.x];
+  const int ns = fd.ns, n = fd.n;
+  if (k0 >= ns) return;
+  const int jb = min(kb, ns - k0);
+  const int m = ns - k0;  // panel rows; the launcher guarantees m <= PR_ROWS
+  cplx<T>* F = (cplx<T>*)fd.F;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ T red_v[2][PR_THREADS / 64];
+  __shared__ int red_i[2][PR_THREADS / 64];
+  __shared__ cplx<T> urow[2][PR_HALF];  // the step's pivot row (slots of the current half)
+  __shared__ cplx<T> jrow[2][PR_HALF];  // the row it replaces
+  __shared__ int pl[PR_HALF];           // the left half's pivots (relative rows)
+  const int rowq[2] = {tid, tid + PR_THREADS};
+  cplx<T> a[2][PR_HALF];
+  int st = 0;  // LDS slot parity, advanced after every step that uses a slot
+
+  auto at = [&](int r, int c) __attribute__((always_inline)) -> cplx<T>* {
+    return F + (int64_t)(k0 + r) + (int64_t)(k0 + c) * n;
+  };
+  // column by column LU of the half-panel in registers (panel columns c0 .. c0+w-1)
+  auto factor_half = [&](int c0, int w) __attribute__((always_inline)) {
+    for (int jj = 0; jj < w; ++jj) {
+      const int cr = c0 + jj;  // relative pivot row / column
+      const int buf = st & 1;
+      T best = -1;
+      int bi = m;
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        if (rowq[q] >= cr && rowq[q] < m) {
+          const T v = cabs1(a[q][0]);
+          if (v > best) {  // rows in ascending order: the first on ties is kept
+            best = v;
+            bi = rowq[q];
+          }
+        }
+      for (int o = 32; o > 0; o >>= 1) {
+        const T ov = __shfl_xor(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ov > best || (ov == best && oi < bi)) {
+          best = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        red_v[buf][wave] = best;
+        red_i[buf][wave] = bi;
+      }
+      __syncthreads();
+      T pv = red_v[buf][0];
+      int p = red_i[buf][0];
+      for (int w2 = 1; w2 < PR_THREADS / 64; ++w2) {
+        const T ov = red_v[buf][w2];
+        const int oi = red_i[buf][w2];
+        if (ov > pv || (ov == pv && oi < p)) {
+          pv = ov;
+          p = oi;
+        }
+      }
+      const bool singular = !(pv > 0) || p >= m;
+      if (singular) p = cr;
+      if (tid == 0) {
+        fd.piv[k0 + cr] = k0 + p;
+        if (c0 == 0) pl[jj] = p;
+        if (singular && atomicCAS(&status[0], 0, 1) == 0) {
+          status[1] = fd.front;
+          status[2] = k0 + cr;
+        }
+      }
+      // the pivot row (row p) and, on an interchange, row cr through LDS
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (rowq[q] == p)
+#pragma unroll
+          for (int c = 0; c < PR_HALF; ++c) urow[buf][c] = a[q][c];
+        if (p != cr && rowq[q] == cr)
+#pragma unroll
+          for (int c = 0; c < PR_HALF; ++c) jrow[buf][c] = a[q][c];
+      }
+      if (p != cr && tid < cr) {  // the interchange in the finished columns (in memory)
+        cplx<T>* x = at(cr, tid);
+        cplx<T>* y = at(p, tid);
+        const cplx<T> t = *x;
+        *x = *y;
+        *y = t;
+      }
+      __syncthreads();
+      const cplx<T> d = urow[buf][0];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (p != cr) {
+          if (rowq[q] == cr) {
+#pragma unroll
+            for (int c = 0; c < PR_HALF; ++c) a[q][c] = urow[buf][c];
+          } else if (rowq[q] == p) {
+#pragma unroll
+            for (int c = 0; c < PR_HALF; ++c) a[q][c] = jrow[buf][c];
+          }
+        }
+        if (rowq[q] > cr && rowq[q] < m) {
+          cplx<T> l = a[q][0];
+          if (!singular) {
+            l = cdiv(l, d);
+            a[q][0] = l;
+          }
+#pragma unroll
+          for (int c = 1; c < PR_HALF; ++c)
+            if (c < w - jj) a[q][c] = csub(a[q][c], cmul(l, urow[buf][c]));
+        }
+        if (rowq[q] < m) *at(rowq[q], cr) = a[q][0];  // column cr is final (interchanges aside)
+#pragma unroll
+        for (int c = 0; c + 1 < PR_HALF; ++c) a[q][c] = a[q][c + 1];
+      }
+      ++st;
+    }
+  };
+
+  const int w1 = min(jb, PR_HALF);
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int c = 0; c < PR_HALF; ++c) a[q][c] = (rowq[q] < m && c < w1) ? *at(rowq[q], c) : cplx<T>{0, 0};
+  factor_half(0, w1);
+  if (jb <= PR_HALF) return;
+  const int w2 = jb - PR_HALF;
+  __syncthreads();  // the left half is in memory and its pivots in LDS
+  // right half with the left half's interchanges applied: position r holds the row at position
+  // s_0(s_1(...s_15(r))), s_j the interchange of rows j and pl[j]
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    int src = rowq[q];
+    for (int j = PR_HALF - 1; j >= 0; --j) {
+      const int pj = pl[j];
+      if (src == j)
+        src = pj;
+      else if (src == pj)
+        src = j;
+    }
+#pragma unroll
+    for (int c = 0; c < PR_HALF; ++c)
+      a[q][c] = (rowq[q] < m && c < w2) ? *at(src, PR_HALF + c) : cplx<T>{0, 0};
+  }
+  __syncthreads();  // every thread has read the right half before any of it is written again
+  // the left half's rank-1 updates, in column order
+  for (int jj = 0; jj < PR_HALF; ++jj) {
+    const int buf = st & 1;
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      if (rowq[q] == jj)
+#pragma unroll
+        for (int c = 0; c < PR_HALF; ++c) urow[buf][c] = a[q][c];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      if (rowq[q] > jj && rowq[q] < m) {
+        const cplx<T> l = *at(rowq[q], jj);
+#pragma unroll
+        for (int c = 0; c < PR_HALF; ++c)
+          if (c < w2) a[q][c] = csub(a[q][c], cmul(l, urow[buf][c]));
+      }
+    ++st;
+  }
+  factor_half(PR_HALF, w2);
+}
+
 // Row interchanges of panel k0 applied to the columns outside the panel, rows
 // 0..ns-1 only (F21 rows are never swapped).
 template <class T>
@@ -333,8 +518,12 @@ hipError_t launch_partial_lu(const FrontDesc* d_fds, int nbatch, const int* h_n,
     maxns = h_ns[b] > maxns ? h_ns[b] : maxns;
     maxn = h_n[b] > maxn ? h_n[b] : maxn;
   }
+  static_assert(KB <= 2 * PR_HALF, "the register panel holds two half-panels");
   for (int k0 = 0; k0 < maxns; k0 += KB) {
-    hipLaunchKernelGGL((panel_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, k0, KB, d_status);
+    if (maxns - k0 <= PR_ROWS)  // every front's panel fits the register kernel
+      hipLaunchKernelGGL((panel_reg_kernel<T>), dim3(nbatch), dim3(PR_THREADS), 0, s, d_fds, k0, KB, d_status);
+    else
+      hipLaunchKernelGGL((panel_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, k0, KB, d_status);
     KCHECK(hipGetLastError());
     int ncols = maxn;  // upper bound on columns outside the panel
     hipLaunchKernelGGL((laswp_kernel<T>), dim3((ncols + 255) / 256, nbatch), dim3(256), 0, s, d_fds, k0, KB);
