@@ -601,7 +601,12 @@ __global__ __launch_bounds__(256) void philox_gauss_batch_kernel(const ProbeTask
 // ------------------------------------------------------------ small solves
 // X A = B for each task: A k x k (lda), B r x k (ldb, overwritten by X).
 // Gaussian elimination with partial pivoting on A^T, one workgroup per task,
-// A is destroyed.
+// A is destroyed.  Per column: the pivot (first row maximising |Re| + |Im|)
+// by wave shuffles and one exchange between the waves, the interchange, the
+// multipliers, then the trailing update of A^T and the same row operations
+// on B^T with every entry in parallel.  Back substitution by columns of the
+// triangle (x_c for all rows of B, then its contribution to the columns
+// before it), again every entry in parallel.
 template <class T>
 __global__ __launch_bounds__(256) void small_solve_right_kernel(const SolveTask* __restrict__ tasks) {
   const SolveTask& tk = tasks[blockIdx.x];
@@ -611,10 +616,11 @@ __global__ __launch_bounds__(256) void small_solve_right_kernel(const SolveTask*
   const int64_t lda = tk.lda, ldb = tk.ldb;
   // X A = B  <=>  A^T X^T = B^T.  Work on At(i, j) = A(j, i): rows of A^T are
   // columns of A.  Eliminate with row pivoting on A^T == column pivoting of A.
-  __shared__ double rv[256];
-  __shared__ int ri[256];
-  const int tid = threadIdx.x;
+  __shared__ double red_v[2][4];
+  __shared__ int red_i[2][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int c = 0; c < k; ++c) {
+    const int buf = c & 1;
     // pivot among At rows c..k-1 of column c: At(i, c) = A(c, i)
     double best = -1;
     int bi = c;
@@ -625,18 +631,26 @@ __global__ __launch_bounds__(256) void small_solve_right_kernel(const SolveTask*
         bi = i;
       }
     }
-    rv[tid] = best;
-    ri[tid] = bi;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s && (rv[tid + s] > rv[tid] || (rv[tid + s] == rv[tid] && ri[tid + s] < ri[tid]))) {
-        rv[tid] = rv[tid + s];
-        ri[tid] = ri[tid + s];
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
       }
-      __syncthreads();
     }
-    const int pr = ri[0];
+    if (lane == 0) {
+      red_v[buf][wave] = best;
+      red_i[buf][wave] = bi;
+    }
     __syncthreads();
+    double pv = red_v[buf][0];
+    int pr = red_i[buf][0];
+    for (int w = 1; w < 4; ++w)
+      if (red_v[buf][w] > pv || (red_v[buf][w] == pv && red_i[buf][w] < pr)) {
+        pv = red_v[buf][w];
+        pr = red_i[buf][w];
+      }
     if (pr != c) {  // swap At rows c and pr: columns c, pr of A; columns c, pr of B
       for (int j = tid; j < k; j += 256) {
         const cplx<T> t = A[j + (int64_t)c * lda];
@@ -652,28 +666,36 @@ __global__ __launch_bounds__(256) void small_solve_right_kernel(const SolveTask*
     __syncthreads();
     const cplx<T> d = A[c + (int64_t)c * lda];
     const bool ok = cabs1(d) > 0;
-    // eliminate At rows i > c: At(i, :) -= l At(c, :), l = At(i, c) / At(c, c)
-    for (int i = c + 1 + tid; i < k; i += 256) {
-      const cplx<T> l = ok ? cdiv(A[c + (int64_t)i * lda], d) : cplx<T>{0, 0};
-      for (int j = c + 1; j < k; ++j) A[j + (int64_t)i * lda] = csub(A[j + (int64_t)i * lda], cmul(l, A[j + (int64_t)c * lda]));
-      A[c + (int64_t)i * lda] = l;
-    }
+    // multipliers l_i = At(i, c) / At(c, c), kept in At(i, c)
+    for (int i = c + 1 + tid; i < k; i += 256)
+      A[c + (int64_t)i * lda] = ok ? cdiv(A[c + (int64_t)i * lda], d) : cplx<T>{0, 0};
     __syncthreads();
-    // same row operation on B^T: B(:, i) -= l B(:, c)
-    for (int e = tid; e < r * (k - c - 1); e += 256) {
+    // At(i, j) -= l_i At(c, j) for i, j > c, and B(:, i) -= l_i B(:, c)
+    const int kr = k - c - 1;
+    for (int e = tid; e < kr * kr; e += 256) {
+      const int i = c + 1 + e / kr, j = c + 1 + e % kr;
+      A[j + (int64_t)i * lda] = csub(A[j + (int64_t)i * lda], cmul(A[c + (int64_t)i * lda], A[j + (int64_t)c * lda]));
+    }
+    for (int e = tid; e < r * kr; e += 256) {
       const int row = e % r, i = c + 1 + e / r;
       B[row + (int64_t)i * ldb] = csub(B[row + (int64_t)i * ldb], cmul(A[c + (int64_t)i * lda], B[row + (int64_t)c * ldb]));
     }
     __syncthreads();
   }
-  // back substitution on the upper triangle of At, per row of B
-  for (int row = tid; row < r; row += 256) {
-    for (int c = k - 1; c >= 0; --c) {
-      cplx<T> s = B[row + (int64_t)c * ldb];
-      for (int j = c + 1; j < k; ++j) s = csub(s, cmul(A[j + (int64_t)c * lda], B[row + (int64_t)j * ldb]));
-      const cplx<T> d = A[c + (int64_t)c * lda];
-      B[row + (int64_t)c * ldb] = cabs1(d) > 0 ? cdiv(s, d) : cplx<T>{0, 0};
+  // back substitution on the upper triangle of At: x_c, then B(:, j) -= At(j, c) x_c for j < c
+  for (int c = k - 1; c >= 0; --c) {
+    const cplx<T> d = A[c + (int64_t)c * lda];
+    const bool ok = cabs1(d) > 0;
+    for (int row = tid; row < r; row += 256) {
+      const cplx<T> s = B[row + (int64_t)c * ldb];
+      B[row + (int64_t)c * ldb] = ok ? cdiv(s, d) : cplx<T>{0, 0};
     }
+    __syncthreads();
+    for (int e = tid; e < r * c; e += 256) {
+      const int row = e % r, j = e / r;
+      B[row + (int64_t)j * ldb] = csub(B[row + (int64_t)j * ldb], cmul(A[c + (int64_t)j * lda], B[row + (int64_t)c * ldb]));
+    }
+    __syncthreads();
   }
 }
 
