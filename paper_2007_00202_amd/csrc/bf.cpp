@@ -62,13 +62,18 @@ void Scratch::release(const Mark& m) {
 void* Scratch::take(size_t bytes) {
   bytes = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
   if (cur < 0 || chunks[cur]->top + bytes > chunks[cur]->b.bytes) {
-    // next chunk: reuse the one above the top if it is large enough
+    // next chunk: the chunks above the top hold nothing, so any of them that is large enough is
+    // moved to the next position; only when none is, a new chunk is inserted there (never freed:
+    // freeing device memory synchronizes the device)
     const size_t next = (size_t)(cur + 1);
-    if (next < chunks.size() && chunks[next]->b.bytes < bytes) chunks.erase(chunks.begin() + next, chunks.end());
-    if (next == chunks.size()) {
+    size_t fit = next;
+    while (fit < chunks.size() && chunks[fit]->b.bytes < bytes) ++fit;
+    if (fit < chunks.size()) {
+      std::swap(chunks[next], chunks[fit]);
+    } else {
       auto ch = std::make_unique<Chunk>();
       dev_alloc(ch->b, std::max(bytes, chunk_bytes));
-      chunks.push_back(std::move(ch));
+      chunks.insert(chunks.begin() + next, std::move(ch));
     }
     cur = (int)next;
     chunks[cur]->top = 0;

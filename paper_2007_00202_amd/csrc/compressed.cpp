@@ -2,6 +2,7 @@
 // BF_SMW), butterfly F12 / F21 by entry evaluation with graph-distance
 // proxies (Alg. 2, Sec. 5.2), the Schur update S by randomized construction
 // (Sec. 3.3), the contribution block, and the compressed sweeps.
+#include "host_pool.hpp"
 #include "compressed.hpp"
 
 #include <algorithm>
@@ -989,11 +990,18 @@ static void factor_level(CompState<T>* st, Context& c, const std::vector<int>& f
     }
     h.by_level.assign(h.max_level + 1, {});
     for (int i = 0; i < (int)h.nodes.size(); ++i) h.by_level[h.nodes[i].level].push_back(i);
-    bfs_lists(c, f, w->cf->ns, 32, w->near11);
-    bfs_lists(c, f, w->cf->ns + w->cf->nu, 32, w->nearall);
     w->seed = c.fopts.seed * 1000003ull + (uint64_t)f;
     W.push_back(std::move(w));
   }
+  // nearest-vertex lists of every front (host work, two independent lists per front) on the
+  // host thread pool
+  HostPool::get().parallel_for(2 * W.size(), [&](size_t t) {
+    FrontWork<T>& w = *W[t / 2];
+    if (t % 2 == 0)
+      bfs_lists(c, w.f, w.cf->ns, 32, w.near11);
+    else
+      bfs_lists(c, w.f, w.cf->ns + w.cf->nu, 32, w.nearall);
+  });
   // leaves D = F11(leaf, leaf): every pool allocation first, then one extraction
   {
     for (auto& w : W)
