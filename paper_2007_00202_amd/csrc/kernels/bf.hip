@@ -293,6 +293,10 @@ __device__ __forceinline__ void block_argmax(double v, int i, double* red_v, int
 
 // R (rows 0 .. kmax-1 of the factor, row i at R + i p) lives in LDS when it fits
 // the launch's dynamic LDS, else in the task's workspace; the body is the same.
+// One workgroup of GRAM_THREADS threads per block: the steps are latency-bound
+// (each needs the previous step's pivot), so more lanes per block shorten the
+// dot products of a step.
+constexpr int GRAM_THREADS = 1024;
 template <class T>
 __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<T>* __restrict__ R,
                                              unsigned char* __restrict__ aux, int maxp) {
@@ -305,18 +309,19 @@ __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<
   int* sel = (int*)(d + maxp);  // step at which a column was chosen, or -1
   int* piv = sel + maxp;
   int* pl = piv + maxp;         // the permutation
-  __shared__ double red_v[2][4];
-  __shared__ int red_i[2][4];
+  __shared__ double red_v[2][GRAM_THREADS / 64];
+  __shared__ int red_i[2][GRAM_THREADS / 64];
   const int tid = threadIdx.x;
-  for (int j = tid; j < p; j += 256) {
+  for (int j = tid; j < p; j += GRAM_THREADS) {
     d[j] = (double)G[j + (int64_t)j * p].re;
     sel[j] = -1;
   }
   __syncthreads();
   const int kmax = min(tk.maxrank, p);
-  // lanes per column in the row update: 256 / p rounded down to a power of two, at most 8
-  const int tpc = p <= 32 ? 8 : p <= 64 ? 4 : p <= 128 ? 2 : 1;
-  const int pcols = (p + 256 / tpc - 1) / (256 / tpc) * (256 / tpc);  // columns padded to whole passes
+  // lanes per column in the row update: GRAM_THREADS / p rounded down to a power of two, at most 16
+  int tpc = 1;
+  while (tpc < 16 && 2 * tpc * p <= GRAM_THREADS) tpc *= 2;
+  const int pcols = (p + GRAM_THREADS / tpc - 1) / (GRAM_THREADS / tpc) * (GRAM_THREADS / tpc);  // columns padded to whole passes
   const int part = tid & (tpc - 1);
   const int wave = tid >> 6, lane = tid & 63;
   // the pivot search of a step: each thread's candidate (largest d, first index on ties), the wave's
@@ -338,7 +343,7 @@ __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<
   {
     double v = -1;
     int vi = p;
-    for (int j = tid; j < p; j += 256)
+    for (int j = tid; j < p; j += GRAM_THREADS)
       if (d[j] > v) {
         v = d[j];
         vi = j;
@@ -351,7 +356,7 @@ __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<
   for (; k < kmax; ++k) {
     double dmax = red_v[k & 1][0];
     int pi = red_i[k & 1][0];
-    for (int w = 1; w < 4; ++w)
+    for (int w = 1; w < GRAM_THREADS / 64; ++w)
       if (red_v[k & 1][w] > dmax || (red_v[k & 1][w] == dmax && red_i[k & 1][w] < pi)) {
         dmax = red_v[k & 1][w];
         pi = red_i[k & 1][w];
@@ -363,7 +368,7 @@ __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<
     // tpc adjacent lanes share a column's sum (lane part takes i = part, part + tpc, ...)
     double v = -1;  // this thread's candidate for the next pivot
     int vi = p;
-    for (int j = tid / tpc; j < pcols; j += 256 / tpc) {
+    for (int j = tid / tpc; j < pcols; j += GRAM_THREADS / tpc) {
       const bool live = j < p && j != pi && sel[j] < 0;
       // G(j, pi) requested before the sum so that its latency overlaps the sum
       cplx<T> g = {0, 0};
@@ -418,28 +423,28 @@ __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<
     }
   }
   __syncthreads();
-  for (int j = tid; j < p; j += 256) tk.perm[j] = pl[j];
+  for (int j = tid; j < p; j += GRAM_THREADS) tk.perm[j] = pl[j];
   // T = R11^-1 R12 with R11(i, m) = R(i, piv[m]) (upper triangular) and R12(:, c) = R(:, pl[rank + c]):
   // back substitution by columns of R11, every (row, column) update of a step in parallel
   cplx<T>* Tout = (cplx<T>*)tk.T;
   const int ldt = tk.maxrank;
   const int nc = p - rank;
-  for (int e = tid; e < rank * nc; e += 256) {
+  for (int e = tid; e < rank * nc; e += GRAM_THREADS) {
     const int i = e % rank, c = e / rank;
     Tout[i + (int64_t)c * ldt] = R[(int64_t)i * p + pl[rank + c]];
   }
   __syncthreads();
   for (int i = rank - 1; i >= 0; --i) {
     const cplx<T> rii = R[(int64_t)i * p + piv[i]];
-    for (int c = tid; c < nc; c += 256) {
+    for (int c = tid; c < nc; c += GRAM_THREADS) {
       cplx<T>* tp = Tout + i + (int64_t)c * ldt;
       const cplx<T> t = cdiv(*tp, rii);
       *tp = t;
       tl[c] = t;
     }
-    for (int m = tid; m < i; m += 256) rc[m] = R[(int64_t)m * p + piv[i]];
+    for (int m = tid; m < i; m += GRAM_THREADS) rc[m] = R[(int64_t)m * p + piv[i]];
     __syncthreads();
-    for (int e = tid; e < i * nc; e += 256) {
+    for (int e = tid; e < i * nc; e += GRAM_THREADS) {
       const int m = e % i, c = e / i;
       cplx<T>* tp = Tout + m + (int64_t)c * ldt;
       *tp = csub(*tp, cmul(rc[m], tl[c]));
@@ -449,7 +454,7 @@ __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void gram_id_kernel(const IdTask* __restrict__ tasks, double tol, int lds_entries,
+__global__ __launch_bounds__(GRAM_THREADS) void gram_id_kernel(const IdTask* __restrict__ tasks, double tol, int lds_entries,
                                                       int maxp) {
   extern __shared__ __align__(16) unsigned char gram_smem[];
   const IdTask& tk = tasks[blockIdx.x];
@@ -968,7 +973,7 @@ hipError_t launch_gram_id(const IdTask* d_tasks, int ntasks, double tol, int lds
     return hipErrorInvalidValue;
   const size_t bytes = gram_aux_bytes(maxp) + (size_t)lds_entries * sizeof(cplx<T>);
   if (bytes > GRAM_LDS_BYTES) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((gram_id_kernel<T>), dim3(ntasks), dim3(256), bytes, s, d_tasks, tol, lds_entries, maxp);
+  hipLaunchKernelGGL((gram_id_kernel<T>), dim3(ntasks), dim3(GRAM_THREADS), bytes, s, d_tasks, tol, lds_entries, maxp);
   return hipGetLastError();
 }
 
