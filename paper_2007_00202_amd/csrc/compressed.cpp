@@ -669,6 +669,7 @@ void smw_dense_batch(BfRuntime<T>& rt, const std::vector<SmwJob<T>*>& jobs, int*
     fd.n = N2;
     fd.ns = n;
     fd.front = -1;
+    fd.f21_unit = 1;  // the bordered front [M I; -I 0]
     fd.piv = piv;
     Fs[i] = F64;
     Fw[i] = F;

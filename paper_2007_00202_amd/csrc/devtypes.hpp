@@ -19,6 +19,9 @@ struct FrontDesc {
   int32_t n, ns;
   int32_t nchild;     // 0..2
   int32_t front;      // front id (postorder)
+  int32_t f21_unit;   // 1: F21 starts as -I (nu == ns), so its column j is zero below row ns + j until
+                      // the panel holding column j is done; the factorization skips those rows
+  int32_t pad_;
   int64_t sbeg;       // first global (new) index of I^s
   const int32_t* inv[2];   // parent-local -> child-local index or -1 (length n)
   const void* cb[2];       // child contribution block (child F at (ns_c, ns_c))

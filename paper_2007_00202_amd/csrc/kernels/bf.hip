@@ -611,9 +611,12 @@ __global__ __launch_bounds__(256) void philox_gauss_batch_kernel(const ProbeTask
 // multipliers, then the trailing update of A^T and the same row operations
 // on B^T with every entry in parallel.  Back substitution by columns of the
 // triangle (x_c for all rows of B, then its contribution to the columns
-// before it), again every entry in parallel.
+// before it), again every entry in parallel.  SOLVE_THREADS lanes per task:
+// the steps are sequential, so more lanes shorten each step.
+constexpr int SOLVE_THREADS = 1024;
+
 template <class T>
-__global__ __launch_bounds__(256) void small_solve_right_kernel(const SolveTask* __restrict__ tasks) {
+__global__ __launch_bounds__(SOLVE_THREADS) void small_solve_right_kernel(const SolveTask* __restrict__ tasks) {
   const SolveTask& tk = tasks[blockIdx.x];
   const int k = tk.k, r = tk.r;
   cplx<T>* A = (cplx<T>*)tk.A;
@@ -621,15 +624,15 @@ __global__ __launch_bounds__(256) void small_solve_right_kernel(const SolveTask*
   const int64_t lda = tk.lda, ldb = tk.ldb;
   // X A = B  <=>  A^T X^T = B^T.  Work on At(i, j) = A(j, i): rows of A^T are
   // columns of A.  Eliminate with row pivoting on A^T == column pivoting of A.
-  __shared__ double red_v[2][4];
-  __shared__ int red_i[2][4];
+  __shared__ double red_v[2][SOLVE_THREADS / 64];
+  __shared__ int red_i[2][SOLVE_THREADS / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int c = 0; c < k; ++c) {
     const int buf = c & 1;
     // pivot among At rows c..k-1 of column c: At(i, c) = A(c, i)
     double best = -1;
     int bi = c;
-    for (int i = c + tid; i < k; i += 256) {
+    for (int i = c + tid; i < k; i += SOLVE_THREADS) {
       const double a = cabs1(A[c + (int64_t)i * lda]);
       if (a > best) {
         best = a;
@@ -651,18 +654,18 @@ __global__ __launch_bounds__(256) void small_solve_right_kernel(const SolveTask*
     __syncthreads();
     double pv = red_v[buf][0];
     int pr = red_i[buf][0];
-    for (int w = 1; w < 4; ++w)
+    for (int w = 1; w < SOLVE_THREADS / 64; ++w)
       if (red_v[buf][w] > pv || (red_v[buf][w] == pv && red_i[buf][w] < pr)) {
         pv = red_v[buf][w];
         pr = red_i[buf][w];
       }
     if (pr != c) {  // swap At rows c and pr: columns c, pr of A; columns c, pr of B
-      for (int j = tid; j < k; j += 256) {
+      for (int j = tid; j < k; j += SOLVE_THREADS) {
         const cplx<T> t = A[j + (int64_t)c * lda];
         A[j + (int64_t)c * lda] = A[j + (int64_t)pr * lda];
         A[j + (int64_t)pr * lda] = t;
       }
-      for (int j = tid; j < r; j += 256) {
+      for (int j = tid; j < r; j += SOLVE_THREADS) {
         const cplx<T> t = B[j + (int64_t)c * ldb];
         B[j + (int64_t)c * ldb] = B[j + (int64_t)pr * ldb];
         B[j + (int64_t)pr * ldb] = t;
@@ -672,16 +675,16 @@ __global__ __launch_bounds__(256) void small_solve_right_kernel(const SolveTask*
     const cplx<T> d = A[c + (int64_t)c * lda];
     const bool ok = cabs1(d) > 0;
     // multipliers l_i = At(i, c) / At(c, c), kept in At(i, c)
-    for (int i = c + 1 + tid; i < k; i += 256)
+    for (int i = c + 1 + tid; i < k; i += SOLVE_THREADS)
       A[c + (int64_t)i * lda] = ok ? cdiv(A[c + (int64_t)i * lda], d) : cplx<T>{0, 0};
     __syncthreads();
     // At(i, j) -= l_i At(c, j) for i, j > c, and B(:, i) -= l_i B(:, c)
     const int kr = k - c - 1;
-    for (int e = tid; e < kr * kr; e += 256) {
+    for (int e = tid; e < kr * kr; e += SOLVE_THREADS) {
       const int i = c + 1 + e / kr, j = c + 1 + e % kr;
       A[j + (int64_t)i * lda] = csub(A[j + (int64_t)i * lda], cmul(A[c + (int64_t)i * lda], A[j + (int64_t)c * lda]));
     }
-    for (int e = tid; e < r * kr; e += 256) {
+    for (int e = tid; e < r * kr; e += SOLVE_THREADS) {
       const int row = e % r, i = c + 1 + e / r;
       B[row + (int64_t)i * ldb] = csub(B[row + (int64_t)i * ldb], cmul(A[c + (int64_t)i * lda], B[row + (int64_t)c * ldb]));
     }
@@ -691,12 +694,12 @@ __global__ __launch_bounds__(256) void small_solve_right_kernel(const SolveTask*
   for (int c = k - 1; c >= 0; --c) {
     const cplx<T> d = A[c + (int64_t)c * lda];
     const bool ok = cabs1(d) > 0;
-    for (int row = tid; row < r; row += 256) {
+    for (int row = tid; row < r; row += SOLVE_THREADS) {
       const cplx<T> s = B[row + (int64_t)c * ldb];
       B[row + (int64_t)c * ldb] = ok ? cdiv(s, d) : cplx<T>{0, 0};
     }
     __syncthreads();
-    for (int e = tid; e < r * c; e += 256) {
+    for (int e = tid; e < r * c; e += SOLVE_THREADS) {
       const int row = e % r, j = e / r;
       B[row + (int64_t)j * ldb] = csub(B[row + (int64_t)j * ldb], cmul(A[c + (int64_t)j * lda], B[row + (int64_t)c * ldb]));
     }
@@ -1012,7 +1015,7 @@ hipError_t launch_philox_gauss(void* Om, int64_t ld, int64_t n, int ncol, int wi
 template <class T>
 hipError_t launch_small_solve_right(const void* d_tasks, int ntasks, hipStream_t s) {
   if (ntasks == 0) return hipSuccess;
-  hipLaunchKernelGGL((small_solve_right_kernel<T>), dim3(ntasks), dim3(256), 0, s, (const SolveTask*)d_tasks);
+  hipLaunchKernelGGL((small_solve_right_kernel<T>), dim3(ntasks), dim3(SOLVE_THREADS), 0, s, (const SolveTask*)d_tasks);
   return hipGetLastError();
 }
 

@@ -425,7 +425,9 @@ __global__ __launch_bounds__(256) void trsm_ru_kernel(const FrontDesc* __restric
   }
   __syncthreads();
   const int r = ns + blockIdx.x * 256 + threadIdx.x;
-  if (r >= n) return;
+  // with F21 = -I at the start, rows ns + i with i >= k0 + jb are still zero in these columns
+  const int rend = fd.f21_unit ? min(n, ns + k0 + jb) : n;
+  if (r >= rend) return;
   cplx<T> x[KB];
 #pragma unroll
   for (int c = 0; c < KB; ++c) x[c] = c < jb ? F[(int64_t)r + (int64_t)(k0 + c) * n] : cplx<T>{0, 0};
@@ -453,7 +455,8 @@ __global__ __launch_bounds__(256) void trailing_kernel(const FrontDesc* __restri
   const int r0 = k0 + jb;
   cplx<T>* F = (cplx<T>*)fd.F;
   const int M1 = ns - r0, N1 = n - r0;
-  const int M2 = n - ns, N2 = ns - r0;
+  // with F21 = -I at the start, F21(:, k0:r0) is zero below row ns + r0
+  const int M2 = fd.f21_unit ? min(n - ns, r0) : n - ns, N2 = ns - r0;
   const int tm1 = (M1 + GEMM_TM - 1) / GEMM_TM, tn1 = (N1 + GEMM_TN - 1) / GEMM_TN;
   const int tm2 = (M2 + GEMM_TM - 1) / GEMM_TM, tn2 = (N2 + GEMM_TN - 1) / GEMM_TN;
   const int t1 = (M1 > 0 && N1 > 0) ? tm1 * tn1 : 0;
