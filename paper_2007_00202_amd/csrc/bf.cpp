@@ -34,6 +34,35 @@ void* upload_tmp(R& rt, const std::vector<V>& v) {
   rt.c->stage.put(d, v.data(), v.size() * sizeof(V), rt.s());
   return d;
 }
+// Several host arrays in one scratch allocation, staged with one copy (a copy call costs the host
+// about as much as a launch).  Parts are 256-byte aligned; part(i) gives a part's device address
+// before the copy (so that other parts can point into it); the sources are read at commit().
+template <class R>
+struct PackedUpload {
+  R& rt;
+  std::vector<std::pair<const void*, size_t>> src;
+  std::vector<size_t> off;
+  size_t total = 0;
+  char* base = nullptr;
+  explicit PackedUpload(R& r) : rt(r) {}
+  int add(const void* p, size_t bytes) {
+    off.push_back(total);
+    src.push_back({p, bytes});
+    total = (total + bytes + 255) & ~(size_t)255;
+    return (int)off.size() - 1;
+  }
+  char* part(int i) {
+    if (!base) base = (char*)rt.scratch.take(std::max<size_t>(total, 16));
+    return base + off[i];
+  }
+  void commit() {
+    if (!base) base = (char*)rt.scratch.take(std::max<size_t>(total, 16));
+    std::vector<char> h(std::max<size_t>(total, 1));
+    for (size_t i = 0; i < src.size(); ++i)
+      if (src[i].second) std::memcpy(h.data() + off[i], src[i].first, src[i].second);
+    rt.c->stage.put(base, h.data(), total, rt.s());
+  }
+};
 }  // namespace
 
 // ------------------------------------------------------------ device memory
@@ -563,14 +592,18 @@ void run_extract_to(BfRuntime<T>& rt, ExtractBatch& b, bool src_single) {
     b.idx.clear();
     return;
   }
-  int32_t* d_idx = (int32_t*)upload_tmp(rt, b.idx);
+  PackedUpload<BfRuntime<T>> pk(rt);  // index lists and tasks in one copy
+  const int pi = pk.add(b.idx.data(), b.idx.size() * sizeof(int32_t));
+  const int pt = pk.add(b.tasks.data(), b.tasks.size() * sizeof(ExtractTask));
+  int32_t* d_idx = (int32_t*)pk.part(pi);
   int64_t maxe = 0;
   for (auto& e : b.tasks) {
     e.rows = d_idx + (intptr_t)e.rows;
     e.cols = d_idx + (intptr_t)e.cols;
     maxe = std::max<int64_t>(maxe, (int64_t)e.nr * e.nc);
   }
-  ExtractTask* d_t = (ExtractTask*)upload_tmp(rt, b.tasks);
+  ExtractTask* d_t = (ExtractTask*)pk.part(pt);
+  pk.commit();
   const int yb = (int)std::min<int64_t>(32, std::max<int64_t>(1, (maxe + 2047) / 2048));
   KernelTimer& tm = rt.c->timer;
   const int tk = tm.want(K_EXTRACT) ? tm.begin(rt.s()) : -1;
@@ -719,8 +752,12 @@ struct IdLevel {
   // expand the interpolation matrices into outs (device, ld per block)
   void expand(const std::vector<void*>& outs, const std::vector<int64_t>& ldo, bool transpose, bool conj) {
     if (ntasks == 0) return;
-    void** d_outs = (void**)upload_tmp(rt, outs);
-    int64_t* d_ldo = (int64_t*)upload_tmp(rt, ldo);
+    PackedUpload<BfRuntime<T>> pk(rt);  // both arrays in one copy
+    const int po = pk.add(outs.data(), outs.size() * sizeof(void*));
+    const int pl = pk.add(ldo.data(), ldo.size() * sizeof(int64_t));
+    void** d_outs = (void**)pk.part(po);
+    int64_t* d_ldo = (int64_t*)pk.part(pl);
+    pk.commit();
     chk(launch_id_expand<T>(d_tasks, ntasks, d_outs, d_ldo, transpose, conj, rt.s()), "id expand");
   }
   IdTask* d_tasks = nullptr;
@@ -1132,9 +1169,14 @@ void random_once_batch(BfRuntime<T>& rt, const std::vector<RandomJob<T>*>& jobs)
     j.max_id_rank = 0;
   }
   if (!ptasks.empty()) {
-    const int32_t* d_gb = (const int32_t*)upload_tmp(rt, gbeg);
-    const int32_t* d_ge = (const int32_t*)upload_tmp(rt, gend);
-    const ProbeTask* d_pt = (const ProbeTask*)upload_tmp(rt, ptasks);
+    PackedUpload<BfRuntime<T>> pk(rt);  // the three arrays in one copy
+    const int p0 = pk.add(gbeg.data(), gbeg.size() * sizeof(int32_t));
+    const int p1 = pk.add(gend.data(), gend.size() * sizeof(int32_t));
+    const int p2 = pk.add(ptasks.data(), ptasks.size() * sizeof(ProbeTask));
+    const int32_t* d_gb = (const int32_t*)pk.part(p0);
+    const int32_t* d_ge = (const int32_t*)pk.part(p1);
+    const ProbeTask* d_pt = (const ProbeTask*)pk.part(p2);
+    pk.commit();
     chk(launch_philox_gauss_batch<T>(d_pt, (int)ptasks.size(), pmax, d_gb, d_ge, rt.seed, s), "probes");
   }
   // the sketches of every job: operators of one structure are applied together (apply_all)
