@@ -330,6 +330,12 @@ const char* bfmf_server_last_error(bfmf_server s);
 /* stops the workers after the admitted batches; queued requests fail */
 void bfmf_server_destroy(bfmf_server s);
 
+/* Number of device allocations (hipMalloc) made by the library in this process
+ * so far.  A handle allocates during its first analyze, factor and solve and
+ * when later calls need more memory; factoring or solving again with the same
+ * sizes and options allocates nothing (a free would synchronize the device). */
+int64_t bfmf_device_allocation_count(void);
+
 const char* bfmf_status_str(bfmf_status s);
 /* Message of the last failed call on h; with h == NULL, of the last failed
  * call on this thread that returned no handle (bfmf_bf_compress_dense). */

@@ -108,6 +108,7 @@ _SIGS = {
     "bfmf_get_kernel_stats": (C.c_int, [_h, C.c_int32, C.POINTER(bfmf_kernel_stat)]),
     "bfmf_reset_kernel_stats": (C.c_int, [_h]),
     "bfmf_set_gemm_tile": (C.c_int, [C.c_int32]),
+    "bfmf_device_allocation_count": (C.c_int64, []),
     "bfmf_get_gemm_tile_launches": (C.c_int, [_h, C.POINTER(C.c_int64), C.c_int32]),
     "bfmf_bf_compress_dense": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, C.c_int32, C.c_double,
                                          C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_P)]),
@@ -283,6 +284,10 @@ def bfmf_reset_kernel_stats(h):
 
 BFMF_GEMM_TILES = 6
 GEMM_TILE_SHAPES = ["64x64", "32x128", "128x32", "16x256", "256x16", "256x16 streaming"]
+
+
+def bfmf_device_allocation_count():
+    return int(_lib.bfmf_device_allocation_count())
 
 
 def bfmf_set_gemm_tile(cfg):

@@ -217,12 +217,12 @@ static bfmf_status solve_common(bfmf_handle h, int64_t nrhs, const double* B, in
       const size_t need = (size_t)h->n * nrhs * elem;
       if (bb.bytes < need) {
         bb.release();
-        HIPCHK(hipMalloc(&bb.p, need));
+        HIPCHK(dev_malloc((void**)&bb.p, need));
         bb.bytes = need;
       }
       if (xb.bytes < need) {
         xb.release();
-        HIPCHK(hipMalloc(&xb.p, need));
+        HIPCHK(dev_malloc((void**)&xb.p, need));
         xb.bytes = need;
       }
       HIPCHK(hipMemcpy2DAsync(bb.p, h->n * elem, B, ldb * elem, h->n * elem, nrhs, hipMemcpyHostToDevice,
@@ -352,6 +352,8 @@ bfmf_status bfmf_get_gemm_tile_launches(bfmf_handle h, int64_t* out, int32_t n) 
   for (int i = 0; i < n; ++i) out[i] = i < GEMM_CFGS ? h->gemm_cfg_launches[i] : 0;
   return BFMF_OK;
 }
+
+int64_t bfmf_device_allocation_count(void) { return g_device_allocations.load(); }
 
 const char* bfmf_status_str(bfmf_status s) {
   switch (s) {

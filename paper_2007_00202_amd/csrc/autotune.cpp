@@ -77,8 +77,8 @@ void build_table(Table& t, hipStream_t s) {
   void* buf = nullptr;
   void* dtask = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  tchk(hipMalloc(&buf, (size_t)max_elems * esz), "operand buffer");
-  tchk(hipMalloc(&dtask, (size_t)max_tasks * (sizeof(GTask) + sizeof(int64_t)) + 64), "task buffer");
+  tchk(dev_malloc((void**)&buf, (size_t)max_elems * esz), "operand buffer");
+  tchk(dev_malloc((void**)&dtask, (size_t)max_tasks * (sizeof(GTask) + sizeof(int64_t)) + 64), "task buffer");
   tchk(hipMemsetAsync(buf, 0, (size_t)max_elems * esz, s), "clear");
   tchk(hipEventCreate(&e0), "event");
   tchk(hipEventCreate(&e1), "event");

@@ -20,7 +20,7 @@ void chk(hipError_t e, const char* what) {
 void dev_alloc(DevBuf& b, size_t bytes) {
   b.release();
   if (bytes == 0) bytes = 256;
-  if (hipMalloc(&b.p, bytes) != hipSuccess) {
+  if (dev_malloc((void**)&b.p, bytes) != hipSuccess) {
     (void)hipGetLastError();
     b.p = nullptr;
     throw Error(BFMF_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed (butterfly)");

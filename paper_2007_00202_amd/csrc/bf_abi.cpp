@@ -79,7 +79,7 @@ bfmf_status bfmf_bf_compress_dense(int32_t device, int32_t m, int32_t n, const d
     b->rt.seed = seed;
     b->rt.samples = samples > 0 ? samples : 64;
     const size_t bytes = (size_t)m * n * 16;
-    ochk(hipMalloc(&b->K.p, bytes), "malloc");
+    ochk(dev_malloc((void**)&b->K.p, bytes), "malloc");
     b->K.bytes = bytes;
     ochk(hipMemcpy2D(b->K.p, (size_t)m * 16, K, (size_t)ldk * 16, (size_t)m * 16, n, hipMemcpyHostToDevice), "upload");
     BTree to = make_tree(m, L, nullptr, 0), ts = make_tree(n, L, nullptr, 0);

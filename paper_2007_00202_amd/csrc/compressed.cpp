@@ -848,7 +848,7 @@ static void reset_state(CompState<T>& st, Context& c, int nfronts) {
   st.rt.sample_hint.clear();
   st.rt.batch = c.fopts.batched != 0;
   if (!st.status.p) {
-    HIPCHK(hipMalloc(&st.status.p, 16));
+    HIPCHK(dev_malloc((void**)&st.status.p, 16));
     st.status.bytes = 16;
   }
 }

@@ -3,6 +3,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include <cstdint>
 #include <array>
 #include <chrono>
@@ -18,6 +20,14 @@
 namespace bfmf {
 
 // RAII device allocation
+// Every device allocation of the library goes through dev_malloc, which counts
+// it (process-wide; bfmf_device_allocation_count reports the count).
+inline std::atomic<int64_t> g_device_allocations{0};
+inline hipError_t dev_malloc(void** p, size_t bytes) {
+  g_device_allocations.fetch_add(1, std::memory_order_relaxed);
+  return hipMalloc(p, bytes);
+}
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;

@@ -30,7 +30,7 @@ double now() {
 void alloc(DevBuf& b, size_t bytes) {
   b.release();
   if (bytes == 0) bytes = 16;
-  hipError_t e = hipMalloc(&b.p, bytes);
+  hipError_t e = dev_malloc((void**)&b.p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     b.p = nullptr;

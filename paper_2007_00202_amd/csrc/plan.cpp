@@ -16,7 +16,7 @@ template <class T>
 void upload(DevBuf& b, const std::vector<T>& v) {
   b.release();
   size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
-  HIPCHK(hipMalloc(&b.p, bytes));
+  HIPCHK(dev_malloc((void**)&b.p, bytes));
   b.bytes = bytes;
   if (!v.empty()) HIPCHK(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
 }
@@ -144,10 +144,10 @@ void upload_plan(Context& c) {
   int64_t npiv = 0;
   for (auto& p : c.fp) npiv += p.ns;
   c.d_piv.release();
-  HIPCHK(hipMalloc(&c.d_piv.p, std::max<int64_t>(npiv, 4) * sizeof(int32_t)));
+  HIPCHK(dev_malloc((void**)&c.d_piv.p, std::max<int64_t>(npiv, 4) * sizeof(int32_t)));
   c.d_piv.bytes = std::max<int64_t>(npiv, 4) * sizeof(int32_t);
   c.d_status.release();
-  HIPCHK(hipMalloc(&c.d_status.p, 16));
+  HIPCHK(dev_malloc((void**)&c.d_status.p, 16));
   c.d_status.bytes = 16;
 }
 

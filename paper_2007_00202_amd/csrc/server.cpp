@@ -36,7 +36,7 @@ struct Arena {
   void init(size_t bytes) {
     bytes = (bytes + 255) & ~(size_t)255;
     if (bytes == 0) return;
-    if (hipMalloc(&buf.p, bytes) != hipSuccess) {
+    if (dev_malloc((void**)&buf.p, bytes) != hipSuccess) {
       (void)hipGetLastError();
       buf.p = nullptr;
       throw Error(BFMF_E_NOMEM, "server: result arena of " + std::to_string(bytes) + " bytes");
@@ -146,7 +146,7 @@ void run_batch(bfmf_server_s* s, Model& m, std::vector<Request*>& batch) {
   const size_t need = std::max<size_t>(nnz, 1) * (2 * sizeof(int32_t) + 2 * sizeof(double));
   if (m.nz.bytes < need) {
     m.nz.release();
-    HIPCHK(hipMalloc(&m.nz.p, need * 2));
+    HIPCHK(dev_malloc((void**)&m.nz.p, need * 2));
     m.nz.bytes = need * 2;
   }
   int32_t* d_rows = m.nz.as<int32_t>();
@@ -308,9 +308,9 @@ bfmf_status bfmf_server_attach(bfmf_server s, bfmf_handle h, int32_t* model) {
     m->charged = need;
     try {  // every batch buffer now, so that no request waits for an allocation
       const size_t blk = (size_t)h->n * mb * 16;
-      HIPCHK(hipMalloc(&m->B.p, blk));
+      HIPCHK(dev_malloc((void**)&m->B.p, blk));
       m->B.bytes = blk;
-      HIPCHK(hipMalloc(&m->X.p, blk));
+      HIPCHK(dev_malloc((void**)&m->X.p, blk));
       m->X.bytes = blk;
       gmres_workspace(*h, mb, restart);
       ensure_workspace(*h, mb);

@@ -182,3 +182,27 @@ def test_direct_mode_and_tolerance_trend(gpu_lib, precision):
         s.close()
     bound = 1e-4 if precision == "c128" else 1e-3
     assert err[1e-6] <= bound and err[1e-6] * 10 <= err[1e-3], err
+
+
+def test_repeated_factor_and_solve_allocate_nothing(gpu_lib):
+    """After a handle's first factorization and solve, factoring and solving again with the
+    same sizes and options makes no device allocation (the scratch stack keeps its chunks and
+    reorders them instead of freeing; a free would synchronize the device), and gives the same
+    solution bit for bit."""
+    dims = (20, 20, 20)
+    rp, ci, v, _ = helmholtz_7pt(dims, 0.05)
+    b = rng_for("test", "rhs", (20, 2)).standard_normal((rp.shape[0] - 1, 2)) + 0j
+    s = gpu_lib.Solver(0).analyze(rp, ci, v, dims=dims, leaf_max=64, sep_leaf=32)
+    try:
+        for it in range(3):
+            s.factor(tol=1e-3, n_min=100, batched=True, precision=gpu_lib.BFMF_C64_MIXED)
+            X, info = s.solve(b, true_rtol=1e-3)
+            assert info["status"] == 0
+            if it == 0:
+                count, X0 = gpu_lib.bfmf_device_allocation_count(), X
+                assert count > 0
+            else:
+                assert gpu_lib.bfmf_device_allocation_count() == count, it
+                assert np.array_equal(X, X0), it
+    finally:
+        s.close()
