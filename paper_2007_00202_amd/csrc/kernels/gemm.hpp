@@ -306,44 +306,46 @@ __device__ __forceinline__ void gemm_tile_cfg(const cplx<T>* __restrict__ A, int
 // rows per k, coalesced), four k-steps ahead of their use.  No LDS.
 constexpr int SKINNY_TM = 256, SKINNY_TN = 16;
 
-template <class T>
+// RB row blocks of 16 per wave (the workgroup covers 64 RB rows); fewer blocks
+// hold fewer registers, so more waves share a SIMD.
+template <class T, int RB = 4>
 __device__ __forceinline__ void gemm_tile_skinny(const cplx<T>* __restrict__ A, int64_t lda,
                                                  const cplx<T>* __restrict__ B, int64_t ldb, cplx<T>* __restrict__ C,
                                                  int64_t ldc, int M, int N, int K, cplx<T> alpha, int beta, int tm) {
   typedef typename Mfma<T>::acc_t acc_t;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int rbase = tm * SKINNY_TM + wave * 64;
+  const int rbase = tm * 64 * RB + wave * 16 * RB;
   if (rbase >= M) return;  // no barrier below: idle waves may leave
   const int lr = lane & 15, lk = lane >> 4;
-  acc_t accr[4], acci[4];
+  acc_t accr[RB], acci[RB];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < RB; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       accr[i][r] = 0;
       acci[i][r] = 0;
     }
   constexpr int U = 4;  // k-steps of 4 per batch of loads
-  cplx<T> a0[U][4], b0[U], a1[U][4], b1[U];  // two named batches: no dynamically indexed registers
-  auto load = [&](cplx<T>(&aa)[U][4], cplx<T>(&bb)[U], int k0) {
+  cplx<T> a0[U][RB], b0[U], a1[U][RB], b1[U];  // two named batches: no dynamically indexed registers
+  auto load = [&](cplx<T>(&aa)[U][RB], cplx<T>(&bb)[U], int k0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int k = k0 + 4 * u + lk;
       const bool kin = k < K;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < RB; ++i) {
         const int row = rbase + 16 * i + lr;
         aa[u][i] = load_or_zero(A + (int64_t)row + (int64_t)k * lda, kin && row < M);
       }
       bb[u] = load_or_zero(B + (int64_t)k + (int64_t)lr * ldb, kin && lr < N);
     }
   };
-  auto mma = [&](cplx<T>(&aa)[U][4], cplx<T>(&bb)[U]) {
+  auto mma = [&](cplx<T>(&aa)[U][RB], cplx<T>(&bb)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const cplx<T> bv = bb[u];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < RB; ++i) {
         const cplx<T> av = aa[u][i];
         accr[i] = Mfma<T>::step(av.re, bv.re, accr[i]);
         accr[i] = Mfma<T>::step(-av.im, bv.im, accr[i]);
@@ -361,7 +363,7 @@ __device__ __forceinline__ void gemm_tile_skinny(const cplx<T>* __restrict__ A, 
     mma(a1, b1);
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < RB; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int gr = rbase + 16 * i + Mfma<T>::row(lane, r);

@@ -285,8 +285,16 @@ __global__ __launch_bounds__(256) void sweep_gemm_kernel(const FrontDesc* __rest
 }
 
 // the same products for at most 16 right-hand sides: 256-row streaming tiles (F21 / F12 read once)
+// rows of a sweep product per workgroup: two 16-row blocks per wave in double precision (fewer
+// registers, more waves per SIMD for this bandwidth-bound stream), four in single
+template <class T>
+constexpr int sweep_skinny_tm() {
+  return sizeof(T) == 8 ? 128 : 256;
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void sweep_gemm_skinny_kernel(const FrontDesc* __restrict__ fds, int nrhs, int mode) {
+  constexpr int RB = sweep_skinny_tm<T>() / 64;
   const FrontDesc& fd = fds[blockIdx.y];
   const int n = fd.n, ns = fd.ns, nu = n - ns;
   if (ns == 0 || nu == 0 || nrhs > SKINNY_TN) return;
@@ -294,11 +302,11 @@ __global__ __launch_bounds__(256) void sweep_gemm_skinny_kernel(const FrontDesc*
   cplx<T>* W = (cplx<T>*)fd.W;
   const int M = mode == 0 ? nu : ns;
   const int t = blockIdx.x;
-  if (t * SKINNY_TM >= M) return;
+  if (t * sweep_skinny_tm<T>() >= M) return;
   if (mode == 0)
-    gemm_tile_skinny<T>(F + ns, n, W, n, W + ns, n, nu, nrhs, ns, cplx<T>{-1, 0}, 1, t);
+    gemm_tile_skinny<T, RB>(F + ns, n, W, n, W + ns, n, nu, nrhs, ns, cplx<T>{-1, 0}, 1, t);
   else
-    gemm_tile_skinny<T>((const cplx<T>*)fd.F12, fd.ld12, W + ns, n, W, n, ns, nrhs, nu, cplx<T>{-1, 0}, 1, t);
+    gemm_tile_skinny<T, RB>((const cplx<T>*)fd.F12, fd.ld12, W + ns, n, W, n, ns, nrhs, nu, cplx<T>{-1, 0}, 1, t);
 }
 
 // ------------------------------------------------------------ GMRES vectors
@@ -432,7 +440,7 @@ hipError_t launch_forward_level(const FrontDesc* d_fds, int nbatch, int maxn, in
     hipLaunchKernelGGL((fwd_trsv_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, nrhs);
   KCHECK(hipGetLastError());
   if (nrhs <= SKINNY_TN) {
-    hipLaunchKernelGGL((sweep_gemm_skinny_kernel<T>), dim3((unsigned)blocks_for(maxn, SKINNY_TM), nbatch), dim3(256), 0,
+    hipLaunchKernelGGL((sweep_gemm_skinny_kernel<T>), dim3((unsigned)blocks_for(maxn, sweep_skinny_tm<T>()), nbatch), dim3(256), 0,
                        s, d_fds, nrhs, 0);
   } else {
     const int tiles = (int)(blocks_for(maxn, GEMM_TM) * blocks_for(nrhs, GEMM_TN));
@@ -450,7 +458,7 @@ hipError_t launch_backward_level(const FrontDesc* d_fds, int nbatch, int maxn, i
                        (const cplx<T>*)x, N, nrhs);
     KCHECK(hipGetLastError());
     if (nrhs <= SKINNY_TN) {
-      hipLaunchKernelGGL((sweep_gemm_skinny_kernel<T>), dim3((unsigned)blocks_for(maxn, SKINNY_TM), nbatch), dim3(256),
+      hipLaunchKernelGGL((sweep_gemm_skinny_kernel<T>), dim3((unsigned)blocks_for(maxn, sweep_skinny_tm<T>()), nbatch), dim3(256),
                          0, s, d_fds, nrhs, 1);
     } else {
       const int tiles = (int)(blocks_for(maxn, GEMM_TM) * blocks_for(nrhs, GEMM_TN));
