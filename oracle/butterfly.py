@@ -17,8 +17,10 @@ Paper Sec. 3.
   extract_bf      entries of submatrices from the factors (Alg. 3)
   bf_dense        the matrix the factors represent (the product written out)
 
-Parity unpinned: bf_random_matvec follows a reading of an algorithm the paper
-only cites; it is pinned by tolerance against dense products only.
+bf_random_matvec follows a reading of an algorithm the paper only cites; it is
+pinned by exactness on generic exact-rank matrices (every ID keeps exactly
+min(r, rows, columns) of its block, the product equals K to rounding, L = 0..3
+on ragged sizes) and by tolerance on oscillatory kernels.
 """
 import numpy as np
 import scipy.linalg as sla

@@ -8,6 +8,8 @@
   kernels -- a Fourier-type kernel exp(2 pi i n x y) and the 3D Helmholtz
   Green's function between two parallel planes -- are compressed with
   ||K - K~||_F <= 10 eps ||K||_F; an exactly rank-3 matrix is reproduced.
+* bf_random_matvec on a generic rank-r matrix: exact to rounding for L = 0..3
+  on ragged sizes, each ID keeping exactly min(r, rows, columns) of its block.
 * extract_bf (Alg. 3): entries equal the decompressed matrix, including the
   1x1 and 1x2 requests of the 2-level example (Fig. 'extract').
 """
@@ -169,3 +171,36 @@ def test_random_matvec_construction(kind):
     bf = bfo.bf_random_matvec(lambda X: K @ X, lambda X: K.conj().T @ X, to, ts, tol, 48, rng)
     err = np.linalg.norm(K - bfo.bf_dense(bf)) / np.linalg.norm(K)
     assert err <= 10 * tol, err
+
+
+@pytest.mark.parametrize("L", [0, 1, 2, 3])
+@pytest.mark.parametrize("r", [1, 5, 11])
+def test_random_matvec_is_exact_on_exact_rank(L, r):
+    """A generic rank-r matrix K = X Y^H: every block K(rows, S_v) has rank min(r, |rows|, |S_v|), and a
+    Gaussian sketch with at least that many columns keeps every row dependency (the range-finder argument
+    of randomized low-rank approximation), so the construction is exact up to rounding and each ID keeps
+    exactly that many rows (columns).  At L = 0 this is the two-sided randomized ID of the whole matrix.
+    Ragged sizes (97 x 83) give unequal siblings at every level."""
+    rng = np.random.default_rng(100 * L + r)
+    m, n = 97, 83
+    X = rng.standard_normal((m, r)) + 1j * rng.standard_normal((m, r))
+    Y = rng.standard_normal((n, r)) + 1j * rng.standard_normal((n, r))
+    K = X @ Y.conj().T
+    to, ts = bfo.Tree(m, L), bfo.Tree(n, L)
+    bf = bfo.bf_random_matvec(lambda V: K @ V, lambda V: K.conj().T @ V, to, ts, 1e-12, 24, rng)
+    assert bf.samples == 24
+    assert np.linalg.norm(bfo.bf_dense(bf) - K) <= 1e-10 * np.linalg.norm(K)
+    for (l, t, v), rows in bf.Obar.items():
+        if l == L:
+            cand = to.node(L, t)[1] - to.node(L, t)[0]
+        else:
+            cand = len(bf.Obar[(l + 1, 2 * t, v // 2)]) + len(bf.Obar[(l + 1, 2 * t + 1, v // 2)])
+        b, e = ts.node(L - l, v)
+        assert len(rows) == min(r, cand, e - b), (l, t, v)
+    for (l, t, v), cols in bf.Sbar.items():
+        if l == 0:
+            cand = ts.node(L, v)[1] - ts.node(L, v)[0]
+        else:
+            cand = len(bf.Sbar[(l - 1, t // 2, 2 * v)]) + len(bf.Sbar[(l - 1, t // 2, 2 * v + 1)])
+        b, e = to.node(l, t)
+        assert len(cols) == min(r, cand, e - b), (l, t, v)
