@@ -294,7 +294,7 @@ def operator_label(cfg):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU (sharding across GPUs is not implemented); --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_2007_00202_amd import bfmf
