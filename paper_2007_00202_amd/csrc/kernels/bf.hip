@@ -41,12 +41,24 @@ __device__ __forceinline__ uintptr_t task_addr(int i, int64_t off, void* b0, voi
   return b + (uintptr_t)off * sizeof(cplx<T>);
 }
 
+// Workgroups are handed to the chip's 8 XCDs in turn (block b to XCD b mod 8), each with its own L2. Runs of
+// XCD_RUN consecutive tiles, which mostly belong to one task and share its operand panels, are given to
+// one XCD; the runs still alternate between XCDs, so the load stays balanced. A bijection of
+// [0, nb): blocks past the last whole group of 8 runs keep their own tile.
+constexpr int64_t XCDS = 8, XCD_RUN = 8;
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
+  const int64_t full = nb / (XCDS * XCD_RUN) * (XCDS * XCD_RUN);
+  if (b >= full) return b;
+  const int64_t x = b % XCDS, j = b / XCDS;
+  return (x + XCDS * (j / XCD_RUN)) * XCD_RUN + j % XCD_RUN;
+}
+
 template <class T, class C>
 __global__ __launch_bounds__(256) void grouped_gemm_kernel(const GTask* __restrict__ tasks,
                                                            const int64_t* __restrict__ tile_start, int ntasks,
                                                            void* b0, void* b1, void* b2, void* b3) {
   __shared__ TileSmem<T, C> sm;
-  const int64_t tile = blockIdx.x;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const int lo = find_task(tile_start, ntasks, tile);
   const GTask& t = tasks[lo];
   const int64_t local = tile - tile_start[lo];
