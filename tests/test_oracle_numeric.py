@@ -8,7 +8,9 @@
 * Partial LU: P L U reproduces F11 (LAPACK getrf on the same block).
 * GMRES: an exact preconditioner converges in one iteration; the residual
   estimate never increases inside a cycle; the unpreconditioned solve reaches
-  the dense solution.
+  the dense solution; each history entry is the least-squares minimum of
+  ||M^-1 (b - A x)|| over the Krylov space (brute force); k distinct
+  eigenvalues give convergence at exactly step k.
 """
 import numpy as np
 import pytest
@@ -175,3 +177,55 @@ def test_gmres_unpreconditioned_properties():
     # restarted run with a small restart length still converges
     x5, it5, _ = gmres.gmres(lambda v: Ad @ v, lambda v: v, b, restart=5, rtol=1e-10, atol=0, max_iter=500)
     assert np.linalg.norm(Ad @ x5 - b) <= 1e-9 * np.linalg.norm(b)
+
+
+def _krylov_min_residual(Mi_A, Mi_b, j):
+    """min over x in K_j(Mi_A, Mi_b) of ||Mi_b - Mi_A x||, by brute force: an orthonormal basis of the
+    Krylov space from a QR of the power basis, then least squares."""
+    K = np.empty((Mi_b.shape[0], j), dtype=np.complex128)
+    v = Mi_b.copy()
+    for c in range(j):
+        K[:, c] = v / np.linalg.norm(v)
+        v = Mi_A @ K[:, c]
+    Q, _ = np.linalg.qr(K)
+    y = np.linalg.lstsq(Mi_A @ Q, Mi_b, rcond=None)[0]
+    return np.linalg.norm(Mi_b - Mi_A @ Q @ y)
+
+
+@pytest.mark.parametrize("precond", [False, True])
+def test_gmres_history_is_the_krylov_minimum_residual(precond):
+    """GMRES (Sec. 6: left preconditioning, zero initial guess) minimises ||M^-1 (b - A x)|| over the
+    Krylov space K_j(M^-1 A, M^-1 b): every entry of the first cycle's history equals that minimum,
+    computed here by least squares over an explicit basis. Complex, non-normal A and M."""
+    rng = np.random.default_rng(5)
+    n = 40
+    A = np.eye(n) * (2 + 1j) + 0.6 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    M = np.eye(n) + (0.2 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+                     if precond else 0)
+    Mi = np.linalg.inv(M)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x, it, hist = gmres.gmres(lambda v: A @ v, lambda v: Mi @ v, b, restart=30, rtol=1e-13, atol=0, max_iter=12)
+    assert it == 12 and len(hist) == 13
+    assert abs(hist[0] - np.linalg.norm(Mi @ b)) <= 1e-13 * hist[0]
+    for j in range(1, 13):
+        ref = _krylov_min_residual(Mi @ A, Mi @ b, j)
+        assert abs(hist[j] - ref) <= 1e-10 * hist[0], (j, hist[j], ref)
+    # the returned iterate attains the last value of the history
+    assert abs(np.linalg.norm(Mi @ (b - A @ x)) - hist[-1]) <= 1e-10 * hist[0]
+
+
+@pytest.mark.parametrize("k", [1, 3, 7])
+def test_gmres_converges_in_as_many_steps_as_distinct_eigenvalues(k):
+    """A diagonalisable A with k distinct eigenvalues has a minimal polynomial of degree k, so GMRES
+    reaches the exact solution at step k and, for a generic b, not before."""
+    rng = np.random.default_rng(10 + k)
+    n = 24
+    lam = rng.standard_normal(k) + 1j * rng.standard_normal(k) + 3
+    S = np.eye(n) + 0.3 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    A = S @ np.diag(lam[np.arange(n) % k]) @ np.linalg.inv(S)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x, it, hist = gmres.gmres(lambda v: A @ v, lambda v: v, b, restart=30, rtol=1e-10, atol=0)
+    assert it == k
+    assert np.linalg.norm(A @ x - b) <= 1e-9 * np.linalg.norm(b)
+    if k > 1:
+        assert hist[k - 1] > 1e-4 * hist[0]
