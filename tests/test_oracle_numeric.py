@@ -5,7 +5,9 @@
 * Multifrontal LU (Alg. 1): brute-force dense solves on grids of at most 8^3,
   manufactured solutions, and the identity C_tau = -A(U,T) A(T,T)^-1 A(T,U)
   for the contribution block of the subtree T of tau with update set U.
-* Partial LU: P L U reproduces F11 (LAPACK getrf on the same block).
+* Partial LU: P L U reproduces F11 (LAPACK getrf on the same block); on the
+  7-point pattern with random values (rows interchanged in most fronts) factor
+  and solve still give the dense solution.
 * GMRES: an exact preconditioner converges in one iteration; the residual
   estimate never increases inside a cycle; the unpreconditioned solve reaches
   the dense solution; each history entry is the least-squares minimum of
@@ -83,6 +85,27 @@ def test_multifrontal_matches_dense_solve(dims, leaf):
     assert np.linalg.norm(X - Xd) <= 1e-10 * np.linalg.norm(Xd)
     assert np.linalg.norm(X - xs) <= 1e-10 * np.linalg.norm(xs)
     assert np.all(mf.rel_residual(rowptr, colind, values, X, B) <= 1e-12)
+
+
+@pytest.mark.parametrize("dims,leaf", [((4, 4, 4), 8), ((6, 5, 4), 30)])
+def test_multifrontal_with_row_interchanges_matches_dense_solve(dims, leaf):
+    """The 7-point pattern with random complex values has no dominant diagonal, so the partial LU of the
+    fronts interchanges rows (pivoting restricted to F11, Alg. 1); factor and solve must still give the
+    dense solution, which fails if an interchange is dropped or applied on the wrong side."""
+    rowptr, colind, values, _ = helmholtz_7pt(dims, 0.05)
+    rng = rng_for("test", "coef", dims)
+    values = rng.standard_normal(values.shape[0]) + 1j * rng.standard_normal(values.shape[0])
+    od = nd.nd_grid(dims, leaf_max=leaf, sep_leaf=8)
+    fac = mf.factor(rowptr, colind, values, od)
+    moved = sum(int(np.any(np.asarray(p) != np.arange(len(p)))) for p in fac.piv)
+    assert moved >= od.nfronts // 2, (moved, od.nfronts)
+    xs = rng.standard_normal((od.n, 2)) + 1j * rng.standard_normal((od.n, 2))
+    Ad = dense(rowptr, colind, values)
+    B = Ad @ xs
+    X = mf.solve(fac, B)
+    Xd = np.linalg.solve(Ad, B)
+    assert np.linalg.norm(X - Xd) <= 1e-8 * np.linalg.norm(Xd)
+    assert np.all(mf.rel_residual(rowptr, colind, values, X, B) <= 1e-10)
 
 
 def test_contribution_blocks_are_subtree_schur_complements():
