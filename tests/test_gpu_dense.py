@@ -5,7 +5,8 @@
   (FP64, same addition order).
 * Partial LU (kernel d): the factored front matches the oracle's LAPACK
   partial factorization of the same assembled front (pivots equal, values
-  to 1e-11 relative).
+  to 1e-11 relative), also on a pattern with random values where most fronts
+  interchange rows.
 * Sweeps (kernel e) and GMRES: x matches the oracle's solve to 1e-10; with
   the exact factorization GMRES stops after one iteration.
 """
@@ -54,6 +55,43 @@ def test_extend_add_bit_exact_and_partial_lu(gpu_lib, dims, leaf, batched):
         assert maxabs(Ff[ns:, :ns] - F21) <= 1e-11 * scale
         assert maxabs(Ff[ns:, ns:] - C) <= 1e-11 * scale
         gpu_cb[f] = Ff[ns:, ns:]
+    s.close()
+
+
+@pytest.mark.parametrize("dims,leaf,batched", [((8, 8, 8), 64, False), ((9, 7, 6), 40, True)])
+def test_row_interchanges_match_oracle(gpu_lib, dims, leaf, batched):
+    """The 7-point pattern with random complex values has no dominant diagonal, so most fronts
+    interchange rows (the Helmholtz fronts above never do): pivots equal the oracle's LAPACK partial
+    factorization of the same assembled front, the factored blocks match it, and the preconditioner
+    applies the interchanges like the oracle's solve."""
+    rp, ci, v, _ = helmholtz_7pt(dims, 0.05)
+    rng = rng_for("test", "coef", dims)
+    v = rng.standard_normal(v.shape[0]) + 1j * rng.standard_normal(v.shape[0])
+    s = gpu_lib.Solver(0).analyze(rp, ci, v, dims=dims, leaf_max=leaf, sep_leaf=16)
+    s.factor(n_min=0, batched=batched, keep_fronts=True)
+    od = nd.nd_grid(dims, leaf_max=leaf, sep_leaf=16)
+    sym = symbolic(rp, ci, od)
+    gpu_cb, moved = {}, 0
+    for f in range(od.nfronts):
+        ns = int(od.send[f] - od.sbeg[f])
+        Fa, Ff, piv = s.front(f, 0), s.front(f, 1), s.front(f, 2)
+        want = mf.assemble_front(rp, ci, v, od, sym, f, gpu_cb)
+        assert np.array_equal(Fa, want), f"front {f}: assembly differs"
+        lu, opiv, F12, F21, C = mf.partial_lu(want.copy(), ns)
+        assert np.array_equal(piv, opiv), f"front {f}: pivots differ"
+        moved += int(np.any(np.asarray(opiv) != np.arange(ns)))
+        scale = max(1.0, np.abs(want).max())
+        assert maxabs(Ff[:ns, :ns] - lu) <= 1e-10 * scale
+        assert maxabs(Ff[:ns, ns:] - F12) <= 1e-10 * scale
+        assert maxabs(Ff[ns:, :ns] - F21) <= 1e-10 * scale
+        assert maxabs(Ff[ns:, ns:] - C) <= 1e-10 * scale
+        gpu_cb[f] = Ff[ns:, ns:]
+    assert moved >= od.nfronts // 2, (moved, od.nfronts)
+    fac = mf.factor(rp, ci, v, od)
+    B = rng.standard_normal((od.n, 2)) + 1j * rng.standard_normal((od.n, 2))
+    X = s.precondition(B)
+    Xo = mf.solve(fac, B)
+    assert np.linalg.norm(X - Xo) <= 1e-9 * np.linalg.norm(Xo)
     s.close()
 
 
