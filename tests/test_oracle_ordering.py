@@ -4,7 +4,8 @@ Checked against the paper's worked 11^2 example (Sec. 5, Fig.
 'separator_ordering'), the closed-form root separator size of a k^3 grid
 (Sec. 6, Poisson paragraph: the top separator of a k^3 grid is k x k), the
 separator property, and a brute-force characterisation of I^u: the update set
-of a front is the set of vertices outside its subtree adjacent to it.
+of a front is the set of vertices outside its subtree adjacent to it; a box of
+exactly leaf_max nodes is a leaf and one node fewer in the bound splits it.
 """
 import json
 import os
@@ -179,3 +180,19 @@ def test_yee_structure_and_update_sets():
     c = meta["coords"][od.perm[od.sbeg[root]:od.send[root]]]
     assert np.all(c[:, 0] == 2 * (n // 2))
     assert c.shape[0] == 2 * n * (n - 1)  # y- and z-edges of one interior node plane
+
+
+@pytest.mark.parametrize("dims,leaf_max", [((8, 8, 8), 512), ((4, 4, 4), 64), ((5, 4, 3), 60), ((7, 1, 1), 7)])
+def test_box_of_exactly_leaf_max_nodes_is_a_leaf(dims, leaf_max):
+    """A box with at most leaf_max nodes is a leaf: exactly leaf_max nodes gives one front holding the
+    whole grid in natural order; one node fewer in the bound splits it at the middle plane of the
+    longest axis, and the root separator is that plane."""
+    n = dims[0] * dims[1] * dims[2]
+    od = nd.nd_grid(dims, leaf_max=leaf_max)
+    assert od.nfronts == 1 and od.leaf[0]
+    assert np.array_equal(np.asarray(od.perm), np.arange(n))
+    od2 = nd.nd_grid(dims, leaf_max=leaf_max - 1)
+    assert od2.nfronts > 1
+    a = int(np.argmax(dims))
+    root = od2.nfronts - 1
+    assert od2.send[root] - od2.sbeg[root] == n // dims[a]
