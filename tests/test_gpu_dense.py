@@ -95,6 +95,41 @@ def test_row_interchanges_match_oracle(gpu_lib, dims, leaf, batched):
     s.close()
 
 
+def test_front_taller_than_the_register_panel_with_interchanges(gpu_lib):
+    """A 33 x 32 x 33 grid has a 1056-node root separator: its first panel is factored by the
+    global-memory panel kernel (more than 1024 rows left), the later ones in registers. With random
+    values every front interchanges rows; pivots equal the oracle's and the factored blocks match it,
+    and one GMRES iteration with the exact factorization solves the system."""
+    dims = (33, 32, 33)
+    rp, ci, v, _ = helmholtz_7pt(dims, 0.05)
+    rng = rng_for("test", "coef", dims)
+    v = rng.standard_normal(v.shape[0]) + 1j * rng.standard_normal(v.shape[0])
+    s = gpu_lib.Solver(0).analyze(rp, ci, v, dims=dims, leaf_max=512, sep_leaf=64)
+    s.factor(n_min=0, batched=True, keep_fronts=True)
+    od = nd.nd_grid(dims, leaf_max=512, sep_leaf=64)
+    sym = symbolic(rp, ci, od)
+    assert max(int(od.send[f] - od.sbeg[f]) for f in range(od.nfronts)) > 1024
+    gpu_cb = {}
+    for f in range(od.nfronts):
+        ns = int(od.send[f] - od.sbeg[f])
+        Fa, Ff, piv = s.front(f, 0), s.front(f, 1), s.front(f, 2)
+        want = mf.assemble_front(rp, ci, v, od, sym, f, gpu_cb)
+        assert np.array_equal(Fa, want), f"front {f}: assembly differs"
+        lu, opiv, F12, F21, C = mf.partial_lu(want.copy(), ns)
+        assert np.array_equal(piv, opiv), f"front {f}: pivots differ"
+        scale = max(1.0, np.abs(want).max())
+        assert maxabs(Ff[:ns, :ns] - lu) <= 1e-9 * scale, f
+        assert maxabs(Ff[:ns, ns:] - F12) <= 1e-9 * scale, f
+        assert maxabs(Ff[ns:, :ns] - F21) <= 1e-9 * scale, f
+        assert maxabs(Ff[ns:, ns:] - C) <= 1e-9 * scale, f
+        gpu_cb[f] = Ff[ns:, ns:]
+    B = rng.standard_normal((od.n, 2)) + 1j * rng.standard_normal((od.n, 2))
+    X, info = s.solve(B)
+    assert info["status"] == 0 and info["iters"] <= 1
+    assert np.all(mf.rel_residual(rp, ci, v, X, B) <= 1e-10)
+    s.close()
+
+
 @pytest.mark.parametrize("dims,leaf,nrhs,batched", [((8, 8, 8), 64, 1, False), ((10, 9, 8), 64, 3, True),
                                                     ((12, 12, 12), 100, 70, True), ((2, 2, 2), 512, 2, False)])
 def test_preconditioner_matches_oracle_solve(gpu_lib, dims, leaf, nrhs, batched):
