@@ -133,6 +133,13 @@ def test_grid_structure_and_update_sets(dims, leaf):
         ns = od.send[p] - od.sbeg[p]
         full = np.concatenate([np.arange(od.sbeg[p], od.send[p]), sym.Iu[p]])
         assert np.array_equal(full[m], sym.Iu[f])
+    # inverse maps: parent-local position -> child-local index, -1 where the child has no entry
+    for f in range(od.nfronts):
+        for k, c in enumerate(od.children[f]):
+            inv = sym.invmaps[f][k]
+            assert inv.shape[0] == (od.send[f] - od.sbeg[f]) + sym.Iu[f].shape[0]
+            assert np.array_equal(inv[sym.maps[c]], np.arange(sym.maps[c].shape[0]))
+            assert np.count_nonzero(inv >= 0) == sym.maps[c].shape[0] and np.all(inv >= -1)
 
 
 def test_24_cubed_tree_matches_stated_shape():
