@@ -6,7 +6,8 @@
 * Partial LU (kernel d): the factored front matches the oracle's LAPACK
   partial factorization of the same assembled front (pivots equal, values
   to 1e-11 relative), also on a pattern with random values where most fronts
-  interchange rows.
+  interchange rows, and for a 1056-row front whose first panel runs in the
+  global-memory panel kernel.
 * Sweeps (kernel e) and GMRES: x matches the oracle's solve to 1e-10; with
   the exact factorization GMRES stops after one iteration.
 """
