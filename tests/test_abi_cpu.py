@@ -131,3 +131,17 @@ def test_one_hip_runtime_per_process():
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_hip_sources_are_built_for_gfx950_without_packed_fp32():
+    """Every HIP source is compiled for gfx950 with the packed-FP32 instructions switched off (the
+    compiler would otherwise emit them from plain float code), and the build covers every .hip and
+    .cpp file under csrc."""
+    from paper_2007_00202_amd import build as b
+    flags = " ".join(b.FLAGS)
+    assert "--offload-arch=gfx950" in flags
+    assert "-Xclang -target-feature -Xclang -packed-fp32-ops" in flags
+    srcs = {os.path.relpath(s, b.CSRC) for s in b.sources()}
+    on_disk = {os.path.relpath(os.path.join(d, f), b.CSRC) for d, _, fs in os.walk(b.CSRC) for f in fs
+               if f.endswith((".hip", ".cpp"))}
+    assert srcs == on_disk and any(s.endswith(".hip") for s in srcs)
