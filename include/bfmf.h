@@ -52,7 +52,7 @@ typedef enum {
     BFMF_E_DEVICE = -6    /* HIP runtime error */
 } bfmf_status;
 
-enum { BFMF_ORD_GRID = 0, BFMF_ORD_YEE = 1 };
+enum { BFMF_ORD_GRID = 0, BFMF_ORD_YEE = 1, BFMF_ORD_USER = 2 };
 enum { BFMF_C128 = 0, BFMF_C64_MIXED = 1 };
 enum { BFMF_HOST = 0, BFMF_DEVICE = 1 };
 
@@ -69,7 +69,21 @@ enum { BFMF_HOST = 0, BFMF_DEVICE = 1 };
  *       levels of the tree are cut across the grid's longest axis (while its
  *       extent in the box is at least 3), so those separators are parallel
  *       planes: F12/F21 of their fronts couple well-separated planes.  E_INVAL
- *       if negative, or nonzero with YEE. */
+ *       if negative, or nonzero with YEE or USER.
+ * USER: the caller's ordering and assembly tree (the "given ordering" of the
+ *       problem statement, Sec. 2): perm[n] maps new index -> original index;
+ *       front f owns the separator [front_ptr[f], front_ptr[f+1]) of the new
+ *       numbering (nfronts + 1 entries, front_ptr[0] = 0, strictly increasing,
+ *       front_ptr[nfronts] = n); front_parent[f] is its parent, -1 for the
+ *       root.  The tree must be in postorder: every parent after its children,
+ *       the root last and alone, each subtree a contiguous run of fronts
+ *       ending at its root.  Fronts without children are leaves (never
+ *       compressed).  Each separator's HOD-BF tree halves its index range
+ *       (first half ceil) down to sep_leaf, so the caller orders a separator
+ *       the way its bisection should go (P-hat, Sec. 5.1).  E_INVAL when perm
+ *       is not a bijection, the tree is not in postorder, or the separator
+ *       property fails (an edge of A, or fill, between two fronts neither of
+ *       which is an ancestor of the other).  The arrays are copied. */
 typedef struct {
     int32_t kind;
     int32_t nx, ny, nz;
@@ -77,6 +91,10 @@ typedef struct {
     int32_t leaf_max; /* default 512 */
     int32_t sep_leaf; /* default 64 */
     int32_t parallel_levels; /* default 0 */
+    int32_t nfronts;              /* USER only */
+    const int64_t* perm;          /* USER only: [n] */
+    const int64_t* front_ptr;     /* USER only: [nfronts + 1] */
+    const int32_t* front_parent;  /* USER only: [nfronts] */
 } bfmf_ordering;
 
 /* Numerical factorization options (Alg. 5; Sec. 3.1 for alpha and k_nn). */
@@ -93,7 +111,11 @@ typedef struct {
     int32_t keep_fronts; /* debug: keep a copy of every assembled dense front, and every
                             factored front whole (no reuse of the level workspaces) */
     int32_t timing;      /* 1: time every kernel class with HIP events (bfmf_get_kernel_stats) */
-    int32_t reserved[6];
+    int32_t smw_dense;   /* HODBF_invert (Alg. 4): BF_SMW blocks of at most this many rows are
+                            inverted densely (FP64 partial LU of the bordered block), larger ones
+                            are split into four children butterflies; 0 means 1024, values in
+                            1..15 are E_INVAL */
+    int32_t reserved[5];
 } bfmf_factor_opts;
 
 /* GMRES options (Sec. 6): restarted GMRES(restart), modified Gram-Schmidt,
@@ -210,6 +232,22 @@ bfmf_status bfmf_get_stats(bfmf_handle h, bfmf_stats* out);
  * n = #I^s + #I^u of the front; out has leading dimension ld >= n.
  * E_INVAL for compressed fronts or out-of-range arguments. */
 bfmf_status bfmf_get_front(bfmf_handle h, int32_t front, int32_t what, void* out, int64_t ld);
+
+/* Debug access to a compressed front after bfmf_factor: Y = B X for one of
+ * its blocks, all in the front's local numbering (I^s in P-hat order, then
+ * I^u sorted), so that the blocks can be compared with the dense ones:
+ *   what = 0: F11 as the HOD-BF built by entry evaluation (Sec. 4.1), ns x ns
+ *   what = 1: F11^-1 as built by HODBF_invert (Alg. 4), ns x ns
+ *   what = 2: F12 (butterfly, Alg. 2), ns x nu
+ *   what = 3: F21 (butterfly, Alg. 2), nu x ns
+ *   what = 4: S = F21 F11^-1 F12 by randomized construction (Sec. 3.3), nu x nu
+ * X (columns of B x nrhs, ld ldx) and Y (rows of B x nrhs, ld ldy) are host
+ * arrays of interleaved complex128, column-major; in the complex64 form X is
+ * rounded to complex64 before the product.  E_INVAL if the front is not
+ * compressed, for what outside 0..4, for 2..4 on a front with an empty
+ * update set, or for bad sizes; E_STATE before bfmf_factor. */
+bfmf_status bfmf_apply_front_block(bfmf_handle h, int32_t front, int32_t what, int32_t nrhs, const double* X,
+                                   int64_t ldx, double* Y, int64_t ldy);
 
 /* Per kernel-class timing, collected with HIP events on the handle's stream
  * while bfmf_factor_opts.timing is set (factor and solve calls accumulate).

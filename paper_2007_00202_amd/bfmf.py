@@ -26,7 +26,7 @@ _lib = C.CDLL(LIB_PATH)
 # --------------------------------------------------------------- constants
 BFMF_OK, BFMF_E_INVAL, BFMF_E_NOMEM, BFMF_E_STATE = 0, -1, -2, -3
 BFMF_E_SINGULAR, BFMF_E_NOCONV, BFMF_E_DEVICE = -4, -5, -6
-BFMF_ORD_GRID, BFMF_ORD_YEE = 0, 1
+BFMF_ORD_GRID, BFMF_ORD_YEE, BFMF_ORD_USER = 0, 1, 2
 BFMF_C128, BFMF_C64_MIXED = 0, 1
 BFMF_HOST, BFMF_DEVICE = 0, 1
 
@@ -34,14 +34,16 @@ BFMF_HOST, BFMF_DEVICE = 0, 1
 class bfmf_ordering(C.Structure):
     _fields_ = [("kind", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("coords", C.POINTER(C.c_int32)), ("leaf_max", C.c_int32), ("sep_leaf", C.c_int32),
-                ("parallel_levels", C.c_int32)]
+                ("parallel_levels", C.c_int32), ("nfronts", C.c_int32), ("perm", C.POINTER(C.c_int64)),
+                ("front_ptr", C.POINTER(C.c_int64)), ("front_parent", C.POINTER(C.c_int32))]
 
 
 class bfmf_factor_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("n_min", C.c_int64), ("precision", C.c_int32),
                 ("batched", C.c_int32), ("samples", C.c_int32), ("knn", C.c_int32),
                 ("alpha", C.c_double), ("seed", C.c_uint64), ("hbm_budget", C.c_uint64),
-                ("keep_fronts", C.c_int32), ("timing", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("keep_fronts", C.c_int32), ("timing", C.c_int32), ("smw_dense", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class bfmf_kernel_stat(C.Structure):
@@ -105,6 +107,7 @@ _SIGS = {
     "bfmf_get_symbolic": (C.c_int, [_h, C.POINTER(bfmf_symbolic_view)]),
     "bfmf_get_stats": (C.c_int, [_h, C.POINTER(bfmf_stats)]),
     "bfmf_get_front": (C.c_int, [_h, C.c_int32, C.c_int32, _P, C.c_int64]),
+    "bfmf_apply_front_block": (C.c_int, [_h, C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64]),
     "bfmf_get_kernel_stats": (C.c_int, [_h, C.c_int32, C.POINTER(bfmf_kernel_stat)]),
     "bfmf_reset_kernel_stats": (C.c_int, [_h]),
     "bfmf_set_gemm_tile": (C.c_int, [C.c_int32]),
@@ -161,14 +164,21 @@ def bfmf_create(device=0, stream=None):
 
 
 def bfmf_analyze(h, rowptr, colind, values, kind=BFMF_ORD_GRID, dims=(0, 0, 0), coords=None,
-                 leaf_max=512, sep_leaf=64, parallel_levels=0):
+                 leaf_max=512, sep_leaf=64, parallel_levels=0, perm=None, front_ptr=None, front_parent=None):
     rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
     colind = np.ascontiguousarray(colind, dtype=np.int32)
     vals = None if values is None else np.ascontiguousarray(values, dtype=np.complex128)
     cc = None if coords is None else np.ascontiguousarray(coords, dtype=np.int32)
+    pm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
+    fp = None if front_ptr is None else np.ascontiguousarray(front_ptr, dtype=np.int64)
+    fpar = None if front_parent is None else np.ascontiguousarray(front_parent, dtype=np.int32)
     o = bfmf_ordering(kind, dims[0], dims[1], dims[2],
                       cc.ctypes.data_as(C.POINTER(C.c_int32)) if cc is not None else None,
-                      leaf_max, sep_leaf, parallel_levels)
+                      leaf_max, sep_leaf, parallel_levels,
+                      0 if fpar is None else fpar.shape[0],
+                      pm.ctypes.data_as(C.POINTER(C.c_int64)) if pm is not None else None,
+                      fp.ctypes.data_as(C.POINTER(C.c_int64)) if fp is not None else None,
+                      fpar.ctypes.data_as(C.POINTER(C.c_int32)) if fpar is not None else None)
     _check(h, _lib.bfmf_analyze(h, rowptr.shape[0] - 1, _ptr(rowptr), _ptr(colind), _ptr(vals), C.byref(o)))
 
 
@@ -268,6 +278,17 @@ def bfmf_get_front(h, front, what, n):
     return out
 
 
+def bfmf_apply_front_block(h, front, what, X, rows):
+    """Y = B X for a block of a compressed front (0 F11, 1 F11^-1, 2 F12, 3 F21, 4 S); rows of B given."""
+    X = np.asfortranarray(X, dtype=np.complex128)
+    if X.ndim == 1:
+        X = X[:, None]
+    Y = np.zeros((rows, X.shape[1]), dtype=np.complex128, order="F")
+    _check(h, _lib.bfmf_apply_front_block(h, front, what, X.shape[1], _ptr(X), max(X.shape[0], 1), _ptr(Y),
+                                          max(rows, 1)))
+    return Y
+
+
 def bfmf_get_kernel_stats(h):
     out = {}
     for k in range(BFMF_KERNEL_CLASSES):
@@ -355,8 +376,11 @@ class Solver:
         self.n = None
 
     def analyze(self, rowptr, colind, values, dims=None, coords=None, cells=None, leaf_max=512, sep_leaf=64,
-                parallel_levels=0):
-        if coords is not None:
+                parallel_levels=0, perm=None, front_ptr=None, front_parent=None):
+        if perm is not None:  # the caller's ordering and assembly tree
+            bfmf_analyze(self.h, rowptr, colind, values, BFMF_ORD_USER, (0, 0, 0), None, leaf_max, sep_leaf,
+                         parallel_levels, perm, front_ptr, front_parent)
+        elif coords is not None:
             bfmf_analyze(self.h, rowptr, colind, values, BFMF_ORD_YEE, (cells, 0, 0), coords, leaf_max, sep_leaf,
                          parallel_levels)
         else:
@@ -366,8 +390,9 @@ class Solver:
         return self
 
     def factor(self, tol=1e-3, n_min=1024, precision=BFMF_C128, batched=False, samples=64, knn=8,
-               alpha=2.0, seed=0, hbm_budget=0, keep_fronts=False, timing=False):
+               alpha=2.0, seed=0, hbm_budget=0, keep_fronts=False, timing=False, smw_dense=0):
         o = bfmf_default_factor_opts()
+        o.smw_dense = smw_dense
         o.timing = int(bool(timing))
         o.tol, o.n_min, o.precision, o.batched = tol, n_min, precision, int(bool(batched))
         o.samples, o.knn, o.alpha, o.seed = samples, knn, alpha, seed
@@ -403,6 +428,13 @@ class Solver:
         if what == 2:
             n = int(sym["send"][f] - sym["sbeg"][f])
         return bfmf_get_front(self.h, f, what, n)
+
+    def front_block(self, f, what, X):
+        """Y = B X for block `what` of compressed front f (0 F11, 1 F11^-1, 2 F12, 3 F21, 4 S)."""
+        sym = self.symbolic()
+        ns = int(sym["send"][f] - sym["sbeg"][f])
+        nu = int(sym["iu_ptr"][f + 1] - sym["iu_ptr"][f])
+        return bfmf_apply_front_block(self.h, f, what, X, ns if what <= 2 else nu)
 
     def close(self):
         if self.h:

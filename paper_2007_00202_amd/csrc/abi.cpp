@@ -144,6 +144,9 @@ bfmf_status bfmf_analyze(bfmf_handle h, int64_t n, const int64_t* rowptr, const 
     } else if (ord->kind == BFMF_ORD_YEE) {
       if (ord->parallel_levels != 0) throw Error(BFMF_E_INVAL, "analyze: parallel_levels applies to GRID orderings");
       ok = nd_yee(ord->nx, n, ord->coords, leaf, sl, h->sym, err);
+    } else if (ord->kind == BFMF_ORD_USER) {
+      if (ord->parallel_levels != 0) throw Error(BFMF_E_INVAL, "analyze: parallel_levels applies to GRID orderings");
+      ok = nd_user(n, ord->perm, ord->nfronts, ord->front_ptr, ord->front_parent, sl, h->sym, err);
     } else {
       throw Error(BFMF_E_INVAL, "analyze: unknown ordering kind");
     }
@@ -180,7 +183,8 @@ bfmf_status bfmf_factor(bfmf_handle h, const bfmf_factor_opts* opts) {
       o = *opts;
     else
       bfmf_default_factor_opts(&o);
-    if (!(o.tol > 0) || o.samples < 0 || o.knn < 0 || o.alpha < 0)
+    if (!(o.tol > 0) || o.samples < 0 || o.knn < 0 || o.alpha < 0 || o.smw_dense < 0 ||
+        (o.smw_dense > 0 && o.smw_dense < 16))
       throw Error(BFMF_E_INVAL, "factor: bad options");
     if (o.precision != BFMF_C128 && o.precision != BFMF_C64_MIXED)
       throw Error(BFMF_E_INVAL, "factor: unknown precision");
@@ -316,6 +320,16 @@ bfmf_status bfmf_get_front(bfmf_handle h, int32_t front, int32_t what, void* out
     if (p.ns > 0 && p.nu > 0)
       HIPCHK(hipMemcpy2D(o + p.ns * ld * elem, ld * elem, P + (int64_t)p.n * p.ns * elem, p.ns * elem, p.ns * elem,
                          p.nu, hipMemcpyDeviceToHost));
+  });
+}
+
+bfmf_status bfmf_apply_front_block(bfmf_handle h, int32_t front, int32_t what, int32_t nrhs, const double* X,
+                                   int64_t ldx, double* Y, int64_t ldy) {
+  return guarded(h, [&] {
+    if (h->state != State::Factored) throw Error(BFMF_E_STATE, "apply_front_block before factor");
+    if (front < 0 || front >= h->sym.nfronts()) throw Error(BFMF_E_INVAL, "apply_front_block: bad front");
+    if (!h->compressed[front] || !h->comp) throw Error(BFMF_E_INVAL, "apply_front_block: front is not compressed");
+    comp_apply_block(h->comp, front, what, nrhs, X, ldx, Y, ldy);
   });
 }
 

@@ -265,6 +265,99 @@ bool nd_yee(int32_t ncell, int64_t n, const int32_t* coords, int32_t leaf_max, i
   return true;
 }
 
+bool nd_user(int64_t n, const int64_t* perm, int32_t nfronts, const int64_t* front_ptr, const int32_t* front_parent,
+             int32_t sep_leaf, Symbolic& s, std::string& err) {
+  if (n <= 0 || !perm || nfronts <= 0 || !front_ptr || !front_parent || sep_leaf <= 0) {
+    err = "user ordering: null array or non-positive size";
+    return false;
+  }
+  std::vector<uint8_t> seen(n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    if (perm[i] < 0 || perm[i] >= n || seen[perm[i]]) {
+      err = "user ordering: perm is not a permutation of 0..n-1";
+      return false;
+    }
+    seen[perm[i]] = 1;
+  }
+  if (front_ptr[0] != 0 || front_ptr[nfronts] != n) {
+    err = "user ordering: front_ptr must start at 0 and end at n";
+    return false;
+  }
+  for (int32_t f = 0; f < nfronts; ++f)
+    if (front_ptr[f + 1] <= front_ptr[f]) {
+      err = "user ordering: every front needs at least one separator unknown (front_ptr increasing)";
+      return false;
+    }
+  // postorder: parent after child, one root (the last front), and the subtree of every front is the
+  // contiguous run of fronts [first[f], f]: children in increasing order, each starting right after
+  // the previous one's subtree
+  if (front_parent[nfronts - 1] != -1) {
+    err = "user ordering: the last front must be the root";
+    return false;
+  }
+  std::vector<std::vector<int32_t>> kids(nfronts);
+  for (int32_t f = 0; f + 1 < nfronts; ++f) {
+    const int32_t p = front_parent[f];
+    if (p <= f || p >= nfronts) {
+      err = "user ordering: front tree not in postorder (parent must follow its child; one root)";
+      return false;
+    }
+    kids[p].push_back(f);
+  }
+  std::vector<int32_t> first(nfronts);
+  for (int32_t f = 0; f < nfronts; ++f) {
+    int32_t next = -1;
+    for (int32_t c : kids[f]) {
+      if (next >= 0 && first[c] != next) {
+        err = "user ordering: front tree not in postorder (subtrees interleave)";
+        return false;
+      }
+      if (next < 0) first[f] = first[c];
+      next = c + 1;
+    }
+    if (kids[f].empty()) first[f] = f;
+    else if (next != f) {
+      err = "user ordering: front tree not in postorder (a subtree does not end right before its root)";
+      return false;
+    }
+  }
+  s = Symbolic();
+  s.n = n;
+  s.perm.assign(perm, perm + n);
+  FrontBuilder fb(s);
+  for (int32_t f = 0; f < nfronts; ++f) {
+    // fb.add_front takes the separator as [beg, perm.size()): perm is already whole, so set the
+    // range directly afterwards
+    const int32_t ns = (int32_t)(front_ptr[f + 1] - front_ptr[f]);
+    fb.add_front(front_ptr[f], kids[f].empty(), kids[f], balanced_tree(ns, sep_leaf));
+    s.send[f] = front_ptr[f + 1];
+  }
+  fb.finish();
+  return true;
+}
+
+bool separator_property(const Symbolic& s, std::string& err) {
+  // every index of I^u_f lies in the separator of an ancestor of f (no edge of A, and no fill,
+  // between two subtrees that are not nested); in postorder g is an ancestor of f iff
+  // first[g] <= f < g, first[g] being the first front of g's subtree
+  const int32_t nf = s.nfronts();
+  std::vector<int32_t> owner(s.n), first(nf);
+  for (int32_t f = 0; f < nf; ++f) {
+    for (int64_t i = s.sbeg[f]; i < s.send[f]; ++i) owner[i] = f;
+    first[f] = s.child_ptr[f + 1] > s.child_ptr[f] ? first[s.child_list[s.child_ptr[f]]] : f;
+  }
+  for (int32_t f = 0; f < nf; ++f)
+    for (int64_t t = s.iu_ptr[f]; t < s.iu_ptr[f + 1]; ++t) {
+      const int32_t g = owner[s.iu[t]];
+      if (!(first[g] <= f && f < g)) {
+        err = "ordering: the separator property fails (front " + std::to_string(f) + " couples to front " +
+              std::to_string(g) + ", which is not one of its ancestors)";
+        return false;
+      }
+    }
+  return true;
+}
+
 bool symbolic_phase(int64_t n, const int64_t* rowptr, const int32_t* colind, Symbolic& s, std::string& err) {
   if (n != s.n) {
     err = "symbolic: matrix size does not match the ordering";
@@ -314,6 +407,7 @@ bool symbolic_phase(int64_t n, const int64_t* rowptr, const int32_t* colind, Sym
     s.iu.insert(s.iu.end(), cand.begin(), cand.end());
     s.iu_ptr[f + 1] = (int64_t)s.iu.size();
   }
+  if (!separator_property(s, err)) return false;
   s.map.assign(s.iu.size(), 0);
   for (int32_t f = 0; f < nf; ++f) {
     int32_t p = s.parent[f];

@@ -47,6 +47,19 @@ bool nd_grid(int32_t nx, int32_t ny, int32_t nz, int32_t leaf_max, int32_t sep_l
 bool nd_yee(int32_t ncell, int64_t n, const int32_t* coords, int32_t leaf_max,
             int32_t sep_leaf, Symbolic& s, std::string& err);
 
+// Caller-supplied ordering: perm (new -> old), the separator of front f is
+// [front_ptr[f], front_ptr[f+1]) of the new numbering, front_parent[f] its
+// parent (-1 at the root).  The tree must be in postorder with the root last;
+// each separator is bisected by halving its index range (first half ceil)
+// down to sep_leaf.  Returns false with a message on a malformed ordering.
+bool nd_user(int64_t n, const int64_t* perm, int32_t nfronts, const int64_t* front_ptr, const int32_t* front_parent,
+             int32_t sep_leaf, Symbolic& s, std::string& err);
+
+// Every update index of a front belongs to an ancestor's separator (the
+// property nested dissection guarantees); checked by symbolic_phase once the
+// update sets are known.
+bool separator_property(const Symbolic& s, std::string& err);
+
 // I^u, extend-add maps and levels from the pattern of A + A^T.
 bool symbolic_phase(int64_t n, const int64_t* rowptr, const int32_t* colind, Symbolic& s,
                     std::string& err);

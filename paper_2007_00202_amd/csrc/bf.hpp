@@ -172,6 +172,7 @@ struct BfRuntime {
   uint64_t seed = 0, stream_id = 0;
   int samples = 64;
   int max_samples = 1024;
+  int smw_dense = 1024;               // BF_SMW blocks of at most this many rows are inverted densely
   double tol = 1e-3;
   int max_rank_seen = 0;
   int64_t n_random = 0, n_entry = 0;  // constructions performed

@@ -368,16 +368,6 @@ struct HodbfInvOp : Op<T> {
   }
 };
 
-// blocks up to this size are inverted densely inside BF_SMW (BFMF_SMW_DENSE overrides, for tuning)
-int smw_dense_limit() {
-  static const int v = [] {
-    const char* e = std::getenv("BFMF_SMW_DENSE");
-    const int x = e ? std::atoi(e) : 0;
-    return x >= 16 ? x : 1024;  // measured on the 100^3 workload: 1024 beats 128, 256, 512 and 2048
-  }();
-  return v;
-}
-
 struct SmwResult {
   std::unique_ptr<Butterfly> bf;
   int64_t dense_off = -1;
@@ -708,7 +698,7 @@ void smw_batch(BfRuntime<T>& rt, const std::vector<SmwJob<T>*>& jobs, int* d_sta
   std::vector<SmwJob<T>*> dense, rec;
   for (auto* j : jobs) {
     const TreeNode& nd = (*j->nodes)[j->node];
-    const bool base = depth_of(*j->nodes, j->node) == 0 || nd.end - nd.beg <= smw_dense_limit();
+    const bool base = depth_of(*j->nodes, j->node) == 0 || nd.end - nd.beg <= rt.smw_dense;
     (base ? dense : rec).push_back(j);
   }
   smw_dense_batch<T>(rt, dense, d_status);
@@ -847,6 +837,8 @@ static void reset_state(CompState<T>& st, Context& c, int nfronts) {
   st.rt.max_rank_seen = 0;
   st.rt.sample_hint.clear();
   st.rt.batch = c.fopts.batched != 0;
+  // measured on the 100^3 workload: a dense base of 1024 rows beats 128, 256, 512 and 2048
+  st.rt.smw_dense = c.fopts.smw_dense > 0 ? c.fopts.smw_dense : 1024;
   if (!st.status.p) {
     HIPCHK(dev_malloc((void**)&st.status.p, 16));
     st.status.bytes = 16;
@@ -1529,6 +1521,57 @@ void backward_compressed_level(void* state, Context& c, const std::vector<int>& 
     backward_level<float>(*h->f, fs, Ws, ns, nrhs);
   else
     backward_level<double>(*h->d, fs, Ws, ns, nrhs);
+}
+
+// Y = B X for one block of a compressed front (debug access): 0 F11, 1 F11^-1,
+// 2 F12, 3 F21, 4 S.  X and Y are host arrays of interleaved complex128.
+template <class T>
+static void apply_block(CompState<T>& st, int f, int what, int nrhs, const double* X, int64_t ldx, double* Y,
+                        int64_t ldy) {
+  BfRuntime<T>& rt = st.rt;
+  if (f < 0 || f >= (int)st.fronts.size() || !st.fronts[f]) throw Error(BFMF_E_INVAL, "front is not compressed");
+  CompressedFront<T>& cf = *st.fronts[f];
+  const int ns = cf.ns, nu = cf.nu;
+  const int rows = (what <= 2) ? ns : nu, cols = (what == 0 || what == 1 || what == 3) ? ns : nu;
+  if (what < 0 || what > 4) throw Error(BFMF_E_INVAL, "apply_front_block: bad 'what'");
+  if (what >= 2 && nu == 0) throw Error(BFMF_E_INVAL, "apply_front_block: the front has no update set");
+  if (nrhs <= 0 || ldx < cols || ldy < rows || !X || !Y) throw Error(BFMF_E_INVAL, "apply_front_block: bad arguments");
+  hipStream_t s = rt.s();
+  std::vector<cplx<T>> hx((size_t)cols * nrhs), hy((size_t)rows * nrhs);
+  for (int j = 0; j < nrhs; ++j)
+    for (int i = 0; i < cols; ++i) {
+      const double* p = X + 2 * ((size_t)j * ldx + i);
+      hx[(size_t)j * cols + i] = cplx<T>{(T)p[0], (T)p[1]};
+    }
+  auto mk = rt.scratch.mark();
+  cplx<T>* dx = (cplx<T>*)rt.scratch.take(hx.size() * sizeof(cplx<T>));
+  cplx<T>* dy = (cplx<T>*)rt.scratch.take(hy.size() * sizeof(cplx<T>));
+  ochk(hipMemcpyAsync(dx, hx.data(), hx.size() * sizeof(cplx<T>), hipMemcpyHostToDevice, s), "upload");
+  switch (what) {
+    case 0: hodbf_apply<T>(rt, cf.f11, dx, cols, dy, rows, nrhs); break;
+    case 1: hodbf_inv_apply<T>(rt, cf.f11, 0, dx, cols, dy, rows, nrhs, false); break;
+    case 2: rt.apply(*cf.f12, dx, cols, dy, rows, nrhs, false, 1.0, 0); break;
+    case 3: rt.apply(*cf.f21, dx, cols, dy, rows, nrhs, false, 1.0, 0); break;
+    default: rt.apply(*cf.s, dx, cols, dy, rows, nrhs, false, 1.0, 0); break;
+  }
+  ochk(hipMemcpyAsync(hy.data(), dy, hy.size() * sizeof(cplx<T>), hipMemcpyDeviceToHost, s), "download");
+  ochk(hipStreamSynchronize(s), "sync");
+  rt.scratch.release(mk);
+  for (int j = 0; j < nrhs; ++j)
+    for (int i = 0; i < rows; ++i) {
+      double* p = Y + 2 * ((size_t)j * ldy + i);
+      p[0] = (double)hy[(size_t)j * rows + i].re;
+      p[1] = (double)hy[(size_t)j * rows + i].im;
+    }
+}
+
+void comp_apply_block(void* state, int f, int what, int nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy) {
+  auto* h = (CompHolder*)state;
+  if (!h) throw Error(BFMF_E_INVAL, "no compressed fronts");
+  if (h->single)
+    apply_block<float>(*h->f, f, what, nrhs, X, ldx, Y, ldy);
+  else
+    apply_block<double>(*h->d, f, what, nrhs, X, ldx, Y, ldy);
 }
 
 template <class T>

@@ -255,6 +255,7 @@ struct Context {
   DevBuf g_tmp_scatter;  // task list of a level's batched scatter in the backward sweep (one per front)
   Staging stage;      // pinned ring of host-to-device uploads
   int64_t g_nrhs = 0, g_restart = 0;
+  void* g_Vp = nullptr;  // Krylov basis: g_V, or the idle level workspace d_work when it is large enough
 
   KernelTimer timer;
 
@@ -298,6 +299,8 @@ void backward_compressed_level(void* state, Context& c, const std::vector<int>& 
                                const std::vector<void*>& Ws, const std::vector<int>& ns, int nrhs);
 void compressed_stats(void* state, double& bytes, int& maxrank);
 uint64_t comp_state_bytes(void* state);  // device bytes held by the compressed fronts' pools
+// Y = B X for a block of compressed front f (0 F11, 1 F11^-1, 2 F12, 3 F21, 4 S); host complex128 arrays
+void comp_apply_block(void* state, int f, int what, int nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy);
 
 // plan.cpp
 void build_plan(Context& c);

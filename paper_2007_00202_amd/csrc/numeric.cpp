@@ -623,8 +623,18 @@ static bool apply_preconditioner_graph(Context& c, const void* in, void* out, in
 void gmres_workspace(Context& c, int64_t nrhs, int m) {
   const size_t elem = 2 * sizeof(double);
   const size_t blk = (size_t)c.n * nrhs * elem;
+  const size_t vbytes = blk * (m + 1);
+  // The Krylov basis takes the level workspace of the factorization when that is large enough: the
+  // workspace holds fronts only while bfmf_factor runs (128^3 with 32 columns: 33 GB of basis inside
+  // 62 GB of workspace).  A later factorization invalidates the captured preconditioner graph anyway.
+  if (!c.fopts.keep_fronts && c.d_work.bytes >= vbytes) {
+    c.g_V.release();
+    c.g_Vp = c.d_work.p;
+  } else {
+    if (c.g_V.bytes < vbytes) alloc(c.g_V, vbytes);
+    c.g_Vp = c.g_V.p;
+  }
   if (c.g_nrhs < nrhs || c.g_restart < m) {
-    alloc(c.g_V, blk * (m + 1));
     alloc(c.g_w, blk);
     alloc(c.g_r, blk);
     alloc(c.g_tmp, blk);
@@ -644,7 +654,7 @@ int gmres_dev(Context& c, const void* dB, int64_t ldb, void* dX, int64_t ldx, in
   const bool use_graph = o.graphs != 0;  // replay the preconditioner of the iterations from a HIP graph
   size_t stage_bytes = 0;
   const int nblk = (int)std::min<int64_t>(256, (N + 255) / 256);
-  cd* V = c.g_V.as<cd>();
+  cd* V = (cd*)c.g_Vp;
   cd* w = c.g_w.as<cd>();
   cd* r = c.g_r.as<cd>();
   cd* tmp = c.g_tmp.as<cd>();

@@ -145,3 +145,82 @@ def test_hip_sources_are_built_for_gfx950_without_packed_fp32():
     on_disk = {os.path.relpath(os.path.join(d, f), b.CSRC) for d, _, fs in os.walk(b.CSRC) for f in fs
                if f.endswith((".hip", ".cpp"))}
     assert srcs == on_disk and any(s.endswith(".hip") for s in srcs)
+
+
+def _user_arrays(od):
+    front_ptr = np.concatenate([np.asarray(od.sbeg, np.int64), [od.n]])
+    return np.asarray(od.perm, np.int64), front_ptr, np.asarray(od.parent, np.int32)
+
+
+@pytest.mark.parametrize("dims,leaf,sl", [((8, 8, 8), 64, 16), ((7, 5, 9), 20, 16), ((12, 12, 12), 100, 16)])
+def test_user_ordering_reproduces_the_oracle_structures(dims, leaf, sl):
+    """A caller-supplied ordering (here the oracle's nested dissection, passed as perm plus front
+    tree) gives the oracle's update sets and extend-add maps; each separator's tree halves its
+    index range (the balanced tree of the oracle)."""
+    rp, ci, v, _ = helmholtz_7pt(dims, 0.05)
+    od = nd.nd_grid(dims, leaf_max=leaf, sep_leaf=sl)
+    sym = symbolic(rp, ci, od)
+    perm, fptr, par = _user_arrays(od)
+    h = bfmf.bfmf_create(-1)
+    try:
+        bfmf.bfmf_analyze(h, rp, ci, v, kind=bfmf.BFMF_ORD_USER, sep_leaf=sl, perm=perm, front_ptr=fptr,
+                          front_parent=par)
+        s = bfmf.bfmf_get_symbolic(h)
+        assert np.array_equal(s["perm"], od.perm)
+        assert np.array_equal(s["sbeg"], od.sbeg) and np.array_equal(s["send"], od.send)
+        assert np.array_equal(s["parent"], od.parent)
+        kids = [list(s["child_list"][s["child_ptr"][f]:s["child_ptr"][f + 1]]) for f in range(od.nfronts)]
+        assert kids == [list(c) for c in od.children]
+        for f in range(od.nfronts):
+            assert np.array_equal(s["iu"][s["iu_ptr"][f]:s["iu_ptr"][f + 1]], sym.Iu[f])
+            assert np.array_equal(s["map"][s["iu_ptr"][f]:s["iu_ptr"][f + 1]], sym.maps[f])
+            nodes = s["sep_nodes"][s["sep_ptr"][f]:s["sep_ptr"][f + 1]]
+            assert nodes.tolist() == nd.balanced_tree(int(od.send[f] - od.sbeg[f]), sl)
+    finally:
+        bfmf.bfmf_destroy(h)
+
+
+def test_user_ordering_rejects_malformed_input():
+    dims = (8, 8, 8)
+    rp, ci, v, _ = helmholtz_7pt(dims, 0.05)
+    od = nd.nd_grid(dims, leaf_max=64, sep_leaf=16)
+    perm, fptr, par = _user_arrays(od)
+    root = od.nfronts - 1
+    left, right = od.children[root]
+
+    def bad(**kw):
+        a = dict(perm=perm, front_ptr=fptr, front_parent=par)
+        a.update(kw)
+        h = bfmf.bfmf_create(-1)
+        try:
+            with pytest.raises(bfmf.BfmfError) as e:
+                bfmf.bfmf_analyze(h, rp, ci, v, kind=bfmf.BFMF_ORD_USER, sep_leaf=16, **a)
+            assert e.value.status == bfmf.BFMF_E_INVAL
+            return bfmf.bfmf_last_error(h)
+        finally:
+            bfmf.bfmf_destroy(h)
+
+    p2 = perm.copy()
+    p2[3] = p2[4]
+    assert "permutation" in bad(perm=p2)
+    q = par.copy()
+    q[0] = -1  # a second root
+    assert "postorder" in bad(front_parent=q)
+    q = par.copy()
+    q[left] = 0  # parent before its child
+    assert "postorder" in bad(front_parent=q)
+    # interleaved subtrees: the first leaf of the left subtree moved under the right child
+    first_leaf = 0
+    q = par.copy()
+    q[first_leaf] = right
+    assert "postorder" in bad(front_parent=q)
+    f2 = fptr.copy()
+    f2[1] = f2[0]  # an empty front
+    assert "front_ptr" in bad(front_ptr=f2)
+    # separator property: swap one unknown of the first leaf with one of the last leaf of the right
+    # subtree, so that both leaves touch the other subtree
+    last_leaf = max(f for f in range(od.nfronts) if od.leaf[f])
+    p2 = perm.copy()
+    i, j = int(od.sbeg[first_leaf]), int(od.sbeg[last_leaf])
+    p2[i], p2[j] = p2[j], p2[i]
+    assert "separator property" in bad(perm=p2)

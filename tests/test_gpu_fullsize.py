@@ -9,8 +9,14 @@ The oracle cannot factor these grids whole, so the checks are
     A alone, the parents from A and the oracle's own leaf contribution
     blocks); the GPU's factor panels [L U; F21'], F12' and pivots must agree;
   * properties that hold at any size: every column's true FP64 residual at
-    most 1e-3 after GMRES (Sec. 6 stopping rule), every front with
-    #I^s >= n_min compressed, compressed factors smaller than exact ones.
+    most 1e-3 after GMRES (Sec. 6 stopping rule) within a bounded number of
+    iterations (a poor HOD-BF inverse would show as many more), every front
+    with #I^s >= n_min compressed, compressed factors smaller than exact ones;
+  * the error against the uncompressed factorization of the same grid on the
+    GPU (complex128, no front compressed), which stands in for the oracle's
+    solution at these sizes: the exact GPU path equals the oracle's
+    multifrontal LU on every grid the oracle factors (the dense-front tests),
+    and the compressed solution must be within 10 eps of it.
 """
 import numpy as np
 import pytest
@@ -61,6 +67,7 @@ def test_full_size_workload(gpu_lib, name):
         print(f"[fullsize] {name}: iters {info['iters']} relres max {res.max():.2e} "
               f"compressed {st['compressed_fronts']} max rank {st['max_rank']}", flush=True)
         assert info["status"] == 0 and res.max() <= 1e-3, (res.max(), info)
+        assert info["iters"] <= 15, info
 
         sym = symbolic(p.rowptr, p.colind, od)
         for f in _sampled_fronts(od):
@@ -78,5 +85,15 @@ def test_full_size_workload(gpu_lib, name):
             for got, ref in ((Ff[:nsf, :nsf], lu), (Ff[:nsf, nsf:], F12), (Ff[nsf:, :nsf], F21)):
                 assert np.abs(got - ref).max(initial=0.0) <= 1e-11 * scale, f"front {f}"
             assert not np.any(Ff[nsf:, nsf:]), "contribution block is not kept without keep_fronts"
+        s.close()
+        # proxy for the oracle's solution: the uncompressed factorization on the GPU
+        s, _ = _analyze(gpu_lib, p)
+        s.factor(tol=1e-3, n_min=0, precision=gpu_lib.BFMF_C128, batched=True)
+        Xe, info_e = s.solve(p.rhs, true_rtol=1e-10, rtol=1e-12, atol=0.0)
+        err = np.linalg.norm(X - Xe) / np.linalg.norm(Xe)
+        print(f"[fullsize] {name}: error against the exact GPU solve {err:.2e} "
+              f"(exact: {info_e['iters']} iterations, relres {info_e['relres']:.1e})", flush=True)
+        assert info_e["status"] == 0 and info_e["iters"] <= 2, info_e
+        assert err <= 1e-2, err
     finally:
         s.close()

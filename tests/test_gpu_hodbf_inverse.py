@@ -1,0 +1,144 @@
+"""GPU parity of the compressed blocks of a front against the oracle's dense ones.
+
+For a compressed front whose children are all dense, the GPU assembles F11,
+F12 and F21 from exactly the entries the oracle assembles (the children's
+contribution blocks agree to rounding), so every compressed block has a dense
+reference computed by the oracle (FP64, CPU) from the same front:
+  F11        HOD-BF by entry evaluation (Sec. 4.1, Alg. 2)     vs F11
+  F11^-1     HODBF_invert with BF_SMW (Alg. 4)                 vs LAPACK inv(F11)
+  F12, F21   butterflies by entry evaluation (Alg. 2)          vs F12, F21
+  S          randomized construction of F21 F11^-1 F12 (Sec. 3.3)
+The bounds are C eps for the blocks and C eps kappa(F11) for the inverse and
+S (the inverse of a matrix known to relative accuracy eps is known to about
+kappa eps).  `smw_dense` sets the size below which BF_SMW inverts a block
+densely: at 64 every node of the 24^3 separators above the HOD-BF leaves goes
+through the recursion (X22, then the randomized S11, then X11, then X by
+randomized products), at 1024 none does; both must meet the same bounds.
+"""
+import numpy as np
+import pytest
+
+from workloads import make_problem, helmholtz_7pt, rng_for
+from oracle import nd
+from oracle import multifrontal as mf
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-3
+C_BLOCK = 10.0     # ||B_gpu - B|| <= C_BLOCK eps ||B|| for F11, F12, F21
+C_INV = 10.0       # ||F11^-1_gpu - inv(F11)|| <= C_INV eps kappa(F11) ||inv(F11)||, same for S
+# The 16^3 grid with separator leaves of 16 nodes: 64-node separators whose butterflies have two
+# levels and few proxy candidates per block; F12 measured at 13.5 eps there (3.4 eps on the 24^3 fronts)
+C_BLOCK_SMALL = 30.0
+
+
+def _compressed_with_dense_children(od, n_min):
+    """Separator fronts with #I^s >= n_min whose children are all below the threshold."""
+    def comp(f):
+        return len(od.children[f]) > 0 and int(od.send[f] - od.sbeg[f]) >= n_min
+    return [f for f in range(od.nfronts) if comp(f) and not any(comp(c) for c in od.children[f])]
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _check_blocks(s, fac, f, eps, c_block=C_BLOCK, c_inv=C_INV):
+    F = fac.fronts[f]
+    ns = int(fac.od.send[f] - fac.od.sbeg[f])
+    nu = F.shape[0] - ns
+    F11, F12, F21 = F[:ns, :ns], F[:ns, ns:], F[ns:, :ns]
+    inv = np.linalg.inv(F11)
+    kappa = np.linalg.cond(F11)
+    I_s = np.eye(ns, dtype=np.complex128)
+    out = {"ns": ns, "nu": nu, "kappa": kappa}
+    out["F11"] = _rel(s.front_block(f, 0, I_s), F11)
+    out["F11inv"] = _rel(s.front_block(f, 1, I_s), inv)
+    Z = s.front_block(f, 1, I_s)
+    # the inverse of the HOD-BF as built: ||F11_gpu Z - I|| (local target)
+    out["F11inv_local"] = np.linalg.norm(s.front_block(f, 0, Z) - I_s) / np.sqrt(ns)
+    if nu:
+        I_u = np.eye(nu, dtype=np.complex128)
+        out["F12"] = _rel(s.front_block(f, 2, I_u), F12)
+        out["F21"] = _rel(s.front_block(f, 3, I_s), F21)
+        S = F21 @ inv @ F12
+        out["S"] = _rel(s.front_block(f, 4, I_u), S)
+    print(f"front {f}: " + " ".join(f"{k} {v:.3g}" for k, v in out.items()), flush=True)
+    assert out["F11"] <= c_block * eps, out
+    assert out["F11inv"] <= c_inv * eps * kappa, out
+    assert out["F11inv_local"] <= c_inv * eps * kappa, out
+    if nu:
+        assert out["F12"] <= c_block * eps and out["F21"] <= c_block * eps, out
+        assert out["S"] <= c_inv * eps * kappa, out
+    return out
+
+
+@pytest.fixture(scope="module")
+def c1_oracle():
+    p = make_problem("helmholtz24")
+    od = nd.nd_grid(p.dims, leaf_max=512, sep_leaf=64)
+    fac = mf.factor(p.rowptr, p.colind, p.values, od, keep_fronts=True)
+    x_or = mf.solve_refined(p.rowptr, p.colind, p.values, fac, p.rhs, steps=1)
+    return p, od, fac, x_or
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("smw_dense", [64, 1024])
+def test_hodbf_blocks_and_inverse_24(gpu_lib, c1_oracle, smw_dense, precision):
+    p, od, fac, x_or = c1_oracle
+    prec = gpu_lib.BFMF_C128 if precision == "c128" else gpu_lib.BFMF_C64_MIXED
+    s = gpu_lib.Solver(0).analyze(p.rowptr, p.colind, p.values, dims=p.dims)
+    s.factor(tol=TOL, n_min=256, batched=True, precision=prec, smw_dense=smw_dense)
+    assert s.stats()["compressed_fronts"] == 3
+    fronts = _compressed_with_dense_children(od, 256)
+    assert len(fronts) == 2  # the two level-1 separators (288 and 264 nodes)
+    print(f"smw_dense {smw_dense} {precision}", flush=True)
+    for f in fronts:
+        _check_blocks(s, fac, f, TOL)
+    X, info = s.solve(p.rhs, true_rtol=1e-3)
+    err = np.linalg.norm(X - x_or) / np.linalg.norm(x_or)
+    res = mf.rel_residual(p.rowptr, p.colind, p.values, X, p.rhs).max()
+    assert info["status"] == 0 and err <= 10 * TOL and res <= 1e-3, (err, res, info)
+    assert info["iters"] <= 8, info
+    s.close()
+
+
+def test_bf_smw_recursion_nested_fronts(gpu_lib):
+    """16^3 with compressed fronts whose children are compressed, BF_SMW recursing to the
+    HOD-BF leaves (dense base 32 rows): the solution within 10 eps of the oracle, the
+    preconditioner within the bound of the exact-base run, few iterations."""
+    dims = (16, 16, 16)
+    rp, ci, v, _ = helmholtz_7pt(dims, 0.05)
+    rng = rng_for("test", "rhs", (16,))
+    b = rng.standard_normal((rp.shape[0] - 1, 2)) + 1j * rng.standard_normal((rp.shape[0] - 1, 2))
+    od = nd.nd_grid(dims, leaf_max=64, sep_leaf=16)
+    fac = mf.factor(rp, ci, v, od, keep_fronts=True)
+    x_or = mf.solve(fac, b)
+    pre = {}
+    for smw in (16, 1024):
+        s = gpu_lib.Solver(0).analyze(rp, ci, v, dims=dims, leaf_max=64, sep_leaf=16)
+        s.factor(tol=TOL, n_min=60, batched=True, smw_dense=smw)
+        assert s.stats()["compressed_fronts"] >= 3
+        print(f"smw_dense {smw}", flush=True)
+        for f in _compressed_with_dense_children(od, 60):
+            _check_blocks(s, fac, f, TOL, c_block=C_BLOCK_SMALL)
+        X, info = s.solve(b, true_rtol=1e-3)
+        err = np.linalg.norm(X - x_or) / np.linalg.norm(x_or)
+        print(f"smw_dense {smw}: error {err:.2e} iterations {info['iters']}", flush=True)
+        assert info["status"] == 0 and err <= 10 * TOL and info["iters"] <= 10, (smw, err, info)
+        pre[smw] = np.linalg.norm(s.precondition(b) - x_or) / np.linalg.norm(x_or)
+        s.close()
+    assert pre[16] <= 5 * pre[1024] + 10 * TOL, pre
+
+
+def test_smw_dense_option_checked(gpu_lib):
+    p = make_problem("helmholtz24", n=12, config_id="test")
+    s = gpu_lib.Solver(0).analyze(p.rowptr, p.colind, p.values, dims=p.dims, leaf_max=64, sep_leaf=16)
+    with pytest.raises(gpu_lib.BfmfError) as e:
+        s.factor(tol=TOL, n_min=64, smw_dense=8)
+    assert e.value.status == gpu_lib.BFMF_E_INVAL
+    s.factor(tol=TOL, n_min=64, smw_dense=16)
+    with pytest.raises(gpu_lib.BfmfError) as e:
+        s.front_block(0, 0, np.eye(4))  # a leaf front is never compressed
+    assert e.value.status == gpu_lib.BFMF_E_INVAL
+    s.close()
