@@ -314,6 +314,19 @@ bfmf_status bfmf_bf_compress_dense(int32_t device, int32_t m, int32_t n, const d
  * host arrays, interleaved complex128, column-major. */
 bfmf_status bfmf_bf_apply(bfmf_bf* b, int32_t adjoint, int32_t nrhs, const double* X, int64_t ldx, double* Y,
                           int64_t ldy);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture aside, tight serving loops, harnesses that forbid hipMalloc): the
+ * product of bfmf_bf_apply with X (dX, in-columns x nrhs, ld ldx) and Y (dY,
+ * ld ldy) in device memory, interleaved complex128, queued on hip_stream
+ * (NULL: the butterfly's own stream).  It calls no hipMalloc, hipFree or
+ * allocating library routine: its task lists and inter-level workspace live
+ * in a fixed device array of 64 MiB per device, held until the process ends.
+ * Every launch uses the 64 x 64 tile, so Y equals bfmf_bf_apply's bit for bit.
+ * Returns after Y is complete (the stream is synchronized).  Calls that
+ * overlap on one device race on the shared array.  E_INVAL for bad sizes or a
+ * product that needs more than the fixed array. */
+bfmf_status bfmf_bf_apply_noalloc(bfmf_bf* b, int32_t adjoint, int32_t nrhs, const double* dX, int64_t ldx,
+                                  double* dY, int64_t ldy, void* hip_stream);
 /* levels, largest rank, number of stored complex entries */
 bfmf_status bfmf_bf_info(bfmf_bf* b, int32_t* L, int32_t* max_rank, int64_t* entries);
 void bfmf_bf_destroy(bfmf_bf* b);

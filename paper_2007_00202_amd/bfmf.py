@@ -116,6 +116,7 @@ _SIGS = {
     "bfmf_bf_compress_dense": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, C.c_int32, C.c_double,
                                          C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_P)]),
     "bfmf_bf_apply": (C.c_int, [_P, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64]),
+    "bfmf_bf_apply_noalloc": (C.c_int, [_P, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P]),
     "bfmf_bf_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     "bfmf_bf_destroy": (None, [_P]),
     "bfmf_default_server_opts": (None, [C.POINTER(bfmf_server_opts)]),
@@ -355,6 +356,12 @@ def bfmf_bf_apply(b, shape, X, adjoint=False):
     if st != BFMF_OK:
         raise BfmfError(st, "bf_apply")
     return Y
+
+
+def bfmf_bf_apply_noalloc(b, adjoint, nrhs, dX, ldx, dY, ldy, stream=None):
+    """Device pointers (e.g. torch tensors' data_ptr()); returns the status (0 on success)."""
+    return _lib.bfmf_bf_apply_noalloc(b, int(adjoint), nrhs, C.c_void_p(dX), ldx, C.c_void_p(dY), ldy,
+                                      C.c_void_p(stream) if stream else None)
 
 
 def bfmf_bf_info(b):

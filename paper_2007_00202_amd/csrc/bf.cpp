@@ -434,19 +434,15 @@ int64_t footprint(int64_t off, int64_t rows, int64_t cols, int64_t ld) {
   if (rows <= 0 || cols <= 0) return -1;
   return off + (rows - 1) + (cols - 1) * ld;
 }
-}  // namespace
 
-template <class T>
-void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y, void* ws, hipStream_t s,
-              const int64_t lim[4], int kind) {
-  HostTimer ht_run(HP_RUN);
-  void* bases[4] = {pool, const_cast<void*>(X), Y, ws};
+// every task's operands inside the buffers of its bases (lim[b] elements from base b; base 4 is
+// absolute and built only from allocations sized for the task)
+void check_plan(const BfPlan& plan, void* const bases[4], const int64_t lim[4]) {
   for (auto& ph : plan.phase)
     for (const GTask& t : ph) {
       const int64_t fa = t.opA == OP_N ? footprint(t.a_off, t.M, t.K, t.lda) : footprint(t.a_off, t.K, t.M, t.lda);
       const int64_t fb = t.opB == OP_N ? footprint(t.b_off, t.K, t.N, t.ldb) : footprint(t.b_off, t.N, t.K, t.ldb);
       const int64_t fc = footprint(t.c_off, t.M, t.N, t.ldc);
-      // base 4 (absolute addresses) is built only from allocations sized for the task; the others are checked
       auto out_of = [&](int b, int64_t off, int64_t f) {
         if (f < 0) return false;
         if (b == 4) return off <= 0;
@@ -458,6 +454,15 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
         throw Error(BFMF_E_INVAL, "internal: butterfly product task outside its buffers (M " + std::to_string(t.M) +
                                       " N " + std::to_string(t.N) + " K " + std::to_string(t.K) + ")");
     }
+}
+}  // namespace
+
+template <class T>
+void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y, void* ws, hipStream_t s,
+              const int64_t lim[4], int kind) {
+  HostTimer ht_run(HP_RUN);
+  void* bases[4] = {pool, const_cast<void*>(X), Y, ws};
+  check_plan(plan, bases, lim);
   // one upload for all phases: per phase its tasks then its tile starts
   std::vector<char> blob;
   std::vector<size_t> toff, soff;
@@ -520,6 +525,56 @@ template void run_plan<double>(const BfPlan&, Context&, char*, const void*, void
                                const int64_t[4], int);
 template void run_plan<float>(const BfPlan&, Context&, char*, const void*, void*, void*, hipStream_t,
                               const int64_t[4], int);
+
+// The task lists of a plan with every launch in tile shape cfg: per phase its tasks, then its tile
+// starts, each phase at a 16-byte boundary.
+static void plan_blob(const BfPlan& plan, int cfg, std::vector<char>& blob, std::vector<size_t>& toff,
+                      std::vector<size_t>& soff, std::vector<int64_t>& ntiles) {
+  blob.clear();
+  for (auto& ph : plan.phase) {
+    std::vector<int64_t> start(ph.size());
+    int64_t tiles = 0;
+    for (size_t i = 0; i < ph.size(); ++i) {
+      start[i] = tiles;
+      tiles += gemm_cfg_tiles(cfg, ph[i].M, ph[i].N);
+    }
+    if (tiles >= ((int64_t)1 << 31)) throw Error(BFMF_E_INVAL, "internal: grouped GEMM launch with 2^31 tiles");
+    size_t o = (blob.size() + 15) & ~(size_t)15;
+    blob.resize(o + ph.size() * sizeof(GTask) + start.size() * sizeof(int64_t));
+    if (!ph.empty()) std::memcpy(blob.data() + o, ph.data(), ph.size() * sizeof(GTask));
+    if (!start.empty())
+      std::memcpy(blob.data() + o + ph.size() * sizeof(GTask), start.data(), start.size() * sizeof(int64_t));
+    toff.push_back(o);
+    soff.push_back(o + ph.size() * sizeof(GTask));
+    ntiles.push_back(tiles);
+  }
+}
+
+template <class T>
+size_t run_plan_fixed(const BfPlan& plan, char* pool, const void* X, void* Y, void* ws, char* dtasks,
+                      size_t tasks_cap, hipStream_t s, const int64_t lim[4], int cfg) {
+  void* bases[4] = {pool, const_cast<void*>(X), Y, ws};
+  check_plan(plan, bases, lim);
+  std::vector<char> blob;
+  std::vector<size_t> toff, soff;
+  std::vector<int64_t> ntiles;
+  plan_blob(plan, cfg, blob, toff, soff, ntiles);
+  if (blob.size() > tasks_cap) return blob.size();
+  if (blob.empty()) return 0;
+  chk(hipMemcpyAsync(dtasks, blob.data(), blob.size(), hipMemcpyHostToDevice, s), "task upload");
+  for (size_t k = 0; k < plan.phase.size(); ++k) {
+    if (plan.phase[k].empty()) continue;
+    chk(launch_grouped_gemm<T>((const GTask*)(dtasks + toff[k]), (const int64_t*)(dtasks + soff[k]),
+                               (int)plan.phase[k].size(), ntiles[k], bases, cfg, s, nullptr, nullptr),
+        "grouped gemm");
+  }
+  // the host copy of the task lists must outlive the upload
+  chk(hipStreamSynchronize(s), "sync");
+  return 0;
+}
+
+template size_t run_plan_fixed<double>(const BfPlan&, char*, const void*, void*, void*, char*, size_t, hipStream_t,
+                                       const int64_t[4], int);
 
 template <class T>
 void BfRuntime<T>::apply(const Butterfly& bf, const void* X, int64_t ldx, void* Y, int64_t ldy, int nrhs, bool adjoint,

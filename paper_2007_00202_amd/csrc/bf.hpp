@@ -131,6 +131,14 @@ template <class T>
 void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y, void* ws, hipStream_t s,
               const int64_t lim[4], int kind = K_BF_GEMM);
 
+// Runs a plan with no allocation: every launch in tile shape cfg, the task lists
+// copied from host memory to dtasks (at most tasks_cap bytes) and the workspace
+// at ws; returns 0 when done (after synchronizing s), else the task-list bytes
+// that did not fit (nothing launched).
+template <class T>
+size_t run_plan_fixed(const BfPlan& plan, char* pool, const void* X, void* Y, void* ws, char* dtasks,
+                      size_t tasks_cap, hipStream_t s, const int64_t lim[4], int cfg);
+
 // ------------------------------------------------------------- operators
 template <class T>
 struct BfRuntime;

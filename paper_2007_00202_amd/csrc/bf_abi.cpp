@@ -2,6 +2,7 @@
 // evaluation (Alg. 2) or by randomized products (Sec. 3.3), products K X and
 // K^H X, and decompression.  Used to check the butterfly kernels in isolation.
 #include <cstring>
+#include <mutex>
 #include <random>
 
 #include "bf.hpp"
@@ -20,6 +21,34 @@ struct bfmf_bf {
 namespace bfmf {
 thread_local std::string g_thread_error;
 }
+
+// Scratch of bfmf_bf_apply_noalloc: the product's task lists, then its
+// inter-level workspace.  Each device holds its own copy for the life of the
+// process; host code reaches it only through the address hipGetSymbolAddress
+// returns for the current device (the name itself is a host-side stand-in).
+#define BFMF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+static __device__ __align__(256) char scratch[BFMF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on `device` (the current device), looked up once per device
+char* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) throw Error(BFMF_E_INVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    ochk(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch address");
+    if (!p) throw Error(BFMF_E_DEVICE, "scratch address is null");
+    g_scratch_ptr[device] = (char*)p;
+  }
+  return g_scratch_ptr[device];
+}
+
+}  // namespace
 
 namespace {
 
@@ -72,6 +101,7 @@ bfmf_status bfmf_bf_compress_dense(int32_t device, int32_t m, int32_t n, const d
   try {
     if (hipSetDevice(device) != hipSuccess) throw Error(BFMF_E_DEVICE, "set device");
     b->ctx.device = device;
+    (void)scratch_address(device);  // set-up of the allocation-free product on this device
     ochk(hipStreamCreateWithFlags(&b->ctx.stream, hipStreamNonBlocking), "stream");
     b->ctx.own_stream = true;
     b->rt.c = &b->ctx;
@@ -123,6 +153,38 @@ bfmf_status bfmf_bf_apply(bfmf_bf* b, int32_t adjoint, int32_t nrhs, const doubl
     b->rt.scratch.release(mk);
   } catch (const Error& e) {
     b->err = e.msg;
+    return e.status;
+  }
+  return BFMF_OK;
+}
+
+bfmf_status bfmf_bf_apply_noalloc(bfmf_bf* b, int32_t adjoint, int32_t nrhs, const double* dX, int64_t ldx,
+                                  double* dY, int64_t ldy, void* hip_stream) {
+  if (!b || !dX || !dY || nrhs <= 0) return BFMF_E_INVAL;
+  const int nin = adjoint ? b->bf->m : b->bf->n, nout = adjoint ? b->bf->n : b->bf->m;
+  if (ldx < nin || ldy < nout) return BFMF_E_INVAL;
+  try {
+    ochk(hipSetDevice(b->ctx.device), "set device");
+    char* base = scratch_address(b->ctx.device);
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : b->ctx.stream;
+    BfPlan plan = make_plan({BfCall{b->bf.get(), 0, 0, 1.0, 0.0, 0}}, adjoint != 0, nrhs, ldx, ldy);
+    const size_t ws_bytes = (size_t)std::max<int64_t>(plan.ws_elems, 1) * 16;
+    if (ws_bytes > BFMF_NOALLOC_SCRATCH_BYTES)
+      throw Error(BFMF_E_INVAL, "apply_noalloc: the product needs " + std::to_string(ws_bytes) +
+                                    " bytes of workspace, more than the fixed scratch of " +
+                                    std::to_string(BFMF_NOALLOC_SCRATCH_BYTES));
+    // workspace first (256-byte aligned at the start of the array), task lists after it
+    const size_t ws_span = (ws_bytes + 255) & ~(size_t)255;
+    const int64_t lim[4] = {(int64_t)(b->rt.pool.used / 16), ldx * nrhs, ldy * nrhs, std::max<int64_t>(plan.ws_elems, 1)};
+    const size_t need = run_plan_fixed<double>(plan, b->rt.pool_base(), dX, dY, base, base + ws_span,
+                                               BFMF_NOALLOC_SCRATCH_BYTES - ws_span, s, lim, 0);
+    if (need)
+      throw Error(BFMF_E_INVAL, "apply_noalloc: the product needs " + std::to_string(ws_span + need) +
+                                    " bytes of scratch, more than the fixed " +
+                                    std::to_string(BFMF_NOALLOC_SCRATCH_BYTES));
+  } catch (const Error& e) {
+    b->err = e.msg;
+    g_thread_error = e.msg;
     return e.status;
   }
   return BFMF_OK;
