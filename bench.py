@@ -1,10 +1,20 @@
 """Benchmark: factor time and RHS/s of the butterfly-compressed multifrontal
-solver on one MI355X, with the roofline of the dominant kernel and the CPU
-oracle timed on a bounded sample of the same workload.
+solver on one MI355X, with the roofline of the dominant kernel, the other
+forms on the same workload, and the CPU oracle timed on complete runs.
 
 One step = bfmf_factor (all fronts) + bfmf_solve of the workload's RHS block
 (GMRES to a true relative residual <= 1e-3), inputs resident in HBM.
 value = RHS per second of whole steps (factorization included).
+
+Default workload: 128^3 Helmholtz with a Gaussian-random-field velocity and
+32 point sources, batched form in complex128 (the paper's precision).  Legs on
+the same workload: the complex64 form (butterflies and sketches in complex64,
+FP64 pivots and GMRES) and the plain GPU form (complex128, fronts and
+constructions one at a time).  Every leg states its error against the
+uncompressed complex128 factorization on the GPU, which stands in for the
+oracle's solution at this size (the oracle's multifrontal LU would take hours
+and its factors about 110 GB of host memory; the exact GPU path equals the
+oracle on every grid the tests factor with both).
 """
 import argparse
 import json
@@ -25,14 +35,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="helmholtz100")
+    ap.add_argument("--config", default="helmholtz128grf")
     ap.add_argument("--n", type=int, default=None, help="override the grid size")
     ap.add_argument("--form", default="batched", choices=["batched", "plain"])
-    ap.add_argument("--precision", default=None, choices=["c128", "c64"], help="default: the workload's")
+    ap.add_argument("--precision", default="c128", choices=["c128", "c64"],
+                    help="precision of the headline leg (the other one runs as a leg)")
     ap.add_argument("--n-min", type=int, default=None, help="compression threshold (0: exact)")
     ap.add_argument("--tol", type=float, default=None)
-    ap.add_argument("--cpu-baseline-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-48", action="store_true", help="cpu baseline on the 24^3 workload only")
+    ap.add_argument("--no-legs", action="store_true", help="skip the other-precision leg")
+    ap.add_argument("--no-exact", action="store_true", help="skip the uncompressed reference solve")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison step")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-seconds", type=float, default=0.25, help="arrival window of the serving run")
@@ -79,53 +92,99 @@ def calibrate_copy(mib):
     print(f"[bench] calibration kernels: {mib} MiB read + {mib} MiB written each", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(prob, budget_s, nrhs, parallel_levels=0):
-    """Oracle (NumPy/SciPy FP64) factorization of the same workload, stopped
-    after about budget_s seconds of fronts in postorder; scaled to the whole
-    factorization by algorithmic flops, plus the sampled solve cost."""
+def host_info():
+    """The host that runs the oracle: CPU model, hardware threads available, RAM, the BLAS
+    library NumPy calls and the threads it runs."""
+    model, mem_gb, blas, threads = "", None, None, None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                mem_gb = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        for info in threadpool_info():
+            if info.get("user_api") == "blas":
+                blas = f"{info.get('internal_api')} {info.get('version')}"
+                threads = info.get("num_threads")
+                break
+    except Exception:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except Exception:
+        nproc = os.cpu_count()
+    return {"cpu_model": model, "nproc": nproc, "ram_gb": mem_gb, "blas": blas, "blas_threads": threads}
+
+
+def oracle_run(prob):
+    """One complete oracle solve (Alg. 1: nested dissection, uncompressed multifrontal LU in
+    FP64 complex, forward and backward sweeps, one step of iterative refinement)."""
     from oracle import nd, multifrontal as mf
     from oracle.symbolic import symbolic
-    od = nd.nd_grid(prob.dims, leaf_max=512, sep_leaf=64, parallel_levels=parallel_levels)
+    t0 = time.perf_counter()
+    od = nd.nd_grid(prob.dims, leaf_max=512, sep_leaf=64)
     sym = symbolic(prob.rowptr, prob.colind, od)
-    total = sum(mf.front_flops(od, sym, f) for f in range(od.nfronts))
-    t0 = time.perf_counter()
-    fac = mf.factor(prob.rowptr, prob.colind, prob.values, od, sym, stop_seconds=budget_s)
-    t_f = time.perf_counter() - t0
-    done = sum(mf.front_flops(od, sym, f) for f in range(fac.done))
-    est_factor = t_f * total / max(done, 1.0)
-    # the solve touches every factor entry once per RHS: scale by factor storage
-    sizes = [(float(od.send[f] - od.sbeg[f]), float(sym.Iu[f].shape[0])) for f in range(od.nfronts)]
-    store = sum(ns * ns + 2 * ns * nu for ns, nu in sizes)
-    store_done = sum(ns * ns + 2 * ns * nu for ns, nu in sizes[:fac.done])
-    t0 = time.perf_counter()
-    Bs = prob.rhs[:, :1]
-    _ = _partial_solve(fac, Bs, fac.done)
-    t_s = (time.perf_counter() - t0) * store / max(store_done, 1.0) * nrhs
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except Exception:
-        cores = os.cpu_count()
-    value = nrhs / (est_factor + t_s)
-    return {"value": value, "unit": "RHS/s", "cores": cores, "kind": "oracle",
-            "sample": f"oracle multifrontal LU of the first {fac.done} of {od.nfronts} fronts (postorder) of the "
-                      f"same grid in {t_f:.1f} s ({100 * done / total:.2f}% of the flops), and their sweeps for "
-                      f"1 RHS; scaled to the whole factorization by flops and to {nrhs} RHS by factor storage",
-            "est_factor_s": est_factor, "est_solve_s": t_s}
+    fac = mf.factor(prob.rowptr, prob.colind, prob.values, od, sym)
+    t1 = time.perf_counter()
+    x = mf.solve_refined(prob.rowptr, prob.colind, prob.values, fac, prob.rhs, steps=1)
+    t2 = time.perf_counter()
+    return t1 - t0, t2 - t1, x
 
 
-def _partial_solve(fac, B, nfr):
-    import scipy.linalg as sla
-    from oracle import multifrontal as mf
-    od, sym = fac.od, fac.sym
-    y = B[od.perm, :].copy()
-    for f in range(nfr):
-        b, e = int(od.sbeg[f]), int(od.send[f])
-        z = y[b:e, :][mf.swaps_to_perm(fac.piv[f]), :]
-        z = sla.solve_triangular(fac.lu[f], z, lower=True, unit_diagonal=True)
-        y[b:e, :] = z
-        if sym.Iu[f].shape[0]:
-            y[sym.Iu[f], :] -= fac.F21[f] @ z
-    return y
+def gpu_run(bfmf, prob, precision, n_min, reps=3):
+    """The GPU on a small workload: median over reps of analyze-free factor + solve, the solution
+    of the last one."""
+    import torch
+    prec = bfmf.BFMF_C128 if precision == "c128" else bfmf.BFMF_C64_MIXED
+    s = bfmf.Solver(0).analyze(prob.rowptr, prob.colind, prob.values, dims=prob.dims)
+    times = []
+    for k in range(reps + 1):  # the first is a warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.factor(tol=1e-3, n_min=n_min, precision=prec, batched=True)
+        X, info = s.solve(prob.rhs, true_rtol=1e-3)
+        times.append(time.perf_counter() - t0)
+    s.close()
+    return float(np.median(times[1:])), X, info
+
+
+def cpu_baseline(bfmf, reps=3, with_48=True):
+    """The oracle timed on complete runs of named workloads (no sampling, no scaling): the 24^3
+    workload (1 RHS, median of reps runs) and, unless with_48 is off, the 48^3 serving grid
+    (1 point source, one run).  The GPU's rate and error on the same workloads are given beside."""
+    from workloads import make_problem
+    c1 = make_problem("helmholtz24")
+    runs = [oracle_run(c1) for _ in range(reps)]
+    tf = float(np.median([r[0] for r in runs]))
+    ts = float(np.median([r[1] for r in runs]))
+    x_or = runs[-1][2]
+    g_t, g_x, g_info = gpu_run(bfmf, c1, "c128", 256)
+    hi = host_info()
+    out = {"value": 1.0 / (tf + ts), "unit": "RHS/s", "cores": hi["blas_threads"] or hi["nproc"], "kind": "oracle",
+           "sample": "complete oracle runs (NumPy/SciPy FP64 multifrontal LU of Alg. 1 + one refinement step), "
+                     f"24^3 Helmholtz (N=13,824, 1 RHS), median of {reps}; the headline grid is not sampled "
+                     "(its oracle factorization takes hours and about 110 GB of host memory)",
+           "host": hi, "workload": "helmholtz24 (24^3, 1 RHS)", "factor_s": tf, "solve_s": ts,
+           "gpu_same_workload": {"rhs_per_s": 1.0 / g_t, "seconds": g_t, "form": "batched c128, n_min 256",
+                                 "rel_err_vs_oracle": float(np.linalg.norm(g_x - x_or) / np.linalg.norm(x_or)),
+                                 "gmres_iters": g_info["iters"]}}
+    if with_48:
+        p48 = make_problem("helmholtz100", n=48, nrhs=1, config_id="serving")
+        f48, s48, x48 = oracle_run(p48)
+        g_t, g_x, g_info = gpu_run(bfmf, p48, "c64", 1024)
+        out["grid48"] = {"workload": "48^3 serving grid (N=110,592, 1 point source), one run", "rhs_per_s": 1.0 / (f48 + s48),
+                         "factor_s": f48, "solve_s": s48,
+                         "gpu_same_workload": {"rhs_per_s": 1.0 / g_t, "seconds": g_t, "form": "batched c64, n_min 1024",
+                                               "rel_err_vs_oracle": float(np.linalg.norm(g_x - x48) / np.linalg.norm(x48)),
+                                               "gmres_iters": g_info["iters"]}}
+    return out
 
 
 def run_form(bfmf, s, prob, nrhs, dB, dX, steps, warmup, form, precision, n_min, tol, timing=True, direct=False):
@@ -160,7 +219,7 @@ def run_form(bfmf, s, prob, nrhs, dB, dX, steps, warmup, form, precision, n_min,
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     st = s.stats()
-    return {"T": T, "value": nrhs * steps / T, "ms_per_step": 1e3 * T / steps,
+    return {"T": T, "X": dX.cpu().numpy().T.copy(), "value": nrhs * steps / T, "ms_per_step": 1e3 * T / steps,
             "factor_s": float(np.mean(fsec)), "solve_s": float(np.mean(ssec)),
             "solve_rhs_per_s": nrhs / float(np.mean(ssec)), "gmres_iters": int(max(iters)),
             "relres_max": float(max(relres)), "factor_flops": st["factor_flops"],
@@ -168,7 +227,7 @@ def run_form(bfmf, s, prob, nrhs, dB, dX, steps, warmup, form, precision, n_min,
             "max_rank": st["max_rank"], "kernels": s.kernel_stats(), "gemm_tiles": s.gemm_tile_launches()}
 
 
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "kernels_helmholtz100_c64.md")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def library_sources_sha256():
@@ -186,21 +245,32 @@ def library_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, precision):
-    """HBM bytes per launch of `kernel` from the committed profiler record (FETCH_SIZE and
-    WRITE_SIZE scaled by a copy of known size), or None when the record is missing, is for
-    another kernel or precision, or the library sources changed since it was taken."""
-    if precision != "c64" or not os.path.exists(TRAFFIC_RECORD):
+def measured_traffic(kernel, config, precision):
+    """HBM bytes per launch of `kernel` from a committed profiler record (a `* record:` line in a
+    summary under profiles/: FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None
+    when no record matches the kernel, workload and precision, or the library sources changed
+    since it was taken."""
+    if not os.path.isdir(PROFILES):
         return None
-    for line in open(TRAFFIC_RECORD):
-        if line.startswith("* record: "):
+    sha = None
+    for name in sorted(os.listdir(PROFILES)):
+        if not name.endswith(".md"):
+            continue
+        for line in open(os.path.join(PROFILES, name)):
+            if not line.startswith("* record: "):
+                continue
             rec = json.loads(line[len("* record: "):])
-            if rec.get("kernel") == kernel and rec.get("sources_sha256") == library_sources_sha256():
+            if rec.get("kernel") != kernel or rec.get("config", "helmholtz100") != config:
+                continue
+            if rec.get("precision", "c64") != precision:
+                continue
+            sha = sha or library_sources_sha256()
+            if rec.get("sources_sha256") == sha:
                 return rec.get("traffic_bytes_per_launch")
     return None
 
 
-def roofline(ks, steps, precision):
+def roofline(ks, steps, precision, config):
     """Roofline of the dominant single-kernel class (estimated total time; sampled classes scaled)."""
     single = {"assemble": "hbm", "schur_gemm": "mfma", "butterfly_gemm": "mfma", "interp_decomp": "alu",
               "entry_extract": "hbm"}
@@ -221,7 +291,7 @@ def roofline(ks, steps, precision):
         ach = kk["flops"] / max(kk["seconds"], 1e-30) / 1e12
         peak, unit = (fp_peak if bound == "mfma" else PEAKS["fp64_tflops"]), "TFLOP/s"
     rf = {"bound": bound, "kernel": dom, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
-          "traffic": measured_traffic(dom, precision), "timed_launches": kk["launches"],
+          "traffic": measured_traffic(dom, config, precision), "timed_launches": kk["launches"],
           "launches": kk["launches_all"],
           "avg_launch_ms": 1e3 * per_launch_s}
     kernels = {k: {"ms": 1e3 * total_s(k) / steps, "launches": v["launches_all"] // max(steps, 1),
@@ -291,6 +361,39 @@ def operator_label(cfg):
     return "3D Helmholtz 7-pt"
 
 
+def exact_solution(bfmf, prob, sep_leaf, parallel_levels):
+    """The uncompressed factorization on the GPU (complex128, every front dense, batched), GMRES to
+    a true residual of 1e-10: the reference the legs' errors are measured against."""
+    s = bfmf.Solver(0).analyze(prob.rowptr, prob.colind, prob.values, dims=prob.dims, sep_leaf=sep_leaf,
+                               parallel_levels=parallel_levels)
+    try:
+        s.factor(tol=1e-3, n_min=0, precision=bfmf.BFMF_C128, batched=True)
+        t_f = s.stats()["factor_seconds"]
+        X, info = s.solve(prob.rhs, true_rtol=1e-10, rtol=1e-12, atol=0.0)
+        return X, {"factor_s": t_f, "solve_s": info["seconds"], "gmres_iters": info["iters"],
+                   "relres_max": info["relres"], "factor_gb": s.stats()["factor_bytes"] / 1e9}
+    finally:
+        s.close()
+
+
+def exact_flops(s):
+    """Flops of the uncompressed multifrontal factorization of the analysed grid (complex, counted
+    as real flops: 8/3 ns^3 + 8 ns^2 nu + 8 ns nu^2 per front)."""
+    sym = s.symbolic()
+    ns = (sym["send"] - sym["sbeg"]).astype(np.float64)
+    nu = np.diff(sym["iu_ptr"]).astype(np.float64)
+    return float(np.sum(8.0 / 3.0 * ns ** 3 + 8.0 * ns * ns * nu + 8.0 * ns * nu * nu))
+
+
+def leg_summary(r, X_ref, nrhs):
+    out = {"value": r["value"], "ms_per_step": r["ms_per_step"], "factor_s": r["factor_s"], "solve_s": r["solve_s"],
+           "solve_rhs_per_s": r["solve_rhs_per_s"], "gmres_iters": r["gmres_iters"], "relres_max": r["relres_max"],
+           "factor_gb": r["factor_bytes"] / 1e9, "max_rank": r["max_rank"]}
+    if X_ref is not None:
+        out["rel_err_vs_exact_gpu"] = float(np.linalg.norm(r["X"] - X_ref) / np.linalg.norm(X_ref))
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -313,15 +416,20 @@ def main():
     prob = make_problem(a.config, n=a.n)
     n_min = cfg["n_min"] if a.n_min is None else a.n_min
     tol = cfg["tol"] if a.tol is None else a.tol
-    precision = a.precision or cfg["precision"]
+    precision = a.precision
     nrhs = prob.rhs.shape[1]
     sep_leaf = a.sep_leaf or cfg.get("sep_leaf", 64)
+    print(f"[bench] {a.config}: N={prob.n}, {nrhs} RHS, {a.form} {precision}", file=sys.stderr, flush=True)
     s = bfmf.Solver(0).analyze(prob.rowptr, prob.colind, prob.values, dims=prob.dims, sep_leaf=sep_leaf,
                                parallel_levels=a.parallel_levels)
     dB = torch.from_numpy(np.ascontiguousarray(prob.rhs.T)).to("cuda")  # column-major (N, nrhs)
     dX = torch.zeros_like(dB)
     r = run_form(bfmf, s, prob, nrhs, dB, dX, a.steps, a.warmup, a.form, precision, n_min, tol, direct=a.direct)
-    rf, kernels = roofline(r["kernels"], a.steps, precision)
+    rf, kernels = roofline(r["kernels"], a.steps, precision, a.config)
+    dtype = {"c128": "c128", "c64": "c64+f64"}[precision]
+    wl = f"{a.config}: {operator_label(cfg)} {prob.dims[0]}^3 (N={prob.n}), {nrhs} RHS"
+    if cfg.get("grf"):
+        wl += ", GRF velocity in [1, 2]"
     out = {
         "metric": "factor time + RHS/s at rel-residual <=1e-3",
         "value": r["value"],
@@ -329,30 +437,49 @@ def main():
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": r["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c128" if precision == "c128" else "c64+f64",
+        "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": f"{a.config}: {operator_label(cfg)} {prob.dims[0]}^3 (N={prob.n}), {nrhs} RHS",
-                   "form": a.form, "n_min": n_min, "tol": tol, "precision": precision, "sep_leaf": sep_leaf,
-                   "parallel_levels": a.parallel_levels,
+        "config": {"workload": wl, "form": a.form, "n_min": n_min, "tol": tol, "precision": precision,
+                   "sep_leaf": sep_leaf, "parallel_levels": a.parallel_levels,
                    "solver": "direct" if a.direct else "gmres"},
         "factor_s": r["factor_s"], "solve_s": r["solve_s"], "solve_rhs_per_s": r["solve_rhs_per_s"],
         "gmres_iters": r["gmres_iters"], "relres_max": r["relres_max"],
-        "factor_tflops": r["factor_flops"] / r["factor_s"] / 1e12,
         "factor_gb": r["factor_bytes"] / 1e9, "dense_factor_gb": r["dense_factor_bytes"] / 1e9,
         "max_rank": r["max_rank"],
+        "exact_factor_flops": exact_flops(s),
         "roofline": rf,
         "kernels": kernels,
         "gemm_tile_launches": {k: v // max(a.steps, 1) for k, v in r["gemm_tiles"].items()},
     }
+    out["factor_dense_equiv_tflops"] = out["exact_factor_flops"] / r["factor_s"] / 1e12
+    legs = {}
+    if not a.no_legs:
+        other = "c64" if precision == "c128" else "c128"
+        print(f"[bench] leg: batched {other}", file=sys.stderr, flush=True)
+        legs[f"batched_{other}"] = run_form(bfmf, s, prob, nrhs, dB, dX, 1, 1, "batched", other, n_min, tol,
+                                             timing=False)
     if not a.no_plain:  # the plain GPU form: complex128, fronts and constructions one at a time
-        p = run_form(bfmf, s, prob, nrhs, dB, dX, 1, 0, "plain", "c128", n_min, tol, timing=False)
-        out["plain"] = {"form": "plain", "precision": "c128", "value": p["value"], "factor_s": p["factor_s"],
-                        "solve_s": p["solve_s"], "gmres_iters": p["gmres_iters"], "relres_max": p["relres_max"]}
+        print("[bench] leg: plain c128", file=sys.stderr, flush=True)
+        legs["plain_c128"] = run_form(bfmf, s, prob, nrhs, dB, dX, 1, 0, "plain", "c128", n_min, tol, timing=False)
     s.close()
+    X_ref = None
+    if not a.no_exact:
+        print("[bench] exact reference: uncompressed c128 factorization", file=sys.stderr, flush=True)
+        X_ref, ex = exact_solution(bfmf, prob, sep_leaf, a.parallel_levels)
+        out["exact_gpu"] = ex
+        out["rel_err_vs_exact_gpu"] = float(np.linalg.norm(r["X"] - X_ref) / np.linalg.norm(X_ref))
+    out["oracle_error"] = ("oracle not run at this size (hours of CPU time, about 110 GB of exact complex128 factors); "
+                           "rel_err_vs_exact_gpu is against the uncompressed GPU factorization, which equals the "
+                           "oracle wherever both run; cpu_baseline gives measured oracle errors on smaller grids")
+    out["legs"] = {k: leg_summary(v, X_ref, nrhs) for k, v in legs.items()}
+    for k, v in legs.items():
+        out["legs"][k]["form"], out["legs"][k]["precision"] = k.split("_")
     if not a.no_serve:
-        out["serving"] = run_serving(bfmf, a.serve_seconds, a.serve_rate, 64, precision)
+        print("[bench] serving", file=sys.stderr, flush=True)
+        out["serving"] = run_serving(bfmf, a.serve_seconds, a.serve_rate, 64, "c64")
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, a.cpu_baseline_seconds, nrhs, a.parallel_levels)
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(bfmf, with_48=not a.no_cpu_48)
     print(json.dumps(out))
 
 

@@ -95,14 +95,8 @@ def partial_lu(F, ns):
     return lu, piv, F12, F21, C
 
 
-def factor(rowptr, colind, values, od, sym=None, keep_fronts=False, stop_seconds=None):
-    """Multifrontal factorization following Alg. 1.
-
-    stop_seconds: stop after the first front that ends past this wall time
-    (used to time a bounded sample); fac.done is the number of fronts done.
-    """
-    import time
-    t0 = time.perf_counter()
+def factor(rowptr, colind, values, od, sym=None, keep_fronts=False):
+    """Multifrontal factorization following Alg. 1."""
     if sym is None:
         sym = symbolic(rowptr, colind, od)
     fac = Factors()
@@ -124,17 +118,7 @@ def factor(rowptr, colind, values, od, sym=None, keep_fronts=False, stop_seconds
         cbs[f] = C
         if keep_fronts:
             fac.cbs[f] = C
-        fac.done = f + 1
-        if stop_seconds is not None and time.perf_counter() - t0 > stop_seconds:
-            break
     return fac
-
-
-def front_flops(od, sym, f):
-    """Algorithmic flops of the dense partial factorization of front f."""
-    ns = float(od.send[f] - od.sbeg[f])
-    nu = float(sym.Iu[f].shape[0])
-    return 8.0 / 3.0 * ns ** 3 + 8.0 * ns * ns * nu + 8.0 * ns * nu * nu
 
 
 def solve(fac, B):
