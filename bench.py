@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-seconds", type=float, default=0.25, help="arrival window of the serving run")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean request arrivals per second")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving workload (three resident grids) and print its line")
     ap.add_argument("--sep-leaf", type=int, default=None,
                     help="separators are bisected down to this many nodes (HOD-BF leaves); default: the workload's")
     ap.add_argument("--parallel-levels", type=int, default=0,
@@ -409,6 +411,9 @@ def main():
     if a.gemm_tile >= 0:
         bfmf.bfmf_set_gemm_tile(a.gemm_tile)
 
+    if a.serve_only:
+        print(json.dumps({"serving": run_serving(bfmf, a.serve_seconds, a.serve_rate, 64, a.precision)}))
+        return
     cfg = CONFIGS[a.config]
     if cfg["kind"] != "grid":
         print(json.dumps({"error": f"{a.config}: the benchmark runs the grid workloads"}))

@@ -115,14 +115,23 @@ typedef struct {
                             inverted densely (FP64 partial LU of the bordered block), larger ones
                             are split into four children butterflies; 0 means 1024, values in
                             1..15 are E_INVAL */
-    int32_t reserved[5];
+    int32_t id_max_cols; /* widest block given to one interpolative-decomposition kernel
+                            (0: the kernels' own limits, 2048 columns for tol >= 1e-4, else
+                            1024); wider blocks are decomposed as an ID of the IDs of column
+                            chunks (about twice the tolerance); values in 1..15 are E_INVAL */
+    int32_t reserved[4];
 } bfmf_factor_opts;
 
 /* GMRES options (Sec. 6): restarted GMRES(restart), modified Gram-Schmidt,
- * zero initial guess, left preconditioning, stop when ||u_i|| <= atol or
- * ||u_i|| / ||u_0|| <= rtol with u_i = M^-1 (A x_i - b).  If true_rtol > 0,
- * iterations continue until the true residual ||b - A x|| / ||b|| of every
- * column is also at most true_rtol. */
+ * zero initial guess, left preconditioning; a cycle of a column ends when
+ * ||u_i|| <= atol or ||u_i|| / ||u_0|| <= rtol with u_i = M^-1 (A x_i - b).
+ * Without true_rtol a column whose cycle ended that way is done.  With
+ * true_rtol > 0 the stop is the true residual instead: at the end of every
+ * restart cycle each column's ||b - A x|| / ||b|| is computed and the column
+ * is done once it is at most true_rtol; a column whose preconditioned test
+ * was met while its true residual was still above true_rtol continues with
+ * a ten times smaller rtol.  Columns are independent: each has its own
+ * Krylov space, and its iterates do not depend on the other columns. */
 typedef struct {
     int32_t restart;     /* default 30 */
     int32_t max_iter;    /* default 300 (0 also means 300); negative: direct solve, X = M^-1 B
@@ -168,7 +177,7 @@ typedef struct {
     int32_t max_rank;
     int32_t singular_front;       /* front of an exact zero pivot, or -1 */
     int32_t singular_index;       /* local pivot index within that front */
-    int32_t reserved0;
+    int32_t id_chunked;           /* ID blocks wider than one kernel, done as IDs of sub-IDs */
     double solve_flops_per_rhs;   /* one preconditioner application */
     uint64_t device_bytes_peak;   /* device memory held by the handle */
     double reserved[8];
@@ -213,6 +222,21 @@ bfmf_status bfmf_factor(bfmf_handle h, const bfmf_factor_opts* opts);
  * Returns E_NOCONV (with the best X) when max_iter is reached. */
 bfmf_status bfmf_solve(bfmf_handle h, int64_t nrhs, const double* B, int64_t ldb,
                        double* X, int64_t ldx, int32_t mem, bfmf_solve_opts* io);
+
+/* The direct solve X = M^-1 B (forward then backward sweep through all
+ * fronts, the approximate factorization used as a direct solver: Sec. 6,
+ * tolerance study) queued on the caller's stream hip_stream (NULL: the
+ * handle's) without waiting for it: dB and dX are device pointers
+ * (interleaved complex128, column-major, ld >= n), X is valid once the
+ * stream has completed the call's work.  The call is ordered after earlier
+ * work of the handle and before its later work.  X equals bfmf_solve's with
+ * max_iter < 0 bit for bit.  io may be NULL; io->max_iter must be negative
+ * (GMRES needs the host at every iteration: E_INVAL otherwise); on return
+ * io->iters_max = 0, io->relres_max = -1 (not computed) and io->seconds is
+ * the host time of the call.  The first call with a new column count may
+ * wait for the device while it sizes its workspaces. */
+bfmf_status bfmf_solve_async(bfmf_handle h, int64_t nrhs, const double* dB, int64_t ldb, double* dX, int64_t ldx,
+                             void* hip_stream, bfmf_solve_opts* io);
 
 /* Apply the preconditioner once, X = M^-1 B (forward then backward sweep
  * through all fronts), without GMRES.  Same layout rules as bfmf_solve. */
@@ -333,33 +357,37 @@ void bfmf_bf_destroy(bfmf_bf* b);
 
 /* ------------------------------------------------------------------ serving
  * Several factored handles stay resident on one device and answer a stream
- * of right-hand-side requests.  Each attached handle gets a worker thread on
- * its own stream; the worker takes every queued request of its model that
- * fits max_batch_rhs columns and the result arena, solves them together with
- * one GMRES call (columns are independent: a request's result does not depend
- * on the other requests of its batch beyond rounding), and keeps each
- * request's solution in the arena until bfmf_server_wait fetches it.
- * Requests arriving while a batch runs join the next batch of their model;
- * models run concurrently.  Factors, batch workspaces and the arena are
- * charged against hbm_budget when models are attached (E_NOMEM beyond it).
- * A handle attached to a server must not be used by the caller afterwards,
- * and must outlive the server.  Not for graph capture. */
+ * of right-hand-side requests with continuous batching.  Each attached
+ * handle gets a worker thread on its own stream and max_batch_rhs column
+ * slots; every column of an admitted request takes a slot and runs its own
+ * restarted GMRES with the handle's preconditioner (the columns of a slot
+ * batch share every launch but not their arithmetic: a request's result is
+ * the same bit for bit alone or beside others).  Between two GMRES
+ * iterations the worker retires the columns that met the stopping test
+ * (solutions go to a result arena until bfmf_server_wait fetches them) and
+ * admits queued requests, whole and in arrival order, into the freed slots
+ * while their solutions fit the arena; so a request arriving while others
+ * are on the device starts at the next iteration.  Models run concurrently.
+ * Factors, slot workspaces and the arena are charged against hbm_budget when
+ * models are attached (E_NOMEM beyond it).  A handle attached to a server
+ * must not be used by the caller afterwards, and must outlive the server.
+ * Not for graph capture. */
 typedef struct bfmf_server_s* bfmf_server;
 typedef struct {
-    int32_t max_batch_rhs;   /* columns of one batch solve (default 64); wider requests are refused */
+    int32_t max_batch_rhs;   /* column slots per model (default 64); wider requests are refused */
     int32_t reserved0;
     uint64_t hbm_budget;     /* bytes for all models and the arena (0: the device's free memory) */
     uint64_t result_bytes;   /* arena for solutions awaiting bfmf_server_wait (default 4 GiB) */
-    bfmf_solve_opts solve;   /* every batch solve (default: true_rtol 1e-3) */
+    bfmf_solve_opts solve;   /* GMRES of every column (default: true_rtol 1e-3; graphs applies) */
 } bfmf_server_opts;
 typedef struct {
-    double t_submit, t_start, t_done;  /* seconds on the server clock: queued, batch started, solution ready */
+    double t_submit, t_start, t_done;  /* seconds on the server clock: queued, admitted, solution ready */
     int32_t model, nrhs;
-    int32_t batch_rhs;                 /* columns of the batch that solved the request */
-    int32_t batch_requests;            /* requests in that batch */
-    int32_t iters;                     /* GMRES iterations of the batch (largest over its columns) */
-    int32_t status;                    /* bfmf_status of the solve */
-    double relres;                     /* largest true relative residual of the batch's columns */
+    int32_t batch_rhs;                 /* most columns in flight on the model while the request was */
+    int32_t batch_requests;            /* most requests in flight on the model while the request was */
+    int32_t iters;                     /* GMRES iterations of the request (largest over its columns) */
+    int32_t status;                    /* bfmf_status of the request's columns */
+    double relres;                     /* largest true relative residual of the request's columns */
 } bfmf_request_info;
 void bfmf_default_server_opts(bfmf_server_opts* o);
 bfmf_status bfmf_server_create(int32_t device, const bfmf_server_opts* o, bfmf_server* out);

@@ -43,7 +43,7 @@ class bfmf_factor_opts(C.Structure):
                 ("batched", C.c_int32), ("samples", C.c_int32), ("knn", C.c_int32),
                 ("alpha", C.c_double), ("seed", C.c_uint64), ("hbm_budget", C.c_uint64),
                 ("keep_fronts", C.c_int32), ("timing", C.c_int32), ("smw_dense", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("id_max_cols", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class bfmf_kernel_stat(C.Structure):
@@ -75,7 +75,7 @@ class bfmf_stats(C.Structure):
                 ("nlevels", C.c_int32), ("analyze_seconds", C.c_double), ("factor_seconds", C.c_double),
                 ("factor_flops", C.c_double), ("factor_bytes", C.c_double),
                 ("dense_factor_bytes", C.c_double), ("max_rank", C.c_int32),
-                ("singular_front", C.c_int32), ("singular_index", C.c_int32), ("reserved0", C.c_int32),
+                ("singular_front", C.c_int32), ("singular_index", C.c_int32), ("id_chunked", C.c_int32),
                 ("solve_flops_per_rhs", C.c_double), ("device_bytes_peak", C.c_uint64),
                 ("reserved", C.c_double * 8)]
 
@@ -103,6 +103,7 @@ _SIGS = {
     "bfmf_factor": (C.c_int, [_h, C.POINTER(bfmf_factor_opts)]),
     "bfmf_solve": (C.c_int, [_h, C.c_int64, _P, C.c_int64, _P, C.c_int64, C.c_int32,
                              C.POINTER(bfmf_solve_opts)]),
+    "bfmf_solve_async": (C.c_int, [_h, C.c_int64, _P, C.c_int64, _P, C.c_int64, _P, C.POINTER(bfmf_solve_opts)]),
     "bfmf_apply_preconditioner": (C.c_int, [_h, C.c_int64, _P, C.c_int64, _P, C.c_int64, C.c_int32]),
     "bfmf_get_symbolic": (C.c_int, [_h, C.POINTER(bfmf_symbolic_view)]),
     "bfmf_get_stats": (C.c_int, [_h, C.POINTER(bfmf_stats)]),
@@ -227,6 +228,16 @@ def bfmf_solve_device(h, dB, ldb, dX, ldx, nrhs, opts=None):
     if st not in (BFMF_OK, BFMF_E_NOCONV):
         _check(h, st)
     return opts, st
+
+
+def bfmf_solve_async(h, dB, ldb, dX, ldx, nrhs, stream=None):
+    """Direct solve X = M^-1 B queued on `stream` (a hipStream_t as an int, e.g. torch's
+    cuda_stream); device pointers of interleaved complex128."""
+    o = bfmf_default_solve_opts()
+    o.max_iter = -1
+    _check(h, _lib.bfmf_solve_async(h, nrhs, C.c_void_p(dB), ldb, C.c_void_p(dX), ldx,
+                                    C.c_void_p(stream) if stream else None, C.byref(o)))
+    return o
 
 
 def bfmf_apply_preconditioner(h, B):
@@ -397,9 +408,9 @@ class Solver:
         return self
 
     def factor(self, tol=1e-3, n_min=1024, precision=BFMF_C128, batched=False, samples=64, knn=8,
-               alpha=2.0, seed=0, hbm_budget=0, keep_fronts=False, timing=False, smw_dense=0):
+               alpha=2.0, seed=0, hbm_budget=0, keep_fronts=False, timing=False, smw_dense=0, id_max_cols=0):
         o = bfmf_default_factor_opts()
-        o.smw_dense = smw_dense
+        o.smw_dense, o.id_max_cols = smw_dense, id_max_cols
         o.timing = int(bool(timing))
         o.tol, o.n_min, o.precision, o.batched = tol, n_min, precision, int(bool(batched))
         o.samples, o.knn, o.alpha, o.seed = samples, knn, alpha, seed

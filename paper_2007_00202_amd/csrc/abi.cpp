@@ -184,14 +184,27 @@ bfmf_status bfmf_factor(bfmf_handle h, const bfmf_factor_opts* opts) {
     else
       bfmf_default_factor_opts(&o);
     if (!(o.tol > 0) || o.samples < 0 || o.knn < 0 || o.alpha < 0 || o.smw_dense < 0 ||
-        (o.smw_dense > 0 && o.smw_dense < 16))
+        (o.smw_dense > 0 && o.smw_dense < 16) || o.id_max_cols < 0 || (o.id_max_cols > 0 && o.id_max_cols < 16))
       throw Error(BFMF_E_INVAL, "factor: bad options");
     if (o.precision != BFMF_C128 && o.precision != BFMF_C64_MIXED)
       throw Error(BFMF_E_INVAL, "factor: unknown precision");
     h->fopts = o;
     h->timer.enabled = o.timing != 0;
     h->state = State::Analyzed;
-    factor_dense(*h);
+    try {
+      factor_dense(*h);
+    } catch (...) {
+      // back to the analyzed state: no factor memory is kept (the next factorization allocates again)
+      (void)hipStreamSynchronize(h->stream);
+      if (h->comp) {
+        comp_state_destroy(h->comp);
+        h->comp = nullptr;
+      }
+      h->d_work.release();
+      h->d_fac.release();
+      h->d_kept.release();
+      throw;
+    }
     h->stats.device_bytes_peak = h->device_bytes();
     h->state = State::Factored;
   });
@@ -255,6 +268,41 @@ static bfmf_status solve_common(bfmf_handle h, int64_t nrhs, const double* B, in
 bfmf_status bfmf_solve(bfmf_handle h, int64_t nrhs, const double* B, int64_t ldb, double* X, int64_t ldx,
                        int32_t mem, bfmf_solve_opts* io) {
   return solve_common(h, nrhs, B, ldb, X, ldx, mem, io, false);
+}
+
+bfmf_status bfmf_solve_async(bfmf_handle h, int64_t nrhs, const double* dB, int64_t ldb, double* dX, int64_t ldx,
+                             void* hip_stream, bfmf_solve_opts* io) {
+  return guarded(h, [&] {
+    if (h->state != State::Factored) throw Error(BFMF_E_STATE, "solve_async before factor");
+    if (nrhs <= 0 || !dB || !dX || ldb < h->n || ldx < h->n) throw Error(BFMF_E_INVAL, "solve_async: bad arguments");
+    if (io && io->max_iter >= 0)
+      throw Error(BFMF_E_INVAL, "solve_async: only the direct solve (max_iter < 0) is queued without host "
+                                "synchronisation; GMRES needs the host at every iteration (use bfmf_solve)");
+    const double t0 = now_s();
+    hipStream_t own = h->stream, s = hip_stream ? (hipStream_t)hip_stream : h->stream;
+    if (!h->async_ev) HIPCHK(hipEventCreateWithFlags(&h->async_ev, hipEventDisableTiming));
+    if (s != own) {  // the handle's earlier work precedes this call's
+      HIPCHK(hipEventRecord(h->async_ev, own));
+      HIPCHK(hipStreamWaitEvent(s, h->async_ev, 0));
+    }
+    h->stream = s;  // every launch and staged copy of the application goes to the caller's stream
+    try {
+      apply_preconditioner_dev(*h, dB, ldb, dX, ldx, nrhs);
+    } catch (...) {
+      h->stream = own;
+      throw;
+    }
+    h->stream = own;
+    if (s != own) {  // and the handle's later work follows it
+      HIPCHK(hipEventRecord(h->async_ev, s));
+      HIPCHK(hipStreamWaitEvent(own, h->async_ev, 0));
+    }
+    if (io) {
+      io->iters_max = 0;
+      io->relres_max = -1;  // not computed: that would need the host to wait
+      io->seconds = now_s() - t0;
+    }
+  });
 }
 
 bfmf_status bfmf_apply_preconditioner(bfmf_handle h, int64_t nrhs, const double* B, int64_t ldb, double* X,
@@ -389,6 +437,7 @@ void bfmf_destroy(bfmf_handle h) {
   if (h->device >= 0) (void)hipSetDevice(h->device);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   h->pgraph.release();
+  if (h->async_ev) (void)hipEventDestroy(h->async_ev);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
 }

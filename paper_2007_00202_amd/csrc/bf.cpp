@@ -72,8 +72,15 @@ size_t DevPool::alloc(size_t bytes, hipStream_t s) {
   if (need > buf.bytes) {
     size_t cap = std::max<size_t>(need, buf.bytes * 2);
     cap = std::max<size_t>(cap, (size_t)64 << 20);
+    if (budget && !budget->fits(cap)) {  // the old buffer is held while the content is copied
+      cap = std::max<size_t>(need, (size_t)1 << 20);
+      if (!budget->fits(cap))
+        throw Error(BFMF_E_NOMEM, "butterfly pool growth to " + std::to_string(cap) +
+                                      " bytes exceeds the HBM budget");
+    }
     DevBuf nb;
     dev_alloc(nb, cap);
+    if (budget) budget->held += cap - buf.bytes;
     if (used) chk(hipMemcpyAsync(nb.p, buf.p, used, hipMemcpyDeviceToDevice, s), "pool grow");
     chk(hipStreamSynchronize(s), "pool grow");
     std::swap(buf.p, nb.p);
@@ -101,7 +108,11 @@ void* Scratch::take(size_t bytes) {
       std::swap(chunks[next], chunks[fit]);
     } else {
       auto ch = std::make_unique<Chunk>();
-      dev_alloc(ch->b, std::max(bytes, chunk_bytes));
+      const size_t cb = std::max(bytes, chunk_bytes);
+      if (budget && !budget->fits(cb))
+        throw Error(BFMF_E_NOMEM, "scratch chunk of " + std::to_string(cb) + " bytes exceeds the HBM budget");
+      dev_alloc(ch->b, cb);
+      if (budget) budget->held += cb;
       chunks.insert(chunks.begin() + next, std::move(ch));
     }
     cur = (int)next;
@@ -499,7 +510,7 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
     {
       HostTimer ht(HP_LAUNCH);
       chk(launch_grouped_gemm<T>((const GTask*)(d + toff[k]), (const int64_t*)(d + soff[k]),
-                                 (int)plan.phase[k].size(), ntiles[k], bases, cfgs[k], s, e0, e1),
+                                 (int)plan.phase[k].size(), ntiles[k], bases, cfgs[k], s, e0, e1, kind == K_ID),
           "grouped gemm");
     }
     c.gemm_cfg_launches[cfgs[k]] += 1;
@@ -693,9 +704,31 @@ template <class T>
 struct IdLevel {
   BfRuntime<T>& rt;
   explicit IdLevel(BfRuntime<T>& r) : rt(r) {}
-  // blocks: A_i (q_i x p_i) already in device memory; returns ranks and perms
+  // widest block one ID kernel takes (the kernels' limits, or a smaller forced one)
+  int max_cols() const {
+    const int lim = rt.tol >= 1e-4 ? GRAM_MAXP : CPQR_MAXP;
+    return rt.id_max_cols > 0 ? std::min(rt.id_max_cols, lim) : lim;
+  }
+  // blocks: A_i (q_i x p_i) already in device memory; returns ranks and perms.  Blocks wider than
+  // max_cols() are decomposed as an ID of sub-IDs: IDs of column chunks, then the ID of the chunks'
+  // skeleton columns, the interpolation matrices composed by one product per chunk.
   void run(const std::vector<void*>& A, const std::vector<int>& q, const std::vector<int>& p, std::vector<int>& rank,
            std::vector<std::vector<int32_t>>& perm) {
+    const int lim = max_cols();
+    bool wide = false;
+    for (int pi : p) wide |= pi > lim;
+    if (!wide) {
+      run_direct(A, q, p, rank, perm);
+      return;
+    }
+    run_chunked(A, q, p, rank, perm, lim);
+  }
+
+  void run_chunked(const std::vector<void*>& A, const std::vector<int>& q, const std::vector<int>& p,
+                   std::vector<int>& rank, std::vector<std::vector<int32_t>>& perm, int lim);
+
+  void run_direct(const std::vector<void*>& A, const std::vector<int>& q, const std::vector<int>& p,
+                  std::vector<int>& rank, std::vector<std::vector<int32_t>>& perm) {
     const size_t nb = A.size();
     hipStream_t s = rt.s();
     std::vector<IdTask> tasks(nb);
@@ -706,8 +739,9 @@ struct IdLevel {
     int64_t po = 0;
     const bool gram = rt.tol >= 1e-4;  // Gram variant for tolerances where eps p / tol^2 is negligible
     for (size_t i = 0; i < nb; ++i) {
-      // the Gram kernel takes up to 2048 columns, the Householder kernel 1024; both up to 2048 rows
-      if (p[i] > (gram ? GRAM_MAXP : CPQR_MAXP) || q[i] > 2048)
+      // the Gram kernel takes up to 2048 columns and any number of rows (it sees A^H A); the
+      // Householder kernel up to 1024 columns and 2048 rows (wider blocks are chunked by run())
+      if (p[i] > (gram ? GRAM_MAXP : CPQR_MAXP) || (!gram && q[i] > 2048))
         throw Error(BFMF_E_INVAL, "ID block too large (" + std::to_string(q[i]) + " x " + std::to_string(p[i]) + ")");
       const int maxrank = std::max(1, std::min(p[i], q[i]));
       void* Tb = rt.scratch.take((size_t)maxrank * std::max(p[i], 1) * sizeof(cplx<double>));
@@ -803,6 +837,7 @@ struct IdLevel {
     }
     d_tasks = dt;
     ntasks = (int)nb;
+    htasks = tasks;
   }
   // expand the interpolation matrices into outs (device, ld per block)
   void expand(const std::vector<void*>& outs, const std::vector<int64_t>& ldo, bool transpose, bool conj) {
@@ -817,7 +852,217 @@ struct IdLevel {
   }
   IdTask* d_tasks = nullptr;
   int ntasks = 0;
+  std::vector<IdTask> htasks;  // host copy of the tasks behind d_tasks
 };
+
+// ID of sub-IDs for blocks wider than one kernel takes.  A block's columns are split into chunks of
+// at most lim; chunk c gives A(:, c) ~= A(:, J_c) Z_c.  The chunks' skeleton columns, side by side,
+// form A2 = A(:, J_1 .. J_m), whose ID A2 ~= A(:, J) Z2 (again chunked if A2 is still too wide)
+// gives the block's skeleton J and, per chunk, Z(:, c) = Z2(:, J_c part) Z_c: one grouped product.
+// The interpolation error is that of the two levels of IDs added (about twice the tolerance).
+template <class T>
+void IdLevel<T>::run_chunked(const std::vector<void*>& A, const std::vector<int>& q, const std::vector<int>& p,
+                             std::vector<int>& rank, std::vector<std::vector<int32_t>>& perm, int lim) {
+  const size_t nb = A.size();
+  hipStream_t s = rt.s();
+  const size_t esz = sizeof(cplx<double>);
+  // stage 1: narrow blocks as they are, wide blocks as chunks, all in one launch
+  std::vector<void*> A1;
+  std::vector<int> q1, p1;
+  std::vector<int> first(nb), nchunk(nb, 1);
+  std::vector<std::vector<int>> cbeg(nb);
+  for (size_t i = 0; i < nb; ++i) {
+    first[i] = (int)A1.size();
+    if (p[i] <= lim) {
+      A1.push_back(A[i]);
+      q1.push_back(q[i]);
+      p1.push_back(p[i]);
+      cbeg[i] = {0, p[i]};
+      continue;
+    }
+    // chunks of near-equal width w <= lim (their number can fall below ceil(p / lim): count them)
+    const int m = (p[i] + lim - 1) / lim, w = (p[i] + m - 1) / m;
+    ++rt.n_chunked;
+    for (int c0 = 0; c0 < p[i]; c0 += w) {
+      const int pc = std::min(w, p[i] - c0);
+      A1.push_back((char*)A[i] + (size_t)c0 * std::max(q[i], 1) * esz);
+      q1.push_back(q[i]);
+      p1.push_back(pc);
+      cbeg[i].push_back(c0);
+    }
+    nchunk[i] = (int)cbeg[i].size();
+    cbeg[i].push_back(p[i]);
+  }
+  // the Householder kernel overwrites its blocks: keep the wide blocks' columns for the second stage
+  std::vector<const cplx<double>*> src(nb);
+  {
+    std::vector<AxpbyTask> cp;
+    for (size_t i = 0; i < nb; ++i) {
+      src[i] = (const cplx<double>*)A[i];
+      if (nchunk[i] == 1 || rt.tol >= 1e-4) continue;
+      const int qq = std::max(q[i], 1);
+      cplx<double>* keep = (cplx<double>*)rt.scratch.take((size_t)qq * std::max(p[i], 1) * esz);
+      cp.push_back(AxpbyTask{keep, A[i], qq, qq, q[i], p[i], 0});
+      src[i] = keep;
+    }
+    int64_t maxe = 0;
+    for (const AxpbyTask& t : cp) maxe = std::max<int64_t>(maxe, t.m * t.ncol);
+    if (!cp.empty())
+      chk(launch_axpby_batch<double>((const AxpbyTask*)upload_tmp(rt, cp), (int)cp.size(), maxe, 1.0, 0.0, s),
+          "keep wide blocks");
+  }
+  std::vector<int> r1;
+  std::vector<std::vector<int32_t>> perm1;
+  run_direct(A1, q1, p1, r1, perm1);
+  const std::vector<IdTask> t1 = htasks;
+  IdTask* d_t1 = d_tasks;
+  std::vector<IdTask> out(nb);
+  rank.assign(nb, 0);
+  perm.assign(nb, {});
+  std::vector<AxpbyTask> gather;  // column copies, run together per phase
+  for (size_t i = 0; i < nb; ++i) {
+    if (nchunk[i] == 1) {
+      out[i] = t1[first[i]];
+      rank[i] = r1[first[i]];
+      perm[i] = perm1[first[i]];
+      continue;
+    }
+    // the chunks' skeleton columns side by side
+    std::vector<int32_t> Jall;
+    std::vector<int> soff;
+    for (int c = 0; c < nchunk[i]; ++c) {
+      const int k = first[i] + c;
+      soff.push_back((int)Jall.size());
+      for (int t = 0; t < r1[k]; ++t) Jall.push_back(cbeg[i][c] + perm1[k][t]);
+    }
+    soff.push_back((int)Jall.size());
+    const int ns = (int)Jall.size(), qq = std::max(q[i], 1);
+    // every chunk of full rank: a second stage would be as wide as the block (no progress); a block
+    // within the kernels' own limits (the cap was forced lower) is decomposed directly instead
+    if (ns >= p[i]) {
+      const int klim = rt.tol >= 1e-4 ? GRAM_MAXP : CPQR_MAXP;
+      if (p[i] > klim)
+        throw Error(BFMF_E_INVAL, "ID block of " + std::to_string(q[i]) + " x " + std::to_string(p[i]) +
+                                      ": its column chunks of at most " + std::to_string(lim) +
+                                      " have full rank, more than one decomposition kernel takes");
+      IdLevel<T> whole(rt);
+      std::vector<int> rw;
+      std::vector<std::vector<int32_t>> pw;
+      whole.run_direct({(void*)src[i]}, {q[i]}, {p[i]}, rw, pw);
+      out[i] = whole.htasks[0];
+      rank[i] = rw[0];
+      perm[i] = pw[0];
+      continue;
+    }
+    cplx<double>* A2 = (cplx<double>*)rt.scratch.take((size_t)std::max(ns, 1) * qq * esz);
+    gather.clear();
+    for (int t = 0; t < ns; ++t)
+      gather.push_back(AxpbyTask{A2 + (size_t)t * qq, src[i] + (size_t)Jall[t] * qq, qq, qq, q[i], 1, 0});
+    if (!gather.empty())
+      chk(launch_axpby_batch<double>((const AxpbyTask*)upload_tmp(rt, gather), (int)gather.size(), q[i], 1.0, 0.0, s),
+          "gather skeleton columns");
+    IdLevel<T> sub(rt);
+    std::vector<int> r2;
+    std::vector<std::vector<int32_t>> perm2;
+    sub.run({(void*)A2}, {q[i]}, {ns}, r2, perm2);
+    const int r = r2[0];
+    // dense interpolation matrices: Z2 (r x ns) and Z_c (r_c x p_c), written transposed by the expansion
+    cplx<double>* Z2 = (cplx<double>*)rt.scratch.take((size_t)std::max(r, 1) * std::max(ns, 1) * esz);
+    std::vector<void*> zo{Z2};
+    std::vector<int64_t> zl{std::max(r, 1)};
+    {
+      PackedUpload<BfRuntime<T>> pk(rt);
+      const int po = pk.add(zo.data(), sizeof(void*)), pl = pk.add(zl.data(), sizeof(int64_t));
+      void** d_o = (void**)pk.part(po);
+      int64_t* d_l = (int64_t*)pk.part(pl);
+      pk.commit();
+      if (r > 0) chk(launch_id_expand<double>(sub.d_tasks, 1, d_o, d_l, true, false, s), "expand Z2");
+    }
+    std::vector<cplx<double>*> Zc(nchunk[i]);
+    {
+      std::vector<void*> co;
+      std::vector<int64_t> cl;
+      for (int c = 0; c < nchunk[i]; ++c) {
+        const int k = first[i] + c;
+        Zc[c] = (cplx<double>*)rt.scratch.take((size_t)std::max(r1[k], 1) * std::max(p1[k], 1) * esz);
+        co.push_back(Zc[c]);
+        cl.push_back(std::max(r1[k], 1));
+      }
+      PackedUpload<BfRuntime<T>> pk(rt);
+      const int po = pk.add(co.data(), co.size() * sizeof(void*)), pl = pk.add(cl.data(), cl.size() * sizeof(int64_t));
+      void** d_o = (void**)pk.part(po);
+      int64_t* d_l = (int64_t*)pk.part(pl);
+      pk.commit();
+      chk(launch_id_expand<double>(d_t1 + first[i], nchunk[i], d_o, d_l, true, false, s), "expand Z_c");
+    }
+    // Z (r x p) = per chunk Z2(:, soff_c .. soff_c + r_c) Z_c
+    const int maxrank = std::max(1, std::min(p[i], q[i]));
+    cplx<double>* Z = (cplx<double>*)rt.scratch.take((size_t)std::max(r, 1) * std::max(p[i], 1) * esz);
+    std::vector<GTask> gt;
+    for (int c = 0; c < nchunk[i]; ++c) {
+      const int k = first[i] + c, rc = r1[k], pc = p1[k];
+      if (r == 0 || pc == 0) continue;
+      GTask g = {};
+      g.a_off = (int64_t)((uintptr_t)(Z2 + (size_t)soff[c] * std::max(r, 1)) / esz);
+      g.lda = std::max(r, 1);
+      g.opA = OP_N;
+      g.abase = 4;
+      g.b_off = (int64_t)((uintptr_t)Zc[c] / esz);
+      g.ldb = std::max(rc, 1);
+      g.opB = OP_N;
+      g.bbase = 4;
+      g.c_off = (int64_t)((uintptr_t)(Z + (size_t)cbeg[i][c] * std::max(r, 1)) / esz);
+      g.ldc = std::max(r, 1);
+      g.cbase = 4;
+      g.M = r;
+      g.N = pc;
+      g.K = rc;
+      g.alpha_re = 1;
+      g.beta = 0;
+      if (rc == 0) {  // no skeleton in the chunk: its columns interpolate to zero
+        gather.clear();
+        gather.push_back(AxpbyTask{Z + (size_t)cbeg[i][c] * r, nullptr, r, r, r, pc, 0});
+        chk(launch_axpby_batch<double>((const AxpbyTask*)upload_tmp(rt, gather), 1, (int64_t)r * pc, 0.0, 0.0, s),
+            "zero chunk");
+        continue;
+      }
+      gt.push_back(g);
+    }
+    if (!gt.empty()) {
+      BfPlan gp;
+      gp.phase.push_back(gt);
+      const int64_t lim4[4] = {0, 0, 0, 0};
+      run_plan<double>(gp, *rt.c, nullptr, nullptr, nullptr, nullptr, s, lim4, K_ID);
+    }
+    // the block's ID: skeleton J (in the order of the second ID), then the other columns ascending;
+    // T = Z(:, other columns)
+    std::vector<int32_t> pm;
+    std::vector<char> isk(p[i], 0);
+    for (int t = 0; t < r; ++t) {
+      pm.push_back(Jall[perm2[0][t]]);
+      isk[Jall[perm2[0][t]]] = 1;
+    }
+    for (int j = 0; j < p[i]; ++j)
+      if (!isk[j]) pm.push_back(j);
+    cplx<double>* Tb = (cplx<double>*)rt.scratch.take((size_t)maxrank * std::max(p[i], 1) * esz);
+    gather.clear();
+    for (int c = 0; c + r < p[i]; ++c)
+      if (r > 0) gather.push_back(AxpbyTask{Tb + (size_t)c * maxrank, Z + (size_t)pm[r + c] * r, maxrank, r, r, 1, 0});
+    if (!gather.empty())
+      chk(launch_axpby_batch<double>((const AxpbyTask*)upload_tmp(rt, gather), (int)gather.size(), r, 1.0, 0.0, s),
+          "interpolation columns");
+    int32_t* d_rk = rt.scratch.template take_n<int32_t>(1);
+    int32_t* d_pm = (int32_t*)upload_tmp(rt, pm);
+    const std::vector<int32_t> rk{r};
+    rt.c->stage.put(d_rk, rk.data(), sizeof(int32_t), s);
+    out[i] = IdTask{A[i], qq, q[i], p[i], maxrank, d_rk, d_pm, Tb, nullptr, nullptr};
+    rank[i] = r;
+    perm[i] = pm;
+  }
+  htasks = out;
+  d_tasks = (IdTask*)upload_tmp(rt, out);
+  ntasks = (int)nb;
+}
 
 template <class T>
 struct FactorAlloc {

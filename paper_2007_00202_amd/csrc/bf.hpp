@@ -27,6 +27,7 @@ namespace bfmf {
 struct DevPool {
   DevBuf buf;
   size_t used = 0;
+  Budget* budget = nullptr;  // growth charged here when set
   size_t alloc(size_t bytes, hipStream_t s);  // 256-byte aligned byte offset
   char* base() const { return buf.as<char>(); }
   void reset() { used = 0; }
@@ -43,6 +44,7 @@ struct Scratch {
   std::vector<std::unique_ptr<Chunk>> chunks;
   int cur = -1;  // chunk holding the top of the stack
   size_t chunk_bytes = (size_t)256 << 20;
+  Budget* budget = nullptr;  // new chunks charged here when set
   struct Mark {
     int cur;
     size_t top;
@@ -181,6 +183,8 @@ struct BfRuntime {
   int samples = 64;
   int max_samples = 1024;
   int smw_dense = 1024;               // BF_SMW blocks of at most this many rows are inverted densely
+  int id_max_cols = 0;                // > 0: blocks wider than this are decomposed as IDs of sub-IDs
+  int64_t n_chunked = 0;              // ID blocks decomposed as IDs of sub-IDs
   double tol = 1e-3;
   int max_rank_seen = 0;
   int64_t n_random = 0, n_entry = 0;  // constructions performed

@@ -830,15 +830,29 @@ static void reset_state(CompState<T>& st, Context& c, int nfronts) {
   st.fronts.resize(nfronts);
   st.rt.c = &c;
   st.rt.pool.reset();
+  // buffers kept from an earlier factorization count against this one's budget; beyond it they are
+  // released and grown again under the budget
+  uint64_t held = st.rt.pool.buf.bytes;
+  for (auto& ch : st.rt.scratch.chunks) held += ch->b.bytes;
+  if (held > c.fbudget.limit) {
+    st.rt.pool.buf.release();
+    st.rt.scratch.clear();
+    held = 0;
+  }
+  c.fbudget.held = held;
+  st.rt.pool.budget = &c.fbudget;
+  st.rt.scratch.budget = &c.fbudget;
   st.rt.tol = c.fopts.tol;
   st.rt.samples = c.fopts.samples > 0 ? c.fopts.samples : 64;
   st.rt.seed = c.fopts.seed;
   st.rt.stream_id = 0;
   st.rt.max_rank_seen = 0;
+  st.rt.n_chunked = 0;
   st.rt.sample_hint.clear();
   st.rt.batch = c.fopts.batched != 0;
   // measured on the 100^3 workload: a dense base of 1024 rows beats 128, 256, 512 and 2048
   st.rt.smw_dense = c.fopts.smw_dense > 0 ? c.fopts.smw_dense : 1024;
+  st.rt.id_max_cols = c.fopts.id_max_cols;
   if (!st.status.p) {
     HIPCHK(dev_malloc((void**)&st.status.p, 16));
     st.status.bytes = 16;
@@ -1587,14 +1601,16 @@ uint64_t comp_state_bytes(void* state) {
   return (h->d ? state_bytes(*h->d) : 0) + (h->f ? state_bytes(*h->f) : 0);
 }
 
-void compressed_stats(void* state, double& bytes, int& maxrank) {
+void compressed_stats(void* state, double& bytes, int& maxrank, int& chunked) {
   auto* h = (CompHolder*)state;
   if (h->single) {
     bytes = (double)h->f->rt.pool.used;
     maxrank = h->f->rt.max_rank_seen;
+    chunked = (int)h->f->rt.n_chunked;
   } else {
     bytes = (double)h->d->rt.pool.used;
     maxrank = h->d->rt.max_rank_seen;
+    chunked = (int)h->d->rt.n_chunked;
   }
 }
 

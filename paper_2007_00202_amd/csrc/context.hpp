@@ -11,6 +11,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <complex>
 #include <vector>
 
 #include "../../include/bfmf.h"
@@ -44,6 +45,15 @@ struct DevBuf {
   T* as() const {
     return (T*)p;
   }
+};
+
+// Device bytes that growable buffers of a factorization may hold together (the
+// hbm_budget left after the level workspaces and dense factors); growth beyond
+// it raises E_NOMEM before anything is allocated.
+struct Budget {
+  uint64_t limit = ~0ull;
+  uint64_t held = 0;
+  bool fits(uint64_t add) const { return held + add <= limit; }
 };
 
 class Error : public std::exception {
@@ -206,6 +216,7 @@ struct Context {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipEvent_t async_ev = nullptr;  // orders bfmf_solve_async's stream with the handle's
   State state = State::Created;
   std::string last_error;
 
@@ -255,6 +266,9 @@ struct Context {
   DevBuf g_tmp_scatter;  // task list of a level's batched scatter in the backward sweep (one per front)
   Staging stage;      // pinned ring of host-to-device uploads
   int64_t g_nrhs = 0, g_restart = 0;
+  std::vector<int32_t> g_col_iters;   // per column of the last GMRES call: iterations,
+  std::vector<double> g_col_relres;   // true relative residual,
+  std::vector<uint8_t> g_col_done;    // and whether it met the stopping test
   void* g_Vp = nullptr;  // Krylov basis: g_V, or the idle level workspace d_work when it is large enough
 
   KernelTimer timer;
@@ -264,6 +278,7 @@ struct Context {
   std::vector<int32_t> level_order;   // fronts in level order, dense first within a level
   std::vector<int32_t> level_ndense;  // dense fronts of each level
   void* comp = nullptr;               // CompState (compressed.cpp)
+  Budget fbudget;                     // what the compressed fronts' pool and scratch may still take
   bool verbose = false;               // BFMF_VERBOSE: phase timings of compressed fronts on stderr
   HostProf hprof;                     // host time of the last factorization by activity (verbose only)
 
@@ -297,10 +312,35 @@ void forward_compressed_level(void* state, Context& c, const std::vector<int>& f
                               const std::vector<int>& ns, int nrhs);
 void backward_compressed_level(void* state, Context& c, const std::vector<int>& fronts,
                                const std::vector<void*>& Ws, const std::vector<int>& ns, int nrhs);
-void compressed_stats(void* state, double& bytes, int& maxrank);
+void compressed_stats(void* state, double& bytes, int& maxrank, int& chunked);
 uint64_t comp_state_bytes(void* state);  // device bytes held by the compressed fronts' pools
 // Y = B X for a block of compressed front f (0 F11, 1 F11^-1, 2 F12, 3 F21, 4 S); host complex128 arrays
 void comp_apply_block(void* state, int f, int what, int nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy);
+
+// Continuous-batching GMRES of the serving form: the columns ("slots") of B and X
+// (device, n x slots, ld n) each run their own restarted GMRES(m) with the
+// handle's preconditioner, at their own step; a column is admitted or retired
+// between iterations, and its arithmetic does not depend on the other columns.
+struct SlotGmres {
+  enum { IDLE = 0, START = 1, RUN = 2 };
+  Context* c = nullptr;
+  int slots = 0, m = 30;
+  bfmf_solve_opts o{};
+  void* B = nullptr;
+  void* X = nullptr;
+  std::vector<int32_t> mode, j, iters;
+  std::vector<double> u0, tol_c, bnorm, relres;
+  std::vector<uint8_t> pc_met, ok;
+  std::vector<std::complex<double>> H, g, cs, sn, y;  // per slot: (m+1) x m, m+1, m, m; y m x slots
+  DevBuf dbuf;   // per-slot device arrays (pointers, modes, counts, norms)
+  int last_width = -1;
+  size_t stage_bytes = 0;
+  void init(Context& ctx, int nslots, const bfmf_solve_opts& opts, void* dB, void* dX);
+  void admit(int q);  // B(:, q) written and X(:, q) zeroed on the stream by the caller
+  bool busy() const;
+  // one iteration of every admitted column; `finished` gets the slots that completed (ok[q]: met the test)
+  void step(std::vector<int>& finished);
+};
 
 // plan.cpp
 void build_plan(Context& c);

@@ -54,10 +54,9 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
 }
 
 template <class T, class C>
-__global__ __launch_bounds__(256) void grouped_gemm_kernel(const GTask* __restrict__ tasks,
-                                                           const int64_t* __restrict__ tile_start, int ntasks,
-                                                           void* b0, void* b1, void* b2, void* b3) {
-  __shared__ TileSmem<T, C> sm;
+__device__ __forceinline__ void grouped_gemm_run(const GTask* __restrict__ tasks,
+                                                 const int64_t* __restrict__ tile_start, int ntasks, void* b0,
+                                                 void* b1, void* b2, void* b3, TileSmem<T, C>& sm) {
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const int lo = find_task(tile_start, ntasks, tile);
   const GTask& t = tasks[lo];
@@ -71,6 +70,25 @@ __global__ __launch_bounds__(256) void grouped_gemm_kernel(const GTask* __restri
   const cplx<T> alpha = {(T)t.alpha_re, (T)t.alpha_im};
   gemm_tile_cfg<T, C>(A, t.lda, t.opA, B, t.ldb, t.opB, Cm, t.ldc, t.M, t.N, t.K, alpha, t.beta, (int)(local % tm),
                       (int)(local / tm), sm);
+}
+
+// butterfly products (and every other grouped product but the Gram matrices of the IDs)
+template <class T, class C>
+__global__ __launch_bounds__(256) void grouped_gemm_kernel(const GTask* __restrict__ tasks,
+                                                           const int64_t* __restrict__ tile_start, int ntasks,
+                                                           void* b0, void* b1, void* b2, void* b3) {
+  __shared__ TileSmem<T, C> sm;
+  grouped_gemm_run<T, C>(tasks, tile_start, ntasks, b0, b1, b2, b3, sm);
+}
+
+// the same product for the Gram matrices G = A^H A of the interpolative decompositions (a kernel of
+// its own name, so that profiles tell the two classes apart)
+template <class T, class C>
+__global__ __launch_bounds__(256) void gram_gemm_kernel(const GTask* __restrict__ tasks,
+                                                        const int64_t* __restrict__ tile_start, int ntasks,
+                                                        void* b0, void* b1, void* b2, void* b3) {
+  __shared__ TileSmem<T, C> sm;
+  grouped_gemm_run<T, C>(tasks, tile_start, ntasks, b0, b1, b2, b3, sm);
 }
 
 // the LDS tile shapes of the launcher's cfg index (GEMM_CFG_TM / GEMM_CFG_TN)
@@ -949,7 +967,7 @@ __global__ void convert_kernel(cplx<T1>* __restrict__ Y, int64_t ldy, const cplx
 template <class T>
 hipError_t launch_grouped_gemm(const GTask* d_tasks, const int64_t* d_tile_start, int ntasks, int64_t ntiles,
                                void* const bases[4], int cfg, hipStream_t s, hipEvent_t ev_start,
-                               hipEvent_t ev_stop) {
+                               hipEvent_t ev_stop, bool gram) {
   if (ntasks == 0 || ntiles == 0) return hipSuccess;
   if (cfg < 0 || cfg >= GEMM_CFGS) return hipErrorInvalidValue;
   // grids are limited to 2^31 - 1 blocks in x (the host checks ntiles)
@@ -962,6 +980,16 @@ hipError_t launch_grouped_gemm(const GTask* d_tasks, const int64_t* d_tile_start
       hipLaunchKernelGGL(kernel, grid, block, 0, s, d_tasks, d_tile_start, ntasks, bases[0], bases[1], bases[2],
                          bases[3]);
   };
+  if (gram && cfg != GEMM_CFG_SKINNY) {
+    switch (cfg) {
+      case 0: go(gram_gemm_kernel<T, Tile64x64>); break;
+      case 1: go(gram_gemm_kernel<T, Tile32x128>); break;
+      case 2: go(gram_gemm_kernel<T, Tile128x32>); break;
+      case 3: go(gram_gemm_kernel<T, Tile16x256>); break;
+      default: go(gram_gemm_kernel<T, Tile256x16>); break;
+    }
+    return hipGetLastError();
+  }
   switch (cfg) {
     case 0: go(grouped_gemm_kernel<T, Tile64x64>); break;
     case 1: go(grouped_gemm_kernel<T, Tile32x128>); break;
@@ -1121,7 +1149,7 @@ hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int6
 
 #define INST(T)                                                                                                       \
   template hipError_t launch_grouped_gemm<T>(const GTask*, const int64_t*, int, int64_t, void* const[4], int,         \
-                                             hipStream_t, hipEvent_t, hipEvent_t);                                    \
+                                             hipStream_t, hipEvent_t, hipEvent_t, bool);                              \
   template hipError_t launch_cpqr_id<T>(const IdTask*, int, double, hipStream_t);                                     \
   template hipError_t launch_gram_id<T>(const IdTask*, int, double, int, int, hipStream_t);                           \
   template hipError_t launch_id_expand<T>(const IdTask*, int, void* const*, const int64_t*, bool, bool, hipStream_t);  \

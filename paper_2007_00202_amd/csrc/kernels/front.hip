@@ -490,6 +490,22 @@ __global__ __launch_bounds__(256) void schur_kernel(const FrontDesc* __restrict_
                1, t % tm, t / tm, sm);
 }
 
+// The same Schur complement with the product on FP32 MFMA: F21 and F12 rounded
+// to complex64 as they are staged, the product accumulated in FP32 and
+// subtracted from F22 in double (the complex64 form of the dense fronts).
+__global__ __launch_bounds__(256) void schur_mixed_kernel(const FrontDesc* __restrict__ fds) {
+  __shared__ GemmSmem<float> sm;
+  const FrontDesc& fd = fds[blockIdx.y];
+  const int ns = fd.ns, n = fd.n, nu = n - ns;
+  if (nu <= 0 || ns <= 0) return;
+  const int tm = (nu + GEMM_TM - 1) / GEMM_TM, tn = tm;
+  const int t = blockIdx.x;
+  if (t >= tm * tn) return;
+  cplx<double>* F = (cplx<double>*)fd.F;
+  gemm_tile<float, double>(F + ns, n, OP_N, F + (int64_t)ns * n, n, F + ns + (int64_t)ns * n, n, nu, nu, ns,
+                           cplx<float>{-1, 0}, 1, t % tm, t / tm, sm);
+}
+
 // ------------------------------------------------------------------ launchers
 #define KCHECK(expr)                       \
   do {                                     \
@@ -569,6 +585,21 @@ hipError_t launch_schur(const FrontDesc* d_fds, int nbatch, const int* h_n, cons
   }
   if (maxtiles > 0) {
     hipLaunchKernelGGL((schur_kernel<T>), dim3(maxtiles, nbatch), dim3(256), 0, s, d_fds);
+    KCHECK(hipGetLastError());
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_schur_mixed(const FrontDesc* d_fds, int nbatch, const int* h_n, const int* h_ns, hipStream_t s) {
+  int maxtiles = 0;
+  for (int b = 0; b < nbatch; ++b) {
+    const int nu = h_n[b] - h_ns[b];
+    if (nu <= 0 || h_ns[b] <= 0) continue;
+    const int t = ((nu + 63) / 64) * ((nu + 63) / 64);
+    maxtiles = t > maxtiles ? t : maxtiles;
+  }
+  if (maxtiles > 0) {
+    hipLaunchKernelGGL(schur_mixed_kernel, dim3(maxtiles, nbatch), dim3(256), 0, s, d_fds);
     KCHECK(hipGetLastError());
   }
   return hipSuccess;

@@ -21,6 +21,11 @@ __device__ __forceinline__ cplx<T> load_or_zero(const cplx<T>* p, bool ok) {
   return v;
 }
 
+template <class TO, class TI>
+__device__ __forceinline__ cplx<TO> to_cplx(cplx<TI> v) {
+  return cplx<TO>{(TO)v.re, (TO)v.im};
+}
+
 template <class T>
 struct GemmSmem {
   cplx<T> a[GEMM_TK][GEMM_TM];
@@ -30,9 +35,12 @@ struct GemmSmem {
 // Computes tile (tm, tn).  opA: OP_N -> A is M x K (lda); OP_T / OP_C -> A is
 // stored K x M (lda) and used transposed / conjugate-transposed.  opB: OP_N ->
 // B is K x N (ldb); OP_T / OP_C -> B is stored N x K.
-template <class T>
-__device__ __forceinline__ void gemm_tile(const cplx<T>* __restrict__ A, int64_t lda, int opA,
-                                          const cplx<T>* __restrict__ B, int64_t ldb, cplx<T>* __restrict__ C,
+// TL is the storage type of A, B and C; T that of the arithmetic (MFMA and
+// accumulation): with TL = double and T = float the operands are rounded to
+// complex64 as they are staged and the tile is added to C in double.
+template <class T, class TL = T>
+__device__ __forceinline__ void gemm_tile(const cplx<TL>* __restrict__ A, int64_t lda, int opA,
+                                          const cplx<TL>* __restrict__ B, int64_t ldb, cplx<TL>* __restrict__ C,
                                           int64_t ldc, int M, int N, int K, cplx<T> alpha, int beta, int tm, int tn,
                                           GemmSmem<T>& sm, int opB = OP_N) {
   typedef typename Mfma<T>::acc_t acc_t;
@@ -62,7 +70,7 @@ __device__ __forceinline__ void gemm_tile(const cplx<T>* __restrict__ A, int64_t
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int gr = row0 + rb0 + q;
-        ra[q] = load_or_zero(A + (int64_t)gr + (int64_t)gk * lda, gk < K && gr < M);
+        ra[q] = to_cplx<T>(load_or_zero(A + (int64_t)gr + (int64_t)gk * lda, gk < K && gr < M));
       }
     } else {
       const int r = tid >> 2, kb = (tid & 3) * 4;
@@ -70,7 +78,7 @@ __device__ __forceinline__ void gemm_tile(const cplx<T>* __restrict__ A, int64_t
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int gk = k0 + kb + q;
-        cplx<T> v = load_or_zero(A + (int64_t)gk + (int64_t)gr * lda, gk < K && gr < M);
+        cplx<T> v = to_cplx<T>(load_or_zero(A + (int64_t)gk + (int64_t)gr * lda, gk < K && gr < M));
         if (opA == OP_C) v.im = -v.im;
         ra[q] = v;
       }
@@ -81,7 +89,7 @@ __device__ __forceinline__ void gemm_tile(const cplx<T>* __restrict__ A, int64_t
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int gk = k0 + kb + q;
-        rb[q] = load_or_zero(B + (int64_t)gk + (int64_t)gc * ldb, gk < K && gc < N);
+        rb[q] = to_cplx<T>(load_or_zero(B + (int64_t)gk + (int64_t)gc * ldb, gk < K && gc < N));
       }
     } else {
       const int k = tid >> 4, cb = (tid & 15) * 4;
@@ -89,7 +97,7 @@ __device__ __forceinline__ void gemm_tile(const cplx<T>* __restrict__ A, int64_t
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int gc = col0 + cb + q;
-        cplx<T> v = load_or_zero(B + (int64_t)gc + (int64_t)gk * ldb, gk < K && gc < N);
+        cplx<T> v = to_cplx<T>(load_or_zero(B + (int64_t)gc + (int64_t)gk * ldb, gk < K && gc < N));
         if (opB == OP_C) v.im = -v.im;
         rb[q] = v;
       }
@@ -150,10 +158,11 @@ __device__ __forceinline__ void gemm_tile(const cplx<T>* __restrict__ A, int64_t
         const int gc = col0 + wc + j * 16 + (lane & 15);
         if (gr < M && gc < N) {
           const T pr = accr[i][j][r], pi = acci[i][j][r];
-          cplx<T> v = {alpha.re * pr - alpha.im * pi, alpha.re * pi + alpha.im * pr};
-          cplx<T>* dst = C + (int64_t)gr + (int64_t)gc * ldc;
-          if (beta) v = cadd(*dst, v);
-          *dst = v;
+          const cplx<T> v = {alpha.re * pr - alpha.im * pi, alpha.re * pi + alpha.im * pr};
+          cplx<TL>* dst = C + (int64_t)gr + (int64_t)gc * ldc;
+          cplx<TL> w = to_cplx<TL>(v);
+          if (beta) w = cadd(*dst, w);
+          *dst = w;
         }
       }
 }

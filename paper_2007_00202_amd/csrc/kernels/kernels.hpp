@@ -29,6 +29,8 @@ hipError_t launch_partial_lu(const FrontDesc* d_fds, int nbatch, const int* h_n,
 // Schur complement C = F22 - F21 F12 of nbatch fronts (after the LU loop).
 template <class T>
 hipError_t launch_schur(const FrontDesc* d_fds, int nbatch, const int* h_n, const int* h_ns, hipStream_t s);
+// the same on FP32 MFMA: complex128 fronts, operands rounded to complex64, product subtracted in double
+hipError_t launch_schur_mixed(const FrontDesc* d_fds, int nbatch, const int* h_n, const int* h_ns, hipStream_t s);
 // copy of the factor panels of dense fronts from F to P / F12 (null P: the host never sends these)
 template <class T>
 hipError_t launch_store_factor(const FrontDesc* d_fds, int nbatch, int64_t max_elems, hipStream_t s);
@@ -76,6 +78,16 @@ hipError_t launch_scale_cols(const void* nrm, const void* Wv, int64_t ldw, void*
 // X(:, c) += sum_{k<m} y(k, c) V_k(:, c), V_k at V + k * vstride
 hipError_t launch_basis_update(const void* y, int ldy, int m, const void* V, int64_t vstride, int64_t ldv, void* X,
                                int64_t ldx, int64_t N, int nrhs, hipStream_t s);
+// slot GMRES of the serving form (per-column arguments; see solve.hip)
+hipError_t launch_slot_gather(const void* const* d_src, void* Vcur, int64_t ld, int64_t N, int ncol, hipStream_t s);
+hipError_t launch_slot_fix(const int32_t* d_mode, const void* B, int64_t ldb, void* T, int64_t ldt, int64_t N, int ncol,
+                           hipStream_t s);
+hipError_t launch_axpy_cols_masked(const void* a, double sign, const void* V, int64_t ldv, void* Wv, int64_t ldw,
+                                   int64_t N, int nrhs, const int32_t* d_lim, int i0, hipStream_t s);
+hipError_t launch_scale_cols_to(const void* nrm, const void* Wv, int64_t ldw, void* const* d_dst, int64_t N, int nrhs,
+                                hipStream_t s);
+hipError_t launch_basis_update_masked(const void* y, int ldy, const int32_t* d_mc, const void* V, int64_t vstride,
+                                      int64_t ldv, void* X, int64_t ldx, int64_t N, int nrhs, hipStream_t s);
 
 // ---- butterfly support (bf.hip)
 // Tile shapes of the grouped GEMM (rows x columns of C per 256-thread
@@ -97,7 +109,7 @@ inline int64_t gemm_cfg_tiles(int cfg, int M, int N) {
 template <class T>
 hipError_t launch_grouped_gemm(const GTask* d_tasks, const int64_t* d_tile_start, int ntasks, int64_t ntiles,
                                void* const bases[4], int cfg, hipStream_t s, hipEvent_t ev_start = nullptr,
-                               hipEvent_t ev_stop = nullptr);
+                               hipEvent_t ev_stop = nullptr, bool gram = false);
 // truncated column-pivoted QR of every task's q x p block (tol: |R_kk| > tol |R_00|)
 template <class T>
 hipError_t launch_cpqr_id(const IdTask* d_tasks, int ntasks, double tol, hipStream_t s);

@@ -440,6 +440,70 @@ __global__ void basis_update_kernel(const cplx<double>* __restrict__ y, int ldy,
   X[i + c * ldx] = s;
 }
 
+// ------------------------------------------------ slot GMRES (serving)
+// Columns ("slots") of a serving batch each run their own GMRES cycle and may
+// be at different steps; these kernels take per-column arguments.
+
+// Vcur(:, c) = *src[c] (null: zero)
+__global__ void slot_gather_kernel(const cplx<double>* const* __restrict__ src, cplx<double>* __restrict__ Vcur,
+                                   int64_t ld, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= N) return;
+  const cplx<double>* p = src[c];
+  Vcur[i + c * ld] = p ? p[i] : cplx<double>{0, 0};
+}
+
+// mode[c] = 1 (restart): T(:, c) = B(:, c) - T(:, c); mode 0 (idle): T(:, c) = 0; mode 2: unchanged
+__global__ void slot_fix_kernel(const int32_t* __restrict__ mode, const cplx<double>* __restrict__ B, int64_t ldb,
+                                cplx<double>* __restrict__ T, int64_t ldt, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= N) return;
+  const int md = mode[c];
+  if (md == 2) return;
+  cplx<double> v = {0, 0};
+  if (md == 1) v = csub(B[i + c * ldb], T[i + c * ldt]);
+  T[i + c * ldt] = v;
+}
+
+// W(:, c) += sign a[c] V(:, c) for the columns with step >= i (lim[c] >= i)
+__global__ void axpy_cols_masked_kernel(const cplx<double>* __restrict__ a, double sign,
+                                        const cplx<double>* __restrict__ V, int64_t ldv, cplx<double>* __restrict__ Wv,
+                                        int64_t ldw, int64_t N, const int32_t* __restrict__ lim, int i0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= N || lim[c] < i0) return;
+  const cplx<double> s = {sign * a[c].re, sign * a[c].im};
+  Wv[i + c * ldw] = cadd(Wv[i + c * ldw], cmul(s, V[i + c * ldv]));
+}
+
+// *dst[c] = W(:, c) / nrm[c].re (0 if nrm is 0) for the columns with a destination
+__global__ void scale_cols_to_kernel(const cplx<double>* __restrict__ nrm, const cplx<double>* __restrict__ Wv,
+                                     int64_t ldw, cplx<double>* const* __restrict__ dst, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  cplx<double>* d = dst[c];
+  if (i >= N || !d) return;
+  const double r = nrm[c].re;
+  const double sc = r > 0 ? 1.0 / r : 0.0;
+  const cplx<double> w = Wv[i + c * ldw];
+  d[i] = cplx<double>{w.re * sc, w.im * sc};
+}
+
+// X(:, c) += sum_{k < mc[c]} y[k, c] Vbasis_k(:, c) for the columns with mc[c] > 0
+__global__ void basis_update_masked_kernel(const cplx<double>* __restrict__ y, int ldy, const int32_t* __restrict__ mc,
+                                           const cplx<double>* __restrict__ V, int64_t vstride, int64_t ldv,
+                                           cplx<double>* __restrict__ X, int64_t ldx, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  const int m = mc[c];
+  if (i >= N || m <= 0) return;
+  cplx<double> s = X[i + c * ldx];
+  for (int k = 0; k < m; ++k) s = cadd(s, cmul(y[k + c * ldy], V[k * vstride + i + c * ldv]));
+  X[i + c * ldx] = s;
+}
+
 // ------------------------------------------------------------------ launchers
 #define KCHECK(expr)                   \
   do {                                 \
@@ -567,6 +631,46 @@ hipError_t launch_basis_update(const void* y, int ldy, int m, const void* V, int
                                int64_t ldx, int64_t N, int nrhs, hipStream_t s) {
   hipLaunchKernelGGL(basis_update_kernel, dim3(blocks_for(N, 256), nrhs), dim3(256), 0, s, (const cplx<double>*)y,
                      ldy, m, (const cplx<double>*)V, vstride, ldv, (cplx<double>*)X, ldx, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_slot_gather(const void* const* d_src, void* Vcur, int64_t ld, int64_t N, int ncol, hipStream_t s) {
+  if (ncol == 0 || N == 0) return hipSuccess;
+  hipLaunchKernelGGL(slot_gather_kernel, dim3(blocks_for(N, 256), ncol), dim3(256), 0, s,
+                     (const cplx<double>* const*)d_src, (cplx<double>*)Vcur, ld, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_slot_fix(const int32_t* d_mode, const void* B, int64_t ldb, void* T, int64_t ldt, int64_t N, int ncol,
+                           hipStream_t s) {
+  if (ncol == 0 || N == 0) return hipSuccess;
+  hipLaunchKernelGGL(slot_fix_kernel, dim3(blocks_for(N, 256), ncol), dim3(256), 0, s, d_mode,
+                     (const cplx<double>*)B, ldb, (cplx<double>*)T, ldt, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_cols_masked(const void* a, double sign, const void* V, int64_t ldv, void* Wv, int64_t ldw,
+                                   int64_t N, int nrhs, const int32_t* d_lim, int i0, hipStream_t s) {
+  if (nrhs == 0 || N == 0) return hipSuccess;
+  hipLaunchKernelGGL(axpy_cols_masked_kernel, dim3(blocks_for(N, 256), nrhs), dim3(256), 0, s,
+                     (const cplx<double>*)a, sign, (const cplx<double>*)V, ldv, (cplx<double>*)Wv, ldw, N, d_lim, i0);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_cols_to(const void* nrm, const void* Wv, int64_t ldw, void* const* d_dst, int64_t N, int nrhs,
+                                hipStream_t s) {
+  if (nrhs == 0 || N == 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_cols_to_kernel, dim3(blocks_for(N, 256), nrhs), dim3(256), 0, s,
+                     (const cplx<double>*)nrm, (const cplx<double>*)Wv, ldw, (cplx<double>* const*)d_dst, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_basis_update_masked(const void* y, int ldy, const int32_t* d_mc, const void* V, int64_t vstride,
+                                      int64_t ldv, void* X, int64_t ldx, int64_t N, int nrhs, hipStream_t s) {
+  if (nrhs == 0 || N == 0) return hipSuccess;
+  hipLaunchKernelGGL(basis_update_masked_kernel, dim3(blocks_for(N, 256), nrhs), dim3(256), 0, s,
+                     (const cplx<double>*)y, ldy, d_mc, (const cplx<double>*)V, vstride, ldv, (cplx<double>*)X, ldx,
+                     N);
   return hipGetLastError();
 }
 

@@ -209,6 +209,10 @@ void factor_dense(Context& c) {
   if (need > budget || need > have)
     throw Error(BFMF_E_NOMEM, "front workspaces and dense factors need " + std::to_string(need) + " bytes, budget " +
                                   std::to_string(std::min<uint64_t>(budget, have)));
+  // the butterfly pool and scratch of the compressed fronts grow during the factorization: charged
+  // against what the budget leaves (unbounded without a budget: growth then fails only in hipMalloc)
+  c.fbudget.limit = c.fopts.hbm_budget ? budget - need : ~0ull;
+  c.fbudget.held = 0;
   if (c.d_work.bytes < (size_t)c.work_elems * elem) alloc(c.d_work, (size_t)c.work_elems * elem);
   if (c.d_fac.bytes < (size_t)c.fac_elems * elem) alloc(c.d_fac, std::max<size_t>((size_t)c.fac_elems * elem, 16));
   if (c.fopts.keep_fronts) {
@@ -317,7 +321,10 @@ void factor_dense(Context& c) {
             "partial LU");
       c.timer.end(tk, c.stream, K_LU, lu_flops, 0);
       tk = c.timer.begin(c.stream);
-      check(launch_schur<double>(dfds + lo, hi - lo, hn.data(), hns.data(), c.stream), "schur");
+      if (c.fopts.precision == BFMF_C64_MIXED)  // complex64 form: the Schur product on FP32 MFMA
+        check(launch_schur_mixed(dfds + lo, hi - lo, hn.data(), hns.data(), c.stream), "schur");
+      else
+        check(launch_schur<double>(dfds + lo, hi - lo, hn.data(), hns.data(), c.stream), "schur");
       c.timer.end(tk, c.stream, K_SCHUR, sch_flops, sch_bytes);
       tk = c.timer.begin(c.stream);
       check(launch_store_factor<double>(dfds + lo, hi - lo, maxstore, c.stream), "factor store");
@@ -390,12 +397,13 @@ void factor_dense(Context& c) {
     flops += 8.0 / 3.0 * ns * ns * ns + 8.0 * ns * ns * nu + 8.0 * ns * nu * nu;
     bytes += fb;
   }
-  int maxrank = 0;
+  int maxrank = 0, chunked = 0;
   if (ncomp) {
     double cb = 0;
-    compressed_stats(c.comp, cb, maxrank);
+    compressed_stats(c.comp, cb, maxrank, chunked);
     bytes += cb;
   }
+  c.stats.id_chunked = chunked;
   c.stats.factor_flops = flops;
   c.stats.factor_bytes = bytes;
   c.stats.dense_factor_bytes = dense_bytes;
@@ -706,9 +714,13 @@ int gmres_dev(Context& c, const void* dB, int64_t ldb, void* dX, int64_t ldx, in
     o.iters_max = 0;
     o.relres_max = 0;
     bool ok = true;
+    c.g_col_iters.assign(nr, 0);
+    c.g_col_relres.assign(relres.begin(), relres.end());
+    c.g_col_done.assign(nr, 1);
     for (int q = 0; q < nr; ++q) {
       o.relres_max = std::max(o.relres_max, relres[q]);
-      ok &= !(o.true_rtol > 0) || relres[q] <= o.true_rtol;
+      c.g_col_done[q] = !(o.true_rtol > 0) || relres[q] <= o.true_rtol;
+      ok &= (bool)c.g_col_done[q];
     }
     return ok ? 0 : 1;
   }
@@ -848,7 +860,264 @@ int gmres_dev(Context& c, const void* dB, int64_t ldb, void* dX, int64_t ldx, in
   }
   bool ok = true;
   for (int q = 0; q < nr; ++q) ok &= (bool)done[q];
+  c.g_col_iters.assign(iters.begin(), iters.end());
+  c.g_col_relres.assign(relres.begin(), relres.end());
+  c.g_col_done.assign(done.begin(), done.end());
   return ok ? 0 : 1;
+}
+
+// ------------------------------------------------------------ slot GMRES
+// Device arrays of a slot iteration (per slot, in dbuf): source pointers of the gathered columns,
+// destination pointers of the new basis vectors, modes, MGS limits, basis-update counts, the norms of
+// the preconditioned vectors and of the true residuals.
+namespace {
+struct SlotArrays {
+  const void** src;
+  void** dst;
+  int32_t *mode, *lim, *mc;
+  std::complex<double>*norm, *tn;
+};
+SlotArrays slot_arrays(DevBuf& b, int slots) {
+  char* p = b.as<char>();
+  SlotArrays a;
+  a.src = (const void**)p;
+  a.dst = (void**)(p + 8 * (size_t)slots);
+  a.mode = (int32_t*)(p + 16 * (size_t)slots);
+  a.lim = a.mode + slots;
+  a.mc = a.lim + slots;
+  a.norm = (std::complex<double>*)(p + ((28 * (size_t)slots + 15) & ~(size_t)15));
+  a.tn = a.norm + slots;
+  return a;
+}
+size_t slot_bytes(int slots) { return ((28 * (size_t)slots + 15) & ~(size_t)15) + 32 * (size_t)slots; }
+}  // namespace
+
+void SlotGmres::init(Context& ctx, int nslots, const bfmf_solve_opts& opts, void* dB, void* dX) {
+  c = &ctx;
+  slots = nslots;
+  o = opts;
+  if (o.restart <= 0) o.restart = 30;
+  if (o.max_iter <= 0) o.max_iter = 300;
+  m = o.restart;
+  B = dB;
+  X = dX;
+  mode.assign(slots, IDLE);
+  j.assign(slots, 0);
+  iters.assign(slots, 0);
+  u0.assign(slots, -1);
+  tol_c.assign(slots, o.rtol);
+  bnorm.assign(slots, -1);
+  relres.assign(slots, 1);
+  pc_met.assign(slots, 0);
+  ok.assign(slots, 0);
+  H.assign((size_t)(m + 1) * m * slots, 0);
+  g.assign((size_t)(m + 1) * slots, 0);
+  cs.assign((size_t)m * slots, 0);
+  sn.assign((size_t)m * slots, 0);
+  y.assign((size_t)m * slots, 0);
+  gmres_workspace(ctx, slots, m);
+  ensure_workspace(ctx, slots);
+  if (dbuf.bytes < slot_bytes(slots)) {
+    dbuf.release();
+    HIPCHK(dev_malloc((void**)&dbuf.p, slot_bytes(slots)));
+    dbuf.bytes = slot_bytes(slots);
+  }
+  last_width = -1;
+}
+
+void SlotGmres::admit(int q) {
+  mode[q] = START;
+  j[q] = 0;
+  iters[q] = 0;
+  u0[q] = -1;
+  tol_c[q] = o.rtol;
+  bnorm[q] = -1;
+  relres[q] = 1;
+  pc_met[q] = 0;
+  ok[q] = 0;
+}
+
+bool SlotGmres::busy() const {
+  for (int md : mode)
+    if (md != IDLE) return true;
+  return false;
+}
+
+void SlotGmres::step(std::vector<int>& finished) {
+  typedef std::complex<double> cd;
+  finished.clear();
+  Context& cc = *c;
+  const int64_t N = cc.n;
+  int width = 0;
+  for (int q = 0; q < slots; ++q)
+    if (mode[q] != IDLE) width = q + 1;
+  if (width == 0) return;
+  int Wd = 1;  // the preconditioner runs on a power-of-two number of columns (one captured graph per width)
+  while (Wd < width) Wd *= 2;
+  Wd = std::min(Wd, slots);
+  gmres_workspace(cc, slots, m);  // the basis may live in the level workspace: refresh its address
+  const size_t elem = sizeof(cd);
+  cd* V = (cd*)cc.g_Vp;
+  cd* Vcur = cc.g_tmp.as<cd>();
+  cd* T = cc.g_r.as<cd>();
+  cd* w = cc.g_w.as<cd>();
+  cd* hcol = cc.g_scal.as<cd>();
+  cd* ydev = hcol + (size_t)(m + 2) * slots;
+  const int64_t vstride = N * slots;
+  const int nblk = (int)std::min<int64_t>(256, (N + 255) / 256);
+  SlotArrays da = slot_arrays(dbuf, slots);
+  // 1. the vector each column multiplies: x (restart: T = b - A x) or its current basis vector
+  std::vector<const void*> src(Wd, nullptr);
+  std::vector<int32_t> md(Wd, 0), lim(Wd, -1);
+  int jmax = -1;
+  for (int q = 0; q < Wd; ++q) {
+    if (mode[q] == START) {
+      src[q] = (cd*)X + (size_t)q * N;
+      md[q] = 1;
+    } else if (mode[q] == RUN) {
+      src[q] = V + (size_t)j[q] * vstride + (size_t)q * N;
+      md[q] = 2;
+      lim[q] = j[q];
+      jmax = std::max(jmax, j[q]);
+    }
+  }
+  cc.stage.put(da.src, src.data(), Wd * sizeof(void*), cc.stream);
+  cc.stage.put(da.mode, md.data(), Wd * sizeof(int32_t), cc.stream);
+  cc.stage.put(da.lim, lim.data(), Wd * sizeof(int32_t), cc.stream);
+  check(launch_slot_gather(da.src, Vcur, N, N, Wd, cc.stream), "slot gather");
+  check(launch_spmv(cc.d_rowptr.as<int64_t>(), cc.d_colind.as<int32_t>(), cc.d_values.p, Vcur, N, T, N, nullptr, 0, N,
+                    Wd, cc.stream),
+        "spmv");
+  check(launch_slot_fix(da.mode, B, N, T, N, N, Wd, cc.stream), "slot fix");
+  check(launch_dots(nullptr, 0, T, N, N, Wd, cc.g_part.p, nblk, da.tn, true, cc.stream), "norm");
+  // 2. w = M^-1 T: an eager application at a new width (it sizes the staged task lists), replays after
+  if (Wd != last_width) {
+    const size_t put0 = cc.stage.put_bytes;
+    apply_preconditioner_dev(cc, T, N, w, N, Wd);
+    stage_bytes = cc.stage.put_bytes - put0;
+    last_width = Wd;
+  } else if (!(o.graphs && apply_preconditioner_graph(cc, T, w, Wd, stage_bytes))) {
+    apply_preconditioner_dev(cc, T, N, w, N, Wd);
+  }
+  // 3. modified Gram-Schmidt of the running columns against their own bases
+  for (int i = 0; i <= jmax; ++i) {
+    cd* Vi = V + (size_t)i * vstride;
+    check(launch_dots(Vi, N, w, N, N, Wd, cc.g_part.p, nblk, hcol + (size_t)i * slots, false, cc.stream), "dot");
+    check(launch_axpy_cols_masked(hcol + (size_t)i * slots, -1.0, Vi, N, w, N, N, Wd, da.lim, i, cc.stream), "axpy");
+  }
+  check(launch_dots(nullptr, 0, w, N, N, Wd, cc.g_part.p, nblk, da.norm, true, cc.stream), "norm");
+  std::vector<cd> hh((size_t)(jmax + 1) * slots + 1), nrm(Wd), tn(Wd);
+  if (jmax >= 0) HIPCHK(hipMemcpyAsync(hh.data(), hcol, (size_t)(jmax + 1) * slots * elem, hipMemcpyDeviceToHost, cc.stream));
+  HIPCHK(hipMemcpyAsync(nrm.data(), da.norm, Wd * elem, hipMemcpyDeviceToHost, cc.stream));
+  HIPCHK(hipMemcpyAsync(tn.data(), da.tn, Wd * elem, hipMemcpyDeviceToHost, cc.stream));
+  HIPCHK(hipStreamSynchronize(cc.stream));
+  // 4. per column: start a cycle, take a step, or end a cycle
+  std::vector<void*> dst(Wd, nullptr);
+  std::vector<int32_t> mc(Wd, 0);
+  bool upd = false;
+  for (int q = 0; q < Wd; ++q) {
+    if (mode[q] == START) {
+      const double t = tn[q].real();
+      if (bnorm[q] < 0) bnorm[q] = t;  // x = 0 at admission: the first residual is b
+      relres[q] = bnorm[q] > 0 ? t / bnorm[q] : 0.0;
+      bool stop = false, good = false;
+      if (bnorm[q] == 0) {
+        stop = good = true;
+      } else if (o.true_rtol > 0 && relres[q] <= o.true_rtol) {
+        stop = good = true;
+      } else if (!(o.true_rtol > 0) && pc_met[q]) {
+        stop = good = true;
+      } else if (iters[q] >= o.max_iter) {
+        stop = true;
+      }
+      const double beta = nrm[q].real();
+      if (!stop) {
+        if (pc_met[q]) tol_c[q] *= 0.1;  // the preconditioned test was met too early for the true one
+        pc_met[q] = 0;
+        if (u0[q] < 0) u0[q] = beta;
+        if (beta <= o.atol || !(beta > 0)) {
+          stop = true;  // no further progress possible
+          good = !(o.true_rtol > 0);
+        } else {
+          while (beta / u0[q] <= tol_c[q] && tol_c[q] > 1e-300) tol_c[q] *= 0.1;
+        }
+      }
+      if (stop) {
+        mode[q] = IDLE;
+        ok[q] = good;
+        finished.push_back(q);
+        continue;
+      }
+      cd* gq = g.data() + (size_t)q * (m + 1);
+      std::fill(gq, gq + m + 1, cd(0));
+      gq[0] = beta;
+      j[q] = 0;
+      mode[q] = RUN;
+      dst[q] = V + (size_t)q * N;  // V_0 = w / beta
+    } else if (mode[q] == RUN) {
+      const int jj = j[q];
+      cd* Hq = H.data() + (size_t)q * (m + 1) * m;
+      cd* gq = g.data() + (size_t)q * (m + 1);
+      cd* csq = cs.data() + (size_t)q * m;
+      cd* snq = sn.data() + (size_t)q * m;
+      for (int i = 0; i <= jj; ++i) Hq[i + (size_t)jj * (m + 1)] = hh[(size_t)i * slots + q];
+      Hq[jj + 1 + (size_t)jj * (m + 1)] = nrm[q];
+      const double hnext = nrm[q].real();
+      for (int i = 0; i < jj; ++i) {  // previous rotations
+        cd a = Hq[i + (size_t)jj * (m + 1)], b = Hq[i + 1 + (size_t)jj * (m + 1)];
+        Hq[i + (size_t)jj * (m + 1)] = csq[i] * a + snq[i] * b;
+        Hq[i + 1 + (size_t)jj * (m + 1)] = -std::conj(snq[i]) * a + std::conj(csq[i]) * b;
+      }
+      cd a = Hq[jj + (size_t)jj * (m + 1)], b = Hq[jj + 1 + (size_t)jj * (m + 1)];
+      const double den = std::sqrt(std::norm(a) + std::norm(b));
+      if (den == 0) {
+        csq[jj] = 1;
+        snq[jj] = 0;
+      } else if (std::abs(a) == 0) {
+        csq[jj] = 0;
+        snq[jj] = std::conj(b) / den;
+      } else {
+        csq[jj] = std::abs(a) / den;
+        snq[jj] = (a / std::abs(a)) * std::conj(b) / den;
+      }
+      Hq[jj + (size_t)jj * (m + 1)] = csq[jj] * a + snq[jj] * b;
+      Hq[jj + 1 + (size_t)jj * (m + 1)] = 0;
+      gq[jj + 1] = -std::conj(snq[jj]) * gq[jj];
+      gq[jj] = csq[jj] * gq[jj];
+      iters[q]++;
+      const double res = std::abs(gq[jj + 1]);
+      const bool conv = res <= o.atol || res / u0[q] <= tol_c[q] || hnext == 0;
+      if (conv || jj + 1 == m || iters[q] >= o.max_iter) {  // end of the cycle: x += V y
+        const int k = jj + 1;
+        cd* yq = y.data() + (size_t)q * m;
+        std::fill(yq, yq + m, cd(0));
+        for (int i = k - 1; i >= 0; --i) {
+          cd sacc = gq[i];
+          for (int l = i + 1; l < k; ++l) sacc -= Hq[i + (size_t)l * (m + 1)] * yq[l];
+          yq[i] = sacc / Hq[i + (size_t)i * (m + 1)];
+        }
+        mc[q] = k;
+        upd = true;
+        pc_met[q] = conv;
+        mode[q] = START;  // the next iteration computes the true residual
+      } else {
+        dst[q] = V + (size_t)(jj + 1) * vstride + (size_t)q * N;
+        j[q] = jj + 1;
+      }
+    }
+  }
+  // 5. new basis vectors and solution updates
+  bool any_dst = false;
+  for (void* d : dst) any_dst |= d != nullptr;
+  if (any_dst) {
+    cc.stage.put(da.dst, dst.data(), Wd * sizeof(void*), cc.stream);
+    check(launch_scale_cols_to(da.norm, w, N, da.dst, N, Wd, cc.stream), "scale");
+  }
+  if (upd) {
+    cc.stage.put(da.mc, mc.data(), Wd * sizeof(int32_t), cc.stream);
+    cc.stage.put(ydev, y.data(), (size_t)m * Wd * elem, cc.stream);
+    check(launch_basis_update_masked(ydev, m, da.mc, V, vstride, N, X, N, N, Wd, cc.stream), "update");
+  }
 }
 
 }  // namespace bfmf

@@ -1,12 +1,14 @@
 // Serving: several factorizations resident in HBM answer a stream of
-// right-hand-side requests.  Each attached model has a worker thread and its
-// handle's stream; a worker takes every queued request of its model that fits
-// its batch and the result arena, solves them together in one GMRES call, and
-// stores each request's columns in the arena until the caller fetches them.
-// Requests that arrive while a batch is on the device join the next batch of
-// their model; batches of different models run at the same time on their own
-// streams.  All device memory (factors, batch workspaces, result arena) is
-// charged against one HBM budget when models are attached.
+// right-hand-side requests with continuous batching.  Each attached model has
+// a worker thread on its handle's stream and max_batch_rhs column slots; every
+// column of an admitted request takes a slot and runs its own restarted GMRES
+// (SlotGmres): between two iterations the worker retires the columns that
+// finished (their solutions go to the result arena) and admits queued
+// requests into the freed slots, so a request that arrives while others are
+// on the device starts at the next iteration instead of waiting for a batch.
+// Models run at the same time on their own streams.  All device memory
+// (factors, slot workspaces, result arena) is charged against one HBM budget
+// when models are attached.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -84,7 +86,14 @@ struct Request {
   std::vector<double> val;           // interleaved complex
   size_t x_off = 0, x_bytes = 0;     // solution columns in the arena
   bool admitted = false, done = false;
+  int cols_done = 0;                 // columns retired so far
+  bool all_ok = true;                // every retired column met the stopping test
   bfmf_request_info info{};
+};
+
+struct SlotRef {  // the request column a slot holds
+  Request* r = nullptr;
+  int col = 0;
 };
 
 struct Model {
@@ -92,8 +101,10 @@ struct Model {
   int id = 0;
   int64_t n = 0;
   std::deque<Request*> queue;
-  DevBuf B, X;                        // batch right-hand sides and solutions (n x max_batch)
-  DevBuf nz;                          // nonzeros of a batch on the device
+  DevBuf B, X;                        // slot right-hand sides and solutions (n x max_batch)
+  DevBuf nz;                          // nonzeros of the admitted columns on the device
+  SlotGmres sg;                       // the slots' GMRES state
+  std::vector<SlotRef> slot;
   std::thread worker;
   uint64_t charged = 0;               // bytes charged against the budget
 };
@@ -126,103 +137,129 @@ uint64_t batch_bytes(const Context& c, int nrhs, int m) {
   return (uint64_t)nrhs * (col * (2 + (m + 1) + 3 + 2) + 16ull * (uint64_t)c.sum_n) + 64ull * (m + 2) * nrhs;
 }
 
-void run_batch(bfmf_server_s* s, Model& m, std::vector<Request*>& batch) {
+// Loads the columns of newly admitted requests into their slots: B(:, q) = the column, X(:, q) = 0.
+void load_columns(Model& m, const std::vector<int>& slots) {
   Context& c = *m.h;
-  HIPCHK(hipSetDevice(c.device));
   const int64_t n = m.n;
-  int cols = 0;
   std::vector<int32_t> rows, colidx;
   std::vector<double> vals;
-  for (Request* r : batch) {
+  std::vector<AxpbyTask> zero;
+  for (int q : slots) {
+    const SlotRef& ref = m.slot[q];
+    const Request* r = ref.r;
     for (size_t k = 0; k < r->row.size(); ++k) {
+      if (r->col[k] != ref.col) continue;
       rows.push_back(r->row[k]);
-      colidx.push_back(cols + r->col[k]);
+      colidx.push_back(q);
       vals.push_back(r->val[2 * k]);
       vals.push_back(r->val[2 * k + 1]);
     }
-    cols += r->nrhs;
+    zero.push_back(AxpbyTask{m.B.as<char>() + (size_t)q * n * 16, nullptr, n, n, n, 1, 0});
+    zero.push_back(AxpbyTask{m.X.as<char>() + (size_t)q * n * 16, nullptr, n, n, n, 1, 0});
   }
   const size_t nnz = rows.size();
-  const size_t need = std::max<size_t>(nnz, 1) * (2 * sizeof(int32_t) + 2 * sizeof(double));
+  const size_t tasks_bytes = (zero.size() * sizeof(AxpbyTask) + 255) & ~(size_t)255;
+  const size_t need = tasks_bytes + std::max<size_t>(nnz, 1) * (2 * sizeof(int32_t) + 2 * sizeof(double)) + 256;
   if (m.nz.bytes < need) {
     m.nz.release();
     HIPCHK(dev_malloc((void**)&m.nz.p, need * 2));
     m.nz.bytes = need * 2;
   }
-  int32_t* d_rows = m.nz.as<int32_t>();
+  AxpbyTask* d_zero = m.nz.as<AxpbyTask>();
+  int32_t* d_rows = (int32_t*)(m.nz.as<char>() + tasks_bytes);
   int32_t* d_cols = d_rows + std::max<size_t>(nnz, 1);
   double* d_vals = (double*)(d_cols + std::max<size_t>(nnz, 1));  // 2 M int32 before it: 8-byte aligned
-  c.stage.put(d_rows, rows.data(), nnz * sizeof(int32_t), c.stream);
-  c.stage.put(d_cols, colidx.data(), nnz * sizeof(int32_t), c.stream);
-  c.stage.put(d_vals, vals.data(), nnz * 2 * sizeof(double), c.stream);
-  HIPCHK(launch_axpby<double>(m.B.p, n, nullptr, 0, n, cols, 0.0, 0.0, c.stream));  // B = 0
-  HIPCHK(launch_scatter_nz(m.B.p, n, d_rows, d_cols, d_vals, (int64_t)nnz, c.stream));
-  bfmf_solve_opts o = s->opts.solve;
-  if (o.restart <= 0) o.restart = 30;
-  if (o.max_iter <= 0) o.max_iter = 300;
-  const int rc = gmres_dev(c, m.B.p, n, m.X.p, n, cols, o);
-  int c0 = 0;
-  for (Request* r : batch) {
-    HIPCHK(hipMemcpyAsync(s->arena.buf.as<char>() + r->x_off, m.X.as<char>() + (size_t)c0 * n * 16,
-                          (size_t)n * r->nrhs * 16, hipMemcpyDeviceToDevice, c.stream));
-    c0 += r->nrhs;
-  }
-  c.stage.sync(c.stream);
-  for (Request* r : batch) {
-    r->info.iters = o.iters_max;
-    r->info.relres = o.relres_max;
-    r->info.status = rc == 0 ? BFMF_OK : BFMF_E_NOCONV;
+  c.stage.put(d_zero, zero.data(), zero.size() * sizeof(AxpbyTask), c.stream);
+  HIPCHK(launch_axpby_batch<double>(d_zero, (int)zero.size(), n, 0.0, 0.0, c.stream));  // B, X columns = 0
+  if (nnz) {
+    c.stage.put(d_rows, rows.data(), nnz * sizeof(int32_t), c.stream);
+    c.stage.put(d_cols, colidx.data(), nnz * sizeof(int32_t), c.stream);
+    c.stage.put(d_vals, vals.data(), nnz * 2 * sizeof(double), c.stream);
+    HIPCHK(launch_scatter_nz(m.B.p, n, d_rows, d_cols, d_vals, (int64_t)nnz, c.stream));
   }
 }
 
 void worker_main(bfmf_server_s* s, Model* m) {
   (void)hipSetDevice(s->device);
-  const int maxb = s->opts.max_batch_rhs;
+  Context& c = *m->h;
+  const int nslot = s->opts.max_batch_rhs;
+  std::vector<int> fin;
   for (;;) {
-    std::vector<Request*> batch;
+    std::vector<int> fresh;  // slots loaded this round
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      // admit requests of this model in arrival order while they fit the batch and the arena
+      // admit whole requests of this model in arrival order while their columns find free slots and their
+      // solutions fit the arena
       auto admit = [&]() {
-        int cols = 0;
-        for (Request* r : batch) cols += r->nrhs;
-        while (!m->queue.empty()) {
+        int nfree = 0;
+        for (const SlotRef& r : m->slot) nfree += r.r == nullptr;
+        while (!m->queue.empty() && !s->stop) {
           Request* r = m->queue.front();
-          if (cols + r->nrhs > maxb) break;
+          if (r->nrhs > nfree) break;
           size_t off = 0;
           if (!s->arena.alloc(r->x_bytes, off)) break;
           r->x_off = off;
           r->admitted = true;
+          r->info.t_start = s->clock();
           m->queue.pop_front();
-          batch.push_back(r);
-          cols += r->nrhs;
+          int col = 0;
+          for (int q = 0; q < nslot && col < r->nrhs; ++q)
+            if (!m->slot[q].r) {
+              m->slot[q] = SlotRef{r, col++};
+              fresh.push_back(q);
+            }
+          nfree -= r->nrhs;
         }
-        return !batch.empty();
+        return !fresh.empty();
       };
-      s->cv.wait(lk, [&] { return admit() || s->stop; });
-      if (batch.empty()) {  // stopped: requests that can no longer be admitted fail
-        for (Request* r : m->queue) {
-          r->info.status = BFMF_E_STATE;
-          r->done = true;
+      if (m->sg.busy()) {
+        admit();
+      } else {
+        s->cv.wait(lk, [&] { return admit() || s->stop; });
+        if (fresh.empty()) {  // stopped with nothing in flight: requests that can no longer be admitted fail
+          for (Request* r : m->queue) {
+            r->info.status = BFMF_E_STATE;
+            r->done = true;
+          }
+          m->queue.clear();
+          lk.unlock();
+          s->cv.notify_all();
+          return;
         }
-        m->queue.clear();
-        lk.unlock();
-        s->cv.notify_all();
-        return;
       }
-      const double t = s->clock();
-      for (Request* r : batch) {
-        r->info.t_start = t;
-        r->info.batch_requests = (int32_t)batch.size();
+      // occupancy of this round, for the requests' reports
+      int busy_cols = 0;
+      std::vector<Request*> in;
+      for (const SlotRef& r : m->slot)
+        if (r.r) {
+          ++busy_cols;
+          if (std::find(in.begin(), in.end(), r.r) == in.end()) in.push_back(r.r);
+        }
+      for (int q : fresh) {
+        Request* r = m->slot[q].r;
+        r->info.batch_rhs = std::max<int32_t>(r->info.batch_rhs, busy_cols);
+        r->info.batch_requests = std::max<int32_t>(r->info.batch_requests, (int32_t)in.size());
       }
-      int cols = 0;
-      for (Request* r : batch) cols += r->nrhs;
-      for (Request* r : batch) r->info.batch_rhs = cols;
+      for (Request* r : in) {  // requests already in flight see the new neighbours too
+        r->info.batch_rhs = std::max<int32_t>(r->info.batch_rhs, busy_cols);
+        r->info.batch_requests = std::max<int32_t>(r->info.batch_requests, (int32_t)in.size());
+      }
     }
     bfmf_status st = BFMF_OK;
     std::string msg;
     try {
-      run_batch(s, *m, batch);
+      if (!fresh.empty()) {
+        load_columns(*m, fresh);
+        for (int q : fresh) m->sg.admit(q);
+      }
+      m->sg.step(fin);
+      for (int q : fin) {  // the column's solution to its request's place in the arena
+        const SlotRef& ref = m->slot[q];
+        HIPCHK(hipMemcpyAsync(s->arena.buf.as<char>() + ref.r->x_off + (size_t)ref.col * m->n * 16,
+                              m->X.as<char>() + (size_t)q * m->n * 16, (size_t)m->n * 16, hipMemcpyDeviceToDevice,
+                              c.stream));
+      }
+      if (!fin.empty()) HIPCHK(hipStreamSynchronize(c.stream));
     } catch (const Error& e) {
       st = e.status;
       msg = e.msg;
@@ -233,14 +270,34 @@ void worker_main(bfmf_server_s* s, Model* m) {
     {
       std::lock_guard<std::mutex> lk(s->mu);
       const double t = s->clock();
-      for (Request* r : batch) {
-        r->info.t_done = t;
-        if (st != BFMF_OK) r->info.status = st;
-        r->done = true;
+      if (st != BFMF_OK) {  // every request in flight fails
+        s->err = msg;
+        for (int q = 0; q < nslot; ++q) {
+          Request* r = m->slot[q].r;
+          if (r && !r->done) {
+            r->info.status = st;
+            r->info.t_done = t;
+            r->done = true;
+          }
+          m->slot[q] = SlotRef{};
+          m->sg.mode[q] = SlotGmres::IDLE;
+        }
+      } else {
+        for (int q : fin) {
+          Request* r = m->slot[q].r;
+          r->info.iters = std::max<int32_t>(r->info.iters, m->sg.iters[q]);
+          r->info.relres = std::max(r->info.relres, m->sg.relres[q]);
+          r->all_ok = r->all_ok && m->sg.ok[q];
+          m->slot[q] = SlotRef{};
+          if (++r->cols_done == r->nrhs) {
+            r->info.status = r->all_ok ? BFMF_OK : BFMF_E_NOCONV;
+            r->info.t_done = t;
+            r->done = true;
+          }
+        }
       }
-      if (st != BFMF_OK) s->err = msg;
     }
-    s->cv.notify_all();
+    if (st != BFMF_OK || !fin.empty()) s->cv.notify_all();
   }
 }
 
@@ -312,8 +369,8 @@ bfmf_status bfmf_server_attach(bfmf_server s, bfmf_handle h, int32_t* model) {
       m->B.bytes = blk;
       HIPCHK(dev_malloc((void**)&m->X.p, blk));
       m->X.bytes = blk;
-      gmres_workspace(*h, mb, restart);
-      ensure_workspace(*h, mb);
+      m->slot.assign(mb, SlotRef{});
+      m->sg.init(*h, mb, s->opts.solve, m->B.p, m->X.p);
       HIPCHK(hipStreamSynchronize(h->stream));
     } catch (...) {
       std::lock_guard<std::mutex> lk(s->mu);

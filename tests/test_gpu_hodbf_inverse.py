@@ -142,3 +142,34 @@ def test_smw_dense_option_checked(gpu_lib):
         s.front_block(0, 0, np.eye(4))  # a leaf front is never compressed
     assert e.value.status == gpu_lib.BFMF_E_INVAL
     s.close()
+
+
+@pytest.mark.parametrize("tol,cap", [(1e-3, 48), (1e-5, 48)])
+def test_ids_of_sub_ids_24(gpu_lib, c1_oracle, tol, cap):
+    """Interpolative decompositions wider than one kernel takes (forced here at `cap` columns) are
+    done as an ID of the IDs of column chunks (Gram kernel at 1e-3, Householder kernel at 1e-5):
+    blocks were chunked, the compressed blocks stay within a small multiple of those of the
+    unchunked factorization plus the tolerance (two levels of IDs), and the solve stays within
+    10 eps of the oracle."""
+    p, od, fac, x_or = c1_oracle
+    fronts = _compressed_with_dense_children(od, 256)
+    errs = {}
+    for mc in (0, cap):
+        s = gpu_lib.Solver(0).analyze(p.rowptr, p.colind, p.values, dims=p.dims)
+        s.factor(tol=tol, n_min=256, batched=True, id_max_cols=mc)
+        chunked = s.stats()["id_chunked"]
+        print(f"id_max_cols {mc}, tol {tol}: {chunked} blocks chunked", flush=True)
+        assert (chunked > 0) == (mc > 0)
+        errs[mc] = [_check_blocks(s, fac, f, tol, c_block=1e9, c_inv=1e9) for f in fronts]
+        X, info = s.solve(p.rhs, true_rtol=1e-3)
+        err = np.linalg.norm(X - x_or) / np.linalg.norm(x_or)
+        assert info["status"] == 0 and err <= 10 * max(tol, 1e-3) and info["iters"] <= 8, (mc, err, info)
+        s.close()
+    for e0, e1 in zip(errs[0], errs[cap]):
+        for k in ("F11", "F11inv", "F12", "F21", "S"):
+            assert e1[k] <= 3 * e0[k] + 3 * tol * (e0["kappa"] if k in ("F11inv", "S") else 1), (k, e0, e1)
+    s = gpu_lib.Solver(0).analyze(p.rowptr, p.colind, p.values, dims=p.dims)
+    with pytest.raises(gpu_lib.BfmfError) as e:
+        s.factor(tol=tol, n_min=256, id_max_cols=8)
+    assert e.value.status == gpu_lib.BFMF_E_INVAL
+    s.close()

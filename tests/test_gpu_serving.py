@@ -1,8 +1,10 @@
 """Serving: resident factorizations answer a stream of point-source requests.
 
-A request's result must be the same when it is solved alone and when it is
-batched with others (GMRES keeps every column's Krylov data apart), and must
-match the FP64 oracle to 10 tol with a true residual at most 1e-3.
+A request's result must be the same, bit for bit, when it is solved alone and
+when it is batched with others (GMRES keeps every column's Krylov data apart
+and every kernel's arithmetic on a column is independent of the other
+columns), with the request's own iteration count and residual reported, and
+must match the FP64 oracle to 10 tol with a true residual at most 1e-3.
 """
 import numpy as np
 import pytest
@@ -40,13 +42,14 @@ def test_alone_equals_mix_and_oracle(gpu_lib, precision):
     ids = [srv.attach(m[0]) for m in models]
     reqs = _requests(14, sizes)
 
-    alone = []
+    alone, alone_info = [], []
     for m, rows in reqs:
         t = srv.submit_points(ids[m], rows)
         X = np.zeros((sizes[m], len(rows)), dtype=np.complex128, order="F")
         info = srv.wait(t, out=X)
         assert info["status"] == 0 and info["batch_requests"] == 1, info
         alone.append(X)
+        alone_info.append(info)
 
     tickets = [srv.submit_points(ids[m], rows) for m, rows in reqs]
     mixed, infos = [], []
@@ -64,9 +67,10 @@ def test_alone_equals_mix_and_oracle(gpu_lib, precision):
     for s, rp, ci, v, dims in models:
         od = nd.nd_grid(dims, leaf_max=512, sep_leaf=64)
         facs.append((mf.factor(rp, ci, v, od), rp, ci, v))
-    for (m, rows), Xa, Xm in zip(reqs, alone, mixed):
-        # alone and in the mix: the same columns up to rounding
-        assert np.linalg.norm(Xm - Xa) <= 1e-10 * np.linalg.norm(Xa)
+    for (m, rows), Xa, Xm, ia, im in zip(reqs, alone, mixed, alone_info, infos):
+        # alone and in the mix: the same columns bit for bit, the request's own iterations and residual
+        assert np.array_equal(Xm, Xa), np.abs(Xm - Xa).max()
+        assert im["iters"] == ia["iters"] and im["relres"] == ia["relres"], (ia, im)
         fac, rp, ci, v = facs[m]
         B = np.zeros((sizes[m], len(rows)), dtype=np.complex128)
         B[rows, np.arange(len(rows))] = 1.0

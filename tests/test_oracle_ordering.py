@@ -203,3 +203,32 @@ def test_box_of_exactly_leaf_max_nodes_is_a_leaf(dims, leaf_max):
     a = int(np.argmax(dims))
     root = od2.nfronts - 1
     assert od2.send[root] - od2.sbeg[root] == n // dims[a]
+
+
+def test_yee_separator_bisection_order_by_hand():
+    """The P-hat bisection of a Yee separator, derived by hand from the reading of the separator
+    bisection (longest in-plane extent of the region in doubled coordinates, ties to the lower axis,
+    ceil(count / 2) coordinate positions first, natural order z, y, x inside a leaf) for 4^3 cells,
+    separator leaves of at most 8 edges.  The root separator is the node plane x = 2 (doubled 4): its
+    y-edges (y odd, z even) and z-edges (y even, z odd) with doubled y, z in [1, 7], 24 edges.
+      split y at [1, 4] | [5, 7]: 14 | 10 edges
+        [1, 4]: split z at [1, 4] | [5, 7]: 8 | 6
+        [5, 7]: split z at [1, 4] | [5, 7]: 6 | 4"""
+    from workloads.maxwell import yee_curlcurl
+    _, _, _, meta = yee_curlcurl(4, 0.03)
+    coords = np.asarray(meta["coords"])
+    od = nd.nd_yee(4, coords, leaf_max=40, sep_leaf=8)
+    root = od.nfronts - 1
+    assert od.septree[root] == [[0, 24, 1, 4], [0, 14, 2, 3], [0, 8, -1, -1], [8, 14, -1, -1],
+                                [14, 24, 5, 6], [14, 20, -1, -1], [20, 24, -1, -1]]
+    sep = [tuple(int(v) for v in coords[e]) for e in od.perm[od.sbeg[root]:od.send[root]]]
+
+    def leaf(ys_yedge, zs_yedge, ys_zedge, zs_zedge):
+        """natural order (z outer, then y, then x) of the leaf's y-edges and z-edges"""
+        pts = [(4, y, z) for y in ys_yedge for z in zs_yedge] + [(4, y, z) for y in ys_zedge for z in zs_zedge]
+        return sorted(pts, key=lambda c: (c[2], c[1], c[0]))
+
+    assert sep[0:8] == leaf([1, 3], [2, 4], [2, 4], [1, 3])
+    assert sep[8:14] == leaf([1, 3], [6], [2, 4], [5, 7])
+    assert sep[14:20] == leaf([5, 7], [2, 4], [6], [1, 3])
+    assert sep[20:24] == leaf([5, 7], [6], [6], [5, 7])
