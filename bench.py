@@ -333,11 +333,28 @@ def run_serving(bfmf, seconds, rate, max_rhs, precision):
 
     th = threading.Thread(target=producer)
     th.start()
-    infos = []
-    for k in range(len(stream)):
-        while tickets[k] is None:
-            time.sleep(0.0005)
-        infos.append(srv.wait(tickets[k]))
+    # one waiter per model (its requests complete in arrival order, the models' do not)
+    infos = [None] * len(stream)
+    done = [0]
+    lock = threading.Lock()
+
+    def waiter(model):
+        for k, (_, m, _) in enumerate(stream):
+            if m != model:
+                continue
+            while tickets[k] is None:
+                time.sleep(0.0005)
+            infos[k] = srv.wait(tickets[k])
+            with lock:
+                done[0] += 1
+                if done[0] % 20 == 0:
+                    print(f"[bench] serving: {done[0]} of {len(stream)} requests done", file=sys.stderr, flush=True)
+
+    ws = [threading.Thread(target=waiter, args=(m,)) for m in range(len(ids))]
+    for w in ws:
+        w.start()
+    for w in ws:
+        w.join()
     th.join()
     srv.close()
     for sv in solvers:

@@ -273,6 +273,18 @@ bfmf_status bfmf_get_front(bfmf_handle h, int32_t front, int32_t what, void* out
 bfmf_status bfmf_apply_front_block(bfmf_handle h, int32_t front, int32_t what, int32_t nrhs, const double* X,
                                    int64_t ldx, double* Y, int64_t ldy);
 
+/* Debug access to the list routing of entry evaluation (Sec. 5): out(i, j)
+ * = F(rows[i], cols[j]) of a front that is never formed, F = [A(Is,Is)
+ * A(Is,Iu); A(Iu,Is) 0] (+) C_nu1 (+) C_nu2, each request split into its
+ * A part and its child parts through the inverse extend-add maps and served
+ * by the extraction kernel the compressed fronts use.  Indices are
+ * front-local (0 .. n-1: I^s, then I^u); out is a host array of interleaved
+ * complex128, column-major, ld ldo >= nrows.  Needs a factorization with
+ * keep_fronts (the children's contribution blocks are kept); E_INVAL
+ * otherwise or for indices outside the front, E_STATE before bfmf_factor. */
+bfmf_status bfmf_extract_front(bfmf_handle h, int32_t front, int32_t nrows, const int32_t* rows, int32_t ncols,
+                               const int32_t* cols, double* out, int64_t ldo);
+
 /* Per kernel-class timing, collected with HIP events on the handle's stream
  * while bfmf_factor_opts.timing is set (factor and solve calls accumulate).
  * Classes: 0 assemble (extend-add), 1 panel LU loop (panel, interchanges,

@@ -108,6 +108,7 @@ _SIGS = {
     "bfmf_get_symbolic": (C.c_int, [_h, C.POINTER(bfmf_symbolic_view)]),
     "bfmf_get_stats": (C.c_int, [_h, C.POINTER(bfmf_stats)]),
     "bfmf_get_front": (C.c_int, [_h, C.c_int32, C.c_int32, _P, C.c_int64]),
+    "bfmf_extract_front": (C.c_int, [_h, C.c_int32, C.c_int32, _P, C.c_int32, _P, _P, C.c_int64]),
     "bfmf_apply_front_block": (C.c_int, [_h, C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64]),
     "bfmf_get_kernel_stats": (C.c_int, [_h, C.c_int32, C.POINTER(bfmf_kernel_stat)]),
     "bfmf_reset_kernel_stats": (C.c_int, [_h]),
@@ -299,6 +300,16 @@ def bfmf_apply_front_block(h, front, what, X, rows):
     _check(h, _lib.bfmf_apply_front_block(h, front, what, X.shape[1], _ptr(X), max(X.shape[0], 1), _ptr(Y),
                                           max(rows, 1)))
     return Y
+
+
+def bfmf_extract_front(h, front, rows, cols):
+    """F(rows, cols) of a front (front-local indices) through the GPU's list routing."""
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    out = np.zeros((rows.shape[0], cols.shape[0]), dtype=np.complex128, order="F")
+    _check(h, _lib.bfmf_extract_front(h, front, rows.shape[0], _ptr(rows), cols.shape[0], _ptr(cols), _ptr(out),
+                                      max(rows.shape[0], 1)))
+    return out
 
 
 def bfmf_get_kernel_stats(h):

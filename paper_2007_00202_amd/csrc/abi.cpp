@@ -381,6 +381,25 @@ bfmf_status bfmf_apply_front_block(bfmf_handle h, int32_t front, int32_t what, i
   });
 }
 
+bfmf_status bfmf_extract_front(bfmf_handle h, int32_t front, int32_t nrows, const int32_t* rows, int32_t ncols,
+                               const int32_t* cols, double* out, int64_t ldo) {
+  return guarded(h, [&] {
+    if (h->state != State::Factored) throw Error(BFMF_E_STATE, "extract_front before factor");
+    if (front < 0 || front >= h->sym.nfronts()) throw Error(BFMF_E_INVAL, "extract_front: bad front");
+    if (!h->fopts.keep_fronts)
+      throw Error(BFMF_E_INVAL, "extract_front: the children's contribution blocks are kept only with keep_fronts");
+    if (nrows <= 0 || ncols <= 0 || !rows || !cols || !out || ldo < nrows)
+      throw Error(BFMF_E_INVAL, "extract_front: bad arguments");
+    const int64_t n = h->fp[front].n;
+    for (int32_t i = 0; i < nrows; ++i)
+      if (rows[i] < 0 || rows[i] >= n) throw Error(BFMF_E_INVAL, "extract_front: row index out of the front");
+    for (int32_t j = 0; j < ncols; ++j)
+      if (cols[j] < 0 || cols[j] >= n) throw Error(BFMF_E_INVAL, "extract_front: column index out of the front");
+    extract_front_entries(*h, front, std::vector<int32_t>(rows, rows + nrows), std::vector<int32_t>(cols, cols + ncols),
+                          out, ldo);
+  });
+}
+
 bfmf_status bfmf_get_kernel_stats(bfmf_handle h, int32_t kind, bfmf_kernel_stat* out) {
   static const char* names[K_COUNT] = {"assemble",      "panel_lu",       "schur_gemm",     "forward_sweep",
                                        "backward_sweep", "spmv",           "gmres_vector",   "butterfly_gemm",

@@ -1579,6 +1579,28 @@ static void apply_block(CompState<T>& st, int f, int what, int nrhs, const doubl
     }
 }
 
+// Entries of the never-formed front f (A entries (+) the children's contribution blocks, the list
+// routing of the compressed fronts' entry evaluation): out(i, j) = F(rows[i], cols[j]), host arrays.
+void extract_front_entries(Context& c, int f, const std::vector<int32_t>& rows, const std::vector<int32_t>& cols,
+                           double* out, int64_t ldo) {
+  BfRuntime<double> rt;
+  rt.c = &c;
+  const size_t nr = rows.size(), nc = cols.size();
+  void* d_out = rt.scratch.take(std::max<size_t>(nr * nc, 1) * sizeof(cplx<double>));
+  const FrontDesc* dfd = c.d_fds.as<FrontDesc>() + c.desc_index[f];
+  ExtractBatch eb;
+  eb.add(dfd, nullptr, 0, rows, 0, cols, 0, d_out, (int64_t)std::max<size_t>(nr, 1), false);
+  run_extract_to<double, double>(rt, eb, false);
+  std::vector<cplx<double>> h(nr * nc);
+  ochk(hipMemcpyAsync(h.data(), d_out, nr * nc * sizeof(cplx<double>), hipMemcpyDeviceToHost, c.stream), "download");
+  ochk(hipStreamSynchronize(c.stream), "sync");
+  for (size_t j = 0; j < nc; ++j)
+    for (size_t i = 0; i < nr; ++i) {
+      out[2 * (i + j * ldo)] = h[i + j * nr].re;
+      out[2 * (i + j * ldo) + 1] = h[i + j * nr].im;
+    }
+}
+
 void comp_apply_block(void* state, int f, int what, int nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy) {
   auto* h = (CompHolder*)state;
   if (!h) throw Error(BFMF_E_INVAL, "no compressed fronts");

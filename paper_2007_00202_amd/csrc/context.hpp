@@ -314,6 +314,9 @@ void backward_compressed_level(void* state, Context& c, const std::vector<int>& 
                                const std::vector<void*>& Ws, const std::vector<int>& ns, int nrhs);
 void compressed_stats(void* state, double& bytes, int& maxrank, int& chunked);
 uint64_t comp_state_bytes(void* state);  // device bytes held by the compressed fronts' pools
+// out(i, j) = F(rows[i], cols[j]) of front f from A and the children's contribution blocks (host, ld ldo)
+void extract_front_entries(Context& c, int f, const std::vector<int32_t>& rows, const std::vector<int32_t>& cols,
+                           double* out, int64_t ldo);
 // Y = B X for a block of compressed front f (0 F11, 1 F11^-1, 2 F12, 3 F21, 4 S); host complex128 arrays
 void comp_apply_block(void* state, int f, int what, int nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy);
 

@@ -1099,7 +1099,7 @@ void SlotGmres::step(std::vector<int>& finished) {
         mc[q] = k;
         upd = true;
         pc_met[q] = conv;
-        mode[q] = START;  // the next iteration computes the true residual
+        mode[q] = START;  // unless the check below finds it done, the next iteration restarts it
       } else {
         dst[q] = V + (size_t)(jj + 1) * vstride + (size_t)q * N;
         j[q] = jj + 1;
@@ -1117,6 +1117,24 @@ void SlotGmres::step(std::vector<int>& finished) {
     cc.stage.put(da.mc, mc.data(), Wd * sizeof(int32_t), cc.stream);
     cc.stage.put(ydev, y.data(), (size_t)m * Wd * elem, cc.stream);
     check(launch_basis_update_masked(ydev, m, da.mc, V, vstride, N, X, N, N, Wd, cc.stream), "update");
+    // the columns whose cycle ended: their true residual and the stopping test now (a residual, no
+    // preconditioner application), so that a finished column leaves its slot at once
+    check(launch_spmv(cc.d_rowptr.as<int64_t>(), cc.d_colind.as<int32_t>(), cc.d_values.p, X, N, T, N, B, N, N, Wd,
+                      cc.stream),
+          "spmv");
+    check(launch_dots(nullptr, 0, T, N, N, Wd, cc.g_part.p, nblk, da.tn, true, cc.stream), "norm");
+    HIPCHK(hipMemcpyAsync(tn.data(), da.tn, Wd * elem, hipMemcpyDeviceToHost, cc.stream));
+    HIPCHK(hipStreamSynchronize(cc.stream));
+    for (int q = 0; q < Wd; ++q) {
+      if (mc[q] == 0) continue;
+      relres[q] = bnorm[q] > 0 ? tn[q].real() / bnorm[q] : 0.0;
+      const bool done = o.true_rtol > 0 ? relres[q] <= o.true_rtol : pc_met[q] != 0;
+      if (done) {
+        mode[q] = IDLE;
+        ok[q] = 1;
+        finished.push_back(q);
+      }
+    }
   }
 }
 
