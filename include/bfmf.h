@@ -363,6 +363,39 @@ bfmf_status bfmf_bf_apply(bfmf_bf* b, int32_t adjoint, int32_t nrhs, const doubl
  * product that needs more than the fixed array. */
 bfmf_status bfmf_bf_apply_noalloc(bfmf_bf* b, int32_t adjoint, int32_t nrhs, const double* dX, int64_t ldx,
                                   double* dY, int64_t ldy, void* hip_stream);
+/* A butterfly from caller-given factors (Sec. 3, the factored form
+ * K = U^L R^{L-1} .. R^{lc} B^{lc} W^{lc} .. W^1 V^0 with lc = floor(L/2)),
+ * over the halving trees of [0, m) and [0, n) (first half ceil) of L levels,
+ * 0 <= L <= 12.  Block (l, t, v) pairs node t at level l of the row tree with
+ * node v at level L - l of the column tree; blk = t * 2^(L-l) + v.
+ *   ranks_left:  (L - lc + 1) x 2^L, row l - lc holds the rank of the left
+ *                factor of block (l, t, v) for l = lc..L (at l = L, v = 0 and
+ *                blk = t: the columns of U_t);
+ *   ranks_right: (lc + 1) x 2^L, row l holds the rank of the right factor of
+ *                block (l, t, v) for l = 0..lc (at l = 0, t = 0 and blk = v:
+ *                the rows of V_v).
+ * Ranks are in 0..4096.  factors (nfactor complex128 entries, interleaved,
+ * host memory, copied) holds, each column-major and in this order:
+ *   U_t, t ascending:                       |O_t| x rl(L, t)
+ *   R of block (l, t, v), l = L-1 .. lc, blk ascending:
+ *                (rl(l+1, 2t, v/2) + rl(l+1, 2t+1, v/2)) x rl(l, t, v)
+ *   B of block (lc, t, v), blk ascending:  rl(lc, t, v) x rr(lc, t, v)
+ *   W of block (l, t, v), l = lc .. 1, blk ascending:
+ *                rr(l, t, v) x (rr(l-1, t/2, 2v) + rr(l-1, t/2, 2v+1))
+ *   V_v, v ascending:                       rr(0, v) x |S_v|
+ * E_INVAL when nfactor differs from the count the ranks imply. */
+bfmf_status bfmf_bf_import(int32_t device, int32_t m, int32_t n, int32_t L, const int32_t* ranks_left,
+                           const int32_t* ranks_right, const double* factors, int64_t nfactor, bfmf_bf** out);
+/* Entries of submatrices K(X_k, Y_k) (extract_BF, Alg. 3) for requests
+ * k = 0..nreq-1 with X_k = rows[row_ptr[k] .. row_ptr[k+1]) and Y_k =
+ * cols[col_ptr[k] .. col_ptr[k+1]) (host arrays, any order, repeats allowed).
+ * out (host, interleaved complex128) receives the blocks one after another,
+ * each |X_k| x |Y_k| column-major.  On first use the butterfly is expanded
+ * to its centre level (every factor block multiplied once, held by the
+ * handle until bfmf_bf_destroy); an entry is then one dot product of its
+ * centre block's rank.  E_INVAL for an index outside the matrix. */
+bfmf_status bfmf_bf_extract(bfmf_bf* b, int32_t nreq, const int64_t* row_ptr, const int32_t* rows,
+                            const int64_t* col_ptr, const int32_t* cols, double* out);
 /* levels, largest rank, number of stored complex entries */
 bfmf_status bfmf_bf_info(bfmf_bf* b, int32_t* L, int32_t* max_rank, int64_t* entries);
 void bfmf_bf_destroy(bfmf_bf* b);

@@ -119,6 +119,9 @@ _SIGS = {
                                          C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_P)]),
     "bfmf_bf_apply": (C.c_int, [_P, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64]),
     "bfmf_bf_apply_noalloc": (C.c_int, [_P, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P]),
+    "bfmf_bf_import": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, C.c_int64,
+                                 C.POINTER(_P)]),
+    "bfmf_bf_extract": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P]),
     "bfmf_bf_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     "bfmf_bf_destroy": (None, [_P]),
     "bfmf_default_server_opts": (None, [C.POINTER(bfmf_server_opts)]),
@@ -384,6 +387,45 @@ def bfmf_bf_apply_noalloc(b, adjoint, nrhs, dX, ldx, dY, ldy, stream=None):
     """Device pointers (e.g. torch tensors' data_ptr()); returns the status (0 on success)."""
     return _lib.bfmf_bf_apply_noalloc(b, int(adjoint), nrhs, C.c_void_p(dX), ldx, C.c_void_p(dY), ldy,
                                       C.c_void_p(stream) if stream else None)
+
+
+def bfmf_bf_import(m, n, L, ranks_left, ranks_right, factors, device=0):
+    """ranks_left: (L - L//2 + 1, 2^L) int, ranks_right: (L//2 + 1, 2^L) int, factors: complex128
+    entries in the order bfmf_bf_import documents."""
+    rl = np.ascontiguousarray(ranks_left, dtype=np.int32)
+    rr = np.ascontiguousarray(ranks_right, dtype=np.int32)
+    f = np.ascontiguousarray(factors, dtype=np.complex128)
+    if rl.shape != (L - L // 2 + 1, 1 << L) or rr.shape != (L // 2 + 1, 1 << L):
+        raise BfmfError(BFMF_E_INVAL, "bf_import: rank arrays of the wrong shape")
+    out = _P()
+    st = _lib.bfmf_bf_import(device, m, n, L, _ptr(rl), _ptr(rr), _ptr(f) if f.size else None, f.size,
+                             C.byref(out))
+    if st != BFMF_OK:
+        raise BfmfError(st, "bf_import: " + _lib.bfmf_last_error(None).decode())
+    return out, (m, n)
+
+
+def bfmf_bf_extract(b, requests):
+    """requests: list of (rows, cols); returns the list of submatrices K(rows, cols)."""
+    rows = [np.asarray(r, dtype=np.int32).ravel() for r, _ in requests]
+    cols = [np.asarray(c, dtype=np.int32).ravel() for _, c in requests]
+    rp = np.zeros(len(requests) + 1, dtype=np.int64)
+    cp = np.zeros(len(requests) + 1, dtype=np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    cp[1:] = np.cumsum([len(c) for c in cols])
+    R = np.concatenate(rows) if rows else np.zeros(0, np.int32)
+    Cc = np.concatenate(cols) if cols else np.zeros(0, np.int32)
+    sizes = [len(r) * len(c) for r, c in zip(rows, cols)]
+    out = np.zeros(max(sum(sizes), 1), dtype=np.complex128)
+    st = _lib.bfmf_bf_extract(b, len(requests), _ptr(rp), _ptr(R) if R.size else None, _ptr(cp),
+                              _ptr(Cc) if Cc.size else None, _ptr(out))
+    if st != BFMF_OK:
+        raise BfmfError(st, "bf_extract")
+    res, pos = [], 0
+    for r, c, sz in zip(rows, cols, sizes):
+        res.append(out[pos:pos + sz].reshape((len(c), len(r))).T.copy())
+        pos += sz
+    return res
 
 
 def bfmf_bf_info(b):

@@ -651,35 +651,71 @@ void ExtractBatch::add(const FrontDesc* fd, const void* dense, int64_t ldd, cons
   tasks.push_back(e);
 }
 
+void ExtractBatch::add_bf(const BfCentreDev* bf, const std::vector<int32_t>& rows, int r0,
+                          const std::vector<int32_t>& cols, int c0, void* out, int64_t ldo, bool trans, double alpha,
+                          bool accumulate) {
+  if (rows.empty() || cols.empty()) return;
+  BfExtractTask e;
+  std::memset(&e, 0, sizeof(e));
+  e.bf = bf;
+  e.rows = (const int32_t*)(intptr_t)idx.size();
+  for (int32_t r : rows) idx.push_back(r0 + r);
+  e.cols = (const int32_t*)(intptr_t)idx.size();
+  for (int32_t c : cols) idx.push_back(c0 + c);
+  e.nr = (int32_t)rows.size();
+  e.nc = (int32_t)cols.size();
+  e.out = out;
+  e.ldo = std::max<int64_t>(ldo, 1);
+  e.trans = trans ? 1 : 0;
+  e.accumulate = accumulate ? 1 : 0;
+  e.alpha = alpha;
+  bf_tasks.push_back(e);
+}
+
 template <class TO, class T>
 void run_extract_to(BfRuntime<T>& rt, ExtractBatch& b, bool src_single) {
   HostTimer ht(HP_EXTRACT);
-  if (b.tasks.empty()) {
+  if (b.tasks.empty() && b.bf_tasks.empty()) {
     b.idx.clear();
     return;
   }
   PackedUpload<BfRuntime<T>> pk(rt);  // index lists and tasks in one copy
   const int pi = pk.add(b.idx.data(), b.idx.size() * sizeof(int32_t));
   const int pt = pk.add(b.tasks.data(), b.tasks.size() * sizeof(ExtractTask));
+  const int pb = pk.add(b.bf_tasks.data(), b.bf_tasks.size() * sizeof(BfExtractTask));
   int32_t* d_idx = (int32_t*)pk.part(pi);
-  int64_t maxe = 0;
+  int64_t maxe = 0, maxb = 0;
   for (auto& e : b.tasks) {
     e.rows = d_idx + (intptr_t)e.rows;
     e.cols = d_idx + (intptr_t)e.cols;
     maxe = std::max<int64_t>(maxe, (int64_t)e.nr * e.nc);
   }
+  for (auto& e : b.bf_tasks) {
+    e.rows = d_idx + (intptr_t)e.rows;
+    e.cols = d_idx + (intptr_t)e.cols;
+    maxb = std::max<int64_t>(maxb, (int64_t)e.nr * e.nc);
+  }
   ExtractTask* d_t = (ExtractTask*)pk.part(pt);
+  void* d_b = pk.part(pb);
   pk.commit();
-  const int yb = (int)std::min<int64_t>(32, std::max<int64_t>(1, (maxe + 2047) / 2048));
   KernelTimer& tm = rt.c->timer;
   const int tk = tm.want(K_EXTRACT) ? tm.begin(rt.s()) : -1;
-  chk(launch_front_extract<TO>(d_t, (int)b.tasks.size(), yb, rt.c->d_values.p, src_single, rt.s()), "extract");
+  if (!b.tasks.empty()) {
+    const int yb = (int)std::min<int64_t>(32, std::max<int64_t>(1, (maxe + 2047) / 2048));
+    chk(launch_front_extract<TO>(d_t, (int)b.tasks.size(), yb, rt.c->d_values.p, src_single, rt.s()), "extract");
+  }
+  if (!b.bf_tasks.empty()) {  // after the front tasks: they may add to the same outputs
+    const int yb = (int)std::min<int64_t>(32, std::max<int64_t>(1, (maxb + 2047) / 2048));
+    chk(launch_bf_extract<TO>(d_b, (int)b.bf_tasks.size(), yb, rt.s()), "butterfly extract");
+  }
   if (tk >= 0) {
     double by = 0;  // every output entry written once, plus its row and column index
     for (auto& e : b.tasks) by += (double)e.nr * e.nc * sizeof(cplx<TO>) + 4.0 * (e.nr + e.nc);
+    for (auto& e : b.bf_tasks) by += (double)e.nr * e.nc * sizeof(cplx<TO>) + 4.0 * (e.nr + e.nc);
     tm.end(tk, rt.s(), K_EXTRACT, 0, by);
   }
   b.tasks.clear();
+  b.bf_tasks.clear();
   b.idx.clear();
 }
 
@@ -693,6 +729,236 @@ template void run_extract<float>(BfRuntime<float>&, ExtractBatch&);
 template void run_extract_to<double, double>(BfRuntime<double>&, ExtractBatch&, bool);
 template void run_extract_to<double, float>(BfRuntime<float>&, ExtractBatch&, bool);
 template void run_extract_to<float, float>(BfRuntime<float>&, ExtractBatch&, bool);
+
+// ------------------------------------------------------------ centre forms
+namespace {
+
+// Placement of the centre forms of a set in one device buffer: per butterfly
+// E and G of every centre block, then the copied dense blocks, then the
+// descriptor arrays and the descriptors.
+struct CentreLayout {
+  std::vector<std::vector<size_t>> e, g;  // byte offsets per butterfly and centre block
+  std::vector<size_t> dense;
+  std::vector<size_t> tb, vb, rk, ep, gp;  // descriptor arrays per butterfly
+  size_t descs = 0, total = 0;
+};
+
+template <class T>
+CentreLayout centre_layout(const CentreSpec& spec) {
+  const size_t esz = sizeof(cplx<T>);
+  CentreLayout lay;
+  size_t off = 0;
+  auto take = [&](size_t bytes, size_t align) {
+    off = (off + align - 1) / align * align;
+    const size_t o = off;
+    off += bytes;
+    return o;
+  };
+  for (const Butterfly* bf : spec.bfs) {
+    const int L = bf->L, lc = bf->lc, nt = 1 << lc, nv = 1 << (L - lc);
+    std::vector<size_t> eo(nt * nv), go(nt * nv);
+    for (int t = 0; t < nt; ++t)
+      for (int v = 0; v < nv; ++v) {
+        const int blk = t * nv + v, r = bf->rl[lc][blk];
+        eo[blk] = take((size_t)bf->to.size(lc, t) * r * esz, 64);
+        go[blk] = take((size_t)r * bf->ts.size(L - lc, v) * esz, 64);
+      }
+    lay.e.push_back(std::move(eo));
+    lay.g.push_back(std::move(go));
+  }
+  for (auto& d : spec.dense) lay.dense.push_back(take((size_t)d.second * d.second * esz, 64));
+  for (const Butterfly* bf : spec.bfs) {
+    const int L = bf->L, lc = bf->lc, nt = 1 << lc, nv = 1 << (L - lc);
+    lay.tb.push_back(take((size_t)(nt + 1) * 4, 8));
+    lay.vb.push_back(take((size_t)(nv + 1) * 4, 8));
+    lay.rk.push_back(take((size_t)nt * nv * 4, 8));
+    lay.ep.push_back(take((size_t)nt * nv * sizeof(void*), 8));
+    lay.gp.push_back(take((size_t)nt * nv * sizeof(void*), 8));
+  }
+  lay.descs = take(spec.bfs.size() * sizeof(BfCentreDev), 64);
+  lay.total = std::max<size_t>(off, 64);
+  return lay;
+}
+
+}  // namespace
+
+template <class T>
+size_t centre_bytes(const CentreSpec& spec) {
+  return centre_layout<T>(spec).total;
+}
+
+// E of level l from E of level l + 1 (left factors, leaves to centre):
+//   E_l(t, v) = [E_{l+1}(2t, v/2) R_top ; E_{l+1}(2t+1, v/2) R_bottom]
+// with R the block's columns of its nu-pair matrix, split after the first
+// child's rank; G = B F_lc with F of level l from level l - 1 (right factors):
+//   F_l(t, v) = [W_1 F_{l-1}(t/2, 2v), W_2 F_{l-1}(t/2, 2v+1)]
+// with W the block's rows of its tau-pair matrix, split after the first
+// child's rank.  One grouped launch per level step for every butterfly.
+template <class T>
+CentreOut build_centres(BfRuntime<T>& rt, const CentreSpec& spec, char* mem) {
+  const size_t esz = sizeof(cplx<T>);
+  const CentreLayout lay = centre_layout<T>(spec);
+  CentreOut out;
+  hipStream_t s = rt.s();
+  char* pool = rt.pool_base();
+  auto mk = rt.scratch.mark();
+  auto abs_off = [&](const void* p) { return (int64_t)((uintptr_t)p / esz); };
+  BfPlan plan;
+  std::vector<AxpbyTask> copies;  // U of a butterfly with lc == L, and the dense blocks
+  int64_t maxcopy = 0;
+  auto phase = [&](int k) -> std::vector<GTask>& {
+    if ((int)plan.phase.size() <= k) plan.phase.resize(k + 1);
+    return plan.phase[k];
+  };
+  auto gt = [](int64_t a_off, int64_t lda, int abase, int64_t b_off, int64_t ldb, int bbase, int64_t c_off,
+               int64_t ldc, int M, int N, int K) {
+    GTask t;
+    std::memset(&t, 0, sizeof(t));
+    t.a_off = a_off;
+    t.lda = std::max<int64_t>(lda, 1);
+    t.opA = OP_N;
+    t.opB = OP_N;
+    t.abase = (int8_t)abase;
+    t.b_off = b_off;
+    t.ldb = std::max<int64_t>(ldb, 1);
+    t.bbase = (int8_t)bbase;
+    t.c_off = c_off;
+    t.ldc = std::max<int64_t>(ldc, 1);
+    t.cbase = 4;
+    t.M = M;
+    t.N = N;
+    t.K = K;
+    t.alpha_re = 1.0;
+    return t;
+  };
+  for (size_t b = 0; b < spec.bfs.size(); ++b) {
+    const Butterfly& bf = *spec.bfs[b];
+    const int L = bf.L, lc = bf.lc;
+    // left side: E(l) per block as (address, is-pool-offset); level L is U in the pool
+    std::vector<int64_t> eaddr(1 << L);  // element offset (pool) or absolute element address
+    std::vector<int> ebase(1 << L, 0);
+    for (int t = 0; t < (1 << L); ++t) eaddr[t] = bf.offL[L][t];
+    if (lc == L) {
+      for (int t = 0; t < (1 << L); ++t) {
+        const int rows = bf.to.size(L, t), r = bf.rl[L][t];
+        if (rows == 0 || r == 0) continue;
+        copies.push_back(AxpbyTask{mem + lay.e[b][t], pool + bf.offL[L][t] * esz, rows, rows, rows, r, 0});
+        maxcopy = std::max<int64_t>(maxcopy, (int64_t)rows * r);
+      }
+    }
+    for (int l = L - 1; l >= lc; --l) {
+      const int vs = 1 << (L - l), vs1 = vs / 2, step = L - 1 - l;
+      std::vector<int64_t> naddr(1 << L, 0);
+      for (int t = 0; t < (1 << l); ++t)
+        for (int v = 0; v < vs; ++v) {
+          const int blk = t * vs + v, r = bf.rl[l][blk];
+          const int mt = bf.to.size(l, t), m1 = bf.to.size(l + 1, 2 * t), m2 = bf.to.size(l + 1, 2 * t + 1);
+          char* dst = l == lc ? mem + lay.e[b][blk] : (char*)rt.scratch.take((size_t)mt * r * esz);
+          naddr[blk] = abs_off(dst);
+          if (r == 0 || mt == 0) continue;
+          const int pair = blk / 2, col_off = (blk & 1) ? bf.rl[l][blk - 1] : 0;
+          const int a1 = (2 * t) * vs1 + v / 2, b1 = (2 * t + 1) * vs1 + v / 2;
+          const int top = bf.rl[l + 1][a1], rrows = top + bf.rl[l + 1][b1];
+          const int64_t roff = bf.offL[l][pair] + (int64_t)col_off * rrows;
+          const int ab = l + 1 == L ? 0 : 4;
+          if (m1 > 0)
+            phase(step).push_back(gt(eaddr[a1], m1, ab, roff, rrows, 0, naddr[blk], mt, m1, r, top));
+          if (m2 > 0)
+            phase(step).push_back(
+                gt(eaddr[b1], m2, ab, roff + top, rrows, 0, naddr[blk] + m1, mt, m2, r, rrows - top));
+        }
+      eaddr.swap(naddr);
+    }
+    // right side: F(0) = Vt in the pool, then F(1..lc), then G = B F(lc)
+    std::vector<int64_t> faddr(1 << L);
+    for (int v = 0; v < (1 << L); ++v) faddr[v] = bf.offR[0][v];
+    for (int l = 1; l <= lc; ++l) {
+      const int vs = 1 << (L - l), step = l - 1;
+      std::vector<int64_t> naddr(1 << L, 0);
+      for (int t = 0; t < (1 << l); ++t)
+        for (int v = 0; v < vs; ++v) {
+          const int blk = t * vs + v, M = bf.rr[l][blk];
+          const int n1 = bf.ts.size(L - l + 1, 2 * v), n2 = bf.ts.size(L - l + 1, 2 * v + 1);
+          char* dst = (char*)rt.scratch.take((size_t)M * (n1 + n2) * esz);
+          naddr[blk] = abs_off(dst);
+          if (M == 0 || n1 + n2 == 0) continue;
+          const int t2 = t / 2, q = t2 * vs + v;
+          const int a = (2 * t2) * vs + v, bb = (2 * t2 + 1) * vs + v;
+          const int wrows = bf.rr[l][a] + bf.rr[l][bb], row_off = (t & 1) ? bf.rr[l][a] : 0;
+          const int ia = t2 * (2 * vs) + 2 * v;
+          const int c1 = bf.rr[l - 1][ia], c2 = bf.rr[l - 1][ia + 1];
+          const int64_t woff = bf.offR[l][q] + row_off;
+          const int fb = l - 1 == 0 ? 0 : 4;
+          if (n1 > 0) phase(step).push_back(gt(woff, wrows, 0, faddr[ia], c1, fb, naddr[blk], M, M, n1, c1));
+          if (n2 > 0)
+            phase(step).push_back(gt(woff + (int64_t)c1 * wrows, wrows, 0, faddr[ia + 1], c2, fb,
+                                     naddr[blk] + (int64_t)n1 * M, M, M, n2, c2));
+        }
+      faddr.swap(naddr);
+    }
+    {
+      const int nt = 1 << lc, nv = 1 << (L - lc), fb = lc == 0 ? 0 : 4;
+      for (int t = 0; t < nt; ++t)
+        for (int v = 0; v < nv; ++v) {
+          const int blk = t * nv + v, M = bf.rl[lc][blk], K = bf.rr[lc][blk], N = bf.ts.size(L - lc, v);
+          if (M == 0 || N == 0) continue;
+          phase(lc).push_back(
+              gt(bf.offB[blk], std::max(M, 1), 0, faddr[blk], std::max(K, 1), fb, abs_off(mem + lay.g[b][blk]), M, M, N, K));
+        }
+    }
+  }
+  for (size_t d = 0; d < spec.dense.size(); ++d) {
+    const int n = spec.dense[d].second;
+    out.dense.push_back(mem + lay.dense[d]);
+    if (n == 0) continue;
+    copies.push_back(AxpbyTask{mem + lay.dense[d], pool + spec.dense[d].first * esz, n, n, n, n, 0});
+    maxcopy = std::max<int64_t>(maxcopy, (int64_t)n * n);
+  }
+  const int64_t lim[4] = {(int64_t)(rt.pool.used / esz), 0, 0, 0};
+  run_plan<T>(plan, *rt.c, pool, nullptr, nullptr, nullptr, s, lim, K_BF_GEMM);
+  if (!copies.empty())
+    chk(launch_mix_batch<T, T>((const AxpbyTask*)upload_tmp(rt, copies), (int)copies.size(), maxcopy, 1.0, 0.0, 0.0,
+                               s),
+        "centre copies");
+  // descriptors
+  std::vector<char> h(lay.total, 0);
+  const size_t dlo = lay.tb.empty() ? lay.descs : lay.tb[0];
+  std::vector<BfCentreDev> descs(spec.bfs.size());
+  for (size_t b = 0; b < spec.bfs.size(); ++b) {
+    const Butterfly& bf = *spec.bfs[b];
+    const int L = bf.L, lc = bf.lc, nt = 1 << lc, nv = 1 << (L - lc);
+    std::memcpy(h.data() + lay.tb[b], bf.to.b[lc].data(), (size_t)(nt + 1) * 4);
+    std::memcpy(h.data() + lay.vb[b], bf.ts.b[L - lc].data(), (size_t)(nv + 1) * 4);
+    std::memcpy(h.data() + lay.rk[b], bf.rl[lc].data(), (size_t)nt * nv * 4);
+    for (int blk = 0; blk < nt * nv; ++blk) {
+      const void* e = mem + lay.e[b][blk];
+      const void* g = mem + lay.g[b][blk];
+      std::memcpy(h.data() + lay.ep[b] + blk * sizeof(void*), &e, sizeof(void*));
+      std::memcpy(h.data() + lay.gp[b] + blk * sizeof(void*), &g, sizeof(void*));
+    }
+    BfCentreDev& d = descs[b];
+    std::memset(&d, 0, sizeof(d));
+    d.tb = (const int32_t*)(mem + lay.tb[b]);
+    d.vb = (const int32_t*)(mem + lay.vb[b]);
+    d.rk = (const int32_t*)(mem + lay.rk[b]);
+    d.E = (const void* const*)(mem + lay.ep[b]);
+    d.G = (const void* const*)(mem + lay.gp[b]);
+    d.nt = nt;
+    d.nv = nv;
+    d.single = sizeof(T) == 4 ? 1 : 0;
+  }
+  if (!descs.empty()) std::memcpy(h.data() + lay.descs, descs.data(), descs.size() * sizeof(BfCentreDev));
+  rt.c->stage.put(mem + dlo, h.data() + dlo, lay.total - dlo, s);
+  out.bfs = (const BfCentreDev*)(mem + lay.descs);
+  // the intermediate levels are reused once the launches above have run (stream order)
+  rt.scratch.release(mk);
+  return out;
+}
+
+template size_t centre_bytes<double>(const CentreSpec&);
+template size_t centre_bytes<float>(const CentreSpec&);
+template CentreOut build_centres<double>(BfRuntime<double>&, const CentreSpec&, char*);
+template CentreOut build_centres<float>(BfRuntime<float>&, const CentreSpec&, char*);
 
 // ------------------------------------------------------------ construction
 namespace {

@@ -202,15 +202,42 @@ struct BfRuntime {
 };
 
 // Extraction requests gathered over many blocks (and butterflies, and
-// fronts) and served by one launch.
+// fronts) and served by one launch (two when butterflies are read: the
+// butterfly tasks run after the front tasks and may add to their outputs).
 struct ExtractBatch {
   std::vector<ExtractTask> tasks;  // rows / cols hold offsets into idx until the launch
+  std::vector<BfExtractTask> bf_tasks;
   std::vector<int32_t> idx;
   // out = F(r0 + rows, c0 + cols) of the front fd, or of the dense matrix
   // (ld ldd) when dense is not null; the transpose when trans.
   void add(const FrontDesc* fd, const void* dense, int64_t ldd, const std::vector<int32_t>& rows, int r0,
            const std::vector<int32_t>& cols, int c0, void* out, int64_t ldo, bool trans);
+  // out = alpha K(r0 + rows, c0 + cols) of a butterfly in centre form (out += ... when accumulate)
+  void add_bf(const BfCentreDev* bf, const std::vector<int32_t>& rows, int r0, const std::vector<int32_t>& cols,
+              int c0, void* out, int64_t ldo, bool trans, double alpha, bool accumulate);
 };
+
+// ------------------------------------------------------------- centre forms
+// Entry extraction from butterflies (Alg. 3): every butterfly of a set is
+// expanded to its centre level (E and G of BfCentreDev) by grouped products,
+// each factor block multiplied once for all rows and columns, after which an
+// entry costs one dot product of its centre block's rank.  Dense square
+// blocks of the pool (the leaves of a HOD-BF) are copied beside them.
+// Everything goes to `mem` (device memory of at least centre_bytes(spec)
+// bytes, kept by the caller while the forms are used): nothing points into
+// the factor pool, which moves when it grows.
+struct CentreSpec {
+  std::vector<const Butterfly*> bfs;
+  std::vector<std::pair<int64_t, int>> dense;  // pool element offset and order (ld = order)
+};
+struct CentreOut {
+  const BfCentreDev* bfs = nullptr;  // device array, one descriptor per butterfly
+  std::vector<const void*> dense;    // device address of each copied dense block
+};
+template <class T>
+size_t centre_bytes(const CentreSpec& spec);
+template <class T>
+CentreOut build_centres(BfRuntime<T>& rt, const CentreSpec& spec, char* mem);
 // Entries written as complex<TO>; src_single: the dense sources (and the
 // contribution blocks) of the batch are complex<float>, else complex<double>.
 template <class TO, class T>

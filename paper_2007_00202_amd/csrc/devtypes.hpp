@@ -8,6 +8,53 @@ namespace bfmf {
 // operand transformation of the GEMM kernels: none, transpose, conjugate transpose
 enum : int32_t { OP_N = 0, OP_T = 1, OP_C = 2 };
 
+// A butterfly expanded to its centre level for entry extraction (Alg. 3 with
+// every factor block multiplied once for all rows and columns).  Centre block
+// blk = t * nv + v (t: node at level lc of the row tree, v: node at level
+// L - lc of the column tree) holds E = (U^L R^{L-1} .. R^{lc}) restricted to
+// the block (rows of t x rank, column-major, ld = rows of t) and G = B F
+// (rank x columns of v, column-major, ld = rank), so that an entry is
+// K(x, y) = E(x, :) G(:, y), one dot product of the block's rank.
+struct BfCentreDev {
+  const int32_t* tb;     // nt + 1 row boundaries at level lc
+  const int32_t* vb;     // nv + 1 column boundaries at level L - lc
+  const void* const* E;  // per block
+  const void* const* G;  // per block
+  const int32_t* rk;     // per block rank
+  int32_t nt, nv;
+  int32_t single;        // entries complex<float> (else complex<double>)
+  int32_t pad;
+};
+
+// One node of a contribution block in HOD-BF form (Sec. 4): rows and
+// columns [beg, end), children split at mid.  A leaf holds its dense block
+// (ld end - beg); an internal node its two off-diagonal butterflies, rows
+// [beg, mid) x columns [mid, end) (b12) and the converse (b21), as indices
+// into the centre-form array (-1: zero block).
+struct HodbfNodeDev {
+  int32_t beg, mid, end, left, right, b12, b21, pad;
+  const void* leaf;
+};
+struct HodbfDev {
+  const HodbfNodeDev* nodes;  // node 0 is the root
+  const BfCentreDev* bfs;
+  int32_t single;             // leaf entries complex<float> (else complex<double>)
+  int32_t depth;              // longest root-to-leaf path (bounds the descent)
+};
+
+// out(i, j) = alpha K(rows[i], cols[j]) (or out += ... when accumulate) for a
+// butterfly in centre form; nr x nc (ld ldo), or the transpose when trans.
+struct BfExtractTask {
+  const BfCentreDev* bf;
+  const int32_t* rows;
+  const int32_t* cols;
+  int32_t nr, nc;
+  void* out;
+  int64_t ldo;
+  int32_t trans, accumulate;
+  double alpha;
+};
+
 // One dense front F (n x n, column-major, ld = n) of the multifrontal tree.
 // F = [F11 F12; F21 F22] with F11 of size ns (the fully-summed variables
 // I^s) and F22 of size n - ns (the update variables I^u).
@@ -26,6 +73,7 @@ struct FrontDesc {
   const int32_t* inv[2];   // parent-local -> child-local index or -1 (length n)
   const void* cb[2];       // child contribution block (child F at (ns_c, ns_c))
   int64_t cb_ld[2];        // child leading dimension (child n)
+  const HodbfDev* chb[2];  // when not null: the child's contribution block in HOD-BF form
   const int64_t* a_ptr;    // n+1 offsets into a_row / a_vidx, per local column
   const int32_t* a_row;    // local row of each A entry of the column
   const int64_t* a_vidx;   // index of the entry in the CSR value array

@@ -531,8 +531,92 @@ __global__ void id_expand_kernel(const IdTask* __restrict__ tasks, void* const* 
 }
 
 // ------------------------------------------------------------ extraction
+// node k of a sorted boundary list b[0..n] with b[k] <= x < b[k + 1] (empty nodes skipped)
+__device__ __forceinline__ int node_of(const int32_t* __restrict__ b, int n, int x) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (b[mid] <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// K(x, y) of a butterfly in centre form: one dot product of the centre block's rank (FP64 sums)
+template <class TE>
+__device__ double2 centre_dot(const BfCentreDev& B, int x, int y) {
+  const int t = node_of(B.tb, B.nt, x), v = node_of(B.vb, B.nv, y);
+  const int blk = t * B.nv + v;
+  const int r = B.rk[blk];
+  const int64_t lde = B.tb[t + 1] - B.tb[t];
+  const cplx<TE>* E = (const cplx<TE>*)B.E[blk] + (x - B.tb[t]);
+  const cplx<TE>* G = (const cplx<TE>*)B.G[blk] + (int64_t)(y - B.vb[v]) * r;
+  double re = 0, im = 0;
+  for (int k = 0; k < r; ++k) {
+    const cplx<TE> e = E[k * lde], g = G[k];
+    re += (double)e.re * (double)g.re - (double)e.im * (double)g.im;
+    im += (double)e.re * (double)g.im + (double)e.im * (double)g.re;
+  }
+  return make_double2(re, im);
+}
+
+__device__ __forceinline__ double2 bf_entry(const BfCentreDev& B, int x, int y) {
+  return B.single ? centre_dot<float>(B, x, y) : centre_dot<double>(B, x, y);
+}
+
+// C(i, j) of a contribution block in HOD-BF form (Sec. 4): descend while i and j fall on the
+// same side of a node; a leaf gives a dense entry, a split the entry of that node's
+// off-diagonal butterfly (extract_HODBF through extract_BF)
+__device__ double2 hodbf_entry(const HodbfDev& H, int i, int j) {
+  int node = 0;
+  for (int d = 0; d <= H.depth; ++d) {
+    const HodbfNodeDev& nd = H.nodes[node];
+    if (nd.left < 0) {
+      const int64_t k = (int64_t)(i - nd.beg) + (int64_t)(j - nd.beg) * (nd.end - nd.beg);
+      if (H.single) {
+        const cplx<float> v = ((const cplx<float>*)nd.leaf)[k];
+        return make_double2(v.re, v.im);
+      }
+      const cplx<double> v = ((const cplx<double>*)nd.leaf)[k];
+      return make_double2(v.re, v.im);
+    }
+    const bool si = i >= nd.mid, sj = j >= nd.mid;
+    if (si == sj) {
+      node = si ? nd.right : nd.left;
+      continue;
+    }
+    const int b = si ? nd.b21 : nd.b12;
+    if (b < 0) return make_double2(0.0, 0.0);
+    return si ? bf_entry(H.bfs[b], i - nd.mid, j - nd.beg) : bf_entry(H.bfs[b], i - nd.beg, j - nd.mid);
+  }
+  return make_double2(0.0, 0.0);  // not reached for a well-formed tree
+}
+
+// out(i, j) = alpha K(rows[i], cols[j]) (+ out when accumulate) for butterflies in centre form
+template <class TO>
+__global__ __launch_bounds__(256) void bf_extract_kernel(const BfExtractTask* __restrict__ tasks) {
+  const BfExtractTask& tk = tasks[blockIdx.x];
+  cplx<TO>* out = (cplx<TO>*)tk.out;
+  const int nr = tk.nr, nc = tk.nc;
+  for (int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x; e < (int64_t)nr * nc; e += (int64_t)gridDim.y * 256) {
+    const int ii = (int)(e % nr), jj = (int)(e / nr);
+    const double2 v = bf_entry(*tk.bf, tk.rows[ii], tk.cols[jj]);
+    cplx<TO>* dst = tk.trans ? out + jj + (int64_t)ii * tk.ldo : out + ii + (int64_t)jj * tk.ldo;
+    double re = tk.alpha * v.x, im = tk.alpha * v.y;
+    if (tk.accumulate) {
+      re += (double)dst->re;
+      im += (double)dst->im;
+    }
+    *dst = cplx<TO>{(TO)re, (TO)im};
+  }
+}
+
 // out(i, j) = F(rows[i], cols[j]) with F = [A(Is,Is) A(Is,Iu); A(Iu,Is) 0]
-// (+) C_nu1 (+) C_nu2; one workgroup per task, threads over entries.
+// (+) C_nu1 (+) C_nu2 (list routing: the sparse matrix, then each child's
+// contribution block, dense or in HOD-BF form); one workgroup per task,
+// threads over entries.
 template <class T, class TC>
 __global__ __launch_bounds__(256) void front_extract_kernel(const ExtractTask* __restrict__ tasks,
                                                             const cplx<double>* __restrict__ values) {
@@ -559,9 +643,15 @@ __global__ __launch_bounds__(256) void front_extract_kernel(const ExtractTask* _
     for (int c = 0; c < fd->nchild; ++c) {
       const int ki = fd->inv[c][i], kj = fd->inv[c][j];
       if (ki >= 0 && kj >= 0) {
-        const TC v = ((const TC*)fd->cb[c])[ki + (int64_t)kj * fd->cb_ld[c]];
-        vr += v.re;
-        vi += v.im;
+        if (fd->chb[c]) {
+          const double2 v = hodbf_entry(*fd->chb[c], ki, kj);
+          vr += v.x;
+          vi += v.y;
+        } else {
+          const TC v = ((const TC*)fd->cb[c])[ki + (int64_t)kj * fd->cb_ld[c]];
+          vr += v.re;
+          vi += v.im;
+        }
       }
     }
     *dst = cplx<T>{(T)vr, (T)vi};
@@ -1043,6 +1133,14 @@ hipError_t launch_front_extract(const ExtractTask* d_tasks, int ntasks, int yblo
   return hipGetLastError();
 }
 
+template <class TO>
+hipError_t launch_bf_extract(const void* d_tasks, int ntasks, int yblocks, hipStream_t s) {
+  if (ntasks == 0) return hipSuccess;
+  hipLaunchKernelGGL((bf_extract_kernel<TO>), dim3(ntasks, yblocks > 0 ? yblocks : 1), dim3(256), 0, s,
+                     (const BfExtractTask*)d_tasks);
+  return hipGetLastError();
+}
+
 template <class T>
 hipError_t launch_philox_gauss(void* Om, int64_t ld, int64_t n, int ncol, int width, const int32_t* d_gbeg,
                                const int32_t* d_gend, uint64_t seed, uint64_t stream_id, hipStream_t s) {
@@ -1154,6 +1252,7 @@ hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int6
   template hipError_t launch_gram_id<T>(const IdTask*, int, double, int, int, hipStream_t);                           \
   template hipError_t launch_id_expand<T>(const IdTask*, int, void* const*, const int64_t*, bool, bool, hipStream_t);  \
   template hipError_t launch_front_extract<T>(const ExtractTask*, int, int, const void*, bool, hipStream_t);          \
+  template hipError_t launch_bf_extract<T>(const void*, int, int, hipStream_t);                                       \
   template hipError_t launch_philox_gauss<T>(void*, int64_t, int64_t, int, int, const int32_t*, const int32_t*,       \
                                              uint64_t, uint64_t, hipStream_t);                                        \
   template hipError_t launch_small_solve_right<T>(const void*, int, hipStream_t);                                     \

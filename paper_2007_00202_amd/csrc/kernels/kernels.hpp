@@ -134,6 +134,9 @@ hipError_t launch_id_expand(const IdTask* d_tasks, int ntasks, void* const* d_ou
 template <class T>
 hipError_t launch_front_extract(const ExtractTask* d_tasks, int ntasks, int yblocks, const void* values, bool src_single,
                                 hipStream_t s);
+// entries of butterflies in centre form (BfExtractTask list), written as complex<TO>
+template <class TO>
+hipError_t launch_bf_extract(const void* d_tasks, int ntasks, int yblocks, hipStream_t s);
 // complex Gaussian probes (Philox4x32-10): column c nonzero on rows [gbeg[c/width], gend[c/width])
 template <class T>
 hipError_t launch_philox_gauss(void* Om, int64_t ld, int64_t n, int ncol, int width, const int32_t* d_gbeg,

@@ -11,10 +11,11 @@ from .maxwell import yee_curlcurl
 from .acoustic import acoustic_27pt
 from .rhs import point_sources, center_source_with_noise, random_edge_dipoles, request_stream
 from .configs import CONFIGS, make_problem
+from .factors import random_butterfly, halving_bounds
 
 __all__ = [
     "rng_for", "CONFIG_IDS", "PURPOSE_IDS",
     "helmholtz_7pt", "omega_for_ppw", "grf_velocity", "yee_curlcurl", "acoustic_27pt",
     "point_sources", "center_source_with_noise", "random_edge_dipoles", "request_stream",
-    "CONFIGS", "make_problem",
+    "CONFIGS", "make_problem", "random_butterfly", "halving_bounds",
 ]

@@ -19,7 +19,7 @@ CONFIG_IDS = {
     "test": 99,           # small grids used by the test-suite
 }
 
-PURPOSE_IDS = {"coef": 0, "rhs": 1, "arrivals": 2, "probe": 3, "manufactured": 4}
+PURPOSE_IDS = {"coef": 0, "rhs": 1, "arrivals": 2, "probe": 3, "manufactured": 4, "factors": 5}
 
 
 def rng_for(config, purpose, extra=()):
