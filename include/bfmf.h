@@ -119,7 +119,14 @@ typedef struct {
                             (0: the kernels' own limits, 2048 columns for tol >= 1e-4, else
                             1024); wider blocks are decomposed as an ID of the IDs of column
                             chunks (about twice the tolerance); values in 1..15 are E_INVAL */
-    int32_t reserved[4];
+    int32_t compress_cb; /* 1: the contribution block of a compressed front whose parent is
+                            compressed too is built as an HOD-BF (tree: balanced bisection of
+                            I^u, leaves of at most 64) by entry evaluation of C_nu1 (+) C_nu2 - S
+                            (Alg. 5, last step), and the parent reads its entries through
+                            extract_HODBF / extract_BF (Alg. 3); such blocks then take no level
+                            workspace.  0 (default): they are dense FP64 blocks there.  Other
+                            values are E_INVAL */
+    int32_t reserved[3];
 } bfmf_factor_opts;
 
 /* GMRES options (Sec. 6): restarted GMRES(restart), modified Gram-Schmidt,
@@ -180,7 +187,12 @@ typedef struct {
     int32_t id_chunked;           /* ID blocks wider than one kernel, done as IDs of sub-IDs */
     double solve_flops_per_rhs;   /* one preconditioner application */
     uint64_t device_bytes_peak;   /* device memory held by the handle */
-    double reserved[8];
+    double cb_bytes;              /* bytes of the contribution blocks kept in HOD-BF form */
+    double cb_dense_bytes;        /* bytes the same blocks take dense (nu^2 entries each) */
+    int32_t cb_compressed;        /* contribution blocks built in HOD-BF form (compress_cb) */
+    int32_t pad0;
+    double workspace_bytes;       /* level workspaces (dense fronts and dense contribution blocks) */
+    double reserved[4];
 } bfmf_stats;
 
 /* Create a handle on HIP device `device`.  `hip_stream` (hipStream_t) is the

@@ -43,7 +43,7 @@ class bfmf_factor_opts(C.Structure):
                 ("batched", C.c_int32), ("samples", C.c_int32), ("knn", C.c_int32),
                 ("alpha", C.c_double), ("seed", C.c_uint64), ("hbm_budget", C.c_uint64),
                 ("keep_fronts", C.c_int32), ("timing", C.c_int32), ("smw_dense", C.c_int32),
-                ("id_max_cols", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("id_max_cols", C.c_int32), ("compress_cb", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class bfmf_kernel_stat(C.Structure):
@@ -77,7 +77,8 @@ class bfmf_stats(C.Structure):
                 ("dense_factor_bytes", C.c_double), ("max_rank", C.c_int32),
                 ("singular_front", C.c_int32), ("singular_index", C.c_int32), ("id_chunked", C.c_int32),
                 ("solve_flops_per_rhs", C.c_double), ("device_bytes_peak", C.c_uint64),
-                ("reserved", C.c_double * 8)]
+                ("cb_bytes", C.c_double), ("cb_dense_bytes", C.c_double), ("cb_compressed", C.c_int32),
+                ("pad0", C.c_int32), ("workspace_bytes", C.c_double), ("reserved", C.c_double * 4)]
 
 
 class bfmf_server_opts(C.Structure):
@@ -461,9 +462,11 @@ class Solver:
         return self
 
     def factor(self, tol=1e-3, n_min=1024, precision=BFMF_C128, batched=False, samples=64, knn=8,
-               alpha=2.0, seed=0, hbm_budget=0, keep_fronts=False, timing=False, smw_dense=0, id_max_cols=0):
+               alpha=2.0, seed=0, hbm_budget=0, keep_fronts=False, timing=False, smw_dense=0, id_max_cols=0,
+               compress_cb=False):
         o = bfmf_default_factor_opts()
         o.smw_dense, o.id_max_cols = smw_dense, id_max_cols
+        o.compress_cb = int(bool(compress_cb))
         o.timing = int(bool(timing))
         o.tol, o.n_min, o.precision, o.batched = tol, n_min, precision, int(bool(batched))
         o.samples, o.knn, o.alpha, o.seed = samples, knn, alpha, seed
@@ -501,7 +504,8 @@ class Solver:
         return bfmf_get_front(self.h, f, what, n)
 
     def front_block(self, f, what, X):
-        """Y = B X for block `what` of compressed front f (0 F11, 1 F11^-1, 2 F12, 3 F21, 4 S)."""
+        """Y = B X for block `what` of compressed front f (0 F11, 1 F11^-1, 2 F12, 3 F21, 4 S, 5 the
+        contribution block in HOD-BF form)."""
         sym = self.symbolic()
         ns = int(sym["send"][f] - sym["sbeg"][f])
         nu = int(sym["iu_ptr"][f + 1] - sym["iu_ptr"][f])

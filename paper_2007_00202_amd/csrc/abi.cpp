@@ -184,7 +184,8 @@ bfmf_status bfmf_factor(bfmf_handle h, const bfmf_factor_opts* opts) {
     else
       bfmf_default_factor_opts(&o);
     if (!(o.tol > 0) || o.samples < 0 || o.knn < 0 || o.alpha < 0 || o.smw_dense < 0 ||
-        (o.smw_dense > 0 && o.smw_dense < 16) || o.id_max_cols < 0 || (o.id_max_cols > 0 && o.id_max_cols < 16))
+        (o.smw_dense > 0 && o.smw_dense < 16) || o.id_max_cols < 0 || (o.id_max_cols > 0 && o.id_max_cols < 16) ||
+        (o.compress_cb != 0 && o.compress_cb != 1))
       throw Error(BFMF_E_INVAL, "factor: bad options");
     if (o.precision != BFMF_C128 && o.precision != BFMF_C64_MIXED)
       throw Error(BFMF_E_INVAL, "factor: unknown precision");
@@ -205,7 +206,16 @@ bfmf_status bfmf_factor(bfmf_handle h, const bfmf_factor_opts* opts) {
       h->d_kept.release();
       throw;
     }
-    h->stats.device_bytes_peak = h->device_bytes();
+    // the centre forms of contribution blocks in HOD-BF form are released level by level: add
+    // the most they held at once beyond what they hold now
+    uint64_t centre_peak = 0;
+    if (h->comp) {
+      double b0 = 0, b1 = 0;
+      int n0 = 0;
+      compressed_cb_stats(h->comp, b0, b1, n0, centre_peak);
+    }
+    const uint64_t now_b = h->device_bytes();
+    h->stats.device_bytes_peak = now_b + centre_peak - std::min<uint64_t>(centre_peak, comp_centre_held(h->comp));
     h->state = State::Factored;
   });
 }

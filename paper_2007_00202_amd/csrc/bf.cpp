@@ -948,7 +948,7 @@ CentreOut build_centres(BfRuntime<T>& rt, const CentreSpec& spec, char* mem) {
     d.single = sizeof(T) == 4 ? 1 : 0;
   }
   if (!descs.empty()) std::memcpy(h.data() + lay.descs, descs.data(), descs.size() * sizeof(BfCentreDev));
-  rt.c->stage.put(mem + dlo, h.data() + dlo, lay.total - dlo, s);
+  if (lay.total > dlo) rt.c->stage.put(mem + dlo, h.data() + dlo, lay.total - dlo, s);
   out.bfs = (const BfCentreDev*)(mem + lay.descs);
   // the intermediate levels are reused once the launches above have run (stream order)
   rt.scratch.release(mk);

@@ -80,6 +80,25 @@ struct FrontSource : EntrySource<T> {
   }
 };
 
+// Entries of a contribution block C = (C_nu1 (+) C_nu2)(Iu, Iu) - S that is
+// never formed (Alg. 5, last step): the children's part by list routing from
+// the front (rows and columns offset by ns), then S by extract_BF of its
+// centre form, subtracted in place.  row0 / col0: first I^u-local row and
+// column of the block being built.
+template <class T>
+struct CbSource : EntrySource<T> {
+  const FrontDesc* d_fd;
+  int ns, row0, col0;
+  const BfCentreDev* s;
+  CbSource(const FrontDesc* fd, int ns_, int r0, int c0, const BfCentreDev* s_)
+      : d_fd(fd), ns(ns_), row0(r0), col0(c0), s(s_) {}
+  void request(ExtractBatch& b, const std::vector<int32_t>& rows, const std::vector<int32_t>& cols, void* out,
+               int64_t ldo, bool trans) override {
+    b.add(d_fd, nullptr, 0, rows, ns + row0, cols, ns + col0, out, ldo, trans);
+    b.add_bf(s, rows, row0, cols, col0, out, ldo, trans, -1.0, true);
+  }
+};
+
 // Proxies: alpha |given| uniform samples plus, for every given index, its
 // k_nn nearest vertices (breadth-first search in the front's graph, layer by
 // layer, ascending index inside a layer) that fall into the node (Sec. 5.2).
@@ -803,6 +822,18 @@ struct CompState {
   BfRuntime<T> rt;
   std::vector<std::unique_ptr<CompressedFront<T>>> fronts;  // by front id (null if dense)
   DevBuf status;                                            // singular leaf or SMW block (int[4])
+  // centre forms and descriptors of the contribution blocks in HOD-BF form, one buffer per
+  // factor_level call, tagged with the tree depth of its fronts; released once the level above
+  // their parents' has started (the parents are then factored)
+  struct CbBuf {
+    int depth;
+    DevBuf buf;
+  };
+  std::vector<std::unique_ptr<CbBuf>> cbufs;
+  uint64_t cbuf_held = 0, cbuf_peak = 0;
+  double cb_bytes = 0, cb_dense_bytes = 0;
+  int cb_count = 0;
+  Budget* budget = nullptr;
 };
 
 template struct CompState<double>;
@@ -828,6 +859,11 @@ template <class T>
 static void reset_state(CompState<T>& st, Context& c, int nfronts) {
   st.fronts.clear();
   st.fronts.resize(nfronts);
+  st.cbufs.clear();
+  st.cbuf_held = st.cbuf_peak = 0;
+  st.cb_bytes = st.cb_dense_bytes = 0;
+  st.cb_count = 0;
+  st.budget = &c.fbudget;
   st.rt.c = &c;
   st.rt.pool.reset();
   // buffers kept from an earlier factorization count against this one's budget; beyond it they are
@@ -939,6 +975,209 @@ struct FrontWork {
 };
 
 }  // namespace
+
+// HOD-BF structure over a preorder bisection tree (node 0 the root)
+template <class T>
+static void hodbf_from_tree(Hodbf<T>& h, const std::vector<TreeNode>& nodes, int n) {
+  h.n = n;
+  h.nodes.clear();
+  h.nodes.resize(nodes.size());
+  h.max_level = 0;
+  std::vector<std::pair<int, int>> stck{{0, 0}};
+  while (!stck.empty() && !nodes.empty()) {
+    auto [i, l] = stck.back();
+    stck.pop_back();
+    auto& hn = h.nodes[i];
+    hn.beg = nodes[i].beg;
+    hn.end = nodes[i].end;
+    hn.left = nodes[i].left;
+    hn.right = nodes[i].right;
+    hn.level = l;
+    hn.depth = depth_of(nodes, i);
+    h.max_level = std::max(h.max_level, l);
+    if (hn.left >= 0) {
+      stck.push_back({hn.left, l + 1});
+      stck.push_back({hn.right, l + 1});
+    }
+  }
+  h.by_level.assign(h.max_level + 1, {});
+  for (int i = 0; i < (int)h.nodes.size(); ++i) h.by_level[h.nodes[i].level].push_back(i);
+}
+
+// Contribution blocks in HOD-BF form (Alg. 5, last step) for the fronts Wc
+// of one level at tree depth `depth`: C = (C_nu1 (+) C_nu2)(Iu, Iu) - S by
+// HODBF_entry_eval over the balanced tree of I^u (dense leaves, then every
+// off-diagonal block by Alg. 2, all fronts' blocks of a step together), each
+// request answered by list routing from the children (dense, or HOD-BF
+// through extract_HODBF) and by extract_BF of S.  Then the centre forms of
+// every block of C and its device descriptor, read by the parent's
+// extractions, in a buffer kept until the parent's level has been factored.
+template <class T>
+static void build_cb_hodbf(CompState<T>* st, Context& c, const std::vector<FrontWork<T>*>& Wc, int depth,
+                           double alpha, int knn) {
+  BfRuntime<T>& rt = st->rt;
+  hipStream_t s = rt.s();
+  const size_t esz = sizeof(cplx<T>);
+  if (Wc.empty()) return;
+  // centre buffers of fronts whose parents have been factored (two levels deeper or more)
+  if (!c.fopts.keep_fronts) {
+    for (auto& b : st->cbufs)
+      if (b && b->depth >= depth + 2) {
+        st->cbuf_held -= b->buf.bytes;
+        st->budget->held -= std::min<uint64_t>(st->budget->held, b->buf.bytes);
+        b.reset();
+      }
+    st->cbufs.erase(std::remove(st->cbufs.begin(), st->cbufs.end(), nullptr), st->cbufs.end());
+  }
+  auto mk = rt.scratch.mark();
+  // S of every front in centre form (temporary)
+  CentreSpec sspec;
+  for (auto* w : Wc) sspec.bfs.push_back(w->cf->s.get());
+  char* smem = (char*)rt.scratch.take(centre_bytes<T>(sspec));
+  const CentreOut scen = build_centres<T>(rt, sspec, smem);
+  // the HOD-BF trees and dense leaves: C(leaf, leaf), every pool allocation first
+  for (auto* w : Wc) {
+    Hodbf<T>& h = w->cf->cbh;
+    hodbf_from_tree<T>(h, w->unodes, w->cf->nu);
+    for (auto& nd : h.nodes)
+      if (nd.left < 0)
+        nd.leaf_off = (int64_t)(rt.pool.alloc((size_t)nd.size() * nd.size() * esz, s) / esz);
+  }
+  {
+    ExtractBatch eb;
+    for (size_t k = 0; k < Wc.size(); ++k) {
+      FrontWork<T>& w = *Wc[k];
+      for (auto& nd : w.cf->cbh.nodes)
+        if (nd.left < 0 && nd.size() > 0) {
+          std::vector<int32_t> r(nd.size());
+          for (int q = 0; q < nd.size(); ++q) r[q] = nd.beg + q;
+          void* out = rt.pool_base() + nd.leaf_off * esz;
+          eb.add(w.d_fd, nullptr, 0, r, w.cf->ns, r, w.cf->ns, out, nd.size(), false);
+          eb.add_bf(scen.bfs + k, r, 0, r, 0, out, nd.size(), false, -1.0, true);
+        }
+    }
+    run_extract<T>(rt, eb);
+  }
+  // off-diagonal butterflies (Alg. 2)
+  {
+    std::vector<std::unique_ptr<EntryJob<T>>> jobs;
+    std::vector<std::pair<HodbfNode<T>*, int>> dest;
+    for (size_t k = 0; k < Wc.size(); ++k) {
+      FrontWork<T>& w = *Wc[k];
+      const auto& nodes = w.unodes;
+      for (int i = 0; i < (int)nodes.size(); ++i) {
+        if (nodes[i].left < 0) continue;
+        const int a = nodes[i].left, b = nodes[i].right;
+        const int L = std::min(depth_of(nodes, a), depth_of(nodes, b));
+        BTree ta = subtree(nodes, a, L), tb = subtree(nodes, b, L);
+        for (int side = 0; side < 2; ++side) {
+          const int r = side ? b : a, cc = side ? a : b;
+          w.srcs.push_back(std::make_unique<CbSource<T>>(w.d_fd, w.cf->ns, nodes[r].beg, nodes[cc].beg, scen.bfs + k));
+          w.samplers.push_back(std::make_unique<BfsSampler>(w.nearall, w.cf->ns + nodes[r].beg,
+                                                            w.cf->ns + nodes[cc].beg, knn, alpha,
+                                                            w.seed + 9001 + 2 * i + side));
+          jobs.push_back(std::make_unique<EntryJob<T>>(
+              EntryJob<T>{w.srcs.back().get(), w.samplers.back().get(), side ? tb : ta, side ? ta : tb, nullptr}));
+          dest.push_back({&w.cf->cbh.nodes[i], side});
+        }
+      }
+    }
+    std::vector<EntryJob<T>*> jp;
+    for (auto& j : jobs) jp.push_back(j.get());
+    bf_entry_eval_batch<T>(rt, jp);
+    for (size_t k = 0; k < jobs.size(); ++k)
+      (dest[k].second ? dest[k].first->b21 : dest[k].first->b12) = std::move(jobs[k]->out);
+  }
+  rt.scratch.release(mk);  // S's centre form is no longer read (stream order)
+  // centre forms of C and the descriptors, in one buffer
+  CentreSpec spec;
+  std::vector<std::vector<int>> b12(Wc.size()), b21(Wc.size()), leaf(Wc.size());
+  for (size_t k = 0; k < Wc.size(); ++k) {
+    const Hodbf<T>& h = Wc[k]->cf->cbh;
+    b12[k].assign(h.nodes.size(), -1);
+    b21[k].assign(h.nodes.size(), -1);
+    leaf[k].assign(h.nodes.size(), -1);
+    for (int i = 0; i < (int)h.nodes.size(); ++i) {
+      const auto& nd = h.nodes[i];
+      if (nd.left < 0) {
+        leaf[k][i] = (int)spec.dense.size();
+        spec.dense.push_back({nd.leaf_off, nd.size()});
+        continue;
+      }
+      if (nd.b12) {
+        b12[k][i] = (int)spec.bfs.size();
+        spec.bfs.push_back(nd.b12.get());
+      }
+      if (nd.b21) {
+        b21[k][i] = (int)spec.bfs.size();
+        spec.bfs.push_back(nd.b21.get());
+      }
+    }
+  }
+  const size_t cbytes = (centre_bytes<T>(spec) + 63) & ~(size_t)63;
+  size_t dbytes = 0;
+  for (auto* w : Wc) dbytes += w->cf->cbh.nodes.size() * sizeof(HodbfNodeDev) + sizeof(HodbfDev) + 128;
+  const size_t total = cbytes + dbytes;
+  if (!st->budget->fits(total))
+    throw Error(BFMF_E_NOMEM, "contribution-block centre forms of " + std::to_string(total) +
+                                  " bytes exceed the HBM budget");
+  auto cb = std::make_unique<typename CompState<T>::CbBuf>();
+  cb->depth = depth;
+  HIPCHK(dev_malloc(&cb->buf.p, total));
+  cb->buf.bytes = total;
+  st->budget->held += total;
+  st->cbuf_held += total;
+  st->cbuf_peak = std::max(st->cbuf_peak, st->cbuf_held);
+  char* mem = (char*)cb->buf.p;
+  const CentreOut cen = build_centres<T>(rt, spec, mem);
+  std::vector<char> hd(dbytes, 0);
+  size_t off = 0;
+  for (size_t k = 0; k < Wc.size(); ++k) {
+    CompressedFront<T>& cf = *Wc[k]->cf;
+    const Hodbf<T>& h = cf.cbh;
+    const size_t node_off = off;
+    for (int i = 0; i < (int)h.nodes.size(); ++i) {
+      const auto& nd = h.nodes[i];
+      HodbfNodeDev d;
+      std::memset(&d, 0, sizeof(d));
+      d.beg = nd.beg;
+      d.end = nd.end;
+      d.left = nd.left;
+      d.right = nd.right;
+      d.mid = nd.left >= 0 ? h.nodes[nd.left].end : nd.end;
+      d.b12 = b12[k][i];
+      d.b21 = b21[k][i];
+      d.leaf = nd.left < 0 ? cen.dense[leaf[k][i]] : nullptr;
+      if (off + sizeof(d) > dbytes) throw Error(BFMF_E_INVAL, "internal: contribution-block descriptors overflow");
+      std::memcpy(hd.data() + off, &d, sizeof(d));
+      off += sizeof(d);
+    }
+    HodbfDev hdv;
+    std::memset(&hdv, 0, sizeof(hdv));
+    hdv.nodes = (const HodbfNodeDev*)(mem + cbytes + node_off);
+    hdv.bfs = cen.bfs;
+    hdv.single = sizeof(T) == 4 ? 1 : 0;
+    hdv.depth = h.nodes.empty() ? 0 : h.nodes[0].depth;
+    off = (off + 63) & ~(size_t)63;
+    if (off + sizeof(hdv) > dbytes) throw Error(BFMF_E_INVAL, "internal: contribution-block descriptors overflow");
+    std::memcpy(hd.data() + off, &hdv, sizeof(hdv));
+    cf.cb_dev = (const HodbfDev*)(mem + cbytes + off);
+    off += sizeof(hdv);
+    off = (off + 63) & ~(size_t)63;
+    // pool entries of the block and what it would take dense
+    int64_t e = 0;
+    for (const auto& nd : h.nodes) {
+      if (nd.left < 0) e += (int64_t)nd.size() * nd.size();
+      if (nd.b12) e += nd.b12->elems;
+      if (nd.b21) e += nd.b21->elems;
+    }
+    st->cb_bytes += (double)e * esz;
+    st->cb_dense_bytes += (double)cf.nu * cf.nu * sizeof(cplx<double>);
+    st->cb_count += 1;
+  }
+  rt.c->stage.put(mem + cbytes, hd.data(), off, s);
+  st->cbufs.push_back(std::move(cb));
+}
 
 // Compressed factorization (Alg. 5) of the fronts `fr` of one level of the
 // assembly tree: d_fds[i] is the device descriptor of fr[i], cbs[i] receives
@@ -1227,11 +1466,16 @@ static void factor_level(CompState<T>* st, Context& c, const std::vector<int>& f
     for (size_t k = 0; k < sw.size(); ++k) dest[k]->s = std::move(sw[k]->j.out);
   }
   tph[4] = clock();
-  // C = (C_nu1 (+) C_nu2)(Iu, Iu) - S, S applied to identity columns
+  // C = (C_nu1 (+) C_nu2)(Iu, Iu) - S: in HOD-BF form where the parent is compressed and
+  // compress_cb is set, else dense FP64 in the level workspace (S applied to identity columns)
+  std::vector<FrontWork<T>*> Wd, Wc;
+  for (auto& w : W)
+    if (w->cf->nu > 0) (c.cbcomp.size() > (size_t)w->f && c.cbcomp[w->f] ? Wc : Wd).push_back(w.get());
+  build_cb_hodbf<T>(st, c, Wc, c.sym.level[fr[0]], alpha, knn);
   {
     ExtractBatch eb;
     int maxnu = 0;
-    for (auto& w : W) {
+    for (auto* w : Wd) {
       const int ns = w->cf->ns, nu = w->cf->nu;
       if (nu == 0) continue;
       maxnu = std::max(maxnu, nu);
@@ -1243,9 +1487,9 @@ static void factor_level(CompState<T>* st, Context& c, const std::vector<int>& f
     // S applied to identity columns in chunks of 1024, chunk c0 of every front in one product
     const int chunk = 1024;
     auto mk = rt.scratch.mark();
-    std::vector<cplx<T>*> I(W.size(), nullptr), St(W.size(), nullptr);
-    for (size_t k = 0; k < W.size(); ++k) {
-      const int nu = W[k]->cf->nu;
+    std::vector<cplx<T>*> I(Wd.size(), nullptr), St(Wd.size(), nullptr);
+    for (size_t k = 0; k < Wd.size(); ++k) {
+      const int nu = Wd[k]->cf->nu;
       if (nu == 0) continue;
       I[k] = (cplx<T>*)rt.scratch.take((size_t)nu * std::min(chunk, nu) * sizeof(cplx<T>));
       if (sizeof(T) != 8) St[k] = (cplx<T>*)rt.scratch.take((size_t)nu * std::min(chunk, nu) * sizeof(cplx<T>));
@@ -1255,15 +1499,15 @@ static void factor_level(CompState<T>* st, Context& c, const std::vector<int>& f
       std::vector<AxpbyTask> eye, upd;
       std::vector<BfCall> calls;
       int64_t maxe = 0;
-      for (size_t k = 0; k < W.size(); ++k) {
-        const int nu = W[k]->cf->nu;
+      for (size_t k = 0; k < Wd.size(); ++k) {
+        const int nu = Wd[k]->cf->nu;
         if (nu <= c0) continue;
         const int wd = std::min(chunk, nu - c0);
         maxe = std::max<int64_t>(maxe, (int64_t)nu * wd);
         eye.push_back(AxpbyTask{I[k], nullptr, nu, nu, nu, wd, c0});  // I(i, c) = 1 where i == c0 + c
-        cplx<double>* cbc = (cplx<double>*)W[k]->cb + (size_t)c0 * nu;  // contribution blocks stay FP64
+        cplx<double>* cbc = (cplx<double>*)Wd[k]->cb + (size_t)c0 * nu;  // contribution blocks stay FP64
         BfCall cl;
-        cl.bf = W[k]->cf->s.get();
+        cl.bf = Wd[k]->cf->s.get();
         cl.x_off = cl.y_off = 0;
         cl.alpha_im = 0;
         cl.x_abs = (int64_t)((uintptr_t)I[k] / esz);
@@ -1547,8 +1791,10 @@ static void apply_block(CompState<T>& st, int f, int what, int nrhs, const doubl
   CompressedFront<T>& cf = *st.fronts[f];
   const int ns = cf.ns, nu = cf.nu;
   const int rows = (what <= 2) ? ns : nu, cols = (what == 0 || what == 1 || what == 3) ? ns : nu;
-  if (what < 0 || what > 4) throw Error(BFMF_E_INVAL, "apply_front_block: bad 'what'");
+  if (what < 0 || what > 5) throw Error(BFMF_E_INVAL, "apply_front_block: bad 'what'");
   if (what >= 2 && nu == 0) throw Error(BFMF_E_INVAL, "apply_front_block: the front has no update set");
+  if (what == 5 && !cf.cb_dev)
+    throw Error(BFMF_E_INVAL, "apply_front_block: the contribution block is not in HOD-BF form");
   if (nrhs <= 0 || ldx < cols || ldy < rows || !X || !Y) throw Error(BFMF_E_INVAL, "apply_front_block: bad arguments");
   hipStream_t s = rt.s();
   std::vector<cplx<T>> hx((size_t)cols * nrhs), hy((size_t)rows * nrhs);
@@ -1566,6 +1812,7 @@ static void apply_block(CompState<T>& st, int f, int what, int nrhs, const doubl
     case 1: hodbf_inv_apply<T>(rt, cf.f11, 0, dx, cols, dy, rows, nrhs, false); break;
     case 2: rt.apply(*cf.f12, dx, cols, dy, rows, nrhs, false, 1.0, 0); break;
     case 3: rt.apply(*cf.f21, dx, cols, dy, rows, nrhs, false, 1.0, 0); break;
+    case 5: hodbf_apply<T>(rt, cf.cbh, dx, cols, dy, rows, nrhs); break;
     default: rt.apply(*cf.s, dx, cols, dy, rows, nrhs, false, 1.0, 0); break;
   }
   ochk(hipMemcpyAsync(hy.data(), dy, hy.size() * sizeof(cplx<T>), hipMemcpyDeviceToHost, s), "download");
@@ -1612,7 +1859,7 @@ void comp_apply_block(void* state, int f, int what, int nrhs, const double* X, i
 
 template <class T>
 static uint64_t state_bytes(const CompState<T>& st) {
-  uint64_t b = st.rt.pool.buf.bytes + st.status.bytes;
+  uint64_t b = st.rt.pool.buf.bytes + st.status.bytes + st.cbuf_held;
   for (auto& ch : st.rt.scratch.chunks) b += ch->b.bytes;
   return b;
 }
@@ -1625,15 +1872,50 @@ uint64_t comp_state_bytes(void* state) {
 
 void compressed_stats(void* state, double& bytes, int& maxrank, int& chunked) {
   auto* h = (CompHolder*)state;
+  // the factors: the pool less the contribution blocks kept in it
   if (h->single) {
-    bytes = (double)h->f->rt.pool.used;
+    bytes = (double)h->f->rt.pool.used - h->f->cb_bytes;
     maxrank = h->f->rt.max_rank_seen;
     chunked = (int)h->f->rt.n_chunked;
   } else {
-    bytes = (double)h->d->rt.pool.used;
+    bytes = (double)h->d->rt.pool.used - h->d->cb_bytes;
     maxrank = h->d->rt.max_rank_seen;
     chunked = (int)h->d->rt.n_chunked;
   }
+}
+
+void compressed_cb_stats(void* state, double& bytes, double& dense_bytes, int& count, uint64_t& centre_peak) {
+  auto* h = (CompHolder*)state;
+  bytes = dense_bytes = 0;
+  count = 0;
+  centre_peak = 0;
+  if (!h) return;
+  auto get = [&](auto& st) {
+    bytes = st.cb_bytes;
+    dense_bytes = st.cb_dense_bytes;
+    count = st.cb_count;
+    centre_peak = st.cbuf_peak;
+  };
+  if (h->single && h->f) get(*h->f);
+  if (!h->single && h->d) get(*h->d);
+}
+
+uint64_t comp_centre_held(void* state) {
+  auto* h = (CompHolder*)state;
+  if (!h) return 0;
+  if (h->single) return h->f ? h->f->cbuf_held : 0;
+  return h->d ? h->d->cbuf_held : 0;
+}
+
+const HodbfDev* comp_cb_dev(void* state, int f) {
+  auto* h = (CompHolder*)state;
+  if (!h) return nullptr;
+  if (h->single) {
+    if (!h->f || f < 0 || f >= (int)h->f->fronts.size() || !h->f->fronts[f]) return nullptr;
+    return h->f->fronts[f]->cb_dev;
+  }
+  if (!h->d || f < 0 || f >= (int)h->d->fronts.size() || !h->d->fronts[f]) return nullptr;
+  return h->d->fronts[f]->cb_dev;
 }
 
 }  // namespace bfmf

@@ -46,6 +46,11 @@ struct CompressedFront {
   std::unique_ptr<Butterfly> f12, f21, s;
   int64_t cb_off = -1;  // dense contribution block nu x nu (byte offset in the front arena)
   double flops = 0;
+  // contribution block in HOD-BF form (when the parent is compressed and compress_cb is set):
+  // leaves and butterflies in the pool, its device descriptor (centre forms, kept until the
+  // parent's level has been factored) for the parent's entry extraction
+  Hodbf<T> cbh;
+  const HodbfDev* cb_dev = nullptr;
 };
 
 // y = alpha F11 x + beta y (the HOD-BF itself)

@@ -275,6 +275,7 @@ struct Context {
 
   // compressed fronts (Alg. 5): flag per front, dense fronts per level first
   std::vector<uint8_t> compressed;
+  std::vector<uint8_t> cbcomp;        // compressed front whose contribution block is kept in HOD-BF form
   std::vector<int32_t> level_order;   // fronts in level order, dense first within a level
   std::vector<int32_t> level_ndense;  // dense fronts of each level
   void* comp = nullptr;               // CompState (compressed.cpp)
@@ -313,11 +314,19 @@ void forward_compressed_level(void* state, Context& c, const std::vector<int>& f
 void backward_compressed_level(void* state, Context& c, const std::vector<int>& fronts,
                                const std::vector<void*>& Ws, const std::vector<int>& ns, int nrhs);
 void compressed_stats(void* state, double& bytes, int& maxrank, int& chunked);
+// contribution blocks in HOD-BF form: their pool bytes, the bytes they take dense, their count,
+// and the largest device memory their centre forms held at once
+void compressed_cb_stats(void* state, double& bytes, double& dense_bytes, int& count, uint64_t& centre_peak);
+// device bytes the centre forms of contribution blocks hold now
+uint64_t comp_centre_held(void* state);
+// device descriptor of front f's contribution block in HOD-BF form (null if it has none)
+const HodbfDev* comp_cb_dev(void* state, int f);
 uint64_t comp_state_bytes(void* state);  // device bytes held by the compressed fronts' pools
 // out(i, j) = F(rows[i], cols[j]) of front f from A and the children's contribution blocks (host, ld ldo)
 void extract_front_entries(Context& c, int f, const std::vector<int32_t>& rows, const std::vector<int32_t>& cols,
                            double* out, int64_t ldo);
-// Y = B X for a block of compressed front f (0 F11, 1 F11^-1, 2 F12, 3 F21, 4 S); host complex128 arrays
+// Y = B X for a block of compressed front f (0 F11, 1 F11^-1, 2 F12, 3 F21, 4 S, 5 the contribution
+// block in HOD-BF form); host complex128 arrays
 void comp_apply_block(void* state, int f, int what, int nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy);
 
 // Continuous-batching GMRES of the serving form: the columns ("slots") of B and X

@@ -150,6 +150,13 @@ void factor_dense(Context& c) {
       c.compressed[f] = 1;
       ++ncomp;
     }
+  // contribution blocks kept in HOD-BF form: compressed fronts with a compressed parent
+  c.cbcomp.assign(nf, 0);
+  if (c.fopts.compress_cb)
+    for (int32_t f = 0; f < nf; ++f) {
+      const int32_t p = c.sym.parent[f];
+      if (c.compressed[f] && p >= 0 && c.compressed[p] && c.fp[f].nu > 0) c.cbcomp[f] = 1;
+    }
   // level order with the dense fronts of a level first
   const int nlev0 = (int)c.level_ptr.size() - 1;
   c.level_order.clear();
@@ -172,6 +179,7 @@ void factor_dense(Context& c) {
   // block stays readable.
   auto wsize = [&](int32_t f) {
     const FrontPlan& p = c.fp[f];
+    if (c.cbcomp[f]) return (int64_t)0;  // its contribution block lives in HOD-BF form
     return c.compressed[f] ? (int64_t)p.nu * p.nu : (int64_t)p.n * p.n;
   };
   int64_t par_max[2] = {0, 0}, uniq = 0;
@@ -251,7 +259,10 @@ void factor_dense(Context& c) {
     for (int q = 0; q < p.nchild; ++q) {
       const FrontPlan& cp = c.fp[p.child[q]];
       d.inv[q] = c.d_inv.as<int32_t>() + p.inv_off[q];
-      if (c.compressed[p.child[q]]) {  // contribution block stored alone (ld nu)
+      if (c.cbcomp[p.child[q]]) {  // HOD-BF: its descriptor is set once the child is factored
+        d.cb[q] = nullptr;
+        d.cb_ld[q] = 1;
+      } else if (c.compressed[p.child[q]]) {  // contribution block stored alone (ld nu)
         d.cb[q] = arena + cp.f_off * elem;
         d.cb_ld[q] = std::max(cp.nu, 1);
       } else {
@@ -345,8 +356,25 @@ void factor_dense(Context& c) {
         cfr.push_back(f);
         cfd.push_back(dfds + k);
         ccb.push_back(arena + c.fp[f].f_off * elem);
+        const FrontDesc& d = c.h_fds[k];
+        for (int q = 0; q < d.nchild; ++q)
+          if (!d.cb[q] && !d.chb[q])
+            throw Error(BFMF_E_INVAL, "internal: a child's contribution block is missing");
       }
       factor_compressed_level(c.comp, c, cfr, cfd, ccb);
+      // the parents read the blocks built in HOD-BF form through these descriptors
+      for (int32_t f : cfr) {
+        if (!c.cbcomp[f]) continue;
+        const int32_t p = c.sym.parent[f];
+        const int kp = c.desc_index[p];
+        const FrontPlan& pp = c.fp[p];
+        const HodbfDev* dv = comp_cb_dev(c.comp, f);
+        if (!dv) throw Error(BFMF_E_INVAL, "internal: contribution block in HOD-BF form without a descriptor");
+        for (int q = 0; q < pp.nchild; ++q)
+          if (pp.child[q] == f) c.h_fds[kp].chb[q] = dv;
+        HIPCHK(hipMemcpyAsync(dfds + kp, &c.h_fds[kp], sizeof(FrontDesc), hipMemcpyHostToDevice, c.stream));
+        HIPCHK(hipStreamSynchronize(c.stream));
+      }
     }
   }
   HIPCHK(hipStreamSynchronize(c.stream));
@@ -404,6 +432,13 @@ void factor_dense(Context& c) {
     bytes += cb;
   }
   c.stats.id_chunked = chunked;
+  c.stats.cb_bytes = c.stats.cb_dense_bytes = 0;
+  c.stats.cb_compressed = 0;
+  if (ncomp) {
+    uint64_t centre_peak = 0;
+    compressed_cb_stats(c.comp, c.stats.cb_bytes, c.stats.cb_dense_bytes, c.stats.cb_compressed, centre_peak);
+  }
+  c.stats.workspace_bytes = (double)c.work_elems * 16.0;
   c.stats.factor_flops = flops;
   c.stats.factor_bytes = bytes;
   c.stats.dense_factor_bytes = dense_bytes;
