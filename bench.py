@@ -56,6 +56,8 @@ def parse():
                     help="separators are bisected down to this many nodes (HOD-BF leaves); default: the workload's")
     ap.add_argument("--parallel-levels", type=int, default=0,
                     help="separator variant: the top levels of the dissection cut across one axis (parallel planes)")
+    ap.add_argument("--compress-cb", action="store_true",
+                    help="contribution blocks of compressed fronts with compressed parents in HOD-BF form")
     ap.add_argument("--direct", action="store_true",
                     help="direct mode: X = M^-1 B from the factorization, no GMRES (use with a tight --tol)")
     ap.add_argument("--gemm-tile", type=int, default=-1,
@@ -189,7 +191,8 @@ def cpu_baseline(bfmf, reps=3, with_48=True):
     return out
 
 
-def run_form(bfmf, s, prob, nrhs, dB, dX, steps, warmup, form, precision, n_min, tol, timing=True, direct=False):
+def run_form(bfmf, s, prob, nrhs, dB, dX, steps, warmup, form, precision, n_min, tol, timing=True, direct=False,
+             compress_cb=False):
     """Factor + GMRES solve of the RHS block (or, direct, one application of the factorization),
     `steps` timed steps after `warmup` untimed ones."""
     import torch
@@ -200,7 +203,8 @@ def run_form(bfmf, s, prob, nrhs, dB, dX, steps, warmup, form, precision, n_min,
         so.max_iter = -1
 
     def step():
-        s.factor(tol=tol, n_min=n_min, precision=prec, batched=(form == "batched"), timing=timing)
+        s.factor(tol=tol, n_min=n_min, precision=prec, batched=(form == "batched"), timing=timing,
+                 compress_cb=compress_cb)
         o, st = bfmf.bfmf_solve_device(s.h, dB.data_ptr(), prob.n, dX.data_ptr(), prob.n, nrhs, so)
         if st != 0:
             raise RuntimeError(f"solve did not converge ({form}, {precision}): relres {o.relres_max}")
@@ -226,7 +230,10 @@ def run_form(bfmf, s, prob, nrhs, dB, dX, steps, warmup, form, precision, n_min,
             "solve_rhs_per_s": nrhs / float(np.mean(ssec)), "gmres_iters": int(max(iters)),
             "relres_max": float(max(relres)), "factor_flops": st["factor_flops"],
             "factor_bytes": st["factor_bytes"], "dense_factor_bytes": st["dense_factor_bytes"],
-            "max_rank": st["max_rank"], "kernels": s.kernel_stats(), "gemm_tiles": s.gemm_tile_launches()}
+            "max_rank": st["max_rank"], "kernels": s.kernel_stats(), "gemm_tiles": s.gemm_tile_launches(),
+            "memory": {"workspace_gb": st["workspace_bytes"] / 1e9, "cb_hodbf": st["cb_compressed"],
+                       "cb_hodbf_gb": st["cb_bytes"] / 1e9, "cb_hodbf_dense_gb": st["cb_dense_bytes"] / 1e9,
+                       "device_peak_gb": st["device_bytes_peak"] / 1e9}}
 
 
 PROFILES = os.path.join(ROOT, "profiles")
@@ -446,7 +453,8 @@ def main():
                                parallel_levels=a.parallel_levels)
     dB = torch.from_numpy(np.ascontiguousarray(prob.rhs.T)).to("cuda")  # column-major (N, nrhs)
     dX = torch.zeros_like(dB)
-    r = run_form(bfmf, s, prob, nrhs, dB, dX, a.steps, a.warmup, a.form, precision, n_min, tol, direct=a.direct)
+    r = run_form(bfmf, s, prob, nrhs, dB, dX, a.steps, a.warmup, a.form, precision, n_min, tol, direct=a.direct,
+                 compress_cb=a.compress_cb)
     rf, kernels = roofline(r["kernels"], a.steps, precision, a.config)
     dtype = {"c128": "c128", "c64": "c64+f64"}[precision]
     wl = f"{a.config}: {operator_label(cfg)} {prob.dims[0]}^3 (N={prob.n}), {nrhs} RHS"
@@ -463,11 +471,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl, "form": a.form, "n_min": n_min, "tol": tol, "precision": precision,
                    "sep_leaf": sep_leaf, "parallel_levels": a.parallel_levels,
-                   "solver": "direct" if a.direct else "gmres"},
+                   "solver": "direct" if a.direct else "gmres", "compress_cb": bool(a.compress_cb)},
         "factor_s": r["factor_s"], "solve_s": r["solve_s"], "solve_rhs_per_s": r["solve_rhs_per_s"],
         "gmres_iters": r["gmres_iters"], "relres_max": r["relres_max"],
         "factor_gb": r["factor_bytes"] / 1e9, "dense_factor_gb": r["dense_factor_bytes"] / 1e9,
         "max_rank": r["max_rank"],
+        "memory": r["memory"],
         "exact_factor_flops": exact_flops(s),
         "roofline": rf,
         "kernels": kernels,
