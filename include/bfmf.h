@@ -332,18 +332,20 @@ bfmf_status bfmf_reset_kernel_stats(bfmf_handle h);
 /* Tile shapes of the grouped GEMM behind every butterfly product (the
  * block-diagonal levels of an apply, Sec. 3, and the products of the
  * constructions).  Rows x columns of C per workgroup:
- *   0: 64 x 64, 1: 32 x 128, 2: 128 x 32, 3: 16 x 256, 4: 256 x 16 (A and B
- *   staged through LDS), 5: 256 x 16 streaming (only for launches whose tasks
- *   all have at most 16 columns and no transposes).
- * By default each launch takes the shape of least predicted time from a table
- * measured on the device on first use (every shape timed on synthetic
- * launches over a grid of task shapes, per precision; about a second, once
- * per process and device).  All shapes give the same result bit for bit.
- * bfmf_set_gemm_tile forces one shape for the whole process (-1: back to the
- * measured choice; shape 5 falls back to 0 where it does not apply); E_INVAL
- * outside -1..5.  bfmf_get_gemm_tile_launches writes the number of launches
- * per shape since the last bfmf_reset_kernel_stats into out[0..5] (n >= 6). */
-enum { BFMF_GEMM_TILES = 6 };
+ *   0: 64 x 64, 1: 32 x 128, 2: 128 x 32, 3: 16 x 256, 4: 256 x 16, 6: 48 x 128,
+ *   7: 96 x 64 (A and B staged through LDS), 5: 256 x 16 streaming (only for
+ *   tasks with at most 16 columns and no transposes).
+ * By default each product phase takes the shape of least predicted time from
+ * a table measured on the device on first use (every shape timed on synthetic
+ * launches over a grid of task shapes, per precision; a few seconds, once per
+ * process and device); a phase whose tasks differ in height is split into one
+ * launch per shape when that is predicted at least 5% faster.  All shapes
+ * give the same result bit for bit.  bfmf_set_gemm_tile forces one shape for
+ * the whole process (-1: back to the measured choice; shape 5 falls back to 0
+ * where it does not apply); E_INVAL outside -1..7.
+ * bfmf_get_gemm_tile_launches writes the number of launches per shape since
+ * the last bfmf_reset_kernel_stats into out[0..7] (n >= 8). */
+enum { BFMF_GEMM_TILES = 8 };
 bfmf_status bfmf_set_gemm_tile(int32_t cfg);
 bfmf_status bfmf_get_gemm_tile_launches(bfmf_handle h, int64_t* out, int32_t n);
 

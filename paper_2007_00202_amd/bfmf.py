@@ -330,8 +330,8 @@ def bfmf_reset_kernel_stats(h):
     _check(h, _lib.bfmf_reset_kernel_stats(h))
 
 
-BFMF_GEMM_TILES = 6
-GEMM_TILE_SHAPES = ["64x64", "32x128", "128x32", "16x256", "256x16", "256x16 streaming"]
+BFMF_GEMM_TILES = 8
+GEMM_TILE_SHAPES = ["64x64", "32x128", "128x32", "16x256", "256x16", "256x16 streaming", "48x128", "96x64"]
 
 
 def bfmf_device_allocation_count():

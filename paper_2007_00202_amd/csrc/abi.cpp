@@ -432,6 +432,8 @@ bfmf_status bfmf_reset_kernel_stats(bfmf_handle h) {
   return BFMF_OK;
 }
 
+static_assert(GEMM_CFGS == BFMF_GEMM_TILES && GEMM_CFGS <= 16, "tile shapes of the C ABI");
+
 bfmf_status bfmf_set_gemm_tile(int32_t cfg) {
   if (cfg < -1 || cfg >= GEMM_CFGS) return BFMF_E_INVAL;
   set_gemm_tile_override(cfg);

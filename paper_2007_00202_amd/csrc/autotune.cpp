@@ -27,14 +27,17 @@ namespace bfmf {
 
 namespace {
 
-constexpr int NM = 5, NN = 6, NK = 4;
-constexpr int MB[NM] = {16, 32, 64, 128, 256};
+// rows in steps that separate the tile heights (16, 32, 48, 64, 96, 128, 256)
+constexpr int NM = 9, NN = 6, NK = 4;
+constexpr int MB[NM] = {16, 32, 48, 64, 80, 96, 128, 192, 256};
 constexpr int NB[NN] = {16, 32, 64, 128, 256, 1024};
 constexpr int KB[NK] = {16, 64, 256, 1024};
 
 struct Table {
   bool ready = false;
   double us[GEMM_CFGS][NM][NN][NK];  // microseconds per task
+  // fastest shape per bucket, without and with the skinny shape allowed (filled once ready)
+  int8_t best[NM][NN][NK][2];
 };
 
 std::mutex g_mu;
@@ -45,6 +48,36 @@ int bucket(const int* b, int n, int v) {
   for (int i = 0; i < n; ++i)
     if (v <= b[i]) return i;
   return n - 1;
+}
+
+// bucket of every value up to the largest bucket (1024), built once
+struct BucketLut {
+  int8_t m[1025], n[1025], k[1025];
+  BucketLut() {
+    for (int v = 0; v <= 1024; ++v) {
+      m[v] = (int8_t)bucket(MB, NM, v);
+      n[v] = (int8_t)bucket(NB, NN, v);
+      k[v] = (int8_t)bucket(KB, NK, v);
+    }
+  }
+};
+const BucketLut& lut() {
+  static const BucketLut l;
+  return l;
+}
+
+void fill_best(Table& t) {
+  for (int mi = 0; mi < NM; ++mi)
+    for (int ni = 0; ni < NN; ++ni)
+      for (int ki = 0; ki < NK; ++ki)
+        for (int sk = 0; sk < 2; ++sk) {
+          int b = 0;
+          for (int cfg = 1; cfg < GEMM_CFGS; ++cfg) {
+            if (cfg == GEMM_CFG_SKINNY && !sk) continue;
+            if (t.us[cfg][mi][ni][ki] < t.us[b][mi][ni][ki]) b = cfg;
+          }
+          t.best[mi][ni][ki][sk] = (int8_t)b;
+        }
 }
 
 void tchk(hipError_t e, const char* what) {
@@ -208,17 +241,31 @@ const Table& table_for(int device, hipStream_t s) {
       build_table<T>(t, s);
       if (!path.empty()) save_table(t, path, esz);
     }
+    fill_best(t);
   }
   return t;
 }
 
+struct Buckets {
+  int mi, ni, ki;
+  double scale;  // beyond the largest bucket: time in proportion
+};
+Buckets buckets_of(const GTask& g) {
+  const BucketLut& l = lut();
+  Buckets b;
+  b.mi = g.M <= 1024 ? l.m[std::max(g.M, 0)] : NM - 1;
+  b.ni = g.N <= 1024 ? l.n[std::max(g.N, 0)] : NN - 1;
+  b.ki = g.K <= 1024 ? l.k[std::max(g.K, 0)] : NK - 1;
+  b.scale = 1.0;
+  if (g.M > MB[NM - 1]) b.scale *= (double)g.M / MB[NM - 1];
+  if (g.N > NB[NN - 1]) b.scale *= (double)g.N / NB[NN - 1];
+  if (g.K > KB[NK - 1]) b.scale *= (double)g.K / KB[NK - 1];
+  return b;
+}
+
 double predict(const Table& t, int cfg, const GTask& g) {
-  const int mi = bucket(MB, NM, g.M), ni = bucket(NB, NN, g.N), ki = bucket(KB, NK, g.K);
-  double v = t.us[cfg][mi][ni][ki];
-  if (g.M > MB[NM - 1]) v *= (double)g.M / MB[NM - 1];
-  if (g.N > NB[NN - 1]) v *= (double)g.N / NB[NN - 1];
-  if (g.K > KB[NK - 1]) v *= (double)g.K / KB[NK - 1];
-  return v;
+  const Buckets b = buckets_of(g);
+  return t.us[cfg][b.mi][b.ni][b.ki] * b.scale;
 }
 
 }  // namespace
@@ -254,6 +301,46 @@ int choose_gemm_cfg(int device, hipStream_t s, const std::vector<GTask>& ph) {
   return arg;
 }
 
+// Shapes for the tasks of one phase: either one shape for all (returned), or,
+// when that pads tasks of very different heights, each task's own best shape
+// (task_cfg filled, -1 returned; the caller launches one group per shape).
+// Groups of fewer than kMinSplitTiles tiles stay with the phase's shape, and
+// the split is taken only when the predicted time, with kLaunchUs for each
+// extra launch, is at least 5% less.
+template <class T>
+int choose_gemm_cfg_split(int device, hipStream_t s, const std::vector<GTask>& ph, std::vector<int>& task_cfg) {
+  constexpr double kLaunchUs = 6.0;
+  constexpr int64_t kMinSplitTiles = 512;
+  const int single = choose_gemm_cfg<T>(device, s, ph);
+  if (g_override.load() >= 0 || ph.size() < 2) return single;
+  const Table& t = table_for<T>(device, s);
+  task_cfg.assign(ph.size(), single);
+  double c_single = 0, c_split = 0;
+  int64_t tiles[GEMM_CFGS] = {};
+  std::vector<Buckets> bk(ph.size());
+  for (size_t i = 0; i < ph.size(); ++i) {
+    const GTask& g = ph[i];
+    const bool sk = g.N <= GEMM_CFG_TN[GEMM_CFG_SKINNY] && g.opA == OP_N && g.opB == OP_N;
+    const Buckets b = bk[i] = buckets_of(g);
+    const int c = t.best[b.mi][b.ni][b.ki][sk ? 1 : 0];
+    task_cfg[i] = c;
+    tiles[c] += gemm_cfg_tiles(c, g.M, g.N);
+    c_single += t.us[single][b.mi][b.ni][b.ki] * b.scale;
+  }
+  int groups = 0;
+  for (size_t i = 0; i < ph.size(); ++i)
+    if (tiles[task_cfg[i]] < kMinSplitTiles) task_cfg[i] = single;
+  bool used[GEMM_CFGS] = {};
+  for (size_t i = 0; i < ph.size(); ++i) {
+    used[task_cfg[i]] = true;
+    c_split += t.us[task_cfg[i]][bk[i].mi][bk[i].ni][bk[i].ki] * bk[i].scale;
+  }
+  for (bool u : used) groups += u ? 1 : 0;
+  if (groups <= 1) return groups == 1 ? task_cfg[0] : single;
+  if (c_split + kLaunchUs * (groups - 1) < 0.95 * c_single) return -1;
+  return single;
+}
+
 template <class T>
 void gemm_tune_table(int device, hipStream_t s, std::vector<double>& out) {
   const Table& t = table_for<T>(device, s);
@@ -264,6 +351,8 @@ template void gemm_autotune<double>(int, hipStream_t);
 template void gemm_autotune<float>(int, hipStream_t);
 template int choose_gemm_cfg<double>(int, hipStream_t, const std::vector<GTask>&);
 template int choose_gemm_cfg<float>(int, hipStream_t, const std::vector<GTask>&);
+template int choose_gemm_cfg_split<double>(int, hipStream_t, const std::vector<GTask>&, std::vector<int>&);
+template int choose_gemm_cfg_split<float>(int, hipStream_t, const std::vector<GTask>&, std::vector<int>&);
 template void gemm_tune_table<double>(int, hipStream_t, std::vector<double>&);
 template void gemm_tune_table<float>(int, hipStream_t, std::vector<double>&);
 

@@ -6,7 +6,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
+#include <cmath>
 #include <cstring>
+#include <deque>
 #include <numeric>
 
 #include "kernels/kernels.hpp"
@@ -474,28 +476,70 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
   HostTimer ht_run(HP_RUN);
   void* bases[4] = {pool, const_cast<void*>(X), Y, ws};
   check_plan(plan, bases, lim);
-  // one upload for all phases: per phase its tasks then its tile starts
+  // launches in phase order: a phase in one tile shape from the autotuned table, or split into
+  // one launch per shape when its tasks differ in height (all shapes give the same result, and
+  // the tasks of a phase are independent, so neither the split nor the order changes it)
+  struct Launch {
+    const GTask* t;
+    size_t n;
+    int cfg;
+  };
+  std::deque<std::vector<GTask>> groups;  // split phases' tasks (a deque keeps them in place)
+  std::vector<Launch> launches;
+  {
+    std::vector<int> task_cfg;
+    for (auto& ph : plan.phase) {
+      if (ph.empty()) continue;
+      const int cfg = choose_gemm_cfg_split<T>(c.device, s, ph, task_cfg);
+      if (cfg >= 0) {
+        launches.push_back(Launch{ph.data(), ph.size(), cfg});
+        continue;
+      }
+      for (int q = 0; q < GEMM_CFGS; ++q) {
+        std::vector<GTask> grp;
+        for (size_t i = 0; i < ph.size(); ++i)
+          if (task_cfg[i] == q) grp.push_back(ph[i]);
+        if (grp.empty()) continue;
+        groups.push_back(std::move(grp));
+        launches.push_back(Launch{groups.back().data(), groups.back().size(), q});
+      }
+    }
+  }
+  // one upload for all launches: per launch its tasks then its tile starts
   std::vector<char> blob;
   std::vector<size_t> toff, soff;
   std::vector<int64_t> ntiles;
-  std::vector<int> cfgs;
-  for (auto& ph : plan.phase) {
-    // tile shape from the autotuned table (all shapes give the same result)
-    const int cfg = ph.empty() ? 0 : choose_gemm_cfg<T>(c.device, s, ph);
-    cfgs.push_back(cfg);
-    std::vector<int64_t> start(ph.size());
+  for (const Launch& ln : launches) {
+    const int cfg = ln.cfg;
+    if (c.verbose && kind == K_BF_GEMM) {
+      const double tm = GEMM_CFG_TM[cfg], tn = GEMM_CFG_TN[cfg];
+      for (size_t i = 0; i < ln.n; ++i) {
+        const GTask& t = ln.t[i];
+        const double M = t.M, N = t.N, K = t.K;
+        const double Mp = std::ceil(M / tm) * tm, Np = std::ceil(N / tn) * tn, Kp = std::ceil(K / 16.0) * 16.0;
+        double* pd = c.timer.pad;
+        pd[0] += M * N * K;
+        pd[1] += Mp * N * K;
+        pd[2] += M * Np * K;
+        pd[3] += M * N * Kp;
+        pd[4] += Mp * Np * Kp;
+        c.timer.mhist[std::min(19, (t.M + 15) / 16)] += M * N * K;
+        c.timer.nhist[std::min(19, (t.N + 15) / 16)] += M * N * K;
+      }
+    }
+    std::vector<int64_t> start(ln.n);
     int64_t tiles = 0;
-    for (size_t i = 0; i < ph.size(); ++i) {
+    for (size_t i = 0; i < ln.n; ++i) {
       start[i] = tiles;
-      tiles += gemm_cfg_tiles(cfg, ph[i].M, ph[i].N);
+      tiles += gemm_cfg_tiles(cfg, ln.t[i].M, ln.t[i].N);
     }
     if (tiles >= ((int64_t)1 << 31)) throw Error(BFMF_E_INVAL, "internal: grouped GEMM launch with 2^31 tiles");
     size_t o = (blob.size() + 15) & ~(size_t)15;
-    blob.resize(o + ph.size() * sizeof(GTask) + start.size() * sizeof(int64_t));
-    if (!ph.empty()) std::memcpy(blob.data() + o, ph.data(), ph.size() * sizeof(GTask));
-    if (!start.empty()) std::memcpy(blob.data() + o + ph.size() * sizeof(GTask), start.data(), start.size() * sizeof(int64_t));
+    blob.resize(o + ln.n * sizeof(GTask) + start.size() * sizeof(int64_t));
+    if (ln.n) std::memcpy(blob.data() + o, ln.t, ln.n * sizeof(GTask));
+    if (!start.empty()) std::memcpy(blob.data() + o + ln.n * sizeof(GTask), start.data(), start.size() * sizeof(int64_t));
     toff.push_back(o);
-    soff.push_back(o + ph.size() * sizeof(GTask));
+    soff.push_back(o + ln.n * sizeof(GTask));
     ntiles.push_back(tiles);
   }
   if (blob.empty()) return;
@@ -503,21 +547,22 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
   if (c.g_tmp_plan.bytes < blob.size()) dev_alloc(c.g_tmp_plan, std::max<size_t>(blob.size() * 2, (size_t)1 << 20));
   char* d = c.g_tmp_plan.as<char>();
   c.stage.put(d, blob.data(), blob.size(), s);
-  for (size_t k = 0; k < plan.phase.size(); ++k) {
-    if (plan.phase[k].empty()) continue;
+  for (size_t k = 0; k < launches.size(); ++k) {
+    const Launch& ln = launches[k];
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const int tk = c.timer.want(kind) ? c.timer.begin_ext(&e0, &e1) : -1;
     {
       HostTimer ht(HP_LAUNCH);
-      chk(launch_grouped_gemm<T>((const GTask*)(d + toff[k]), (const int64_t*)(d + soff[k]),
-                                 (int)plan.phase[k].size(), ntiles[k], bases, cfgs[k], s, e0, e1, kind == K_ID),
+      chk(launch_grouped_gemm<T>((const GTask*)(d + toff[k]), (const int64_t*)(d + soff[k]), (int)ln.n, ntiles[k],
+                                 bases, ln.cfg, s, e0, e1, kind == K_ID),
           "grouped gemm");
     }
-    c.gemm_cfg_launches[cfgs[k]] += 1;
+    c.gemm_cfg_launches[ln.cfg] += 1;
     if (tk >= 0) {
       double fl = 0, by = 0;
       int mm = 0, mn = 0, mk = 0;
-      for (const GTask& t : plan.phase[k]) {
+      for (size_t i = 0; i < ln.n; ++i) {
+        const GTask& t = ln.t[i];
         const double M = t.M, N = t.N, K = t.K;
         fl += 8.0 * M * N * K;
         by += sizeof(cplx<T>) * (M * K + K * N + M * N * (t.beta ? 2.0 : 1.0));
@@ -525,7 +570,7 @@ void run_plan(const BfPlan& plan, Context& c, char* pool, const void* X, void* Y
         mn = std::max(mn, t.N);
         mk = std::max(mk, t.K);
       }
-      c.timer.set_shape(tk, (int)plan.phase[k].size(), mm, mn, mk);
+      c.timer.set_shape(tk, (int)ln.n, mm, mn, mk);
       c.timer.end_ext(tk, kind, fl, by);
     }
   }

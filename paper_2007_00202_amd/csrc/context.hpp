@@ -153,6 +153,10 @@ struct KernelTimer {
   double hist_n[64] = {}, hist_s[64] = {}, hist_f[64] = {};
   // timed butterfly GEMM launches by log2 of (tasks, M, N, K): count, seconds, flops
   std::map<std::array<int, 4>, std::array<double, 3>> shapes;
+  // every butterfly GEMM task (diagnostics, BFMF_VERBOSE): multiply-adds as given, and with M, N, K
+  // padded to the launch's tile (one at a time, then all); multiply-adds by ceil(M/16) and ceil(N/16)
+  double pad[5] = {};
+  double mhist[20] = {}, nhist[20] = {};
   void set_shape(int token, int ntasks, int m, int n, int k) {
     if (token >= 0) recs[token].shape[0] = ntasks, recs[token].shape[1] = m, recs[token].shape[2] = n,
                     recs[token].shape[3] = k;
@@ -241,7 +245,7 @@ struct Context {
 
   // device: matrix and plan
   DevBuf d_rowptr, d_colind, d_values, d_perm;
-  DevBuf d_aptr, d_arow, d_avidx, d_inv, d_iu32, d_piv, d_status;
+  DevBuf d_aptr, d_arow, d_avidx, d_inv, d_iu32, d_piv, d_pperm, d_status;
   DevBuf d_fds;            // FrontDesc per front, in level order (level_fronts order)
   std::vector<FrontDesc> h_fds;
   std::vector<int32_t> desc_index;  // front id -> index in h_fds
@@ -251,7 +255,7 @@ struct Context {
   DevBuf d_fac;            // factors of the dense fronts, kept for the sweeps
   DevBuf d_kept;           // debug copies of assembled fronts
   bfmf_factor_opts fopts{};
-  int64_t gemm_cfg_launches[8] = {};  // grouped-GEMM launches per tile shape (since the last stats reset)
+  int64_t gemm_cfg_launches[16] = {};  // grouped-GEMM launches per tile shape (since the last stats reset)
   bfmf_stats stats{};
 
   // device: solve workspaces
@@ -296,6 +300,9 @@ template <class T>
 void gemm_autotune(int device, hipStream_t s);
 template <class T>
 int choose_gemm_cfg(int device, hipStream_t s, const std::vector<GTask>& ph);
+// one shape for the phase (returned), or -1 with each task's shape in task_cfg
+template <class T>
+int choose_gemm_cfg_split(int device, hipStream_t s, const std::vector<GTask>& ph, std::vector<int>& task_cfg);
 template <class T>
 void gemm_tune_table(int device, hipStream_t s, std::vector<double>& out);
 void set_gemm_tile_override(int cfg);

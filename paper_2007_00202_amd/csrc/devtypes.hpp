@@ -78,6 +78,7 @@ struct FrontDesc {
   const int32_t* a_row;    // local row of each A entry of the column
   const int64_t* a_vidx;   // index of the entry in the CSR value array
   int32_t* piv;            // ns pivots (LAPACK interchange convention, 0-based)
+  int32_t* pperm;          // the interchanges as one permutation: row i of P^T F11 is row pperm[i]
   const int32_t* iu;       // I^u as global new indices (length n - ns)
   void* W;                 // solve workspace (n x nrhs, ld = n)
   const void* cw[2];       // children's solve workspaces (contribution part at row ns_c)

@@ -41,18 +41,6 @@ __device__ __forceinline__ uintptr_t task_addr(int i, int64_t off, void* b0, voi
   return b + (uintptr_t)off * sizeof(cplx<T>);
 }
 
-// Workgroups are handed to the chip's 8 XCDs in turn (block b to XCD b mod 8), each with its own L2. Runs of
-// XCD_RUN consecutive tiles, which mostly belong to one task and share its operand panels, are given to
-// one XCD; the runs still alternate between XCDs, so the load stays balanced. A bijection of
-// [0, nb): blocks past the last whole group of 8 runs keep their own tile.
-constexpr int64_t XCDS = 8, XCD_RUN = 8;
-__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
-  const int64_t full = nb / (XCDS * XCD_RUN) * (XCDS * XCD_RUN);
-  if (b >= full) return b;
-  const int64_t x = b % XCDS, j = b / XCDS;
-  return (x + XCDS * (j / XCD_RUN)) * XCD_RUN + j % XCD_RUN;
-}
-
 template <class T, class C>
 __device__ __forceinline__ void grouped_gemm_run(const GTask* __restrict__ tasks,
                                                  const int64_t* __restrict__ tile_start, int ntasks, void* b0,
@@ -97,12 +85,16 @@ typedef TileCfg<2, 2, 1, 4> Tile32x128;
 typedef TileCfg<2, 2, 4, 1> Tile128x32;
 typedef TileCfg<1, 4, 1, 4> Tile16x256;
 typedef TileCfg<4, 1, 4, 1> Tile256x16;
+typedef TileCfg<3, 2, 1, 4> Tile48x128;
+typedef TileCfg<3, 2, 2, 2> Tile96x64;
 static_assert(Tile64x64::TM == GEMM_CFG_TM[0] && Tile64x64::TN == GEMM_CFG_TN[0], "tile table");
 static_assert(Tile32x128::TM == GEMM_CFG_TM[1] && Tile32x128::TN == GEMM_CFG_TN[1], "tile table");
 static_assert(Tile128x32::TM == GEMM_CFG_TM[2] && Tile128x32::TN == GEMM_CFG_TN[2], "tile table");
 static_assert(Tile16x256::TM == GEMM_CFG_TM[3] && Tile16x256::TN == GEMM_CFG_TN[3], "tile table");
 static_assert(Tile256x16::TM == GEMM_CFG_TM[4] && Tile256x16::TN == GEMM_CFG_TN[4], "tile table");
 static_assert(SKINNY_TM == GEMM_CFG_TM[GEMM_CFG_SKINNY] && SKINNY_TN == GEMM_CFG_TN[GEMM_CFG_SKINNY], "tile table");
+static_assert(Tile48x128::TM == GEMM_CFG_TM[6] && Tile48x128::TN == GEMM_CFG_TN[6], "tile table");
+static_assert(Tile96x64::TM == GEMM_CFG_TM[7] && Tile96x64::TN == GEMM_CFG_TN[7], "tile table");
 
 // phases whose tasks are all C = beta C + alpha A B (no transposes) with N <= 16: 256-row tiles
 template <class T>
@@ -1076,6 +1068,8 @@ hipError_t launch_grouped_gemm(const GTask* d_tasks, const int64_t* d_tile_start
       case 1: go(gram_gemm_kernel<T, Tile32x128>); break;
       case 2: go(gram_gemm_kernel<T, Tile128x32>); break;
       case 3: go(gram_gemm_kernel<T, Tile16x256>); break;
+      case 6: go(gram_gemm_kernel<T, Tile48x128>); break;
+      case 7: go(gram_gemm_kernel<T, Tile96x64>); break;
       default: go(gram_gemm_kernel<T, Tile256x16>); break;
     }
     return hipGetLastError();
@@ -1086,6 +1080,8 @@ hipError_t launch_grouped_gemm(const GTask* d_tasks, const int64_t* d_tile_start
     case 2: go(grouped_gemm_kernel<T, Tile128x32>); break;
     case 3: go(grouped_gemm_kernel<T, Tile16x256>); break;
     case 4: go(grouped_gemm_kernel<T, Tile256x16>); break;
+    case 6: go(grouped_gemm_kernel<T, Tile48x128>); break;
+    case 7: go(grouped_gemm_kernel<T, Tile96x64>); break;
     default: go(grouped_gemm_skinny_kernel<T>); break;
   }
   return hipGetLastError();

@@ -40,6 +40,18 @@ __device__ __forceinline__ T cabs1(cplx<T> a) {
   return fabs(a.re) + fabs(a.im);
 }
 
+// Workgroups are handed to the chip's 8 XCDs in turn (block b to XCD b mod 8), each with its own L2. Runs of
+// XCD_RUN consecutive tiles, which mostly belong to one task and share its operand panels, are given to
+// one XCD; the runs still alternate between XCDs, so the load stays balanced. A bijection of
+// [0, nb): blocks past the last whole group of 8 runs keep their own tile.
+constexpr int64_t XCDS = 8, XCD_RUN = 8;
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
+  const int64_t full = nb / (XCDS * XCD_RUN) * (XCDS * XCD_RUN);
+  if (b >= full) return b;
+  const int64_t x = b % XCDS, j = b / XCDS;
+  return (x + XCDS * (j / XCD_RUN)) * XCD_RUN + j % XCD_RUN;
+}
+
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 

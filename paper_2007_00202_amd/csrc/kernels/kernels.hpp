@@ -49,6 +49,8 @@ template <class T>
 hipError_t launch_forward_level(const FrontDesc* d_fds, int nbatch, int maxn, int maxnu, int maxns, const void* y,
                                 int64_t N, int nrhs, hipStream_t s);
 // Backward sweep over the fronts of one level (ancestors done before).
+// the pivot interchanges of every dense front as one permutation (FrontDesc::pperm), for the sweeps
+hipError_t launch_pivot_perm(const FrontDesc* d_fds, int nfront, hipStream_t s);
 template <class T>
 hipError_t launch_backward_level(const FrontDesc* d_fds, int nbatch, int maxn, int maxnu, int maxns, void* x,
                                  int64_t N, int nrhs, hipStream_t s);
@@ -91,12 +93,15 @@ hipError_t launch_basis_update_masked(const void* y, int ldy, const int32_t* d_m
 
 // ---- butterfly support (bf.hip)
 // Tile shapes of the grouped GEMM (rows x columns of C per 256-thread
-// workgroup).  0..4 stage A and B through LDS; 5 is the skinny shape (no LDS,
-// only for tasks with N <= 16 and no transposes).  All give identical results.
-constexpr int GEMM_CFGS = 6;
+// workgroup).  0..4, 6 and 7 stage A and B through LDS; 5 is the skinny shape
+// (no LDS, only for tasks with N <= 16 and no transposes).  The 48- and
+// 96-row shapes fit the ranks of butterfly blocks (tasks of 33..48 and
+// 65..96 rows) that the 32/64/128-row shapes pad by up to a half.  All give
+// identical results.
+constexpr int GEMM_CFGS = 8;
 constexpr int GEMM_CFG_SKINNY = 5;
-constexpr int GEMM_CFG_TM[GEMM_CFGS] = {64, 32, 128, 16, 256, 256};
-constexpr int GEMM_CFG_TN[GEMM_CFGS] = {64, 128, 32, 256, 16, 16};
+constexpr int GEMM_CFG_TM[GEMM_CFGS] = {64, 32, 128, 16, 256, 256, 48, 96};
+constexpr int GEMM_CFG_TN[GEMM_CFGS] = {64, 128, 32, 256, 16, 16, 128, 64};
 inline int64_t gemm_cfg_tiles(int cfg, int M, int N) {
   if (M <= 0 || N <= 0) return 0;
   return (int64_t)((M + GEMM_CFG_TM[cfg] - 1) / GEMM_CFG_TM[cfg]) * ((N + GEMM_CFG_TN[cfg] - 1) / GEMM_CFG_TN[cfg]);

@@ -258,6 +258,244 @@ __global__ __launch_bounds__(256) void bwd_trsv_reg_kernel(const FrontDesc* __re
 }
 
 
+// ------------------------------------------------------------ blocked sweeps
+// The dense fronts' substitutions on the matrix cores.  A workgroup takes
+// BLK_RC right-hand sides of one front and keeps W_f(0:ns, those columns) in
+// the accumulators of its four waves: row block b (16 rows) in wave b % 4,
+// slot b / 4, in the f64 16x16x4 result layout (lane l, item r: row
+// l/16 + 4r, column l%16).  Diagonal block by diagonal block of F11, the
+// owner wave solves its 16 x 16 triangle in registers (the triangle staged
+// in LDS, each solved row broadcast to the lanes of its columns by
+// shuffles) and publishes the 16 solved rows through LDS; then every wave
+// subtracts the product of the panel of L below (U above) the block with
+// them from its own row blocks (f64 MFMA, the panel read once per
+// workgroup).  Two barriers per 16 columns.  Workgroups of one front are
+// adjacent in the XCD order, so the other column groups find the panels in
+// the same L2.
+constexpr int BLK_RC = 16;
+constexpr int BLK_MAXNS = 512;    // 8 row blocks per wave (16 would spill registers)
+constexpr int PERM_MAXNS = 4096;  // pivot permutations built in LDS
+
+// LDS entries that other lanes of the same wave read without a barrier in
+// between (the triangle solves): volatile, so that every store is performed
+// in program order and no value is forwarded in registers (one wave's LDS
+// operations complete in order)
+__device__ __forceinline__ cplx<double> vld(const volatile cplx<double>* p) { return cplx<double>{p->re, p->im}; }
+__device__ __forceinline__ void vst(volatile cplx<double>* p, cplx<double> v) {
+  p->re = v.re;
+  p->im = v.im;
+}
+
+// one product step Y_b -= A Y_jb on 16 x 16 blocks: A from F (rows gi, columns
+// 16 jb + 4q + lr), Y_jb from LDS
+__device__ __forceinline__ void blk_update(d4_t& yr, d4_t& yi, const cplx<double>* __restrict__ F, int64_t n,
+                                           int gi, int jb, int ns, int lr, int col,
+                                           const cplx<double> (*Ys)[17]) {
+  cplx<double> a[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int gk = 16 * jb + 4 * q + lr;
+    const bool ok = gi < ns && gk < ns;
+    a[q] = load_or_zero(F + (ok ? gi : 0) + (int64_t)(ok ? gk : 0) * n, ok);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const cplx<double> bv = Ys[4 * q + lr][col];
+    // the real and imaginary chains alternate, so consecutive MFMAs are independent
+    yr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[q].re, bv.re, yr, 0, 0, 0);
+    yi = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[q].re, bv.im, yi, 0, 0, 0);
+    yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q].im, bv.im, yr, 0, 0, 0);
+    yi = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[q].im, bv.re, yi, 0, 0, 0);
+  }
+}
+
+// W_f(0:ns) <- L^-1 P^T W_f(0:ns) for fronts with ns <= 64 MB
+template <int MB>
+__global__ __launch_bounds__(256) void fwd_trsv_blk_kernel(const FrontDesc* __restrict__ fds, int nfront, int nrhs) {
+  __shared__ cplx<double> Ls[2][16][17];  // Ls[buf][k][i] = L(16 jb + i, 16 jb + k), strictly lower
+  __shared__ cplx<double> Ys[2][16][17];  // Ys[buf][k][c] = Y(16 jb + k, c)
+  const int ngrp = (nrhs + BLK_RC - 1) / BLK_RC;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int fi = (int)(tile / ngrp), grp = (int)(tile % ngrp);
+  if (fi >= nfront) return;
+  const FrontDesc& fd = fds[fi];
+  const int n = fd.n, ns = fd.ns;
+  if (ns == 0 || ns > 64 * MB) return;  // uniform; the host never sends these
+  const int c0 = grp * BLK_RC, ncl = min(BLK_RC, nrhs - c0);
+  const cplx<double>* F = (const cplx<double>*)fd.P;  // [L U; F21'], ld n
+  cplx<double>* W = (cplx<double>*)fd.W + (int64_t)c0 * n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, lr = lane >> 4;
+  const int nb = (ns + 15) / 16;
+  d4_t yr[MB], yi[MB];
+#pragma unroll
+  for (int s = 0; s < MB; ++s)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * (4 * s + wave) + lr + 4 * r;
+      const bool ok = row < ns && col < ncl;
+      const cplx<double> v = load_or_zero(W + (ok ? fd.pperm[row] + (int64_t)col * n : 0), ok);
+      yr[s][r] = v.re;
+      yi[s][r] = v.im;
+    }
+  __syncthreads();  // every row is read (through the permutation) before any is written
+  for (int jb = 0; jb < nb; ++jb) {
+    const int buf = jb & 1, sj = jb >> 2;
+    {
+      const int i = tid & 15, k = tid >> 4, gi = 16 * jb + i, gk = 16 * jb + k;
+      const bool ok = i > k && gi < ns;
+      Ls[buf][k][i] = load_or_zero(F + (ok ? gi + (int64_t)gk * n : 0), ok);
+    }
+    __syncthreads();
+    if (wave == (jb & 3)) {  // the owner: block jb to LDS, its triangle there, then out to W
+      volatile cplx<double>(*V)[17] = Ys[buf];
+#pragma unroll
+      for (int s = 0; s < MB; ++s)
+        if (s == sj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) vst(&V[lr + 4 * r][col], cplx<double>{yr[s][r], yi[s][r]});
+#pragma unroll
+      for (int k = 0; k < 15; ++k) {
+        const cplx<double> yk = vld(&V[k][col]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = lr + 4 * r;
+          if (i > k) vst(&V[i][col], csub(vld(&V[i][col]), cmul(Ls[buf][k][i], yk)));
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * jb + lr + 4 * r;
+        if (row < ns && col < ncl) W[row + (int64_t)col * n] = vld(&V[lr + 4 * r][col]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < MB; ++s2) {
+      const int b2 = 4 * s2 + wave;
+      if (b2 > jb && b2 < nb) blk_update(yr[s2], yi[s2], F, n, 16 * b2 + col, jb, ns, lr, col, Ys[buf]);
+    }
+  }
+}
+
+// x(I^s) <- U^-1 W_f(0:ns) for fronts with ns <= 64 MB (W_f(0:ns) already holds W - F12 x(I^u))
+template <int MB>
+__global__ __launch_bounds__(256) void bwd_trsv_blk_kernel(const FrontDesc* __restrict__ fds, int nfront,
+                                                           cplx<double>* __restrict__ x, int64_t N, int nrhs) {
+  __shared__ cplx<double> Us[2][16][17];  // Us[buf][k][i] = U(16 jb + i, 16 jb + k), upper with the diagonal
+  __shared__ cplx<double> Ys[2][16][17];
+  const int ngrp = (nrhs + BLK_RC - 1) / BLK_RC;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int fi = (int)(tile / ngrp), grp = (int)(tile % ngrp);
+  if (fi >= nfront) return;
+  const FrontDesc& fd = fds[fi];
+  const int n = fd.n, ns = fd.ns;
+  if (ns == 0 || ns > 64 * MB) return;  // uniform; the host never sends these
+  const int c0 = grp * BLK_RC, ncl = min(BLK_RC, nrhs - c0);
+  const cplx<double>* F = (const cplx<double>*)fd.P;
+  const cplx<double>* W = (const cplx<double>*)fd.W + (int64_t)c0 * n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, lr = lane >> 4;
+  const int nb = (ns + 15) / 16;
+  d4_t yr[MB], yi[MB];
+#pragma unroll
+  for (int s = 0; s < MB; ++s)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * (4 * s + wave) + lr + 4 * r;
+      const bool ok = row < ns && col < ncl;
+      const cplx<double> v = load_or_zero(W + (ok ? row + (int64_t)col * n : 0), ok);
+      yr[s][r] = v.re;
+      yi[s][r] = v.im;
+    }
+  for (int jb = nb - 1; jb >= 0; --jb) {
+    const int buf = jb & 1, sj = jb >> 2;
+    {
+      const int i = tid & 15, k = tid >> 4, gi = 16 * jb + i, gk = 16 * jb + k;
+      const bool ok = i <= k && gk < ns;
+      Us[buf][k][i] = load_or_zero(F + (ok ? gi + (int64_t)gk * n : 0), ok);
+    }
+    __syncthreads();
+    if (wave == (jb & 3)) {
+      volatile cplx<double>(*V)[17] = Ys[buf];
+#pragma unroll
+      for (int s = 0; s < MB; ++s)
+        if (s == sj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) vst(&V[lr + 4 * r][col], cplx<double>{yr[s][r], yi[s][r]});
+      const int kmax = min(16, ns - 16 * jb);  // rows of the block inside the front
+#pragma unroll
+      for (int k = 15; k >= 0; --k) {
+        if (k < kmax) {  // uniform
+          if (lr == (k & 3)) vst(&V[k][col], cdiv(vld(&V[k][col]), Us[buf][k][k]));
+          const cplx<double> yk = vld(&V[k][col]);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = lr + 4 * r;
+            if (i < k) vst(&V[i][col], csub(vld(&V[i][col]), cmul(Us[buf][k][i], yk)));
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * jb + lr + 4 * r;
+        if (row < ns && col < ncl) x[fd.sbeg + row + (int64_t)(c0 + col) * N] = vld(&V[lr + 4 * r][col]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < MB; ++s2) {
+      const int b2 = 4 * s2 + wave;
+      if (b2 < jb) blk_update(yr[s2], yi[s2], F, n, 16 * b2 + col, jb, ns, lr, col, Ys[buf]);
+    }
+  }
+}
+
+// The interchanges of F11's partial pivoting (row k swapped with piv[k], k
+// ascending) as one permutation, applied to an index vector: pperm[i] is the
+// row of F11 that ends up at position i.  One workgroup per dense front.
+__global__ __launch_bounds__(256) void pivot_perm_kernel(const FrontDesc* __restrict__ fds, int nfront) {
+  __shared__ int32_t idx[PERM_MAXNS];
+  const FrontDesc& fd = fds[blockIdx.x];
+  const int ns = fd.ns;
+  if (!fd.P || ns == 0 || ns > PERM_MAXNS) return;  // compressed fronts and the largest dense ones
+  for (int i = threadIdx.x; i < ns; i += 256) idx[i] = i;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < ns; ++k) {
+      const int p = fd.piv[k];
+      if (p != k && p >= 0 && p < ns) {
+        const int t = idx[k];
+        idx[k] = idx[p];
+        idx[p] = t;
+      }
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ns; i += 256) fd.pperm[i] = idx[i];
+}
+
+// the sweep products (W(ns:n) -= F21 W(0:ns), W(0:ns) -= F12 W(ns:n)) in a tile shape of the grouped GEMM
+template <class C>
+__global__ __launch_bounds__(256) void sweep_gemm_cfg_kernel(const FrontDesc* __restrict__ fds, int nrhs, int mode) {
+  __shared__ TileSmem<double, C> sm;
+  const FrontDesc& fd = fds[blockIdx.y];
+  const int n = fd.n, ns = fd.ns, nu = n - ns;
+  if (ns == 0 || nu == 0) return;
+  const cplx<double>* F = (const cplx<double>*)fd.P;
+  cplx<double>* W = (cplx<double>*)fd.W;
+  const int M = mode == 0 ? nu : ns;
+  const int tm = (M + C::TM - 1) / C::TM, tn = (nrhs + C::TN - 1) / C::TN;
+  const int t = blockIdx.x;
+  if (t >= tm * tn) return;
+  if (mode == 0)
+    gemm_tile_cfg<double, C>(F + ns, n, OP_N, W, n, OP_N, W + ns, n, nu, nrhs, ns, cplx<double>{-1, 0}, 1, t % tm,
+                             t / tm, sm);
+  else
+    gemm_tile_cfg<double, C>((const cplx<double>*)fd.F12, fd.ld12, OP_N, W + ns, n, OP_N, W, n, ns, nrhs, nu,
+                             cplx<double>{-1, 0}, 1, t % tm, t / tm, sm);
+}
+typedef TileCfg<2, 2, 4, 1> SweepTile128x32;
+
 // Upper substitution on W_f(0:ns, :) and scatter of the result into x.
 template <class T>
 __global__ __launch_bounds__(256) void bwd_trsv_kernel(const FrontDesc* __restrict__ fds, cplx<T>* __restrict__ x,
@@ -536,15 +774,29 @@ hipError_t launch_forward_level(const FrontDesc* d_fds, int nbatch, int maxn, in
   hipLaunchKernelGGL((fwd_gather_kernel<T>), dim3(blocks_for(maxn, 256), nbatch), dim3(256), 0, s, d_fds,
                      (const cplx<T>*)y, N, nrhs);
   KCHECK(hipGetLastError());
-  if (sizeof(T) == 8 && maxns > 0 && maxns <= TRSV_MAXNS)  // LDS for the interchanges sized to the level
+  if (sizeof(T) == 8 && maxns > 0 && maxns <= BLK_MAXNS) {
+    const dim3 grid((unsigned)((int64_t)nbatch * ((nrhs + BLK_RC - 1) / BLK_RC)));
+    if (maxns <= 64)
+      hipLaunchKernelGGL((fwd_trsv_blk_kernel<1>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs);
+    else if (maxns <= 128)
+      hipLaunchKernelGGL((fwd_trsv_blk_kernel<2>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs);
+    else if (maxns <= 256)
+      hipLaunchKernelGGL((fwd_trsv_blk_kernel<4>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs);
+    else
+      hipLaunchKernelGGL((fwd_trsv_blk_kernel<8>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs);
+  } else if (sizeof(T) == 8 && maxns > 0 && maxns <= TRSV_MAXNS) {  // LDS for the interchanges sized to the level
     hipLaunchKernelGGL((fwd_trsv_reg_kernel<T>), dim3(nbatch, (nrhs + TRSV_RC - 1) / TRSV_RC), dim3(256),
                        (size_t)maxns * TRSV_RC * sizeof(cplx<T>), s, d_fds, nrhs);
-  else
+  } else {
     hipLaunchKernelGGL((fwd_trsv_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, nrhs);
+  }
   KCHECK(hipGetLastError());
   if (nrhs <= SKINNY_TN) {
     hipLaunchKernelGGL((sweep_gemm_skinny_kernel<T>), dim3((unsigned)blocks_for(maxn, sweep_skinny_tm<T>()), nbatch), dim3(256), 0,
                        s, d_fds, nrhs, 0);
+  } else if (sizeof(T) == 8 && nrhs <= SweepTile128x32::TN) {
+    const int tiles = (int)(blocks_for(maxn, SweepTile128x32::TM) * blocks_for(nrhs, SweepTile128x32::TN));
+    hipLaunchKernelGGL((sweep_gemm_cfg_kernel<SweepTile128x32>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs, 0);
   } else {
     const int tiles = (int)(blocks_for(maxn, GEMM_TM) * blocks_for(nrhs, GEMM_TN));
     hipLaunchKernelGGL((sweep_gemm_kernel<T>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs, 0);
@@ -563,17 +815,39 @@ hipError_t launch_backward_level(const FrontDesc* d_fds, int nbatch, int maxn, i
     if (nrhs <= SKINNY_TN) {
       hipLaunchKernelGGL((sweep_gemm_skinny_kernel<T>), dim3((unsigned)blocks_for(maxn, sweep_skinny_tm<T>()), nbatch), dim3(256),
                          0, s, d_fds, nrhs, 1);
+    } else if (sizeof(T) == 8 && nrhs <= SweepTile128x32::TN) {
+      const int tiles = (int)(blocks_for(maxn, SweepTile128x32::TM) * blocks_for(nrhs, SweepTile128x32::TN));
+      hipLaunchKernelGGL((sweep_gemm_cfg_kernel<SweepTile128x32>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs,
+                         1);
     } else {
       const int tiles = (int)(blocks_for(maxn, GEMM_TM) * blocks_for(nrhs, GEMM_TN));
       hipLaunchKernelGGL((sweep_gemm_kernel<T>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs, 1);
     }
     KCHECK(hipGetLastError());
   }
-  if (sizeof(T) == 8 && maxns > 0 && maxns <= TRSV_MAXNS)
+  if (sizeof(T) == 8 && maxns > 0 && maxns <= BLK_MAXNS) {
+    const dim3 grid((unsigned)((int64_t)nbatch * ((nrhs + BLK_RC - 1) / BLK_RC)));
+    cplx<double>* xd = (cplx<double>*)x;
+    if (maxns <= 64)
+      hipLaunchKernelGGL((bwd_trsv_blk_kernel<1>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs);
+    else if (maxns <= 128)
+      hipLaunchKernelGGL((bwd_trsv_blk_kernel<2>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs);
+    else if (maxns <= 256)
+      hipLaunchKernelGGL((bwd_trsv_blk_kernel<4>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs);
+    else
+      hipLaunchKernelGGL((bwd_trsv_blk_kernel<8>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs);
+  } else if (sizeof(T) == 8 && maxns > 0 && maxns <= TRSV_MAXNS) {
     hipLaunchKernelGGL((bwd_trsv_reg_kernel<T>), dim3(nbatch, (nrhs + TRSV_RC - 1) / TRSV_RC), dim3(256), 0, s,
                        d_fds, (cplx<T>*)x, N, nrhs);
-  else
+  } else {
     hipLaunchKernelGGL((bwd_trsv_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, (cplx<T>*)x, N, nrhs);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pivot_perm(const FrontDesc* d_fds, int nfront, hipStream_t s) {
+  if (nfront == 0) return hipSuccess;
+  hipLaunchKernelGGL(pivot_perm_kernel, dim3(nfront), dim3(256), 0, s, d_fds, nfront);
   return hipGetLastError();
 }
 

@@ -132,6 +132,8 @@ void KernelTimer::reset() {
     seconds[k] = flops[k] = bytes[k] = 0;
   }
   for (int b = 0; b < 64; ++b) hist_n[b] = hist_s[b] = hist_f[b] = 0;
+  for (double& x : pad) x = 0;
+  for (int b = 0; b < 20; ++b) mhist[b] = nhist[b] = 0;
   shapes.clear();
 }
 
@@ -274,6 +276,7 @@ void factor_dense(Context& c) {
     d.a_row = c.d_arow.as<int32_t>();
     d.a_vidx = c.d_avidx.as<int64_t>();
     d.piv = c.d_piv.as<int32_t>() + p.piv_off;
+    d.pperm = c.d_pperm.as<int32_t>() + p.piv_off;
     d.iu = c.d_iu32.as<int32_t>() + p.iu_off;
   }
   if (c.d_fds.bytes < nf * sizeof(FrontDesc)) alloc(c.d_fds, nf * sizeof(FrontDesc));
@@ -377,6 +380,8 @@ void factor_dense(Context& c) {
       }
     }
   }
+  // the dense fronts' row interchanges as permutations, read by the blocked sweeps
+  check(launch_pivot_perm(dfds, nf, c.stream), "pivot permutation");
   HIPCHK(hipStreamSynchronize(c.stream));
   c.stats.factor_seconds = now() - t0;
   if (c.verbose) {
@@ -402,6 +407,15 @@ void factor_dense(Context& c) {
     std::vector<std::pair<double, std::array<int, 4>>> top;
     for (auto& kv : c.timer.shapes) top.push_back({kv.second[1], kv.first});
     std::sort(top.rbegin(), top.rend());
+    const double* pd = c.timer.pad;
+    if (pd[0] > 0) {
+      fprintf(stderr,
+              "[bfmf] butterfly GEMM padding to the tile (all launches): M %.3f N %.3f K %.3f all %.3f\n",
+              pd[1] / pd[0], pd[2] / pd[0], pd[3] / pd[0], pd[4] / pd[0]);
+      fprintf(stderr, "[bfmf] butterfly GEMM work by ceil(M/16), ceil(N/16) (share of multiply-adds):\n[bfmf]  ");
+      for (int b = 1; b < 20; ++b) fprintf(stderr, " %d:%.3f/%.3f", b, c.timer.mhist[b] / pd[0], c.timer.nhist[b] / pd[0]);
+      fprintf(stderr, "\n");
+    }
     fprintf(stderr, "[bfmf] butterfly GEMM launch classes by time (log2 of tasks, max M, N, K): count ms TFLOP/s\n");
     for (size_t q = 0; q < std::min<size_t>(top.size(), 25); ++q) {
       const auto& v = c.timer.shapes[top[q].second];

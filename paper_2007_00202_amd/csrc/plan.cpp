@@ -146,6 +146,9 @@ void upload_plan(Context& c) {
   c.d_piv.release();
   HIPCHK(dev_malloc((void**)&c.d_piv.p, std::max<int64_t>(npiv, 4) * sizeof(int32_t)));
   c.d_piv.bytes = std::max<int64_t>(npiv, 4) * sizeof(int32_t);
+  c.d_pperm.release();
+  HIPCHK(dev_malloc((void**)&c.d_pperm.p, std::max<int64_t>(npiv, 4) * sizeof(int32_t)));
+  c.d_pperm.bytes = std::max<int64_t>(npiv, 4) * sizeof(int32_t);
   c.d_status.release();
   HIPCHK(dev_malloc((void**)&c.d_status.p, 16));
   c.d_status.bytes = 16;
@@ -218,7 +221,7 @@ Context::~Context() {
 uint64_t Context::device_bytes() const {
   uint64_t t = 0;
   for (const DevBuf* b : {&d_rowptr, &d_colind, &d_values, &d_perm, &d_aptr, &d_arow, &d_avidx, &d_inv, &d_iu32,
-                          &d_piv, &d_status, &d_fds, &d_work, &d_fac, &d_kept, &d_W, &d_y, &d_x, &g_B, &g_X, &g_V, &g_w, &g_tmp_scatter,
+                          &d_piv, &d_pperm, &d_status, &d_fds, &d_work, &d_fac, &d_kept, &d_W, &d_y, &d_x, &g_B, &g_X, &g_V, &g_w, &g_tmp_scatter,
                           &g_r, &g_scal, &g_part, &g_tmp})
     t += b->bytes;
   t += stage.cap;  // pinned host ring (counted with the handle's memory)

@@ -94,8 +94,8 @@ def test_rectangular_and_many_rhs(gpu_lib):
 
 
 def test_every_gemm_tile_shape_gives_the_same_result(gpu_lib):
-    """The grouped GEMM behind every butterfly product runs in one of six tile
-    shapes (autotuned per launch); each adds the products of an entry in the
+    """The grouped GEMM behind every butterfly product runs in one of eight tile
+    shapes (autotuned per launch, phases split by task height); each adds the products of an entry in the
     same order, so forcing any shape reproduces the autotuned result bit for
     bit: for applies of K and K^H with 1, 16 and 130 right-hand sides, and for
     a construction by randomized products."""
@@ -105,7 +105,7 @@ def test_every_gemm_tile_shape_gives_the_same_result(gpu_lib):
          for nr in (1, 16, 130)}
     ref, ref_d = None, None
     try:
-        for cfg in [-1, 0, 1, 2, 3, 4, 5]:
+        for cfg in [-1, 0, 1, 2, 3, 4, 5, 6, 7]:
             gpu_lib.bfmf_set_gemm_tile(cfg)
             b, shape = gpu_lib.bfmf_bf_compress_dense(K, 3, 1e-6, method=1, seed=5)
             try:
@@ -124,7 +124,7 @@ def test_every_gemm_tile_shape_gives_the_same_result(gpu_lib):
     finally:
         gpu_lib.bfmf_set_gemm_tile(-1)
     with pytest.raises(gpu_lib.BfmfError):
-        gpu_lib.bfmf_set_gemm_tile(6)
+        gpu_lib.bfmf_set_gemm_tile(8)
 
 
 @pytest.mark.parametrize("method", [0, 1])

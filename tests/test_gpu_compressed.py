@@ -132,7 +132,8 @@ def test_autotuned_tiles_match_a_fixed_tile(gpu_lib, precision):
         gpu_lib.bfmf_set_gemm_tile(-1)
     assert np.array_equal(out[0], out[1])
     assert sum(used[1].values()) == used[1]["64x64"] > 0
-    assert sum(used[0].values()) == sum(used[1].values())
+    # the autotuned run may split a phase into one launch per shape
+    assert sum(used[0].values()) >= sum(used[1].values())
 
 
 @pytest.mark.parametrize("precision,n_min", [("c128", 60), ("c64", 60), ("c64", 120)])
