@@ -88,176 +88,6 @@ __global__ __launch_bounds__(256) void fwd_trsv_kernel(const FrontDesc* __restri
   }
 }
 
-// ------------------------------------------------------------ register sweeps
-// The same substitutions with the right-hand sides in registers: a workgroup
-// takes TRSV_RC columns of one front (ns <= TRSV_MAXNS); thread t owns rows
-// t + 256 q (q < 4) of every column.  Step j: the owner of row j publishes its
-// final value (backward: divided by U_jj) through a double-buffered LDS slot,
-// one barrier, and every thread updates its rows with column j of L (U), which
-// is prefetched from HBM TRSV_D steps ahead into a ring indexed by j mod TRSV_D.
-// Columns run in aligned groups of TRSV_D inside 256-column segments, so the
-// owner's register row is a compile-time index.  Every arithmetic operation is
-// the column-sweep's, in the same order.
-constexpr int TRSV_MAXNS = 1024;
-constexpr int TRSV_RC = 4;  // right-hand sides per workgroup
-constexpr int TRSV_D = 4;   // prefetch depth (columns)
-
-template <class T>
-__global__ __launch_bounds__(256) void fwd_trsv_reg_kernel(const FrontDesc* __restrict__ fds, int nrhs) {
-  const FrontDesc& fd = fds[blockIdx.x];
-  const int n = fd.n, ns = fd.ns;
-  const int c0 = blockIdx.y * TRSV_RC, ncl = min(TRSV_RC, nrhs - c0);
-  if (ns == 0 || ncl <= 0 || ns > TRSV_MAXNS) return;  // the host never sends these
-  extern __shared__ __align__(16) unsigned char trsv_smem[];
-  cplx<T>* wl = (cplx<T>*)trsv_smem;  // the block in LDS for the row interchanges: wl[r + c ns]
-  __shared__ cplx<T> xs[2][TRSV_RC];
-  const cplx<T>* F = (const cplx<T>*)fd.P;  // [L U; F21'], ld n
-  cplx<T>* W = (cplx<T>*)fd.W + (int64_t)c0 * n;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < ns * ncl; e += 256) wl[e] = W[e % ns + (int64_t)(e / ns) * n];
-  __syncthreads();
-  if (tid < ncl)  // row interchanges, in order, one thread per column
-    for (int k = 0; k < ns; ++k) {
-      const int p = fd.piv[k];
-      if (p != k) {
-        const cplx<T> t = wl[k + tid * ns];
-        wl[k + tid * ns] = wl[p + tid * ns];
-        wl[p + tid * ns] = t;
-      }
-    }
-  __syncthreads();
-  cplx<T> w[4][TRSV_RC];
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int c = 0; c < TRSV_RC; ++c) {
-      const int r = tid + 256 * q;
-      w[q][c] = (r < ns && c < ncl) ? wl[r + c * ns] : cplx<T>{0, 0};
-    }
-  cplx<T> ring[TRSV_D][4];  // ring[j % D]: column j of L, this thread's rows
-  auto fetch = [&](cplx<T>(&cc)[4], int j) {
-    const int jj = j < ns ? j : 0;  // addresses stay inside the front
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = tid + 256 * q;
-      const bool ok = j < ns && r > j && r < ns;
-      cc[q] = load_or_zero(F + (ok ? r : 0) + (int64_t)jj * n, ok);
-    }
-  };
-#pragma unroll
-  for (int u = 0; u < TRSV_D; ++u) fetch(ring[u], u);
-#pragma unroll
-  for (int qs = 0; qs < 4; ++qs) {  // segment of columns [256 qs, 256 qs + 256): row j is w[qs] of thread j - 256 qs
-    const int jend = min(ns - 1, 256 * (qs + 1));
-    for (int g = 256 * qs; g < jend; g += TRSV_D) {
-#pragma unroll
-      for (int u = 0; u < TRSV_D; ++u) {
-        const int j = g + u;
-        if (j < jend) {  // uniform across the workgroup
-          const int buf = j & 1;
-          if (tid == j - 256 * qs)
-#pragma unroll
-            for (int c = 0; c < TRSV_RC; ++c) xs[buf][c] = w[qs][c];
-          __syncthreads();
-#pragma unroll
-          for (int c = 0; c < TRSV_RC; ++c) {
-            const cplx<T> wj = xs[buf][c];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int r = tid + 256 * q;
-              if (r > j && r < ns) w[q][c] = csub(w[q][c], cmul(ring[u][q], wj));
-            }
-          }
-          fetch(ring[u], j + TRSV_D);
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int c = 0; c < TRSV_RC; ++c) {
-      const int r = tid + 256 * q;
-      if (r < ns && c < ncl) W[r + (int64_t)c * n] = w[q][c];
-    }
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void bwd_trsv_reg_kernel(const FrontDesc* __restrict__ fds, cplx<T>* __restrict__ x,
-                                                           int64_t N, int nrhs) {
-  const FrontDesc& fd = fds[blockIdx.x];
-  const int n = fd.n, ns = fd.ns;
-  const int c0 = blockIdx.y * TRSV_RC, ncl = min(TRSV_RC, nrhs - c0);
-  if (ns == 0 || ncl <= 0 || ns > TRSV_MAXNS) return;  // the host never sends these
-  __shared__ cplx<T> xs[2][TRSV_RC];
-  const cplx<T>* F = (const cplx<T>*)fd.P;  // [L U; F21'], ld n
-  const cplx<T>* W = (const cplx<T>*)fd.W + (int64_t)c0 * n;
-  const int tid = threadIdx.x;
-  cplx<T> w[4][TRSV_RC];  // unscaled: x_r = w_r / U_rr is formed when written out
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int c = 0; c < TRSV_RC; ++c) {
-      const int r = tid + 256 * q;
-      w[q][c] = (r < ns && c < ncl) ? W[r + (int64_t)c * n] : cplx<T>{0, 0};
-    }
-  cplx<T> ring[TRSV_D][4], dg[TRSV_D];  // ring[j % D]: column j of U above the diagonal, dg: U_jj
-  auto fetch = [&](cplx<T>(&cc)[4], cplx<T>& d, int j) {
-    const int jj = j >= 0 ? j : 0;  // addresses stay inside the front
-    d = load_or_zero(F + jj + (int64_t)jj * n, j >= 0);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = tid + 256 * q;
-      const bool ok = j >= 0 && r < j;
-      cc[q] = load_or_zero(F + (ok ? r : 0) + (int64_t)jj * n, ok);
-    }
-  };
-  // groups of TRSV_D columns aligned to multiples of TRSV_D, from the top group down; slot j % D
-  const int gtop = (ns - 1) / TRSV_D * TRSV_D;
-#pragma unroll
-  for (int u = 0; u < TRSV_D; ++u) {
-    int j = gtop + u;
-    if (j >= ns) j -= TRSV_D;  // the top group is partial: the slot starts one group lower
-    fetch(ring[u], dg[u], j);
-  }
-#pragma unroll
-  for (int qs = 3; qs >= 0; --qs) {  // segment [256 qs, 256 qs + 256): row j is w[qs] of thread j - 256 qs
-    if (256 * qs >= ns) continue;    // uniform
-    const int gfirst = min(gtop, 256 * qs + 256 - TRSV_D);
-    for (int g = gfirst; g >= 256 * qs; g -= TRSV_D) {
-#pragma unroll
-      for (int uu = TRSV_D - 1; uu >= 0; --uu) {
-        const int j = g + uu;
-        if (j < ns) {  // uniform across the workgroup
-          const int buf = j & 1;
-          if (tid == j - 256 * qs)
-#pragma unroll
-            for (int c = 0; c < TRSV_RC; ++c) xs[buf][c] = cdiv(w[qs][c], dg[uu]);
-          __syncthreads();
-#pragma unroll
-          for (int c = 0; c < TRSV_RC; ++c) {
-            const cplx<T> xj = xs[buf][c];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int r = tid + 256 * q;
-              if (r < j) w[q][c] = csub(w[q][c], cmul(ring[uu][q], xj));
-            }
-          }
-          fetch(ring[uu], dg[uu], j - TRSV_D);
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int c = 0; c < TRSV_RC; ++c) {
-      const int r = tid + 256 * q;
-      if (r < ns && c < ncl) x[fd.sbeg + r + (int64_t)(c0 + c) * N] = cdiv(w[q][c], F[r + (int64_t)r * n]);
-    }
-}
-
-
 // ------------------------------------------------------------ blocked sweeps
 // The dense fronts' substitutions on the matrix cores.  A workgroup takes
 // BLK_RC right-hand sides of one front and keeps W_f(0:ns, those columns) in
@@ -273,7 +103,7 @@ __global__ __launch_bounds__(256) void bwd_trsv_reg_kernel(const FrontDesc* __re
 // adjacent in the XCD order, so the other column groups find the panels in
 // the same L2.
 constexpr int BLK_RC = 16;
-constexpr int BLK_MAXNS = 512;    // 8 row blocks per wave (16 would spill registers)
+constexpr int BLK_MAXNS = 1024;   // up to 16 row blocks per wave
 constexpr int PERM_MAXNS = 4096;  // pivot permutations built in LDS
 
 // LDS entries that other lanes of the same wave read without a barrier in
@@ -782,12 +612,11 @@ hipError_t launch_forward_level(const FrontDesc* d_fds, int nbatch, int maxn, in
       hipLaunchKernelGGL((fwd_trsv_blk_kernel<2>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs);
     else if (maxns <= 256)
       hipLaunchKernelGGL((fwd_trsv_blk_kernel<4>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs);
-    else
+    else if (maxns <= 512)
       hipLaunchKernelGGL((fwd_trsv_blk_kernel<8>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs);
-  } else if (sizeof(T) == 8 && maxns > 0 && maxns <= TRSV_MAXNS) {  // LDS for the interchanges sized to the level
-    hipLaunchKernelGGL((fwd_trsv_reg_kernel<T>), dim3(nbatch, (nrhs + TRSV_RC - 1) / TRSV_RC), dim3(256),
-                       (size_t)maxns * TRSV_RC * sizeof(cplx<T>), s, d_fds, nrhs);
-  } else {
+    else
+      hipLaunchKernelGGL((fwd_trsv_blk_kernel<16>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs);
+  } else {  // larger fronts (and complex64): one workgroup per front, one barrier per column
     hipLaunchKernelGGL((fwd_trsv_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, nrhs);
   }
   KCHECK(hipGetLastError());
@@ -834,11 +663,10 @@ hipError_t launch_backward_level(const FrontDesc* d_fds, int nbatch, int maxn, i
       hipLaunchKernelGGL((bwd_trsv_blk_kernel<2>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs);
     else if (maxns <= 256)
       hipLaunchKernelGGL((bwd_trsv_blk_kernel<4>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs);
-    else
+    else if (maxns <= 512)
       hipLaunchKernelGGL((bwd_trsv_blk_kernel<8>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs);
-  } else if (sizeof(T) == 8 && maxns > 0 && maxns <= TRSV_MAXNS) {
-    hipLaunchKernelGGL((bwd_trsv_reg_kernel<T>), dim3(nbatch, (nrhs + TRSV_RC - 1) / TRSV_RC), dim3(256), 0, s,
-                       d_fds, (cplx<T>*)x, N, nrhs);
+    else
+      hipLaunchKernelGGL((bwd_trsv_blk_kernel<16>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs);
   } else {
     hipLaunchKernelGGL((bwd_trsv_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, (cplx<T>*)x, N, nrhs);
   }
