@@ -34,7 +34,9 @@ __global__ void permute_out_kernel(const cplx<T>* __restrict__ x, cplx<double>* 
   X[perm[i] + c * ldx] = cplx<double>{(double)v.re, (double)v.im};
 }
 
-// W_f(i, c) = [y(sbeg + i, c) if i < ns] (+) child updates, in child order.
+// W_f(i, c) = [y(sbeg + r, c) if r < ns] (+) child updates at r, in child order, with r = i except
+// for the rows of a dense front's F11, where r = pperm[i]: the gather applies the row interchanges
+// of the partial pivoting (P^T) on the way in.
 template <class T>
 __global__ __launch_bounds__(256) void fwd_gather_kernel(const FrontDesc* __restrict__ fds,
                                                          const cplx<T>* __restrict__ y, int64_t N, int nrhs) {
@@ -42,20 +44,23 @@ __global__ __launch_bounds__(256) void fwd_gather_kernel(const FrontDesc* __rest
   const int n = fd.n, ns = fd.ns;
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  const int k1 = fd.nchild > 0 ? fd.inv[0][i] : -1;
-  const int k2 = fd.nchild > 1 ? fd.inv[1][i] : -1;
+  const int r = (fd.P && i < ns) ? fd.pperm[i] : i;
+  const int k1 = fd.nchild > 0 ? fd.inv[0][r] : -1;
+  const int k2 = fd.nchild > 1 ? fd.inv[1][r] : -1;
   cplx<T>* W = (cplx<T>*)fd.W;
   for (int c = 0; c < nrhs; ++c) {
     cplx<T> v = {0, 0};
-    if (i < ns) v = y[fd.sbeg + i + c * N];
+    if (r < ns) v = y[fd.sbeg + r + c * N];
     if (k1 >= 0) v = cadd(v, ((const cplx<T>*)fd.cw[0])[k1 + c * fd.cw_ld[0]]);
     if (k2 >= 0) v = cadd(v, ((const cplx<T>*)fd.cw[1])[k2 + c * fd.cw_ld[1]]);
     W[i + (int64_t)c * n] = v;
   }
 }
 
-// Row interchanges then unit-lower substitution on W_f(0:ns, :), one
-// workgroup per front; threads own rows, one synchronisation per column.
+// Unit-lower substitution on W_f(0:ns, :) (already interchanged by the
+// gather), one workgroup per front; threads own rows, one synchronisation
+// per column.  Complex64 fronts only (the double-precision ones take the
+// blocked sweeps).
 template <class T>
 __global__ __launch_bounds__(256) void fwd_trsv_kernel(const FrontDesc* __restrict__ fds, int nrhs) {
   const FrontDesc& fd = fds[blockIdx.x];
@@ -63,18 +68,6 @@ __global__ __launch_bounds__(256) void fwd_trsv_kernel(const FrontDesc* __restri
   if (ns == 0) return;
   const cplx<T>* F = (const cplx<T>*)fd.P;  // [L U; F21'], ld n
   cplx<T>* W = (cplx<T>*)fd.W;
-  for (int c = threadIdx.x; c < nrhs; c += 256) {
-    cplx<T>* w = W + (int64_t)c * n;
-    for (int k = 0; k < ns; ++k) {
-      const int p = fd.piv[k];
-      if (p != k) {
-        const cplx<T> t = w[k];
-        w[k] = w[p];
-        w[p] = t;
-      }
-    }
-  }
-  __syncthreads();
   for (int j = 0; j < ns - 1; ++j) {
     const cplx<T>* Lj = F + (int64_t)j * n;
     for (int r = j + 1 + threadIdx.x; r < ns; r += 256) {
@@ -104,7 +97,7 @@ __global__ __launch_bounds__(256) void fwd_trsv_kernel(const FrontDesc* __restri
 // the same L2.
 constexpr int BLK_RC = 16;
 constexpr int BLK_MAXNS = 1024;   // up to 16 row blocks per wave
-constexpr int PERM_MAXNS = 4096;  // pivot permutations built in LDS
+constexpr int PERM_MAXNS = 16384;  // pivot permutations built in LDS (64 KiB)
 
 // LDS entries that other lanes of the same wave read without a barrier in
 // between (the triangle solves): volatile, so that every store is performed
@@ -139,9 +132,26 @@ __device__ __forceinline__ void blk_update(d4_t& yr, d4_t& yi, const cplx<double
   }
 }
 
-// W_f(0:ns) <- L^-1 P^T W_f(0:ns) for fronts with ns <= 64 MB
+// The rows a blocked sweep takes in one launch: the whole F11 (seg < 0) of a
+// front with ns <= BLK_MAXNS, or rows [r0, r1) = segment seg of 1024 rows of a
+// larger front (the others' segments come with their own launches, and the
+// panels between segments with sweep_seg_gemm_kernel).  False: not this launch's.
+__device__ __forceinline__ bool blk_range(const FrontDesc& fd, int seg, int& r0, int& r1) {
+  if (seg < 0) {
+    r0 = 0;
+    r1 = fd.ns;
+    return fd.ns > 0 && fd.ns <= BLK_MAXNS;
+  }
+  r0 = seg * BLK_MAXNS;
+  r1 = min(fd.ns, r0 + BLK_MAXNS);
+  return fd.ns > BLK_MAXNS && r0 < fd.ns;
+}
+
+// W_f(r0:r1) <- L(r0:r1, r0:r1)^-1 W_f(r0:r1) (the interchanges were applied by the gather) for
+// the rows blk_range gives, at most 64 MB of them
 template <int MB>
-__global__ __launch_bounds__(256) void fwd_trsv_blk_kernel(const FrontDesc* __restrict__ fds, int nfront, int nrhs) {
+__global__ __launch_bounds__(256) void fwd_trsv_blk_kernel(const FrontDesc* __restrict__ fds, int nfront, int nrhs,
+                                                           int seg) {
   __shared__ cplx<double> Ls[2][16][17];  // Ls[buf][k][i] = L(16 jb + i, 16 jb + k), strictly lower
   __shared__ cplx<double> Ys[2][16][17];  // Ys[buf][k][c] = Y(16 jb + k, c)
   const int ngrp = (nrhs + BLK_RC - 1) / BLK_RC;
@@ -149,11 +159,12 @@ __global__ __launch_bounds__(256) void fwd_trsv_blk_kernel(const FrontDesc* __re
   const int fi = (int)(tile / ngrp), grp = (int)(tile % ngrp);
   if (fi >= nfront) return;
   const FrontDesc& fd = fds[fi];
-  const int n = fd.n, ns = fd.ns;
-  if (ns == 0 || ns > 64 * MB) return;  // uniform; the host never sends these
+  int r0, r1;
+  if (!blk_range(fd, seg, r0, r1) || r1 - r0 > 64 * MB) return;  // uniform; the host never sends the latter
+  const int n = fd.n, ns = r1 - r0;  // from here on rows are relative to r0
   const int c0 = grp * BLK_RC, ncl = min(BLK_RC, nrhs - c0);
-  const cplx<double>* F = (const cplx<double>*)fd.P;  // [L U; F21'], ld n
-  cplx<double>* W = (cplx<double>*)fd.W + (int64_t)c0 * n;
+  const cplx<double>* F = (const cplx<double>*)fd.P + r0 + (int64_t)r0 * n;  // L(r0:, r0:), ld n
+  cplx<double>* W = (cplx<double>*)fd.W + r0 + (int64_t)c0 * n;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, lr = lane >> 4;
   const int nb = (ns + 15) / 16;
@@ -164,11 +175,10 @@ __global__ __launch_bounds__(256) void fwd_trsv_blk_kernel(const FrontDesc* __re
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * (4 * s + wave) + lr + 4 * r;
       const bool ok = row < ns && col < ncl;
-      const cplx<double> v = load_or_zero(W + (ok ? fd.pperm[row] + (int64_t)col * n : 0), ok);
+      const cplx<double> v = load_or_zero(W + (ok ? row + (int64_t)col * n : 0), ok);
       yr[s][r] = v.re;
       yi[s][r] = v.im;
     }
-  __syncthreads();  // every row is read (through the permutation) before any is written
   for (int jb = 0; jb < nb; ++jb) {
     const int buf = jb & 1, sj = jb >> 2;
     {
@@ -208,10 +218,13 @@ __global__ __launch_bounds__(256) void fwd_trsv_blk_kernel(const FrontDesc* __re
   }
 }
 
-// x(I^s) <- U^-1 W_f(0:ns) for fronts with ns <= 64 MB (W_f(0:ns) already holds W - F12 x(I^u))
+// x(r0:r1) <- U(r0:r1, r0:r1)^-1 W_f(r0:r1) for the rows blk_range gives (W_f(r0:r1) already
+// holds W - F12 x(I^u) minus the segments below); a segment's solution also goes back to W_f
+// for the panel product above it
 template <int MB>
 __global__ __launch_bounds__(256) void bwd_trsv_blk_kernel(const FrontDesc* __restrict__ fds, int nfront,
-                                                           cplx<double>* __restrict__ x, int64_t N, int nrhs) {
+                                                           cplx<double>* __restrict__ x, int64_t N, int nrhs,
+                                                           int seg) {
   __shared__ cplx<double> Us[2][16][17];  // Us[buf][k][i] = U(16 jb + i, 16 jb + k), upper with the diagonal
   __shared__ cplx<double> Ys[2][16][17];
   const int ngrp = (nrhs + BLK_RC - 1) / BLK_RC;
@@ -219,11 +232,13 @@ __global__ __launch_bounds__(256) void bwd_trsv_blk_kernel(const FrontDesc* __re
   const int fi = (int)(tile / ngrp), grp = (int)(tile % ngrp);
   if (fi >= nfront) return;
   const FrontDesc& fd = fds[fi];
-  const int n = fd.n, ns = fd.ns;
-  if (ns == 0 || ns > 64 * MB) return;  // uniform; the host never sends these
+  int r0, r1;
+  if (!blk_range(fd, seg, r0, r1) || r1 - r0 > 64 * MB) return;  // uniform
+  const int n = fd.n, ns = r1 - r0;
   const int c0 = grp * BLK_RC, ncl = min(BLK_RC, nrhs - c0);
-  const cplx<double>* F = (const cplx<double>*)fd.P;
-  const cplx<double>* W = (const cplx<double>*)fd.W + (int64_t)c0 * n;
+  const cplx<double>* F = (const cplx<double>*)fd.P + r0 + (int64_t)r0 * n;
+  cplx<double>* W = (cplx<double>*)fd.W + r0 + (int64_t)c0 * n;
+  cplx<double>* xs = x + fd.sbeg + r0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, lr = lane >> 4;
   const int nb = (ns + 15) / 16;
@@ -269,7 +284,11 @@ __global__ __launch_bounds__(256) void bwd_trsv_blk_kernel(const FrontDesc* __re
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * jb + lr + 4 * r;
-        if (row < ns && col < ncl) x[fd.sbeg + row + (int64_t)(c0 + col) * N] = vld(&V[lr + 4 * r][col]);
+        if (row < ns && col < ncl) {
+          const cplx<double> v = vld(&V[lr + 4 * r][col]);
+          xs[row + (int64_t)(c0 + col) * N] = v;
+          if (seg >= 0) W[row + (int64_t)col * n] = v;
+        }
       }
     }
     __syncthreads();
@@ -285,10 +304,11 @@ __global__ __launch_bounds__(256) void bwd_trsv_blk_kernel(const FrontDesc* __re
 // ascending) as one permutation, applied to an index vector: pperm[i] is the
 // row of F11 that ends up at position i.  One workgroup per dense front.
 __global__ __launch_bounds__(256) void pivot_perm_kernel(const FrontDesc* __restrict__ fds, int nfront) {
-  __shared__ int32_t idx[PERM_MAXNS];
+  extern __shared__ int32_t perm_smem[];
   const FrontDesc& fd = fds[blockIdx.x];
   const int ns = fd.ns;
-  if (!fd.P || ns == 0 || ns > PERM_MAXNS) return;  // compressed fronts and the largest dense ones
+  if (!fd.P || ns == 0) return;  // compressed fronts
+  int32_t* idx = ns <= PERM_MAXNS ? perm_smem : fd.pperm;  // the largest fronts in place in memory
   for (int i = threadIdx.x; i < ns; i += 256) idx[i] = i;
   __syncthreads();
   if (threadIdx.x == 0)
@@ -301,7 +321,34 @@ __global__ __launch_bounds__(256) void pivot_perm_kernel(const FrontDesc* __rest
       }
     }
   __syncthreads();
-  for (int i = threadIdx.x; i < ns; i += 256) fd.pperm[i] = idx[i];
+  if (ns <= PERM_MAXNS)
+    for (int i = threadIdx.x; i < ns; i += 256) fd.pperm[i] = idx[i];
+}
+
+// Panel products between the segments of a front with ns > BLK_MAXNS, after segment seg =
+// rows [r0, r1) is solved: forward (mode 0) W(r1:n) -= P(r1:n, r0:r1) W(r0:r1), which for the
+// last segment includes F21 (rows ns..n of P); backward (mode 1) W(0:r0) -= U(0:r0, r0:r1) x(r0:r1).
+template <class C>
+__global__ __launch_bounds__(256) void sweep_seg_gemm_kernel(const FrontDesc* __restrict__ fds, int nrhs, int seg,
+                                                             int mode) {
+  __shared__ TileSmem<double, C> sm;
+  const FrontDesc& fd = fds[blockIdx.y];
+  int r0, r1;
+  if (!blk_range(fd, seg, r0, r1)) return;
+  const int n = fd.n;
+  const cplx<double>* F = (const cplx<double>*)fd.P;
+  cplx<double>* W = (cplx<double>*)fd.W;
+  const int M = mode == 0 ? n - r1 : r0, K = r1 - r0;
+  if (M <= 0) return;
+  const int tm = (M + C::TM - 1) / C::TM, tn = (nrhs + C::TN - 1) / C::TN;
+  const int t = blockIdx.x;
+  if (t >= tm * tn) return;
+  if (mode == 0)
+    gemm_tile_cfg<double, C>(F + r1 + (int64_t)r0 * n, n, OP_N, W + r0, n, OP_N, W + r1, n, M, nrhs, K,
+                             cplx<double>{-1, 0}, 1, t % tm, t / tm, sm);
+  else
+    gemm_tile_cfg<double, C>(F + (int64_t)r0 * n, n, OP_N, W + r0, n, OP_N, W, n, M, nrhs, K, cplx<double>{-1, 0}, 1,
+                             t % tm, t / tm, sm);
 }
 
 // the sweep products (W(ns:n) -= F21 W(0:ns), W(0:ns) -= F12 W(ns:n)) in a tile shape of the grouped GEMM
@@ -311,6 +358,7 @@ __global__ __launch_bounds__(256) void sweep_gemm_cfg_kernel(const FrontDesc* __
   const FrontDesc& fd = fds[blockIdx.y];
   const int n = fd.n, ns = fd.ns, nu = n - ns;
   if (ns == 0 || nu == 0) return;
+  if (mode == 0 && ns > BLK_MAXNS) return;  // the segment panels carry F21
   const cplx<double>* F = (const cplx<double>*)fd.P;
   cplx<double>* W = (cplx<double>*)fd.W;
   const int M = mode == 0 ? nu : ns;
@@ -379,6 +427,7 @@ __global__ __launch_bounds__(256) void sweep_gemm_kernel(const FrontDesc* __rest
   const FrontDesc& fd = fds[blockIdx.y];
   const int n = fd.n, ns = fd.ns, nu = n - ns;
   if (ns == 0 || nu == 0) return;
+  if (sizeof(T) == 8 && mode == 0 && ns > BLK_MAXNS) return;  // the segment panels carry F21
   const cplx<T>* F = (const cplx<T>*)fd.P;  // [L U; F21'], ld n
   cplx<T>* W = (cplx<T>*)fd.W;
   const int M = mode == 0 ? nu : ns;
@@ -406,6 +455,7 @@ __global__ __launch_bounds__(256) void sweep_gemm_skinny_kernel(const FrontDesc*
   const FrontDesc& fd = fds[blockIdx.y];
   const int n = fd.n, ns = fd.ns, nu = n - ns;
   if (ns == 0 || nu == 0 || nrhs > SKINNY_TN) return;
+  if (sizeof(T) == 8 && mode == 0 && ns > BLK_MAXNS) return;  // the segment panels carry F21
   const cplx<T>* F = (const cplx<T>*)fd.P;  // [L U; F21'], ld n
   cplx<T>* W = (cplx<T>*)fd.W;
   const int M = mode == 0 ? nu : ns;
@@ -604,19 +654,31 @@ hipError_t launch_forward_level(const FrontDesc* d_fds, int nbatch, int maxn, in
   hipLaunchKernelGGL((fwd_gather_kernel<T>), dim3(blocks_for(maxn, 256), nbatch), dim3(256), 0, s, d_fds,
                      (const cplx<T>*)y, N, nrhs);
   KCHECK(hipGetLastError());
-  if (sizeof(T) == 8 && maxns > 0 && maxns <= BLK_MAXNS) {
+  if (sizeof(T) == 8 && maxns > 0) {
+    // fronts with ns <= BLK_MAXNS whole (the kernel for the level's largest of them), then the
+    // larger ones segment by segment with the panel products in between
     const dim3 grid((unsigned)((int64_t)nbatch * ((nrhs + BLK_RC - 1) / BLK_RC)));
-    if (maxns <= 64)
-      hipLaunchKernelGGL((fwd_trsv_blk_kernel<1>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs);
-    else if (maxns <= 128)
-      hipLaunchKernelGGL((fwd_trsv_blk_kernel<2>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs);
-    else if (maxns <= 256)
-      hipLaunchKernelGGL((fwd_trsv_blk_kernel<4>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs);
-    else if (maxns <= 512)
-      hipLaunchKernelGGL((fwd_trsv_blk_kernel<8>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs);
+    const int small = maxns <= BLK_MAXNS ? maxns : BLK_MAXNS;
+    if (small <= 64)
+      hipLaunchKernelGGL((fwd_trsv_blk_kernel<1>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs, -1);
+    else if (small <= 128)
+      hipLaunchKernelGGL((fwd_trsv_blk_kernel<2>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs, -1);
+    else if (small <= 256)
+      hipLaunchKernelGGL((fwd_trsv_blk_kernel<4>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs, -1);
+    else if (small <= 512)
+      hipLaunchKernelGGL((fwd_trsv_blk_kernel<8>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs, -1);
     else
-      hipLaunchKernelGGL((fwd_trsv_blk_kernel<16>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs);
-  } else {  // larger fronts (and complex64): one workgroup per front, one barrier per column
+      hipLaunchKernelGGL((fwd_trsv_blk_kernel<16>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs, -1);
+    KCHECK(hipGetLastError());
+    const int tiles = (int)(blocks_for(maxn, SweepTile128x32::TM) * blocks_for(nrhs, SweepTile128x32::TN));
+    for (int seg = 0; seg * BLK_MAXNS < maxns && maxns > BLK_MAXNS; ++seg) {
+      hipLaunchKernelGGL((fwd_trsv_blk_kernel<16>), grid, dim3(256), 0, s, d_fds, nbatch, nrhs, seg);
+      KCHECK(hipGetLastError());
+      hipLaunchKernelGGL((sweep_seg_gemm_kernel<SweepTile128x32>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs,
+                         seg, 0);
+      KCHECK(hipGetLastError());
+    }
+  } else {  // complex64: one workgroup per front, one barrier per column
     hipLaunchKernelGGL((fwd_trsv_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, nrhs);
   }
   KCHECK(hipGetLastError());
@@ -654,19 +716,29 @@ hipError_t launch_backward_level(const FrontDesc* d_fds, int nbatch, int maxn, i
     }
     KCHECK(hipGetLastError());
   }
-  if (sizeof(T) == 8 && maxns > 0 && maxns <= BLK_MAXNS) {
+  if (sizeof(T) == 8 && maxns > 0) {
     const dim3 grid((unsigned)((int64_t)nbatch * ((nrhs + BLK_RC - 1) / BLK_RC)));
     cplx<double>* xd = (cplx<double>*)x;
-    if (maxns <= 64)
-      hipLaunchKernelGGL((bwd_trsv_blk_kernel<1>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs);
-    else if (maxns <= 128)
-      hipLaunchKernelGGL((bwd_trsv_blk_kernel<2>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs);
-    else if (maxns <= 256)
-      hipLaunchKernelGGL((bwd_trsv_blk_kernel<4>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs);
-    else if (maxns <= 512)
-      hipLaunchKernelGGL((bwd_trsv_blk_kernel<8>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs);
+    const int tiles = (int)(blocks_for(maxn, SweepTile128x32::TM) * blocks_for(nrhs, SweepTile128x32::TN));
+    // the larger fronts segment by segment from the bottom, then the others whole
+    for (int seg = (maxns - 1) / BLK_MAXNS; seg >= 0 && maxns > BLK_MAXNS; --seg) {
+      hipLaunchKernelGGL((bwd_trsv_blk_kernel<16>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs, seg);
+      KCHECK(hipGetLastError());
+      hipLaunchKernelGGL((sweep_seg_gemm_kernel<SweepTile128x32>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs,
+                         seg, 1);
+      KCHECK(hipGetLastError());
+    }
+    const int small = maxns <= BLK_MAXNS ? maxns : BLK_MAXNS;
+    if (small <= 64)
+      hipLaunchKernelGGL((bwd_trsv_blk_kernel<1>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs, -1);
+    else if (small <= 128)
+      hipLaunchKernelGGL((bwd_trsv_blk_kernel<2>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs, -1);
+    else if (small <= 256)
+      hipLaunchKernelGGL((bwd_trsv_blk_kernel<4>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs, -1);
+    else if (small <= 512)
+      hipLaunchKernelGGL((bwd_trsv_blk_kernel<8>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs, -1);
     else
-      hipLaunchKernelGGL((bwd_trsv_blk_kernel<16>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs);
+      hipLaunchKernelGGL((bwd_trsv_blk_kernel<16>), grid, dim3(256), 0, s, d_fds, nbatch, xd, N, nrhs, -1);
   } else {
     hipLaunchKernelGGL((bwd_trsv_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, (cplx<T>*)x, N, nrhs);
   }
@@ -675,7 +747,7 @@ hipError_t launch_backward_level(const FrontDesc* d_fds, int nbatch, int maxn, i
 
 hipError_t launch_pivot_perm(const FrontDesc* d_fds, int nfront, hipStream_t s) {
   if (nfront == 0) return hipSuccess;
-  hipLaunchKernelGGL(pivot_perm_kernel, dim3(nfront), dim3(256), 0, s, d_fds, nfront);
+  hipLaunchKernelGGL(pivot_perm_kernel, dim3(nfront), dim3(256), PERM_MAXNS * sizeof(int32_t), s, d_fds, nfront);
   return hipGetLastError();
 }
 
