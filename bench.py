@@ -56,6 +56,8 @@ def parse():
                     help="separators are bisected down to this many nodes (HOD-BF leaves); default: the workload's")
     ap.add_argument("--parallel-levels", type=int, default=0,
                     help="separator variant: the top levels of the dissection cut across one axis (parallel planes)")
+    ap.add_argument("--smw-dense", type=int, default=0,
+                    help="BF_SMW blocks of at most this many rows are inverted densely (0: the library's 1024)")
     ap.add_argument("--compress-cb", action="store_true",
                     help="contribution blocks of compressed fronts with compressed parents in HOD-BF form")
     ap.add_argument("--direct", action="store_true",
@@ -192,7 +194,7 @@ def cpu_baseline(bfmf, reps=3, with_48=True):
 
 
 def run_form(bfmf, s, prob, nrhs, dB, dX, steps, warmup, form, precision, n_min, tol, timing=True, direct=False,
-             compress_cb=False):
+             compress_cb=False, smw_dense=0):
     """Factor + GMRES solve of the RHS block (or, direct, one application of the factorization),
     `steps` timed steps after `warmup` untimed ones."""
     import torch
@@ -204,7 +206,7 @@ def run_form(bfmf, s, prob, nrhs, dB, dX, steps, warmup, form, precision, n_min,
 
     def step():
         s.factor(tol=tol, n_min=n_min, precision=prec, batched=(form == "batched"), timing=timing,
-                 compress_cb=compress_cb)
+                 compress_cb=compress_cb, smw_dense=smw_dense)
         o, st = bfmf.bfmf_solve_device(s.h, dB.data_ptr(), prob.n, dX.data_ptr(), prob.n, nrhs, so)
         if st != 0:
             raise RuntimeError(f"solve did not converge ({form}, {precision}): relres {o.relres_max}")
@@ -454,7 +456,7 @@ def main():
     dB = torch.from_numpy(np.ascontiguousarray(prob.rhs.T)).to("cuda")  # column-major (N, nrhs)
     dX = torch.zeros_like(dB)
     r = run_form(bfmf, s, prob, nrhs, dB, dX, a.steps, a.warmup, a.form, precision, n_min, tol, direct=a.direct,
-                 compress_cb=a.compress_cb)
+                 compress_cb=a.compress_cb, smw_dense=a.smw_dense)
     rf, kernels = roofline(r["kernels"], a.steps, precision, a.config)
     dtype = {"c128": "c128", "c64": "c64+f64"}[precision]
     wl = f"{a.config}: {operator_label(cfg)} {prob.dims[0]}^3 (N={prob.n}), {nrhs} RHS"
@@ -471,7 +473,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl, "form": a.form, "n_min": n_min, "tol": tol, "precision": precision,
                    "sep_leaf": sep_leaf, "parallel_levels": a.parallel_levels,
-                   "solver": "direct" if a.direct else "gmres", "compress_cb": bool(a.compress_cb)},
+                   "solver": "direct" if a.direct else "gmres", "compress_cb": bool(a.compress_cb),
+                   "smw_dense": a.smw_dense or 1024},
         "factor_s": r["factor_s"], "solve_s": r["solve_s"], "solve_rhs_per_s": r["solve_rhs_per_s"],
         "gmres_iters": r["gmres_iters"], "relres_max": r["relres_max"],
         "factor_gb": r["factor_bytes"] / 1e9, "dense_factor_gb": r["dense_factor_bytes"] / 1e9,

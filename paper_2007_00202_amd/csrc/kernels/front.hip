@@ -359,18 +359,19 @@ __global__ __launch_bounds__(PR_THREADS) void panel_reg_kernel(const FrontDesc* 
   factor_half(PR_HALF, w2);
 }
 
-// Row interchanges of panel k0 applied to the columns outside the panel, rows
-// 0..ns-1 only (F21 rows are never swapped).
+// Row interchanges of the pivot rows [k0, k0+jb) applied to columns outside
+// the panel, rows 0..ns-1 only (F21 rows are never swapped): columns
+// [cbeg, k0) and then [max(k0+jb, cfrom), min(cend, n)).
 template <class T>
-__global__ __launch_bounds__(256) void laswp_kernel(const FrontDesc* __restrict__ fds, int k0, int kb) {
+__global__ __launch_bounds__(256) void laswp_kernel(const FrontDesc* __restrict__ fds, int k0, int kb, int cbeg,
+                                                    int cfrom, int cend) {
   const FrontDesc& fd = fds[blockIdx.y];
   const int ns = fd.ns, n = fd.n;
   if (k0 >= ns) return;
   const int jb = min(kb, ns - k0);
-  int c = blockIdx.x * 256 + threadIdx.x;
-  // columns [0, k0) then [k0+jb, n)
-  if (c >= k0) c += jb;
-  if (c >= n) return;
+  const int idx = blockIdx.x * 256 + threadIdx.x, nleft = max(k0 - cbeg, 0);
+  const int c = idx < nleft ? cbeg + idx : max(k0 + jb, cfrom) + (idx - nleft);
+  if (c >= min(cend, n)) return;
   cplx<T>* Fc = (cplx<T>*)fd.F + (int64_t)c * n;
   for (int k = k0; k < k0 + jb; ++k) {
     const int p = fd.piv[k];
@@ -382,10 +383,13 @@ __global__ __launch_bounds__(256) void laswp_kernel(const FrontDesc* __restrict_
   }
 }
 
-// F(k0:k0+jb, c) <- L_kk^-1 F(k0:k0+jb, c) for c in [k0+jb, n): one wave per
-// column, lane i holds row k0+i, forward substitution with shuffles.
+// F(k0:k0+jb, c) <- L_kk^-1 F(k0:k0+jb, c) for c in [max(k0+jb, cfrom),
+// min(cend, n)): one wave per column, lane i holds row k0+i, forward
+// substitution with shuffles.
 template <class T, int KB>
-__global__ __launch_bounds__(256) void trsm_ll_kernel(const FrontDesc* __restrict__ fds, int k0) {
+__global__ __launch_bounds__(256) void trsm_ll_kernel(const FrontDesc* __restrict__ fds, int k0, int cfrom,
+                                                      int cend) {
+  static_assert(KB <= 64, "one lane per row of the block");
   const FrontDesc& fd = fds[blockIdx.y];
   const int ns = fd.ns, n = fd.n;
   if (k0 >= ns) return;
@@ -398,8 +402,8 @@ __global__ __launch_bounds__(256) void trsm_ll_kernel(const FrontDesc* __restric
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int c = k0 + jb + blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (c >= n) return;
+  const int c = max(k0 + jb, cfrom) + blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= min(cend, n)) return;
   cplx<T>* col = F + (int64_t)c * n + k0;
   cplx<T> x = lane < jb ? col[lane] : cplx<T>{0, 0};
   for (int j = 0; j < jb - 1; ++j) {
@@ -443,20 +447,21 @@ __global__ __launch_bounds__(256) void trsm_ru_kernel(const FrontDesc* __restric
     if (c < jb) F[(int64_t)r + (int64_t)(k0 + c) * n] = x[c];
 }
 
-// Rank-jb update after panel k0: rows [k0+jb, ns) x cols [k0+jb, n) and
-// rows [ns, n) x cols [k0+jb, ns).
+// Rank-jb update after the panel of columns [k0, k0+jb): rows [k0+jb, ns) x
+// cols [k0+jb, ce) and rows [ns, n) x cols [k0+jb, min(ce, ns)), ce = min(cend, n).
 template <class T>
-__global__ __launch_bounds__(256) void trailing_kernel(const FrontDesc* __restrict__ fds, int k0, int kb) {
+__global__ __launch_bounds__(256) void trailing_kernel(const FrontDesc* __restrict__ fds, int k0, int kb, int cend) {
   __shared__ GemmSmem<T> sm;
   const FrontDesc& fd = fds[blockIdx.y];
   const int ns = fd.ns, n = fd.n;
   if (k0 >= ns) return;
   const int jb = min(kb, ns - k0);
   const int r0 = k0 + jb;
+  const int ce = min(cend, n);
   cplx<T>* F = (cplx<T>*)fd.F;
-  const int M1 = ns - r0, N1 = n - r0;
+  const int M1 = ns - r0, N1 = ce - r0;
   // with F21 = -I at the start, F21(:, k0:r0) is zero below row ns + r0
-  const int M2 = fd.f21_unit ? min(n - ns, r0) : n - ns, N2 = ns - r0;
+  const int M2 = fd.f21_unit ? min(n - ns, r0) : n - ns, N2 = min(ce, ns) - r0;
   const int tm1 = (M1 + GEMM_TM - 1) / GEMM_TM, tn1 = (N1 + GEMM_TN - 1) / GEMM_TN;
   const int tm2 = (M2 + GEMM_TM - 1) / GEMM_TM, tn2 = (N2 + GEMM_TN - 1) / GEMM_TN;
   const int t1 = (M1 > 0 && N1 > 0) ? tm1 * tn1 : 0;
@@ -538,37 +543,78 @@ hipError_t launch_partial_lu(const FrontDesc* d_fds, int nbatch, const int* h_n,
     maxn = h_n[b] > maxn ? h_n[b] : maxn;
   }
   static_assert(KB <= 2 * PR_HALF, "the register panel holds two half-panels");
-  for (int k0 = 0; k0 < maxns; k0 += KB) {
+  // Blocks of 2 KB columns: the first half panel is factored, its interchanges, row-block solve and
+  // rank-KB update applied to the second half's columns (and F21) only; then the second half panel;
+  // then, once per block, the interchanges of both halves, the 2 KB x 2 KB row-block solve and one
+  // rank-2 KB update of everything to the right, so the trailing matrix is rewritten once per 2 KB
+  // columns.  The panels see exactly the values of a KB-column right-looking sweep, so the pivots
+  // are the same.
+  auto tiles_for = [&](int k0, int kb, int cend) {
+    int mt = 0;
+    for (int b = 0; b < nbatch; ++b) {
+      if (k0 >= h_ns[b]) continue;
+      const int jb = (h_ns[b] - k0) < kb ? (h_ns[b] - k0) : kb;
+      const int r0 = k0 + jb, ce = cend < h_n[b] ? cend : h_n[b];
+      const int M1 = h_ns[b] - r0, N1 = ce - r0, M2 = h_n[b] - h_ns[b], N2 = (ce < h_ns[b] ? ce : h_ns[b]) - r0;
+      int t = 0;
+      if (M1 > 0 && N1 > 0) t += ((M1 + 63) / 64) * ((N1 + 63) / 64);
+      if (M2 > 0 && N2 > 0) t += ((M2 + 63) / 64) * ((N2 + 63) / 64);
+      mt = t > mt ? t : mt;
+    }
+    return mt;
+  };
+  int maxnu = 0;
+  for (int b = 0; b < nbatch; ++b) maxnu = (h_n[b] - h_ns[b]) > maxnu ? (h_n[b] - h_ns[b]) : maxnu;
+  // does any front have columns in [k0+jb, min(cend, n)) for the pivot rows [k0, k0+jb)?
+  auto right_cols = [&](int k0, int kb, int cend) {
+    for (int b = 0; b < nbatch; ++b) {
+      if (k0 >= h_ns[b]) continue;
+      const int jb = (h_ns[b] - k0) < kb ? (h_ns[b] - k0) : kb;
+      if (k0 + jb < (cend < h_n[b] ? cend : h_n[b])) return true;
+    }
+    return false;
+  };
+  auto half = [&](int k0, int cend) {  // factor columns [k0, k0+KB); update columns up to cend
     if (maxns - k0 <= PR_ROWS)  // every front's panel fits the register kernel
       hipLaunchKernelGGL((panel_reg_kernel<T>), dim3(nbatch), dim3(PR_THREADS), 0, s, d_fds, k0, KB, d_status);
     else
       hipLaunchKernelGGL((panel_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, k0, KB, d_status);
     KCHECK(hipGetLastError());
-    int ncols = maxn;  // upper bound on columns outside the panel
-    hipLaunchKernelGGL((laswp_kernel<T>), dim3((ncols + 255) / 256, nbatch), dim3(256), 0, s, d_fds, k0, KB);
+    hipLaunchKernelGGL((laswp_kernel<T>), dim3((cend + 255) / 256, nbatch), dim3(256), 0, s, d_fds, k0, KB, 0, 0,
+                       cend);
     KCHECK(hipGetLastError());
-    hipLaunchKernelGGL((trsm_ll_kernel<T, KB>), dim3((maxn - k0 + 3) / 4, nbatch), dim3(256), 0, s, d_fds, k0);
-    KCHECK(hipGetLastError());
-    int maxnu = 0, maxtiles = 0;
-    for (int b = 0; b < nbatch; ++b) {
-      if (k0 >= h_ns[b]) continue;
-      const int jb = (h_ns[b] - k0) < KB ? (h_ns[b] - k0) : KB;
-      const int r0 = k0 + jb;
-      const int nu = h_n[b] - h_ns[b];
-      maxnu = nu > maxnu ? nu : maxnu;
-      const int M1 = h_ns[b] - r0, N1 = h_n[b] - r0, M2 = nu, N2 = h_ns[b] - r0;
-      int t = 0;
-      if (M1 > 0 && N1 > 0) t += ((M1 + 63) / 64) * ((N1 + 63) / 64);
-      if (M2 > 0 && N2 > 0) t += ((M2 + 63) / 64) * ((N2 + 63) / 64);
-      maxtiles = t > maxtiles ? t : maxtiles;
+    if (right_cols(k0, KB, cend)) {
+      hipLaunchKernelGGL((trsm_ll_kernel<T, KB>), dim3((cend - k0 + 3) / 4, nbatch), dim3(256), 0, s, d_fds, k0, 0,
+                         cend);
+      KCHECK(hipGetLastError());
     }
     if (maxnu > 0) {
       hipLaunchKernelGGL((trsm_ru_kernel<T, KB>), dim3((maxnu + 255) / 256, nbatch), dim3(256), 0, s, d_fds, k0);
       KCHECK(hipGetLastError());
     }
-    if (maxtiles > 0) {
-      hipLaunchKernelGGL((trailing_kernel<T>), dim3(maxtiles, nbatch), dim3(256), 0, s, d_fds, k0, KB);
+    const int mt = tiles_for(k0, KB, cend);
+    if (mt > 0) {
+      hipLaunchKernelGGL((trailing_kernel<T>), dim3(mt, nbatch), dim3(256), 0, s, d_fds, k0, KB, cend);
       KCHECK(hipGetLastError());
+    }
+  };
+  for (int k0 = 0; k0 < maxns; k0 += 2 * KB) {
+    const int kend = k0 + 2 * KB;
+    half(k0, kend);                           // right updates reach the second half's columns only
+    if (k0 + KB < maxns) half(k0 + KB, kend);  // interchanges left of it; right columns only past ns
+    if (maxn > kend) {
+      // columns from kend on: both halves' interchanges, the row-block solve, one rank-2 KB update
+      hipLaunchKernelGGL((laswp_kernel<T>), dim3((maxn - kend + 255) / 256, nbatch), dim3(256), 0, s, d_fds, k0, 2 * KB,
+                         k0, kend, maxn);
+      KCHECK(hipGetLastError());
+      hipLaunchKernelGGL((trsm_ll_kernel<T, 2 * KB>), dim3((maxn - kend + 3) / 4, nbatch), dim3(256), 0, s, d_fds, k0,
+                         kend, maxn);
+      KCHECK(hipGetLastError());
+      const int mt = tiles_for(k0, 2 * KB, maxn);
+      if (mt > 0) {
+        hipLaunchKernelGGL((trailing_kernel<T>), dim3(mt, nbatch), dim3(256), 0, s, d_fds, k0, 2 * KB, maxn);
+        KCHECK(hipGetLastError());
+      }
     }
   }
   return hipSuccess;
