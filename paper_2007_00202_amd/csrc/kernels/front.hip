@@ -383,9 +383,22 @@ __global__ __launch_bounds__(256) void laswp_kernel(const FrontDesc* __restrict_
   }
 }
 
+// The value v of lane j (j uniform over the wave), through the scalar unit.
+__device__ __forceinline__ double lane_value(double v, int j) {
+  const int64_t b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, j), hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
+  return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ float lane_value(float v, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+
 // F(k0:k0+jb, c) <- L_kk^-1 F(k0:k0+jb, c) for c in [max(k0+jb, cfrom),
-// min(cend, n)): one wave per column, lane i holds row k0+i, forward
-// substitution with shuffles.
+// min(cend, n)), forward substitution with lane i holding row k0+i.  A wave
+// solves TRSM_CW consecutive columns together (one read of L per step for all
+// of them, the step's pivot values read from lane j), and a workgroup takes
+// TRSM_COLS columns so that its copy of L_kk in LDS serves all of them.
+constexpr int TRSM_CW = 4, TRSM_GR = 2, TRSM_COLS = 4 * TRSM_CW * TRSM_GR;
 template <class T, int KB>
 __global__ __launch_bounds__(256) void trsm_ll_kernel(const FrontDesc* __restrict__ fds, int k0, int cfrom,
                                                       int cend) {
@@ -394,23 +407,37 @@ __global__ __launch_bounds__(256) void trsm_ll_kernel(const FrontDesc* __restric
   const int ns = fd.ns, n = fd.n;
   if (k0 >= ns) return;
   const int jb = min(KB, ns - k0);
+  const int c0 = max(k0 + jb, cfrom) + blockIdx.x * TRSM_COLS, c1 = min(cend, n);
+  if (c0 >= c1) return;  // the same for the whole workgroup
+  // strictly lower part of L_kk, zero elsewhere (rows past jb included)
   __shared__ cplx<T> L[KB][KB + 1];
   cplx<T>* F = (cplx<T>*)fd.F;
   for (int e = threadIdx.x; e < KB * KB; e += 256) {
     const int i = e % KB, j = e / KB;
-    L[i][j] = (i < jb && j < jb) ? F[(int64_t)(k0 + i) + (int64_t)(k0 + j) * n] : cplx<T>{0, 0};
+    L[i][j] = (i > j && i < jb) ? F[(int64_t)(k0 + i) + (int64_t)(k0 + j) * n] : cplx<T>{0, 0};
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int c = max(k0 + jb, cfrom) + blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (c >= min(cend, n)) return;
-  cplx<T>* col = F + (int64_t)c * n + k0;
-  cplx<T> x = lane < jb ? col[lane] : cplx<T>{0, 0};
-  for (int j = 0; j < jb - 1; ++j) {
-    const T xr = __shfl(x.re, j), xi = __shfl(x.im, j);
-    if (lane > j && lane < jb) x = csub(x, cmul(L[lane][j], cplx<T>{xr, xi}));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane < KB ? lane : 0;  // row 0 of the strictly lower part is zero
+  for (int g = 0; g < TRSM_GR; ++g) {
+    const int cb = c0 + (g * 4 + w) * TRSM_CW;
+    if (cb >= c1) break;  // the same for the whole wave
+    cplx<T> x[TRSM_CW];
+#pragma unroll
+    for (int q = 0; q < TRSM_CW; ++q)
+      x[q] = (lane < jb && cb + q < c1) ? F[(int64_t)(cb + q) * n + k0 + lane] : cplx<T>{0, 0};
+    for (int j = 0; j < jb - 1; ++j) {
+      const cplx<T> l = L[li][j];
+#pragma unroll
+      for (int q = 0; q < TRSM_CW; ++q) {
+        const cplx<T> xj = {lane_value(x[q].re, j), lane_value(x[q].im, j)};
+        x[q] = csub(x[q], cmul(l, xj));
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < TRSM_CW; ++q)
+      if (lane < jb && cb + q < c1) F[(int64_t)(cb + q) * n + k0 + lane] = x[q];
   }
-  if (lane < jb) col[lane] = x;
 }
 
 // F21(r, k0:k0+jb) <- F21(r, k0:k0+jb) U_kk^-1 for rows r in [ns, n): one
@@ -584,8 +611,8 @@ hipError_t launch_partial_lu(const FrontDesc* d_fds, int nbatch, const int* h_n,
                        cend);
     KCHECK(hipGetLastError());
     if (right_cols(k0, KB, cend)) {
-      hipLaunchKernelGGL((trsm_ll_kernel<T, KB>), dim3((cend - k0 + 3) / 4, nbatch), dim3(256), 0, s, d_fds, k0, 0,
-                         cend);
+      hipLaunchKernelGGL((trsm_ll_kernel<T, KB>), dim3((cend - k0 + TRSM_COLS - 1) / TRSM_COLS, nbatch), dim3(256), 0,
+                         s, d_fds, k0, 0, cend);
       KCHECK(hipGetLastError());
     }
     if (maxnu > 0) {
@@ -607,8 +634,8 @@ hipError_t launch_partial_lu(const FrontDesc* d_fds, int nbatch, const int* h_n,
       hipLaunchKernelGGL((laswp_kernel<T>), dim3((maxn - kend + 255) / 256, nbatch), dim3(256), 0, s, d_fds, k0, 2 * KB,
                          k0, kend, maxn);
       KCHECK(hipGetLastError());
-      hipLaunchKernelGGL((trsm_ll_kernel<T, 2 * KB>), dim3((maxn - kend + 3) / 4, nbatch), dim3(256), 0, s, d_fds, k0,
-                         kend, maxn);
+      hipLaunchKernelGGL((trsm_ll_kernel<T, 2 * KB>), dim3((maxn - kend + TRSM_COLS - 1) / TRSM_COLS, nbatch),
+                         dim3(256), 0, s, d_fds, k0, kend, maxn);
       KCHECK(hipGetLastError());
       const int mt = tiles_for(k0, 2 * KB, maxn);
       if (mt > 0) {
