@@ -62,7 +62,7 @@ __device__ __forceinline__ void grouped_gemm_run(const GTask* __restrict__ tasks
 
 // butterfly products (and every other grouped product but the Gram matrices of the IDs)
 template <class T, class C>
-__global__ __launch_bounds__(256) void grouped_gemm_kernel(const GTask* __restrict__ tasks,
+__global__ __launch_bounds__(256, C::MINB) void grouped_gemm_kernel(const GTask* __restrict__ tasks,
                                                            const int64_t* __restrict__ tile_start, int ntasks,
                                                            void* b0, void* b1, void* b2, void* b3) {
   __shared__ TileSmem<T, C> sm;
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void grouped_gemm_kernel(const GTask* __restri
 // the same product for the Gram matrices G = A^H A of the interpolative decompositions (a kernel of
 // its own name, so that profiles tell the two classes apart)
 template <class T, class C>
-__global__ __launch_bounds__(256) void gram_gemm_kernel(const GTask* __restrict__ tasks,
+__global__ __launch_bounds__(256, C::MINB) void gram_gemm_kernel(const GTask* __restrict__ tasks,
                                                         const int64_t* __restrict__ tile_start, int ntasks,
                                                         void* b0, void* b1, void* b2, void* b3) {
   __shared__ TileSmem<T, C> sm;

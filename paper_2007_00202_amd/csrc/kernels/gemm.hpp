@@ -12,13 +12,32 @@ namespace bfmf {
 
 constexpr int GEMM_TM = 64, GEMM_TN = 64, GEMM_TK = 16;
 
+// Operands in device memory are read through the global address space: a
+// generic (flat) load also counts against the LDS wait counter, so every wait
+// for a staged LDS operand would wait for the next block's prefetch as well.
+// The global pointer is made from the address's integer value (a cast between
+// pointer types can be dropped again by the optimizer).
+template <class T>
+using gcptr = const __attribute__((address_space(1))) cplx<T>*;
+template <class T>
+__device__ __forceinline__ gcptr<T> as_global(const cplx<T>* p) {
+  return (gcptr<T>)(uintptr_t)p;
+}
+
 // *p when ok, else 0 (a guarded load: a select between the global address and
 // a local zero would put the zero in scratch memory)
 template <class T>
-__device__ __forceinline__ cplx<T> load_or_zero(const cplx<T>* p, bool ok) {
+__device__ __forceinline__ cplx<T> load_or_zero(gcptr<T> p, bool ok) {
   cplx<T> v = {0, 0};
-  if (ok) v = *p;
+  if (ok) {
+    v.re = p->re;
+    v.im = p->im;
+  }
   return v;
+}
+template <class T>
+__device__ __forceinline__ cplx<T> load_or_zero(const cplx<T>* p, bool ok) {
+  return load_or_zero(as_global(p), ok);
 }
 
 template <class TO, class TI>
@@ -26,10 +45,19 @@ __device__ __forceinline__ cplx<TO> to_cplx(cplx<TI> v) {
   return cplx<TO>{(TO)v.re, (TO)v.im};
 }
 
+// LDS layout of a staged operand block (TK = 16 rows k, a row of t entries m):
+// row stride lds_ld(t), congruent to 16 modulo 32 entries, and entry (k, m)
+// stored at column m ^ k, which permutes each aligned run of 16 entries.  A
+// wave's MFMA operand read (rows k..k+3, 16 consecutive m each) and both
+// staging patterns (consecutive m in a row, or consecutive k down a column)
+// then fall on distinct banks in every group of lanes the LDS serves at once.
+__host__ __device__ constexpr int lds_ld(int t) { return t % 32 == 0 ? t + 16 : t; }
+__device__ __forceinline__ int lds_swz(int k, int m) { return m ^ (k & 15); }
+
 template <class T>
 struct GemmSmem {
-  cplx<T> a[GEMM_TK][GEMM_TM];
-  cplx<T> b[GEMM_TK][GEMM_TN];
+  cplx<T> a[GEMM_TK][lds_ld(GEMM_TM)];
+  cplx<T> b[GEMM_TK][lds_ld(GEMM_TN)];
 };
 
 // Computes tile (tm, tn).  opA: OP_N -> A is M x K (lda); OP_T / OP_C -> A is
@@ -59,68 +87,51 @@ __device__ __forceinline__ void gemm_tile(const cplx<TL>* __restrict__ A, int64_
         accr[i][j][r] = 0;
         acci[i][j][r] = 0;
       }
-  // Each thread stages 4 A and 4 B entries per k-block of depth 16.  The
-  // next block is fetched into registers before the MFMAs of the current
-  // block run, so its global-memory latency overlaps the arithmetic.
-  cplx<T> ra[4], rb[4];
+  // Each thread stages 4 A and 4 B entries per k-block of depth 16, entry
+  // e = tid + 256 q: consecutive threads take consecutive addresses of the
+  // operand's contiguous dimension.  The next block is fetched into registers
+  // as stored before the MFMAs of the current block run, so its global-memory
+  // latency overlaps the arithmetic; conversion and conjugation wait for the
+  // staging.
+  cplx<TL> ra[4], rb[4];
+  const gcptr<TL> Ag = as_global(A), Bg = as_global(B);
+  // one guarded load per entry, its address chosen without branches: loads in
+  // alternative branches would share destination registers, and the compiler
+  // then waits for each load before issuing the next
+  const bool an = opA == OP_N, bn = opB == OP_N;
   auto fetch = [&](int k0) {
-    if (opA == OP_N) {
-      const int k = tid >> 4, rb0 = (tid & 15) * 4;
-      const int gk = k0 + k;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int gr = row0 + rb0 + q;
-        ra[q] = to_cplx<T>(load_or_zero(A + (int64_t)gr + (int64_t)gk * lda, gk < K && gr < M));
-      }
-    } else {
-      const int r = tid >> 2, kb = (tid & 3) * 4;
-      const int gr = row0 + r;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int gk = k0 + kb + q;
-        cplx<T> v = to_cplx<T>(load_or_zero(A + (int64_t)gk + (int64_t)gr * lda, gk < K && gr < M));
-        if (opA == OP_C) v.im = -v.im;
-        ra[q] = v;
-      }
-    }
-    if (opB == OP_N) {
-      const int c = tid >> 2, kb = (tid & 3) * 4;
-      const int gc = col0 + c;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int gk = k0 + kb + q;
-        rb[q] = to_cplx<T>(load_or_zero(B + (int64_t)gk + (int64_t)gc * ldb, gk < K && gc < N));
-      }
-    } else {
-      const int k = tid >> 4, cb = (tid & 15) * 4;
-      const int gk = k0 + k;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int gc = col0 + cb + q;
-        cplx<T> v = to_cplx<T>(load_or_zero(B + (int64_t)gc + (int64_t)gk * ldb, gk < K && gc < N));
-        if (opB == OP_C) v.im = -v.im;
-        rb[q] = v;
-      }
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int ar = row0 + (an ? e % GEMM_TM : e / GEMM_TK), ak = k0 + (an ? e / GEMM_TM : e % GEMM_TK);
+      ra[q] = load_or_zero(Ag + (an ? (int64_t)ar + (int64_t)ak * lda : (int64_t)ak + (int64_t)ar * lda),
+                           ak < K && ar < M);
+      const int bc = col0 + (bn ? e / GEMM_TK : e % GEMM_TN), bk = k0 + (bn ? e % GEMM_TK : e / GEMM_TN);
+      rb[q] = load_or_zero(Bg + (bn ? (int64_t)bk + (int64_t)bc * ldb : (int64_t)bc + (int64_t)bk * ldb),
+                           bk < K && bc < N);
     }
   };
   auto stage = [&]() {
-    if (opA == OP_N) {
-      const int k = tid >> 4, rb0 = (tid & 15) * 4;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) sm.a[k][rb0 + q] = ra[q];
-    } else {
-      const int r = tid >> 2, kb = (tid & 3) * 4;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) sm.a[kb + q][r] = ra[q];
-    }
-    if (opB == OP_N) {
-      const int c = tid >> 2, kb = (tid & 3) * 4;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) sm.b[kb + q][c] = rb[q];
-    } else {
-      const int k = tid >> 4, cb = (tid & 15) * 4;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) sm.b[k][cb + q] = rb[q];
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      cplx<T> va = to_cplx<T>(ra[q]), vb = to_cplx<T>(rb[q]);
+      if (opA == OP_C) va.im = -va.im;
+      if (opB == OP_C) vb.im = -vb.im;
+      if (opA == OP_N) {
+        const int k = e / GEMM_TM, m = e % GEMM_TM;
+        sm.a[k][lds_swz(k, m)] = va;
+      } else {
+        const int k = e % GEMM_TK, m = e / GEMM_TK;
+        sm.a[k][lds_swz(k, m)] = va;
+      }
+      if (opB == OP_N) {
+        const int k = e % GEMM_TK, c = e / GEMM_TK;
+        sm.b[k][lds_swz(k, c)] = vb;
+      } else {
+        const int k = e / GEMM_TN, c = e % GEMM_TN;
+        sm.b[k][lds_swz(k, c)] = vb;
+      }
     }
   };
   if (K > 0) fetch(0);
@@ -133,9 +144,9 @@ __device__ __forceinline__ void gemm_tile(const cplx<TL>* __restrict__ A, int64_
       const int k = kk + (lane >> 4);
       cplx<T> a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = sm.a[k][wr + i * 16 + (lane & 15)];
+      for (int i = 0; i < 2; ++i) a[i] = sm.a[k][lds_swz(k, wr + i * 16 + (lane & 15))];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = sm.b[k][wc + j * 16 + (lane & 15)];
+      for (int j = 0; j < 2; ++j) b[j] = sm.b[k][lds_swz(k, wc + j * 16 + (lane & 15))];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -178,17 +189,21 @@ template <int BI_, int BJ_, int WI_, int WJ_>
 struct TileCfg {
   static constexpr int BI = BI_, BJ = BJ_, WI = WI_, WJ = WJ_;
   static constexpr int TM = 16 * BI * WI, TN = 16 * BJ * WJ, TK = 16;
+  // workgroups per CU the registers must allow: two for shapes of four 16x16 blocks per wave and
+  // sides of at most 128 (two waves per SIMD hide each other's barriers and staging), one for the
+  // others (which would spill)
+  static constexpr int MINB = BI * BJ <= 4 && TM <= 128 && TN <= 128 ? 2 : 1;
   static_assert(WI * WJ == 4, "four waves per workgroup");
   static_assert(TM * TK % 256 == 0 && TN * TK % 256 == 0, "whole staging loads per thread");
 };
 
-// One padding entry per row: operands stored with k contiguous (B untransposed,
-// A transposed) are written down a column, 16 lanes at a row stride that
-// would otherwise map them all to the same LDS banks.
+// The layout of lds_ld / lds_swz: operands stored with k contiguous (B
+// untransposed, A transposed) are written down a column, the others along a
+// row, and both are read four rows at a time by the MFMA operand loads.
 template <class T, class C>
 struct TileSmem {
-  cplx<T> a[C::TK][C::TM + 1];
-  cplx<T> b[C::TK][C::TN + 1];
+  cplx<T> a[C::TK][lds_ld(C::TM)];
+  cplx<T> b[C::TK][lds_ld(C::TN)];
 };
 
 // Tile (tm, tn) of C = beta C + alpha op(A) op(B); operand conventions as in gemm_tile.
@@ -218,50 +233,48 @@ __device__ __forceinline__ void gemm_tile_cfg(const cplx<T>* __restrict__ A, int
   // staged entry e = tid + 256 q: consecutive threads take consecutive
   // addresses of the operand's contiguous dimension
   cplx<T> ra[NA], rb[NB];
+  const gcptr<T> Ag = as_global(A), Bg = as_global(B);
+  // one guarded load per entry, its address chosen without branches: loads in
+  // alternative branches would share destination registers, and the compiler
+  // then waits for each load before issuing the next
+  const bool an = opA == OP_N, bn = opB == OP_N;
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
       const int e = tid + 256 * q;
-      if (opA == OP_N) {
-        const int gr = row0 + e % TM, gk = k0 + e / TM;
-        ra[q] = load_or_zero(A + (int64_t)gr + (int64_t)gk * lda, gk < K && gr < M);
-      } else {
-        const int gk = k0 + e % TK, gr = row0 + e / TK;
-        cplx<T> v = load_or_zero(A + (int64_t)gk + (int64_t)gr * lda, gk < K && gr < M);
-        if (opA == OP_C) v.im = -v.im;
-        ra[q] = v;
-      }
+      const int ar = row0 + (an ? e % TM : e / TK), ak = k0 + (an ? e / TM : e % TK);
+      ra[q] = load_or_zero(Ag + (an ? (int64_t)ar + (int64_t)ak * lda : (int64_t)ak + (int64_t)ar * lda),
+                           ak < K && ar < M);
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       const int e = tid + 256 * q;
-      if (opB == OP_N) {
-        const int gk = k0 + e % TK, gc = col0 + e / TK;
-        rb[q] = load_or_zero(B + (int64_t)gk + (int64_t)gc * ldb, gk < K && gc < N);
-      } else {
-        const int gc = col0 + e % TN, gk = k0 + e / TN;
-        cplx<T> v = load_or_zero(B + (int64_t)gc + (int64_t)gk * ldb, gk < K && gc < N);
-        if (opB == OP_C) v.im = -v.im;
-        rb[q] = v;
-      }
+      const int bc = col0 + (bn ? e / TK : e % TN), bk = k0 + (bn ? e % TK : e / TN);
+      rb[q] = load_or_zero(Bg + (bn ? (int64_t)bk + (int64_t)bc * ldb : (int64_t)bc + (int64_t)bk * ldb),
+                           bk < K && bc < N);
     }
   };
+  // conjugation at staging, so that nothing waits for a prefetched value before its staging
   auto stage = [&]() {
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
       const int e = tid + 256 * q;
+      cplx<T> v = ra[q];
+      if (opA == OP_C) v.im = -v.im;
       if (opA == OP_N)
-        sm.a[e / TM][e % TM] = ra[q];
+        sm.a[e / TM][lds_swz(e / TM, e % TM)] = v;
       else
-        sm.a[e % TK][e / TK] = ra[q];
+        sm.a[e % TK][lds_swz(e % TK, e / TK)] = v;
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       const int e = tid + 256 * q;
+      cplx<T> v = rb[q];
+      if (opB == OP_C) v.im = -v.im;
       if (opB == OP_N)
-        sm.b[e % TK][e / TK] = rb[q];
+        sm.b[e % TK][lds_swz(e % TK, e / TK)] = v;
       else
-        sm.b[e / TN][e % TN] = rb[q];
+        sm.b[e / TN][lds_swz(e / TN, e % TN)] = v;
     }
   };
   if (K > 0) fetch(0);
@@ -274,9 +287,9 @@ __device__ __forceinline__ void gemm_tile_cfg(const cplx<T>* __restrict__ A, int
       const int k = kk + (lane >> 4);
       cplx<T> a[BI], b[BJ];
 #pragma unroll
-      for (int i = 0; i < BI; ++i) a[i] = sm.a[k][wr + i * 16 + (lane & 15)];
+      for (int i = 0; i < BI; ++i) a[i] = sm.a[k][lds_swz(k, wr + i * 16 + (lane & 15))];
 #pragma unroll
-      for (int j = 0; j < BJ; ++j) b[j] = sm.b[k][wc + j * 16 + (lane & 15)];
+      for (int j = 0; j < BJ; ++j) b[j] = sm.b[k][lds_swz(k, wc + j * 16 + (lane & 15))];
 #pragma unroll
       for (int i = 0; i < BI; ++i)
 #pragma unroll
