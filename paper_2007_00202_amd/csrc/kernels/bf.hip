@@ -319,11 +319,24 @@ __device__ __forceinline__ void block_argmax(double v, int i, double* red_v, int
 // (each needs the previous step's pivot), so more lanes per block shorten the
 // dot products of a step.
 constexpr int GRAM_THREADS = 1024;
-template <class T>
+// RG: R in device memory (else in LDS)
+template <class T, bool RG>
 __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<T>* __restrict__ R,
                                              unsigned char* __restrict__ aux, int maxp) {
   const int p = tk.p;
   const cplx<T>* G = (const cplx<T>*)tk.G;
+  auto rget = [&](int64_t i) -> cplx<T> {
+    if constexpr (RG)
+      return gld(R + i);
+    else
+      return R[i];
+  };
+  auto rput = [&](int64_t i, cplx<T> v) {
+    if constexpr (RG)
+      gst(R + i, v);
+    else
+      R[i] = v;
+  };
   // per-column state in the launch's dynamic LDS (maxp entries each; maxp is a multiple of 16)
   cplx<T>* rc = (cplx<T>*)aux;  // R(0:k, pivot) of the step
   cplx<T>* tl = rc + maxp;      // row i of T in the back substitution
@@ -335,7 +348,7 @@ __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<
   __shared__ int red_i[2][GRAM_THREADS / 64];
   const int tid = threadIdx.x;
   for (int j = tid; j < p; j += GRAM_THREADS) {
-    d[j] = (double)G[j + (int64_t)j * p].re;
+    d[j] = (double)gld(G + j + (int64_t)j * p).re;
     sel[j] = -1;
   }
   __syncthreads();
@@ -394,11 +407,11 @@ __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<
       const bool live = j < p && j != pi && sel[j] < 0;
       // G(j, pi) requested before the sum so that its latency overlaps the sum
       cplx<T> g = {0, 0};
-      if (live && part == 0) g = G[j + (int64_t)pi * p];
+      if (live && part == 0) g = gld(G + j + (int64_t)pi * p);
       double sr = 0, si = 0;
       if (live)
         for (int i = part; i < k; i += tpc) {
-          const cplx<T> a = R[(int64_t)i * p + pi], b = R[(int64_t)i * p + j];
+          const cplx<T> a = rget((int64_t)i * p + pi), b = rget((int64_t)i * p + j);
           sr += (double)a.re * b.re + (double)a.im * b.im;  // conj(a) b
           si += (double)a.re * b.im - (double)a.im * b.re;
         }
@@ -422,7 +435,7 @@ __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<
             vi = j;
           }
         }
-        R[(int64_t)k * p + j] = out;
+        rput((int64_t)k * p + j, out);
       }
     }
     if (tid == 0) {
@@ -435,7 +448,7 @@ __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<
   const int rank = k;
   // perm: the pivots, then the other columns in ascending order
   if (tid == 0) {
-    *tk.rank = rank;
+    gst(tk.rank, (int32_t)rank);
     int c = rank;
     for (int j = 0; j < p; ++j) {
       if (sel[j] >= 0)
@@ -445,7 +458,7 @@ __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<
     }
   }
   __syncthreads();
-  for (int j = tid; j < p; j += GRAM_THREADS) tk.perm[j] = pl[j];
+  for (int j = tid; j < p; j += GRAM_THREADS) gst(tk.perm + j, (int32_t)pl[j]);
   // T = R11^-1 R12 with R11(i, m) = R(i, piv[m]) (upper triangular) and R12(:, c) = R(:, pl[rank + c]):
   // back substitution by columns of R11, every (row, column) update of a step in parallel
   cplx<T>* Tout = (cplx<T>*)tk.T;
@@ -453,23 +466,23 @@ __device__ __forceinline__ void gram_id_body(const IdTask& tk, double tol, cplx<
   const int nc = p - rank;
   for (int e = tid; e < rank * nc; e += GRAM_THREADS) {
     const int i = e % rank, c = e / rank;
-    Tout[i + (int64_t)c * ldt] = R[(int64_t)i * p + pl[rank + c]];
+    gst(Tout + i + (int64_t)c * ldt, rget((int64_t)i * p + pl[rank + c]));
   }
   __syncthreads();
   for (int i = rank - 1; i >= 0; --i) {
-    const cplx<T> rii = R[(int64_t)i * p + piv[i]];
+    const cplx<T> rii = rget((int64_t)i * p + piv[i]);
     for (int c = tid; c < nc; c += GRAM_THREADS) {
       cplx<T>* tp = Tout + i + (int64_t)c * ldt;
-      const cplx<T> t = cdiv(*tp, rii);
-      *tp = t;
+      const cplx<T> t = cdiv(gld(tp), rii);
+      gst(tp, t);
       tl[c] = t;
     }
-    for (int m = tid; m < i; m += GRAM_THREADS) rc[m] = R[(int64_t)m * p + piv[i]];
+    for (int m = tid; m < i; m += GRAM_THREADS) rc[m] = rget((int64_t)m * p + piv[i]);
     __syncthreads();
     for (int e = tid; e < i * nc; e += GRAM_THREADS) {
       const int m = e % i, c = e / i;
       cplx<T>* tp = Tout + m + (int64_t)c * ldt;
-      *tp = csub(*tp, cmul(rc[m], tl[c]));
+      gst(tp, csub(gld(tp), cmul(rc[m], tl[c])));
     }
     __syncthreads();
   }
@@ -488,9 +501,9 @@ __global__ __launch_bounds__(GRAM_THREADS) void gram_id_kernel(const IdTask* __r
   unsigned char* aux = gram_smem;
   cplx<T>* Rl = (cplx<T>*)(gram_smem + gram_aux_bytes(maxp));
   if ((int64_t)min(tk.maxrank, p) * p <= lds_entries)
-    gram_id_body<T>(tk, tol, Rl, aux, maxp);
+    gram_id_body<T, false>(tk, tol, Rl, aux, maxp);
   else
-    gram_id_body<T>(tk, tol, (cplx<T>*)tk.R, aux, maxp);
+    gram_id_body<T, true>(tk, tol, (cplx<T>*)tk.R, aux, maxp);
 }
 
 // U (p x rank, ld p): U[perm[i], i] = 1 (i < rank), U[perm[rank + j], :] = T[:, j]^T,

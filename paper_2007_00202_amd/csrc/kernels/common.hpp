@@ -40,6 +40,34 @@ __device__ __forceinline__ T cabs1(cplx<T> a) {
   return fabs(a.re) + fabs(a.im);
 }
 
+// Device-memory access through the global address space.  A generic (flat)
+// access also counts against the LDS wait counter, so in a kernel that mixes
+// memory and LDS traffic every wait for an LDS result would wait for the
+// memory accesses in flight as well.  The pointer is made from the address's
+// integer value (a cast between pointer types can be dropped again by the
+// optimizer); complex values move component by component.
+template <class T>
+using gmem_t = __attribute__((address_space(1))) T;
+template <class T>
+__device__ __forceinline__ T gld(const T* p) {
+  return *(const gmem_t<T>*)(uintptr_t)p;
+}
+template <class T>
+__device__ __forceinline__ void gst(T* p, T v) {
+  *(gmem_t<T>*)(uintptr_t)p = v;
+}
+template <class T>
+__device__ __forceinline__ cplx<T> gld(const cplx<T>* p) {
+  const gmem_t<T>* q = (const gmem_t<T>*)(uintptr_t)p;
+  return cplx<T>{q[0], q[1]};
+}
+template <class T>
+__device__ __forceinline__ void gst(cplx<T>* p, cplx<T> v) {
+  gmem_t<T>* q = (gmem_t<T>*)(uintptr_t)p;
+  q[0] = v.re;
+  q[1] = v.im;
+}
+
 // Workgroups are handed to the chip's 8 XCDs in turn (block b to XCD b mod 8), each with its own L2. Runs of
 // XCD_RUN consecutive tiles, which mostly belong to one task and share its operand panels, are given to
 // one XCD; the runs still alternate between XCDs, so the load stays balanced. A bijection of

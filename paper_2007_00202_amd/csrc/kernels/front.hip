@@ -256,7 +256,7 @@ __global__ __launch_bounds__(PR_THREADS) void panel_reg_kernel(const FrontDesc* 
       const bool singular = !(pv > 0) || p >= m;
       if (singular) p = cr;
       if (tid == 0) {
-        fd.piv[k0 + cr] = k0 + p;
+        gst(fd.piv + k0 + cr, (int32_t)(k0 + p));
         if (c0 == 0) pl[jj] = p;
         if (singular && atomicCAS(&status[0], 0, 1) == 0) {
           status[1] = fd.front;
@@ -276,9 +276,9 @@ __global__ __launch_bounds__(PR_THREADS) void panel_reg_kernel(const FrontDesc* 
       if (p != cr && tid < cr) {  // the interchange in the finished columns (in memory)
         cplx<T>* x = at(cr, tid);
         cplx<T>* y = at(p, tid);
-        const cplx<T> t = *x;
-        *x = *y;
-        *y = t;
+        const cplx<T> t = gld(x);
+        gst(x, gld(y));
+        gst(y, t);
       }
       __syncthreads();
       const cplx<T> d = urow[buf][0];
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(PR_THREADS) void panel_reg_kernel(const FrontDesc* 
           for (int c = 1; c < PR_HALF; ++c)
             if (c < w - jj) a[q][c] = csub(a[q][c], cmul(l, urow[buf][c]));
         }
-        if (rowq[q] < m) *at(rowq[q], cr) = a[q][0];  // column cr is final (interchanges aside)
+        if (rowq[q] < m) gst(at(rowq[q], cr), a[q][0]);  // column cr is final (interchanges aside)
 #pragma unroll
         for (int c = 0; c + 1 < PR_HALF; ++c) a[q][c] = a[q][c + 1];
       }
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(PR_THREADS) void panel_reg_kernel(const FrontDesc* 
 #pragma unroll
   for (int q = 0; q < 2; ++q)
 #pragma unroll
-    for (int c = 0; c < PR_HALF; ++c) a[q][c] = (rowq[q] < m && c < w1) ? *at(rowq[q], c) : cplx<T>{0, 0};
+    for (int c = 0; c < PR_HALF; ++c) a[q][c] = (rowq[q] < m && c < w1) ? gld(at(rowq[q], c)) : cplx<T>{0, 0};
   factor_half(0, w1);
   if (jb <= PR_HALF) return;
   const int w2 = jb - PR_HALF;
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(PR_THREADS) void panel_reg_kernel(const FrontDesc* 
     }
 #pragma unroll
     for (int c = 0; c < PR_HALF; ++c)
-      a[q][c] = (rowq[q] < m && c < w2) ? *at(src, PR_HALF + c) : cplx<T>{0, 0};
+      a[q][c] = (rowq[q] < m && c < w2) ? gld(at(src, PR_HALF + c)) : cplx<T>{0, 0};
   }
   __syncthreads();  // every thread has read the right half before any of it is written again
   // the left half's rank-1 updates, in column order
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(PR_THREADS) void panel_reg_kernel(const FrontDesc* 
 #pragma unroll
     for (int q = 0; q < 2; ++q)
       if (rowq[q] > jj && rowq[q] < m) {
-        const cplx<T> l = *at(rowq[q], jj);
+        const cplx<T> l = gld(at(rowq[q], jj));
 #pragma unroll
         for (int c = 0; c < PR_HALF; ++c)
           if (c < w2) a[q][c] = csub(a[q][c], cmul(l, urow[buf][c]));
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(256) void trsm_ll_kernel(const FrontDesc* __restric
   cplx<T>* F = (cplx<T>*)fd.F;
   for (int e = threadIdx.x; e < KB * KB; e += 256) {
     const int i = e % KB, j = e / KB;
-    L[i][j] = (i > j && i < jb) ? F[(int64_t)(k0 + i) + (int64_t)(k0 + j) * n] : cplx<T>{0, 0};
+    L[i][j] = (i > j && i < jb) ? gld(F + (int64_t)(k0 + i) + (int64_t)(k0 + j) * n) : cplx<T>{0, 0};
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -425,7 +425,7 @@ __global__ __launch_bounds__(256) void trsm_ll_kernel(const FrontDesc* __restric
     cplx<T> x[TRSM_CW];
 #pragma unroll
     for (int q = 0; q < TRSM_CW; ++q)
-      x[q] = (lane < jb && cb + q < c1) ? F[(int64_t)(cb + q) * n + k0 + lane] : cplx<T>{0, 0};
+      x[q] = (lane < jb && cb + q < c1) ? gld(F + (int64_t)(cb + q) * n + k0 + lane) : cplx<T>{0, 0};
     for (int j = 0; j < jb - 1; ++j) {
       const cplx<T> l = L[li][j];
 #pragma unroll
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(256) void trsm_ll_kernel(const FrontDesc* __restric
     }
 #pragma unroll
     for (int q = 0; q < TRSM_CW; ++q)
-      if (lane < jb && cb + q < c1) F[(int64_t)(cb + q) * n + k0 + lane] = x[q];
+      if (lane < jb && cb + q < c1) gst(F + (int64_t)(cb + q) * n + k0 + lane, x[q]);
   }
 }
 
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(256) void trsm_ru_kernel(const FrontDesc* __restric
   cplx<T>* F = (cplx<T>*)fd.F;
   for (int e = threadIdx.x; e < KB * KB; e += 256) {
     const int i = e % KB, j = e / KB;
-    U[i][j] = (i < jb && j < jb) ? F[(int64_t)(k0 + i) + (int64_t)(k0 + j) * n] : cplx<T>{1, 0};
+    U[i][j] = (i < jb && j < jb) ? gld(F + (int64_t)(k0 + i) + (int64_t)(k0 + j) * n) : cplx<T>{1, 0};
   }
   __syncthreads();
   const int r = ns + blockIdx.x * 256 + threadIdx.x;
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(256) void trsm_ru_kernel(const FrontDesc* __restric
   if (r >= rend) return;
   cplx<T> x[KB];
 #pragma unroll
-  for (int c = 0; c < KB; ++c) x[c] = c < jb ? F[(int64_t)r + (int64_t)(k0 + c) * n] : cplx<T>{0, 0};
+  for (int c = 0; c < KB; ++c) x[c] = c < jb ? gld(F + (int64_t)r + (int64_t)(k0 + c) * n) : cplx<T>{0, 0};
 #pragma unroll
   for (int c = 0; c < KB; ++c) {
     cplx<T> s = x[c];
@@ -471,7 +471,7 @@ __global__ __launch_bounds__(256) void trsm_ru_kernel(const FrontDesc* __restric
   }
 #pragma unroll
   for (int c = 0; c < KB; ++c)
-    if (c < jb) F[(int64_t)r + (int64_t)(k0 + c) * n] = x[c];
+    if (c < jb) gst(F + (int64_t)r + (int64_t)(k0 + c) * n, x[c]);
 }
 
 // Rank-jb update after the panel of columns [k0, k0+jb): rows [k0+jb, ns) x
