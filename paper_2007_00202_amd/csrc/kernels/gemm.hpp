@@ -320,17 +320,20 @@ __device__ __forceinline__ void gemm_tile_cfg(const cplx<T>* __restrict__ A, int
       }
 }
 
-// Skinny product for at most 16 right-hand sides: C = beta C + alpha A B with
-// A (M x K, column-major, not transposed) streamed from memory once.  A
+// Skinny product for at most 16 (or 32) right-hand sides: C = beta C + alpha A B
+// with A (M x K, column-major, not transposed) streamed from memory once.  A
 // workgroup computes rows [256 tm, 256 tm + 256) and all N <= 16 columns; wave
 // w owns 64 rows as four 16x16 MFMA blocks and loads its A operands straight
 // into registers in the MFMA layout (lane l: row l%16, k l/16: 16 consecutive
-// rows per k, coalesced), four k-steps ahead of their use.  No LDS.
+// rows per k, coalesced), four k-steps ahead of their use.  No LDS.  The
+// products of an entry are added in the order of the LDS tiles (k in steps of
+// 4, increasing), so the results are those of the other tile shapes.
 constexpr int SKINNY_TM = 256, SKINNY_TN = 16;
 
 // RB row blocks of 16 per wave (the workgroup covers 64 RB rows); fewer blocks
-// hold fewer registers, so more waves share a SIMD.
-template <class T, int RB = 4>
+// hold fewer registers, so more waves share a SIMD.  NB column blocks of 16
+// (N <= 16 NB): each A operand serves NB blocks of MFMAs.
+template <class T, int RB = 4, int NB = 1>
 __device__ __forceinline__ void gemm_tile_skinny(const cplx<T>* __restrict__ A, int64_t lda,
                                                  const cplx<T>* __restrict__ B, int64_t ldb, cplx<T>* __restrict__ C,
                                                  int64_t ldc, int M, int N, int K, cplx<T> alpha, int beta, int tm) {
@@ -339,17 +342,20 @@ __device__ __forceinline__ void gemm_tile_skinny(const cplx<T>* __restrict__ A, 
   const int rbase = tm * 64 * RB + wave * 16 * RB;
   if (rbase >= M) return;  // no barrier below: idle waves may leave
   const int lr = lane & 15, lk = lane >> 4;
-  acc_t accr[RB], acci[RB];
+  const gcptr<T> Ag = as_global(A), Bg = as_global(B);
+  acc_t accr[RB][NB], acci[RB][NB];
 #pragma unroll
   for (int i = 0; i < RB; ++i)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      accr[i][r] = 0;
-      acci[i][r] = 0;
-    }
-  constexpr int U = 4;  // k-steps of 4 per batch of loads
-  cplx<T> a0[U][RB], b0[U], a1[U][RB], b1[U];  // two named batches: no dynamically indexed registers
-  auto load = [&](cplx<T>(&aa)[U][RB], cplx<T>(&bb)[U], int k0) {
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        accr[i][j][r] = 0;
+        acci[i][j][r] = 0;
+      }
+  constexpr int U = NB == 1 ? 4 : 2;  // k-steps of 4 per batch of loads
+  cplx<T> a0[U][RB], b0[U][NB], a1[U][RB], b1[U][NB];  // two named batches: no dynamically indexed registers
+  auto load = [&](cplx<T>(&aa)[U][RB], cplx<T>(&bb)[U][NB], int k0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int k = k0 + 4 * u + lk;
@@ -357,22 +363,29 @@ __device__ __forceinline__ void gemm_tile_skinny(const cplx<T>* __restrict__ A, 
 #pragma unroll
       for (int i = 0; i < RB; ++i) {
         const int row = rbase + 16 * i + lr;
-        aa[u][i] = load_or_zero(A + (int64_t)row + (int64_t)k * lda, kin && row < M);
+        aa[u][i] = load_or_zero(Ag + (int64_t)row + (int64_t)k * lda, kin && row < M);
       }
-      bb[u] = load_or_zero(B + (int64_t)k + (int64_t)lr * ldb, kin && lr < N);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int col = 16 * j + lr;
+        bb[u][j] = load_or_zero(Bg + (int64_t)k + (int64_t)col * ldb, kin && col < N);
+      }
     }
   };
-  auto mma = [&](cplx<T>(&aa)[U][RB], cplx<T>(&bb)[U]) {
+  auto mma = [&](cplx<T>(&aa)[U][RB], cplx<T>(&bb)[U][NB]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const cplx<T> bv = bb[u];
 #pragma unroll
       for (int i = 0; i < RB; ++i) {
         const cplx<T> av = aa[u][i];
-        accr[i] = Mfma<T>::step(av.re, bv.re, accr[i]);
-        accr[i] = Mfma<T>::step(-av.im, bv.im, accr[i]);
-        acci[i] = Mfma<T>::step(av.re, bv.im, acci[i]);
-        acci[i] = Mfma<T>::step(av.im, bv.re, acci[i]);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const cplx<T> bv = bb[u][j];
+          accr[i][j] = Mfma<T>::step(av.re, bv.re, accr[i][j]);
+          accr[i][j] = Mfma<T>::step(-av.im, bv.im, accr[i][j]);
+          acci[i][j] = Mfma<T>::step(av.re, bv.im, acci[i][j]);
+          acci[i][j] = Mfma<T>::step(av.im, bv.re, acci[i][j]);
+        }
       }
     }
   };
@@ -387,17 +400,19 @@ __device__ __forceinline__ void gemm_tile_skinny(const cplx<T>* __restrict__ A, 
 #pragma unroll
   for (int i = 0; i < RB; ++i)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int gr = rbase + 16 * i + Mfma<T>::row(lane, r);
-      const int gc = lr;
-      if (gr < M && gc < N) {
-        const T pr = accr[i][r], pi = acci[i][r];
-        cplx<T> v = {alpha.re * pr - alpha.im * pi, alpha.re * pi + alpha.im * pr};
-        cplx<T>* dst = C + (int64_t)gr + (int64_t)gc * ldc;
-        if (beta) v = cadd(*dst, v);
-        *dst = v;
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = rbase + 16 * i + Mfma<T>::row(lane, r);
+        const int gc = 16 * j + lr;
+        if (gr < M && gc < N) {
+          const T pr = accr[i][j][r], pi = acci[i][j][r];
+          cplx<T> v = {alpha.re * pr - alpha.im * pi, alpha.re * pi + alpha.im * pr};
+          cplx<T>* dst = C + (int64_t)gr + (int64_t)gc * ldc;
+          if (beta) v = cadd(*dst, v);
+          *dst = v;
+        }
       }
-    }
 }
 
 }  // namespace bfmf

@@ -351,27 +351,6 @@ __global__ __launch_bounds__(256) void sweep_seg_gemm_kernel(const FrontDesc* __
                              t % tm, t / tm, sm);
 }
 
-// the sweep products (W(ns:n) -= F21 W(0:ns), W(0:ns) -= F12 W(ns:n)) in a tile shape of the grouped GEMM
-template <class C>
-__global__ __launch_bounds__(256) void sweep_gemm_cfg_kernel(const FrontDesc* __restrict__ fds, int nrhs, int mode) {
-  __shared__ TileSmem<double, C> sm;
-  const FrontDesc& fd = fds[blockIdx.y];
-  const int n = fd.n, ns = fd.ns, nu = n - ns;
-  if (ns == 0 || nu == 0) return;
-  if (mode == 0 && ns > BLK_MAXNS) return;  // the segment panels carry F21
-  const cplx<double>* F = (const cplx<double>*)fd.P;
-  cplx<double>* W = (cplx<double>*)fd.W;
-  const int M = mode == 0 ? nu : ns;
-  const int tm = (M + C::TM - 1) / C::TM, tn = (nrhs + C::TN - 1) / C::TN;
-  const int t = blockIdx.x;
-  if (t >= tm * tn) return;
-  if (mode == 0)
-    gemm_tile_cfg<double, C>(F + ns, n, OP_N, W, n, OP_N, W + ns, n, nu, nrhs, ns, cplx<double>{-1, 0}, 1, t % tm,
-                             t / tm, sm);
-  else
-    gemm_tile_cfg<double, C>((const cplx<double>*)fd.F12, fd.ld12, OP_N, W + ns, n, OP_N, W, n, ns, nrhs, nu,
-                             cplx<double>{-1, 0}, 1, t % tm, t / tm, sm);
-}
 typedef TileCfg<2, 2, 4, 1> SweepTile128x32;
 
 // Upper substitution on W_f(0:ns, :) and scatter of the result into x.
@@ -449,12 +428,14 @@ constexpr int sweep_skinny_tm() {
   return sizeof(T) == 8 ? 128 : 256;
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void sweep_gemm_skinny_kernel(const FrontDesc* __restrict__ fds, int nrhs, int mode) {
+// NB column blocks of 16: at most 16 NB right-hand sides (two workgroups per CU: the stream's latency is
+// hidden by the other workgroup's MFMAs)
+template <class T, int NB = 1>
+__global__ __launch_bounds__(256, 2) void sweep_gemm_skinny_kernel(const FrontDesc* __restrict__ fds, int nrhs, int mode) {
   constexpr int RB = sweep_skinny_tm<T>() / 64;
   const FrontDesc& fd = fds[blockIdx.y];
   const int n = fd.n, ns = fd.ns, nu = n - ns;
-  if (ns == 0 || nu == 0 || nrhs > SKINNY_TN) return;
+  if (ns == 0 || nu == 0 || nrhs > SKINNY_TN * NB) return;
   if (sizeof(T) == 8 && mode == 0 && ns > BLK_MAXNS) return;  // the segment panels carry F21
   const cplx<T>* F = (const cplx<T>*)fd.P;  // [L U; F21'], ld n
   cplx<T>* W = (cplx<T>*)fd.W;
@@ -462,9 +443,10 @@ __global__ __launch_bounds__(256) void sweep_gemm_skinny_kernel(const FrontDesc*
   const int t = blockIdx.x;
   if (t * sweep_skinny_tm<T>() >= M) return;
   if (mode == 0)
-    gemm_tile_skinny<T, RB>(F + ns, n, W, n, W + ns, n, nu, nrhs, ns, cplx<T>{-1, 0}, 1, t);
+    gemm_tile_skinny<T, RB, NB>(F + ns, n, W, n, W + ns, n, nu, nrhs, ns, cplx<T>{-1, 0}, 1, t);
   else
-    gemm_tile_skinny<T, RB>((const cplx<T>*)fd.F12, fd.ld12, W + ns, n, W, n, ns, nrhs, nu, cplx<T>{-1, 0}, 1, t);
+    gemm_tile_skinny<T, RB, NB>((const cplx<T>*)fd.F12, fd.ld12, W + ns, n, W, n, ns, nrhs, nu, cplx<T>{-1, 0}, 1,
+                                t);
 }
 
 // ------------------------------------------------------------ GMRES vectors
@@ -646,6 +628,22 @@ hipError_t launch_permute_out(const void* x, void* X, int64_t ldx, const int64_t
   return hipGetLastError();
 }
 
+// the sweep products of a level (mode 0: W(ns:n) -= F21 W(0:ns); mode 1: W(0:ns) -= F12 W(ns:n)): F21 or
+// F12 streamed once by the register-operand kernel for up to 32 right-hand sides, tiles through LDS beyond
+template <class T>
+hipError_t launch_sweep_product(const FrontDesc* d_fds, int nbatch, int maxn, int nrhs, int mode, hipStream_t s) {
+  const dim3 sgrid((unsigned)blocks_for(maxn, sweep_skinny_tm<T>()), nbatch);
+  if (nrhs <= SKINNY_TN) {
+    hipLaunchKernelGGL((sweep_gemm_skinny_kernel<T, 1>), sgrid, dim3(256), 0, s, d_fds, nrhs, mode);
+  } else if (nrhs <= 2 * SKINNY_TN) {
+    hipLaunchKernelGGL((sweep_gemm_skinny_kernel<T, 2>), sgrid, dim3(256), 0, s, d_fds, nrhs, mode);
+  } else {
+    const int tiles = (int)(blocks_for(maxn, GEMM_TM) * blocks_for(nrhs, GEMM_TN));
+    hipLaunchKernelGGL((sweep_gemm_kernel<T>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs, mode);
+  }
+  return hipGetLastError();
+}
+
 template <class T>
 hipError_t launch_forward_level(const FrontDesc* d_fds, int nbatch, int maxn, int maxnu, int maxns, const void* y,
                                 int64_t N, int nrhs, hipStream_t s) {
@@ -682,17 +680,7 @@ hipError_t launch_forward_level(const FrontDesc* d_fds, int nbatch, int maxn, in
     hipLaunchKernelGGL((fwd_trsv_kernel<T>), dim3(nbatch), dim3(256), 0, s, d_fds, nrhs);
   }
   KCHECK(hipGetLastError());
-  if (nrhs <= SKINNY_TN) {
-    hipLaunchKernelGGL((sweep_gemm_skinny_kernel<T>), dim3((unsigned)blocks_for(maxn, sweep_skinny_tm<T>()), nbatch), dim3(256), 0,
-                       s, d_fds, nrhs, 0);
-  } else if (sizeof(T) == 8 && nrhs <= SweepTile128x32::TN) {
-    const int tiles = (int)(blocks_for(maxn, SweepTile128x32::TM) * blocks_for(nrhs, SweepTile128x32::TN));
-    hipLaunchKernelGGL((sweep_gemm_cfg_kernel<SweepTile128x32>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs, 0);
-  } else {
-    const int tiles = (int)(blocks_for(maxn, GEMM_TM) * blocks_for(nrhs, GEMM_TN));
-    hipLaunchKernelGGL((sweep_gemm_kernel<T>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs, 0);
-  }
-  return hipGetLastError();
+  return launch_sweep_product<T>(d_fds, nbatch, maxn, nrhs, 0, s);
 }
 
 template <class T>
@@ -703,18 +691,7 @@ hipError_t launch_backward_level(const FrontDesc* d_fds, int nbatch, int maxn, i
     hipLaunchKernelGGL((bwd_gather_kernel<T>), dim3(blocks_for(maxnu, 256), nbatch), dim3(256), 0, s, d_fds,
                        (const cplx<T>*)x, N, nrhs);
     KCHECK(hipGetLastError());
-    if (nrhs <= SKINNY_TN) {
-      hipLaunchKernelGGL((sweep_gemm_skinny_kernel<T>), dim3((unsigned)blocks_for(maxn, sweep_skinny_tm<T>()), nbatch), dim3(256),
-                         0, s, d_fds, nrhs, 1);
-    } else if (sizeof(T) == 8 && nrhs <= SweepTile128x32::TN) {
-      const int tiles = (int)(blocks_for(maxn, SweepTile128x32::TM) * blocks_for(nrhs, SweepTile128x32::TN));
-      hipLaunchKernelGGL((sweep_gemm_cfg_kernel<SweepTile128x32>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs,
-                         1);
-    } else {
-      const int tiles = (int)(blocks_for(maxn, GEMM_TM) * blocks_for(nrhs, GEMM_TN));
-      hipLaunchKernelGGL((sweep_gemm_kernel<T>), dim3(tiles, nbatch), dim3(256), 0, s, d_fds, nrhs, 1);
-    }
-    KCHECK(hipGetLastError());
+    KCHECK(launch_sweep_product<T>(d_fds, nbatch, maxn, nrhs, 1, s));
   }
   if (sizeof(T) == 8 && maxns > 0) {
     const dim3 grid((unsigned)((int64_t)nbatch * ((nrhs + BLK_RC - 1) / BLK_RC)));
