@@ -507,6 +507,27 @@ __global__ __launch_bounds__(256) void trailing_kernel(const FrontDesc* __restri
   }
 }
 
+// Rows [k0+jb, min(rend, ns)) x cols [max(k0+jb, cfrom), min(cend, n)) -= F(rows, k0:k0+jb) F(k0:k0+jb, cols):
+// the product between the two halves of a row-block solve taller than one wave's 64 lanes.
+template <class T>
+__global__ __launch_bounds__(256) void rowblock_update_kernel(const FrontDesc* __restrict__ fds, int k0, int kb,
+                                                              int rend, int cfrom, int cend) {
+  __shared__ GemmSmem<T> sm;
+  const FrontDesc& fd = fds[blockIdx.y];
+  const int ns = fd.ns, n = fd.n;
+  if (k0 >= ns) return;
+  const int jb = min(kb, ns - k0);
+  const int r0 = k0 + jb, c0 = max(r0, cfrom);
+  const int M = min(rend, ns) - r0, N = min(cend, n) - c0;
+  if (M <= 0 || N <= 0) return;
+  const int tm = (M + GEMM_TM - 1) / GEMM_TM, tn = (N + GEMM_TN - 1) / GEMM_TN;
+  const int t = blockIdx.x;
+  if (t >= tm * tn) return;
+  cplx<T>* F = (cplx<T>*)fd.F;
+  gemm_tile<T>(F + r0 + (int64_t)k0 * n, n, OP_N, F + k0 + (int64_t)c0 * n, n, F + r0 + (int64_t)c0 * n, n, M, N, jb,
+               cplx<T>{-1, 0}, 1, t % tm, t / tm, sm);
+}
+
 // Schur complement C = F22 - F21 F12 (depth ns).
 template <class T>
 __global__ __launch_bounds__(256) void schur_kernel(const FrontDesc* __restrict__ fds) {
@@ -570,12 +591,12 @@ hipError_t launch_partial_lu(const FrontDesc* d_fds, int nbatch, const int* h_n,
     maxn = h_n[b] > maxn ? h_n[b] : maxn;
   }
   static_assert(KB <= 2 * PR_HALF, "the register panel holds two half-panels");
-  // Blocks of 2 KB columns: the first half panel is factored, its interchanges, row-block solve and
-  // rank-KB update applied to the second half's columns (and F21) only; then the second half panel;
-  // then, once per block, the interchanges of both halves, the 2 KB x 2 KB row-block solve and one
-  // rank-2 KB update of everything to the right, so the trailing matrix is rewritten once per 2 KB
-  // columns.  The panels see exactly the values of a KB-column right-looking sweep, so the pivots
-  // are the same.
+  // Columns in blocks of 4 KB, each made of two blocks of 2 KB, each made of two panels of KB (the
+  // register panel). A block's interchanges, row-block solve and right-looking update reach only the
+  // columns of the enclosing block until the block is complete; then one solve and one rank-w update
+  // (w = 2 KB, 4 KB) cover the enclosing block's columns (or everything to the right, for the outermost
+  // blocks). The panels see exactly the values of a KB-column right-looking sweep, so the pivots are the
+  // same; the trailing matrix is rewritten once per 4 KB columns.
   auto tiles_for = [&](int k0, int kb, int cend) {
     int mt = 0;
     for (int b = 0; b < nbatch; ++b) {
@@ -601,7 +622,7 @@ hipError_t launch_partial_lu(const FrontDesc* d_fds, int nbatch, const int* h_n,
     }
     return false;
   };
-  auto half = [&](int k0, int cend) {  // factor columns [k0, k0+KB); update columns up to cend
+  auto half = [&](int k0, int cend) -> hipError_t {  // factor columns [k0, k0+KB); update columns up to cend
     if (maxns - k0 <= PR_ROWS)  // every front's panel fits the register kernel
       hipLaunchKernelGGL((panel_reg_kernel<T>), dim3(nbatch), dim3(PR_THREADS), 0, s, d_fds, k0, KB, d_status);
     else
@@ -624,25 +645,45 @@ hipError_t launch_partial_lu(const FrontDesc* d_fds, int nbatch, const int* h_n,
       hipLaunchKernelGGL((trailing_kernel<T>), dim3(mt, nbatch), dim3(256), 0, s, d_fds, k0, KB, cend);
       KCHECK(hipGetLastError());
     }
+    return hipSuccess;
   };
-  for (int k0 = 0; k0 < maxns; k0 += 2 * KB) {
-    const int kend = k0 + 2 * KB;
-    half(k0, kend);                           // right updates reach the second half's columns only
-    if (k0 + KB < maxns) half(k0 + KB, kend);  // interchanges left of it; right columns only past ns
-    if (maxn > kend) {
-      // columns from kend on: both halves' interchanges, the row-block solve, one rank-2 KB update
-      hipLaunchKernelGGL((laswp_kernel<T>), dim3((maxn - kend + 255) / 256, nbatch), dim3(256), 0, s, d_fds, k0, 2 * KB,
-                         k0, kend, maxn);
+  // pivot rows [k0, k0+w) applied to columns [cfrom, cend): interchanges, row-block solve (rows of a 64-row
+  // half one lane each; for w = 4 KB two halves with the product between them), rank-w update
+  auto block_update = [&](int k0, int w, int cfrom, int cend) -> hipError_t {
+    const int ncol = cend - cfrom;
+    hipLaunchKernelGGL((laswp_kernel<T>), dim3((ncol + 255) / 256, nbatch), dim3(256), 0, s, d_fds, k0, w, k0, cfrom,
+                       cend);
+    KCHECK(hipGetLastError());
+    const dim3 sgrid((ncol + TRSM_COLS - 1) / TRSM_COLS, nbatch);
+    hipLaunchKernelGGL((trsm_ll_kernel<T, 2 * KB>), sgrid, dim3(256), 0, s, d_fds, k0, cfrom, cend);
+    KCHECK(hipGetLastError());
+    if (w > 2 * KB) {
+      hipLaunchKernelGGL((rowblock_update_kernel<T>), dim3((ncol + GEMM_TN - 1) / GEMM_TN, nbatch), dim3(256), 0, s,
+                         d_fds, k0, 2 * KB, k0 + w, cfrom, cend);
       KCHECK(hipGetLastError());
-      hipLaunchKernelGGL((trsm_ll_kernel<T, 2 * KB>), dim3((maxn - kend + TRSM_COLS - 1) / TRSM_COLS, nbatch),
-                         dim3(256), 0, s, d_fds, k0, kend, maxn);
+      hipLaunchKernelGGL((trsm_ll_kernel<T, 2 * KB>), sgrid, dim3(256), 0, s, d_fds, k0 + 2 * KB, cfrom, cend);
       KCHECK(hipGetLastError());
-      const int mt = tiles_for(k0, 2 * KB, maxn);
-      if (mt > 0) {
-        hipLaunchKernelGGL((trailing_kernel<T>), dim3(mt, nbatch), dim3(256), 0, s, d_fds, k0, 2 * KB, maxn);
-        KCHECK(hipGetLastError());
-      }
     }
+    const int mt = tiles_for(k0, w, cend);
+    if (mt > 0) {
+      hipLaunchKernelGGL((trailing_kernel<T>), dim3(mt, nbatch), dim3(256), 0, s, d_fds, k0, w, cend);
+      KCHECK(hipGetLastError());
+    }
+    return hipSuccess;
+  };
+  // columns [k0, k0 + 2 KB), right updates up to cend
+  auto block2 = [&](int k0, int cend) -> hipError_t {
+    const int kend = k0 + 2 * KB;
+    KCHECK(half(k0, kend));
+    if (k0 + KB < maxns) KCHECK(half(k0 + KB, kend));
+    if (maxn > kend && cend > kend) KCHECK(block_update(k0, 2 * KB, kend, cend));
+    return hipSuccess;
+  };
+  for (int k0 = 0; k0 < maxns; k0 += 4 * KB) {
+    const int kend = k0 + 4 * KB;
+    KCHECK(block2(k0, kend));
+    if (k0 + 2 * KB < maxns) KCHECK(block2(k0 + 2 * KB, kend));
+    if (maxn > kend) KCHECK(block_update(k0, 4 * KB, kend, maxn));
   }
   return hipSuccess;
 }
