@@ -54,11 +54,34 @@ __device__ __forceinline__ cplx<TO> to_cplx(cplx<TI> v) {
 __host__ __device__ constexpr int lds_ld(int t) { return t % 32 == 0 ? t + 16 : t; }
 __device__ __forceinline__ int lds_swz(int k, int m) { return m ^ (k & 15); }
 
-template <class T>
-struct GemmSmem {
-  cplx<T> a[GEMM_TK][lds_ld(GEMM_TM)];
-  cplx<T> b[GEMM_TK][lds_ld(GEMM_TN)];
+// Real and imaginary parts in separate planes: every LDS access moves 8
+// (or 4) contiguous bytes per lane, so a wave's access covers distinct banks.
+template <class T, int TK, int TM, int TN>
+struct SplitSmem {
+  T are[TK][lds_ld(TM)], aim[TK][lds_ld(TM)];
+  T bre[TK][lds_ld(TN)], bim[TK][lds_ld(TN)];
+  __device__ __forceinline__ void put_a(int k, int m, cplx<T> v) {
+    const int c = lds_swz(k, m);
+    are[k][c] = v.re;
+    aim[k][c] = v.im;
+  }
+  __device__ __forceinline__ void put_b(int k, int n, cplx<T> v) {
+    const int c = lds_swz(k, n);
+    bre[k][c] = v.re;
+    bim[k][c] = v.im;
+  }
+  __device__ __forceinline__ cplx<T> get_a(int k, int m) const {
+    const int c = lds_swz(k, m);
+    return cplx<T>{are[k][c], aim[k][c]};
+  }
+  __device__ __forceinline__ cplx<T> get_b(int k, int n) const {
+    const int c = lds_swz(k, n);
+    return cplx<T>{bre[k][c], bim[k][c]};
+  }
 };
+
+template <class T>
+struct GemmSmem : SplitSmem<T, GEMM_TK, GEMM_TM, GEMM_TN> {};
 
 // Computes tile (tm, tn).  opA: OP_N -> A is M x K (lda); OP_T / OP_C -> A is
 // stored K x M (lda) and used transposed / conjugate-transposed.  opB: OP_N ->
@@ -118,20 +141,14 @@ __device__ __forceinline__ void gemm_tile(const cplx<TL>* __restrict__ A, int64_
       cplx<T> va = to_cplx<T>(ra[q]), vb = to_cplx<T>(rb[q]);
       if (opA == OP_C) va.im = -va.im;
       if (opB == OP_C) vb.im = -vb.im;
-      if (opA == OP_N) {
-        const int k = e / GEMM_TM, m = e % GEMM_TM;
-        sm.a[k][lds_swz(k, m)] = va;
-      } else {
-        const int k = e % GEMM_TK, m = e / GEMM_TK;
-        sm.a[k][lds_swz(k, m)] = va;
-      }
-      if (opB == OP_N) {
-        const int k = e % GEMM_TK, c = e / GEMM_TK;
-        sm.b[k][lds_swz(k, c)] = vb;
-      } else {
-        const int k = e / GEMM_TN, c = e % GEMM_TN;
-        sm.b[k][lds_swz(k, c)] = vb;
-      }
+      if (opA == OP_N)
+        sm.put_a(e / GEMM_TM, e % GEMM_TM, va);
+      else
+        sm.put_a(e % GEMM_TK, e / GEMM_TK, va);
+      if (opB == OP_N)
+        sm.put_b(e % GEMM_TK, e / GEMM_TK, vb);
+      else
+        sm.put_b(e / GEMM_TN, e % GEMM_TN, vb);
     }
   };
   if (K > 0) fetch(0);
@@ -144,9 +161,9 @@ __device__ __forceinline__ void gemm_tile(const cplx<TL>* __restrict__ A, int64_
       const int k = kk + (lane >> 4);
       cplx<T> a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = sm.a[k][lds_swz(k, wr + i * 16 + (lane & 15))];
+      for (int i = 0; i < 2; ++i) a[i] = sm.get_a(k, wr + i * 16 + (lane & 15));
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = sm.b[k][lds_swz(k, wc + j * 16 + (lane & 15))];
+      for (int j = 0; j < 2; ++j) b[j] = sm.get_b(k, wc + j * 16 + (lane & 15));
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -201,10 +218,7 @@ struct TileCfg {
 // untransposed, A transposed) are written down a column, the others along a
 // row, and both are read four rows at a time by the MFMA operand loads.
 template <class T, class C>
-struct TileSmem {
-  cplx<T> a[C::TK][lds_ld(C::TM)];
-  cplx<T> b[C::TK][lds_ld(C::TN)];
-};
+struct TileSmem : SplitSmem<T, C::TK, C::TM, C::TN> {};
 
 // Tile (tm, tn) of C = beta C + alpha op(A) op(B); operand conventions as in gemm_tile.
 template <class T, class C>
@@ -262,9 +276,9 @@ __device__ __forceinline__ void gemm_tile_cfg(const cplx<T>* __restrict__ A, int
       cplx<T> v = ra[q];
       if (opA == OP_C) v.im = -v.im;
       if (opA == OP_N)
-        sm.a[e / TM][lds_swz(e / TM, e % TM)] = v;
+        sm.put_a(e / TM, e % TM, v);
       else
-        sm.a[e % TK][lds_swz(e % TK, e / TK)] = v;
+        sm.put_a(e % TK, e / TK, v);
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
@@ -272,9 +286,9 @@ __device__ __forceinline__ void gemm_tile_cfg(const cplx<T>* __restrict__ A, int
       cplx<T> v = rb[q];
       if (opB == OP_C) v.im = -v.im;
       if (opB == OP_N)
-        sm.b[e % TK][lds_swz(e % TK, e / TK)] = v;
+        sm.put_b(e % TK, e / TK, v);
       else
-        sm.b[e / TN][lds_swz(e / TN, e % TN)] = v;
+        sm.put_b(e / TN, e % TN, v);
     }
   };
   if (K > 0) fetch(0);
@@ -287,9 +301,9 @@ __device__ __forceinline__ void gemm_tile_cfg(const cplx<T>* __restrict__ A, int
       const int k = kk + (lane >> 4);
       cplx<T> a[BI], b[BJ];
 #pragma unroll
-      for (int i = 0; i < BI; ++i) a[i] = sm.a[k][lds_swz(k, wr + i * 16 + (lane & 15))];
+      for (int i = 0; i < BI; ++i) a[i] = sm.get_a(k, wr + i * 16 + (lane & 15));
 #pragma unroll
-      for (int j = 0; j < BJ; ++j) b[j] = sm.b[k][lds_swz(k, wc + j * 16 + (lane & 15))];
+      for (int j = 0; j < BJ; ++j) b[j] = sm.get_b(k, wc + j * 16 + (lane & 15));
 #pragma unroll
       for (int i = 0; i < BI; ++i)
 #pragma unroll
