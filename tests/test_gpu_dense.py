@@ -132,7 +132,8 @@ def test_front_taller_than_the_register_panel_with_interchanges(gpu_lib):
 
 
 @pytest.mark.parametrize("dims,leaf,nrhs,batched", [((8, 8, 8), 64, 1, False), ((10, 9, 8), 64, 3, True),
-                                                    ((12, 12, 12), 100, 70, True), ((2, 2, 2), 512, 2, False)])
+                                                    ((12, 12, 12), 100, 24, True), ((12, 12, 12), 100, 70, True),
+                                                    ((2, 2, 2), 512, 2, False)])
 def test_preconditioner_matches_oracle_solve(gpu_lib, dims, leaf, nrhs, batched):
     rp, ci, v, _ = helmholtz_7pt(dims, 0.05)
     od = nd.nd_grid(dims, leaf_max=leaf, sep_leaf=16)
@@ -148,6 +149,21 @@ def test_preconditioner_matches_oracle_solve(gpu_lib, dims, leaf, nrhs, batched)
     assert info["status"] == 0 and info["iters"] <= 1
     assert np.all(mf.rel_residual(rp, ci, v, Xg, B) <= 1e-12)
     s.close()
+
+
+def test_sweep_columns_independent_of_the_batch_width(gpu_lib):
+    # 24 right-hand sides take the two-column-block streaming sweep product, 8 the one-block form;
+    # both add the products of an entry in the same order, so the shared columns agree
+    dims = (12, 12, 12)
+    rp, ci, v, _ = helmholtz_7pt(dims, 0.05)
+    rng = rng_for("test", "rhs", (24,))
+    B = rng.standard_normal((1728, 24)) + 1j * rng.standard_normal((1728, 24))
+    s = gpu_lib.Solver(0).analyze(rp, ci, v, dims=dims, leaf_max=100, sep_leaf=16)
+    s.factor(n_min=0, batched=True)
+    X24 = s.precondition(B)
+    X8 = s.precondition(np.asfortranarray(B[:, :8]))
+    s.close()
+    assert np.linalg.norm(X24[:, :8] - X8) <= 1e-13 * np.linalg.norm(X8)
 
 
 def test_batched_equals_plain_bitwise(gpu_lib):
