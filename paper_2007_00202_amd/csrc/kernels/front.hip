@@ -477,7 +477,7 @@ __global__ __launch_bounds__(256) void trsm_ru_kernel(const FrontDesc* __restric
 // Rank-jb update after the panel of columns [k0, k0+jb): rows [k0+jb, ns) x
 // cols [k0+jb, ce) and rows [ns, n) x cols [k0+jb, min(ce, ns)), ce = min(cend, n).
 template <class T>
-__global__ __launch_bounds__(256) void trailing_kernel(const FrontDesc* __restrict__ fds, int k0, int kb, int cend) {
+__global__ __launch_bounds__(256, 2) void trailing_kernel(const FrontDesc* __restrict__ fds, int k0, int kb, int cend) {
   __shared__ GemmSmem<T> sm;
   const FrontDesc& fd = fds[blockIdx.y];
   const int ns = fd.ns, n = fd.n;
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(256) void trailing_kernel(const FrontDesc* __restri
 // Rows [k0+jb, min(rend, ns)) x cols [max(k0+jb, cfrom), min(cend, n)) -= F(rows, k0:k0+jb) F(k0:k0+jb, cols):
 // the product between the two halves of a row-block solve taller than one wave's 64 lanes.
 template <class T>
-__global__ __launch_bounds__(256) void rowblock_update_kernel(const FrontDesc* __restrict__ fds, int k0, int kb,
+__global__ __launch_bounds__(256, 2) void rowblock_update_kernel(const FrontDesc* __restrict__ fds, int k0, int kb,
                                                               int rend, int cfrom, int cend) {
   __shared__ GemmSmem<T> sm;
   const FrontDesc& fd = fds[blockIdx.y];
@@ -530,7 +530,7 @@ __global__ __launch_bounds__(256) void rowblock_update_kernel(const FrontDesc* _
 
 // Schur complement C = F22 - F21 F12 (depth ns).
 template <class T>
-__global__ __launch_bounds__(256) void schur_kernel(const FrontDesc* __restrict__ fds) {
+__global__ __launch_bounds__(256, 2) void schur_kernel(const FrontDesc* __restrict__ fds) {
   __shared__ GemmSmem<T> sm;
   const FrontDesc& fd = fds[blockIdx.y];
   const int ns = fd.ns, n = fd.n, nu = n - ns;
@@ -546,7 +546,7 @@ __global__ __launch_bounds__(256) void schur_kernel(const FrontDesc* __restrict_
 // The same Schur complement with the product on FP32 MFMA: F21 and F12 rounded
 // to complex64 as they are staged, the product accumulated in FP32 and
 // subtracted from F22 in double (the complex64 form of the dense fronts).
-__global__ __launch_bounds__(256) void schur_mixed_kernel(const FrontDesc* __restrict__ fds) {
+__global__ __launch_bounds__(256, 2) void schur_mixed_kernel(const FrontDesc* __restrict__ fds) {
   __shared__ GemmSmem<float> sm;
   const FrontDesc& fd = fds[blockIdx.y];
   const int ns = fd.ns, n = fd.n, nu = n - ns;
