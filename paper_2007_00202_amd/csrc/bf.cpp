@@ -2027,7 +2027,7 @@ void bf_random_matvec_batch(BfRuntime<T>& rt, const std::vector<RandomJob<T>*>& 
       rt.sample_hint[b] = j->S;
       rt.max_rank_seen = std::max(rt.max_rank_seen, j->out->max_rank());
     }
-    if (again.size() == pending.size()) rt.pool.used = pool_mark;  // every attempt of this round is discarded
+    if (again.size() == pending.size()) rt.pool.used = pool_mark;  // every attempt of this pass is discarded
     for (auto* j : again) {
       j->out.reset();
       j->S *= 2;

@@ -185,7 +185,7 @@ void worker_main(bfmf_server_s* s, Model* m) {
   const int nslot = s->opts.max_batch_rhs;
   std::vector<int> fin;
   for (;;) {
-    std::vector<int> fresh;  // slots loaded this round
+    std::vector<int> fresh;  // slots loaded in this admission pass
     {
       std::unique_lock<std::mutex> lk(s->mu);
       // admit whole requests of this model in arrival order while their columns find free slots and their
@@ -227,7 +227,7 @@ void worker_main(bfmf_server_s* s, Model* m) {
           return;
         }
       }
-      // occupancy of this round, for the requests' reports
+      // occupancy of this pass, for the requests' reports
       int busy_cols = 0;
       std::vector<Request*> in;
       for (const SlotRef& r : m->slot)
