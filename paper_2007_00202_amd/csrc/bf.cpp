@@ -1038,8 +1038,9 @@ struct IdLevel {
   void run_chunked(const std::vector<void*>& A, const std::vector<int>& q, const std::vector<int>& p,
                    std::vector<int>& rank, std::vector<std::vector<int32_t>>& perm, int lim);
 
+  // householder: the Householder kernel whatever the tolerance (the Gram kernel's column limit is lower)
   void run_direct(const std::vector<void*>& A, const std::vector<int>& q, const std::vector<int>& p,
-                  std::vector<int>& rank, std::vector<std::vector<int32_t>>& perm) {
+                  std::vector<int>& rank, std::vector<std::vector<int32_t>>& perm, bool householder = false) {
     const size_t nb = A.size();
     hipStream_t s = rt.s();
     std::vector<IdTask> tasks(nb);
@@ -1048,11 +1049,13 @@ struct IdLevel {
     int32_t* d_rank = rt.scratch.template take_n<int32_t>(std::max<size_t>(nb, 1));
     int32_t* d_perm = rt.scratch.template take_n<int32_t>(std::max<int64_t>(tot_perm, 1));
     int64_t po = 0;
-    const bool gram = rt.tol >= 1e-4;  // Gram variant for tolerances where eps p / tol^2 is negligible
+    // Gram variant for tolerances where eps p / tol^2 is negligible
+    const bool gram = !householder && rt.tol >= 1e-4;
     for (size_t i = 0; i < nb; ++i) {
-      // the Gram kernel takes up to 2048 columns and any number of rows (it sees A^H A); the
-      // Householder kernel up to 1024 columns and 2048 rows (wider blocks are chunked by run())
-      if (p[i] > (gram ? GRAM_MAXP : CPQR_MAXP) || (!gram && q[i] > 2048))
+      // the Gram kernel takes up to GRAM_MAXP columns and any number of rows (it sees A^H A); the
+      // Householder kernel up to CPQR_WIDE_MAXP columns and CPQR_MAXQ rows (run() splits blocks wider
+      // than CPQR_MAXP into column chunks and sends a whole block only when its chunks have full rank)
+      if (p[i] > (gram ? GRAM_MAXP : CPQR_WIDE_MAXP) || (!gram && q[i] > CPQR_MAXQ))
         throw Error(BFMF_E_INVAL, "ID block too large (" + std::to_string(q[i]) + " x " + std::to_string(p[i]) + ")");
       const int maxrank = std::max(1, std::min(p[i], q[i]));
       void* Tb = rt.scratch.take((size_t)maxrank * std::max(p[i], 1) * sizeof(cplx<double>));
@@ -1111,7 +1114,7 @@ struct IdLevel {
     if (gram)
       chk(launch_gram_id<double>(dt, (int)nb, rt.tol, lds_entries, maxp, s), "gram id");
     else
-      chk(launch_cpqr_id<double>(dt, (int)nb, rt.tol, s), "cpqr");
+      chk(launch_cpqr_id<double>(dt, (int)nb, rt.tol, maxp, s), "cpqr");
     if (tk >= 0) {
       double fl = 0, by = 0;  // pivoted QR of q x p truncated at rank k ~ min(p, q): 8 q p k flops, A read and written
       for (size_t i = 0; i < nb; ++i) {
@@ -1248,18 +1251,30 @@ void IdLevel<T>::run_chunked(const std::vector<void*>& A, const std::vector<int>
     }
     soff.push_back((int)Jall.size());
     const int ns = (int)Jall.size(), qq = std::max(q[i], 1);
-    // every chunk of full rank: a second stage would be as wide as the block (no progress); a block
-    // within the kernels' own limits (the cap was forced lower) is decomposed directly instead
+    // every chunk of full rank: a second stage would be as wide as the block (no progress), so the
+    // whole block is decomposed directly instead: by the runtime's own kernel where it fits (the cap
+    // was forced lower), else by the Householder kernel up to its wide limit, on a copy in the Gram
+    // case (the Householder kernel overwrites its block, the Gram kernel leaves it as it was)
     if (ns >= p[i]) {
-      const int klim = rt.tol >= 1e-4 ? GRAM_MAXP : CPQR_MAXP;
-      if (p[i] > klim)
+      const bool gram = rt.tol >= 1e-4;
+      const bool wide = p[i] > (gram ? GRAM_MAXP : CPQR_MAXP);
+      if (wide && (p[i] > CPQR_WIDE_MAXP || q[i] > CPQR_MAXQ))
         throw Error(BFMF_E_INVAL, "ID block of " + std::to_string(q[i]) + " x " + std::to_string(p[i]) +
                                       ": its column chunks of at most " + std::to_string(lim) +
-                                      " have full rank, more than one decomposition kernel takes");
+                                      " have full rank, and the block is larger than one decomposition kernel"
+                                      " takes");
+      void* blk = (void*)src[i];
+      if (wide && gram) {
+        blk = rt.scratch.take((size_t)qq * std::max(p[i], 1) * esz);
+        const AxpbyTask cp{blk, src[i], qq, qq, q[i], p[i], 0};
+        chk(launch_axpby_batch<double>((const AxpbyTask*)upload_tmp(rt, std::vector<AxpbyTask>{cp}), 1,
+                                       (int64_t)q[i] * p[i], 1.0, 0.0, s),
+            "copy the wide block");
+      }
       IdLevel<T> whole(rt);
       std::vector<int> rw;
       std::vector<std::vector<int32_t>> pw;
-      whole.run_direct({(void*)src[i]}, {q[i]}, {p[i]}, rw, pw);
+      whole.run_direct({blk}, {q[i]}, {p[i]}, rw, pw, wide);
       out[i] = whole.htasks[0];
       rank[i] = rw[0];
       perm[i] = pw[0];

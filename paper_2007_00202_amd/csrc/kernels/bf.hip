@@ -118,9 +118,9 @@ __global__ __launch_bounds__(256) void grouped_gemm_skinny_kernel(const GTask* _
 // One workgroup per block.  Columns of A (q x p) are pivoted by largest
 // remaining norm (first maximum); the factorization stops at the first
 // |R_kk| <= tol |R_00| (rank k) or at maxrank.  Householder vectors live in
-// LDS; one wave applies a reflector to one column at a time.
-constexpr int ID_MAXP = CPQR_MAXP;  // columns of a Householder ID block
-constexpr int ID_MAXQ = 2048;
+// LDS; one wave applies a reflector to one column at a time.  The column
+// norms and the permutation live in dynamic LDS: maxp doubles, then maxp ints.
+constexpr int ID_MAXQ = CPQR_MAXQ;
 
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -129,17 +129,18 @@ __device__ __forceinline__ T wave_sum(T v) {
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void cpqr_id_kernel(const IdTask* __restrict__ tasks, double tol) {
+__global__ __launch_bounds__(256) void cpqr_id_kernel(const IdTask* __restrict__ tasks, double tol, int maxp) {
   const IdTask& tk = tasks[blockIdx.x];
   const int q = tk.q, p = tk.p;
   const int64_t lda = tk.lda;
   cplx<T>* A = (cplx<T>*)tk.A;
-  if (q > ID_MAXQ || p > ID_MAXP || q < 0 || p < 0) {  // the host never sends these; refuse, never overflow LDS
+  if (q > ID_MAXQ || p > maxp || q < 0 || p < 0) {  // the host never sends these; refuse, never overflow LDS
     if (threadIdx.x == 0) *tk.rank = -1;
     return;
   }
-  __shared__ double nrm[ID_MAXP];
-  __shared__ int perm[ID_MAXP];
+  extern __shared__ __align__(16) unsigned char cpqr_smem[];
+  double* nrm = (double*)cpqr_smem;
+  int* perm = (int*)(cpqr_smem + (size_t)maxp * sizeof(double));
   __shared__ cplx<T> v[ID_MAXQ];
   __shared__ double red_v[256];
   __shared__ int red_i[256];
@@ -1101,9 +1102,11 @@ hipError_t launch_grouped_gemm(const GTask* d_tasks, const int64_t* d_tile_start
 }
 
 template <class T>
-hipError_t launch_cpqr_id(const IdTask* d_tasks, int ntasks, double tol, hipStream_t s) {
+hipError_t launch_cpqr_id(const IdTask* d_tasks, int ntasks, double tol, int maxp, hipStream_t s) {
   if (ntasks == 0) return hipSuccess;
-  hipLaunchKernelGGL((cpqr_id_kernel<T>), dim3(ntasks), dim3(256), 0, s, d_tasks, tol);
+  if (maxp <= 0 || maxp > CPQR_WIDE_MAXP) return hipErrorInvalidValue;
+  const size_t bytes = (size_t)maxp * (sizeof(double) + sizeof(int));
+  hipLaunchKernelGGL((cpqr_id_kernel<T>), dim3(ntasks), dim3(256), bytes, s, d_tasks, tol, maxp);
   return hipGetLastError();
 }
 
@@ -1257,7 +1260,7 @@ hipError_t launch_convert(void* Y, int64_t ldy, const void* X, int64_t ldx, int6
 #define INST(T)                                                                                                       \
   template hipError_t launch_grouped_gemm<T>(const GTask*, const int64_t*, int, int64_t, void* const[4], int,         \
                                              hipStream_t, hipEvent_t, hipEvent_t, bool);                              \
-  template hipError_t launch_cpqr_id<T>(const IdTask*, int, double, hipStream_t);                                     \
+  template hipError_t launch_cpqr_id<T>(const IdTask*, int, double, int, hipStream_t);                                \
   template hipError_t launch_gram_id<T>(const IdTask*, int, double, int, int, hipStream_t);                           \
   template hipError_t launch_id_expand<T>(const IdTask*, int, void* const*, const int64_t*, bool, bool, hipStream_t);  \
   template hipError_t launch_front_extract<T>(const ExtractTask*, int, int, const void*, bool, hipStream_t);          \

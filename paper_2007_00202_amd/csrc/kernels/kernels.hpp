@@ -115,15 +115,18 @@ template <class T>
 hipError_t launch_grouped_gemm(const GTask* d_tasks, const int64_t* d_tile_start, int ntasks, int64_t ntiles,
                                void* const bases[4], int cfg, hipStream_t s, hipEvent_t ev_start = nullptr,
                                hipEvent_t ev_stop = nullptr, bool gram = false);
-// truncated column-pivoted QR of every task's q x p block (tol: |R_kk| > tol |R_00|)
+// truncated column-pivoted QR of every task's q x p block (tol: |R_kk| > tol |R_00|), p <= maxp <=
+// CPQR_WIDE_MAXP (the per-column state, 12 bytes a column, sits in dynamic LDS sized by maxp)
 template <class T>
-hipError_t launch_cpqr_id(const IdTask* d_tasks, int ntasks, double tol, hipStream_t s);
+hipError_t launch_cpqr_id(const IdTask* d_tasks, int ntasks, double tol, int maxp, hipStream_t s);
 // the same decompositions from G = A^H A (IdTask.G) by pivoted Cholesky: the rows of R in
 // lds_entries complex entries of dynamic LDS per workgroup where min(maxrank, p) * p fits, else
 // in IdTask.R
 constexpr int GRAM_LDS_MAX = 4096;
 constexpr int GRAM_MAXP = 2048;  // most columns of a Gram ID block
-constexpr int CPQR_MAXP = 1024;  // most columns of a Householder ID block
+constexpr int CPQR_MAXP = 1024;       // widest Householder ID block before blocks are split into column chunks
+constexpr int CPQR_WIDE_MAXP = 8192;  // most columns of a Householder ID block
+constexpr int CPQR_MAXQ = 2048;       // most rows of a Householder ID block
 constexpr size_t GRAM_LDS_BYTES = 159 * 1024;  // the dynamic LDS of a Gram ID launch at most (one CU's 160 KiB, less the static part)
 // dynamic LDS of a Gram ID launch whose blocks have at most maxp columns (maxp a multiple of 16): per-column
 // state (pivot search, selection, permutation: 20 bytes; two complex<double> rows: 32 bytes), then the R rows

@@ -142,3 +142,31 @@ def test_interpolative_decomposition_over_1296_columns(gpu_lib, method):
         assert gpu_lib.bfmf_bf_info(b)["max_rank"] < 400
     finally:
         gpu_lib.bfmf_bf_destroy(b)
+
+
+@pytest.mark.parametrize("m,n,r,tol", [(1300, 1100, 800, 1e-8), (2200, 1300, 1200, 1e-3)])
+def test_wide_id_block_whose_column_chunks_have_full_rank(gpu_lib, m, n, r, tol):
+    """Entry evaluation with L = 0 gives one ID over all m rows (with all n
+    columns as proxies) and one over all n columns (all m rows as proxies).
+    Blocks wider than one ID kernel takes are split into column chunks; when
+    every chunk has full rank (rank r above the chunk width) the chunks'
+    skeletons are as wide as the block and the whole block goes to one
+    Householder ID instead (up to 8192 columns): at tol 1e-8 from the
+    Householder limit of 1024 columns (both IDs), at tol 1e-3 from the Gram
+    limit of 2048 (the 2200-column row ID).  K has exact rank r, so the
+    butterfly has rank r and reproduces K to rounding.  Its factors have
+    orthonormal columns and rows, so a chunk of K's rows or columns keeps
+    singular values far above tol relative to its largest (a Gaussian
+    factor's condition number would truncate the chunks below full rank)."""
+    rng = np.random.default_rng(m + r)
+    U = np.linalg.qr(rng.standard_normal((m, r)) + 1j * rng.standard_normal((m, r)))[0]
+    V = np.linalg.qr(rng.standard_normal((n, r)) + 1j * rng.standard_normal((n, r)))[0].conj().T
+    K = U @ V
+    b, shape = gpu_lib.bfmf_bf_compress_dense(K, 0, tol, method=0, seed=13)
+    try:
+        assert gpu_lib.bfmf_bf_info(b)["max_rank"] == r
+        D = decompress(gpu_lib, b, shape)
+        err = np.linalg.norm(K - D) / np.linalg.norm(K)
+        assert err <= 1e-6, err
+    finally:
+        gpu_lib.bfmf_bf_destroy(b)
