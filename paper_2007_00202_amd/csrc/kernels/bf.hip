@@ -115,12 +115,16 @@ __global__ __launch_bounds__(256) void grouped_gemm_skinny_kernel(const GTask* _
 }
 
 // ---------------------------------------------------------------- CPQR ID
-// One workgroup per block.  Columns of A (q x p) are pivoted by largest
-// remaining norm (first maximum); the factorization stops at the first
-// |R_kk| <= tol |R_00| (rank k) or at maxrank.  Householder vectors live in
-// LDS; one wave applies a reflector to one column at a time.  The column
-// norms and the permutation live in dynamic LDS: maxp doubles, then maxp ints.
+// One workgroup of CPQR_THREADS threads per block.  Columns of A (q x p) are
+// pivoted by largest remaining norm (first maximum); the factorization stops
+// at the first |R_kk| <= tol |R_00| (rank k) or at maxrank.  Householder
+// vectors live in LDS; one wave applies a reflector to one column at a time,
+// so the trailing columns of a step stream through the CU with 16 waves in
+// flight.  The column norms and the permutation live in dynamic LDS: maxp
+// doubles, then maxp ints.
 constexpr int ID_MAXQ = CPQR_MAXQ;
+constexpr int CPQR_THREADS = 1024;
+constexpr int CPQR_WAVES = CPQR_THREADS / 64;
 
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -128,8 +132,44 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// the workgroup's largest v (first index i on ties) into bv, bi for every thread; red_v and
+// red_i hold one entry per wave and are not read again before the caller's next barrier
+__device__ __forceinline__ void cpqr_argmax(double v, int i, double* red_v, int* red_i, double& bv, int& bi) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(v, o);
+    const int oi = __shfl_xor(i, o);
+    if (ov > v || (ov == v && oi < i)) {
+      v = ov;
+      i = oi;
+    }
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red_v[wave] = v;
+    red_i[wave] = i;
+  }
+  __syncthreads();
+  bv = red_v[0];
+  bi = red_i[0];
+  for (int w = 1; w < CPQR_WAVES; ++w)
+    if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bi)) {
+      bv = red_v[w];
+      bi = red_i[w];
+    }
+}
+
+// the workgroup's sum of v for every thread, added in wave order (the same value in every thread)
+__device__ __forceinline__ double cpqr_sum(double v, double* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0;
+  for (int w = 0; w < CPQR_WAVES; ++w) t += red[w];
+  return t;
+}
+
 template <class T>
-__global__ __launch_bounds__(256) void cpqr_id_kernel(const IdTask* __restrict__ tasks, double tol, int maxp) {
+__global__ __launch_bounds__(CPQR_THREADS) void cpqr_id_kernel(const IdTask* __restrict__ tasks, double tol, int maxp) {
   const IdTask& tk = tasks[blockIdx.x];
   const int q = tk.q, p = tk.p;
   const int64_t lda = tk.lda;
@@ -142,54 +182,42 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const IdTask* __restrict__
   double* nrm = (double*)cpqr_smem;
   int* perm = (int*)(cpqr_smem + (size_t)maxp * sizeof(double));
   __shared__ cplx<T> v[ID_MAXQ];
-  __shared__ double red_v[256];
-  __shared__ int red_i[256];
-  __shared__ double sh_ref;
-  __shared__ int sh_rank;
+  // per-wave partials, two sets each used on alternate steps: a set is written again only two
+  // steps later, after several barriers, so no barrier is needed behind its readers
+  __shared__ double red_v[2][CPQR_WAVES];
+  __shared__ int red_i[2][CPQR_WAVES];
+  __shared__ double red_s[2][CPQR_WAVES];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int j = tid; j < p; j += 256) {
+  for (int j = wave; j < p; j += CPQR_WAVES) {  // squared column norms, one column per wave
     const cplx<T>* a = A + (int64_t)j * lda;
     double s = 0;
-    for (int i = 0; i < q; ++i) s += (double)a[i].re * a[i].re + (double)a[i].im * a[i].im;
-    nrm[j] = s;
-    perm[j] = j;
-  }
-  if (tid == 0) {
-    sh_rank = 0;
-    sh_ref = 0;
+    for (int i = lane; i < q; i += 64) s += (double)a[i].re * a[i].re + (double)a[i].im * a[i].im;
+    s = wave_sum(s);
+    if (lane == 0) {
+      nrm[j] = s;
+      perm[j] = j;
+    }
   }
   __syncthreads();
   const int kmax = min(min(p, q), tk.maxrank);
+  double ref = 0;  // |R_00|
   int k = 0;
   for (; k < kmax; ++k) {
     // pivot: largest remaining norm, first index on ties
     double best = -1;
     int bi = p;
-    for (int j = k + tid; j < p; j += 256)
+    for (int j = k + tid; j < p; j += CPQR_THREADS)
       if (nrm[j] > best) {
         best = nrm[j];
         bi = j;
       }
-    red_v[tid] = best;
-    red_i[tid] = bi;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s) {
-        const double o = red_v[tid + s];
-        const int oi = red_i[tid + s];
-        if (o > red_v[tid] || (o == red_v[tid] && oi < red_i[tid])) {
-          red_v[tid] = o;
-          red_i[tid] = oi;
-        }
-      }
-      __syncthreads();
-    }
-    const int jp = red_i[0];
-    __syncthreads();
+    double bv;
+    int jp;
+    cpqr_argmax(best, bi, red_v[k & 1], red_i[k & 1], bv, jp);
     if (jp != k && jp < p) {
       cplx<T>* a = A + (int64_t)k * lda;
       cplx<T>* b = A + (int64_t)jp * lda;
-      for (int i = tid; i < q; i += 256) {
+      for (int i = tid; i < q; i += CPQR_THREADS) {
         const cplx<T> t = a[i];
         a[i] = b[i];
         b[i] = t;
@@ -207,24 +235,16 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const IdTask* __restrict__
     // exact norm of the trailing part of column k
     cplx<T>* ak = A + (int64_t)k * lda;
     double s = 0;
-    for (int i = k + tid; i < q; i += 256) s += (double)ak[i].re * ak[i].re + (double)ak[i].im * ak[i].im;
-    red_v[tid] = s;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if (tid < st) red_v[tid] += red_v[tid + st];
-      __syncthreads();
-    }
-    const double alpha = sqrt(red_v[0]);
-    __syncthreads();
-    if (k == 0 && tid == 0) sh_ref = alpha;
-    __syncthreads();
-    if (!(alpha > tol * sh_ref) || alpha == 0) break;
+    for (int i = k + tid; i < q; i += CPQR_THREADS) s += (double)ak[i].re * ak[i].re + (double)ak[i].im * ak[i].im;
+    const double alpha = sqrt(cpqr_sum(s, red_s[k & 1]));
+    if (k == 0) ref = alpha;
+    if (!(alpha > tol * ref) || alpha == 0) break;
     // Householder vector v = x + s alpha e1, tau = 1 / (alpha (alpha + |x0|))
     const cplx<T> x0 = ak[k];
     const double ax0 = sqrt((double)x0.re * x0.re + (double)x0.im * x0.im);
     const double sr = ax0 > 0 ? x0.re / ax0 : 1.0, si = ax0 > 0 ? x0.im / ax0 : 0.0;
     const double tau = 1.0 / (alpha * (alpha + ax0));
-    for (int i = k + tid; i < q; i += 256) {
+    for (int i = k + tid; i < q; i += CPQR_THREADS) {
       cplx<T> x = ak[i];
       if (i == k) {
         x.re = (T)(x.re + sr * alpha);
@@ -237,7 +257,7 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const IdTask* __restrict__
       ak[k] = cplx<T>{(T)(-sr * alpha), (T)(-si * alpha)};  // R_kk
     }
     // apply H to columns k+1..p-1: a -= tau v (v^H a)
-    for (int j = k + 1 + wave; j < p; j += 4) {
+    for (int j = k + 1 + wave; j < p; j += CPQR_WAVES) {
       cplx<T>* a = A + (int64_t)j * lda;
       double wr = 0, wi = 0;
       for (int i = k + lane; i < q; i += 64) {
@@ -256,7 +276,7 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const IdTask* __restrict__
     }
     __syncthreads();
     // downdate the remaining column norms with the new row k of R
-    for (int j = k + 1 + tid; j < p; j += 256) {
+    for (int j = k + 1 + tid; j < p; j += CPQR_THREADS) {
       const cplx<T> r = A[k + (int64_t)j * lda];
       const double d = nrm[j] - ((double)r.re * r.re + (double)r.im * r.im);
       nrm[j] = d > 0 ? d : 0;
@@ -265,11 +285,11 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const IdTask* __restrict__
   }
   const int rank = k;
   if (tid == 0) *tk.rank = rank;
-  for (int j = tid; j < p; j += 256) tk.perm[j] = perm[j];
+  for (int j = tid; j < p; j += CPQR_THREADS) tk.perm[j] = perm[j];
   // T = R11^-1 R12: back substitution, one thread per column of R12
   cplx<T>* Tout = (cplx<T>*)tk.T;
   const int ldt = tk.maxrank;
-  for (int j = rank + tid; j < p; j += 256) {
+  for (int j = rank + tid; j < p; j += CPQR_THREADS) {
     cplx<T>* tcol = Tout + (int64_t)(j - rank) * ldt;
     for (int i = rank - 1; i >= 0; --i) {
       cplx<T> s = A[i + (int64_t)j * lda];
@@ -288,31 +308,6 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const IdTask* __restrict__
 // T = R11^-1 R12 by back substitution over the whole workgroup.
 // Rounding in G limits the accuracy of T to about eps p / tol^2 (relative),
 // so the host uses this variant only for tolerances where that is small.
-template <class T>
-__device__ __forceinline__ void block_argmax(double v, int i, double* red_v, int* red_i, double& bv, int& bi) {
-  // wave maximum (first index on ties), then across the four waves
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ov = __shfl_xor(v, o);
-    const int oi = __shfl_xor(i, o);
-    if (ov > v || (ov == v && oi < i)) {
-      v = ov;
-      i = oi;
-    }
-  }
-  const int wave = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    red_v[wave] = v;
-    red_i[wave] = i;
-  }
-  __syncthreads();
-  bv = red_v[0];
-  bi = red_i[0];
-  for (int w = 1; w < 4; ++w)
-    if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bi)) {
-      bv = red_v[w];
-      bi = red_i[w];
-    }
-}
 
 // R (rows 0 .. kmax-1 of the factor, row i at R + i p) lives in LDS when it fits
 // the launch's dynamic LDS, else in the task's workspace; the body is the same.
@@ -1106,7 +1101,7 @@ hipError_t launch_cpqr_id(const IdTask* d_tasks, int ntasks, double tol, int max
   if (ntasks == 0) return hipSuccess;
   if (maxp <= 0 || maxp > CPQR_WIDE_MAXP) return hipErrorInvalidValue;
   const size_t bytes = (size_t)maxp * (sizeof(double) + sizeof(int));
-  hipLaunchKernelGGL((cpqr_id_kernel<T>), dim3(ntasks), dim3(256), bytes, s, d_tasks, tol, maxp);
+  hipLaunchKernelGGL((cpqr_id_kernel<T>), dim3(ntasks), dim3(CPQR_THREADS), bytes, s, d_tasks, tol, maxp);
   return hipGetLastError();
 }
 
