@@ -256,22 +256,34 @@ __global__ __launch_bounds__(CPQR_THREADS) void cpqr_id_kernel(const IdTask* __r
     if (tid == 0) {
       ak[k] = cplx<T>{(T)(-sr * alpha), (T)(-si * alpha)};  // R_kk
     }
-    // apply H to columns k+1..p-1: a -= tau v (v^H a)
-    for (int j = k + 1 + wave; j < p; j += CPQR_WAVES) {
+    // apply H to columns k+1..p-1: a -= tau v (v^H a), two columns per wave at a time (j and
+    // j + CPQR_WAVES) for twice the independent loads in flight; each column's sums run in the
+    // same order as with one column at a time
+    for (int j = k + 1 + wave; j < p; j += 2 * CPQR_WAVES) {
+      const bool two = j + CPQR_WAVES < p;
       cplx<T>* a = A + (int64_t)j * lda;
-      double wr = 0, wi = 0;
+      cplx<T>* b = A + (int64_t)(two ? j + CPQR_WAVES : j) * lda;  // read only, as a, when !two
+      double wr = 0, wi = 0, xr = 0, xi = 0;
       for (int i = k + lane; i < q; i += 64) {
-        const cplx<T> vi = v[i], ai = a[i];
+        const cplx<T> vi = v[i], ai = a[i], bi = b[i];
         wr += (double)vi.re * ai.re + (double)vi.im * ai.im;
         wi += (double)vi.re * ai.im - (double)vi.im * ai.re;
+        xr += (double)vi.re * bi.re + (double)vi.im * bi.im;
+        xi += (double)vi.re * bi.im - (double)vi.im * bi.re;
       }
       wr = wave_sum(wr);
       wi = wave_sum(wi);
-      const double cr = tau * wr, ci = tau * wi;
+      xr = wave_sum(xr);
+      xi = wave_sum(xi);
+      const double cr = tau * wr, ci = tau * wi, dr = tau * xr, di = tau * xi;
       for (int i = k + lane; i < q; i += 64) {
         const cplx<T> vi = v[i];
         a[i].re -= (T)(vi.re * cr - vi.im * ci);
         a[i].im -= (T)(vi.re * ci + vi.im * cr);
+        if (two) {
+          b[i].re -= (T)(vi.re * dr - vi.im * di);
+          b[i].im -= (T)(vi.re * di + vi.im * dr);
+        }
       }
     }
     __syncthreads();
