@@ -118,7 +118,10 @@ typedef struct {
     int32_t id_max_cols; /* widest block given to one interpolative-decomposition kernel
                             (0: the kernels' own limits, 2048 columns for tol >= 1e-4, else
                             1024); wider blocks are decomposed as an ID of the IDs of column
-                            chunks (about twice the tolerance); values in 1..15 are E_INVAL */
+                            chunks (about twice the tolerance), or whole by the Householder
+                            kernel (up to 8192 columns and 2048 rows) when every chunk has
+                            full rank; a block beyond that gives E_INVAL; values in 1..15 are
+                            E_INVAL */
     int32_t compress_cb; /* 1: the contribution block of a compressed front whose parent is
                             compressed too is built as an HOD-BF (tree: balanced bisection of
                             I^u, leaves of at most 64) by entry evaluation of C_nu1 (+) C_nu2 - S
