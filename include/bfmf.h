@@ -356,7 +356,8 @@ bfmf_status bfmf_get_gemm_tile_launches(bfmf_handle h, int64_t* out, int32_t n);
  * checking the butterfly kernels on their own.  K: m x n complex128,
  * column-major (ld >= m), host memory, copied.  L: levels of the row and
  * column trees (halving bisection of [0, m) and [0, n)).  method 0: entry
- * evaluation with alpha = 4 uniform proxies per block (Alg. 2); method 1:
+ * evaluation with alpha = 4 uniform proxies per block, at most 2048 below
+ * tol 1e-4 (Alg. 2); method 1:
  * randomized products with K and K^H (Sec. 3.3), `samples` probes per tree
  * node (doubled while an ID rank comes within 8 of it).  tol: ID tolerance.
  * E_INVAL for bad sizes, E_DEVICE / E_NOMEM from the runtime. */

@@ -2,6 +2,7 @@
 // evaluation (Alg. 2) or by randomized products (Sec. 3.3), products K X and
 // K^H X, and decompression.  Used to check the butterfly kernels in isolation.
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <random>
 
@@ -64,15 +65,16 @@ struct DenseSource : EntrySource<double> {
   }
 };
 
-// alpha * |given| uniform proxies (without replacement) inside the node
+// alpha * |given| uniform proxies (without replacement) inside the node, at most cap
 struct UniformSampler : ProxySampler {
   std::mt19937_64 g;
   double alpha;
-  UniformSampler(uint64_t seed, double a) : g(seed), alpha(a) {}
+  int cap;
+  UniformSampler(uint64_t seed, double a, int c) : g(seed), alpha(a), cap(c) {}
   void pick(size_t given, int beg, int end, std::vector<int32_t>& out) {
     out.clear();
     const int n = end - beg;
-    const int k = std::min(n, std::max(8, (int)(alpha * (double)given)));
+    const int k = std::min({n, cap, std::max(8, (int)(alpha * (double)given))});
     std::vector<int32_t> all(n);
     for (int i = 0; i < n; ++i) all[i] = beg + i;
     for (int i = 0; i < k; ++i) {
@@ -307,7 +309,9 @@ bfmf_status bfmf_bf_compress_dense(int32_t device, int32_t m, int32_t n, const d
     BTree to = make_tree(m, L, nullptr, 0), ts = make_tree(n, L, nullptr, 0);
     if (method == 0) {
       DenseSource src(b->K.p, m);
-      UniformSampler ps(seed ^ 0x9e3779b97f4a7c15ull, 4.0);
+      // proxies are the rows of the ID blocks: below tol 1e-4 the Householder kernel takes at most
+      // CPQR_MAXQ of them (the Gram kernel any number)
+      UniformSampler ps(seed ^ 0x9e3779b97f4a7c15ull, 4.0, tol < 1e-4 ? CPQR_MAXQ : std::numeric_limits<int>::max());
       b->bf = bf_entry_eval<double>(b->rt, src, ps, to, ts);
     } else {
       DenseOp<double> op(b->rt, b->K.p, m, m, n);

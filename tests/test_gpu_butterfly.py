@@ -170,3 +170,24 @@ def test_wide_id_block_whose_column_chunks_have_full_rank(gpu_lib, m, n, r, tol)
         assert err <= 1e-6, err
     finally:
         gpu_lib.bfmf_bf_destroy(b)
+
+
+def test_proxies_capped_at_the_householder_row_limit(gpu_lib):
+    """Below tol 1e-4 the ID blocks go to the Householder kernel, which takes
+    at most 2048 rows; entry evaluation on a 2600 x 700 matrix would draw
+    min(2600, 4 * 700) = 2600 proxy rows for the column ID, so the sampler
+    stops at 2048.  K has exact rank 300, which 2048 random rows still span,
+    so the butterfly reproduces K to rounding."""
+    rng = np.random.default_rng(17)
+    m, n, r = 2600, 700, 300
+    U = np.linalg.qr(rng.standard_normal((m, r)) + 1j * rng.standard_normal((m, r)))[0]
+    V = np.linalg.qr(rng.standard_normal((n, r)) + 1j * rng.standard_normal((n, r)))[0].conj().T
+    K = U @ V
+    b, shape = gpu_lib.bfmf_bf_compress_dense(K, 0, 1e-8, method=0, seed=19)
+    try:
+        assert gpu_lib.bfmf_bf_info(b)["max_rank"] == r
+        D = decompress(gpu_lib, b, shape)
+        err = np.linalg.norm(K - D) / np.linalg.norm(K)
+        assert err <= 1e-6, err
+    finally:
+        gpu_lib.bfmf_bf_destroy(b)
